@@ -1,0 +1,118 @@
+/* w-stacking dirty image at chosen pixels only -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Used to check the full-size workloads, where the whole float64 pipeline
+ * does not fit a test's time budget.  For a pixel (p, q) the gridded planes,
+ * their inverse DFT and the phase screen collapse to one pass over the
+ * visibilities, because the kernel is separable:
+ *
+ *   F_k[q][p] = sum_{j in plane k} A_j  X_j(p) Y_j(q),
+ *   X_j(p)    = sum_t g_{s_x}[t] exp(+2 pi i (c_x + t - h - N/2)(p - N/2) / N)
+ *   I[q][p]   = n_pq sum_k Re(exp(+2 pi i w_k (n_pq - 1)) F_k[q][p]) / (C_p C_q sum W)
+ *
+ * which is the same sum as gridding onto the cells, transforming and
+ * screening, taken in another order.  The per-visibility position, plane and
+ * drop decisions repeat the float64 steps of the Python oracle operation by
+ * operation (no contraction, round-half-even, floor division).
+ * exp(2 pi i j / N) for integer j is read from a table built with the exact
+ * integer residue j mod N.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int64_t floordiv(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+/* Returns the number of kept visibilities; acc must hold npix * nw complex
+ * (re, im interleaved) and is overwritten; *sum_w receives sum W. */
+int64_t oracle_wstack_pixels(
+    int64_t nrow, int32_t nchan, const double *uvw, const double *scales /* or NULL */,
+    const float *vis /* re,im pairs [nrow][nchan] */, const float *weight /* or NULL */,
+    int32_t grid_n, int32_t nw, int32_t support, int32_t oversample, double fov,
+    double w_min, double dw, const double *table /* [OS][W] */,
+    int64_t npix, const int32_t *pix_p, const int32_t *pix_q,
+    double *acc /* [npix][nw][2] */, double *sum_w_out)
+{
+    const int64_t N = grid_n, OS = oversample, h = (support - 1) / 2;
+    const double two_pi = 6.283185307179586476925286766559;
+    double *cs = (double *)malloc(sizeof(double) * 2 * N);
+    for (int64_t j = 0; j < N; ++j) {
+        cs[2 * j] = cos(two_pi * (double)j / (double)N);
+        cs[2 * j + 1] = sin(two_pi * (double)j / (double)N);
+    }
+    memset(acc, 0, sizeof(double) * 2 * npix * nw);
+    int64_t kept_total = 0;
+    double sumw_total = 0.0;
+    const double half = (double)(N * OS) / 2.0;
+    const double lim = 1073741824.0; /* 2^30 */
+    #pragma omp parallel
+    {
+        double *lacc = (double *)calloc((size_t)(2 * npix * nw), sizeof(double));
+        int64_t kept = 0;
+        double sumw = 0.0;
+        #pragma omp for schedule(static)
+        for (int64_t r = 0; r < nrow; ++r) {
+            for (int32_t c = 0; c < nchan; ++c) {
+                double u, v, w;
+                if (scales) {
+                    u = uvw[3 * r] * scales[c];
+                    v = uvw[3 * r + 1] * scales[c];
+                    w = uvw[3 * r + 2] * scales[c];
+                } else {
+                    u = uvw[3 * r]; v = uvw[3 * r + 1]; w = uvw[3 * r + 2];
+                }
+                const int64_t vi = r * nchan + c;
+                const double vr = vis[2 * vi], vim = vis[2 * vi + 1];
+                const double wt = weight ? (double)weight[vi] : 1.0;
+                if (!(isfinite(u) && isfinite(v) && isfinite(w) && isfinite(vr) && isfinite(vim) && isfinite(wt)))
+                    continue;
+                double xs = u * fov; xs = xs * (double)OS; xs = xs + half;
+                double ys = v * fov; ys = ys * (double)OS; ys = ys + half;
+                if (!(fabs(xs) <= lim && fabs(ys) <= lim)) continue;
+                const int64_t X = (int64_t)rint(xs), Y = (int64_t)rint(ys);
+                const int64_t cx = floordiv(X + OS / 2, OS), cy = floordiv(Y + OS / 2, OS);
+                const int64_t sx = X - cx * OS, sy = Y - cy * OS;
+                if (!(wt > 0.0)) continue;
+                if (cx - h < 0 || cx + h > N - 1 || cy - h < 0 || cy + h > N - 1) continue;
+                double kf = floor((w - w_min) / dw);
+                if (!isfinite(kf)) kf = 0.0;
+                if (kf < 0.0) kf = 0.0;
+                if (kf > (double)(nw - 1)) kf = (double)(nw - 1);
+                const int64_t k = (int64_t)kf;
+                ++kept;
+                sumw += wt;
+                const double ar = wt * vr, ai = wt * vim;
+                const double *gx = table + (sx + OS / 2) * support;
+                const double *gy = table + (sy + OS / 2) * support;
+                for (int64_t ip = 0; ip < npix; ++ip) {
+                    const int64_t pp = pix_p[ip] - N / 2, qq = pix_q[ip] - N / 2;
+                    double xr = 0, xi = 0, yr = 0, yi = 0;
+                    for (int64_t t = 0; t < support; ++t) {
+                        int64_t jx = ((cx + t - h - N / 2) * pp) % N; if (jx < 0) jx += N;
+                        int64_t jy = ((cy + t - h - N / 2) * qq) % N; if (jy < 0) jy += N;
+                        xr += gx[t] * cs[2 * jx]; xi += gx[t] * cs[2 * jx + 1];
+                        yr += gy[t] * cs[2 * jy]; yi += gy[t] * cs[2 * jy + 1];
+                    }
+                    const double er = xr * yr - xi * yi, ei = xr * yi + xi * yr;
+                    double *dst = lacc + 2 * (ip * nw + k);
+                    dst[0] += ar * er - ai * ei;
+                    dst[1] += ar * ei + ai * er;
+                }
+            }
+        }
+        #pragma omp critical
+        {
+            for (int64_t i = 0; i < 2 * npix * nw; ++i) acc[i] += lacc[i];
+            kept_total += kept;
+            sumw_total += sumw;
+        }
+        free(lacc);
+    }
+    free(cs);
+    *sum_w_out = sumw_total;
+    return kept_total;
+}
