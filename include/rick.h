@@ -1,0 +1,212 @@
+/*
+ * rick.h -- C ABI of the MI355X (gfx950) w-stacking imager.
+ *
+ * The library computes a dirty image from interferometric visibilities by
+ * w-stacking (Sec. 2.1 of "Green computing toward SKA era with RICK",
+ * arXiv:2504.00959): every visibility is mapped to the closest w-plane and
+ * convolved onto that plane's (u, v) mesh with a finite Gaussian or
+ * Kaiser-Bessel kernel (Eq. 3), every plane is inverse-FFT'd, plane k is
+ * multiplied by the w phase screen exp(+2 pi i w_k (n - 1)) and the planes
+ * are summed into the image (Eq. 1, whose visibility model is Eq. 2).
+ *
+ * Four calls make one image, each asynchronous on the caller's stream:
+ *   rick_grid          bin-and-sort by (w-plane, uv tile), then LDS-tiled gridding
+ *   rick_fft_planes    batched, centred 2-D inverse FFT of every plane
+ *   rick_wstack_image  phase screen + sum over planes + normalisation
+ *   rick_reset         start a new image (clears the weight sum and counters)
+ *
+ * Conventions shared by every call:
+ *   - All entry points return a rick_status; no exception, abort or exit
+ *     crosses the ABI.  Arguments are validated on the host before any
+ *     device work is queued.  A launch failure returns RICK_E_HIP; a fault
+ *     inside a kernel surfaces at the caller's next synchronisation.
+ *   - Device pointers are HIP device (or managed) addresses on the plan's
+ *     device.  Host pointers are ordinary process memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - A plan is used by one host thread and one stream at a time; distinct
+ *     plans are independent.
+ *   - The plan owns every device buffer it allocates; rick_plan allocates
+ *     them all once, the other calls allocate nothing.
+ *
+ * Coordinates (the paper leaves them implicit; these are this library's):
+ *   cell i of the N-cell axis sits at u_i = (i - N/2) du, du = 1 / FoV;
+ *   pixel p sits at l_p = (p - N/2) dl, dl = FoV / N; the mesh and the
+ *   image are row-major with rows along v (resp. m) and columns along u
+ *   (resp. l); the image is Re of the plane sum times n = sqrt(1 - l^2 - m^2)
+ *   divided by the sum of gridded weights and by the kernel taper
+ *   C(l') C(m'); pixels with l^2 + m^2 >= 1 are 0.
+ */
+#ifndef RICK_H
+#define RICK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rick_status;
+
+enum {
+    RICK_OK = 0,
+    RICK_E_INVALID_ARG = 1,   /* bad pointer, size, alignment or plan parameter */
+    RICK_E_NO_DEVICE = 2,     /* no HIP device, or the requested ordinal does not exist */
+    RICK_E_OOM = 3,           /* the plan's buffers do not fit the device's free memory */
+    RICK_E_HIP = 4,           /* a HIP runtime call or kernel launch failed */
+    RICK_E_CAPACITY = 5,      /* nrow * nchan exceeds the plan's max_vis */
+    RICK_E_BAD_PLAN = 6,      /* NULL or destroyed plan handle */
+    RICK_E_STATE = 7,         /* call out of order (e.g. rick_wstack_image before rick_fft_planes) */
+    RICK_E_UNSUPPORTED = 8    /* valid but not built (e.g. a grid size without an FFT kernel) */
+};
+
+enum { RICK_KERNEL_GAUSSIAN = 0, RICK_KERNEL_KAISER_BESSEL = 1 };
+
+enum {
+    RICK_PREC_FP32 = 0,        /* float mesh, FFT and plane sum; float64 phase argument and normalisation */
+    RICK_PREC_FP32_KAHAN = 1,  /* as FP32, compensated (Kahan) summation over w-planes */
+    RICK_PREC_FP64 = 2         /* every step in float64 (complex128 mesh) */
+};
+
+enum { RICK_FLAG_TIMING = 1 }; /* record per-kernel HIP events; read them with rick_plan_info */
+
+/* Plan parameters (Sec. 2.1: mesh N_u x N_v x N_w, kernel type and support). */
+typedef struct rick_plan_desc {
+    int32_t grid_n;        /* N = N_u = N_v: power of two, 64..8192 */
+    int32_t n_wplanes;     /* N_w >= 1 */
+    int32_t support;       /* kernel support W in cells: odd, 1..15 */
+    int32_t oversample;    /* OS sub-cell positions per cell: power of two, 1..256 */
+    int32_t kernel;        /* RICK_KERNEL_* */
+    int32_t precision;     /* RICK_PREC_* */
+    double kernel_param;   /* Gaussian sigma in cells, or Kaiser-Bessel beta; <= 0 selects the default
+                              (sigma with g(W/2) = 1e-3; beta of Beatty et al. 2005 at alpha = 2) */
+    double fov_rad;        /* field of view FoV: 0 < FoV and FoV^2 / 2 < 1 (image corners inside the sky) */
+    double w_min, w_max;   /* w range in wavelengths covered by the planes; w_max > w_min.  Plane k
+                              spans [w_min + k dw, w_min + (k+1) dw), dw = (w_max - w_min) / N_w, with
+                              centre w_k; w outside the range goes to the nearest end plane. */
+    int64_t max_vis;       /* largest nrow * nchan one rick_grid call accepts; 1..2^29 */
+    int32_t device;        /* HIP device ordinal */
+    int32_t flags;         /* RICK_FLAG_* */
+    int32_t tile;          /* uv tile edge T in cells for binning and gridding: 0 = default (64), else a
+                              power of two 16..128 with T >= W */
+    int32_t chunk;         /* largest number of binned records one gridding block takes: 0 = default */
+} rick_plan_desc;
+
+typedef struct rick_plan_s rick_plan_t;   /* opaque plan handle */
+
+/* Counters and layout of a plan (read back synchronously). */
+typedef struct rick_plan_info_t {
+    int64_t n_gridded;       /* visibilities gridded since the last reset */
+    int64_t n_dropped;       /* visibilities dropped since the last reset (non-finite input, weight <= 0,
+                                kernel footprint leaving the mesh) */
+    int64_t n_records;       /* binned records written by the last rick_grid (a visibility whose footprint
+                                straddles tile edges is binned once per tile it touches) */
+    double sum_weights;      /* sum of the weights of gridded visibilities since the last reset */
+    double du, dl, dw;       /* cell size [wavelengths], pixel size [rad], plane width [wavelengths] */
+    void *mesh;              /* device pointer to the planes, [N_w][N][N] complex64 (complex128 in FP64
+                                mode), interleaved (re, im): G_k after rick_grid, F_k after rick_fft_planes */
+    int64_t mesh_bytes;
+    int32_t tile, chunk;     /* effective tile edge and chunk size */
+    int32_t state;           /* 0 = empty, 1 = gridded, 2 = transformed */
+    int32_t n_timers;        /* number of valid entries in kernel_ms / kernel_calls / kernel_names */
+    float kernel_ms[16];     /* with RICK_FLAG_TIMING: mean device time per launch of each kernel over the
+                                launches since the previous rick_plan_info (the last 64 at most) */
+    int32_t kernel_calls[16];/* launches the mean covers */
+    const char *kernel_names[16];
+} rick_plan_info_t;
+
+/*
+ * rick_plan -- validate `d`, build the kernel tap table, the taper C(l'),
+ * the plane centres w_k and the FFT twiddles in float64 on the host, and
+ * allocate every device buffer the plan needs (mesh, binning scratch,
+ * tables) once.  Device memory is checked against hipMemGetInfo first.
+ * On success *out receives the plan; on failure *out is NULL.
+ * Errors: RICK_E_INVALID_ARG, RICK_E_NO_DEVICE, RICK_E_OOM, RICK_E_HIP,
+ * RICK_E_UNSUPPORTED.
+ */
+rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out);
+
+/*
+ * rick_grid -- map visibilities to the closest w-plane and convolve them onto
+ * the mesh (Sec. 2.1, Eq. 3), accumulating onto what earlier rick_grid calls
+ * since the last reset gridded (frequency or time chunks, Sec. 2.2).
+ *   uvw      device, float64 [nrow][3]: metres if freq_hz != NULL, else wavelengths
+ *   freq_hz  HOST, float64 [nchan] channel frequencies, or NULL (then nchan must be 1)
+ *   vis      device, complex64 [nrow][nchan] interleaved (re, im) (complex128 in FP64 mode)
+ *   weight   device, float32 [nrow][nchan], or NULL for unit weights
+ * u [wavelengths] = uvw[r][0] * freq_hz[c] / c0, c0 = 299792458 m/s, and
+ * likewise v, w.  Position quantised to 1/OS cell, nearest cell, plane by
+ * floor((w - w_min) / dw) clamped; a visibility is dropped (counted, not an
+ * error) if any input is non-finite, its weight is <= 0 or its W x W
+ * footprint leaves the mesh.  uvw and vis must be 8-byte (16-byte in FP64
+ * mode) aligned.  Inputs must stay alive until `stream` reaches this work.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL pointer, nrow < 0,
+ * nchan < 1, nchan > 1 without freq_hz, misalignment, non-finite or
+ * non-positive frequency), RICK_E_CAPACITY, RICK_E_STATE (after
+ * rick_fft_planes without a reset), RICK_E_HIP.
+ */
+rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                      const float *weight, int64_t nrow, int32_t nchan, void *stream);
+
+/*
+ * rick_fft_planes -- in place, every plane becomes its centred inverse DFT
+ * (the FFT step of Sec. 2.1):
+ *   F_k[q][p] = sum_{j,i} G_k[j][i] exp(+2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
+ * (unnormalised).  Requires a gridded mesh (RICK_E_STATE otherwise; a mesh
+ * that nothing was gridded onto since the reset is transformed as zeros).
+ * Errors: RICK_E_BAD_PLAN, RICK_E_STATE, RICK_E_HIP.
+ */
+rick_status rick_fft_planes(rick_plan_t *p, void *stream);
+
+/*
+ * rick_wstack_image -- w-correction and plane reduction (Sec. 2.1, Eq. 1):
+ *   I[q][p] = n_pq sum_k Re(exp(+2 pi i w_k (n_pq - 1)) F_k[q][p]) / (C(l'_p) C(l'_q) sum W)
+ * with n - 1 formed as -r^2 / (1 + sqrt(1 - r^2)) in float64, the phase
+ * w_k (n - 1) formed and range-reduced in float64, and the sum over planes
+ * in the plan's precision.  `image` is device float32 [N][N] (float64 in FP64
+ * mode), owned by the caller.  May be called again on the same planes.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL image), RICK_E_STATE
+ * (planes not transformed), RICK_E_HIP.
+ */
+rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream);
+
+/*
+ * rick_reset -- begin a new image: zero the weight sum and the counters;
+ * the next rick_grid overwrites the mesh instead of accumulating.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_HIP.
+ */
+rick_status rick_reset(rick_plan_t *p, void *stream);
+
+/*
+ * rick_plan_info -- fill *out.  Synchronises the plan's device (it copies
+ * counters back), so call it outside timed regions.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL out), RICK_E_HIP.
+ */
+rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out);
+
+/*
+ * rick_plan_destroy -- free every buffer of the plan.  The caller must have
+ * synchronised the streams that used it.  Destroying NULL returns
+ * RICK_E_BAD_PLAN; the handle is invalid afterwards.
+ */
+rick_status rick_plan_destroy(rick_plan_t *p);
+
+/*
+ * rick_plan_bin_counts -- copy the per-bin record counts of the last
+ * rick_grid to HOST memory `counts` [n], n = N_w * (N/T)^2, bin index
+ * (k * (N/T) + tile_row) * (N/T) + tile_col.  A visibility adds one record
+ * to every tile its W x W footprint touches.  Synchronises the device.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL counts, wrong n), RICK_E_HIP.
+ */
+rick_status rick_plan_bin_counts(rick_plan_t *p, int32_t *counts, int64_t n);
+
+/* Static message for a status code (never NULL). */
+const char *rick_status_str(rick_status s);
+
+/* Detail of the last failing call on this host thread (static storage, never NULL). */
+const char *rick_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RICK_H */

@@ -79,7 +79,7 @@ int64_t oracle_wstack_pixels(
                 if (!(wt > 0.0)) continue;
                 if (cx - h < 0 || cx + h > N - 1 || cy - h < 0 || cy + h > N - 1) continue;
                 double kf = floor((w - w_min) / dw);
-                if (!isfinite(kf)) kf = 0.0;
+                if (isnan(kf)) kf = 0.0;   /* w outside the range -> nearest end plane */
                 if (kf < 0.0) kf = 0.0;
                 if (kf > (double)(nw - 1)) kf = (double)(nw - 1);
                 const int64_t k = (int64_t)kf;

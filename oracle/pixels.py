@@ -71,6 +71,8 @@ def wstack_pixels(uvw, freq, vis, weight, pix_p, pix_q, *, grid_n, n_wplanes, su
     tr = tau - np.rint(tau)
     S = (np.cos(2 * np.pi * tr) * F.real - np.sin(2 * np.pi * tr) * F.imag).sum(axis=1)
     corr = grid_correction(table, grid_n)
+    if not sum_w.value > 0.0:
+        return np.zeros(npix), F, int(kept), 0.0
     img = (1.0 + nm1z) * S / (corr[pix_p] * corr[pix_q] * sum_w.value)
     return np.where(inside, img, 0.0), F, int(kept), float(sum_w.value)
 

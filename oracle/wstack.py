@@ -199,9 +199,9 @@ def bin_visibilities(uvw, freq, vis, weight, *, grid_n, n_wplanes, support, over
     sx = X - cx * OS
     sy = Y - cy * OS
     dw = (w_max - w_min) / n_wplanes
-    with np.errstate(invalid="ignore"):
+    with np.errstate(invalid="ignore", over="ignore"):
         kf = np.floor((w - w_min) / dw)
-        kf = np.where(np.isfinite(kf), kf, 0.0)
+        kf = np.where(np.isnan(kf), 0.0, kf)      # w outside the range -> nearest end plane
     k = np.clip(kf, 0, n_wplanes - 1).astype(np.int64)
     keep = (ok & (wt > 0) & (cx - h >= 0) & (cx + h <= N - 1) & (cy - h >= 0) & (cy + h <= N - 1))
     with np.errstate(invalid="ignore"):
@@ -223,22 +223,32 @@ def grid(b: Binned, table: np.ndarray, *, grid_n, n_wplanes) -> np.ndarray:
     OS, support = table.shape
     h = (support - 1) // 2
     N = grid_n
-    idx = np.nonzero(b.keep)[0]
-    cx, cy, k = b.cx[idx], b.cy[idx], b.k[idx]
+    G = np.zeros((n_wplanes, N, N), dtype=np.complex128)
+    keep = np.nonzero(b.keep)[0]
+    for kk in range(n_wplanes):
+        grid_plane(G[kk], b, keep[b.k[keep] == kk], table)
+    return G
+
+
+def grid_plane(Gk: np.ndarray, b: Binned, idx: np.ndarray, table: np.ndarray) -> None:
+    """Add the visibilities ``idx`` (all of one plane) onto plane ``Gk`` [N][N]:
+    Gk[c_y + t_y - h][c_x + t_x - h] += W V g_{s_y}[t_y] g_{s_x}[t_x]."""
+    OS, support = table.shape
+    h = (support - 1) // 2
+    N = Gk.shape[-1]
+    if idx.size == 0:
+        return
+    t = np.arange(support) - h
     gx = table[b.sx[idx] + OS // 2]          # [n, W]
     gy = table[b.sy[idx] + OS // 2]
-    wv = b.wv[idx]
-    size = n_wplanes * N * N
-    acc_re = np.zeros(size)
-    acc_im = np.zeros(size)
-    for ty in range(support):
-        row = (k * N + (cy + ty - h)) * N
-        for tx in range(support):
-            cell = row + (cx + tx - h)
-            wgt = gy[:, ty] * gx[:, tx]
-            acc_re += np.bincount(cell, weights=wv.real * wgt, minlength=size)
-            acc_im += np.bincount(cell, weights=wv.imag * wgt, minlength=size)
-    return (acc_re + 1j * acc_im).reshape(n_wplanes, N, N)
+    rows = (b.cy[idx][:, None] + t[None, :]) * N            # [n, W]
+    cols = b.cx[idx][:, None] + t[None, :]
+    cell = (rows[:, :, None] + cols[:, None, :]).reshape(-1)                 # [n * W * W]
+    wgt = (gy[:, :, None] * gx[:, None, :]).reshape(idx.size, -1)           # [n, W * W]
+    wv = b.wv[idx][:, None]
+    re = np.bincount(cell, weights=(wv.real * wgt).reshape(-1), minlength=N * N)
+    im = np.bincount(cell, weights=(wv.imag * wgt).reshape(-1), minlength=N * N)
+    Gk += (re + 1j * im).reshape(N, N)
 
 
 # ---------------------------------------------------------------------------
@@ -272,8 +282,11 @@ def screen_sum(F: np.ndarray, w_k: np.ndarray, fov: float) -> np.ndarray:
 
 
 def normalise(S: np.ndarray, corr: np.ndarray, sum_w: float, fov: float) -> np.ndarray:
-    """I[q][p] = n_pq S[q][p] / (C(l'_p) C(l'_q) sum W); zero outside the unit circle."""
+    """I[q][p] = n_pq S[q][p] / (C(l'_p) C(l'_q) sum W); zero outside the unit circle,
+    and zero everywhere when no visibility was gridded (sum W = 0)."""
     N = S.shape[-1]
+    if not sum_w > 0.0:
+        return np.zeros_like(S)
     l = pixel_lm(N, fov)
     nm1 = nm1_of(l[None, :], l[:, None])
     inside = np.isfinite(nm1)

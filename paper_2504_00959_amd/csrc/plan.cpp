@@ -1,0 +1,614 @@
+// Host side of the w-stacking imager: argument validation, float64 tables,
+// one-time device allocation, and the C ABI entry points of include/rick.h.
+//
+// Everything the device needs is allocated in rick_plan; the per-image
+// calls only queue kernels on the caller's stream (the paper's GPU gridder
+// lost most of its time to per-sector hipMalloc/hipFree, Sec. 4.2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rick_internal.h"
+
+using namespace rick;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x5249434bu;  // "RICK"
+constexpr uint32_t kDead = 0xdeadbeefu;
+
+thread_local char g_err[512] = "";
+
+rick_status fail(rick_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+rick_status hip_fail(hipError_t e, const char *what) {
+    return fail(RICK_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int64_t x) {
+    int r = 0;
+    while ((int64_t(1) << r) < x) ++r;
+    return r;
+}
+
+// Modified Bessel function I0 from its power series sum ((x/2)^k / k!)^2.
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / (double(k) * double(k));
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+// Continuous kernel g(d), zero for |d| >= W/2 (Sec. 2.1: Gaussian or Kaiser-Bessel).
+double kernel_at(double d, int W, int kind, double param) {
+    const double half = 0.5 * W;
+    if (!(std::fabs(d) < half)) return 0.0;
+    if (kind == RICK_KERNEL_GAUSSIAN) {
+        return std::exp(-d * d / (2.0 * param * param));
+    }
+    const double a = 1.0 - (2.0 * d / W) * (2.0 * d / W);
+    return bessel_i0(param * std::sqrt(a > 0.0 ? a : 0.0)) / bessel_i0(param);
+}
+
+double default_param(int W, int kind) {
+    if (kind == RICK_KERNEL_GAUSSIAN) return (0.5 * W) / std::sqrt(2.0 * std::log(1000.0));
+    // Beatty, Nishimura & Pauly (2005), oversampling ratio 2
+    const double alpha = 2.0;
+    const double x = (W / alpha) * (W / alpha) * (alpha - 0.5) * (alpha - 0.5) - 0.8;
+    return x > 0.0 ? M_PI * std::sqrt(x) : 0.0;
+}
+
+}  // namespace
+
+struct rick_plan_s {
+    uint32_t magic;
+    rick_plan_desc d;
+    Geom g;
+    bool fp64;
+    int state;               // 0 empty, 1 gridded, 2 transformed
+    bool mesh_written;       // a rick_grid since the last reset wrote every tile
+    double du, dl;
+    int64_t max_items;       // gridding launch bound per visibility (items <= nbins + 4 nvis / CH)
+    size_t real_bytes;
+    // device buffers
+    void *mesh = nullptr;
+    size_t mesh_bytes = 0;
+    void *lut = nullptr;
+    void *twiddle = nullptr;
+    double *corr = nullptr;
+    double *wk = nullptr;
+    double *scales = nullptr;
+    Stats *stats = nullptr;
+    int32_t *counts = nullptr;
+    BinScan *scan = nullptr;
+    int32_t *block_sums = nullptr;
+    int32_t *cursor = nullptr;
+    uint32_t *rec_pos = nullptr;
+    void *rec_vis = nullptr;
+    int64_t rec_cap = 0;
+    // host copies of tables (for tests and info)
+    std::vector<double> lut_host, corr_host, wk_host;
+    // timing: per kernel slot a ring of (start, stop) event pairs
+    hipEvent_t ev[kMaxTimers][2 * kTimerRing] = {};
+    const char *ev_name[kMaxTimers] = {};
+    int64_t ev_calls[kMaxTimers] = {};
+    bool timing = false;
+};
+
+namespace {
+
+bool plan_ok(const rick_plan_t *p) { return p != nullptr && p->magic == kMagic; }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void free_all(rick_plan_t *p) {
+    void *bufs[] = {p->mesh, p->lut, p->twiddle, p->corr, p->wk, p->scales, p->stats, p->counts,
+                    p->scan, p->block_sums, p->cursor, p->rec_pos, p->rec_vis};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (int i = 0; i < kMaxTimers; ++i)
+        for (int j = 0; j < 2 * kTimerRing; ++j)
+            if (p->ev[i][j]) (void)hipEventDestroy(p->ev[i][j]);
+}
+
+rick_status validate(const rick_plan_desc *d) {
+    if (!d) return fail(RICK_E_INVALID_ARG, "desc is NULL");
+    if (!is_pow2(d->grid_n) || d->grid_n < 64 || d->grid_n > 8192)
+        return fail(RICK_E_INVALID_ARG, "grid_n=%d: must be a power of two in [64, 8192]", d->grid_n);
+    if (d->n_wplanes < 1 || d->n_wplanes > 65536)
+        return fail(RICK_E_INVALID_ARG, "n_wplanes=%d: must be in [1, 65536]", d->n_wplanes);
+    if (d->support < 1 || d->support > 15 || (d->support & 1) == 0)
+        return fail(RICK_E_INVALID_ARG, "support=%d: must be odd in [1, 15]", d->support);
+    if (!is_pow2(d->oversample) || d->oversample > 256)
+        return fail(RICK_E_INVALID_ARG, "oversample=%d: must be a power of two in [1, 256]", d->oversample);
+    if (d->kernel != RICK_KERNEL_GAUSSIAN && d->kernel != RICK_KERNEL_KAISER_BESSEL)
+        return fail(RICK_E_INVALID_ARG, "kernel=%d: unknown", d->kernel);
+    if (d->precision < RICK_PREC_FP32 || d->precision > RICK_PREC_FP64)
+        return fail(RICK_E_INVALID_ARG, "precision=%d: unknown", d->precision);
+    if (!std::isfinite(d->kernel_param))
+        return fail(RICK_E_INVALID_ARG, "kernel_param is not finite");
+    if (!(d->fov_rad > 0.0) || !(d->fov_rad * d->fov_rad / 2.0 < 1.0))
+        return fail(RICK_E_INVALID_ARG, "fov_rad=%g: need 0 < fov and fov^2/2 < 1", d->fov_rad);
+    if (!std::isfinite(d->w_min) || !std::isfinite(d->w_max) || !(d->w_max > d->w_min))
+        return fail(RICK_E_INVALID_ARG, "w range [%g, %g]: need finite w_min < w_max", d->w_min, d->w_max);
+    if (d->max_vis < 1 || d->max_vis >= (int64_t(1) << 29))
+        return fail(RICK_E_INVALID_ARG, "max_vis=%lld: must be in [1, 2^29)", (long long)d->max_vis);
+    if (d->device < 0) return fail(RICK_E_INVALID_ARG, "device=%d", d->device);
+    if (d->flags & ~int32_t(RICK_FLAG_TIMING)) return fail(RICK_E_INVALID_ARG, "flags=%d: unknown bits", d->flags);
+    if (d->tile != 0) {
+        if (!is_pow2(d->tile) || d->tile < 16 || d->tile > 128 || d->tile < d->support || d->tile > d->grid_n)
+            return fail(RICK_E_INVALID_ARG, "tile=%d: power of two in [16, 128], >= support, <= grid_n", d->tile);
+    }
+    if (d->chunk < 0 || d->chunk > (1 << 24)) return fail(RICK_E_INVALID_ARG, "chunk=%d", d->chunk);
+    return RICK_OK;
+}
+
+// Timer slots: per kernel a ring of (start, stop) event pairs, so that the
+// mean over every launch since the last rick_plan_info can be reported.
+void timer_begin(rick_plan_t *p, int slot, const char *name, hipStream_t s) {
+    if (!p->timing) return;
+    p->ev_name[slot] = name;
+    const int r = int(p->ev_calls[slot] % kTimerRing);
+    (void)hipEventRecord(p->ev[slot][2 * r], s);
+}
+void timer_end(rick_plan_t *p, int slot, hipStream_t s) {
+    if (!p->timing) return;
+    const int r = int(p->ev_calls[slot] % kTimerRing);
+    (void)hipEventRecord(p->ev[slot][2 * r + 1], s);
+    ++p->ev_calls[slot];
+}
+
+enum TimerSlot { T_COUNT = 0, T_SCAN, T_SCATTER, T_ZERO_HEAVY, T_GRID, T_FFT_ROWS, T_FFT_COLS, T_SCREEN, T_RESET };
+
+}  // namespace
+
+extern "C" {
+
+const char *rick_status_str(rick_status s) {
+    switch (s) {
+        case RICK_OK: return "success";
+        case RICK_E_INVALID_ARG: return "invalid argument";
+        case RICK_E_NO_DEVICE: return "no usable HIP device";
+        case RICK_E_OOM: return "not enough device memory for the plan";
+        case RICK_E_HIP: return "HIP runtime error";
+        case RICK_E_CAPACITY: return "more visibilities than the plan's max_vis";
+        case RICK_E_BAD_PLAN: return "invalid plan handle";
+        case RICK_E_STATE: return "call out of order for the plan's state";
+        case RICK_E_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char *rick_last_error(void) { return g_err; }
+
+rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
+    if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    rick_status st = validate(d);
+    if (st != RICK_OK) return st;
+    if (!fft_supported(d->grid_n)) return fail(RICK_E_UNSUPPORTED, "no FFT kernel for N=%d", d->grid_n);
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(RICK_E_NO_DEVICE, "no HIP device available");
+    if (d->device >= ndev) return fail(RICK_E_NO_DEVICE, "device %d of %d", d->device, ndev);
+
+    rick_plan_t *p = new (std::nothrow) rick_plan_t();
+    if (!p) return fail(RICK_E_OOM, "host allocation");
+    p->magic = kMagic;
+    p->d = *d;
+    p->fp64 = d->precision == RICK_PREC_FP64;
+    p->real_bytes = p->fp64 ? 8 : 4;
+    p->timing = (d->flags & RICK_FLAG_TIMING) != 0;
+
+    Geom &g = p->g;
+    g.N = d->grid_n;
+    g.Nw = d->n_wplanes;
+    g.W = d->support;
+    g.h = (d->support - 1) / 2;
+    g.OS = d->oversample;
+    g.log2OS = ilog2(d->oversample);
+    g.T = d->tile ? d->tile : (g.N >= 64 ? 64 : g.N);
+    if (g.T < g.W) g.T = 16 >= g.W ? 16 : 32;
+    g.log2T = ilog2(g.T);
+    g.nt = g.N / g.T;
+    const int64_t nbins64 = int64_t(g.Nw) * g.nt * g.nt;
+    if (nbins64 >= (int64_t(1) << 30)) {
+        delete p;
+        return fail(RICK_E_INVALID_ARG, "too many (plane, tile) bins: %lld", (long long)nbins64);
+    }
+    g.nbins = int32_t(nbins64);
+    g.CH = d->chunk ? d->chunk : 8192;
+    {
+        // LDS row pitch congruent to W mod 32 floats: a W x W footprint then
+        // spreads over distinct banks (one tap per lane, see grid.hip)
+        int pitch = g.T;
+        while ((pitch - g.W) % 32 != 0) ++pitch;
+        g.pitch = pitch;
+    }
+    g.fov = d->fov_rad;
+    g.half = double(int64_t(g.N) * g.OS) / 2.0;
+    g.w_min = d->w_min;
+    g.dw = (d->w_max - d->w_min) / double(g.Nw);
+    p->du = 1.0 / d->fov_rad;
+    p->dl = d->fov_rad / g.N;
+    p->rec_cap = 4 * d->max_vis;
+    p->max_items = g.nbins + (p->rec_cap + g.CH - 1) / g.CH;
+
+    // ---- float64 tables on the host ----
+    const double param = d->kernel_param > 0 ? d->kernel_param : default_param(g.W, d->kernel);
+    if (!(param > 0.0) && d->kernel == RICK_KERNEL_GAUSSIAN) {
+        delete p;
+        return fail(RICK_E_INVALID_ARG, "Gaussian width must be positive");
+    }
+    p->lut_host.assign(size_t(g.OS) * g.W, 0.0);
+    for (int r = 0; r < g.OS; ++r) {
+        const int s = r - g.OS / 2;
+        double sum = 0.0;
+        for (int t = 0; t < g.W; ++t) {
+            const double dist = double(t - g.h) - double(s) / g.OS;
+            p->lut_host[size_t(r) * g.W + t] = kernel_at(dist, g.W, d->kernel, param);
+            sum += p->lut_host[size_t(r) * g.W + t];
+        }
+        for (int t = 0; t < g.W; ++t) p->lut_host[size_t(r) * g.W + t] /= sum;
+    }
+    // taper C(l') = (1/OS) sum_s sum_t g_s[t] cos(2 pi (t - h - s/OS) l'), l' = (p - N/2)/N
+    p->corr_host.assign(g.N, 0.0);
+    for (int px = 0; px < g.N; ++px) {
+        const double lp = double(px - g.N / 2) / g.N;
+        double c = 0.0;
+        for (int r = 0; r < g.OS; ++r) {
+            const int s = r - g.OS / 2;
+            for (int t = 0; t < g.W; ++t) {
+                const double dist = double(t - g.h) - double(s) / g.OS;
+                c += p->lut_host[size_t(r) * g.W + t] * std::cos(2.0 * M_PI * dist * lp);
+            }
+        }
+        p->corr_host[px] = c / g.OS;
+    }
+    p->wk_host.resize(g.Nw);
+    for (int k = 0; k < g.Nw; ++k) p->wk_host[k] = d->w_min + (double(k) + 0.5) * g.dw;
+
+    // ---- device allocation, once ----
+    DeviceGuard guard(d->device);
+    const size_t rb = p->real_bytes;
+    p->mesh_bytes = size_t(g.Nw) * g.N * g.N * 2 * rb;
+    const size_t sz_lut = size_t(g.OS) * g.W * rb;
+    const size_t sz_tw = size_t(g.N) * 2 * rb;
+    const size_t sz_counts = size_t(g.nbins + 1) * sizeof(int32_t);
+    const size_t sz_scan = size_t(g.nbins + 1) * sizeof(BinScan);
+    const size_t n_blk = (size_t(g.nbins) + 1 + 2047) / 2048 + 1;
+    const size_t sz_bsum = n_blk * 2 * sizeof(int32_t) + 64;
+    const size_t sz_pos = size_t(p->rec_cap) * sizeof(uint32_t);
+    const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
+    const size_t total = p->mesh_bytes + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
+                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_counts +
+                         sz_pos + sz_rvis;
+    size_t free_b = 0, total_b = 0;
+    hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMemGetInfo");
+    }
+    if (total + (size_t(256) << 20) > free_b) {
+        delete p;
+        return fail(RICK_E_OOM, "plan needs %.3f GB, device has %.3f GB free", total / 1e9, free_b / 1e9);
+    }
+#define ALLOC(ptr, bytes)                                        \
+    do {                                                         \
+        e = hipMalloc((void **)&(ptr), (bytes));                 \
+        if (e != hipSuccess) {                                   \
+            free_all(p);                                         \
+            delete p;                                            \
+            return e == hipErrorOutOfMemory ? fail(RICK_E_OOM, "hipMalloc %zu bytes", size_t(bytes)) \
+                                            : hip_fail(e, "hipMalloc");                               \
+        }                                                        \
+    } while (0)
+    ALLOC(p->mesh, p->mesh_bytes);
+    ALLOC(p->lut, sz_lut);
+    ALLOC(p->twiddle, sz_tw);
+    ALLOC(p->corr, size_t(g.N) * 8);
+    ALLOC(p->wk, size_t(g.Nw) * 8);
+    ALLOC(p->scales, size_t(kMaxChan) * 8);
+    ALLOC(p->stats, sizeof(Stats));
+    ALLOC(p->counts, sz_counts);
+    ALLOC(p->scan, sz_scan);
+    ALLOC(p->block_sums, sz_bsum);
+    ALLOC(p->cursor, sz_counts);
+    ALLOC(p->rec_pos, sz_pos);
+    ALLOC(p->rec_vis, sz_rvis);
+#undef ALLOC
+
+    // tables: tap LUT and twiddles rounded to the plan's real type
+    std::vector<double> tw(size_t(g.N) * 2);
+    for (int i = 0; i < g.N; ++i) {
+        // exp(+2 pi i i / N), evaluated in long double and rounded
+        const long double a = 2.0L * M_PI * (long double)i / (long double)g.N;
+        tw[2 * i] = (double)std::cos(a);
+        tw[2 * i + 1] = (double)std::sin(a);
+    }
+    std::vector<char> lut_dev(sz_lut), tw_dev(sz_tw);
+    if (p->fp64) {
+        std::memcpy(lut_dev.data(), p->lut_host.data(), sz_lut);
+        std::memcpy(tw_dev.data(), tw.data(), sz_tw);
+    } else {
+        float *lf = reinterpret_cast<float *>(lut_dev.data());
+        for (size_t i = 0; i < p->lut_host.size(); ++i) lf[i] = float(p->lut_host[i]);
+        float *tf = reinterpret_cast<float *>(tw_dev.data());
+        for (size_t i = 0; i < tw.size(); ++i) tf[i] = float(tw[i]);
+    }
+    struct Cp { void *dst; const void *src; size_t n; } cps[] = {
+        {p->lut, lut_dev.data(), sz_lut},
+        {p->twiddle, tw_dev.data(), sz_tw},
+        {p->corr, p->corr_host.data(), size_t(g.N) * 8},
+        {p->wk, p->wk_host.data(), size_t(g.Nw) * 8},
+    };
+    for (auto &c : cps) {
+        e = hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_all(p);
+            delete p;
+            return hip_fail(e, "hipMemcpy tables");
+        }
+    }
+    e = hipMemset(p->stats, 0, sizeof(Stats));
+    if (e == hipSuccess) e = hipMemset(p->mesh, 0, p->mesh_bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_all(p);
+        delete p;
+        return hip_fail(e, "plan initialisation");
+    }
+    if (p->timing) {
+        for (int i = 0; i < kMaxTimers; ++i) {
+            for (int j = 0; j < 2 * kTimerRing; ++j) {
+                e = hipEventCreate(&p->ev[i][j]);
+                if (e != hipSuccess) {
+                    free_all(p);
+                    delete p;
+                    return hip_fail(e, "hipEventCreate");
+                }
+            }
+        }
+    }
+    p->state = 0;
+    p->mesh_written = false;
+    *out = p;
+    return RICK_OK;
+}
+
+rick_status rick_plan_destroy(rick_plan_t *p) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    DeviceGuard guard(p->d.device);
+    free_all(p);
+    p->magic = kDead;
+    delete p;
+    return RICK_OK;
+}
+
+rick_status rick_reset(rick_plan_t *p, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    timer_begin(p, T_RESET, "reset", s);
+    hipError_t e = launch_zero_stats(p->stats, s);
+    timer_end(p, T_RESET, s);
+    if (e != hipSuccess) return hip_fail(e, "reset");
+    p->state = 0;
+    p->mesh_written = false;
+    return RICK_OK;
+}
+
+rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                      const float *weight, int64_t nrow, int32_t nchan, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
+    if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
+    if (!freq_hz && nchan != 1) return fail(RICK_E_INVALID_ARG, "nchan=%d without freq_hz", nchan);
+    if (nchan > kMaxChan) return fail(RICK_E_INVALID_ARG, "nchan=%d > %d", nchan, kMaxChan);
+    if (nrow > 0 && (!uvw || !vis)) return fail(RICK_E_INVALID_ARG, "uvw or vis is NULL");
+    if (((uintptr_t)uvw & 7) || ((uintptr_t)vis & (p->fp64 ? 15 : 7)) || ((uintptr_t)weight & 3))
+        return fail(RICK_E_INVALID_ARG, "misaligned input pointer");
+    if (nrow * int64_t(nchan) > p->d.max_vis)
+        return fail(RICK_E_CAPACITY, "nrow*nchan=%lld > max_vis=%lld", (long long)(nrow * nchan),
+                    (long long)p->d.max_vis);
+    if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed; call rick_reset first");
+    std::vector<double> sc(nchan, 1.0);
+    if (freq_hz) {
+        for (int c = 0; c < nchan; ++c) {
+            if (!std::isfinite(freq_hz[c]) || !(freq_hz[c] > 0.0))
+                return fail(RICK_E_INVALID_ARG, "freq_hz[%d]=%g", c, freq_hz[c]);
+            sc[c] = freq_hz[c] / kC0;
+        }
+    }
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_set_scales(p->scales, sc.data(), nchan, s);
+    if (e != hipSuccess) return hip_fail(e, "channel scales upload");
+    const Geom &g = p->g;
+    const int accumulate = p->mesh_written ? 1 : 0;
+    const int64_t nvis = nrow * nchan;
+    const int32_t max_items = int32_t(g.nbins + (4 * nvis + g.CH - 1) / g.CH);
+
+    timer_begin(p, T_COUNT, "bin_count", s);
+    e = launch_reset_counts(p->counts, g.nbins + 1, s);
+    if (e == hipSuccess) {
+        if (p->fp64)
+            e = launch_bin_count<double>(g, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
+                                         p->counts, p->stats, s);
+        else
+            e = launch_bin_count<float>(g, uvw, p->scales, (const float *)vis, weight, nrow, nchan,
+                                        p->counts, p->stats, s);
+    }
+    timer_end(p, T_COUNT, s);
+    if (e != hipSuccess) return hip_fail(e, "bin_count");
+    timer_begin(p, T_SCAN, "bin_scan", s);
+    e = launch_bin_scan(g, p->counts, p->scan, p->block_sums, p->cursor, p->stats, s);
+    timer_end(p, T_SCAN, s);
+    if (e != hipSuccess) return hip_fail(e, "bin_scan");
+    timer_begin(p, T_SCATTER, "bin_scatter", s);
+    if (p->fp64)
+        e = launch_bin_scatter<double>(g, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
+                                       p->cursor, p->rec_pos, (double *)p->rec_vis, s);
+    else
+        e = launch_bin_scatter<float>(g, uvw, p->scales, (const float *)vis, weight, nrow, nchan,
+                                      p->cursor, p->rec_pos, (float *)p->rec_vis, s);
+    timer_end(p, T_SCATTER, s);
+    if (e != hipSuccess) return hip_fail(e, "bin_scatter");
+    if (!accumulate) {
+        timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
+        if (p->fp64) e = launch_zero_heavy<double>(g, p->scan, (double *)p->mesh, max_items, s);
+        else e = launch_zero_heavy<float>(g, p->scan, (float *)p->mesh, max_items, s);
+        timer_end(p, T_ZERO_HEAVY, s);
+        if (e != hipSuccess) return hip_fail(e, "zero_heavy");
+    }
+    timer_begin(p, T_GRID, "grid", s);
+    if (p->fp64)
+        e = launch_grid<double>(g, p->scan, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
+                                (double *)p->mesh, accumulate, max_items, s);
+    else
+        e = launch_grid<float>(g, p->scan, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
+                               (float *)p->mesh, accumulate, max_items, s);
+    timer_end(p, T_GRID, s);
+    if (e != hipSuccess) return hip_fail(e, "grid");
+    p->mesh_written = true;
+    p->state = 1;
+    return RICK_OK;
+}
+
+rick_status rick_fft_planes(rick_plan_t *p, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!p->mesh_written) {
+        // nothing gridded since the reset: the planes are zero
+        if (p->fp64) e = launch_zero_mesh<double>((double *)p->mesh, int64_t(p->mesh_bytes / 8), s);
+        else e = launch_zero_mesh<float>((float *)p->mesh, int64_t(p->mesh_bytes / 4), s);
+        if (e != hipSuccess) return hip_fail(e, "zero mesh");
+        p->mesh_written = true;
+    }
+    timer_begin(p, T_FFT_ROWS, "fft_rows", s);
+    if (p->fp64) e = launch_fft_rows<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
+    else e = launch_fft_rows<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
+    timer_end(p, T_FFT_ROWS, s);
+    if (e != hipSuccess) return hip_fail(e, "fft_rows");
+    timer_begin(p, T_FFT_COLS, "fft_cols", s);
+    if (p->fp64) e = launch_fft_cols<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
+    else e = launch_fft_cols<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
+    timer_end(p, T_FFT_COLS, s);
+    if (e != hipSuccess) return hip_fail(e, "fft_cols");
+    p->state = 2;
+    return RICK_OK;
+}
+
+rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!image) return fail(RICK_E_INVALID_ARG, "image is NULL");
+    if (((uintptr_t)image) & (p->fp64 ? 7 : 3)) return fail(RICK_E_INVALID_ARG, "misaligned image");
+    if (p->state != 2) return fail(RICK_E_STATE, "planes not transformed; call rick_fft_planes first");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    const int kahan = p->d.precision == RICK_PREC_FP32_KAHAN;
+    timer_begin(p, T_SCREEN, "wscreen", s);
+    if (p->fp64)
+        e = launch_wscreen<double>(p->g, (const double *)p->mesh, p->wk, p->corr, p->stats, (double *)image, 0, s);
+    else
+        e = launch_wscreen<float>(p->g, (const float *)p->mesh, p->wk, p->corr, p->stats, (float *)image, kahan, s);
+    timer_end(p, T_SCREEN, s);
+    if (e != hipSuccess) return hip_fail(e, "wscreen");
+    return RICK_OK;
+}
+
+rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");
+    DeviceGuard guard(p->d.device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise");
+    Stats st;
+    e = hipMemcpy(&st, p->stats, sizeof st, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read counters");
+    std::memset(out, 0, sizeof *out);
+    out->n_gridded = (int64_t)st.n_gridded;
+    out->n_dropped = (int64_t)st.n_dropped;
+    out->n_records = (int64_t)st.n_records;
+    out->sum_weights = st.sum_w;
+    out->du = p->du;
+    out->dl = p->dl;
+    out->dw = p->g.dw;
+    out->mesh = p->mesh;
+    out->mesh_bytes = (int64_t)p->mesh_bytes;
+    out->tile = p->g.T;
+    out->chunk = p->g.CH;
+    out->state = p->state;
+    out->n_timers = 0;
+    if (p->timing) {
+        int nt = 0;
+        for (int i = 0; i < kMaxTimers && nt < 16; ++i) {
+            if (!p->ev_name[i] || p->ev_calls[i] == 0) continue;
+            const int64_t n = p->ev_calls[i] < kTimerRing ? p->ev_calls[i] : kTimerRing;
+            double sum = 0.0;
+            int64_t ok = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, p->ev[i][2 * j], p->ev[i][2 * j + 1]) == hipSuccess) {
+                    sum += ms;
+                    ++ok;
+                }
+            }
+            out->kernel_ms[nt] = ok ? float(sum / ok) : -1.0f;
+            out->kernel_calls[nt] = (int32_t)ok;
+            out->kernel_names[nt] = p->ev_name[i];
+            ++nt;
+            p->ev_calls[i] = 0;
+        }
+        out->n_timers = nt;
+        (void)hipGetLastError();
+    }
+    return RICK_OK;
+}
+
+rick_status rick_plan_bin_counts(rick_plan_t *p, int32_t *counts, int64_t n) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!counts) return fail(RICK_E_INVALID_ARG, "counts is NULL");
+    if (n != p->g.nbins) return fail(RICK_E_INVALID_ARG, "n=%lld, plan has %d bins", (long long)n, p->g.nbins);
+    DeviceGuard guard(p->d.device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(counts, p->counts, size_t(n) * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read bin counts");
+    return RICK_OK;
+}
+
+}  // extern "C"

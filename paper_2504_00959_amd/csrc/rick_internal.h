@@ -1,0 +1,98 @@
+// Internal declarations shared by the host plan and the HIP kernels of the
+// w-stacking imager.  Not part of the public ABI (see include/rick.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rick.h"
+
+namespace rick {
+
+constexpr double kC0 = 299792458.0;      // speed of light, m/s
+constexpr int kMaxInlineChan = 32;       // channel scale factors per kernel-argument upload
+constexpr int kMaxChan = 1 << 16;        // capacity of the plan's channel scale buffer
+constexpr int kMaxTimers = 16;
+constexpr int kTimerRing = 64;         // launches per kernel whose times are kept between reads
+
+// A batch of channel scale factors nu_c / c0, passed by value.
+struct ChanScales {
+    double s[kMaxInlineChan];
+};
+
+// Geometry of one plan, passed by value to kernels.
+struct Geom {
+    int32_t N;          // grid edge
+    int32_t Nw;         // number of w-planes
+    int32_t W;          // kernel support
+    int32_t h;          // (W - 1) / 2
+    int32_t OS;         // oversampling
+    int32_t log2OS;
+    int32_t T;          // tile edge
+    int32_t log2T;
+    int32_t nt;         // tiles per axis, N / T
+    int32_t nbins;      // Nw * nt * nt
+    int32_t CH;         // records per gridding chunk
+    int32_t pitch;      // LDS row pitch (floats) of the gridding tile
+    double fov;
+    double half;        // N * OS / 2
+    double w_min;
+    double dw;
+};
+
+// Device-side counters of one plan (zeroed by rick_reset).
+struct Stats {
+    unsigned long long n_gridded;
+    unsigned long long n_dropped;
+    unsigned long long n_records;   // records written by the last rick_grid
+    unsigned long long pad;
+    double sum_w;
+    double pad2[3];
+};
+
+// Binning bookkeeping written by the scan: per bin, exclusive prefix sums of
+// the record count (x) and of the number of gridding chunks (y).
+struct BinScan {
+    int32_t rec;
+    int32_t item;
+};
+
+// ---- kernel launchers (each returns hipGetLastError() of its launches) ----
+hipError_t launch_zero_stats(Stats *st, hipStream_t s);
+template <typename real>
+hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s);
+hipError_t launch_reset_counts(int32_t *counts, int32_t n, hipStream_t s);
+
+// Pass 1 of bin-and-sort: per-bin record counts, drop counts and weight sum.
+// Channel scale factors nu_c / c0 into the plan's device buffer (kernel arguments, no copies).
+hipError_t launch_set_scales(double *dst, const double *host_scales, int32_t nchan, hipStream_t s);
+template <typename real>
+hipError_t launch_bin_count(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
+                            const float *weight, int64_t nrow, int32_t nchan, int32_t *counts, Stats *st,
+                            hipStream_t s);
+// Exclusive scan of counts into BinScan, chunk counts, cursors = record offsets.
+hipError_t launch_bin_scan(const Geom &g, const int32_t *counts, BinScan *scan, int32_t *block_sums,
+                           int32_t *cursor, Stats *st, hipStream_t s);
+// Pass 2: scatter records {packed position, W V} into their bins.
+template <typename real>
+hipError_t launch_bin_scatter(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
+                              const float *weight, int64_t nrow, int32_t nchan, int32_t *cursor, uint32_t *rec_pos,
+                              real *rec_vis, hipStream_t s);
+// Gridding: zero heavy tiles, then one block per (bin, chunk) item.
+template <typename real>
+hipError_t launch_grid(const Geom &g, const BinScan *scan, const uint32_t *rec_pos, const real *rec_vis,
+                       const real *lut, real *mesh, int accumulate, int32_t max_items, hipStream_t s);
+template <typename real>
+hipError_t launch_zero_heavy(const Geom &g, const BinScan *scan, real *mesh, int32_t max_heavy, hipStream_t s);
+// Batched centred 2-D inverse FFT, in place, all planes.
+template <typename real>
+hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
+template <typename real>
+hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
+bool fft_supported(int N);
+// Phase screen + plane sum + normalisation.
+template <typename real>
+hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *wk, const double *corr,
+                          const Stats *st, real *image, int kahan, hipStream_t s);
+
+}  // namespace rick

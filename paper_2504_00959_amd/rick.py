@@ -1,0 +1,265 @@
+"""Python binding of the w-stacking imager's C ABI (``include/rick.h``).
+
+Argument marshalling only: device tensors are passed as raw pointers with
+the current HIP stream; every step of the imaging path runs in the HIP
+kernels of ``librick.so``.  There is no fallback: if the library is missing
+or fails, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librick.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "rick.h")
+
+RICK_OK = 0
+STATUS_NAMES = {0: "RICK_OK", 1: "RICK_E_INVALID_ARG", 2: "RICK_E_NO_DEVICE", 3: "RICK_E_OOM", 4: "RICK_E_HIP",
+                5: "RICK_E_CAPACITY", 6: "RICK_E_BAD_PLAN", 7: "RICK_E_STATE", 8: "RICK_E_UNSUPPORTED"}
+KERNELS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1}
+PRECISIONS = {"fp32": 0, "fp32_kahan": 1, "fp64": 2}
+FLAG_TIMING = 1
+
+
+class RickError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("grid_n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("kernel_param", ctypes.c_double), ("fov_rad", ctypes.c_double), ("w_min", ctypes.c_double),
+                ("w_max", ctypes.c_double), ("max_vis", ctypes.c_int64), ("device", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_gridded", ctypes.c_int64), ("n_dropped", ctypes.c_int64), ("n_records", ctypes.c_int64),
+                ("sum_weights", ctypes.c_double), ("du", ctypes.c_double), ("dl", ctypes.c_double),
+                ("dw", ctypes.c_double), ("mesh", ctypes.c_void_p), ("mesh_bytes", ctypes.c_int64),
+                ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("state", ctypes.c_int32),
+                ("n_timers", ctypes.c_int32), ("kernel_ms", ctypes.c_float * 16),
+                ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librick.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(the imager has no non-HIP path)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.rick_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]
+    L.rick_grid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
+    L.rick_fft_planes.argtypes = [P, P]
+    L.rick_wstack_image.argtypes = [P, P, P]
+    L.rick_reset.argtypes = [P, P]
+    L.rick_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    L.rick_plan_destroy.argtypes = [P]
+    L.rick_plan_bin_counts.argtypes = [P, P, ctypes.c_int64]
+    for f in ("rick_plan", "rick_grid", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
+              "rick_plan_destroy", "rick_plan_bin_counts"):
+        getattr(L, f).restype = ctypes.c_int32
+    L.rick_status_str.argtypes = [ctypes.c_int32]
+    L.rick_status_str.restype = ctypes.c_char_p
+    L.rick_last_error.argtypes = []
+    L.rick_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def header_functions() -> list:
+    """Names of the functions include/rick.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rick_\w+)\s*\(", txt, flags=re.M)
+
+
+def _check(status: int, where: str):
+    if status != RICK_OK:
+        raise RickError(status, where, lib().rick_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel="gaussian", kernel_param=0.0,
+              precision="fp32", max_vis=1 << 20, device=0, timing=False, tile=0, chunk=0) -> PlanDesc:
+    return PlanDesc(grid_n=grid_n, n_wplanes=n_wplanes, support=support, oversample=oversample,
+                    kernel=KERNELS[kernel], precision=PRECISIONS[precision], kernel_param=kernel_param,
+                    fov_rad=fov, w_min=w_min, w_max=w_max, max_vis=max_vis, device=device,
+                    flags=FLAG_TIMING if timing else 0, tile=tile, chunk=chunk)
+
+
+class Plan:
+    """One imaging plan (device buffers allocated once at construction)."""
+
+    def __init__(self, grid_n: int, n_wplanes: int, support: int, oversample: int, fov: float, w_min: float,
+                 w_max: float, kernel: str = "gaussian", kernel_param: float = 0.0, precision: str = "fp32",
+                 max_vis: int = 1 << 20, device: int = 0, timing: bool = False, tile: int = 0, chunk: int = 0):
+        self.desc = make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel, kernel_param,
+                              precision, max_vis, device, timing, tile, chunk)
+        self.precision = precision
+        self.grid_n = grid_n
+        self.n_wplanes = n_wplanes
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().rick_plan(ctypes.byref(self.desc), ctypes.byref(h)), "rick_plan")
+        self._h = h
+
+    @classmethod
+    def for_dataset(cls, ds, **kw):
+        args = dict(ds.plan_kwargs())
+        args.setdefault("max_vis", max(1, ds.nvis))
+        args.update(kw)
+        return cls(**args)
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def _device_tensor(self, t, name, dtype):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda" or (t.device.index or 0) != self.device:
+            raise ValueError(f"{name} must be on cuda:{self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def grid(self, uvw, vis, weight=None, freq: Optional[Sequence[float]] = None, stream=None):
+        """Bin-and-sort + grid.  uvw float64 [R,3] (metres if freq given, else wavelengths),
+        vis complex [R,C], weight float32 [R,C] or None, freq host sequence [C] in Hz or None."""
+        import torch
+        self._device_tensor(uvw, "uvw", torch.float64)
+        self._device_tensor(vis, "vis", self.complex_dtype)
+        if uvw.dim() != 2 or uvw.shape[1] != 3:
+            raise ValueError("uvw must be [nrow, 3]")
+        nrow = uvw.shape[0]
+        if vis.dim() == 1:
+            vis = vis.reshape(nrow, 1)
+        nchan = vis.shape[1]
+        if vis.shape[0] != nrow:
+            raise ValueError("vis must be [nrow, nchan]")
+        wptr = None
+        if weight is not None:
+            self._device_tensor(weight, "weight", torch.float32)
+            if weight.numel() != nrow * nchan:
+                raise ValueError("weight must be [nrow, nchan]")
+            wptr = weight.data_ptr()
+        fptr = None
+        if freq is not None:
+            f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).reshape(-1))
+            if f.shape[0] != nchan:
+                raise ValueError("freq must have nchan entries")
+            self._freq_keep = f
+            fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(lib().rick_grid(self._h, uvw.data_ptr(), fptr, vis.data_ptr(), wptr, nrow, nchan,
+                               _stream_handle(stream)), "rick_grid")
+
+    def fft(self, stream=None):
+        _check(lib().rick_fft_planes(self._h, _stream_handle(stream)), "rick_fft_planes")
+
+    def image(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.grid_n, self.grid_n), dtype=self.real_dtype, device=f"cuda:{self.device}")
+        self._device_tensor(out, "out", self.real_dtype)
+        if out.numel() != self.grid_n * self.grid_n:
+            raise ValueError("out must be [N, N]")
+        _check(lib().rick_wstack_image(self._h, out.data_ptr(), _stream_handle(stream)), "rick_wstack_image")
+        return out
+
+    def reset(self, stream=None):
+        _check(lib().rick_reset(self._h, _stream_handle(stream)), "rick_reset")
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib().rick_plan_info(self._h, ctypes.byref(inf)), "rick_plan_info")
+        timers = {}
+        for i in range(inf.n_timers):
+            name = inf.kernel_names[i]
+            if name:
+                timers[name.decode()] = (float(inf.kernel_ms[i]), int(inf.kernel_calls[i]))
+        return dict(n_gridded=inf.n_gridded, n_dropped=inf.n_dropped, n_records=inf.n_records,
+                    sum_weights=inf.sum_weights, du=inf.du, dl=inf.dl, dw=inf.dw, mesh_ptr=inf.mesh,
+                    mesh_bytes=inf.mesh_bytes, tile=inf.tile, chunk=inf.chunk, state=inf.state, timers=timers)
+
+    def bin_counts(self, n_bins: int) -> np.ndarray:
+        """Per-(plane, tile) record counts of the last grid() (host int32 array)."""
+        out = np.zeros(n_bins, dtype=np.int32)
+        _check(lib().rick_plan_bin_counts(self._h, out.ctypes.data, n_bins), "rick_plan_bin_counts")
+        return out
+
+    def mesh(self):
+        """Copy of the planes: G_k after grid(), F_k after fft(); complex [N_w, N, N] on the device."""
+        import torch
+        inf = self.info()
+        shape = (self.n_wplanes, self.grid_n, self.grid_n)
+
+        class _View:
+            __cuda_array_interface__ = {"shape": shape, "typestr": "<c16" if self.precision == "fp64" else "<c8",
+                                        "data": (inf["mesh_ptr"], False), "version": 2, "strides": None}
+        return torch.as_tensor(_View(), device=f"cuda:{self.device}").clone()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().rick_plan_destroy(self._h), "rick_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def wstack_image(ds, device: int = 0, precision: str = "fp32", **kw):
+    """Convenience: reset + grid + fft + image for a synth.Dataset whose arrays
+    are moved to the device; returns (image tensor, plan info)."""
+    import torch
+    dev = f"cuda:{device}"
+    uvw = torch.as_tensor(ds.uvw, dtype=torch.float64).to(dev)
+    cd = torch.complex128 if precision == "fp64" else torch.complex64
+    vis = ds.vis if isinstance(ds.vis, torch.Tensor) else torch.as_tensor(ds.vis)
+    vis = vis.to(device=dev, dtype=cd).contiguous()
+    wt = None if ds.weight is None else torch.as_tensor(ds.weight, dtype=torch.float32).to(dev).contiguous()
+    with Plan.for_dataset(ds, precision=precision, device=device, **kw) as p:
+        p.reset()
+        p.grid(uvw, vis, wt, ds.freq)
+        p.fft()
+        img = p.image()
+        torch.cuda.synchronize(dev)
+        return img, p.info()

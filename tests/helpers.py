@@ -1,0 +1,43 @@
+"""Shared helpers for the GPU parity tests (inputs, oracle-side bin counts, metrics)."""
+import numpy as np
+
+
+def rel_rms(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a))
+
+
+def oracle_bin_counts(b, grid_n, n_wplanes, support, tile):
+    """Records per (plane, tile) bin implied by the oracle's per-visibility
+    decisions: a kept visibility adds one record to each tile its footprint
+    [c - h, c + h]^2 touches."""
+    h = (support - 1) // 2
+    nt = grid_n // tile
+    idx = np.nonzero(b.keep)[0]
+    cx, cy, k = b.cx[idx], b.cy[idx], b.k[idx]
+    counts = np.zeros(n_wplanes * nt * nt, dtype=np.int64)
+    tx0, tx1 = (cx - h) // tile, (cx + h) // tile
+    ty0, ty1 = (cy - h) // tile, (cy + h) // tile
+    for second_y in (False, True):
+        for second_x in (False, True):
+            ty = ty1 if second_y else ty0
+            tx = tx1 if second_x else tx0
+            sel = np.ones(idx.size, bool)
+            if second_y:
+                sel &= ty1 != ty0
+            if second_x:
+                sel &= tx1 != tx0
+            np.add.at(counts, (k[sel] * nt + ty[sel]) * nt + tx[sel], 1)
+    return counts
+
+
+def to_device(ds, precision="fp32", device="cuda:0"):
+    import torch
+    uvw = torch.as_tensor(ds.uvw, dtype=torch.float64).to(device)
+    cd = torch.complex128 if precision == "fp64" else torch.complex64
+    vis = ds.vis if isinstance(ds.vis, torch.Tensor) else torch.as_tensor(np.asarray(ds.vis))
+    vis = vis.to(device=device, dtype=cd).contiguous()
+    wt = None if ds.weight is None else torch.as_tensor(ds.weight, dtype=torch.float32).to(device).contiguous()
+    return uvw, vis, wt

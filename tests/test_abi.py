@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every declared symbol, and validates
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+
+import pytest
+
+from paper_2504_00959_amd import rick
+
+
+def test_library_exports_every_header_symbol():
+    L = rick.lib()
+    names = rick.header_functions()
+    assert {"rick_plan", "rick_grid", "rick_fft_planes", "rick_wstack_image", "rick_reset",
+            "rick_plan_info", "rick_plan_destroy", "rick_status_str"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = rick.lib()
+    for s in range(0, 9):
+        assert L.rick_status_str(s)
+    assert L.rick_status_str(99) == b"unknown status"
+
+
+def _plan_status(**over):
+    L = rick.lib()
+    kw = dict(grid_n=256, n_wplanes=8, support=7, oversample=32, fov=0.2, w_min=-50.0, w_max=50.0)
+    kw.update(over)
+    d = rick.make_desc(**kw)
+    h = ctypes.c_void_p(1234)
+    st = L.rick_plan(ctypes.byref(d), ctypes.byref(h))
+    return st, h.value
+
+
+@pytest.mark.parametrize("over", [
+    dict(grid_n=100), dict(grid_n=32), dict(grid_n=16384), dict(n_wplanes=0), dict(support=4),
+    dict(support=17), dict(oversample=3), dict(oversample=512), dict(fov=0.0), dict(fov=1.5),
+    dict(w_min=1.0, w_max=1.0), dict(w_min=float("nan")), dict(max_vis=0), dict(max_vis=1 << 29),
+    dict(tile=48), dict(tile=8), dict(tile=256), dict(grid_n=64, tile=128),
+    dict(device=-1), dict(kernel_param=float("inf")), dict(chunk=-1),
+])
+def test_invalid_plan_rejected_before_device(over):
+    st, h = _plan_status(**over)
+    assert st == 1, rick.lib().rick_last_error()      # RICK_E_INVALID_ARG
+    assert h is None                                    # *out cleared
+
+
+def test_null_arguments():
+    L = rick.lib()
+    assert L.rick_plan(None, None) == 1
+    h = ctypes.c_void_p()
+    assert L.rick_plan(None, ctypes.byref(h)) == 1
+    for call in (lambda: L.rick_grid(None, None, None, None, None, 0, 1, None),
+                 lambda: L.rick_fft_planes(None, None), lambda: L.rick_wstack_image(None, None, None),
+                 lambda: L.rick_reset(None, None), lambda: L.rick_plan_info(None, None),
+                 lambda: L.rick_plan_destroy(None), lambda: L.rick_plan_bin_counts(None, None, 0)):
+        assert call() == 6                              # RICK_E_BAD_PLAN
+
+
+def test_valid_plan_without_device_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = _plan_status()
+    assert st == 2 and h is None                        # RICK_E_NO_DEVICE
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(rick, "_lib", None)
+    monkeypatch.setattr(rick, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        rick.lib()

@@ -1,0 +1,222 @@
+"""GPU path (through the C ABI) against the float64 oracle, element by element.
+
+Stage by stage on the tiny workload: integer binning (bit-exact), the gridded
+planes G_k, the FFT of the GPU's own planes, the screen of the GPU's own
+F_k, and the end-to-end image; then precision modes, kernels, supports,
+oversampling, tile sizes, heavy-bin splitting, accumulation, edge cases.
+Tolerances are relative RMS errors (||a - b|| / ||b||):
+  per-stage FP32 1e-6, end-to-end FP32 image 1e-5, FP64 mode 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import wstack as ow
+from paper_2504_00959_amd import rick
+from tests.helpers import oracle_bin_counts, rel_rms, to_device
+
+pytestmark = pytest.mark.gpu
+
+FP32_IMG = 1e-5
+FP32_STAGE = 1e-6
+FP64_IMG = 1e-10
+
+
+def run_gpu(ds, precision="fp32", **kw):
+    import torch
+    uvw, vis, wt = to_device(ds, precision)
+    p = rick.Plan.for_dataset(ds, precision=precision, **kw)
+    p.reset()
+    p.grid(uvw, vis, wt, ds.freq)
+    torch.cuda.synchronize()
+    G = p.mesh().cpu().numpy()
+    info = p.info()
+    nt = ds.grid_n // info["tile"]
+    counts = p.bin_counts(ds.n_wplanes * nt * nt)
+    p.fft()
+    torch.cuda.synchronize()
+    F = p.mesh().cpu().numpy()
+    img = p.image().double().cpu().numpy()
+    torch.cuda.synchronize()
+    p.close()
+    return dict(G=G, F=F, img=img, info=info, counts=counts)
+
+
+def oracle_of(ds, **over):
+    return oracle.wstack.wstack_dataset(ds, **over)
+
+
+def check_stages(ds, gpu, ref, stage_tol=FP32_STAGE, img_tol=FP32_IMG):
+    info = gpu["info"]
+    b = ref.binned
+    # integer decisions: exact
+    assert info["n_gridded"] == int(b.keep.sum())
+    assert info["n_dropped"] == int((~b.keep).sum())
+    oc = oracle_bin_counts(b, ds.grid_n, ds.n_wplanes, ds.support, info["tile"])
+    assert np.array_equal(gpu["counts"].astype(np.int64), oc)
+    assert info["n_records"] == int(oc.sum())
+    assert abs(info["sum_weights"] - ref.sum_w) <= 1e-12 * max(1.0, ref.sum_w)
+    # gridded planes
+    assert rel_rms(gpu["G"], ref.planes) <= stage_tol
+    # FFT of the GPU's own planes
+    assert rel_rms(gpu["F"], ow.ifft_planes(gpu["G"].astype(np.complex128))) <= stage_tol
+    # screen + normalisation of the GPU's own F_k
+    S = ow.screen_sum(gpu["F"].astype(np.complex128), ref.w_k, ds.fov)
+    mine = ow.normalise(S, ref.corr, ref.sum_w, ds.fov)
+    assert rel_rms(gpu["img"], mine) <= stage_tol
+    # end to end
+    assert rel_rms(gpu["img"], ref.image) <= img_tol
+
+
+def test_tiny_stagewise_fp32():
+    ds = synth.tiny()
+    check_stages(ds, run_gpu(ds), oracle_of(ds))
+
+
+def test_tiny_fp64_mode():
+    ds = synth.tiny()
+    gpu = run_gpu(ds, precision="fp64")
+    ref = oracle_of(ds)
+    assert rel_rms(gpu["G"], ref.planes) <= 1e-12
+    assert rel_rms(gpu["img"], ref.image) <= FP64_IMG
+
+
+def test_tiny_kahan():
+    ds = synth.tiny()
+    gpu = run_gpu(ds, precision="fp32_kahan")
+    assert rel_rms(gpu["img"], oracle_of(ds).image) <= FP32_IMG
+
+
+def test_heavy_bins_split_over_chunks():
+    """Small chunks force the dense central bins through the multi-chunk path."""
+    ds = synth.tiny()
+    gpu = run_gpu(ds, chunk=64)
+    check_stages(ds, gpu, oracle_of(ds))
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "kaiser_bessel"])
+@pytest.mark.parametrize("W,OS,tile", [(1, 1, 16), (3, 4, 32), (5, 256, 64), (7, 64, 128), (9, 8, 16),
+                                       (15, 2, 32)])
+def test_kernels_supports_oversampling_tiles(kernel, W, OS, tile):
+    ds = synth.tiny(nrow=20000, seed=4, support=W, oversample=OS, kernel=kernel)
+    check_stages(ds, run_gpu(ds, tile=tile), oracle_of(ds))
+
+
+def test_multichannel_metres_and_weights():
+    ds = synth.ska_low_small()
+    rng = np.random.default_rng(5)
+    ds.weight = rng.uniform(0.2, 2.0, (ds.nrow, ds.nchan)).astype(np.float32)
+    check_stages(ds, run_gpu(ds), oracle_of(ds))
+
+
+def test_many_channels_beyond_one_scale_upload():
+    ds = synth.ska_low_small(n_chan=40, n_times=4, n_src=3)
+    check_stages(ds, run_gpu(ds), oracle_of(ds))
+
+
+@pytest.mark.parametrize("N", [64, 128, 512, 1024, 2048, 4096, 8192])
+def test_grid_sizes(N):
+    ds = synth.tiny(nrow=5000, seed=6, grid_n=N, n_wplanes=2, fov=0.2 * N / 256)
+    check_stages(ds, run_gpu(ds), oracle_of(ds))
+
+
+def test_dropped_inputs_match_oracle():
+    ds = synth.tiny(nrow=6000, seed=9, weights=True)
+    uvw = ds.uvw.copy()
+    vis = np.asarray(ds.vis).copy()
+    wt = ds.weight.copy()
+    uvw[0, 0] = np.nan
+    uvw[1, 2] = np.inf
+    vis[2, 0] = np.nan
+    wt[3, 0] = 0.0
+    wt[4, 0] = -1.0
+    wt[5, 0] = np.nan
+    uvw[6, 0] = 5000.0      # far outside the grid
+    uvw[7, 1] = -633.0      # footprint leaves the low edge
+    uvw[8, 2] = 1e6         # beyond w_max: last plane
+    ds.uvw, ds.vis, ds.weight = uvw, vis, wt
+    ref = oracle_of(ds)
+    assert (~ref.binned.keep).sum() >= 8
+    check_stages(ds, run_gpu(ds), ref)
+
+
+def test_accumulating_two_grid_calls_equals_one():
+    import torch
+    ds = synth.tiny(nrow=30000, seed=10)
+    uvw, vis, _ = to_device(ds)
+    with rick.Plan.for_dataset(ds) as p:
+        p.reset()
+        p.grid(uvw[:12345], vis[:12345])
+        p.grid(uvw[12345:], vis[12345:])
+        p.fft()
+        img2 = p.image().double().cpu().numpy()
+        n2 = p.info()["n_gridded"]
+        # reuse after reset
+        p.reset()
+        p.grid(uvw, vis)
+        p.fft()
+        img1 = p.image().double().cpu().numpy()
+        torch.cuda.synchronize()
+    ref = oracle_of(ds).image
+    assert n2 == ds.nvis
+    assert rel_rms(img2, ref) <= FP32_IMG
+    assert rel_rms(img1, ref) <= FP32_IMG
+
+
+def test_empty_and_all_dropped_give_zero_image():
+    import torch
+    ds = synth.tiny(nrow=100, seed=11)
+    uvw, vis, _ = to_device(ds)
+    with rick.Plan.for_dataset(ds) as p:
+        p.reset()
+        p.grid(uvw[:0], vis[:0])
+        p.fft()
+        img = p.image()
+        torch.cuda.synchronize()
+        assert float(img.abs().max()) == 0.0
+        p.reset()
+        p.grid(uvw * 1000.0, vis)           # every footprint leaves the grid
+        p.fft()
+        img = p.image()
+        inf = p.info()
+        assert inf["n_gridded"] == 0 and inf["n_dropped"] == 100
+        assert float(img.abs().max()) == 0.0
+
+
+def test_call_order_and_capacity_errors():
+    ds = synth.tiny(nrow=1000, seed=12)
+    uvw, vis, _ = to_device(ds)
+    with rick.Plan.for_dataset(ds, max_vis=1000) as p:
+        with pytest.raises(rick.RickError) as e:
+            p.image()
+        assert e.value.status == 7
+        p.reset()
+        with pytest.raises(rick.RickError) as e:
+            import torch
+            p.grid(torch.cat([uvw, uvw]), torch.cat([vis, vis]))
+        assert e.value.status == 5
+        p.grid(uvw, vis)
+        p.fft()
+        with pytest.raises(rick.RickError) as e:
+            p.grid(uvw, vis)
+        assert e.value.status == 7
+
+
+def test_gpu_error_vs_dft_equals_oracle_error_vs_dft():
+    """The GPU image's distance to the direct DFT equals the oracle's within 1 %."""
+    ds = synth.tiny()
+    ref = oracle_of(ds)
+    gpu = run_gpu(ds)
+    rows = cols = slice(96, 160)
+    D = oracle.dft.dft_of_binned(ref.binned, ds.fov, ds.grid_n, rows=rows, cols=cols)
+    e_or = rel_rms(ref.image[rows, cols], D)
+    e_gpu = rel_rms(gpu["img"][rows, cols], D)
+    assert abs(e_gpu - e_or) <= 0.01 * e_or, (e_gpu, e_or)
+
+
+def test_phase_centre_source_unit_peak():
+    ds = synth.tiny(nrow=20000, seed=13)
+    ds.vis = np.full((ds.nrow, 1), 1.5, np.complex64)
+    gpu = run_gpu(ds)
+    assert abs(gpu["img"][128, 128] - 1.5) < 1e-5
