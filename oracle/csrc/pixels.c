@@ -21,11 +21,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-static int64_t floordiv(int64_t a, int64_t b) {
-    int64_t q = a / b;
-    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
-    return q;
-}
+#include "decide.h"
 
 /* Returns the number of kept visibilities; acc must hold npix * nw complex
  * (re, im interleaved) and is overwritten; *sum_w receives sum W. */
@@ -47,8 +43,6 @@ int64_t oracle_wstack_pixels(
     memset(acc, 0, sizeof(double) * 2 * npix * nw);
     int64_t kept_total = 0;
     double sumw_total = 0.0;
-    const double half = (double)(N * OS) / 2.0;
-    const double lim = 1073741824.0; /* 2^30 */
     #pragma omp parallel
     {
         double *lacc = (double *)calloc((size_t)(2 * npix * nw), sizeof(double));
@@ -57,35 +51,13 @@ int64_t oracle_wstack_pixels(
         #pragma omp for schedule(static)
         for (int64_t r = 0; r < nrow; ++r) {
             for (int32_t c = 0; c < nchan; ++c) {
-                double u, v, w;
-                if (scales) {
-                    u = uvw[3 * r] * scales[c];
-                    v = uvw[3 * r + 1] * scales[c];
-                    w = uvw[3 * r + 2] * scales[c];
-                } else {
-                    u = uvw[3 * r]; v = uvw[3 * r + 1]; w = uvw[3 * r + 2];
-                }
-                const int64_t vi = r * nchan + c;
-                const double vr = vis[2 * vi], vim = vis[2 * vi + 1];
-                const double wt = weight ? (double)weight[vi] : 1.0;
-                if (!(isfinite(u) && isfinite(v) && isfinite(w) && isfinite(vr) && isfinite(vim) && isfinite(wt)))
+                oracle_vis_t o;
+                if (!oracle_decide(r, c, nchan, uvw, scales, vis, weight, N, OS, h, nw, fov, w_min, dw, &o))
                     continue;
-                double xs = u * fov; xs = xs * (double)OS; xs = xs + half;
-                double ys = v * fov; ys = ys * (double)OS; ys = ys + half;
-                if (!(fabs(xs) <= lim && fabs(ys) <= lim)) continue;
-                const int64_t X = (int64_t)rint(xs), Y = (int64_t)rint(ys);
-                const int64_t cx = floordiv(X + OS / 2, OS), cy = floordiv(Y + OS / 2, OS);
-                const int64_t sx = X - cx * OS, sy = Y - cy * OS;
-                if (!(wt > 0.0)) continue;
-                if (cx - h < 0 || cx + h > N - 1 || cy - h < 0 || cy + h > N - 1) continue;
-                double kf = floor((w - w_min) / dw);
-                if (isnan(kf)) kf = 0.0;   /* w outside the range -> nearest end plane */
-                if (kf < 0.0) kf = 0.0;
-                if (kf > (double)(nw - 1)) kf = (double)(nw - 1);
-                const int64_t k = (int64_t)kf;
+                const int64_t cx = o.cx, cy = o.cy, sx = o.sx, sy = o.sy, k = o.k;
                 ++kept;
-                sumw += wt;
-                const double ar = wt * vr, ai = wt * vim;
+                sumw += o.wt;
+                const double ar = o.ar, ai = o.ai;
                 const double *gx = table + (sx + OS / 2) * support;
                 const double *gy = table + (sy + OS / 2) * support;
                 for (int64_t ip = 0; ip < npix; ++ip) {

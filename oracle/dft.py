@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_liboracle.so")
-_SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("dft.c", "pixels.c")]
+_SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("dft.c", "pixels.c", "binstats.c")]
 _lib = None
 
 
@@ -27,7 +27,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
-               "-o", tmp] + [s for s in _SOURCES if os.path.exists(s)] + ["-lm"]
+               "-I", os.path.join(_HERE, "csrc"), "-o", tmp] + [s for s in _SOURCES if os.path.exists(s)] + ["-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

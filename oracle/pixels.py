@@ -82,3 +82,38 @@ def wstack_pixels_dataset(ds, pix_p, pix_q, vis=None):
     if hasattr(v, "detach"):
         v = v.detach().cpu().numpy()
     return wstack_pixels(ds.uvw, ds.freq, v, ds.weight, pix_p, pix_q, **ds.plan_kwargs())
+
+
+def bin_stats(uvw, freq, vis, weight, *, tile, grid_n, n_wplanes, support, oversample, fov, w_min, w_max,
+              **_ignored):
+    """Whole-input binning statistics (see ``csrc/binstats.c``): per-(plane, tile)
+    record counts [N_w * (N/T)^2] (int64), per-plane sums of W V (complex), kept count, sum W."""
+    L = _lib()
+    if not getattr(L, "_binstats_sig", False):
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        lp = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_bin_stats.argtypes = [ctypes.c_int64, ctypes.c_int32, dp, dp, fp, fp, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int32, lp, dp, dp]
+        L.oracle_bin_stats.restype = ctypes.c_int64
+        L._binstats_sig = True
+    uvw = np.ascontiguousarray(uvw, dtype=np.float64)
+    nrow = uvw.shape[0]
+    sc = scales_of(freq)
+    nchan = 1 if sc is None else len(sc)
+    vis = np.ascontiguousarray(np.asarray(vis).reshape(nrow, nchan), dtype=np.complex64)
+    wt = None if weight is None else np.ascontiguousarray(weight, dtype=np.float32).reshape(nrow, nchan)
+    nt = grid_n // tile
+    counts = np.zeros(n_wplanes * nt * nt, dtype=np.int64)
+    psum = np.zeros((n_wplanes, 2))
+    sum_w = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    sc_arr = None if sc is None else np.ascontiguousarray(sc)
+    kept = L.oracle_bin_stats(
+        nrow, nchan, uvw.ctypes.data_as(dp), None if sc_arr is None else sc_arr.ctypes.data_as(dp),
+        vis.view(np.float32).ctypes.data_as(fp), None if wt is None else wt.ctypes.data_as(fp), grid_n, n_wplanes,
+        support, oversample, fov, w_min, (w_max - w_min) / n_wplanes, tile,
+        counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), psum.ctypes.data_as(dp), ctypes.byref(sum_w))
+    return counts, psum[:, 0] + 1j * psum[:, 1], int(kept), float(sum_w.value)

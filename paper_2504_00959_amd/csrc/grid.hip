@@ -2,12 +2,12 @@
 // the w-plane stack.
 //
 // One block takes one work item: a chunk of at most CH records of one
-// (plane, tile) bin.  The tile's T x T accumulator lives in LDS; each wave
-// takes one record at a time with one lane per kernel tap (lane t < W*W is
-// tap (t / W, t % W)), so one record costs two LDS atomic adds per tap row of
-// lanes and no lane pair of an instruction shares an address.  The LDS row
-// pitch is congruent to W modulo 32 floats, which puts the W x W footprint on
-// distinct banks.  Taps outside the tile are skipped: a record whose
+// (plane, tile) bin.  The tile's T x T accumulator (float64 re and im planes)
+// lives in LDS; each wave takes one record at a time with one lane per kernel
+// tap (lane t < W*W is tap (t / W, t % W)), so one record costs two LDS
+// atomic adds and no lane pair of an instruction shares an address.  Records
+// arrive 64 at a time in one coalesced load and are broadcast across the wave
+// with readlane.  The LDS row pitch is congruent to W modulo 32 elements.  Taps outside the tile are skipped: a record whose
 // footprint straddles tile edges was binned into every tile it touches.
 //
 // After the records, the tile is written to HBM once, row-coalesced:
@@ -101,9 +101,11 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     if (r_end > scan[b + 1].rec) r_end = scan[b + 1].rec;
 
     const int32_t T = g.T, P = g.pitch;
-    real *acc_re = reinterpret_cast<real *>(smem);
-    real *acc_im = acc_re + T * P;
-    real *s_lut = acc_im + T * P;
+    // float64 accumulators in both precisions: dense cells collect thousands
+    // of terms, and float32 accumulation there costs ~1e-5 of image RMS
+    double *acc_re = reinterpret_cast<double *>(smem);
+    double *acc_im = acc_re + T * P;
+    real *s_lut = reinterpret_cast<real *>(acc_im + T * P);
     const int nacc = T * P;
     for (int i = threadIdx.x; i < nacc; i += kGridBlock) {
         acc_re[i] = 0;
@@ -158,8 +160,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                 }
                 if (on) {
                     const real wgt = s_lut[ly + tap_ty[gi]] * s_lut[lx + tap_tx[gi]];
-                    atomicAdd(&acc_re[base + tap_off[gi]], wgt * vr);
-                    atomicAdd(&acc_im[base + tap_off[gi]], wgt * vi);
+                    atomicAdd(&acc_re[base + tap_off[gi]], (double)(wgt * vr));
+                    atomicAdd(&acc_im[base + tap_off[gi]], (double)(wgt * vi));
                 }
             }
         }
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     const bool shared_tile = nchunk > 1;
     for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
         const int32_t y = c >> g.log2T, x = c & (T - 1);
-        const real re = acc_re[y * P + x], im = acc_im[y * P + x];
+        const real re = (real)acc_re[y * P + x], im = (real)acc_im[y * P + x];
         r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
         if (shared_tile) {
             if (re != 0) atomic_add_real(&dst->x, re);
@@ -211,7 +213,7 @@ hipError_t launch_zero_heavy(const Geom &g, const BinScan *scan, real *mesh, int
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const uint32_t *rec_pos, const real *rec_vis, const real *lut,
                   real *mesh, int accumulate, int32_t max_items, hipStream_t s) {
-    const size_t lds = (size_t(2) * g.T * g.pitch + size_t(g.OS) * g.W) * sizeof(real);
+    const size_t lds = size_t(2) * g.T * g.pitch * sizeof(double) + size_t(g.OS) * g.W * sizeof(real);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)k_grid<real, W>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -255,6 +255,16 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         while ((pitch - g.W) % 32 != 0) ++pitch;
         g.pitch = pitch;
     }
+    {
+        // the gridding block keeps two T x pitch float64 accumulators and the tap table in LDS
+        const size_t rb = p->fp64 ? 8 : 4;
+        const size_t lds = size_t(2) * g.T * g.pitch * 8 + size_t(g.OS) * g.W * rb;
+        if (lds > size_t(160) * 1024) {
+            delete p;
+            return fail(RICK_E_INVALID_ARG, "tile=%d with support %d, oversample %d needs %zu B of LDS (> 160 KB)",
+                        g.T, g.W, g.OS, lds);
+        }
+    }
     g.fov = d->fov_rad;
     g.half = double(int64_t(g.N) * g.OS) / 2.0;
     g.w_min = d->w_min;

@@ -96,7 +96,7 @@ def test_heavy_bins_split_over_chunks():
 
 
 @pytest.mark.parametrize("kernel", ["gaussian", "kaiser_bessel"])
-@pytest.mark.parametrize("W,OS,tile", [(1, 1, 16), (3, 4, 32), (5, 256, 64), (7, 64, 128), (9, 8, 16),
+@pytest.mark.parametrize("W,OS,tile", [(1, 1, 16), (3, 4, 32), (5, 256, 64), (7, 64, 64), (9, 8, 16),
                                        (15, 2, 32)])
 def test_kernels_supports_oversampling_tiles(kernel, W, OS, tile):
     ds = synth.tiny(nrow=20000, seed=4, support=W, oversample=OS, kernel=kernel)
@@ -117,7 +117,7 @@ def test_many_channels_beyond_one_scale_upload():
 
 @pytest.mark.parametrize("N", [64, 128, 512, 1024, 2048, 4096, 8192])
 def test_grid_sizes(N):
-    ds = synth.tiny(nrow=5000, seed=6, grid_n=N, n_wplanes=2, fov=0.2 * N / 256)
+    ds = synth.tiny(nrow=5000, seed=6, grid_n=N, n_wplanes=2, uv_radius=120.0 * N / 256)
     check_stages(ds, run_gpu(ds), oracle_of(ds))
 
 

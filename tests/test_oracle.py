@@ -375,3 +375,25 @@ def test_pixel_oracle_matches_full_pipeline(maker):
     ref = r.image[qq, pp]
     assert np.max(np.abs(img - ref)) < 1e-12 * np.max(np.abs(r.image))
     assert np.max(np.abs(F - r.fplanes[:, qq, pp].T)) < 1e-12 * np.max(np.abs(r.fplanes))
+
+
+@pytest.mark.parametrize("maker", ["tiny", "ska_small"])
+def test_bin_stats_match_python_oracle(maker):
+    """The C whole-input statistics repeat the Python oracle's decisions exactly."""
+    from tests.helpers import oracle_bin_counts
+    ds = synth.tiny(nrow=20000, weights=True) if maker == "tiny" else synth.ska_low_small()
+    uvw = ds.uvw.copy()
+    uvw[0, 0] = np.nan
+    uvw[1, 0] = 1e6
+    ds.uvw = uvw
+    r = oracle.wstack.wstack_dataset(ds)
+    b = r.binned
+    for tile in (16, 64):
+        counts, psum, kept, sw = oracle.pixels.bin_stats(ds.uvw, ds.freq, ds.vis, ds.weight, tile=tile,
+                                                         **ds.plan_kwargs())
+        assert kept == int(b.keep.sum())
+        assert np.array_equal(counts, oracle_bin_counts(b, ds.grid_n, ds.n_wplanes, ds.support, tile))
+        for k in range(ds.n_wplanes):
+            sel = b.keep & (b.k == k)
+            assert abs(psum[k] - b.wv[sel].sum()) <= 1e-9 * max(1.0, np.abs(b.wv[sel]).sum())
+        assert abs(sw - r.sum_w) <= 1e-9 * r.sum_w
