@@ -4,8 +4,14 @@ Stage by stage on the tiny workload: integer binning (bit-exact), the gridded
 planes G_k, the FFT of the GPU's own planes, the screen of the GPU's own
 F_k, and the end-to-end image; then precision modes, kernels, supports,
 oversampling, tile sizes, heavy-bin splitting, accumulation, edge cases.
-Tolerances are relative RMS errors (||a - b|| / ||b||):
-  per-stage FP32 1e-6, end-to-end FP32 image 1e-5, FP64 mode 1e-10.
+Tolerances are relative RMS errors (||a - b|| / ||b||): per-stage FP32 1e-6;
+end-to-end FP32 image 1e-5 on the apparent image (before the division by the
+kernel taper, which both sides apply as the same float64 per-pixel scale) and
+on the corrected image where the taper product C(l')C(m') >= 0.1; FP64 mode
+1e-10 on the whole corrected image.  (Behind the split: the taper division
+amplifies any float32 rounding by up to 1/C^2 at the image edge -- 6.4e3 for
+the default Gaussian, unbounded for wide ones -- and a float32 numpy/scipy
+pipeline shows the same whole-image errors.)
 """
 import numpy as np
 import pytest
@@ -14,7 +20,7 @@ import oracle
 import synth
 from oracle import wstack as ow
 from paper_2504_00959_amd import rick
-from tests.helpers import oracle_bin_counts, rel_rms, to_device
+from tests.helpers import image_errors, oracle_bin_counts, rel_rms, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +70,12 @@ def check_stages(ds, gpu, ref, stage_tol=FP32_STAGE, img_tol=FP32_IMG):
     # screen + normalisation of the GPU's own F_k
     S = ow.screen_sum(gpu["F"].astype(np.complex128), ref.w_k, ds.fov)
     mine = ow.normalise(S, ref.corr, ref.sum_w, ds.fov)
-    assert rel_rms(gpu["img"], mine) <= stage_tol
+    assert rel_rms(gpu["img"] * np.outer(ref.corr, ref.corr), mine * np.outer(ref.corr, ref.corr)) <= stage_tol
     # end to end
-    assert rel_rms(gpu["img"], ref.image) <= img_tol
+    err = image_errors(gpu["img"], ref.image, ref.corr)
+    assert err["apparent"] <= img_tol, err
+    assert err["central"] <= img_tol, err
+    return err
 
 
 def test_tiny_stagewise_fp32():
@@ -85,7 +94,9 @@ def test_tiny_fp64_mode():
 def test_tiny_kahan():
     ds = synth.tiny()
     gpu = run_gpu(ds, precision="fp32_kahan")
-    assert rel_rms(gpu["img"], oracle_of(ds).image) <= FP32_IMG
+    ref = oracle_of(ds)
+    err = image_errors(gpu["img"], ref.image, ref.corr)
+    assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
 
 
 def test_heavy_bins_split_over_chunks():
@@ -158,10 +169,11 @@ def test_accumulating_two_grid_calls_equals_one():
         p.fft()
         img1 = p.image().double().cpu().numpy()
         torch.cuda.synchronize()
-    ref = oracle_of(ds).image
+    ref = oracle_of(ds)
     assert n2 == ds.nvis
-    assert rel_rms(img2, ref) <= FP32_IMG
-    assert rel_rms(img1, ref) <= FP32_IMG
+    for img in (img1, img2):
+        err = image_errors(img, ref.image, ref.corr)
+        assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
 
 
 def test_empty_and_all_dropped_give_zero_image():
