@@ -87,8 +87,7 @@ typedef struct rick_plan_desc {
     int32_t device;        /* HIP device ordinal */
     int32_t flags;         /* RICK_FLAG_* */
     int32_t tile;          /* uv tile edge T in cells for binning and gridding: 0 = default (64), else a
-                              power of two 16..128 with T >= W whose gridding tile fits in LDS (in
-                              practice 16..64) */
+                              power of two 16..64 with T >= W */
     int32_t chunk;         /* largest number of binned records one gridding block takes: 0 = default */
 } rick_plan_desc;
 

@@ -7,7 +7,9 @@
 //               cell, closest w-plane, drop test; one count per (plane, tile)
 //               bin the W x W footprint touches (1, 2 or 4 bins);
 //               weight sum and gridded/dropped counters.
-//   bin_scan    exclusive prefix sums of record counts and gridding chunks.
+//   bin_scan    exclusive prefix sums of record counts and gridding chunks;
+//               per-copy cursors, the list of gridding work items and the
+//               list of bins split over several chunks.
 //   bin_scatter repeats the quantisation and writes 12-byte records
 //               {packed local position, W V} at cursor-allocated slots.
 //
@@ -25,19 +27,23 @@ namespace rick {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxBlocks = 8192;
+constexpr int kMaxBlocks = 8192;   // count and scatter use the same grid: a visibility meets the same counter copy
 
 __global__ void k_zero_stats(Stats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->n_gridded = 0;
         st->n_dropped = 0;
         st->n_records = 0;
+        st->n_heavy = 0;
         st->sum_w = 0.0;
     }
 }
 
-__global__ void k_fill_i32(int32_t *__restrict__ a, int32_t n, int32_t v) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = v;
+// zero the per-copy bin counters and the per-call heavy-bin count
+__global__ void k_reset_counts(int32_t *__restrict__ a, int64_t n, Stats *__restrict__ st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_heavy = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
 }
 
 __global__ void k_set_scales(double *__restrict__ dst, ChanScales cs, int32_t n) {
@@ -107,27 +113,49 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Wave-aggregated atomicAdd(&arr[key], 1) for every active lane; returns the
-// lane's old value (its slot).  Must be called by all lanes of the wave.
-__device__ __forceinline__ int32_t aggregated_slot(int32_t *arr, int32_t key, bool active) {
-    int32_t slot = 0;
+// Wave-aggregated atomicAdd(&arr[key], 1) for every active lane (no result).
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ void aggregated_count(int32_t *arr, int32_t key, bool active) {
     uint64_t pending = __ballot(active);
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const int32_t lkey = __builtin_amdgcn_readlane(key, leader);
         const bool mine = active && key == lkey;
         const uint64_t same = __ballot(mine);
-        int32_t base = 0;
-        if ((int)__lane_id() == leader) base = atomicAdd(&arr[lkey], (int32_t)__popcll(same));
-        base = __builtin_amdgcn_readlane(base, leader);
+        if ((int)__lane_id() == leader) atomicAdd(&arr[lkey], (int32_t)__popcll(same));
+        if (mine) active = false;
+        pending &= ~same;
+    }
+}
+
+// Wave-aggregated slot allocation: lanes with equal keys share one
+// atomicAdd(&arr[key], count).  The atomics are only issued here; the lane's
+// slot is base(leader) + rank, read after all of a wave's atomics are in
+// flight (slot_of), so the wave waits for the round trips once.
+struct SlotReq {
+    int32_t base;     // the returned old value (valid in leader lanes)
+    int32_t leader;   // lane holding this lane's base
+    int32_t rank;     // this lane's position among the lanes of its key
+};
+__device__ __forceinline__ SlotReq aggregated_slot_issue(int32_t *arr, int32_t key, bool active) {
+    SlotReq r{0, 0, 0};
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t lkey = __builtin_amdgcn_readlane(key, leader);
+        const bool mine = active && key == lkey;
+        const uint64_t same = __ballot(mine);
+        if ((int)__lane_id() == leader) r.base = atomicAdd(&arr[lkey], (int32_t)__popcll(same));
         if (mine) {
-            slot = base + (int32_t)__popcll(same & lanemask_lt());
+            r.leader = leader;
+            r.rank = (int32_t)__popcll(same & lanemask_lt());
             active = false;
         }
         pending &= ~same;
     }
-    return slot;
+    return r;
 }
+__device__ __forceinline__ int32_t slot_of(const SlotReq &r) { return __shfl(r.base, r.leader) + r.rank; }
 
 template <typename real>
 __device__ __forceinline__ void load_vis(const Geom &g, const double *__restrict__ uvw,
@@ -156,6 +184,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__re
     __shared__ unsigned long long s_kept[kBlock / 64], s_drop[kBlock / 64];
     double sum_w = 0.0;
     unsigned long long kept = 0, dropped = 0;
+    // counters are privatised over kCopies copies (by block), which spreads
+    // the atomics on the dense central bins over several cache lines
+    int32_t *my_counts = counts + (int64_t)(blockIdx.x % kCopies) * (g.nbins + 1);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t start = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     // loop bound uniform across the block so that every lane joins the ballots
@@ -180,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__re
         int32_t bin[4] = {0, 0, 0, 0};
         uint32_t pos[4];
         const int nb = keep ? footprint_bins(g, q, bin, pos) : 0;
-        for (int j = 0; j < 4; ++j) (void)aggregated_slot(counts, bin[j], j < nb);
+        for (int j = 0; j < 4; ++j) aggregated_count(my_counts, bin[j], j < nb);
     }
     // block reduction, one atomic per block and counter
     for (int off = 32; off > 0; off >>= 1) {
@@ -218,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__
                                                         const float *__restrict__ weight, int64_t nvis,
                                                         int32_t nchan, int32_t *__restrict__ cursor,
                                                         uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
+    int32_t *my_cursor = cursor + (int64_t)(blockIdx.x % kCopies) * g.nbins;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t start = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t iters = (nvis + stride - 1) / stride;
@@ -238,8 +270,12 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__
         int32_t bin[4] = {0, 0, 0, 0};
         uint32_t pos[4] = {0, 0, 0, 0};
         const int nb = keep ? footprint_bins(g, q, bin, pos) : 0;
+        SlotReq req[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) req[j] = aggregated_slot_issue(my_cursor, bin[j], j < nb);
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int32_t slot = aggregated_slot(cursor, bin[j], j < nb);
+            const int32_t slot = slot_of(req[j]);
             if (j < nb) {
                 rec_pos[slot] = pos[j];
                 store2(rec_vis + 2 * (int64_t)slot, ar, ai);
@@ -290,14 +326,22 @@ __device__ __forceinline__ void block_scan2(int32_t &a, int32_t &b, int32_t &tot
     __syncthreads();
 }
 
+__device__ __forceinline__ int32_t total_count(const int32_t *__restrict__ counts, int32_t n, int64_t i) {
+    int32_t c = 0;
+#pragma unroll
+    for (int s = 0; s < kCopies; ++s) c += counts[(int64_t)s * (n + 1) + i];
+    return c;
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_scan_partials(const int32_t *__restrict__ counts, int32_t n,
                                                               int32_t CH, int32_t *__restrict__ bsum) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int32_t a = 0, b = 0;
     for (int k = 0; k < kScanPer; ++k) {
         if (base + k < n) {
-            a += counts[base + k];
-            b += chunks_of(counts[base + k], CH);
+            const int32_t c = total_count(counts, n, base + k);
+            a += c;
+            b += chunks_of(c, CH);
         }
     }
     int32_t ta, tb;
@@ -328,11 +372,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(int32_t *__restrict__ b
 __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int32_t *__restrict__ counts, int32_t n, int32_t CH,
                                                            const int32_t *__restrict__ bsum,
                                                            BinScan *__restrict__ scan, int32_t *__restrict__ cursor,
-                                                           Stats *__restrict__ st) {
+                                                           int32_t *__restrict__ item_bin,
+                                                           int32_t *__restrict__ heavy_bins, Stats *__restrict__ st) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int32_t c[kScanPer], a = 0, b = 0;
     for (int k = 0; k < kScanPer; ++k) {
-        c[k] = base + k < n ? counts[base + k] : 0;
+        c[k] = base + k < n ? total_count(counts, n, base + k) : 0;
         a += c[k];
         b += base + k < n ? chunks_of(c[k], CH) : 0;
     }
@@ -345,9 +390,17 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int32_t *__rest
         if (i < n) {
             scan[i].rec = a;
             scan[i].item = b;
-            cursor[i] = a;
+            // each counter copy owns a contiguous sub-range of the bin
+            int32_t cur = a;
+            for (int s = 0; s < kCopies; ++s) {
+                cursor[(int64_t)s * n + i] = cur;
+                cur += counts[(int64_t)s * (n + 1) + i];
+            }
+            const int32_t nch = chunks_of(c[k], CH);
+            for (int32_t j = 0; j < nch; ++j) item_bin[b + j] = (int32_t)i;
+            if (nch > 1) heavy_bins[atomicAdd(&st->n_heavy, 1ull)] = (int32_t)i;
             a += c[k];
-            b += chunks_of(c[k], CH);
+            b += nch;
         } else if (i == n) {
             scan[i].rec = a;
             scan[i].item = b;
@@ -370,10 +423,11 @@ hipError_t launch_zero_stats(Stats *st, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_reset_counts(int32_t *counts, int32_t n, hipStream_t s) {
-    int blocks = (n + 255) / 256;
+hipError_t launch_reset_counts(const Geom &g, int32_t *counts, Stats *st, hipStream_t s) {
+    const int64_t n = (int64_t)kCopies * (g.nbins + 1);
+    int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, counts, n, 0);
+    hipLaunchKernelGGL(k_reset_counts, dim3((unsigned)blocks), dim3(256), 0, s, counts, n, st);
     return hipGetLastError();
 }
 
@@ -399,13 +453,13 @@ hipError_t launch_bin_count(const Geom &g, const double *uvw, const double *scal
 }
 
 hipError_t launch_bin_scan(const Geom &g, const int32_t *counts, BinScan *scan, int32_t *block_sums, int32_t *cursor,
-                           Stats *st, hipStream_t s) {
+                           int32_t *item_bin, int32_t *heavy_bins, Stats *st, hipStream_t s) {
     const int32_t n = g.nbins;
     const int32_t nblk = (n + 1 + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_partials, dim3(nblk), dim3(kScanBlock), 0, s, counts, n, g.CH, block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, block_sums, nblk);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanBlock), 0, s, counts, n, g.CH, block_sums, scan, cursor,
-                       st);
+                       item_bin, heavy_bins, st);
     return hipGetLastError();
 }
 

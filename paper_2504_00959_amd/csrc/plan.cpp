@@ -102,6 +102,8 @@ struct rick_plan_s {
     BinScan *scan = nullptr;
     int32_t *block_sums = nullptr;
     int32_t *cursor = nullptr;
+    int32_t *item_bin = nullptr;
+    int32_t *heavy_bins = nullptr;
     uint32_t *rec_pos = nullptr;
     void *rec_vis = nullptr;
     int64_t rec_cap = 0;
@@ -132,7 +134,7 @@ struct DeviceGuard {
 
 void free_all(rick_plan_t *p) {
     void *bufs[] = {p->mesh, p->lut, p->twiddle, p->corr, p->wk, p->scales, p->stats, p->counts,
-                    p->scan, p->block_sums, p->cursor, p->rec_pos, p->rec_vis};
+                    p->scan, p->block_sums, p->cursor, p->item_bin, p->heavy_bins, p->rec_pos, p->rec_vis};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < kMaxTimers; ++i)
@@ -165,8 +167,8 @@ rick_status validate(const rick_plan_desc *d) {
     if (d->device < 0) return fail(RICK_E_INVALID_ARG, "device=%d", d->device);
     if (d->flags & ~int32_t(RICK_FLAG_TIMING)) return fail(RICK_E_INVALID_ARG, "flags=%d: unknown bits", d->flags);
     if (d->tile != 0) {
-        if (!is_pow2(d->tile) || d->tile < 16 || d->tile > 128 || d->tile < d->support || d->tile > d->grid_n)
-            return fail(RICK_E_INVALID_ARG, "tile=%d: power of two in [16, 128], >= support, <= grid_n", d->tile);
+        if (!is_pow2(d->tile) || d->tile < 16 || d->tile > 64 || d->tile < d->support || d->tile > d->grid_n)
+            return fail(RICK_E_INVALID_ARG, "tile=%d: power of two in [16, 64], >= support, <= grid_n", d->tile);
     }
     if (d->chunk < 0 || d->chunk > (1 << 24)) return fail(RICK_E_INVALID_ARG, "chunk=%d", d->chunk);
     return RICK_OK;
@@ -256,9 +258,9 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         g.pitch = pitch;
     }
     {
-        // the gridding block keeps two T x pitch float64 accumulators and the tap table in LDS
+        // the gridding block keeps two T x pitch accumulators and the tap table in LDS
         const size_t rb = p->fp64 ? 8 : 4;
-        const size_t lds = size_t(2) * g.T * g.pitch * 8 + size_t(g.OS) * g.W * rb;
+        const size_t lds = size_t(2) * g.T * g.pitch * rb + size_t(g.OS) * g.W * rb;
         if (lds > size_t(160) * 1024) {
             delete p;
             return fail(RICK_E_INVALID_ARG, "tile=%d with support %d, oversample %d needs %zu B of LDS (> 160 KB)",
@@ -314,7 +316,9 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     p->mesh_bytes = size_t(g.Nw) * g.N * g.N * 2 * rb;
     const size_t sz_lut = size_t(g.OS) * g.W * rb;
     const size_t sz_tw = size_t(g.N) * 2 * rb;
-    const size_t sz_counts = size_t(g.nbins + 1) * sizeof(int32_t);
+    const size_t sz_counts = size_t(kCopies) * (g.nbins + 1) * sizeof(int32_t);
+    const size_t sz_items = size_t(p->max_items + 1) * sizeof(int32_t);
+    const size_t sz_heavy = size_t(p->rec_cap / (g.CH + 1) + 2) * sizeof(int32_t);
     const size_t sz_scan = size_t(g.nbins + 1) * sizeof(BinScan);
     const size_t n_blk = (size_t(g.nbins) + 1 + 2047) / 2048 + 1;
     const size_t sz_bsum = n_blk * 2 * sizeof(int32_t) + 64;
@@ -322,6 +326,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
     const size_t total = p->mesh_bytes + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
                          size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_counts +
+                         sz_items + sz_heavy +
                          sz_pos + sz_rvis;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
@@ -354,6 +359,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->scan, sz_scan);
     ALLOC(p->block_sums, sz_bsum);
     ALLOC(p->cursor, sz_counts);
+    ALLOC(p->item_bin, sz_items);
+    ALLOC(p->heavy_bins, sz_heavy);
     ALLOC(p->rec_pos, sz_pos);
     ALLOC(p->rec_vis, sz_rvis);
 #undef ALLOC
@@ -470,7 +477,7 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     const int32_t max_items = int32_t(g.nbins + (4 * nvis + g.CH - 1) / g.CH);
 
     timer_begin(p, T_COUNT, "bin_count", s);
-    e = launch_reset_counts(p->counts, g.nbins + 1, s);
+    e = launch_reset_counts(g, p->counts, p->stats, s);
     if (e == hipSuccess) {
         if (p->fp64)
             e = launch_bin_count<double>(g, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
@@ -482,7 +489,7 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     timer_end(p, T_COUNT, s);
     if (e != hipSuccess) return hip_fail(e, "bin_count");
     timer_begin(p, T_SCAN, "bin_scan", s);
-    e = launch_bin_scan(g, p->counts, p->scan, p->block_sums, p->cursor, p->stats, s);
+    e = launch_bin_scan(g, p->counts, p->scan, p->block_sums, p->cursor, p->item_bin, p->heavy_bins, p->stats, s);
     timer_end(p, T_SCAN, s);
     if (e != hipSuccess) return hip_fail(e, "bin_scan");
     timer_begin(p, T_SCATTER, "bin_scatter", s);
@@ -496,17 +503,17 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     if (e != hipSuccess) return hip_fail(e, "bin_scatter");
     if (!accumulate) {
         timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
-        if (p->fp64) e = launch_zero_heavy<double>(g, p->scan, (double *)p->mesh, max_items, s);
-        else e = launch_zero_heavy<float>(g, p->scan, (float *)p->mesh, max_items, s);
+        if (p->fp64) e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, (double *)p->mesh, s);
+        else e = launch_zero_heavy<float>(g, p->heavy_bins, p->stats, (float *)p->mesh, s);
         timer_end(p, T_ZERO_HEAVY, s);
         if (e != hipSuccess) return hip_fail(e, "zero_heavy");
     }
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
-        e = launch_grid<double>(g, p->scan, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
+        e = launch_grid<double>(g, p->scan, p->item_bin, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
                                 (double *)p->mesh, accumulate, max_items, s);
     else
-        e = launch_grid<float>(g, p->scan, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
+        e = launch_grid<float>(g, p->scan, p->item_bin, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
                                (float *)p->mesh, accumulate, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
@@ -616,8 +623,10 @@ rick_status rick_plan_bin_counts(rick_plan_t *p, int32_t *counts, int64_t n) {
     if (n != p->g.nbins) return fail(RICK_E_INVALID_ARG, "n=%lld, plan has %d bins", (long long)n, p->g.nbins);
     DeviceGuard guard(p->d.device);
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(counts, p->counts, size_t(n) * sizeof(int32_t), hipMemcpyDeviceToHost);
+    std::vector<BinScan> sc(size_t(n) + 1);
+    if (e == hipSuccess) e = hipMemcpy(sc.data(), p->scan, (size_t(n) + 1) * sizeof(BinScan), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read bin counts");
+    for (int64_t i = 0; i < n; ++i) counts[i] = sc[i + 1].rec - sc[i].rec;
     return RICK_OK;
 }
 

@@ -13,6 +13,7 @@ constexpr double kC0 = 299792458.0;      // speed of light, m/s
 constexpr int kMaxInlineChan = 32;       // channel scale factors per kernel-argument upload
 constexpr int kMaxChan = 1 << 16;        // capacity of the plan's channel scale buffer
 constexpr int kMaxTimers = 16;
+constexpr int kCopies = 16;              // privatised copies of the per-bin counters
 constexpr int kTimerRing = 64;         // launches per kernel whose times are kept between reads
 
 // A batch of channel scale factors nu_c / c0, passed by value.
@@ -45,7 +46,7 @@ struct Stats {
     unsigned long long n_gridded;
     unsigned long long n_dropped;
     unsigned long long n_records;   // records written by the last rick_grid
-    unsigned long long pad;
+    unsigned long long n_heavy;     // bins of the last rick_grid split over several chunks
     double sum_w;
     double pad2[3];
 };
@@ -61,7 +62,7 @@ struct BinScan {
 hipError_t launch_zero_stats(Stats *st, hipStream_t s);
 template <typename real>
 hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s);
-hipError_t launch_reset_counts(int32_t *counts, int32_t n, hipStream_t s);
+hipError_t launch_reset_counts(const Geom &g, int32_t *counts, Stats *st, hipStream_t s);
 
 // Pass 1 of bin-and-sort: per-bin record counts, drop counts and weight sum.
 // Channel scale factors nu_c / c0 into the plan's device buffer (kernel arguments, no copies).
@@ -70,9 +71,9 @@ template <typename real>
 hipError_t launch_bin_count(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
                             const float *weight, int64_t nrow, int32_t nchan, int32_t *counts, Stats *st,
                             hipStream_t s);
-// Exclusive scan of counts into BinScan, chunk counts, cursors = record offsets.
+// Exclusive scan of counts into BinScan; per-copy cursors; gridding item list; heavy-bin list.
 hipError_t launch_bin_scan(const Geom &g, const int32_t *counts, BinScan *scan, int32_t *block_sums,
-                           int32_t *cursor, Stats *st, hipStream_t s);
+                           int32_t *cursor, int32_t *item_bin, int32_t *heavy_bins, Stats *st, hipStream_t s);
 // Pass 2: scatter records {packed position, W V} into their bins.
 template <typename real>
 hipError_t launch_bin_scatter(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
@@ -80,10 +81,11 @@ hipError_t launch_bin_scatter(const Geom &g, const double *uvw, const double *sc
                               real *rec_vis, hipStream_t s);
 // Gridding: zero heavy tiles, then one block per (bin, chunk) item.
 template <typename real>
-hipError_t launch_grid(const Geom &g, const BinScan *scan, const uint32_t *rec_pos, const real *rec_vis,
-                       const real *lut, real *mesh, int accumulate, int32_t max_items, hipStream_t s);
+hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
+                       const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
+                       hipStream_t s);
 template <typename real>
-hipError_t launch_zero_heavy(const Geom &g, const BinScan *scan, real *mesh, int32_t max_heavy, hipStream_t s);
+hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, real *mesh, hipStream_t s);
 // Batched centred 2-D inverse FFT, in place, all planes.
 template <typename real>
 hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);

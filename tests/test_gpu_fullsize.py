@@ -32,7 +32,7 @@ def share():
     nt = ds.grid_n // info["tile"]
     counts = p.bin_counts(ds.n_wplanes * nt * nt)
     G = p.mesh()
-    plane_sums = G.sum(dim=(1, 2)).cpu().numpy().astype(np.complex128)
+    plane_sums = G.to(torch.complex128).sum(dim=(1, 2)).cpu().numpy()
     del G
     p.fft()
     F = p.mesh()
