@@ -41,6 +41,7 @@ def algorithmic_bytes(name, ds, info):
         "fft_rows": 16 * cells,
         "fft_cols": 16 * cells,
         "wscreen": 8 * cells + 4 * ds.grid_n * ds.grid_n,
+        "fft_cols_screen": 8 * cells + 4 * ds.grid_n * ds.grid_n,
     }
     return table.get(name)
 
@@ -120,6 +121,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_kahan", "fp64"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--unfused", action="store_true",
+                    help="column FFT and w-screen as separate kernels (F_k written to HBM)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-pixels", type=int, default=6,
                     help="pixels of the timed image checked against the float64 oracle (0 = skip)")
@@ -152,7 +155,8 @@ def main():
     cd = torch.complex128 if args.precision == "fp64" else torch.complex64
     vis = ds.vis.to(dtype=cd).contiguous()
     wt = None
-    plan = rick.Plan.for_dataset(ds, precision=args.precision, timing=True, tile=args.tile, chunk=args.chunk)
+    plan = rick.Plan.for_dataset(ds, precision=args.precision, timing=True, tile=args.tile, chunk=args.chunk,
+                                 fused=not args.unfused)
     stream = torch.cuda.current_stream()
     img = torch.empty((ds.grid_n, ds.grid_n), dtype=plan.real_dtype, device=dev)
 
@@ -232,7 +236,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": describe(ds), "n_vis": ds.nvis, "grid_n": ds.grid_n, "n_wplanes": ds.n_wplanes,
                    "support": ds.support, "oversample": ds.oversample, "precision": args.precision,
-                   "tile": info["tile"], "chunk": info["chunk"], "parallelism": "1 GPU"},
+                   "tile": info["tile"], "chunk": info["chunk"], "fused_screen": not args.unfused,
+                   "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

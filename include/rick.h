@@ -67,7 +67,12 @@ enum {
     RICK_PREC_FP64 = 2         /* every step in float64 (complex128 mesh) */
 };
 
-enum { RICK_FLAG_TIMING = 1 }; /* record per-kernel HIP events; read them with rick_plan_info */
+enum {
+    RICK_FLAG_TIMING = 1,       /* record per-kernel HIP events; read them with rick_plan_info */
+    RICK_FLAG_FUSED_SCREEN = 2  /* rick_fft_planes transforms rows only; rick_wstack_image transforms the
+                                   columns plane by plane and screens and sums them in the same pass, so
+                                   F_k is never written to HBM (the mesh then holds the row transforms) */
+};
 
 /* Plan parameters (Sec. 2.1: mesh N_u x N_v x N_w, kernel type and support). */
 typedef struct rick_plan_desc {
@@ -151,7 +156,8 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
  * rick_fft_planes -- in place, every plane becomes its centred inverse DFT
  * (the FFT step of Sec. 2.1):
  *   F_k[q][p] = sum_{j,i} G_k[j][i] exp(+2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
- * (unnormalised).  Requires a gridded mesh (RICK_E_STATE otherwise; a mesh
+ * (unnormalised).  With RICK_FLAG_FUSED_SCREEN only the sum over i (the row
+ * transform) is done here and the sum over j happens in rick_wstack_image.  Requires a gridded mesh (RICK_E_STATE otherwise; a mesh
  * that nothing was gridded onto since the reset is transformed as zeros).
  * Errors: RICK_E_BAD_PLAN, RICK_E_STATE, RICK_E_HIP.
  */

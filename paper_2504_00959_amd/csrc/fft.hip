@@ -11,7 +11,9 @@
 //   a_j = x[b + j n] * w_{L R}^{j k},  A = DFT_R(a),  y[(b / L) L R + k + q L] = A_q
 // with w_M = exp(+2 pi i / M); the first stage has radix 2 or 4 when log2 N
 // is not a multiple of 3, the rest radix 8.  Twiddles come from a table of
-// exp(+2 pi i m / N) computed in float64 on the host and rounded.
+// exp(+2 pi i m / N) computed in float64 on the host and rounded; a radix-8
+// butterfly reads w, w^2, w^4 and forms w^3, w^5, w^6, w^7 as one product of
+// two table entries each.
 //
 // Centring: for N divisible by 4,
 //   sum_i x_i exp(+2 pi i (i - N/2)(p - N/2) / N) = (-1)^p sum_i (-1)^i x_i exp(+2 pi i i p / N),
@@ -119,12 +121,25 @@ __device__ __forceinline__ void stage(C *buf, int L, int tb, int v0, const C *__
         const int b = tb + i * NT;
         const int k = b & (L - 1);
         if (L > 1) {
+            // w^j for j < R: w, w^2, w^4 from the table, the rest as one product
+            // of two table entries each
             const int step = k * (N / (L * R));
+            C wj[R];
+            wj[1] = tw[step];
+            if constexpr (R >= 4) {
+                wj[2] = tw[2 * step];
+                wj[3] = cmul(wj[1], wj[2]);
+            }
+            if constexpr (R == 8) {
+                wj[4] = tw[4 * step];
+                wj[5] = cmul(wj[1], wj[4]);
+                wj[6] = cmul(wj[2], wj[4]);
+                wj[7] = cmul(wj[3], wj[4]);
+            }
 #pragma unroll
             for (int j = 1; j < R; ++j) {
-                const C w = tw[j * step];
 #pragma unroll
-                for (int v = 0; v < VC; ++v) a[i][v][j] = cmul(a[i][v][j], w);
+                for (int v = 0; v < VC; ++v) a[i][v][j] = cmul(a[i][v][j], wj[j]);
             }
         }
 #pragma unroll
@@ -215,6 +230,108 @@ __global__ __launch_bounds__((N / 8) * (V / VC)) void k_fft_cols(real *__restric
     }
 }
 
+__device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
+
+// ---- columns fused with the w-correction and the plane sum ----
+// One block per strip of V columns loops over all planes: the strip of plane
+// k (already transformed along rows) is staged in LDS and transformed along
+// columns, and each thread adds Re(exp(+2 pi i w_k (n - 1)) F_k) for the
+// pixels it owns; plane k + 1 is fetched into registers meanwhile.  The
+// transformed planes are never written back, and the image is written once.
+// Phase in float64 turns, reduced to [-1/2, 1/2] before sincospi, as in the
+// stand-alone screen.
+template <typename real, int N, int V, int VC, bool KAHAN>
+__global__ __launch_bounds__((N / 8) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
+                                                                        const real *__restrict__ twr,
+                                                                        const double *__restrict__ wk,
+                                                                        const double *__restrict__ corr,
+                                                                        const Stats *__restrict__ st,
+                                                                        real *__restrict__ image) {
+    using C = typename R2T<real>::t;
+    constexpr int NT = N / 8;
+    constexpr int NTH = NT * (V / VC);
+    constexpr int NSTRIP = N / V;
+    constexpr int PPT = N * V / NTH;   // pixels per thread
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *buf = reinterpret_cast<C *>(smem);
+    const C *tw = reinterpret_cast<const C *>(twr);
+    int strip = blockIdx.x;
+    if ((NSTRIP & 7) == 0) strip = (blockIdx.x & 7) * (NSTRIP >> 3) + (blockIdx.x >> 3);
+    const int c0 = strip * V;
+    const C *g0 = reinterpret_cast<const C *>(mesh) + c0;
+    const int64_t plane_stride = (int64_t)N * N;
+    const double dl = g.fov / N;
+    // n - 1 of the strip's pixels, float64, in LDS after the strip buffer
+    double *s_nm1 = reinterpret_cast<double *>(buf + (N + N / 8) * V);
+    real acc[PPT], comp[PPT];
+    C pre[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int idx = threadIdx.x + NTH * i;
+        const int e = idx / V, v = idx % V;
+        const double l = (double)(c0 + v - N / 2) * dl, m = (double)(e - N / 2) * dl;
+        const double r2 = l * l + m * m;
+        s_nm1[idx] = r2 < 1.0 ? -r2 / (1.0 + sqrt(1.0 - r2)) : 0.0;
+        acc[i] = 0;
+        comp[i] = 0;
+        pre[i] = g0[(int64_t)e * N + v];
+    }
+    const int tb = threadIdx.x % NT, v0 = (threadIdx.x / NT) * VC;
+    for (int k = 0; k < g.Nw; ++k) {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int idx = threadIdx.x + NTH * i;
+            const int e = idx / V, v = idx % V;
+            buf[padi(e) * V + v] = cneg_if(pre[i], e & 1);
+        }
+        __syncthreads();
+        if (k + 1 < g.Nw) {
+            const C *gk = g0 + (int64_t)(k + 1) * plane_stride;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int idx = threadIdx.x + NTH * i;
+                const int e = idx / V, v = idx % V;
+                pre[i] = gk[(int64_t)e * N + v];
+            }
+        }
+        fft_lds<N, V, VC, NT>(buf, tb, v0, tw);
+        const double w = wk[k];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int idx = threadIdx.x + NTH * i;
+            const int e = idx / V, v = idx % V;
+            const C f = cneg_if(buf[padi(e) * V + v], e & 1);
+            const double tau = w * s_nm1[idx];
+            const double tr = tau - rint(tau);
+            real sn, cs;
+            sincospi_r((real)(2.0 * tr), &sn, &cs);
+            const real term = cs * f.x - sn * f.y;
+            if (KAHAN) {
+                const real y = term - comp[i];
+                const real t = acc[i] + y;
+                comp[i] = (t - acc[i]) - y;
+                acc[i] = t;
+            } else {
+                acc[i] += term;
+            }
+        }
+        __syncthreads();
+    }
+    const double sw = st->sum_w;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int idx = threadIdx.x + NTH * i;
+        const int e = idx / V, v = idx % V;
+        const int p = c0 + v, q = e;
+        const double l = (double)(p - N / 2) * dl, m = (double)(q - N / 2) * dl;
+        const bool in_sky = l * l + m * m < 1.0;
+        const double val =
+            (sw > 0.0 && in_sky) ? (1.0 + s_nm1[idx]) * (double)acc[i] / (corr[p] * corr[q] * sw) : 0.0;
+        image[(int64_t)q * N + p] = (real)val;
+    }
+}
+
 template <typename real, int N>
 hipError_t rows_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     using C = typename R2T<real>::t;
@@ -236,8 +353,9 @@ hipError_t rows_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
 template <typename real, int N>
 hipError_t cols_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     using C = typename R2T<real>::t;
-    // V columns per block: the strip fills about 128 KB of LDS (16 for small N)
-    constexpr int VRAW = (16384 * 8 / (int)sizeof(C)) / N;
+    // V columns per block: the strip fills about 74 KB of LDS, so that two
+    // blocks share a CU and one loads while the other computes (16 for small N)
+    constexpr int VRAW = (8192 * 8 / (int)sizeof(C)) / N;
     constexpr int V = VRAW < 1 ? 1 : (VRAW > 16 ? 16 : VRAW);
     constexpr int NT = N / 8;
     constexpr int VC = (NT * V > 1024) ? (NT * V) / 1024 : 1;
@@ -254,9 +372,60 @@ hipError_t cols_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename real, int N>
+hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const double *wk, const double *corr,
+                         const Stats *st, real *image, int kahan, hipStream_t s) {
+    using C = typename R2T<real>::t;
+    // two columns per strip for N >= 4096 (one in float64 at 8192): a 74 KB strip
+    // and eight pixels per thread of plane-sum state
+    constexpr int VRAW = (8192 * 8 / (int)sizeof(C)) / N;
+    constexpr int V = VRAW < 1 ? 1 : (VRAW > 16 ? 16 : VRAW);
+    constexpr int NT = N / 8;
+    constexpr int VC = (NT * V > 1024) ? (NT * V) / 1024 : 1;
+    const size_t lds = size_t(N + N / 8) * V * sizeof(C) + size_t(N) * V * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, V, VC, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, V, VC, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    if (kahan)
+        hipLaunchKernelGGL((k_fft_cols_screen<real, N, V, VC, true>), dim3(N / V), dim3(NT * (V / VC)), lds, s, g,
+                           mesh, tw, wk, corr, st, image);
+    else
+        hipLaunchKernelGGL((k_fft_cols_screen<real, N, V, VC, false>), dim3(N / V), dim3(NT * (V / VC)), lds, s, g,
+                           mesh, tw, wk, corr, st, image);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool fft_supported(int N) { return N >= 64 && N <= 8192 && (N & (N - 1)) == 0; }
+
+size_t fused_screen_lds_bytes(int N, size_t real_bytes) {
+    const int cbytes = (int)(2 * real_bytes);
+    int v = (8192 * 8 / cbytes) / N;
+    v = v < 1 ? 1 : (v > 16 ? 16 : v);
+    return size_t(N + N / 8) * v * cbytes + size_t(N) * v * sizeof(double);
+}
+
+template <typename real>
+hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *wk,
+                                  const double *corr, const Stats *st, real *image, int kahan, hipStream_t s) {
+    switch (g.N) {
+#define CASE(n) \
+    case n: return cols_screen_n<real, n>(g, mesh, tw, wk, corr, st, image, kahan, s);
+        CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, const float *, const double *,
+                                                  const double *, const Stats *, float *, int, hipStream_t);
+template hipError_t launch_fft_cols_screen<double>(const Geom &, const double *, const double *, const double *,
+                                                   const double *, const Stats *, double *, int, hipStream_t);
 
 template <typename real>
 hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *tw, hipStream_t s) {

@@ -2,23 +2,30 @@
 // the w-plane stack.
 //
 // One block takes one work item: a chunk of at most CH records of one
-// (plane, tile) bin.  The tile's T x T accumulator (re and im planes) lives in
-// LDS; each wave takes one record at a time with one lane per kernel tap
-// (lane t < W*W is tap (t / W, t % W)), so one record costs two LDS atomic
-// adds and no lane pair of an instruction shares an address.  Records arrive
-// 64 at a time in one coalesced load and are broadcast across the wave with
-// readlane.  The LDS row pitch is congruent to W modulo 32 elements.  Every
-// 4 x 64 records per wave the LDS tile is folded into float64 registers
-// (each thread owns T^2/256 cells) and cleared: dense cells collect
-// thousands of terms, and float32 accumulation of all of them would cost
-// about 1e-5 of image RMS.  Taps outside the tile are skipped: a record whose
-// footprint straddles tile edges was binned into every tile it touches.
+// (plane, tile) bin.  The tile's T x T accumulator (float64 re and im planes)
+// lives in LDS; each wave takes one record at a time with one lane per kernel
+// tap (lane t < W*W is tap (t / W, t % W)), so one record costs two LDS
+// atomic adds and no lane pair of an instruction shares an address.  The LDS
+// row pitch is congruent to W modulo 32 elements, which spreads the W x W
+// footprint over the banks.
 //
-// After the records, the tile is written to HBM once, row-coalesced:
+// Accumulators are float64 in every precision mode: float64 LDS atomic adds
+// run at the rate of plain LDS traffic on gfx950, float32 ones several times
+// slower, and dense cells collect thousands of terms, which float32
+// accumulation would round to ~1e-5 of image RMS.
+//
+// Records arrive 64 at a time in one coalesced load; each lane decodes the
+// record it loaded (footprint origin, tap-table rows, whether the footprint
+// lies inside the tile), and the decoded fields are broadcast with readlane,
+// two records per step so that their tap-table reads overlap.  Taps outside
+// the tile are skipped: a record whose footprint straddles tile edges was
+// binned into every tile it touches.
+//
+// After the records the tile is written to HBM once, row-coalesced:
 //   - bins with a single chunk own their tile and store it (empty bins store
 //     zeros, so the mesh needs no clearing);
 //   - bins split over several chunks (the dense uv centre) add their partial
-//     tiles with float atomics onto a tile zeroed beforehand.
+//     tiles with atomics onto a tile zeroed beforehand.
 // On a rick_grid that accumulates onto an earlier one, every tile is added.
 #include "rick_internal.h"
 
@@ -26,7 +33,8 @@ namespace rick {
 
 namespace {
 
-constexpr int kGridBlock = 256;
+constexpr int kGridBlock = 512;   // 8 waves share one tile
+constexpr int kZeroBlock = 256;
 
 template <typename real>
 struct real2_t;
@@ -39,6 +47,7 @@ struct real2_t<double> {
     using type = double2;
 };
 
+__device__ __forceinline__ int32_t bcast(int32_t v, int j) { return __builtin_amdgcn_readlane(v, j); }
 __device__ __forceinline__ float bcast(float v, int j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
@@ -54,30 +63,55 @@ __device__ __forceinline__ void atomic_add_real(double *p, double v) { unsafeAto
 
 // Heavy bins (several chunks) are zeroed before gridding; the scan lists them.
 template <typename real>
-__global__ __launch_bounds__(kGridBlock) void k_zero_heavy(Geom g, const int32_t *__restrict__ heavy_bins,
+__global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t *__restrict__ heavy_bins,
                                                            const Stats *__restrict__ st, real *__restrict__ mesh) {
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
     const int32_t nheavy = (int32_t)st->n_heavy;
-    for (int32_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
-        const int32_t b = heavy_bins[h];
+    for (int32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
+        const int32_t b = heavy_bins[hb];
         const int32_t k = b / (g.nt * g.nt);
         const int32_t rem = b - k * g.nt * g.nt;
         const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
-        for (int32_t c = threadIdx.x; c < g.T * g.T; c += kGridBlock) {
+        for (int32_t c = threadIdx.x; c < g.T * g.T; c += kZeroBlock) {
             const int32_t y = c >> g.log2T, x = c & (g.T - 1);
             m[((int64_t)k * g.N + y0 + y) * g.N + x0 + x] = r2{0, 0};
         }
     }
 }
 
-// acc_t: LDS accumulator type (float in the float32 modes, double in float64
-// mode).  The LDS tile is folded into float64 registers every kRound records
-// per block, so a float accumulator only ever sums a few terms per cell.
-constexpr int kBatchesPerRound = 4;                       // per wave
-constexpr int kMaxCellsPerThread = 16;                    // T <= 64
+// One decoded record, as broadcast to the wave.
+template <typename real>
+struct Rec {
+    int32_t base;   // LDS index of the footprint's first tap (may be < 0 for straddling records)
+    int32_t lxy;    // tap-table row offsets: (s_x row * W) | (s_y row * W) << 16
+    int32_t oxy;    // footprint origin in tile cells, (ox + 64) | (oy + 64) << 8, bit 31: fully inside
+    real vr, vi;
+};
 
-template <typename real, typename acc_t, int W>
+template <typename real, int W, int NG>
+__device__ __forceinline__ void add_record(const Rec<real> &r, const int (&tap_ty)[NG], const int (&tap_tx)[NG],
+                                           const int (&tap_off)[NG], const bool (&tap_on)[NG], int T,
+                                           const real *__restrict__ s_lut, double *acc_re, double *acc_im) {
+    const bool inside = r.oxy < 0;
+    const int ox = (r.oxy & 0xff) - 64, oy = ((r.oxy >> 8) & 0xff) - 64;
+    const int lx = r.lxy & 0xffff, ly = r.lxy >> 16;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+        bool on = tap_on[gi];
+        if (!inside) {
+            const int x = ox + tap_tx[gi], y = oy + tap_ty[gi];
+            on = on && x >= 0 && x < T && y >= 0 && y < T;
+        }
+        if (on) {
+            const real wgt = s_lut[ly + tap_ty[gi]] * s_lut[lx + tap_tx[gi]];
+            atomicAdd(&acc_re[r.base + tap_off[gi]], (double)(wgt * r.vr));
+            atomicAdd(&acc_im[r.base + tap_off[gi]], (double)(wgt * r.vi));
+        }
+    }
+}
+
+template <typename real, int W>
 __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__restrict__ scan,
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
@@ -101,28 +135,34 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     const int32_t n = r_end - r_begin;
 
     const int32_t T = g.T, P = g.pitch;
-    acc_t *acc_re = reinterpret_cast<acc_t *>(smem);
-    acc_t *acc_im = acc_re + T * P;
-    real *s_lut = reinterpret_cast<real *>(acc_im + T * P);
-    // cells owned by this thread for the register fold and the final store
-    const int cpt = (T * T) / kGridBlock;
-    double fre[kMaxCellsPerThread], fim[kMaxCellsPerThread];
-#pragma unroll
-    for (int i = 0; i < kMaxCellsPerThread; ++i) {
-        fre[i] = 0.0;
-        fim[i] = 0.0;
-    }
-    if (n > 0) {
-        for (int i = threadIdx.x; i < T * P; i += kGridBlock) {
-            acc_re[i] = 0;
-            acc_im[i] = 0;
+    const int32_t k = b / (g.nt * g.nt);
+    const int32_t rem = b - k * g.nt * g.nt;
+    const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
+    using r2 = typename real2_t<real>::type;
+    r2 *m = reinterpret_cast<r2 *>(mesh);
+    if (n == 0) {
+        // empty bin: a single chunk that owns its tile; store zeros unless accumulating
+        if (!accumulate) {
+            for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
+                const int32_t y = c >> g.log2T, x = c & (T - 1);
+                m[((int64_t)k * g.N + y0 + y) * g.N + x0 + x] = r2{0, 0};
+            }
         }
+        return;
+    }
+    double *acc_re = reinterpret_cast<double *>(smem);
+    double *acc_im = acc_re + T * P;
+    real *s_lut = reinterpret_cast<real *>(acc_im + T * P);
+    for (int i = threadIdx.x; i < T * P; i += kGridBlock) {
+        acc_re[i] = 0.0;
+        acc_im[i] = 0.0;
+    }
+    {
         for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
         __syncthreads();
 
         const int lane = __lane_id();
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        // per-lane taps: lane + 64 gi -> (ty, tx)
         int tap_ty[NG], tap_tx[NG], tap_off[NG];
         bool tap_on[NG];
 #pragma unroll
@@ -134,86 +174,53 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
             tap_off[gi] = tap_ty[gi] * P + tap_tx[gi];
         }
         const int32_t nbatch = (n + 63) >> 6;
-        const int32_t per_round = nwave * kBatchesPerRound;
-        const int32_t nround = (nbatch + per_round - 1) / per_round;
-        for (int32_t rd = 0; rd < nround; ++rd) {
-            // records in batches of 64: one coalesced load per batch, broadcast by readlane
-            for (int f = 0; f < kBatchesPerRound; ++f) {
-                const int32_t bt = rd * per_round + f * nwave + wave;
-                if (bt >= nbatch) break;
-                const int32_t r0 = r_begin + (bt << 6);
-                const int32_t cnt = min(64, r_end - r0);
-                uint32_t vpos = 0;
-                real vre = 0, vim = 0;
-                if (lane < cnt) {
-                    vpos = rec_pos[r0 + lane];
-                    vre = rec_vis[2 * (int64_t)(r0 + lane)];
-                    vim = rec_vis[2 * (int64_t)(r0 + lane) + 1];
-                }
-                for (int j = 0; j < cnt; ++j) {
-                    const uint32_t pos = __builtin_amdgcn_readlane(vpos, j);
-                    const real vr = bcast(vre, j);
-                    const real vi = bcast(vim, j);
-                    const int ox = (int)(pos & 0xffu) - 2 * H;
-                    const int oy = (int)((pos >> 8) & 0xffu) - 2 * H;
-                    const int lx = (int)((pos >> 16) & 0xffu) * W;
-                    const int ly = (int)(pos >> 24) * W;
-                    const int base = oy * P + ox;
-                    const bool inside = ox >= 0 && oy >= 0 && ox + W <= T && oy + W <= T;
-#pragma unroll
-                    for (int gi = 0; gi < NG; ++gi) {
-                        bool on = tap_on[gi];
-                        if (!inside) {
-                            const int x = ox + tap_tx[gi], y = oy + tap_ty[gi];
-                            on = on && x >= 0 && x < T && y >= 0 && y < T;
-                        }
-                        if (on) {
-                            const real wgt = s_lut[ly + tap_ty[gi]] * s_lut[lx + tap_tx[gi]];
-                            atomicAdd(&acc_re[base + tap_off[gi]], (acc_t)(wgt * vr));
-                            atomicAdd(&acc_im[base + tap_off[gi]], (acc_t)(wgt * vi));
-                        }
-                    }
-                }
+        for (int32_t bt = wave; bt < nbatch; bt += nwave) {
+            const int32_t r0 = r_begin + (bt << 6);
+            const int32_t cnt = min(64, r_end - r0);
+            // lane j loads and decodes record r0 + j
+            Rec<real> mine{0, 0, 0, 0, 0};
+            if (lane < cnt) {
+                const uint32_t pos = rec_pos[r0 + lane];
+                mine.vr = rec_vis[2 * (int64_t)(r0 + lane)];
+                mine.vi = rec_vis[2 * (int64_t)(r0 + lane) + 1];
+                const int ox = (int)(pos & 0xffu) - 2 * H;
+                const int oy = (int)((pos >> 8) & 0xffu) - 2 * H;
+                mine.base = oy * P + ox;
+                mine.lxy = (int)((pos >> 16) & 0xffu) * W | ((int)(pos >> 24) * W) << 16;
+                const bool inside = ox >= 0 && oy >= 0 && ox + W <= T && oy + W <= T;
+                mine.oxy = (ox + 64) | (oy + 64) << 8 | (inside ? (int)0x80000000 : 0);
             }
-            __syncthreads();
-            // fold the LDS tile into float64 registers and clear it
-#pragma unroll
-            for (int i = 0; i < kMaxCellsPerThread; ++i) {
-                if (i < cpt) {
-                    const int c = threadIdx.x + i * kGridBlock;
-                    const int idx = (c >> g.log2T) * P + (c & (T - 1));
-                    fre[i] += (double)acc_re[idx];
-                    fim[i] += (double)acc_im[idx];
-                    acc_re[idx] = 0;
-                    acc_im[idx] = 0;
-                }
+            int j = 0;
+            for (; j + 1 < cnt; j += 2) {
+                const Rec<real> a{bcast(mine.base, j), bcast(mine.lxy, j), bcast(mine.oxy, j), bcast(mine.vr, j),
+                                  bcast(mine.vi, j)};
+                const Rec<real> c{bcast(mine.base, j + 1), bcast(mine.lxy, j + 1), bcast(mine.oxy, j + 1),
+                                  bcast(mine.vr, j + 1), bcast(mine.vi, j + 1)};
+                add_record<real, W, NG>(a, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re, acc_im);
+                add_record<real, W, NG>(c, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re, acc_im);
             }
-            __syncthreads();
+            if (j < cnt) {
+                const Rec<real> a{bcast(mine.base, j), bcast(mine.lxy, j), bcast(mine.oxy, j), bcast(mine.vr, j),
+                                  bcast(mine.vi, j)};
+                add_record<real, W, NG>(a, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re, acc_im);
+            }
         }
     }
+    __syncthreads();
 
-    const int32_t k = b / (g.nt * g.nt);
-    const int32_t rem = b - k * g.nt * g.nt;
-    const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
-    using r2 = typename real2_t<real>::type;
-    r2 *m = reinterpret_cast<r2 *>(mesh);
     const bool shared_tile = nchunk > 1;
-#pragma unroll
-    for (int i = 0; i < kMaxCellsPerThread; ++i) {
-        if (i < cpt) {
-            const int32_t c = threadIdx.x + i * kGridBlock;
-            const int32_t y = c >> g.log2T, x = c & (T - 1);
-            const real re = (real)fre[i], im = (real)fim[i];
-            r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
-            if (shared_tile) {
-                if (re != 0) atomic_add_real(&dst->x, re);
-                if (im != 0) atomic_add_real(&dst->y, im);
-            } else if (accumulate) {
-                const r2 old = *dst;
-                *dst = r2{old.x + re, old.y + im};
-            } else {
-                *dst = r2{re, im};
-            }
+    for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
+        const int32_t y = c >> g.log2T, x = c & (T - 1);
+        const real re = (real)acc_re[y * P + x], im = (real)acc_im[y * P + x];
+        r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
+        if (shared_tile) {
+            if (re != 0) atomic_add_real(&dst->x, re);
+            if (im != 0) atomic_add_real(&dst->y, im);
+        } else if (accumulate) {
+            const r2 old = *dst;
+            *dst = r2{old.x + re, old.y + im};
+        } else {
+            *dst = r2{re, im};
         }
     }
 }
@@ -224,7 +231,27 @@ __global__ void k_zero_mesh(real *__restrict__ a, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0;
 }
 
+template <typename real, int W>
+hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
+                  const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
+                  hipStream_t s) {
+    const size_t lds = size_t(2) * g.T * g.pitch * sizeof(double) + size_t(g.OS) * g.W * sizeof(real);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_grid<real, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(160 * 1024));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_grid<real, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin, rec_pos,
+                       rec_vis, lut, mesh, accumulate);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
+    return size_t(2) * g.T * g.pitch * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
+}
 
 template <typename real>
 hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
@@ -234,23 +261,7 @@ hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
 
 template <typename real>
 hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, real *mesh, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kGridBlock), 0, s, g, heavy_bins, st, mesh);
-    return hipGetLastError();
-}
-
-template <typename real, typename acc_t, int W>
-hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                  const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
-                  hipStream_t s) {
-    const size_t lds = size_t(2) * g.T * g.pitch * sizeof(acc_t) + size_t(g.OS) * g.W * sizeof(real);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_grid<real, acc_t, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(160 * 1024));
-        attr = true;
-    }
-    hipLaunchKernelGGL((k_grid<real, acc_t, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin,
-                       rec_pos, rec_vis, lut, mesh, accumulate);
+    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, mesh);
     return hipGetLastError();
 }
 
@@ -258,10 +269,9 @@ template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
                        hipStream_t s) {
-    using acc_t = real;   // float LDS atomics for float32, double for float64 (both folded into float64)
     switch (g.W) {
 #define CASE(w) \
-    case w: return grid_w<real, acc_t, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, accumulate, max_items, s);
+    case w: return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, accumulate, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;

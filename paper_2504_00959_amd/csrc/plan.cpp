@@ -114,6 +114,7 @@ struct rick_plan_s {
     const char *ev_name[kMaxTimers] = {};
     int64_t ev_calls[kMaxTimers] = {};
     bool timing = false;
+    bool fused = false;      // column transform fused into rick_wstack_image
 };
 
 namespace {
@@ -165,7 +166,8 @@ rick_status validate(const rick_plan_desc *d) {
     if (d->max_vis < 1 || d->max_vis >= (int64_t(1) << 29))
         return fail(RICK_E_INVALID_ARG, "max_vis=%lld: must be in [1, 2^29)", (long long)d->max_vis);
     if (d->device < 0) return fail(RICK_E_INVALID_ARG, "device=%d", d->device);
-    if (d->flags & ~int32_t(RICK_FLAG_TIMING)) return fail(RICK_E_INVALID_ARG, "flags=%d: unknown bits", d->flags);
+    if (d->flags & ~int32_t(RICK_FLAG_TIMING | RICK_FLAG_FUSED_SCREEN))
+        return fail(RICK_E_INVALID_ARG, "flags=%d: unknown bits", d->flags);
     if (d->tile != 0) {
         if (!is_pow2(d->tile) || d->tile < 16 || d->tile > 64 || d->tile < d->support || d->tile > d->grid_n)
             return fail(RICK_E_INVALID_ARG, "tile=%d: power of two in [16, 64], >= support, <= grid_n", d->tile);
@@ -218,6 +220,9 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     rick_status st = validate(d);
     if (st != RICK_OK) return st;
     if (!fft_supported(d->grid_n)) return fail(RICK_E_UNSUPPORTED, "no FFT kernel for N=%d", d->grid_n);
+    if ((d->flags & RICK_FLAG_FUSED_SCREEN) &&
+        fused_screen_lds_bytes(d->grid_n, d->precision == RICK_PREC_FP64 ? 8 : 4) > size_t(160) * 1024)
+        return fail(RICK_E_UNSUPPORTED, "fused screen: a column strip of N=%d does not fit in LDS", d->grid_n);
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -231,6 +236,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     p->fp64 = d->precision == RICK_PREC_FP64;
     p->real_bytes = p->fp64 ? 8 : 4;
     p->timing = (d->flags & RICK_FLAG_TIMING) != 0;
+    p->fused = (d->flags & RICK_FLAG_FUSED_SCREEN) != 0;
 
     Geom &g = p->g;
     g.N = d->grid_n;
@@ -258,9 +264,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         g.pitch = pitch;
     }
     {
-        // the gridding block keeps two T x pitch accumulators and the tap table in LDS
-        const size_t rb = p->fp64 ? 8 : 4;
-        const size_t lds = size_t(2) * g.T * g.pitch * rb + size_t(g.OS) * g.W * rb;
+        // the gridding block keeps two T x pitch float64 accumulators and the tap table in LDS
+        const size_t lds = grid_lds_bytes(g, p->fp64 ? 8 : 4);
         if (lds > size_t(160) * 1024) {
             delete p;
             return fail(RICK_E_INVALID_ARG, "tile=%d with support %d, oversample %d needs %zu B of LDS (> 160 KB)",
@@ -540,11 +545,13 @@ rick_status rick_fft_planes(rick_plan_t *p, void *stream) {
     else e = launch_fft_rows<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
     timer_end(p, T_FFT_ROWS, s);
     if (e != hipSuccess) return hip_fail(e, "fft_rows");
-    timer_begin(p, T_FFT_COLS, "fft_cols", s);
-    if (p->fp64) e = launch_fft_cols<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
-    else e = launch_fft_cols<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
-    timer_end(p, T_FFT_COLS, s);
-    if (e != hipSuccess) return hip_fail(e, "fft_cols");
+    if (!p->fused) {
+        timer_begin(p, T_FFT_COLS, "fft_cols", s);
+        if (p->fp64) e = launch_fft_cols<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
+        else e = launch_fft_cols<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
+        timer_end(p, T_FFT_COLS, s);
+        if (e != hipSuccess) return hip_fail(e, "fft_cols");
+    }
     p->state = 2;
     return RICK_OK;
 }
@@ -558,6 +565,18 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     const int kahan = p->d.precision == RICK_PREC_FP32_KAHAN;
+    if (p->fused) {
+        timer_begin(p, T_SCREEN, "fft_cols_screen", s);
+        if (p->fp64)
+            e = launch_fft_cols_screen<double>(p->g, (const double *)p->mesh, (const double *)p->twiddle, p->wk,
+                                               p->corr, p->stats, (double *)image, 0, s);
+        else
+            e = launch_fft_cols_screen<float>(p->g, (const float *)p->mesh, (const float *)p->twiddle, p->wk,
+                                              p->corr, p->stats, (float *)image, kahan, s);
+        timer_end(p, T_SCREEN, s);
+        if (e != hipSuccess) return hip_fail(e, "fft_cols_screen");
+        return RICK_OK;
+    }
     timer_begin(p, T_SCREEN, "wscreen", s);
     if (p->fp64)
         e = launch_wscreen<double>(p->g, (const double *)p->mesh, p->wk, p->corr, p->stats, (double *)image, 0, s);

@@ -84,6 +84,8 @@ template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
                        hipStream_t s);
+// LDS bytes of one gridding block (float64 accumulators + tap table)
+size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 template <typename real>
 hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, real *mesh, hipStream_t s);
 // Batched centred 2-D inverse FFT, in place, all planes.
@@ -92,6 +94,11 @@ hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, hipSt
 template <typename real>
 hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
 bool fft_supported(int N);
+// Column transform fused with the w-correction, plane sum and normalisation.
+size_t fused_screen_lds_bytes(int N, size_t real_bytes);
+template <typename real>
+hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *wk,
+                                  const double *corr, const Stats *st, real *image, int kahan, hipStream_t s);
 // Phase screen + plane sum + normalisation.
 template <typename real>
 hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *wk, const double *corr,

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "RICK_OK", 1: "RICK_E_INVALID_ARG", 2: "RICK_E_NO_DEVICE", 3:
 KERNELS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1}
 PRECISIONS = {"fp32": 0, "fp32_kahan": 1, "fp64": 2}
 FLAG_TIMING = 1
+FLAG_FUSED_SCREEN = 2
 
 
 class RickError(RuntimeError):
@@ -101,11 +102,13 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 def make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel="gaussian", kernel_param=0.0,
-              precision="fp32", max_vis=1 << 20, device=0, timing=False, tile=0, chunk=0) -> PlanDesc:
+              precision="fp32", max_vis=1 << 20, device=0, timing=False, tile=0, chunk=0,
+              fused=False) -> PlanDesc:
+    flags = (FLAG_TIMING if timing else 0) | (FLAG_FUSED_SCREEN if fused else 0)
     return PlanDesc(grid_n=grid_n, n_wplanes=n_wplanes, support=support, oversample=oversample,
                     kernel=KERNELS[kernel], precision=PRECISIONS[precision], kernel_param=kernel_param,
                     fov_rad=fov, w_min=w_min, w_max=w_max, max_vis=max_vis, device=device,
-                    flags=FLAG_TIMING if timing else 0, tile=tile, chunk=chunk)
+                    flags=flags, tile=tile, chunk=chunk)
 
 
 class Plan:
@@ -113,9 +116,11 @@ class Plan:
 
     def __init__(self, grid_n: int, n_wplanes: int, support: int, oversample: int, fov: float, w_min: float,
                  w_max: float, kernel: str = "gaussian", kernel_param: float = 0.0, precision: str = "fp32",
-                 max_vis: int = 1 << 20, device: int = 0, timing: bool = False, tile: int = 0, chunk: int = 0):
+                 max_vis: int = 1 << 20, device: int = 0, timing: bool = False, tile: int = 0, chunk: int = 0,
+                 fused: bool = False):
         self.desc = make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel, kernel_param,
-                              precision, max_vis, device, timing, tile, chunk)
+                              precision, max_vis, device, timing, tile, chunk, fused)
+        self.fused = fused
         self.precision = precision
         self.grid_n = grid_n
         self.n_wplanes = n_wplanes

@@ -1,6 +1,7 @@
 """Full-size parity: the SKA-LOW-like one-GPU share (209,305,600 visibilities,
-4096^2 x 64 planes, W = 7, OS = 64) in the launch configuration the benchmark
-times, checked where the float64 oracle can follow at this size:
+4096^2 x 64 planes, W = 7, OS = 64), in the launch configuration the benchmark
+times (fused column transform + screen) and in the unfused one, checked where
+the float64 oracle can follow at this size:
   - binning: kept count, per-(plane, tile) record counts (bit-exact), sum W;
   - gridding: every plane's cell sum equals its sum of W V (rows of taps sum to 1);
   - F_k and the image at sampled pixels (bright sources, centre, random) against
@@ -38,6 +39,15 @@ def share():
     F = p.mesh()
     img = p.image()
     torch.cuda.synchronize()
+    p.close()
+    # the benchmark's configuration: column transform fused with the screen
+    pf = rick.Plan.for_dataset(ds, fused=True)
+    pf.reset()
+    pf.grid(uvw, vis, None, ds.freq)
+    pf.fft()
+    img_fused = pf.image()
+    torch.cuda.synchronize()
+    pf.close()
     vis_host = vis.cpu().numpy()
     # sampled pixels: source positions (bright), the centre, random
     lm = ds.fov / ds.grid_n
@@ -49,12 +59,12 @@ def share():
     qq = np.r_[qs, ds.grid_n // 2, rng.integers(0, ds.grid_n, 5)]
     Fs = F[:, qq, pp].cpu().numpy().T.astype(np.complex128)       # [npix][N_w]
     img_s = img.double().cpu().numpy()[qq, pp]
+    img_fused_s = img_fused.double().cpu().numpy()[qq, pp]
     img_rms = float(img.double().pow(2).mean().sqrt())
     del F
-    p.close()
     print("[fullsize] GPU path done; running oracle passes", flush=True)
     return dict(ds=ds, vis_host=vis_host, info=info, counts=counts, plane_sums=plane_sums, pp=pp, qq=qq, Fs=Fs,
-                img_s=img_s, img_rms=img_rms)
+                img_s=img_s, img_fused_s=img_fused_s, img_rms=img_rms)
 
 
 def test_fullsize_binning_and_plane_sums(share):
@@ -78,8 +88,10 @@ def test_fullsize_sampled_pixels(share):
     c2 = corr[share["pp"]] * corr[share["qq"]]
     e_f = rel_rms(share["Fs"], Fref)
     e_img = rel_rms(share["img_s"] * c2, ref * c2)
-    print(f"[fullsize] F rel-RMS {e_f:.2e}, apparent image rel-RMS {e_img:.2e}", flush=True)
+    e_fused = rel_rms(share["img_fused_s"] * c2, ref * c2)
+    print(f"[fullsize] F rel-RMS {e_f:.2e}, apparent image rel-RMS {e_img:.2e} (fused {e_fused:.2e})", flush=True)
     assert e_f <= 1e-5
     assert e_img <= 1e-5
+    assert e_fused <= 1e-5
     # every sampled pixel within 1e-5 of the image RMS
     assert np.max(np.abs(share["img_s"] - ref) * c2) <= 1e-5 * max(share["img_rms"], np.max(np.abs(ref)))

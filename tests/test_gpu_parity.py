@@ -30,6 +30,8 @@ FP64_IMG = 1e-10
 
 
 def run_gpu(ds, precision="fp32", **kw):
+    """Grid, transform and image through the C ABI; with fused=True the mesh
+    after rick_fft_planes holds the row transforms only (returned as F)."""
     import torch
     uvw, vis, wt = to_device(ds, precision)
     p = rick.Plan.for_dataset(ds, precision=precision, **kw)
@@ -53,7 +55,7 @@ def oracle_of(ds, **over):
     return oracle.wstack.wstack_dataset(ds, **over)
 
 
-def check_stages(ds, gpu, ref, stage_tol=FP32_STAGE, img_tol=FP32_IMG):
+def check_stages(ds, gpu, ref, stage_tol=FP32_STAGE, img_tol=FP32_IMG, fused=False):
     info = gpu["info"]
     b = ref.binned
     # integer decisions: exact
@@ -65,10 +67,19 @@ def check_stages(ds, gpu, ref, stage_tol=FP32_STAGE, img_tol=FP32_IMG):
     assert abs(info["sum_weights"] - ref.sum_w) <= 1e-12 * max(1.0, ref.sum_w)
     # gridded planes
     assert rel_rms(gpu["G"], ref.planes) <= stage_tol
-    # FFT of the GPU's own planes
-    assert rel_rms(gpu["F"], ow.ifft_planes(gpu["G"].astype(np.complex128))) <= stage_tol
-    # screen + normalisation of the GPU's own F_k
-    S = ow.screen_sum(gpu["F"].astype(np.complex128), ref.w_k, ds.fov)
+    G = gpu["G"].astype(np.complex128)
+    if fused:
+        # rows transformed only: H_k[j][p] = sum_i G_k[j][i] exp(+2 pi i (i - N/2)(p - N/2) / N)
+        N = ds.grid_n
+        H = np.fft.fftshift(np.fft.ifft(np.fft.ifftshift(G, axes=-1), axis=-1), axes=-1) * N
+        assert rel_rms(gpu["F"], H) <= stage_tol
+        F_own = ow.ifft_planes(G)
+    else:
+        # FFT of the GPU's own planes
+        assert rel_rms(gpu["F"], ow.ifft_planes(G)) <= stage_tol
+        F_own = gpu["F"].astype(np.complex128)
+    # screen + normalisation of the GPU's own transformed planes
+    S = ow.screen_sum(F_own, ref.w_k, ds.fov)
     mine = ow.normalise(S, ref.corr, ref.sum_w, ds.fov)
     assert rel_rms(gpu["img"] * np.outer(ref.corr, ref.corr), mine * np.outer(ref.corr, ref.corr)) <= stage_tol
     # end to end
@@ -81,6 +92,25 @@ def check_stages(ds, gpu, ref, stage_tol=FP32_STAGE, img_tol=FP32_IMG):
 def test_tiny_stagewise_fp32():
     ds = synth.tiny()
     check_stages(ds, run_gpu(ds), oracle_of(ds))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan"])
+def test_tiny_fused_screen(precision):
+    """Column transform fused with the screen: same image, F_k never written."""
+    ds = synth.tiny()
+    check_stages(ds, run_gpu(ds, precision=precision, fused=True), oracle_of(ds), fused=True)
+
+
+@pytest.mark.parametrize("N", [64, 256, 1024, 4096, 8192])
+def test_fused_screen_grid_sizes(N):
+    ds = synth.tiny(nrow=5000, seed=16, grid_n=N, n_wplanes=3, uv_radius=120.0 * N / 256)
+    check_stages(ds, run_gpu(ds, fused=True), oracle_of(ds), fused=True)
+
+
+def test_fused_screen_fp64():
+    ds = synth.tiny()
+    gpu = run_gpu(ds, precision="fp64", fused=True)
+    assert rel_rms(gpu["img"], oracle_of(ds).image) <= FP64_IMG
 
 
 def test_tiny_fp64_mode():
