@@ -157,14 +157,36 @@ __device__ __forceinline__ SlotReq aggregated_slot_issue(int32_t *arr, int32_t k
 }
 __device__ __forceinline__ int32_t slot_of(const SlotReq &r) { return __shfl(r.base, r.leader) + r.rank; }
 
+// Grid-stride walk over visibility index i = r * nchan + c with the row r and
+// channel c updated incrementally (no division per step; indices fit 32 bits
+// because a plan takes fewer than 2^29 visibilities).
+struct VisWalk {
+    uint32_t i, r, c, di, dr, dc;
+    __device__ __forceinline__ VisWalk(uint32_t start, uint32_t stride, uint32_t nchan) {
+        i = start;
+        r = start / nchan;
+        c = start - r * nchan;
+        di = stride;
+        dr = stride / nchan;
+        dc = stride - dr * nchan;
+    }
+    __device__ __forceinline__ void next(uint32_t nchan) {
+        i += di;
+        r += dr;
+        c += dc;
+        if (c >= nchan) {
+            c -= nchan;
+            ++r;
+        }
+    }
+};
+
 template <typename real>
 __device__ __forceinline__ void load_vis(const Geom &g, const double *__restrict__ uvw,
                                          const double *__restrict__ scales, const real *__restrict__ vis,
-                                         const float *__restrict__ weight, int64_t i, int32_t nchan, double &u,
-                                         double &v, double &w, real &vr, real &vi, float &wt) {
+                                         const float *__restrict__ weight, uint32_t i, uint32_t r, uint32_t c,
+                                         double &u, double &v, double &w, real &vr, real &vi, float &wt) {
 #pragma clang fp contract(off)
-    const int64_t r = i / nchan;
-    const int32_t c = (int32_t)(i - r * nchan);
     const double sc = scales[c];
     u = uvw[3 * r] * sc;
     v = uvw[3 * r + 1] * sc;
@@ -186,20 +208,19 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__re
     unsigned long long kept = 0, dropped = 0;
     // counters are privatised over kCopies copies (by block), which spreads
     // the atomics on the dense central bins over several cache lines
-    int32_t *my_counts = counts + (int64_t)(blockIdx.x % kCopies) * (g.nbins + 1);
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t start = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t *my_counts = counts + (blockIdx.x % kCopies) * (g.nbins + 1);
+    const uint32_t stride = gridDim.x * kBlock;
     // loop bound uniform across the block so that every lane joins the ballots
-    const int64_t iters = (nvis + stride - 1) / stride;
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t i = start + it * stride;
+    const uint32_t iters = (uint32_t)((nvis + stride - 1) / stride);
+    VisWalk vw(blockIdx.x * kBlock + threadIdx.x, stride, (uint32_t)nchan);
+    for (uint32_t it = 0; it < iters; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
-        if (i < nvis) {
+        if (vw.i < (uint32_t)nvis) {
             double u, v, w;
             real vr, vi;
             float wt;
-            load_vis<real>(g, uvw, scales, vis, weight, i, nchan, u, v, w, vr, vi, wt);
+            load_vis<real>(g, uvw, scales, vis, weight, vw.i, vw.r, vw.c, u, v, w, vr, vi, wt);
             keep = quantise<real>(g, u, v, w, vr, vi, wt, q);
             if (keep) {
                 ++kept;
@@ -249,20 +270,19 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__
                                                         const float *__restrict__ weight, int64_t nvis,
                                                         int32_t nchan, int32_t *__restrict__ cursor,
                                                         uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
-    int32_t *my_cursor = cursor + (int64_t)(blockIdx.x % kCopies) * g.nbins;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t start = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t iters = (nvis + stride - 1) / stride;
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t i = start + it * stride;
+    int32_t *my_cursor = cursor + (blockIdx.x % kCopies) * g.nbins;
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t iters = (uint32_t)((nvis + stride - 1) / stride);
+    VisWalk vw(blockIdx.x * kBlock + threadIdx.x, stride, (uint32_t)nchan);
+    for (uint32_t it = 0; it < iters; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
         real ar = 0, ai = 0;
-        if (i < nvis) {
+        if (vw.i < (uint32_t)nvis) {
             double u, v, w;
             real vr, vi;
             float wt;
-            load_vis<real>(g, uvw, scales, vis, weight, i, nchan, u, v, w, vr, vi, wt);
+            load_vis<real>(g, uvw, scales, vis, weight, vw.i, vw.r, vw.c, u, v, w, vr, vi, wt);
             keep = quantise<real>(g, u, v, w, vr, vi, wt, q);
             ar = (real)wt * vr;
             ai = (real)wt * vi;
@@ -278,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__
             const int32_t slot = slot_of(req[j]);
             if (j < nb) {
                 rec_pos[slot] = pos[j];
-                store2(rec_vis + 2 * (int64_t)slot, ar, ai);
+                store2(rec_vis + 2 * (uint32_t)slot, ar, ai);
             }
         }
     }

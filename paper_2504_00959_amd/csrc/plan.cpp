@@ -250,7 +250,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     g.log2T = ilog2(g.T);
     g.nt = g.N / g.T;
     const int64_t nbins64 = int64_t(g.Nw) * g.nt * g.nt;
-    if (nbins64 >= (int64_t(1) << 30)) {
+    if (nbins64 >= (int64_t(1) << 26)) {
         delete p;
         return fail(RICK_E_INVALID_ARG, "too many (plane, tile) bins: %lld", (long long)nbins64);
     }
