@@ -17,7 +17,7 @@
 // Records arrive 64 at a time in one coalesced load; each lane decodes the
 // record it loaded (footprint origin, tap-table rows, whether the footprint
 // lies inside the tile), and the decoded fields are broadcast with readlane,
-// two records per step so that their tap-table reads overlap.  Taps outside
+// four records per step whose tap-table reads are issued together.  Taps outside
 // the tile are skipped: a record whose footprint straddles tile edges was
 // binned into every tile it touches.
 //
@@ -34,6 +34,7 @@ namespace rick {
 namespace {
 
 constexpr int kGridBlock = 512;   // 8 waves share one tile
+constexpr int kGroup = 4;         // records whose tap-table reads are issued together
 constexpr int kZeroBlock = 256;
 
 template <typename real>
@@ -89,24 +90,42 @@ struct Rec {
     real vr, vi;
 };
 
-template <typename real, int W, int NG>
-__device__ __forceinline__ void add_record(const Rec<real> &r, const int (&tap_ty)[NG], const int (&tap_tx)[NG],
-                                           const int (&tap_off)[NG], const bool (&tap_on)[NG], int T,
-                                           const real *__restrict__ s_lut, double *acc_re, double *acc_im) {
-    const bool inside = r.oxy < 0;
-    const int ox = (r.oxy & 0xff) - 64, oy = ((r.oxy >> 8) & 0xff) - 64;
-    const int lx = r.lxy & 0xffff, ly = r.lxy >> 16;
+// Adds G records: all tap-table reads first, then all atomics, so the wave
+// waits for LDS once per group (LDS operations retire in order, and a wait
+// for a table read also waits for every earlier atomic).
+template <typename real, int W, int NG, int G>
+__device__ __forceinline__ void add_records(const Rec<real> (&r)[G], int valid, const int (&tap_ty)[NG],
+                                            const int (&tap_tx)[NG], const int (&tap_off)[NG],
+                                            const bool (&tap_on)[NG], int T, const real *__restrict__ s_lut,
+                                            double *acc_re, double *acc_im) {
+    real gy[G][NG], gx[G][NG];
+    bool on[G][NG];
 #pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-        bool on = tap_on[gi];
-        if (!inside) {
-            const int x = ox + tap_tx[gi], y = oy + tap_ty[gi];
-            on = on && x >= 0 && x < T && y >= 0 && y < T;
+    for (int q = 0; q < G; ++q) {
+        const bool inside = r[q].oxy < 0;
+        const int ox = (r[q].oxy & 0xff) - 64, oy = ((r[q].oxy >> 8) & 0xff) - 64;
+        const int lx = r[q].lxy & 0xffff, ly = r[q].lxy >> 16;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            bool o = tap_on[gi] && q < valid;
+            if (!inside) {
+                const int x = ox + tap_tx[gi], y = oy + tap_ty[gi];
+                o = o && x >= 0 && x < T && y >= 0 && y < T;
+            }
+            on[q][gi] = o;
+            gy[q][gi] = s_lut[ly + tap_ty[gi]];
+            gx[q][gi] = s_lut[lx + tap_tx[gi]];
         }
-        if (on) {
-            const real wgt = s_lut[ly + tap_ty[gi]] * s_lut[lx + tap_tx[gi]];
-            atomicAdd(&acc_re[r.base + tap_off[gi]], (double)(wgt * r.vr));
-            atomicAdd(&acc_im[r.base + tap_off[gi]], (double)(wgt * r.vi));
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            if (on[q][gi]) {
+                const real wgt = gy[q][gi] * gx[q][gi];
+                atomicAdd(&acc_re[r[q].base + tap_off[gi]], (double)(wgt * r[q].vr));
+                atomicAdd(&acc_im[r[q].base + tap_off[gi]], (double)(wgt * r[q].vi));
+            }
         }
     }
 }
@@ -190,19 +209,18 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                 const bool inside = ox >= 0 && oy >= 0 && ox + W <= T && oy + W <= T;
                 mine.oxy = (ox + 64) | (oy + 64) << 8 | (inside ? (int)0x80000000 : 0);
             }
-            int j = 0;
-            for (; j + 1 < cnt; j += 2) {
-                const Rec<real> a{bcast(mine.base, j), bcast(mine.lxy, j), bcast(mine.oxy, j), bcast(mine.vr, j),
-                                  bcast(mine.vi, j)};
-                const Rec<real> c{bcast(mine.base, j + 1), bcast(mine.lxy, j + 1), bcast(mine.oxy, j + 1),
-                                  bcast(mine.vr, j + 1), bcast(mine.vi, j + 1)};
-                add_record<real, W, NG>(a, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re, acc_im);
-                add_record<real, W, NG>(c, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re, acc_im);
-            }
-            if (j < cnt) {
-                const Rec<real> a{bcast(mine.base, j), bcast(mine.lxy, j), bcast(mine.oxy, j), bcast(mine.vr, j),
-                                  bcast(mine.vi, j)};
-                add_record<real, W, NG>(a, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re, acc_im);
+            // groups of kGroup records (the last group is partial); lanes past
+            // cnt decoded a zero record whose taps are all switched off
+            for (int j = 0; j < cnt; j += kGroup) {
+                Rec<real> rg[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    const int jj = (j + q) & 63;
+                    rg[q] = Rec<real>{bcast(mine.base, jj), bcast(mine.lxy, jj), bcast(mine.oxy, jj),
+                                      bcast(mine.vr, jj), bcast(mine.vi, jj)};
+                }
+                add_records<real, W, NG, kGroup>(rg, cnt - j, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re,
+                                                 acc_im);
             }
         }
     }
