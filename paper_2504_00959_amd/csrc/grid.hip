@@ -14,12 +14,14 @@
 // slower, and dense cells collect thousands of terms, which float32
 // accumulation would round to ~1e-5 of image RMS.
 //
-// Records arrive 64 at a time in one coalesced load; each lane decodes the
-// record it loaded (footprint origin, tap-table rows, whether the footprint
-// lies inside the tile), and the decoded fields are broadcast with readlane,
-// four records per step whose tap-table reads are issued together.  Taps outside
-// the tile are skipped: a record whose footprint straddles tile edges was
-// binned into every tile it touches.
+// Records arrive 64 at a time in one coalesced load (the next 64 are loaded
+// while these are gridded); each lane decodes the record it loaded (footprint
+// origin, tap-table rows), and the decoded fields are broadcast with readlane.
+// Per record and lane the work is two table reads, three multiplies, two
+// conversions, a three-instruction in-tile test and two atomics; the table
+// reads of the next four records are issued before the atomics of the current
+// four.  Taps outside the tile are skipped: a record whose footprint straddles
+// tile edges was binned into every tile it touches.
 //
 // After the records the tile is written to HBM once, row-coalesced:
 //   - bins with a single chunk own their tile and store it (empty bins store
@@ -34,7 +36,6 @@ namespace rick {
 namespace {
 
 constexpr int kGridBlock = 512;   // 8 waves share one tile
-constexpr int kGroup = 4;         // records whose tap-table reads are issued together
 constexpr int kZeroBlock = 256;
 
 template <typename real>
@@ -81,54 +82,18 @@ __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t
     }
 }
 
-// One decoded record, as broadcast to the wave.
-template <typename real>
-struct Rec {
-    int32_t base;   // LDS index of the footprint's first tap (may be < 0 for straddling records)
-    int32_t lxy;    // tap-table row offsets: (s_x row * W) | (s_y row * W) << 16
-    int32_t oxy;    // footprint origin in tile cells, (ox + 64) | (oy + 64) << 8, bit 31: fully inside
-    real vr, vi;
-};
+// Offset (in doubles) of the imaginary accumulator plane from the real one:
+// the size of a 64-row plane, a compile-time constant so that the second
+// atomic of a tap reuses the first one's address register with an immediate
+// offset.  It is a multiple of 32 doubles, so both planes map a footprint to
+// the same LDS banks.
+template <int W>
+constexpr int im_plane_offset() { return 64 * (64 + W % 32); }
 
-// Adds G records: all tap-table reads first, then all atomics, so the wave
-// waits for LDS once per group (LDS operations retire in order, and a wait
-// for a table read also waits for every earlier atomic).
-template <typename real, int W, int NG, int G>
-__device__ __forceinline__ void add_records(const Rec<real> (&r)[G], int valid, const int (&tap_ty)[NG],
-                                            const int (&tap_tx)[NG], const int (&tap_off)[NG],
-                                            const bool (&tap_on)[NG], int T, const real *__restrict__ s_lut,
-                                            double *acc_re, double *acc_im) {
-    real gy[G][NG], gx[G][NG];
-    bool on[G][NG];
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-        const bool inside = r[q].oxy < 0;
-        const int ox = (r[q].oxy & 0xff) - 64, oy = ((r[q].oxy >> 8) & 0xff) - 64;
-        const int lx = r[q].lxy & 0xffff, ly = r[q].lxy >> 16;
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-            bool o = tap_on[gi] && q < valid;
-            if (!inside) {
-                const int x = ox + tap_tx[gi], y = oy + tap_ty[gi];
-                o = o && x >= 0 && x < T && y >= 0 && y < T;
-            }
-            on[q][gi] = o;
-            gy[q][gi] = s_lut[ly + tap_ty[gi]];
-            gx[q][gi] = s_lut[lx + tap_tx[gi]];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-            if (on[q][gi]) {
-                const real wgt = gy[q][gi] * gx[q][gi];
-                atomicAdd(&acc_re[r[q].base + tap_off[gi]], (double)(wgt * r[q].vr));
-                atomicAdd(&acc_im[r[q].base + tap_off[gi]], (double)(wgt * r[q].vi));
-            }
-        }
-    }
-}
+// Records per group.  The tap-table reads of the next group are issued before
+// the atomics of this one, so a wait for table values never waits for the
+// atomics just issued (LDS operations complete in order).
+constexpr int kGroup = 4;
 
 template <typename real, int W>
 __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__restrict__ scan,
@@ -140,6 +105,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
     constexpr int nwave = kGridBlock / 64;
+    constexpr int KOFF = im_plane_offset<W>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t total = scan[g.nbins].item;
     const int32_t item = blockIdx.x;
@@ -169,59 +135,123 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
         }
         return;
     }
+    // LDS: real plane at byte 0, imaginary plane KOFF doubles further, then the tap table
     double *acc_re = reinterpret_cast<double *>(smem);
-    double *acc_im = acc_re + T * P;
-    real *s_lut = reinterpret_cast<real *>(acc_im + T * P);
+    double *acc_im = acc_re + KOFF;
+    const int32_t lut_byte = (KOFF + T * P) * (int32_t)sizeof(double);
+    real *s_lut = reinterpret_cast<real *>(smem + lut_byte);
     for (int i = threadIdx.x; i < T * P; i += kGridBlock) {
         acc_re[i] = 0.0;
         acc_im[i] = 0.0;
     }
-    {
-        for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
-        __syncthreads();
+    for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
+    __syncthreads();
 
-        const int lane = __lane_id();
-        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        int tap_ty[NG], tap_tx[NG], tap_off[NG];
-        bool tap_on[NG];
+    const int lane = __lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Per-lane tap constants.  A tap at footprint offset (tx, ty) of a record
+    // with origin (ox, oy) lies in the tile when both ox + tx and oy + ty are
+    // in [0, T).  Origins are biased by 2^14 and packed as two 16-bit halves,
+    // so one add gives both coordinates (no carry crosses the halves), and for
+    // a power-of-two T a coordinate c + 2^14 is in range exactly when its half
+    // masked by ~(T - 1) equals 2^14.  Lanes without a tap carry 2^15 in the
+    // low half, which never passes.
+    int tap_txy[NG], tap_off8[NG], lut_x[NG], lut_y[NG];
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-            const int t = lane + 64 * gi;
-            tap_on[gi] = t < W2;
-            tap_ty[gi] = tap_on[gi] ? t / W : 0;
-            tap_tx[gi] = tap_on[gi] ? t - tap_ty[gi] * W : 0;
-            tap_off[gi] = tap_ty[gi] * P + tap_tx[gi];
+    for (int gi = 0; gi < NG; ++gi) {
+        const int t = lane + 64 * gi;
+        const bool on = t < W2;
+        const int ty = on ? t / W : 0, tx = on ? t - (t / W) * W : 0;
+        tap_txy[gi] = on ? (tx | ty << 16) : 0x8000;
+        tap_off8[gi] = (ty * P + tx) * (int)sizeof(double);
+        lut_x[gi] = lut_byte + tx * (int)sizeof(real);
+        lut_y[gi] = lut_byte + ty * (int)sizeof(real);
+    }
+    const uint32_t inmask = (0xffffu & ~(uint32_t)(T - 1)) * 0x10001u;
+    constexpr uint32_t inval = 0x40004000u;
+
+    // this wave's batches of 64 records, one record per lane; the next
+    // batch's raw fields are loaded while the current one is gridded
+    const int32_t nbatch = (n + 63) >> 6;
+    int32_t bt = wave;
+    uint32_t raw_pos = 0;
+    real raw_vr = 0, raw_vi = 0;
+    auto fetch = [&](int32_t bi) {
+        const int32_t r = r_begin + (bi << 6) + lane;
+        if (r < r_end) {
+            raw_pos = rec_pos[r];
+            raw_vr = rec_vis[2 * (int64_t)r];
+            raw_vi = rec_vis[2 * (int64_t)r + 1];
         }
-        const int32_t nbatch = (n + 63) >> 6;
-        for (int32_t bt = wave; bt < nbatch; bt += nwave) {
-            const int32_t r0 = r_begin + (bt << 6);
-            const int32_t cnt = min(64, r_end - r0);
-            // lane j loads and decodes record r0 + j
-            Rec<real> mine{0, 0, 0, 0, 0};
-            if (lane < cnt) {
-                const uint32_t pos = rec_pos[r0 + lane];
-                mine.vr = rec_vis[2 * (int64_t)(r0 + lane)];
-                mine.vi = rec_vis[2 * (int64_t)(r0 + lane) + 1];
-                const int ox = (int)(pos & 0xffu) - 2 * H;
-                const int oy = (int)((pos >> 8) & 0xffu) - 2 * H;
-                mine.base = oy * P + ox;
-                mine.lxy = (int)((pos >> 16) & 0xffu) * W | ((int)(pos >> 24) * W) << 16;
-                const bool inside = ox >= 0 && oy >= 0 && ox + W <= T && oy + W <= T;
-                mine.oxy = (ox + 64) | (oy + 64) << 8 | (inside ? (int)0x80000000 : 0);
-            }
-            // groups of kGroup records (the last group is partial); lanes past
-            // cnt decoded a zero record whose taps are all switched off
-            for (int j = 0; j < cnt; j += kGroup) {
-                Rec<real> rg[kGroup];
+    };
+    if (bt < nbatch) fetch(bt);
+    for (; bt < nbatch; bt += nwave) {
+        const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
+        // decode this lane's record: byte offset of the footprint origin in
+        // the real plane (negative for origins left of or above the tile),
+        // packed biased origin, tap-table row byte offsets, visibility
+        int32_t d_base8 = 0, d_oxy = 0x8000, d_lxy = 0;
+        real d_vr = 0, d_vi = 0;
+        if (lane < cnt) {
+            const int ox = (int)(raw_pos & 0xffu) - 2 * H;
+            const int oy = (int)((raw_pos >> 8) & 0xffu) - 2 * H;
+            const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
+            d_base8 = (oy * P + ox) * (int)sizeof(double);
+            d_oxy = (ox + 0x4000) | (oy + 0x4000) << 16;
+            d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
+            d_vr = raw_vr;
+            d_vi = raw_vi;
+        }
+        if (bt + nwave < nbatch) fetch(bt + nwave);
+
+        // tap-table values of one group of records (indices past the batch
+        // wrap to lanes holding a switched-off record: the reads stay in the
+        // table and their values go unused)
+        auto lut_reads = [&](int j, real (&gy)[kGroup][NG], real (&gx)[kGroup][NG]) {
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const int jj = (j + q) & 63;
-                    rg[q] = Rec<real>{bcast(mine.base, jj), bcast(mine.lxy, jj), bcast(mine.oxy, jj),
-                                      bcast(mine.vr, jj), bcast(mine.vi, jj)};
+            for (int q = 0; q < kGroup; ++q) {
+                const int32_t lxy = bcast(d_lxy, (j + q) & 63);
+                const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
+                    gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
                 }
-                add_records<real, W, NG, kGroup>(rg, cnt - j, tap_ty, tap_tx, tap_off, tap_on, T, s_lut, acc_re,
-                                                 acc_im);
             }
+        };
+        auto add_group = [&](int j, const real (&gy)[kGroup][NG], const real (&gx)[kGroup][NG]) {
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const int32_t base8 = bcast(d_base8, (j + q) & 63);
+                const uint32_t oxy = (uint32_t)bcast(d_oxy, (j + q) & 63);
+                const real vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    // the products are formed outside the branch, so the wait
+                    // for the table values is the same on every path
+                    const real wgt = gy[q][gi] * gx[q][gi];
+                    double tr = (double)(wgt * vr), ti = (double)(wgt * vi);
+                    __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
+                    if (((oxy + (uint32_t)tap_txy[gi]) & inmask) == inval) {
+                        double *a = reinterpret_cast<double *>(smem + (base8 + tap_off8[gi]));
+                        atomicAdd(a, tr);
+                        atomicAdd(a + KOFF, ti);
+                    }
+                }
+            }
+        };
+        // two table buffers used in turn: the reads for group j + kGroup are
+        // issued before the atomics of group j, and no value is copied
+        real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
+        lut_reads(0, ay, ax);
+#pragma unroll
+        for (int j = 0; j < 64; j += 2 * kGroup) {
+            lut_reads(j + kGroup, by, bx);
+            add_group(j, ay, ax);
+            if (j + kGroup >= cnt) break;
+            lut_reads(j + 2 * kGroup, ay, ax);
+            add_group(j + kGroup, by, bx);
+            if (j + 2 * kGroup >= cnt) break;
         }
     }
     __syncthreads();
@@ -253,7 +283,7 @@ template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
                   hipStream_t s) {
-    const size_t lds = size_t(2) * g.T * g.pitch * sizeof(double) + size_t(g.OS) * g.W * sizeof(real);
+    const size_t lds = grid_lds_bytes(g, sizeof(real));
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)k_grid<real, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -268,7 +298,9 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
 }  // namespace
 
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
-    return size_t(2) * g.T * g.pitch * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
+    // the imaginary plane starts 64 (64 + W % 32) doubles after the real one
+    const size_t koff = size_t(64) * (64 + g.W % 32);
+    return (koff + size_t(g.T) * g.pitch) * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
 }
 
 template <typename real>
