@@ -95,6 +95,225 @@ def cpu_baseline(ds, vis_host, n_rows_sample=262_144, n_planes_sample=2):
             "sample_seconds": round(t_bin + t_grid + t_fft + t_screen, 2)}
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 runs and their text summaries.  `--profile OUT` runs each pass as a
+# child process (in /tmp, TMPDIR=/tmp, the program after `--`), each under its
+# own time limit, stops at the first pass that fails, and writes the summaries
+# into OUT/summary; those are the files kept under profiles/.
+# ---------------------------------------------------------------------------
+PROFILE_BENCH = ["--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--check-pixels", "0"]
+COPY_MIB = 1024
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS",
+               "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"]
+# library kernel -> the plan timer that brackets it
+KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_reset_counts": "bin_count",
+                "k_bin_count": "bin_count", "k_scan_partials": "bin_scan", "k_scan_top": "bin_scan",
+                "k_scan_apply": "bin_scan", "k_bin_scatter": "bin_scatter", "k_zero_heavy": "zero_heavy",
+                "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_cols": "fft_cols",
+                "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen"}
+
+
+def kernel_sources_digest():
+    """sha256 over the library's kernel and plan sources: counters taken on
+    other sources do not describe the kernels that run now."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2504_00959_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "rick.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, timer):
+    """HBM bytes per launch of the kernel behind `timer`, from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the
+    kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    digest, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# source_sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            elif line.startswith("timer "):
+                _, name, val = line.split()
+                rows[name] = float(val)
+    if digest != kernel_sources_digest():
+        return None, "kernel sources changed since the counters were taken"
+    if timer not in rows:
+        return None, f"no counters for {timer}"
+    return int(rows[timer]), f"FETCH_SIZE + WRITE_SIZE, copy-calibrated ({os.path.basename(path)})"
+
+
+def short_kernel(name):
+    import re
+    m = re.search(r"::(k_[a-z0-9_]+)(<[^()]*>)?\(", name)
+    return (m.group(1), m.group(1) + (m.group(2) or "")) if m else (None, name[:60])
+
+
+def read_counters(path):
+    """{kernel (short name with template args): [values per dispatch]} for one counter run."""
+    import csv
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            base, full = short_kernel(r["Kernel_Name"])
+            key = full if base else r["Kernel_Name"]
+            out.setdefault((key, r["Counter_Name"]), {}).setdefault(r["Dispatch_Id"], 0.0)
+            out[(key, r["Counter_Name"])][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    return out
+
+
+def profile_commands(out, workload):
+    py, me = sys.executable, os.path.abspath(__file__)
+    bench = [py, me, "--workload", workload] + PROFILE_BENCH
+    copy = [py, me, "--copy-calibration", str(COPY_MIB)]
+
+    def pmc(name, regex, counters, prog, limit):
+        return (name, ["rocprofv3", "--kernel-include-regex", regex, "--pmc"] + counters +
+                ["-f", "csv", "-d", os.path.join(out, name), "-o", "run", "--"] + prog, limit)
+    return [
+        ("trace", ["rocprofv3", "--kernel-trace", "--stats", "-f", "csv", "-d", os.path.join(out, "trace"), "-o",
+                   "run", "--"] + bench, 600),
+        pmc("fetch", "rick", ["FETCH_SIZE"], bench, 300),
+        pmc("write", "rick", ["WRITE_SIZE"], bench, 300),
+        pmc("copy_fetch", "copyBuffer", ["FETCH_SIZE"], copy, 120),
+        pmc("copy_write", "copyBuffer", ["WRITE_SIZE"], copy, 120),
+        pmc("sq", "rick", SQ_COUNTERS, bench, 300),
+    ]
+
+
+def run_profiles(out, workload):
+    import signal
+    import subprocess
+    os.makedirs(out, exist_ok=True)
+    env = dict(os.environ, TMPDIR="/tmp")
+    for name, cmd, limit in profile_commands(out, workload):
+        print(f"[profile] {name}: {' '.join(cmd)}", file=sys.stderr, flush=True)
+        with open(os.path.join(out, f"{name}.log"), "w") as log:
+            p = subprocess.Popen(cmd, cwd="/tmp", env=env, stdout=log, stderr=subprocess.STDOUT,
+                                 start_new_session=True)
+            try:
+                rc = p.wait(timeout=limit)
+            except subprocess.TimeoutExpired:
+                os.killpg(p.pid, signal.SIGKILL)
+                p.wait()
+                raise SystemExit(f"[profile] {name} exceeded {limit} s; later passes not started")
+        results = [f for f in os.listdir(os.path.join(out, name))] if os.path.isdir(os.path.join(out, name)) else []
+        print(f"[profile] {name}: rc={rc}, files {sorted(results)}", file=sys.stderr, flush=True)
+        if rc != 0:
+            # the profiler can end with a fault of its own after a complete run;
+            # accept only when the program printed its last line and results exist
+            with open(os.path.join(out, f"{name}.log")) as fh:
+                done = any(l.startswith('{"') for l in fh)
+            if not (done and results):
+                raise SystemExit(f"[profile] {name} failed (rc={rc}); later passes not started")
+    summarize_profiles(out, workload)
+
+
+def summarize_profiles(out, workload):
+    import csv
+    summ = os.path.join(out, "summary")
+    os.makedirs(summ, exist_ok=True)
+    cmds = {name: " ".join(cmd).replace(sys.executable, "python").replace(ROOT, "<repo>")
+            for name, cmd, _ in profile_commands(out, workload)}
+    prelude = "cd /tmp && export TMPDIR=/tmp   # <repo> = the repository root (absolute path)\n"
+    bench_json = None
+    with open(os.path.join(out, "trace.log")) as fh:
+        for line in fh:
+            if line.startswith('{"'):
+                bench_json = json.loads(line)
+    # 1. kernel trace
+    rows = []
+    with open(os.path.join(out, "trace", "run_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            base, full = short_kernel(r["Name"])
+            if base is None or "rick" not in r["Name"]:
+                continue
+            rows.append((full, KERNEL_TIMER.get(base, "?"), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6))
+    rows.sort(key=lambda t: -t[6])
+    steps = int(PROFILE_BENCH[1]) + int(PROFILE_BENCH[3])
+    lines = [f"# rocprofv3 kernel trace, {workload}: {bench_json['config']['workload'] if bench_json else ''}",
+             "# command:", "#   " + prelude.strip(), "#   " + cmds["trace"],
+             f"# {steps} steps traced (warmup included); library kernels only (the workload generator's "
+             "torch kernels are left out)",
+             f"# bench line of the same run: {bench_json['value']} Mvis/s, {bench_json['ms_per_step']} ms/step"
+             if bench_json else "#",
+             f"{'kernel':48s} {'plan timer':16s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+             f"{'total_ms':>10s}"]
+    for full, timer, calls, avg, mn, mx, tot in rows:
+        lines.append(f"{full:48s} {timer:16s} {calls:6d} {avg:10.1f} {mn:10.1f} {mx:10.1f} {tot:10.2f}")
+    if bench_json:
+        lines.append("# plan timers (HIP events in the bench's timed region), ms per call:")
+        for k, v in bench_json["kernels"].items():
+            lines.append(f"#   {k:16s} {v['ms']:.4f}")
+    with open(os.path.join(summ, f"kernel_trace_{workload}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    # 2. HBM traffic, copy-calibrated
+    def mean_per_dispatch(path, counter):
+        res = {}
+        for (k, c), per in read_counters(path).items():
+            if c == counter:
+                res[k] = sum(per.values()) / len(per)
+        return res
+    cf = mean_per_dispatch(os.path.join(out, "copy_fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    cw = mean_per_dispatch(os.path.join(out, "copy_write", "run_counter_collection.csv"), "WRITE_SIZE")
+    copy_bytes = COPY_MIB << 20
+    f_fetch = copy_bytes / (1024.0 * max(cf.values()))
+    f_write = copy_bytes / (1024.0 * max(cw.values()))
+    fetch = mean_per_dispatch(os.path.join(out, "fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    write = mean_per_dispatch(os.path.join(out, "write", "run_counter_collection.csv"), "WRITE_SIZE")
+    by_timer = {}
+    lines = [f"# HBM traffic per dispatch, {workload}", "# commands:", "#   " + prelude.strip()]
+    lines += ["#   " + cmds[n] for n in ("fetch", "write", "copy_fetch", "copy_write")]
+    lines += [f"# calibration: a plain {COPY_MIB} MiB device copy reads FETCH_SIZE {max(cf.values()):.0f} KiB and "
+              f"WRITE_SIZE {max(cw.values()):.0f} KiB per launch; scale factors {f_fetch:.4f} (fetch) and "
+              f"{f_write:.4f} (write)",
+              f"# source_sha256: {kernel_sources_digest()}",
+              f"{'kernel':48s} {'fetch_KiB':>14s} {'write_KiB':>14s} {'traffic_bytes':>16s} {'algorithmic':>16s} "
+              f"{'ratio':>7s}"]
+    for k in sorted(set(fetch) | set(write), key=lambda k: -(fetch.get(k, 0) + write.get(k, 0))):
+        base = k.split("<")[0]
+        t = fetch.get(k, 0.0) * 1024 * f_fetch + write.get(k, 0.0) * 1024 * f_write
+        timer = KERNEL_TIMER.get(base)
+        alg = bench_json["kernels"].get(timer, {}).get("bytes") if bench_json and timer else None
+        ratio = f"{t / alg:7.3f}" if alg else "      -"
+        lines.append(f"{k:48s} {fetch.get(k, 0):14.0f} {write.get(k, 0):14.0f} {t:16.0f} "
+                     f"{alg if alg else '-':>16} {ratio}")
+        if timer:
+            by_timer[timer] = by_timer.get(timer, 0.0) + t
+    for timer, t in by_timer.items():
+        lines.append(f"timer {timer} {t:.0f}")
+    with open(os.path.join(summ, f"hbm_traffic_{workload}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    # 3. SQ instruction counters
+    sq_path = os.path.join(out, "sq", "run_counter_collection.csv")
+    if os.path.exists(sq_path):
+        sq = read_counters(sq_path)
+        kernels = sorted({k for k, _ in sq})
+        lines = [f"# SQ counters per dispatch (summed over the chip), {workload}", "# command:",
+                 "#   " + prelude.strip(), "#   " + cmds["sq"],
+                 f"{'kernel':48s} " + " ".join(f"{c[3:]:>16s}" for c in SQ_COUNTERS)]
+        for k in kernels:
+            vals = []
+            for c in SQ_COUNTERS:
+                per = sq.get((k, c), {})
+                vals.append(sum(per.values()) / len(per) if per else float("nan"))
+            lines.append(f"{k:48s} " + " ".join(f"{v:16.4g}" for v in vals))
+        with open(os.path.join(summ, f"sq_counters_{workload}.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    print(f"[profile] summaries in {summ}", file=sys.stderr, flush=True)
+
+
 def make_workload(name, device):
     import synth
     if name == "ska_low_share":
@@ -128,7 +347,17 @@ def main():
                     help="pixels of the timed image checked against the float64 oracle (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
+    ap.add_argument("--profile", metavar="OUT",
+                    help="run the rocprofv3 passes (kernel trace, HBM byte counters with copy calibration, SQ "
+                         "counters) on this workload as child processes and summarise them in OUT/summary")
+    ap.add_argument("--summarize", metavar="OUT", help="only rewrite the summaries of an earlier --profile OUT")
     args = ap.parse_args()
+    if args.profile:
+        run_profiles(os.path.abspath(args.profile), args.workload)
+        return
+    if args.summarize:
+        summarize_profiles(os.path.abspath(args.summarize), args.workload)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
@@ -198,7 +427,11 @@ def main():
     for k, v in kernels.items():
         ab = algorithmic_bytes(k, ds, info)
         if ab is not None:
+            v["bytes"] = int(ab)
             v["GBps"] = round(ab / (v["ms"] * 1e-3) / 1e9, 1)
+    roofline["traffic"], roofline["traffic_note"] = measured_traffic(args.workload, dominant)
+    if roofline["traffic"] is not None:
+        roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / dbytes, 3)
 
     check = None
     vis_host = None

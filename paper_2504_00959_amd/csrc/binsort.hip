@@ -13,9 +13,11 @@
 //   bin_scatter repeats the quantisation and writes 12-byte records
 //               {packed local position, W V} at cursor-allocated slots.
 //
-// Slot allocation is aggregated per wavefront: lanes with equal bins take one
-// atomic between them, so the dense bins at the uv centre do not serialise on
-// per-visibility atomics.
+// Counts and slots are taken per run: consecutive visibilities of a wave (the
+// channels of a row, in memory order) whose footprints cover the same bins
+// form a run, found without loops by comparing each lane's footprint key with
+// its left neighbour's; the first lane of a run takes one atomic per bin for
+// the whole run, and the others take the slots that follow.
 //
 // The float64 position arithmetic is written operation by operation with
 // contraction off, so that cell, sub-cell offset, plane and drop decisions are
@@ -86,76 +88,61 @@ __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, doub
     return true;
 }
 
-// Bins touched by the footprint and the record for each.  Returns the count
-// (1..4); bin[i] / pos[i] for i < count.
-__device__ __forceinline__ int footprint_bins(const Geom &g, const Quant &q, int32_t *bin, uint32_t *pos) {
-    const int32_t tx0 = (q.cx - g.h) >> g.log2T, tx1 = (q.cx + g.h) >> g.log2T;
-    const int32_t ty0 = (q.cy - g.h) >> g.log2T, ty1 = (q.cy + g.h) >> g.log2T;
-    const uint32_t sub = (uint32_t)(q.sx + (g.OS >> 1)) << 16 | (uint32_t)(q.sy + (g.OS >> 1)) << 24;
-    int n = 0;
-    for (int32_t ty = ty0; ty <= ty1; ++ty) {
-        for (int32_t tx = tx0; tx <= tx1; ++tx) {
-            const int32_t ox = q.cx - g.h - (tx << g.log2T) + 2 * g.h;   // in [0, T + 2h)
-            const int32_t oy = q.cy - g.h - (ty << g.log2T) + 2 * g.h;
-            bin[n] = (q.k * g.nt + ty) * g.nt + tx;
-            pos[n] = (uint32_t)ox | (uint32_t)oy << 8 | sub;
-            ++n;
-        }
-    }
-    return n;
+// The bins a footprint touches: its top-left tile (tx0, ty0) and whether it
+// also reaches the next tile column (dx) and row (dy).  A tile is at least W
+// cells wide, so a footprint touches at most two tiles per axis.  Packed as
+// ((plane * nt + ty0) * nt + tx0) * 4 + dx * 2 + dy, the key of the set.
+struct Footprint {
+    int32_t base;   // bin of the top-left tile
+    int32_t dx, dy;
+};
+__device__ __forceinline__ Footprint footprint(const Geom &g, const Quant &q) {
+    const int32_t tx0 = (q.cx - g.h) >> g.log2T, ty0 = (q.cy - g.h) >> g.log2T;
+    Footprint f;
+    f.dx = ((q.cx + g.h) >> g.log2T) - tx0;
+    f.dy = ((q.cy + g.h) >> g.log2T) - ty0;
+    f.base = (q.k * g.nt + ty0) * g.nt + tx0;
+    return f;
+}
+// Bin j of the set (j = 0: top-left, 1: right, 2: below, 3: below right), if present.
+__device__ __forceinline__ bool has_bin(const Footprint &f, int j) {
+    return (j & 1 ? f.dx : 1) && (j & 2 ? f.dy : 1);
+}
+__device__ __forceinline__ int32_t bin_of(const Geom &g, const Footprint &f, int j) {
+    return f.base + (j & 1) + (j >> 1) * g.nt;
+}
+// The record of a visibility in bin j: footprint origin relative to the tile
+// (biased by 2h so that it is non-negative) and sub-cell offsets.
+__device__ __forceinline__ uint32_t record_pos(const Geom &g, const Quant &q, int j) {
+    const int32_t tx = ((q.cx - g.h) >> g.log2T) + (j & 1), ty = ((q.cy - g.h) >> g.log2T) + (j >> 1);
+    const int32_t ox = q.cx - g.h - (tx << g.log2T) + 2 * g.h;   // in [0, T + 2h)
+    const int32_t oy = q.cy - g.h - (ty << g.log2T) + 2 * g.h;
+    return (uint32_t)ox | (uint32_t)oy << 8 | (uint32_t)(q.sx + (g.OS >> 1)) << 16 |
+           (uint32_t)(q.sy + (g.OS >> 1)) << 24;
 }
 
 __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
 __device__ __forceinline__ void store2(double *p, double a, double b) { *(double2 *)p = make_double2(a, b); }
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    const uint32_t lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Wave-aggregated atomicAdd(&arr[key], 1) for every active lane (no result).
-// Must be called by all lanes of the wave.
-__device__ __forceinline__ void aggregated_count(int32_t *arr, int32_t key, bool active) {
-    uint64_t pending = __ballot(active);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t lkey = __builtin_amdgcn_readlane(key, leader);
-        const bool mine = active && key == lkey;
-        const uint64_t same = __ballot(mine);
-        if ((int)__lane_id() == leader) atomicAdd(&arr[lkey], (int32_t)__popcll(same));
-        if (mine) active = false;
-        pending &= ~same;
-    }
-}
-
-// Wave-aggregated slot allocation: lanes with equal keys share one
-// atomicAdd(&arr[key], count).  The atomics are only issued here; the lane's
-// slot is base(leader) + rank, read after all of a wave's atomics are in
-// flight (slot_of), so the wave waits for the round trips once.
-struct SlotReq {
-    int32_t base;     // the returned old value (valid in leader lanes)
-    int32_t leader;   // lane holding this lane's base
-    int32_t rank;     // this lane's position among the lanes of its key
+// Runs of equal keys along the lanes of a wave.  Must be called by all lanes.
+// Lane 0 always starts a run; `leader` is the first lane of this lane's run,
+// `len` (meaningful in leaders) the run's length.
+struct Run {
+    int32_t leader, len;
+    bool head;
 };
-__device__ __forceinline__ SlotReq aggregated_slot_issue(int32_t *arr, int32_t key, bool active) {
-    SlotReq r{0, 0, 0};
-    uint64_t pending = __ballot(active);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t lkey = __builtin_amdgcn_readlane(key, leader);
-        const bool mine = active && key == lkey;
-        const uint64_t same = __ballot(mine);
-        if ((int)__lane_id() == leader) r.base = atomicAdd(&arr[lkey], (int32_t)__popcll(same));
-        if (mine) {
-            r.leader = leader;
-            r.rank = (int32_t)__popcll(same & lanemask_lt());
-            active = false;
-        }
-        pending &= ~same;
-    }
+__device__ __forceinline__ Run runs_of(int32_t key) {
+    const int lane = (int)__lane_id();
+    const int32_t prev = __shfl_up(key, 1);   // key of lane - 1
+    Run r;
+    r.head = lane == 0 || key != prev;
+    const uint64_t heads = __ballot(r.head);
+    const uint64_t upto = heads & (~0ull >> (63 - lane));               // heads at lanes <= lane
+    const uint64_t after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+    r.leader = 63 - __clzll((long long)upto);
+    r.len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
     return r;
 }
-__device__ __forceinline__ int32_t slot_of(const SlotReq &r) { return __shfl(r.base, r.leader) + r.rank; }
 
 // Grid-stride walk over visibility index i = r * nchan + c with the row r and
 // channel c updated incrementally (no division per step; indices fit 32 bits
@@ -229,10 +216,13 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__re
                 ++dropped;
             }
         }
-        int32_t bin[4] = {0, 0, 0, 0};
-        uint32_t pos[4];
-        const int nb = keep ? footprint_bins(g, q, bin, pos) : 0;
-        for (int j = 0; j < 4; ++j) aggregated_count(my_counts, bin[j], j < nb);
+        const Footprint f = footprint(g, q);
+        const Run run = runs_of(keep ? f.base * 4 + f.dx * 2 + f.dy : -1);
+        if (keep && run.head) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (has_bin(f, j)) atomicAdd(&my_counts[bin_of(g, f, j)], run.len);
+        }
     }
     // block reduction, one atomic per block and counter
     for (int off = 32; off > 0; off >>= 1) {
@@ -287,17 +277,22 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__
             ar = (real)wt * vr;
             ai = (real)wt * vi;
         }
-        int32_t bin[4] = {0, 0, 0, 0};
-        uint32_t pos[4] = {0, 0, 0, 0};
-        const int nb = keep ? footprint_bins(g, q, bin, pos) : 0;
-        SlotReq req[4];
+        const Footprint f = footprint(g, q);
+        const Run run = runs_of(keep ? f.base * 4 + f.dx * 2 + f.dy : -1);
+        // the run's first lane takes the slots of the whole run in each bin;
+        // all atomics are issued before any result is read
+        int32_t base[4] = {0, 0, 0, 0};
+        if (keep && run.head) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) req[j] = aggregated_slot_issue(my_cursor, bin[j], j < nb);
+            for (int j = 0; j < 4; ++j)
+                if (has_bin(f, j)) base[j] = atomicAdd(&my_cursor[bin_of(g, f, j)], run.len);
+        }
+        const int32_t rank = (int32_t)__lane_id() - run.leader;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int32_t slot = slot_of(req[j]);
-            if (j < nb) {
-                rec_pos[slot] = pos[j];
+            const int32_t slot = __shfl(base[j], run.leader) + rank;
+            if (keep && has_bin(f, j)) {
+                rec_pos[slot] = record_pos(g, q, j);
                 store2(rec_vis + 2 * (uint32_t)slot, ar, ai);
             }
         }
