@@ -304,8 +304,35 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols(real *__restri
     }
 }
 
-__device__ __forceinline__ void sincospi_r(float x, float *s, float *c) { sincospif(x, s, c); }
-__device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sincospi(x, s, c); }
+// Re(exp(+i pi t2) f) (-1)^flip for a phase t2 in float64 half turns.
+// t2 = q + g with q the nearest integer, so exp(+i pi t2) = (-1)^q exp(+i pi g),
+// |g| <= 1/2.  float32: sin(pi g) = g P(g^2), cos(pi g) = Q(g^2), minimax
+// polynomials fitted on [-1/2, 1/2] (Horner form, float32 fma; abs error
+// below 2.5e-7).  float64: sincospi of the float64 remainder.
+__device__ __forceinline__ float screen_term(double t2, float2 f, int flip) {
+    const double qd = rint(t2);
+    const float g = (float)(t2 - qd);
+    const float g2 = g * g;
+    float ps = fmaf(g2, 0.07805382838216549f, -0.5985074114168937f);
+    ps = fmaf(g2, ps, 2.5501159030870695f);
+    ps = fmaf(g2, ps, -5.167712346356822f);
+    ps = fmaf(g2, ps, 3.141592653446274f);
+    const float sn = g * ps;
+    float pc = fmaf(g2, -0.02468992584886284f, 0.23511454480404714f);
+    pc = fmaf(g2, pc, -1.3352479005812146f);
+    pc = fmaf(g2, pc, 4.05871189644457f);
+    pc = fmaf(g2, pc, -4.934802200064621f);
+    pc = fmaf(g2, pc, 1.0f);
+    const float t = fmaf(pc, f.x, -sn * f.y);
+    return (((int)qd ^ flip) & 1) ? -t : t;
+}
+__device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
+    const double qd = rint(t2);
+    double sn, cs;
+    sincospi(t2 - qd, &sn, &cs);
+    const double t = cs * f.x - sn * f.y;
+    return (((int)qd ^ flip) & 1) ? -t : t;
+}
 
 // ---- columns fused with the w-correction and the plane sum ----
 // One block per strip of V columns loops over all planes: the strip of plane
@@ -313,8 +340,8 @@ __device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sin
 // registers, and each thread adds Re(exp(+2 pi i w_k (n - 1)) F_k) for the 16
 // x VC pixels it owns; plane k + 1 is fetched into registers meanwhile.  The
 // transformed planes are never written back, and the image is written once.
-// Phase in float64 turns, reduced to [-1/2, 1/2] before sincospi; n - 1 of
-// the strip's pixels is kept in LDS in float64.
+// n - 1 of the strip's pixels is kept in LDS in float64; the phase
+// 2 w_k (n - 1) is formed in float64 half turns.
 template <typename real, int N, int V, int VC, bool KAHAN>
 __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
                                                                          const real *__restrict__ twr,
@@ -379,18 +406,13 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         // read the previous plane's last exchange before this plane's first
         __syncthreads();
         fft_regs<N, V, VC>(x, buf, tb, v0, tw);
-        const double w = wk[k];
+        const double w2 = 2.0 * wk[k];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = out_elem<N>(tb, q);
 #pragma unroll
             for (int v = 0; v < VC; ++v) {
-                const C f = cneg_if(x[q][v], e & 1);
-                const double tau = w * s_nm1[e * V + v0 + v];
-                const double tr = tau - rint(tau);
-                real sn, cs;
-                sincospi_r((real)(2.0 * tr), &sn, &cs);
-                const real term = cs * f.x - sn * f.y;
+                const real term = screen_term(w2 * s_nm1[e * V + v0 + v], x[q][v], e & 1);
                 if (KAHAN) {
                     const real y = term - comp[q][v];
                     const real t = acc[q][v] + y;

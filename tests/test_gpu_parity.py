@@ -136,6 +136,15 @@ def test_heavy_bins_split_over_chunks():
     check_stages(ds, gpu, oracle_of(ds))
 
 
+@pytest.mark.parametrize("tile,chunk", [(16, 512), (32, 2048)])
+def test_split_bins_at_other_tiles_and_chunks(tile, chunk):
+    """bins split over several chunks at smaller tiles: partial tiles merged onto the mesh"""
+    ds = synth.tiny()
+    gpu = run_gpu(ds, tile=tile, chunk=chunk)
+    assert gpu["counts"].max() > chunk              # split bins occur
+    check_stages(ds, gpu, oracle_of(ds))
+
+
 @pytest.mark.parametrize("kernel", ["gaussian", "kaiser_bessel"])
 @pytest.mark.parametrize("W,OS,tile", [(1, 1, 16), (3, 4, 32), (5, 256, 64), (7, 64, 64), (9, 8, 16),
                                        (15, 2, 32)])
@@ -182,11 +191,13 @@ def test_dropped_inputs_match_oracle():
     check_stages(ds, run_gpu(ds), ref)
 
 
-def test_accumulating_two_grid_calls_equals_one():
+@pytest.mark.parametrize("tile,chunk", [(0, 0), (16, 512), (16, 64)])
+def test_accumulating_two_grid_calls_equals_one(tile, chunk):
+    """also with bins split over several chunks (16, 512) and (16, 64)"""
     import torch
     ds = synth.tiny(nrow=30000, seed=10)
     uvw, vis, _ = to_device(ds)
-    with rick.Plan.for_dataset(ds) as p:
+    with rick.Plan.for_dataset(ds, tile=tile, chunk=chunk) as p:
         p.reset()
         p.grid(uvw[:12345], vis[:12345])
         p.grid(uvw[12345:], vis[12345:])
