@@ -24,6 +24,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CU_COUNT = 256
+CLOCK_HZ = 2.4e9
 METRIC = "Mvis/s through grid+iFFT+w-stack at fixed image RMS vs FP64 DFT oracle"
 
 
@@ -35,7 +37,7 @@ def algorithmic_bytes(name, ds, info):
     cells = ds.n_wplanes * ds.grid_n * ds.grid_n
     wbytes = 4 * nvis if ds.weight is not None else 0
     table = {
-        "bin_count": 24 * nrow + wbytes,
+        "bin_count": 24 * nrow + 8 * nvis + wbytes,     # the drop test reads the visibilities too
         "bin_scatter": 24 * nrow + 8 * nvis + wbytes + 12 * nvis,
         "grid": 12 * nvis + 8 * cells,
         "fft_rows": 16 * cells,
@@ -46,10 +48,10 @@ def algorithmic_bytes(name, ds, info):
     return table.get(name)
 
 
-def cpu_baseline(ds, vis_host, n_rows_sample=262_144, n_planes_sample=2):
+def cpu_baseline(ds, vis_host, n_rows_sample=1_048_576, n_grid_target=2_000_000, n_planes_fft=2):
     """The float64 oracle, as it stands, timed stage by stage on a bounded sample
-    of the same workload and scaled to the whole job:
-      T = (t_bin + t_grid) / n_sample_vis * N_vis + N_w * (t_fft_plane + t_screen_plane)."""
+    of the same workload (about 15 s of one host core) and scaled to the whole job:
+      T = t_bin / n_binned * N_vis + t_grid / n_gridded * N_kept + N_w * (t_fft + t_screen) / n_planes."""
     import oracle
     from oracle import wstack as ow
     kw = ds.plan_kwargs()
@@ -67,32 +69,39 @@ def cpu_baseline(ds, vis_host, n_rows_sample=262_144, n_planes_sample=2):
     table = ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param)
     keep = np.nonzero(b.keep)[0]
     kk = b.k[keep]
-    planes = np.argsort(-np.bincount(kk, minlength=ds.n_wplanes))[:n_planes_sample]
     G = np.zeros((1, ds.grid_n, ds.grid_n), np.complex128)
-    t_grid, n_grid = 0.0, 0
-    for k in planes:
+    t_grid, n_grid, n_planes = 0.0, 0, 0
+    for k in np.argsort(-np.bincount(kk, minlength=ds.n_wplanes)):
+        if n_grid >= n_grid_target:
+            break
         idx = keep[kk == k]
         G[0] = 0
         t0 = time.perf_counter()
         ow.grid_plane(G[0], b, idx, table)
         t_grid += time.perf_counter() - t0
         n_grid += idx.size
-    t0 = time.perf_counter()
-    F = ow.ifft_planes(G)
-    t_fft = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    S = ow.screen_sum(F, ow.plane_centres(ds.w_min, ds.w_max, ds.n_wplanes)[:1], ds.fov)
+        n_planes += 1
+    t_fft = t_screen = 0.0
     corr = ow.grid_correction(table, ds.grid_n)
-    ow.normalise(S, corr, 1.0, ds.fov)
-    t_screen = time.perf_counter() - t0
-    per_vis = t_bin / n_s + (t_grid / n_grid if n_grid else 0.0)
-    total = per_vis * ds.nvis + ds.n_wplanes * (t_fft + t_screen)
-    sample = (f"oracle stages timed on {n_s:,} visibilities ({uvw_s.shape[0]:,} rows x {ds.nchan} channels, "
-              f"binned), {n_grid:,} of them gridded onto {len(planes)} plane(s), one {ds.grid_n}^2 plane "
-              f"transformed and screened; per-visibility and per-plane costs scaled to {ds.nvis:,} "
-              f"visibilities and {ds.n_wplanes} planes (est. {total:.1f} s per image)")
+    wk = ow.plane_centres(ds.w_min, ds.w_max, ds.n_wplanes)
+    for j in range(n_planes_fft):
+        t0 = time.perf_counter()
+        F = ow.ifft_planes(G)
+        t_fft += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        S = ow.screen_sum(F, wk[j:j + 1], ds.fov)
+        ow.normalise(S, corr, 1.0, ds.fov)
+        t_screen += time.perf_counter() - t0
+    kept_frac = float(b.keep.mean()) if n_s else 0.0
+    total = (t_bin / n_s * ds.nvis + (t_grid / n_grid if n_grid else 0.0) * kept_frac * ds.nvis +
+             ds.n_wplanes * (t_fft + t_screen) / n_planes_fft)
+    spent = t_bin + t_grid + t_fft + t_screen
+    sample = (f"oracle stages timed on {n_s:,} visibilities binned ({uvw_s.shape[0]:,} rows x {ds.nchan} channels, "
+              f"every {step}th row), {n_grid:,} of them gridded onto {n_planes} plane(s), {n_planes_fft} "
+              f"{ds.grid_n}^2 planes transformed and screened ({spent:.1f} s); per-visibility and per-plane costs "
+              f"scaled to {ds.nvis:,} visibilities and {ds.n_wplanes} planes (est. {total:.0f} s per image)")
     return {"value": ds.nvis / total / 1e6, "unit": "Mvis/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "sample_seconds": round(t_bin + t_grid + t_fft + t_screen, 2)}
+            "sample_seconds": round(spent, 2)}
 
 
 # ---------------------------------------------------------------------------
@@ -142,8 +151,8 @@ def measured_traffic(workload, timer):
             if line.startswith("# source_sha256:"):
                 digest = line.split(":", 1)[1].strip()
             elif line.startswith("timer "):
-                _, name, val = line.split()
-                rows[name] = float(val)
+                name, val = line[len("timer "):].rsplit(None, 1)
+                rows[name.strip()] = float(val)
     if digest != kernel_sources_digest():
         return None, "kernel sources changed since the counters were taken"
     if timer not in rows:
@@ -430,6 +439,14 @@ def main():
             v["bytes"] = int(ab)
             v["GBps"] = round(ab / (v["ms"] * 1e-3) / 1e9, 1)
     roofline["traffic"], roofline["traffic_note"] = measured_traffic(args.workload, dominant)
+    if dominant == "grid" and info["n_records"] > 0:
+        # the gridder is bound by LDS instruction issue, not HBM: per record
+        # two ds_add_f64 and two ds_read_b32, at the per-CU rates measured on
+        # gfx950 (8.31 and 2.37 clocks per wave instruction)
+        floor_clk = 2 * 8.31 + 2 * 2.37
+        clk = kernels["grid"]["ms"] * 1e-3 * CU_COUNT * CLOCK_HZ / info["n_records"]
+        roofline["lds_issue"] = {"records": int(info["n_records"]), "clk_per_record": round(clk, 2),
+                                 "floor_clk_per_record": floor_clk, "frac": round(floor_clk / clk, 3)}
     if roofline["traffic"] is not None:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / dbytes, 3)
 
