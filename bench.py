@@ -38,7 +38,9 @@ def algorithmic_bytes(name, ds, info):
     wbytes = 4 * nvis if ds.weight is not None else 0
     table = {
         "bin_count": 24 * nrow + 8 * nvis + wbytes,     # the drop test reads the visibilities too
-        "bin_scatter": 24 * nrow + 8 * nvis + wbytes + 12 * nvis,
+        "bin_scatter": 24 * nrow + 8 * nvis + wbytes + 16 * nvis,   # writes 16-byte level-1 records
+        "fine_count": 8 * nvis,                                    # reads their positions
+        "fine_scatter": 16 * nvis + 12 * nvis,                     # reads them, writes 12-byte records
         "grid": 12 * nvis + 8 * cells,
         "fft_rows": 16 * cells,
         "fft_cols": 16 * cells,
@@ -115,9 +117,12 @@ COPY_MIB = 1024
 SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS",
                "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"]
 # library kernel -> the plan timer that brackets it
-KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_reset_counts": "bin_count",
-                "k_bin_count": "bin_count", "k_scan_partials": "bin_scan", "k_scan_top": "bin_scan",
-                "k_scan_apply": "bin_scan", "k_bin_scatter": "bin_scatter", "k_zero_heavy": "zero_heavy",
+KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_l1_count": "bin_count",
+                "k_flat_partials": "bin_scan", "k_flat_top": "bin_scan", "k_flat_apply": "bin_scan",
+                "k_l2_chunks": "bin_scan", "k_l1_scatter": "bin_scatter", "k_l2_count": "fine_count",
+                "k_l2_totals": "fine_scan", "k_scan_partials": "fine_scan", "k_scan_top": "fine_scan",
+                "k_scan_apply": "fine_scan", "k_l2_bases": "fine_scan", "k_l2_scatter": "fine_scatter",
+                "k_zero_heavy": "zero_heavy",
                 "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_cols": "fft_cols",
                 "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen"}
 

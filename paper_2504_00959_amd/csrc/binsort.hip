@@ -2,22 +2,33 @@
 // paper's per-sector bucketing of visibilities before convolution
 // (Sec. 2.1, "an array is created for each sector").
 //
-// Three passes over the inputs, all streaming:
-//   bin_count   per visibility: position quantised to 1/OS cell, nearest
-//               cell, closest w-plane, drop test; one count per (plane, tile)
-//               bin the W x W footprint touches (1, 2 or 4 bins);
-//               weight sum and gridded/dropped counters.
-//   bin_scan    exclusive prefix sums of record counts and gridding chunks;
-//               per-copy cursors, the list of gridding work items and the
-//               list of bins split over several chunks.
-//   bin_scatter repeats the quantisation and writes 12-byte records
-//               {packed local position, W V} at cursor-allocated slots.
+// Two levels, so that no pass needs global atomics (on this part every
+// device atomic is executed at the memory side, far slower than LDS):
+//   level 1  coarse bins = (plane, coarse tile of C x C tiles), at most 8192.
+//     bin_count    each block takes a contiguous range of visibilities:
+//                  position quantised to 1/OS cell, nearest cell, closest
+//                  w-plane, drop test; counts per coarse bin the footprint
+//                  touches, in an LDS histogram; writes its column of the
+//                  (coarse bin, block) count table; weight sum and counters.
+//     bin_scan     exclusive scan of that table (coarse-bin major), then the
+//                  level-2 chunk list (each coarse bin cut into chunks).
+//     bin_scatter  repeats the quantisation; slots from LDS cursors seeded
+//                  with the block's scanned offsets; writes level-1 records
+//                  {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}.
+//   level 2  bins = (plane, tile) inside each coarse bin, at most C^2 = 16384.
+//     fine_count   one block per chunk: LDS histogram over the tiles of the
+//                  coarse tile that each record's footprint touches.
+//     fine_scan    per bin, the total over its coarse bin's chunks; exclusive
+//                  scan of records and gridding chunks in bin order (item and
+//                  heavy-bin lists); per (chunk, tile) record offsets.
+//     fine_scatter one block per chunk: slots from LDS cursors; writes the
+//                  12-byte records {packed position in the tile, W V}.
 //
-// Counts and slots are taken per run: consecutive visibilities of a wave (the
-// channels of a row, in memory order) whose footprints cover the same bins
-// form a run, found without loops by comparing each lane's footprint key with
-// its left neighbour's; the first lane of a run takes one atomic per bin for
-// the whole run, and the others take the slots that follow.
+// Counts and slots in LDS are taken per run: consecutive records of a wave
+// whose footprints cover the same bins form a run, found without loops by
+// comparing each lane's footprint key with its left neighbour's; the first
+// lane of a run takes one LDS atomic per bin for the whole run, and the
+// others take the slots that follow.
 //
 // The float64 position arithmetic is written operation by operation with
 // contraction off, so that cell, sub-cell offset, plane and drop decisions are
@@ -29,7 +40,6 @@ namespace rick {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxBlocks = 8192;   // count and scatter use the same grid: a visibility meets the same counter copy
 
 __global__ void k_zero_stats(Stats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -39,13 +49,6 @@ __global__ void k_zero_stats(Stats *st) {
         st->n_heavy = 0;
         st->sum_w = 0.0;
     }
-}
-
-// zero the per-copy bin counters and the per-call heavy-bin count
-__global__ void k_reset_counts(int32_t *__restrict__ a, int64_t n, Stats *__restrict__ st) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_heavy = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = 0;
 }
 
 __global__ void k_set_scales(double *__restrict__ dst, ChanScales cs, int32_t n) {
@@ -88,37 +91,24 @@ __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, doub
     return true;
 }
 
-// The bins a footprint touches: its top-left tile (tx0, ty0) and whether it
-// also reaches the next tile column (dx) and row (dy).  A tile is at least W
-// cells wide, so a footprint touches at most two tiles per axis.  Packed as
-// ((plane * nt + ty0) * nt + tx0) * 4 + dx * 2 + dy, the key of the set.
-struct Footprint {
-    int32_t base;   // bin of the top-left tile
-    int32_t dx, dy;
+// Tiles of edge 2^shift cells that the W x W footprint of cell (cx, cy)
+// touches: the top-left one (x0, y0) and whether it also reaches the next
+// column (dx) and row (dy).  A tile is at least W cells wide, so at most two
+// per axis.
+struct Span {
+    int32_t x0, y0, dx, dy;
 };
-__device__ __forceinline__ Footprint footprint(const Geom &g, const Quant &q) {
-    const int32_t tx0 = (q.cx - g.h) >> g.log2T, ty0 = (q.cy - g.h) >> g.log2T;
-    Footprint f;
-    f.dx = ((q.cx + g.h) >> g.log2T) - tx0;
-    f.dy = ((q.cy + g.h) >> g.log2T) - ty0;
-    f.base = (q.k * g.nt + ty0) * g.nt + tx0;
-    return f;
+__device__ __forceinline__ Span span_of(const Quant &q, int32_t h, int32_t shift) {
+    Span s;
+    s.x0 = (q.cx - h) >> shift;
+    s.y0 = (q.cy - h) >> shift;
+    s.dx = ((q.cx + h) >> shift) - s.x0;
+    s.dy = ((q.cy + h) >> shift) - s.y0;
+    return s;
 }
-// Bin j of the set (j = 0: top-left, 1: right, 2: below, 3: below right), if present.
-__device__ __forceinline__ bool has_bin(const Footprint &f, int j) {
-    return (j & 1 ? f.dx : 1) && (j & 2 ? f.dy : 1);
-}
-__device__ __forceinline__ int32_t bin_of(const Geom &g, const Footprint &f, int j) {
-    return f.base + (j & 1) + (j >> 1) * g.nt;
-}
-// The record of a visibility in bin j: footprint origin relative to the tile
-// (biased by 2h so that it is non-negative) and sub-cell offsets.
-__device__ __forceinline__ uint32_t record_pos(const Geom &g, const Quant &q, int j) {
-    const int32_t tx = ((q.cx - g.h) >> g.log2T) + (j & 1), ty = ((q.cy - g.h) >> g.log2T) + (j >> 1);
-    const int32_t ox = q.cx - g.h - (tx << g.log2T) + 2 * g.h;   // in [0, T + 2h)
-    const int32_t oy = q.cy - g.h - (ty << g.log2T) + 2 * g.h;
-    return (uint32_t)ox | (uint32_t)oy << 8 | (uint32_t)(q.sx + (g.OS >> 1)) << 16 |
-           (uint32_t)(q.sy + (g.OS >> 1)) << 24;
+// member j of a span (j = 0: top-left, 1: right, 2: below, 3: below right), if present
+__device__ __forceinline__ bool in_span(int32_t dx, int32_t dy, int j) {
+    return (j & 1) <= dx && (j >> 1) <= dy;
 }
 
 __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
@@ -183,27 +173,34 @@ __device__ __forceinline__ void load_vis(const Geom &g, const double *__restrict
     wt = weight ? weight[i] : 1.0f;
 }
 
+// ---- level 1: coarse bins ----
+
+// Level-1 partition: block b takes visibilities [b per, min((b + 1) per, nvis)).
+struct L1Part {
+    int32_t nb1;
+    int32_t per;   // a multiple of kBlock
+};
+
 template <typename real>
-__global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__restrict__ uvw,
-                                                      const double *__restrict__ scales,
-                                                      const real *__restrict__ vis, const float *__restrict__ weight,
-                                                      int64_t nvis, int32_t nchan, int32_t *__restrict__ counts,
-                                                      Stats *__restrict__ st) {
+__global__ __launch_bounds__(kBlock) void k_l1_count(Geom g, const double *__restrict__ uvw,
+                                                     const double *__restrict__ scales, const real *__restrict__ vis,
+                                                     const float *__restrict__ weight, int64_t nvis, int32_t nchan,
+                                                     L1Part part, int32_t *__restrict__ cnt1, Stats *__restrict__ st) {
+    extern __shared__ int32_t s_cnt[];   // g.n1 counters
     __shared__ double s_w[kBlock / 64];
     __shared__ unsigned long long s_kept[kBlock / 64], s_drop[kBlock / 64];
+    for (int i = threadIdx.x; i < g.n1; i += kBlock) s_cnt[i] = 0;
+    __syncthreads();
+    const int64_t v0 = (int64_t)blockIdx.x * part.per;
+    const int64_t v1 = v0 + part.per < nvis ? v0 + part.per : nvis;
+    const int32_t cshift = g.log2T + g.log2C;
     double sum_w = 0.0;
     unsigned long long kept = 0, dropped = 0;
-    // counters are privatised over kCopies copies (by block), which spreads
-    // the atomics on the dense central bins over several cache lines
-    int32_t *my_counts = counts + (blockIdx.x % kCopies) * (g.nbins + 1);
-    const uint32_t stride = gridDim.x * kBlock;
-    // loop bound uniform across the block so that every lane joins the ballots
-    const uint32_t iters = (uint32_t)((nvis + stride - 1) / stride);
-    VisWalk vw(blockIdx.x * kBlock + threadIdx.x, stride, (uint32_t)nchan);
-    for (uint32_t it = 0; it < iters; ++it, vw.next((uint32_t)nchan)) {
+    VisWalk vw((uint32_t)(v0 + threadIdx.x), kBlock, (uint32_t)nchan);
+    for (int32_t it = 0; it < part.per / kBlock; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
-        if (vw.i < (uint32_t)nvis) {
+        if ((int64_t)vw.i < v1) {
             double u, v, w;
             real vr, vi;
             float wt;
@@ -216,15 +213,16 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__re
                 ++dropped;
             }
         }
-        const Footprint f = footprint(g, q);
-        const Run run = runs_of(keep ? f.base * 4 + f.dx * 2 + f.dy : -1);
+        const Span cs = span_of(q, g.h, cshift);
+        const int32_t base = (q.k * g.nct + cs.y0) * g.nct + cs.x0;
+        const Run run = runs_of(keep ? base * 4 + cs.dx * 2 + cs.dy : -1);
         if (keep && run.head) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (has_bin(f, j)) atomicAdd(&my_counts[bin_of(g, f, j)], run.len);
+                if (in_span(cs.dx, cs.dy, j)) atomicAdd(&s_cnt[base + (j & 1) + (j >> 1) * g.nct], run.len);
         }
     }
-    // block reduction, one atomic per block and counter
+    // block reduction of the counters, one atomic per block and counter
     for (int off = 32; off > 0; off >>= 1) {
         sum_w += __shfl_down(sum_w, off);
         kept += __shfl_down(kept, off);
@@ -251,24 +249,29 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Geom g, const double *__re
         }
         if (td) atomicAdd(&st->n_dropped, td);
     }
+    // this block's column of the (coarse bin, block) table
+    for (int i = threadIdx.x; i < g.n1; i += kBlock) cnt1[(int64_t)i * part.nb1 + blockIdx.x] = s_cnt[i];
 }
 
 template <typename real>
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__restrict__ uvw,
-                                                        const double *__restrict__ scales,
-                                                        const real *__restrict__ vis,
-                                                        const float *__restrict__ weight, int64_t nvis,
-                                                        int32_t nchan, int32_t *__restrict__ cursor,
-                                                        uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
-    int32_t *my_cursor = cursor + (blockIdx.x % kCopies) * g.nbins;
-    const uint32_t stride = gridDim.x * kBlock;
-    const uint32_t iters = (uint32_t)((nvis + stride - 1) / stride);
-    VisWalk vw(blockIdx.x * kBlock + threadIdx.x, stride, (uint32_t)nchan);
-    for (uint32_t it = 0; it < iters; ++it, vw.next((uint32_t)nchan)) {
+__global__ __launch_bounds__(kBlock) void k_l1_scatter(Geom g, const double *__restrict__ uvw,
+                                                       const double *__restrict__ scales,
+                                                       const real *__restrict__ vis, const float *__restrict__ weight,
+                                                       int64_t nvis, int32_t nchan, L1Part part,
+                                                       const int32_t *__restrict__ base1, uint2 *__restrict__ pos1,
+                                                       real *__restrict__ vis1) {
+    extern __shared__ int32_t s_cur[];   // g.n1 cursors
+    for (int i = threadIdx.x; i < g.n1; i += kBlock) s_cur[i] = base1[(int64_t)i * part.nb1 + blockIdx.x];
+    __syncthreads();
+    const int64_t v0 = (int64_t)blockIdx.x * part.per;
+    const int64_t v1 = v0 + part.per < nvis ? v0 + part.per : nvis;
+    const int32_t cshift = g.log2T + g.log2C;
+    VisWalk vw((uint32_t)(v0 + threadIdx.x), kBlock, (uint32_t)nchan);
+    for (int32_t it = 0; it < part.per / kBlock; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
         real ar = 0, ai = 0;
-        if (vw.i < (uint32_t)nvis) {
+        if ((int64_t)vw.i < v1) {
             double u, v, w;
             real vr, vi;
             float wt;
@@ -277,36 +280,35 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(Geom g, const double *__
             ar = (real)wt * vr;
             ai = (real)wt * vi;
         }
-        const Footprint f = footprint(g, q);
-        const Run run = runs_of(keep ? f.base * 4 + f.dx * 2 + f.dy : -1);
-        // the run's first lane takes the slots of the whole run in each bin;
-        // all atomics are issued before any result is read
-        int32_t base[4] = {0, 0, 0, 0};
+        const Span cs = span_of(q, g.h, cshift);
+        const int32_t base = (q.k * g.nct + cs.y0) * g.nct + cs.x0;
+        const Run run = runs_of(keep ? base * 4 + cs.dx * 2 + cs.dy : -1);
+        // the run's first lane takes the slots of the whole run in each coarse bin
+        int32_t b4[4] = {0, 0, 0, 0};
         if (keep && run.head) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (has_bin(f, j)) base[j] = atomicAdd(&my_cursor[bin_of(g, f, j)], run.len);
+                if (in_span(cs.dx, cs.dy, j)) b4[j] = atomicAdd(&s_cur[base + (j & 1) + (j >> 1) * g.nct], run.len);
         }
         const int32_t rank = (int32_t)__lane_id() - run.leader;
+        const uint2 p1 = make_uint2((uint32_t)q.cx | (uint32_t)q.cy << 16,
+                                    (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
+                                        (uint32_t)q.k << 16);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int32_t slot = __shfl(base[j], run.leader) + rank;
-            if (keep && has_bin(f, j)) {
-                rec_pos[slot] = record_pos(g, q, j);
-                store2(rec_vis + 2 * (uint32_t)slot, ar, ai);
+            const int32_t slot = __shfl(b4[j], run.leader) + rank;
+            if (keep && in_span(cs.dx, cs.dy, j)) {
+                pos1[slot] = p1;
+                store2(vis1 + 2 * (int64_t)slot, ar, ai);
             }
         }
     }
 }
 
-// ---- scan of per-bin counts ----
+// ---- scans ----
 constexpr int kScanBlock = 1024;
 constexpr int kScanPer = 2;
 constexpr int kScanTile = kScanBlock * kScanPer;
-
-__device__ __forceinline__ int32_t chunks_of(int32_t count, int32_t CH) {
-    return count <= CH ? 1 : (count + CH - 1) / CH;
-}
 
 // block-wide exclusive scan of (a, b) pairs; returns totals through refs
 __device__ __forceinline__ void block_scan2(int32_t &a, int32_t &b, int32_t &tot_a, int32_t &tot_b) {
@@ -341,11 +343,239 @@ __device__ __forceinline__ void block_scan2(int32_t &a, int32_t &b, int32_t &tot
     __syncthreads();
 }
 
-__device__ __forceinline__ int32_t total_count(const int32_t *__restrict__ counts, int32_t n, int64_t i) {
-    int32_t c = 0;
-#pragma unroll
-    for (int s = 0; s < kCopies; ++s) c += counts[(int64_t)s * (n + 1) + i];
+// flat exclusive scan of an int32 array, in place; a[n] receives the total
+__global__ __launch_bounds__(kScanBlock) void k_flat_partials(const int32_t *__restrict__ a, int64_t n,
+                                                              int32_t *__restrict__ bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int32_t x = 0, y = 0;
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) x += a[base + k];
+    int32_t tx, ty;
+    block_scan2(x, y, tx, ty);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tx;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_flat_top(int32_t *__restrict__ bsum, int32_t nblk) {
+    int32_t carry = 0;
+    for (int32_t s0 = 0; s0 < nblk; s0 += kScanBlock) {
+        const int32_t i = s0 + threadIdx.x;
+        int32_t x = i < nblk ? bsum[i] : 0, y = 0;
+        int32_t tx, ty;
+        block_scan2(x, y, tx, ty);
+        if (i < nblk) bsum[i] = x + carry;
+        carry += tx;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_flat_apply(int32_t *__restrict__ a, int64_t n,
+                                                           const int32_t *__restrict__ bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int32_t c[kScanPer], x = 0, y = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        c[k] = base + k < n ? a[base + k] : 0;
+        x += c[k];
+    }
+    int32_t tx, ty;
+    block_scan2(x, y, tx, ty);
+    x += bsum[blockIdx.x];
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) a[base + k] = x;
+        else if (base + k == n) a[n] = x;
+        x += c[k];
+    }
+}
+
+// Level-2 chunk list: coarse bin c (offsets off(c) = cnt1[c nb1], total at
+// cnt1[n1 nb1]) is cut into ceil(n_c / CHK) chunks; key_chunk0[c] is its first
+// chunk and chunk_key[] names the coarse bin of each chunk.  One block.
+__global__ __launch_bounds__(kScanBlock) void k_l2_chunks(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
+                                                          int32_t *__restrict__ key_chunk0,
+                                                          int32_t *__restrict__ chunk_key, Stats *__restrict__ st) {
+    int32_t carry = 0;
+    for (int32_t s0 = 0; s0 < g.n1; s0 += kScanBlock) {
+        const int32_t c = s0 + threadIdx.x;
+        int32_t nch = 0;
+        if (c < g.n1) {
+            const int32_t n = base1[(int64_t)(c + 1) * nb1] - base1[(int64_t)c * nb1];
+            nch = (n + g.CHK - 1) / g.CHK;
+        }
+        int32_t x = nch, y = 0, tx, ty;
+        block_scan2(x, y, tx, ty);
+        if (c < g.n1) {
+            key_chunk0[c] = carry + x;
+            for (int32_t j = 0; j < nch; ++j) chunk_key[carry + x + j] = c;
+        }
+        carry += tx;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        key_chunk0[g.n1] = carry;
+        st->n_chunks = (unsigned long long)carry;
+        st->n_heavy = 0;
+    }
+}
+
+// ---- level 2: bins inside each coarse bin ----
+
+// Chunk `chunk` of coarse bin `key`: records [r0, r1) of the level-1 array.
+struct Chunk {
+    int32_t key, r0, r1, ctx, cty;
+};
+__device__ __forceinline__ Chunk chunk_of(const Geom &g, const int32_t *__restrict__ base1, int32_t nb1,
+                                          const int32_t *__restrict__ key_chunk0,
+                                          const int32_t *__restrict__ chunk_key, int32_t chunk) {
+    Chunk c;
+    c.key = chunk_key[chunk];
+    const int32_t j = chunk - key_chunk0[c.key];
+    const int32_t end = base1[(int64_t)(c.key + 1) * nb1];
+    c.r0 = base1[(int64_t)c.key * nb1] + j * g.CHK;
+    c.r1 = c.r0 + g.CHK < end ? c.r0 + g.CHK : end;
+    const int32_t rem = c.key % (g.nct * g.nct);
+    c.cty = rem / g.nct;
+    c.ctx = rem % g.nct;
     return c;
+}
+
+// Tiles of the coarse tile (ctx, cty) that a level-1 record's footprint
+// touches: local columns fx0..fx0+dfx, rows fy0..fy0+dfy.
+struct Local {
+    int32_t fx0, fy0, dfx, dfy;
+};
+__device__ __forceinline__ Local local_span(const Geom &g, uint32_t cxy, int32_t ctx, int32_t cty) {
+    const int32_t cx = (int32_t)(cxy & 0xffffu), cy = (int32_t)(cxy >> 16);
+    const int32_t lo_x = ctx << g.log2C, lo_y = cty << g.log2C, hi = g.C - 1;
+    int32_t x0 = ((cx - g.h) >> g.log2T) - lo_x, x1 = ((cx + g.h) >> g.log2T) - lo_x;
+    int32_t y0 = ((cy - g.h) >> g.log2T) - lo_y, y1 = ((cy + g.h) >> g.log2T) - lo_y;
+    x0 = x0 < 0 ? 0 : x0;
+    y0 = y0 < 0 ? 0 : y0;
+    x1 = x1 > hi ? hi : x1;
+    y1 = y1 > hi ? hi : y1;
+    return Local{x0, y0, x1 - x0, y1 - y0};
+}
+
+__global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
+                                                     const int32_t *__restrict__ key_chunk0,
+                                                     const int32_t *__restrict__ chunk_key,
+                                                     const Stats *__restrict__ st, const uint2 *__restrict__ pos1,
+                                                     int32_t *__restrict__ cnt2) {
+    extern __shared__ int32_t s_h[];   // C^2 counters
+    const int32_t chunk = blockIdx.x;
+    if (chunk >= (int32_t)st->n_chunks) return;
+    const int32_t C2 = g.C * g.C;
+    for (int i = threadIdx.x; i < C2; i += kBlock) s_h[i] = 0;
+    __syncthreads();
+    const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
+    for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
+        const int32_t r = r00 + threadIdx.x;
+        const bool valid = r < ck.r1;
+        Local ls{0, 0, 0, 0};
+        if (valid) ls = local_span(g, pos1[r].x, ck.ctx, ck.cty);
+        const Run run = runs_of(valid ? ((ls.fy0 * g.C + ls.fx0) * 2 + ls.dfx) * 2 + ls.dfy : -1);
+        if (valid && run.head) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (in_span(ls.dfx, ls.dfy, j))
+                    atomicAdd(&s_h[(ls.fy0 + (j >> 1)) * g.C + ls.fx0 + (j & 1)], run.len);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < C2; i += kBlock) cnt2[(int64_t)chunk * C2 + i] = s_h[i];
+}
+
+// bin b = (plane, tile y, tile x) -> its coarse bin and its index inside it
+__device__ __forceinline__ void bin_place(const Geom &g, int32_t b, int32_t &key, int32_t &f) {
+    const int32_t k = b / (g.nt * g.nt);
+    const int32_t rem = b - k * g.nt * g.nt;
+    const int32_t ty = rem / g.nt, tx = rem % g.nt;
+    key = (k * g.nct + (ty >> g.log2C)) * g.nct + (tx >> g.log2C);
+    f = (ty & (g.C - 1)) * g.C + (tx & (g.C - 1));
+}
+
+// records per bin: the sum over its coarse bin's chunks
+__global__ __launch_bounds__(kBlock) void k_l2_totals(Geom g, const int32_t *__restrict__ key_chunk0,
+                                                      const int32_t *__restrict__ cnt2, int32_t *__restrict__ counts) {
+    const int32_t b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= g.nbins) return;
+    int32_t key, f;
+    bin_place(g, b, key, f);
+    const int64_t C2 = (int64_t)g.C * g.C;
+    int32_t t = 0;
+    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) t += cnt2[c * C2 + f];
+    counts[b] = t;
+}
+
+// per (chunk, tile) record offsets, in place over the counts
+__global__ __launch_bounds__(kBlock) void k_l2_bases(Geom g, const int32_t *__restrict__ key_chunk0,
+                                                     const BinScan *__restrict__ scan, int32_t *__restrict__ cnt2) {
+    const int32_t b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= g.nbins) return;
+    int32_t key, f;
+    bin_place(g, b, key, f);
+    const int64_t C2 = (int64_t)g.C * g.C;
+    int32_t run = scan[b].rec;
+    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) {
+        const int32_t t = cnt2[c * C2 + f];
+        cnt2[c * C2 + f] = run;
+        run += t;
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
+                                                       const int32_t *__restrict__ key_chunk0,
+                                                       const int32_t *__restrict__ chunk_key,
+                                                       const Stats *__restrict__ st, const uint2 *__restrict__ pos1,
+                                                       const real *__restrict__ vis1,
+                                                       const int32_t *__restrict__ base2,
+                                                       uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
+    extern __shared__ int32_t s_cur[];   // C^2 cursors
+    const int32_t chunk = blockIdx.x;
+    if (chunk >= (int32_t)st->n_chunks) return;
+    const int32_t C2 = g.C * g.C;
+    for (int i = threadIdx.x; i < C2; i += kBlock) s_cur[i] = base2[(int64_t)chunk * C2 + i];
+    __syncthreads();
+    const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
+    const int32_t tx_lo = ck.ctx << g.log2C, ty_lo = ck.cty << g.log2C;
+    for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
+        const int32_t r = r00 + threadIdx.x;
+        const bool valid = r < ck.r1;
+        Local ls{0, 0, 0, 0};
+        uint2 p = make_uint2(0u, 0u);
+        real vr = 0, vi = 0;
+        if (valid) {
+            p = pos1[r];
+            vr = vis1[2 * (int64_t)r];
+            vi = vis1[2 * (int64_t)r + 1];
+            ls = local_span(g, p.x, ck.ctx, ck.cty);
+        }
+        const Run run = runs_of(valid ? ((ls.fy0 * g.C + ls.fx0) * 2 + ls.dfx) * 2 + ls.dfy : -1);
+        int32_t b4[4] = {0, 0, 0, 0};
+        if (valid && run.head) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (in_span(ls.dfx, ls.dfy, j))
+                    b4[j] = atomicAdd(&s_cur[(ls.fy0 + (j >> 1)) * g.C + ls.fx0 + (j & 1)], run.len);
+        }
+        const int32_t rank = (int32_t)__lane_id() - run.leader;
+        const int32_t cx = (int32_t)(p.x & 0xffffu), cy = (int32_t)(p.x >> 16);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t slot = __shfl(b4[j], run.leader) + rank;
+            if (valid && in_span(ls.dfx, ls.dfy, j)) {
+                const int32_t tx = tx_lo + ls.fx0 + (j & 1), ty = ty_lo + ls.fy0 + (j >> 1);
+                const int32_t ox = cx - g.h - (tx << g.log2T) + 2 * g.h;   // in [0, T + 2h)
+                const int32_t oy = cy - g.h - (ty << g.log2T) + 2 * g.h;
+                rec_pos[slot] = (uint32_t)ox | (uint32_t)oy << 8 | (p.y & 0xffffu) << 16;
+                store2(rec_vis + 2 * (int64_t)slot, vr, vi);
+            }
+        }
+    }
+}
+
+// ---- scan of per-bin record counts in bin order ----
+__device__ __forceinline__ int32_t chunks_of(int32_t count, int32_t CH) {
+    return count <= CH ? 1 : (count + CH - 1) / CH;
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_partials(const int32_t *__restrict__ counts, int32_t n,
@@ -354,7 +584,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_partials(const int32_t *__r
     int32_t a = 0, b = 0;
     for (int k = 0; k < kScanPer; ++k) {
         if (base + k < n) {
-            const int32_t c = total_count(counts, n, base + k);
+            const int32_t c = counts[base + k];
             a += c;
             b += chunks_of(c, CH);
         }
@@ -369,8 +599,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_partials(const int32_t *__r
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_top(int32_t *__restrict__ bsum, int32_t nblk) {
     int32_t carry_a = 0, carry_b = 0;
-    for (int32_t s = 0; s < nblk; s += kScanBlock) {
-        const int32_t i = s + threadIdx.x;
+    for (int32_t s0 = 0; s0 < nblk; s0 += kScanBlock) {
+        const int32_t i = s0 + threadIdx.x;
         int32_t a = i < nblk ? bsum[2 * i] : 0, b = i < nblk ? bsum[2 * i + 1] : 0;
         int32_t ta, tb;
         block_scan2(a, b, ta, tb);
@@ -386,13 +616,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(int32_t *__restrict__ b
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int32_t *__restrict__ counts, int32_t n, int32_t CH,
                                                            const int32_t *__restrict__ bsum,
-                                                           BinScan *__restrict__ scan, int32_t *__restrict__ cursor,
-                                                           int32_t *__restrict__ item_bin,
+                                                           BinScan *__restrict__ scan, int32_t *__restrict__ item_bin,
                                                            int32_t *__restrict__ heavy_bins, Stats *__restrict__ st) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int32_t c[kScanPer], a = 0, b = 0;
     for (int k = 0; k < kScanPer; ++k) {
-        c[k] = base + k < n ? total_count(counts, n, base + k) : 0;
+        c[k] = base + k < n ? counts[base + k] : 0;
         a += c[k];
         b += base + k < n ? chunks_of(c[k], CH) : 0;
     }
@@ -405,12 +634,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int32_t *__rest
         if (i < n) {
             scan[i].rec = a;
             scan[i].item = b;
-            // each counter copy owns a contiguous sub-range of the bin
-            int32_t cur = a;
-            for (int s = 0; s < kCopies; ++s) {
-                cursor[(int64_t)s * n + i] = cur;
-                cur += counts[(int64_t)s * (n + 1) + i];
-            }
             const int32_t nch = chunks_of(c[k], CH);
             for (int32_t j = 0; j < nch; ++j) item_bin[b + j] = (int32_t)i;
             if (nch > 1) heavy_bins[atomicAdd(&st->n_heavy, 1ull)] = (int32_t)i;
@@ -424,25 +647,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int32_t *__rest
     }
 }
 
-int grid_blocks(int64_t nvis) {
-    int64_t b = (nvis + kBlock - 1) / kBlock;
-    if (b < 1) b = 1;
-    if (b > kMaxBlocks) b = kMaxBlocks;
-    return (int)b;
-}
-
 }  // namespace
 
 hipError_t launch_zero_stats(Stats *st, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, s, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_reset_counts(const Geom &g, int32_t *counts, Stats *st, hipStream_t s) {
-    const int64_t n = (int64_t)kCopies * (g.nbins + 1);
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_reset_counts, dim3((unsigned)blocks), dim3(256), 0, s, counts, n, st);
     return hipGetLastError();
 }
 
@@ -456,48 +664,86 @@ hipError_t launch_set_scales(double *dst, const double *host_scales, int32_t nch
     return hipGetLastError();
 }
 
-template <typename real>
-hipError_t launch_bin_count(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
-                            const float *weight, int64_t nrow, int32_t nchan, int32_t *counts, Stats *st,
-                            hipStream_t s) {
-    const int64_t nvis = nrow * nchan;
-    if (nvis == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_bin_count<real>, dim3(grid_blocks(nvis)), dim3(kBlock), 0, s, g, uvw, scales_dev, vis,
-                       weight, nvis, nchan, counts, st);
-    return hipGetLastError();
+// level-1 partition of nvis visibilities over at most kL1Blocks blocks
+static L1Part l1_part(int64_t nvis) {
+    int64_t nb = (nvis + kBlock - 1) / kBlock;
+    if (nb < 1) nb = 1;
+    if (nb > kL1Blocks) nb = kL1Blocks;
+    int64_t per = (nvis + nb - 1) / nb;
+    per = (per + kBlock - 1) / kBlock * kBlock;
+    if (per < kBlock) per = kBlock;
+    nb = (nvis + per - 1) / per;
+    if (nb < 1) nb = 1;
+    return L1Part{(int32_t)nb, (int32_t)per};
 }
 
-hipError_t launch_bin_scan(const Geom &g, const int32_t *counts, BinScan *scan, int32_t *block_sums, int32_t *cursor,
-                           int32_t *item_bin, int32_t *heavy_bins, Stats *st, hipStream_t s) {
-    const int32_t n = g.nbins;
-    const int32_t nblk = (n + 1 + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_partials, dim3(nblk), dim3(kScanBlock), 0, s, counts, n, g.CH, block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, block_sums, nblk);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanBlock), 0, s, counts, n, g.CH, block_sums, scan, cursor,
-                       item_bin, heavy_bins, st);
-    return hipGetLastError();
+int32_t bin_max_chunks(const Geom &g, int64_t max_records) {
+    return (int32_t)(g.n1 + (max_records + g.CHK - 1) / g.CHK);
 }
 
 template <typename real>
-hipError_t launch_bin_scatter(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
-                              const float *weight, int64_t nrow, int32_t nchan, int32_t *cursor, uint32_t *rec_pos,
-                              real *rec_vis, hipStream_t s) {
+hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw, const double *scales_dev,
+                             const real *vis, const float *weight, int64_t nrow, int32_t nchan, Stats *st, int phase,
+                             hipStream_t s) {
     const int64_t nvis = nrow * nchan;
-    if (nvis == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_bin_scatter<real>, dim3(grid_blocks(nvis)), dim3(kBlock), 0, s, g, uvw, scales_dev, vis,
-                       weight, nvis, nchan, cursor, rec_pos, rec_vis);
+    const L1Part part = l1_part(nvis);
+    const size_t lds = size_t(g.n1) * sizeof(int32_t);
+    if (phase == 0) {
+        hipLaunchKernelGGL(k_l1_count<real>, dim3(part.nb1), dim3(kBlock), lds, s, g, uvw, scales_dev, vis, weight,
+                           nvis, nchan, part, bb.cnt1, st);
+    } else if (phase == 1) {
+        const int64_t n = (int64_t)g.n1 * part.nb1;
+        const int32_t nblk = (int32_t)((n + 1 + kScanTile - 1) / kScanTile);
+        hipLaunchKernelGGL(k_flat_partials, dim3(nblk), dim3(kScanBlock), 0, s, bb.cnt1, n, bb.bsum);
+        hipLaunchKernelGGL(k_flat_top, dim3(1), dim3(kScanBlock), 0, s, bb.bsum, nblk);
+        hipLaunchKernelGGL(k_flat_apply, dim3(nblk), dim3(kScanBlock), 0, s, bb.cnt1, n, bb.bsum);
+        hipLaunchKernelGGL(k_l2_chunks, dim3(1), dim3(kScanBlock), 0, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
+                           bb.chunk_key, st);
+    } else {
+        hipLaunchKernelGGL(k_l1_scatter<real>, dim3(part.nb1), dim3(kBlock), lds, s, g, uvw, scales_dev, vis,
+                           weight, nvis, nchan, part, bb.cnt1, bb.pos1, (real *)bb.vis1);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_bin_count<float>(const Geom &, const double *, const double *, const float *,
-                                            const float *, int64_t, int32_t, int32_t *, Stats *, hipStream_t);
-template hipError_t launch_bin_count<double>(const Geom &, const double *, const double *, const double *,
-                                             const float *, int64_t, int32_t, int32_t *, Stats *, hipStream_t);
-template hipError_t launch_bin_scatter<float>(const Geom &, const double *, const double *, const float *,
-                                              const float *, int64_t, int32_t, int32_t *, uint32_t *, float *,
+template <typename real>
+hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int32_t nchan, Stats *st, int phase,
+                             hipStream_t s) {
+    const int64_t nvis = nrow * nchan;
+    const L1Part part = l1_part(nvis);
+    // chunks of this call: at most one per coarse bin plus one per CHK level-1 records (<= 4 per visibility)
+    const int32_t nchunk = bin_max_chunks(g, 4 * nvis);
+    const size_t lds = size_t(g.C) * g.C * sizeof(int32_t);
+    const int32_t nbb = (g.nbins + kBlock - 1) / kBlock;
+    if (phase == 0) {
+        hipLaunchKernelGGL(k_l2_count, dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
+                           bb.chunk_key, st, bb.pos1, bb.cnt2);
+    } else if (phase == 1) {
+        hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.counts);
+        const int32_t n = g.nbins;
+        const int32_t nblk = (n + 1 + kScanTile - 1) / kScanTile;
+        hipLaunchKernelGGL(k_scan_partials, dim3(nblk), dim3(kScanBlock), 0, s, bb.counts, n, g.CH, bb.bsum);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, bb.bsum, nblk);
+        hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanBlock), 0, s, bb.counts, n, g.CH, bb.bsum, bb.scan,
+                           bb.item_bin, bb.heavy_bins, st);
+        hipLaunchKernelGGL(k_l2_bases, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.scan, bb.cnt2);
+    } else {
+        hipLaunchKernelGGL(k_l2_scatter<real>, dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+                           bb.key_chunk0, bb.chunk_key, st, bb.pos1, (const real *)bb.vis1, bb.cnt2, bb.rec_pos,
+                           (real *)bb.rec_vis);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_bin_level1<float>(const Geom &, const BinBufs &, const double *, const double *,
+                                             const float *, const float *, int64_t, int32_t, Stats *, int,
+                                             hipStream_t);
+template hipError_t launch_bin_level1<double>(const Geom &, const BinBufs &, const double *, const double *,
+                                              const double *, const float *, int64_t, int32_t, Stats *, int,
                                               hipStream_t);
-template hipError_t launch_bin_scatter<double>(const Geom &, const double *, const double *, const double *,
-                                               const float *, int64_t, int32_t, int32_t *, uint32_t *, double *,
-                                               hipStream_t);
+template hipError_t launch_bin_level2<float>(const Geom &, const BinBufs &, int64_t, int32_t, Stats *, int,
+                                             hipStream_t);
+template hipError_t launch_bin_level2<double>(const Geom &, const BinBufs &, int64_t, int32_t, Stats *, int,
+                                              hipStream_t);
 
 }  // namespace rick

@@ -101,7 +101,13 @@ struct rick_plan_s {
     int32_t *counts = nullptr;
     BinScan *scan = nullptr;
     int32_t *block_sums = nullptr;
-    int32_t *cursor = nullptr;
+    int32_t *cnt1 = nullptr;
+    uint2 *pos1 = nullptr;
+    void *vis1 = nullptr;
+    int32_t *key_chunk0 = nullptr;
+    int32_t *chunk_key = nullptr;
+    int32_t *cnt2 = nullptr;
+    int32_t max_chunks = 0;
     int32_t *item_bin = nullptr;
     int32_t *heavy_bins = nullptr;
     uint32_t *rec_pos = nullptr;
@@ -134,8 +140,10 @@ struct DeviceGuard {
 };
 
 void free_all(rick_plan_t *p) {
-    void *bufs[] = {p->mesh, p->lut, p->twiddle, p->corr, p->wk, p->scales, p->stats, p->counts,
-                    p->scan, p->block_sums, p->cursor, p->item_bin, p->heavy_bins, p->rec_pos, p->rec_vis};
+    void *bufs[] = {p->mesh,      p->lut,        p->twiddle,   p->corr,   p->wk,       p->scales,
+                    p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->pos1,
+                    p->vis1,      p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
+                    p->rec_pos,   p->rec_vis};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < kMaxTimers; ++i)
@@ -147,8 +155,8 @@ rick_status validate(const rick_plan_desc *d) {
     if (!d) return fail(RICK_E_INVALID_ARG, "desc is NULL");
     if (!is_pow2(d->grid_n) || d->grid_n < 64 || d->grid_n > 8192)
         return fail(RICK_E_INVALID_ARG, "grid_n=%d: must be a power of two in [64, 8192]", d->grid_n);
-    if (d->n_wplanes < 1 || d->n_wplanes > 65536)
-        return fail(RICK_E_INVALID_ARG, "n_wplanes=%d: must be in [1, 65536]", d->n_wplanes);
+    if (d->n_wplanes < 1 || d->n_wplanes > kMaxPlanes)
+        return fail(RICK_E_INVALID_ARG, "n_wplanes=%d: must be in [1, %d]", d->n_wplanes, kMaxPlanes);
     if (d->support < 1 || d->support > 15 || (d->support & 1) == 0)
         return fail(RICK_E_INVALID_ARG, "support=%d: must be odd in [1, 15]", d->support);
     if (!is_pow2(d->oversample) || d->oversample > 256)
@@ -191,7 +199,10 @@ void timer_end(rick_plan_t *p, int slot, hipStream_t s) {
     ++p->ev_calls[slot];
 }
 
-enum TimerSlot { T_COUNT = 0, T_SCAN, T_SCATTER, T_ZERO_HEAVY, T_GRID, T_FFT_ROWS, T_FFT_COLS, T_SCREEN, T_RESET };
+enum TimerSlot {
+    T_COUNT = 0, T_SCAN, T_SCATTER, T_ZERO_HEAVY, T_GRID, T_FFT_ROWS, T_FFT_COLS, T_SCREEN, T_RESET,
+    T_FINE_COUNT, T_FINE_SCAN, T_FINE_SCATTER
+};
 
 }  // namespace
 
@@ -257,6 +268,21 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     g.nbins = int32_t(nbins64);
     g.CH = d->chunk ? d->chunk : 8192;
     {
+        // level-1 binning: coarse tiles of C x C tiles, the smallest C (a
+        // power of two) that leaves at most kMaxCoarse coarse bins
+        int C = 1;
+        while (C < g.nt && int64_t(g.Nw) * (g.nt / C) * (g.nt / C) > kMaxCoarse) C *= 2;
+        g.C = C;
+        g.log2C = ilog2(C);
+        g.nct = g.nt / C;
+        g.n1 = g.Nw * g.nct * g.nct;
+        g.CHK = 16 * C * C > 16384 ? 16 * C * C : 16384;
+        if (g.n1 > kMaxCoarse || int64_t(C) * C > 16384) {
+            delete p;
+            return fail(RICK_E_INVALID_ARG, "no coarse binning fits %d planes of %d x %d tiles", g.Nw, g.nt, g.nt);
+        }
+    }
+    {
         // LDS row pitch congruent to W mod 32 floats: a W x W footprint then
         // spreads over distinct banks (one tap per lane, see grid.hip)
         int pitch = g.T;
@@ -321,18 +347,26 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     p->mesh_bytes = size_t(g.Nw) * g.N * g.N * 2 * rb;
     const size_t sz_lut = size_t(g.OS) * g.W * rb;
     const size_t sz_tw = size_t(g.N) * 2 * rb;
-    const size_t sz_counts = size_t(kCopies) * (g.nbins + 1) * sizeof(int32_t);
+    const size_t sz_counts = size_t(g.nbins + 1) * sizeof(int32_t);
     const size_t sz_items = size_t(p->max_items + 1) * sizeof(int32_t);
     const size_t sz_heavy = size_t(p->rec_cap / (g.CH + 1) + 2) * sizeof(int32_t);
     const size_t sz_scan = size_t(g.nbins + 1) * sizeof(BinScan);
-    const size_t n_blk = (size_t(g.nbins) + 1 + 2047) / 2048 + 1;
-    const size_t sz_bsum = n_blk * 2 * sizeof(int32_t) + 64;
+    const size_t n_cnt1 = size_t(g.n1) * kL1Blocks + 1;
+    const size_t n_scanned = n_cnt1 > size_t(g.nbins) + 1 ? n_cnt1 : size_t(g.nbins) + 1;
+    const size_t sz_bsum = (n_scanned + 2047) / 2048 * 2 * sizeof(int32_t) + 64;
+    const size_t sz_cnt1 = n_cnt1 * sizeof(int32_t);
+    // level-1 records: a footprint touches at most four coarse bins
+    const size_t sz_pos1 = size_t(p->rec_cap) * sizeof(uint2);
+    const size_t sz_vis1 = size_t(p->rec_cap) * 2 * rb;
+    p->max_chunks = bin_max_chunks(g, p->rec_cap);
+    const size_t sz_kc0 = size_t(g.n1 + 1) * sizeof(int32_t);
+    const size_t sz_ckey = size_t(p->max_chunks) * sizeof(int32_t);
+    const size_t sz_cnt2 = size_t(p->max_chunks) * g.C * g.C * sizeof(int32_t);
     const size_t sz_pos = size_t(p->rec_cap) * sizeof(uint32_t);
     const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
     const size_t total = p->mesh_bytes + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
-                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_counts +
-                         sz_items + sz_heavy +
-                         sz_pos + sz_rvis;
+                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_pos1 +
+                         sz_vis1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) {
@@ -363,7 +397,12 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->counts, sz_counts);
     ALLOC(p->scan, sz_scan);
     ALLOC(p->block_sums, sz_bsum);
-    ALLOC(p->cursor, sz_counts);
+    ALLOC(p->cnt1, sz_cnt1);
+    ALLOC(p->pos1, sz_pos1);
+    ALLOC(p->vis1, sz_vis1);
+    ALLOC(p->key_chunk0, sz_kc0);
+    ALLOC(p->chunk_key, sz_ckey);
+    ALLOC(p->cnt2, sz_cnt2);
     ALLOC(p->item_bin, sz_items);
     ALLOC(p->heavy_bins, sz_heavy);
     ALLOC(p->rec_pos, sz_pos);
@@ -481,31 +520,29 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     const int64_t nvis = nrow * nchan;
     const int32_t max_items = int32_t(g.nbins + (4 * nvis + g.CH - 1) / g.CH);
 
-    timer_begin(p, T_COUNT, "bin_count", s);
-    e = launch_reset_counts(g, p->counts, p->stats, s);
-    if (e == hipSuccess) {
-        if (p->fp64)
-            e = launch_bin_count<double>(g, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
-                                         p->counts, p->stats, s);
+    const BinBufs bb{p->cnt1,     p->block_sums, p->pos1,   p->vis1,     p->key_chunk0, p->chunk_key, p->cnt2,
+                     p->counts,   p->scan,       p->item_bin, p->heavy_bins, p->rec_pos,  p->rec_vis};
+    struct Pass {
+        int slot;
+        const char *name;
+        int level, phase;
+    } passes[] = {
+        {T_COUNT, "bin_count", 1, 0},       {T_SCAN, "bin_scan", 1, 1},        {T_SCATTER, "bin_scatter", 1, 2},
+        {T_FINE_COUNT, "fine_count", 2, 0}, {T_FINE_SCAN, "fine_scan", 2, 1}, {T_FINE_SCATTER, "fine_scatter", 2, 2},
+    };
+    for (const Pass &ps : passes) {
+        timer_begin(p, ps.slot, ps.name, s);
+        if (ps.level == 1)
+            e = p->fp64 ? launch_bin_level1<double>(g, bb, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
+                                                    p->stats, ps.phase, s)
+                        : launch_bin_level1<float>(g, bb, uvw, p->scales, (const float *)vis, weight, nrow, nchan,
+                                                   p->stats, ps.phase, s);
         else
-            e = launch_bin_count<float>(g, uvw, p->scales, (const float *)vis, weight, nrow, nchan,
-                                        p->counts, p->stats, s);
+            e = p->fp64 ? launch_bin_level2<double>(g, bb, nrow, nchan, p->stats, ps.phase, s)
+                        : launch_bin_level2<float>(g, bb, nrow, nchan, p->stats, ps.phase, s);
+        timer_end(p, ps.slot, s);
+        if (e != hipSuccess) return hip_fail(e, ps.name);
     }
-    timer_end(p, T_COUNT, s);
-    if (e != hipSuccess) return hip_fail(e, "bin_count");
-    timer_begin(p, T_SCAN, "bin_scan", s);
-    e = launch_bin_scan(g, p->counts, p->scan, p->block_sums, p->cursor, p->item_bin, p->heavy_bins, p->stats, s);
-    timer_end(p, T_SCAN, s);
-    if (e != hipSuccess) return hip_fail(e, "bin_scan");
-    timer_begin(p, T_SCATTER, "bin_scatter", s);
-    if (p->fp64)
-        e = launch_bin_scatter<double>(g, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
-                                       p->cursor, p->rec_pos, (double *)p->rec_vis, s);
-    else
-        e = launch_bin_scatter<float>(g, uvw, p->scales, (const float *)vis, weight, nrow, nchan,
-                                      p->cursor, p->rec_pos, (float *)p->rec_vis, s);
-    timer_end(p, T_SCATTER, s);
-    if (e != hipSuccess) return hip_fail(e, "bin_scatter");
     if (!accumulate) {
         timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
         if (p->fp64) e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, (double *)p->mesh, s);

@@ -13,7 +13,9 @@ constexpr double kC0 = 299792458.0;      // speed of light, m/s
 constexpr int kMaxInlineChan = 32;       // channel scale factors per kernel-argument upload
 constexpr int kMaxChan = 1 << 16;        // capacity of the plan's channel scale buffer
 constexpr int kMaxTimers = 16;
-constexpr int kCopies = 16;              // privatised copies of the per-bin counters
+constexpr int kL1Blocks = 2048;          // blocks of the level-1 binning passes (at most)
+constexpr int kMaxCoarse = 8192;         // coarse bins of level-1 binning (LDS counters per block)
+constexpr int kMaxPlanes = 8192;         // w-planes per plan
 constexpr int kTimerRing = 64;         // launches per kernel whose times are kept between reads
 
 // A batch of channel scale factors nu_c / c0, passed by value.
@@ -35,6 +37,12 @@ struct Geom {
     int32_t nbins;      // Nw * nt * nt
     int32_t CH;         // records per gridding chunk
     int32_t pitch;      // LDS row pitch (floats) of the gridding tile
+    int32_t C;          // tiles per coarse-tile edge (level-1 binning)
+    int32_t log2C;
+    int32_t nct;        // coarse tiles per axis, nt / C
+    int32_t n1;         // coarse bins, Nw * nct * nct
+    int32_t CHK;        // level-1 records per level-2 chunk
+    int32_t pad0;
     double fov;
     double half;        // N * OS / 2
     double w_min;
@@ -48,7 +56,8 @@ struct Stats {
     unsigned long long n_records;   // records written by the last rick_grid
     unsigned long long n_heavy;     // bins of the last rick_grid split over several chunks
     double sum_w;
-    double pad2[3];
+    unsigned long long n_chunks;    // level-2 binning chunks of the last rick_grid
+    double pad2[2];
 };
 
 // Binning bookkeeping written by the scan: per bin, exclusive prefix sums of
@@ -62,23 +71,39 @@ struct BinScan {
 hipError_t launch_zero_stats(Stats *st, hipStream_t s);
 template <typename real>
 hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s);
-hipError_t launch_reset_counts(const Geom &g, int32_t *counts, Stats *st, hipStream_t s);
 
-// Pass 1 of bin-and-sort: per-bin record counts, drop counts and weight sum.
 // Channel scale factors nu_c / c0 into the plan's device buffer (kernel arguments, no copies).
 hipError_t launch_set_scales(double *dst, const double *host_scales, int32_t nchan, hipStream_t s);
+
+// Device buffers of the two-level bin-and-sort.
+struct BinBufs {
+    int32_t *cnt1;        // [n1 * kL1Blocks + 1] per (coarse bin, block) counts, scanned in place
+    int32_t *bsum;        // partial sums of the scans
+    uint2 *pos1;          // level-1 records: cell x | y << 16, sub-cell x | y << 8 | plane << 16
+    void *vis1;           // level-1 records: W V (2 reals)
+    int32_t *key_chunk0;  // [n1 + 1] first level-2 chunk of each coarse bin
+    int32_t *chunk_key;   // [max chunks] coarse bin of each level-2 chunk
+    int32_t *cnt2;        // [max chunks][C^2] per (chunk, tile) counts, then record offsets
+    int32_t *counts;      // [nbins] records per bin
+    BinScan *scan;        // [nbins + 1]
+    int32_t *item_bin;    // gridding work items
+    int32_t *heavy_bins;  // bins split over several gridding chunks
+    uint32_t *rec_pos;    // records: packed position in the tile
+    void *rec_vis;        // records: W V (2 reals)
+};
+// Upper bound of level-2 chunks for max_records level-1 records.
+int32_t bin_max_chunks(const Geom &g, int64_t max_records);
+// Level 1 of bin-and-sort.  phase 0: coarse counts, drop test, weight sum;
+// 1: scan of the count table and level-2 chunk list; 2: level-1 records.
 template <typename real>
-hipError_t launch_bin_count(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
-                            const float *weight, int64_t nrow, int32_t nchan, int32_t *counts, Stats *st,
-                            hipStream_t s);
-// Exclusive scan of counts into BinScan; per-copy cursors; gridding item list; heavy-bin list.
-hipError_t launch_bin_scan(const Geom &g, const int32_t *counts, BinScan *scan, int32_t *block_sums,
-                           int32_t *cursor, int32_t *item_bin, int32_t *heavy_bins, Stats *st, hipStream_t s);
-// Pass 2: scatter records {packed position, W V} into their bins.
+hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw, const double *scales_dev,
+                             const real *vis, const float *weight, int64_t nrow, int32_t nchan, Stats *st, int phase,
+                             hipStream_t s);
+// Level 2.  phase 0: per (chunk, tile) counts; 1: per-bin totals, scan in
+// bin order (gridding items, heavy bins), per (chunk, tile) offsets; 2: records.
 template <typename real>
-hipError_t launch_bin_scatter(const Geom &g, const double *uvw, const double *scales_dev, const real *vis,
-                              const float *weight, int64_t nrow, int32_t nchan, int32_t *cursor, uint32_t *rec_pos,
-                              real *rec_vis, hipStream_t s);
+hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int32_t nchan, Stats *st, int phase,
+                             hipStream_t s);
 // Gridding: zero heavy tiles, then one block per (bin, chunk) item.
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,

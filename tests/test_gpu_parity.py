@@ -136,6 +136,15 @@ def test_heavy_bins_split_over_chunks():
     check_stages(ds, gpu, oracle_of(ds))
 
 
+@pytest.mark.parametrize("grid_n,tile,n_wplanes", [(1024, 16, 8), (512, 16, 40)])
+def test_binning_with_coarse_tiles(grid_n, tile, n_wplanes):
+    """More (plane, tile) bins than one level of LDS counters holds: coarse
+    tiles of several tiles (1024/16: 2 x 2; 512/16 with 40 planes: 4 x 4),
+    with many footprints straddling coarse-tile edges."""
+    ds = synth.tiny(nrow=40000, seed=21, grid_n=grid_n, n_wplanes=n_wplanes, uv_radius=120.0 * grid_n / 256)
+    check_stages(ds, run_gpu(ds, tile=tile), oracle_of(ds))
+
+
 @pytest.mark.parametrize("tile,chunk", [(16, 512), (32, 2048)])
 def test_split_bins_at_other_tiles_and_chunks(tile, chunk):
     """bins split over several chunks at smaller tiles: partial tiles merged onto the mesh"""
