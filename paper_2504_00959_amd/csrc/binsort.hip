@@ -13,8 +13,8 @@
 //     bin_scan     exclusive scan of that table (coarse-bin major), then the
 //                  level-2 chunk list (each coarse bin cut into chunks).
 //     bin_scatter  repeats the quantisation; slots from LDS cursors seeded
-//                  with the block's scanned offsets; writes level-1 records
-//                  {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}.
+//                  with the block's scanned offsets; writes 16-byte level-1
+//                  records {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}.
 //   level 2  bins = (plane, tile) inside each coarse bin, at most C^2 = 16384.
 //     fine_count   one block per chunk: LDS histogram over the tiles of the
 //                  coarse tile that each record's footprint touches.
@@ -40,6 +40,14 @@ namespace rick {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kL1Block = 1024;   // threads of a level-1 block (one contiguous range of visibilities)
+
+// A level-1 record: cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V.
+template <typename real>
+struct Rec1 {
+    uint32_t cxy, sub;
+    real vr, vi;
+};
 
 __global__ void k_zero_stats(Stats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -182,22 +190,22 @@ struct L1Part {
 };
 
 template <typename real>
-__global__ __launch_bounds__(kBlock) void k_l1_count(Geom g, const double *__restrict__ uvw,
+__global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__restrict__ uvw,
                                                      const double *__restrict__ scales, const real *__restrict__ vis,
                                                      const float *__restrict__ weight, int64_t nvis, int32_t nchan,
                                                      L1Part part, int32_t *__restrict__ cnt1, Stats *__restrict__ st) {
     extern __shared__ int32_t s_cnt[];   // g.n1 counters
-    __shared__ double s_w[kBlock / 64];
-    __shared__ unsigned long long s_kept[kBlock / 64], s_drop[kBlock / 64];
-    for (int i = threadIdx.x; i < g.n1; i += kBlock) s_cnt[i] = 0;
+    __shared__ double s_w[kL1Block / 64];
+    __shared__ unsigned long long s_kept[kL1Block / 64], s_drop[kL1Block / 64];
+    for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cnt[i] = 0;
     __syncthreads();
     const int64_t v0 = (int64_t)blockIdx.x * part.per;
     const int64_t v1 = v0 + part.per < nvis ? v0 + part.per : nvis;
     const int32_t cshift = g.log2T + g.log2C;
     double sum_w = 0.0;
     unsigned long long kept = 0, dropped = 0;
-    VisWalk vw((uint32_t)(v0 + threadIdx.x), kBlock, (uint32_t)nchan);
-    for (int32_t it = 0; it < part.per / kBlock; ++it, vw.next((uint32_t)nchan)) {
+    VisWalk vw((uint32_t)(v0 + threadIdx.x), kL1Block, (uint32_t)nchan);
+    for (int32_t it = 0; it < part.per / kL1Block; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
         if ((int64_t)vw.i < v1) {
@@ -238,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_l1_count(Geom g, const double *__res
     if (threadIdx.x == 0) {
         double tw = 0.0;
         unsigned long long tk = 0, td = 0;
-        for (int k = 0; k < kBlock / 64; ++k) {
+        for (int k = 0; k < kL1Block / 64; ++k) {
             tw += s_w[k];
             tk += s_kept[k];
             td += s_drop[k];
@@ -250,24 +258,24 @@ __global__ __launch_bounds__(kBlock) void k_l1_count(Geom g, const double *__res
         if (td) atomicAdd(&st->n_dropped, td);
     }
     // this block's column of the (coarse bin, block) table
-    for (int i = threadIdx.x; i < g.n1; i += kBlock) cnt1[(int64_t)i * part.nb1 + blockIdx.x] = s_cnt[i];
+    for (int i = threadIdx.x; i < g.n1; i += kL1Block) cnt1[(int64_t)i * part.nb1 + blockIdx.x] = s_cnt[i];
 }
 
 template <typename real>
-__global__ __launch_bounds__(kBlock) void k_l1_scatter(Geom g, const double *__restrict__ uvw,
-                                                       const double *__restrict__ scales,
-                                                       const real *__restrict__ vis, const float *__restrict__ weight,
-                                                       int64_t nvis, int32_t nchan, L1Part part,
-                                                       const int32_t *__restrict__ base1, uint2 *__restrict__ pos1,
-                                                       real *__restrict__ vis1) {
+__global__ __launch_bounds__(kL1Block) void k_l1_scatter(Geom g, const double *__restrict__ uvw,
+                                                         const double *__restrict__ scales,
+                                                         const real *__restrict__ vis, const float *__restrict__ weight,
+                                                         int64_t nvis, int32_t nchan, L1Part part,
+                                                         const int32_t *__restrict__ base1,
+                                                         Rec1<real> *__restrict__ rec1) {
     extern __shared__ int32_t s_cur[];   // g.n1 cursors
-    for (int i = threadIdx.x; i < g.n1; i += kBlock) s_cur[i] = base1[(int64_t)i * part.nb1 + blockIdx.x];
+    for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cur[i] = base1[(int64_t)i * part.nb1 + blockIdx.x];
     __syncthreads();
     const int64_t v0 = (int64_t)blockIdx.x * part.per;
     const int64_t v1 = v0 + part.per < nvis ? v0 + part.per : nvis;
     const int32_t cshift = g.log2T + g.log2C;
-    VisWalk vw((uint32_t)(v0 + threadIdx.x), kBlock, (uint32_t)nchan);
-    for (int32_t it = 0; it < part.per / kBlock; ++it, vw.next((uint32_t)nchan)) {
+    VisWalk vw((uint32_t)(v0 + threadIdx.x), kL1Block, (uint32_t)nchan);
+    for (int32_t it = 0; it < part.per / kL1Block; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
         real ar = 0, ai = 0;
@@ -291,16 +299,14 @@ __global__ __launch_bounds__(kBlock) void k_l1_scatter(Geom g, const double *__r
                 if (in_span(cs.dx, cs.dy, j)) b4[j] = atomicAdd(&s_cur[base + (j & 1) + (j >> 1) * g.nct], run.len);
         }
         const int32_t rank = (int32_t)__lane_id() - run.leader;
-        const uint2 p1 = make_uint2((uint32_t)q.cx | (uint32_t)q.cy << 16,
-                                    (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
-                                        (uint32_t)q.k << 16);
+        const Rec1<real> r1{(uint32_t)q.cx | (uint32_t)q.cy << 16,
+                            (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
+                                (uint32_t)q.k << 16,
+                            ar, ai};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int32_t slot = __shfl(b4[j], run.leader) + rank;
-            if (keep && in_span(cs.dx, cs.dy, j)) {
-                pos1[slot] = p1;
-                store2(vis1 + 2 * (int64_t)slot, ar, ai);
-            }
+            if (keep && in_span(cs.dx, cs.dy, j)) rec1[slot] = r1;
         }
     }
 }
@@ -457,8 +463,8 @@ __device__ __forceinline__ Local local_span(const Geom &g, uint32_t cxy, int32_t
 __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                      const int32_t *__restrict__ key_chunk0,
                                                      const int32_t *__restrict__ chunk_key,
-                                                     const Stats *__restrict__ st, const uint2 *__restrict__ pos1,
-                                                     int32_t *__restrict__ cnt2) {
+                                                     const Stats *__restrict__ st, const uint32_t *__restrict__ rec1,
+                                                     int32_t rec1_words, int32_t *__restrict__ cnt2) {
     extern __shared__ int32_t s_h[];   // C^2 counters
     const int32_t chunk = blockIdx.x;
     if (chunk >= (int32_t)st->n_chunks) return;
@@ -470,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__re
         const int32_t r = r00 + threadIdx.x;
         const bool valid = r < ck.r1;
         Local ls{0, 0, 0, 0};
-        if (valid) ls = local_span(g, pos1[r].x, ck.ctx, ck.cty);
+        if (valid) ls = local_span(g, rec1[(int64_t)r * rec1_words], ck.ctx, ck.cty);
         const Run run = runs_of(valid ? ((ls.fy0 * g.C + ls.fx0) * 2 + ls.dfx) * 2 + ls.dfy : -1);
         if (valid && run.head) {
 #pragma unroll
@@ -525,8 +531,8 @@ template <typename real>
 __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                        const int32_t *__restrict__ key_chunk0,
                                                        const int32_t *__restrict__ chunk_key,
-                                                       const Stats *__restrict__ st, const uint2 *__restrict__ pos1,
-                                                       const real *__restrict__ vis1,
+                                                       const Stats *__restrict__ st,
+                                                       const Rec1<real> *__restrict__ rec1,
                                                        const int32_t *__restrict__ base2,
                                                        uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
     extern __shared__ int32_t s_cur[];   // C^2 cursors
@@ -541,13 +547,10 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
         const int32_t r = r00 + threadIdx.x;
         const bool valid = r < ck.r1;
         Local ls{0, 0, 0, 0};
-        uint2 p = make_uint2(0u, 0u);
-        real vr = 0, vi = 0;
+        Rec1<real> p{0u, 0u, 0, 0};
         if (valid) {
-            p = pos1[r];
-            vr = vis1[2 * (int64_t)r];
-            vi = vis1[2 * (int64_t)r + 1];
-            ls = local_span(g, p.x, ck.ctx, ck.cty);
+            p = rec1[r];
+            ls = local_span(g, p.cxy, ck.ctx, ck.cty);
         }
         const Run run = runs_of(valid ? ((ls.fy0 * g.C + ls.fx0) * 2 + ls.dfx) * 2 + ls.dfy : -1);
         int32_t b4[4] = {0, 0, 0, 0};
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
                     b4[j] = atomicAdd(&s_cur[(ls.fy0 + (j >> 1)) * g.C + ls.fx0 + (j & 1)], run.len);
         }
         const int32_t rank = (int32_t)__lane_id() - run.leader;
-        const int32_t cx = (int32_t)(p.x & 0xffffu), cy = (int32_t)(p.x >> 16);
+        const int32_t cx = (int32_t)(p.cxy & 0xffffu), cy = (int32_t)(p.cxy >> 16);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int32_t slot = __shfl(b4[j], run.leader) + rank;
@@ -566,8 +569,8 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
                 const int32_t tx = tx_lo + ls.fx0 + (j & 1), ty = ty_lo + ls.fy0 + (j >> 1);
                 const int32_t ox = cx - g.h - (tx << g.log2T) + 2 * g.h;   // in [0, T + 2h)
                 const int32_t oy = cy - g.h - (ty << g.log2T) + 2 * g.h;
-                rec_pos[slot] = (uint32_t)ox | (uint32_t)oy << 8 | (p.y & 0xffffu) << 16;
-                store2(rec_vis + 2 * (int64_t)slot, vr, vi);
+                rec_pos[slot] = (uint32_t)ox | (uint32_t)oy << 8 | (p.sub & 0xffffu) << 16;
+                store2(rec_vis + 2 * (int64_t)slot, p.vr, p.vi);
             }
         }
     }
@@ -666,12 +669,12 @@ hipError_t launch_set_scales(double *dst, const double *host_scales, int32_t nch
 
 // level-1 partition of nvis visibilities over at most kL1Blocks blocks
 static L1Part l1_part(int64_t nvis) {
-    int64_t nb = (nvis + kBlock - 1) / kBlock;
+    int64_t nb = (nvis + kL1Block - 1) / kL1Block;
     if (nb < 1) nb = 1;
     if (nb > kL1Blocks) nb = kL1Blocks;
     int64_t per = (nvis + nb - 1) / nb;
-    per = (per + kBlock - 1) / kBlock * kBlock;
-    if (per < kBlock) per = kBlock;
+    per = (per + kL1Block - 1) / kL1Block * kL1Block;
+    if (per < kL1Block) per = kL1Block;
     nb = (nvis + per - 1) / per;
     if (nb < 1) nb = 1;
     return L1Part{(int32_t)nb, (int32_t)per};
@@ -689,8 +692,8 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
     const L1Part part = l1_part(nvis);
     const size_t lds = size_t(g.n1) * sizeof(int32_t);
     if (phase == 0) {
-        hipLaunchKernelGGL(k_l1_count<real>, dim3(part.nb1), dim3(kBlock), lds, s, g, uvw, scales_dev, vis, weight,
-                           nvis, nchan, part, bb.cnt1, st);
+        hipLaunchKernelGGL(k_l1_count<real>, dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev, vis,
+                           weight, nvis, nchan, part, bb.cnt1, st);
     } else if (phase == 1) {
         const int64_t n = (int64_t)g.n1 * part.nb1;
         const int32_t nblk = (int32_t)((n + 1 + kScanTile - 1) / kScanTile);
@@ -700,8 +703,8 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
         hipLaunchKernelGGL(k_l2_chunks, dim3(1), dim3(kScanBlock), 0, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
                            bb.chunk_key, st);
     } else {
-        hipLaunchKernelGGL(k_l1_scatter<real>, dim3(part.nb1), dim3(kBlock), lds, s, g, uvw, scales_dev, vis,
-                           weight, nvis, nchan, part, bb.cnt1, bb.pos1, (real *)bb.vis1);
+        hipLaunchKernelGGL(k_l1_scatter<real>, dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev, vis,
+                           weight, nvis, nchan, part, bb.cnt1, (Rec1<real> *)bb.rec1);
     }
     return hipGetLastError();
 }
@@ -717,7 +720,7 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
     const int32_t nbb = (g.nbins + kBlock - 1) / kBlock;
     if (phase == 0) {
         hipLaunchKernelGGL(k_l2_count, dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
-                           bb.chunk_key, st, bb.pos1, bb.cnt2);
+                           bb.chunk_key, st, (const uint32_t *)bb.rec1, (int32_t)(sizeof(Rec1<real>) / 4), bb.cnt2);
     } else if (phase == 1) {
         hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.counts);
         const int32_t n = g.nbins;
@@ -729,7 +732,7 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
         hipLaunchKernelGGL(k_l2_bases, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.scan, bb.cnt2);
     } else {
         hipLaunchKernelGGL(k_l2_scatter<real>, dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
-                           bb.key_chunk0, bb.chunk_key, st, bb.pos1, (const real *)bb.vis1, bb.cnt2, bb.rec_pos,
+                           bb.key_chunk0, bb.chunk_key, st, (const Rec1<real> *)bb.rec1, bb.cnt2, bb.rec_pos,
                            (real *)bb.rec_vis);
     }
     return hipGetLastError();

@@ -102,8 +102,7 @@ struct rick_plan_s {
     BinScan *scan = nullptr;
     int32_t *block_sums = nullptr;
     int32_t *cnt1 = nullptr;
-    uint2 *pos1 = nullptr;
-    void *vis1 = nullptr;
+    void *rec1 = nullptr;
     int32_t *key_chunk0 = nullptr;
     int32_t *chunk_key = nullptr;
     int32_t *cnt2 = nullptr;
@@ -141,8 +140,8 @@ struct DeviceGuard {
 
 void free_all(rick_plan_t *p) {
     void *bufs[] = {p->mesh,      p->lut,        p->twiddle,   p->corr,   p->wk,       p->scales,
-                    p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->pos1,
-                    p->vis1,      p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
+                    p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
+                    p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
                     p->rec_pos,   p->rec_vis};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -356,8 +355,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_bsum = (n_scanned + 2047) / 2048 * 2 * sizeof(int32_t) + 64;
     const size_t sz_cnt1 = n_cnt1 * sizeof(int32_t);
     // level-1 records: a footprint touches at most four coarse bins
-    const size_t sz_pos1 = size_t(p->rec_cap) * sizeof(uint2);
-    const size_t sz_vis1 = size_t(p->rec_cap) * 2 * rb;
+    const size_t sz_rec1 = size_t(p->rec_cap) * (8 + 2 * rb);
     p->max_chunks = bin_max_chunks(g, p->rec_cap);
     const size_t sz_kc0 = size_t(g.n1 + 1) * sizeof(int32_t);
     const size_t sz_ckey = size_t(p->max_chunks) * sizeof(int32_t);
@@ -365,8 +363,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_pos = size_t(p->rec_cap) * sizeof(uint32_t);
     const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
     const size_t total = p->mesh_bytes + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
-                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_pos1 +
-                         sz_vis1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis;
+                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) {
@@ -398,8 +395,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->scan, sz_scan);
     ALLOC(p->block_sums, sz_bsum);
     ALLOC(p->cnt1, sz_cnt1);
-    ALLOC(p->pos1, sz_pos1);
-    ALLOC(p->vis1, sz_vis1);
+    ALLOC(p->rec1, sz_rec1);
     ALLOC(p->key_chunk0, sz_kc0);
     ALLOC(p->chunk_key, sz_ckey);
     ALLOC(p->cnt2, sz_cnt2);
@@ -520,7 +516,7 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     const int64_t nvis = nrow * nchan;
     const int32_t max_items = int32_t(g.nbins + (4 * nvis + g.CH - 1) / g.CH);
 
-    const BinBufs bb{p->cnt1,     p->block_sums, p->pos1,   p->vis1,     p->key_chunk0, p->chunk_key, p->cnt2,
+    const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2,
                      p->counts,   p->scan,       p->item_bin, p->heavy_bins, p->rec_pos,  p->rec_vis};
     struct Pass {
         int slot;

@@ -13,7 +13,7 @@ constexpr double kC0 = 299792458.0;      // speed of light, m/s
 constexpr int kMaxInlineChan = 32;       // channel scale factors per kernel-argument upload
 constexpr int kMaxChan = 1 << 16;        // capacity of the plan's channel scale buffer
 constexpr int kMaxTimers = 16;
-constexpr int kL1Blocks = 2048;          // blocks of the level-1 binning passes (at most)
+constexpr int kL1Blocks = 512;           // blocks of the level-1 binning passes (at most)
 constexpr int kMaxCoarse = 8192;         // coarse bins of level-1 binning (LDS counters per block)
 constexpr int kMaxPlanes = 8192;         // w-planes per plan
 constexpr int kTimerRing = 64;         // launches per kernel whose times are kept between reads
@@ -79,8 +79,7 @@ hipError_t launch_set_scales(double *dst, const double *host_scales, int32_t nch
 struct BinBufs {
     int32_t *cnt1;        // [n1 * kL1Blocks + 1] per (coarse bin, block) counts, scanned in place
     int32_t *bsum;        // partial sums of the scans
-    uint2 *pos1;          // level-1 records: cell x | y << 16, sub-cell x | y << 8 | plane << 16
-    void *vis1;           // level-1 records: W V (2 reals)
+    void *rec1;           // level-1 records {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}
     int32_t *key_chunk0;  // [n1 + 1] first level-2 chunk of each coarse bin
     int32_t *chunk_key;   // [max chunks] coarse bin of each level-2 chunk
     int32_t *cnt2;        // [max chunks][C^2] per (chunk, tile) counts, then record offsets
