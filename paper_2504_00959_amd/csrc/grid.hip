@@ -149,26 +149,18 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
 
     const int lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // Per-lane tap constants.  A tap at footprint offset (tx, ty) of a record
-    // with origin (ox, oy) lies in the tile when both ox + tx and oy + ty are
-    // in [0, T).  Origins are biased by 2^14 and packed as two 16-bit halves,
-    // so one add gives both coordinates (no carry crosses the halves), and for
-    // a power-of-two T a coordinate c + 2^14 is in range exactly when its half
-    // masked by ~(T - 1) equals 2^14.  Lanes without a tap carry 2^15 in the
-    // low half, which never passes.
-    int tap_txy[NG], tap_off8[NG], lut_x[NG], lut_y[NG];
+    // Per-lane tap constants: LDS byte offset of the tap from the footprint
+    // origin, and the byte addresses of its tap-table columns.
+    int tap_off8[NG], lut_x[NG], lut_y[NG];
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
         const int t = lane + 64 * gi;
         const bool on = t < W2;
         const int ty = on ? t / W : 0, tx = on ? t - (t / W) * W : 0;
-        tap_txy[gi] = on ? (tx | ty << 16) : 0x8000;
         tap_off8[gi] = (ty * P + tx) * (int)sizeof(double);
         lut_x[gi] = lut_byte + tx * (int)sizeof(real);
         lut_y[gi] = lut_byte + ty * (int)sizeof(real);
     }
-    const uint32_t inmask = (0xffffu & ~(uint32_t)(T - 1)) * 0x10001u;
-    constexpr uint32_t inval = 0x40004000u;
 
     // this wave's batches of 64 records, one record per lane; the next
     // batch's raw fields are loaded while the current one is gridded
@@ -189,18 +181,36 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
         const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
         // decode this lane's record: byte offset of the footprint origin in
         // the real plane (negative for origins left of or above the tile),
-        // packed biased origin, tap-table row byte offsets, visibility
-        int32_t d_base8 = 0, d_oxy = 0x8000, d_lxy = 0;
+        // tap-table row byte offsets, visibility, and the mask of its taps
+        // that fall inside the tile (bit t of group t / 64 for tap t =
+        // ty W + tx: the rectangle of tx, ty with ox + tx, oy + ty in [0, T))
+        int32_t d_base8 = 0, d_lxy = 0;
         real d_vr = 0, d_vi = 0;
+        uint64_t d_mask[NG];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) d_mask[gi] = 0;
         if (lane < cnt) {
             const int ox = (int)(raw_pos & 0xffu) - 2 * H;
             const int oy = (int)((raw_pos >> 8) & 0xffu) - 2 * H;
             const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
             d_base8 = (oy * P + ox) * (int)sizeof(double);
-            d_oxy = (ox + 0x4000) | (oy + 0x4000) << 16;
             d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
             d_vr = raw_vr;
             d_vi = raw_vi;
+            const int tx_lo = ox < 0 ? -ox : 0, tx_hi = T - 1 - ox < W - 1 ? T - 1 - ox : W - 1;
+            const int ty_lo = oy < 0 ? -oy : 0, ty_hi = T - 1 - oy < W - 1 ? T - 1 - oy : W - 1;
+            const uint64_t row = ((2ull << tx_hi) - 1) & ~((1ull << tx_lo) - 1);
+#pragma unroll
+            for (int ty = 0; ty < W; ++ty) {
+                if (ty >= ty_lo && ty <= ty_hi) {
+#pragma unroll
+                    for (int gi = 0; gi < NG; ++gi) {
+                        const int rel = ty * W - 64 * gi;   // bit of the row's first tap in group gi
+                        if (rel >= 0 && rel < 64) d_mask[gi] |= row << rel;
+                        else if (rel < 0 && rel > -W) d_mask[gi] |= row >> (-rel);
+                    }
+                }
+            }
         }
         if (bt + nwave < nbatch) fetch(bt + nwave);
 
@@ -223,16 +233,19 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 const int32_t base8 = bcast(d_base8, (j + q) & 63);
-                const uint32_t oxy = (uint32_t)bcast(d_oxy, (j + q) & 63);
                 const real vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
+                    const uint64_t m = (uint64_t)(uint32_t)bcast((int32_t)(d_mask[gi] >> 32), (j + q) & 63) << 32 |
+                                       (uint32_t)bcast((int32_t)d_mask[gi], (j + q) & 63);
                     // the products are formed outside the branch, so the wait
                     // for the table values is the same on every path
                     const real wgt = gy[q][gi] * gx[q][gi];
                     double tr = (double)(wgt * vr), ti = (double)(wgt * vi);
                     __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
-                    if (((oxy + (uint32_t)tap_txy[gi]) & inmask) == inval) {
+                    // lanes whose tap of this record lies in the tile (the mask
+                    // is wave-uniform and becomes the execution mask directly)
+                    if (__builtin_amdgcn_inverse_ballot_w64(m)) {
                         double *a = reinterpret_cast<double *>(smem + (base8 + tap_off8[gi]));
                         atomicAdd(a, tr);
                         atomicAdd(a + KOFF, ti);
