@@ -50,9 +50,9 @@ def algorithmic_bytes(name, ds, info):
     return table.get(name)
 
 
-def cpu_baseline(ds, vis_host, n_rows_sample=1_048_576, n_grid_target=2_000_000, n_planes_fft=2):
+def cpu_baseline(ds, vis_host, n_rows_sample=4_194_304, n_grid_target=8_000_000, n_planes_fft=4):
     """The float64 oracle, as it stands, timed stage by stage on a bounded sample
-    of the same workload (about 15 s of one host core) and scaled to the whole job:
+    of the same workload (10-30 s of one host core) and scaled to the whole job:
       T = t_bin / n_binned * N_vis + t_grid / n_gridded * N_kept + N_w * (t_fft + t_screen) / n_planes."""
     import oracle
     from oracle import wstack as ow
