@@ -69,9 +69,10 @@ enum {
 
 enum {
     RICK_FLAG_TIMING = 1,       /* record per-kernel HIP events; read them with rick_plan_info */
-    RICK_FLAG_FUSED_SCREEN = 2  /* rick_fft_planes transforms rows only; rick_wstack_image transforms the
-                                   columns plane by plane and screens and sums them in the same pass, so
-                                   F_k is never written to HBM (the mesh then holds the row transforms) */
+    RICK_FLAG_FUSED_SCREEN = 2  /* rick_fft_planes transforms rows only, into a second buffer (row_mesh,
+                                   in column-panel order); rick_wstack_image transforms the columns plane by
+                                   plane and screens and sums them in the same pass, so F_k is never
+                                   written to HBM.  The mesh keeps G_k.  Needs a second mesh-sized buffer. */
 };
 
 /* Plan parameters (Sec. 2.1: mesh N_u x N_v x N_w, kernel type and support). */
@@ -108,8 +109,14 @@ typedef struct rick_plan_info_t {
     double sum_weights;      /* sum of the weights of gridded visibilities since the last reset */
     double du, dl, dw;       /* cell size [wavelengths], pixel size [rad], plane width [wavelengths] */
     void *mesh;              /* device pointer to the planes, [N_w][N][N] complex64 (complex128 in FP64
-                                mode), interleaved (re, im): G_k after rick_grid, F_k after rick_fft_planes */
+                                mode), interleaved (re, im): G_k after rick_grid, F_k after rick_fft_planes
+                                (with RICK_FLAG_FUSED_SCREEN it keeps G_k) */
     int64_t mesh_bytes;
+    void *row_mesh;          /* with RICK_FLAG_FUSED_SCREEN (else NULL): the row transforms H_k written by
+                                rick_fft_planes, mesh_bytes long, in column-panel order: element (plane k,
+                                row q, column p) at k N^2 + (p / panel) N panel + q panel + p % panel */
+    int32_t panel;           /* columns per panel of row_mesh (0 without RICK_FLAG_FUSED_SCREEN) */
+    int32_t pad0;
     int32_t tile, chunk;     /* effective tile edge and chunk size */
     int32_t state;           /* 0 = empty, 1 = gridded, 2 = transformed */
     int32_t n_timers;        /* number of valid entries in kernel_ms / kernel_calls / kernel_names */
@@ -157,7 +164,9 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
  * (the FFT step of Sec. 2.1):
  *   F_k[q][p] = sum_{j,i} G_k[j][i] exp(+2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
  * (unnormalised).  With RICK_FLAG_FUSED_SCREEN only the sum over i (the row
- * transform) is done here and the sum over j happens in rick_wstack_image.  Requires a gridded mesh (RICK_E_STATE otherwise; a mesh
+ * transform) is done here, into row_mesh (see rick_plan_info_t; the mesh
+ * keeps G_k), and the sum over j happens in rick_wstack_image.  Requires a
+ * gridded mesh (RICK_E_STATE otherwise; a mesh
  * that nothing was gridded onto since the reset is transformed as zeros).
  * Errors: RICK_E_BAD_PLAN, RICK_E_STATE, RICK_E_HIP.
  */

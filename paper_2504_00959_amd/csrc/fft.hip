@@ -241,6 +241,63 @@ __device__ __forceinline__ int out_elem(int tb, int q) {
     return tb + q * Shape<N>::NT;
 }
 
+// XCD-aware order: blocks are dealt to the 8 XCDs round-robin; blocks that
+// share an XCD get adjacent strips, so their row segments share L2 lines.
+__device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t nblk) {
+    return (nblk & 7) == 0 ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+}
+
+// ---- rows into column panels (for the fused column pass) ----
+// The output goes to a separate buffer in column-panel order: panels of PW
+// adjacent columns, each panel stored row after row, element (plane k, row q,
+// column p) at k N^2 + (p / PW) N PW + q PW + p % PW, so that the column pass
+// reads a strip as RB-row runs of whole cache lines.  A block transforms RB
+// consecutive rows (PW RB complex values = one 128-byte line per panel),
+// stages them in LDS, and writes each panel's RB x PW values as one line;
+// blocks are taken in an XCD-aware order.
+template <typename real, int N, int RB, int PW>
+__global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(const real *__restrict__ in,
+                                                                  real *__restrict__ out,
+                                                                  const real *__restrict__ twr) {
+    using C = typename R2T<real>::t;
+    using SH = Shape<N>;
+    constexpr int NT = SH::NT;
+    constexpr int CE = 16 / (int)sizeof(C);          // complex values per 16-byte chunk
+    constexpr int CPP = RB * PW / CE;                // chunks per panel line
+    extern __shared__ __align__(16) unsigned char smem[];
+    const C *tw = reinterpret_cast<const C *>(twr);
+    const int rb = threadIdx.x / NT, tb = threadIdx.x % NT;
+    const int64_t blk = xcd_order(blockIdx.x, gridDim.x);
+    const int64_t row0 = blk * RB;                   // RB divides N
+    C *buf = reinterpret_cast<C *>(smem) + rb * SH::PADN;
+    const C *gi = reinterpret_cast<const C *>(in) + (row0 + rb) * N;
+    C x[16][1];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = in_elem<N>(tb, i);
+        x[i][0] = cneg_if(gi[e], e & 1);
+    }
+    fft_regs<N, 1, 1>(x, buf, tb, 0, tw);
+    __syncthreads();   // every thread has read the last exchange
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = out_elem<N>(tb, q);
+        buf[padi(e)] = cneg_if(x[q][0], e & 1);
+    }
+    __syncthreads();
+    const int64_t k = row0 / N, r0 = row0 % N;
+    C *go = reinterpret_cast<C *>(out) + k * N * N + r0 * PW;
+    const C *stage = reinterpret_cast<const C *>(smem);
+    for (int c = threadIdx.x; c < N / PW * CPP; c += RB * NT) {
+        const int pnl = c / CPP, part = c % CPP;
+        const int r = (part * CE) / PW, col = pnl * PW + (part * CE) % PW;
+        const C *src = stage + r * SH::PADN + padi(col);   // CE values, contiguous (col even when CE = 2)
+        C *dst = go + (int64_t)pnl * N * PW + r * PW + (part * CE) % PW;
+#pragma unroll
+        for (int j = 0; j < CE; ++j) dst[j] = src[j];
+    }
+}
+
 // ---- rows: B rows per block, NT threads per row ----
 template <typename real, int N, int B>
 __global__ __launch_bounds__((N / 16) * B) void k_fft_rows(real *__restrict__ mesh, const real *__restrict__ twr) {
@@ -264,12 +321,6 @@ __global__ __launch_bounds__((N / 16) * B) void k_fft_rows(real *__restrict__ me
         const int e = out_elem<N>(tb, q);
         g[e] = cneg_if(x[q][0], e & 1);
     }
-}
-
-// XCD-aware order: blocks are dealt to the 8 XCDs round-robin; blocks that
-// share an XCD get adjacent strips, so their row segments share L2 lines.
-__device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t nblk) {
-    return (nblk & 7) == 0 ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
 }
 
 // ---- columns: one block per (plane, strip of V columns) ----
@@ -342,7 +393,7 @@ __device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
 // transformed planes are never written back, and the image is written once.
 // n - 1 of the strip's pixels is kept in LDS in float64; the phase
 // 2 w_k (n - 1) is formed in float64 half turns.
-template <typename real, int N, int V, int VC, bool KAHAN>
+template <typename real, int N, int V, int VC, int PW, bool KAHAN>
 __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
                                                                          const real *__restrict__ twr,
                                                                          const double *__restrict__ wk,
@@ -359,7 +410,9 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
     const int strip = (int)xcd_order(blockIdx.x, NSTRIP);
     const int c0 = strip * V;
     const int vg = threadIdx.x % (V / VC), tb = threadIdx.x / (V / VC), v0 = vg * VC;
-    const C *gbase = reinterpret_cast<const C *>(mesh) + c0 + v0;
+    // the row transforms in column-panel order: row e of column c at
+    // (c / PW) N PW + e PW + c % PW (the strip lies inside one panel)
+    const C *gbase = reinterpret_cast<const C *>(mesh) + (int64_t)(c0 / PW) * N * PW + c0 % PW + v0;
     const int64_t plane_stride = (int64_t)N * N;
     const double dl = g.fov / N;
     // owned pixels: rows out_elem(tb, q), columns c0 + v0 + v
@@ -382,7 +435,7 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         for (int v = 0; v < VC; ++v) {
             acc[i][v] = 0;
             comp[i][v] = 0;
-            pre[i][v] = gbase[(int64_t)e * N + v];
+            pre[i][v] = gbase[(int64_t)e * PW + v];
         }
     }
     for (int k = 0; k < g.Nw; ++k) {
@@ -399,7 +452,7 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
             for (int i = 0; i < 16; ++i) {
                 const int e = in_elem<N>(tb, i);
 #pragma unroll
-                for (int v = 0; v < VC; ++v) pre[i][v] = gk[(int64_t)e * N + v];
+                for (int v = 0; v < VC; ++v) pre[i][v] = gk[(int64_t)e * PW + v];
             }
         }
         // the LDS strip is reused plane after plane: every thread must have
@@ -486,25 +539,57 @@ hipError_t cols_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Column panels of the fused path: PW columns by RB rows make one 128-byte
+// line (RB <= 4 and at most 1024 threads per row block); PW >= V.
+template <typename real, int N>
+struct PanelShape {
+    static constexpr int L = 128 / (2 * (int)sizeof(real));   // complex values per 128-byte line
+    static constexpr int NT = N / 16;
+    static constexpr int RBT = 1024 / NT < 4 ? (1024 / NT < 1 ? 1 : 1024 / NT) : 4;          // threads
+    static constexpr int RBL = (160 * 1024) / (Shape<N>::PADN * 2 * (int)sizeof(real));      // LDS
+    static constexpr int RBMAX = RBT < RBL ? RBT : (RBL < 1 ? 1 : RBL);
+    static constexpr int PW0 = L / RBMAX > 0 ? L / RBMAX : 1;
+    static constexpr int PW = PW0 > ColShape<real, N>::V ? PW0 : ColShape<real, N>::V;
+    static constexpr int RB = L / PW > 0 ? (L / PW < RBMAX ? L / PW : RBMAX) : 1;
+};
+
+template <typename real, int N>
+hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw, hipStream_t s) {
+    using C = typename R2T<real>::t;
+    using PS = PanelShape<real, N>;
+    const int64_t nrows = (int64_t)g.Nw * N;
+    const size_t lds = size_t(PS::RB) * Shape<N>::PADN * sizeof(C);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_fft_rows_panel<real, N, PS::RB, PS::PW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_fft_rows_panel<real, N, PS::RB, PS::PW>), dim3((unsigned)(nrows / PS::RB)),
+                       dim3(PS::NT * PS::RB), lds, s, in, out, tw);
+    return hipGetLastError();
+}
+
 template <typename real, int N>
 hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const double *wk, const double *corr,
                          const Stats *st, real *image, int kahan, hipStream_t s) {
     using CS = ColShape<real, N>;
+    constexpr int PW = PanelShape<real, N>::PW;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, false>,
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, true>,
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
     if (kahan)
-        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, true>), dim3(N / CS::V), dim3(CS::THREADS), lds,
-                           s, g, mesh, tw, wk, corr, st, image);
-    else
-        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, false>), dim3(N / CS::V), dim3(CS::THREADS),
+        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>), dim3(N / CS::V), dim3(CS::THREADS),
                            lds, s, g, mesh, tw, wk, corr, st, image);
+    else
+        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>), dim3(N / CS::V),
+                           dim3(CS::THREADS), lds, s, g, mesh, tw, wk, corr, st, image);
     return hipGetLastError();
 }
 
@@ -524,6 +609,27 @@ hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *tw, hipStream_
     switch (g.N) {
 #define CASE(n) \
     case n: return rows_n<real, n>(g, mesh, tw, s);
+        CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int fused_panel_width(int N, size_t real_bytes) {
+    switch (N) {
+#define CASE(n) \
+    case n: return real_bytes == 8 ? PanelShape<double, n>::PW : PanelShape<float, n>::PW;
+        CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
+#undef CASE
+        default: return 0;
+    }
+}
+
+template <typename real>
+hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *tw, hipStream_t s) {
+    switch (g.N) {
+#define CASE(n) \
+    case n: return rows_panel_n<real, n>(g, in, out, tw, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -555,6 +661,9 @@ hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *t
 
 template hipError_t launch_fft_rows<float>(const Geom &, float *, const float *, hipStream_t);
 template hipError_t launch_fft_rows<double>(const Geom &, double *, const double *, hipStream_t);
+template hipError_t launch_fft_rows_panel<float>(const Geom &, const float *, float *, const float *, hipStream_t);
+template hipError_t launch_fft_rows_panel<double>(const Geom &, const double *, double *, const double *,
+                                                  hipStream_t);
 template hipError_t launch_fft_cols<float>(const Geom &, float *, const float *, hipStream_t);
 template hipError_t launch_fft_cols<double>(const Geom &, double *, const double *, hipStream_t);
 template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, const float *, const double *,

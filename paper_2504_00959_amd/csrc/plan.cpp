@@ -92,6 +92,8 @@ struct rick_plan_s {
     // device buffers
     void *mesh = nullptr;
     size_t mesh_bytes = 0;
+    void *row_mesh = nullptr;   // fused: row transforms in column-panel order
+    int32_t panel = 0;
     void *lut = nullptr;
     void *twiddle = nullptr;
     double *corr = nullptr;
@@ -139,7 +141,7 @@ struct DeviceGuard {
 };
 
 void free_all(rick_plan_t *p) {
-    void *bufs[] = {p->mesh,      p->lut,        p->twiddle,   p->corr,   p->wk,       p->scales,
+    void *bufs[] = {p->mesh,      p->row_mesh,  p->lut,        p->twiddle,   p->corr,   p->wk,       p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
                     p->rec_pos,   p->rec_vis};
@@ -362,7 +364,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_cnt2 = size_t(p->max_chunks) * g.C * g.C * sizeof(int32_t);
     const size_t sz_pos = size_t(p->rec_cap) * sizeof(uint32_t);
     const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
-    const size_t total = p->mesh_bytes + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
+    const size_t total = p->mesh_bytes * (p->fused ? 2 : 1) + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
                          size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
@@ -385,6 +387,10 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         }                                                        \
     } while (0)
     ALLOC(p->mesh, p->mesh_bytes);
+    if (p->fused) {
+        p->panel = fused_panel_width(g.N, rb);
+        ALLOC(p->row_mesh, p->mesh_bytes);
+    }
     ALLOC(p->lut, sz_lut);
     ALLOC(p->twiddle, sz_tw);
     ALLOC(p->corr, size_t(g.N) * 8);
@@ -574,8 +580,15 @@ rick_status rick_fft_planes(rick_plan_t *p, void *stream) {
         p->mesh_written = true;
     }
     timer_begin(p, T_FFT_ROWS, "fft_rows", s);
-    if (p->fp64) e = launch_fft_rows<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
-    else e = launch_fft_rows<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
+    if (p->fused)
+        e = p->fp64 ? launch_fft_rows_panel<double>(p->g, (const double *)p->mesh, (double *)p->row_mesh,
+                                                    (const double *)p->twiddle, s)
+                    : launch_fft_rows_panel<float>(p->g, (const float *)p->mesh, (float *)p->row_mesh,
+                                                   (const float *)p->twiddle, s);
+    else if (p->fp64)
+        e = launch_fft_rows<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
+    else
+        e = launch_fft_rows<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
     timer_end(p, T_FFT_ROWS, s);
     if (e != hipSuccess) return hip_fail(e, "fft_rows");
     if (!p->fused) {
@@ -601,10 +614,10 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
     if (p->fused) {
         timer_begin(p, T_SCREEN, "fft_cols_screen", s);
         if (p->fp64)
-            e = launch_fft_cols_screen<double>(p->g, (const double *)p->mesh, (const double *)p->twiddle, p->wk,
+            e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle, p->wk,
                                                p->corr, p->stats, (double *)image, 0, s);
         else
-            e = launch_fft_cols_screen<float>(p->g, (const float *)p->mesh, (const float *)p->twiddle, p->wk,
+            e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle, p->wk,
                                               p->corr, p->stats, (float *)image, kahan, s);
         timer_end(p, T_SCREEN, s);
         if (e != hipSuccess) return hip_fail(e, "fft_cols_screen");
@@ -638,6 +651,8 @@ rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
     out->dl = p->dl;
     out->dw = p->g.dw;
     out->mesh = p->mesh;
+    out->row_mesh = p->row_mesh;
+    out->panel = p->panel;
     out->mesh_bytes = (int64_t)p->mesh_bytes;
     out->tile = p->g.T;
     out->chunk = p->g.CH;

@@ -117,6 +117,11 @@ template <typename real>
 hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
 template <typename real>
 hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
+// Row pass of the fused path: from the mesh into `out` in column-panel order
+// (panels of fused_panel_width(N) columns, each stored row after row).
+template <typename real>
+hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *twiddle, hipStream_t s);
+int fused_panel_width(int N, size_t real_bytes);
 bool fft_supported(int N);
 // Column transform fused with the w-correction, plane sum and normalisation.
 size_t fused_screen_lds_bytes(int N, size_t real_bytes);

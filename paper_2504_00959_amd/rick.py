@@ -45,6 +45,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_gridded", ctypes.c_int64), ("n_dropped", ctypes.c_int64), ("n_records", ctypes.c_int64),
                 ("sum_weights", ctypes.c_double), ("du", ctypes.c_double), ("dl", ctypes.c_double),
                 ("dw", ctypes.c_double), ("mesh", ctypes.c_void_p), ("mesh_bytes", ctypes.c_int64),
+                ("row_mesh", ctypes.c_void_p), ("panel", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("state", ctypes.c_int32),
                 ("n_timers", ctypes.c_int32), ("kernel_ms", ctypes.c_float * 16),
                 ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16)]
@@ -214,7 +215,8 @@ class Plan:
                 timers[name.decode()] = (float(inf.kernel_ms[i]), int(inf.kernel_calls[i]))
         return dict(n_gridded=inf.n_gridded, n_dropped=inf.n_dropped, n_records=inf.n_records,
                     sum_weights=inf.sum_weights, du=inf.du, dl=inf.dl, dw=inf.dw, mesh_ptr=inf.mesh,
-                    mesh_bytes=inf.mesh_bytes, tile=inf.tile, chunk=inf.chunk, state=inf.state, timers=timers)
+                    mesh_bytes=inf.mesh_bytes, row_mesh_ptr=inf.row_mesh, panel=inf.panel, tile=inf.tile,
+                    chunk=inf.chunk, state=inf.state, timers=timers)
 
     def bin_counts(self, n_bins: int) -> np.ndarray:
         """Per-(plane, tile) record counts of the last grid() (host int32 array)."""
@@ -222,16 +224,29 @@ class Plan:
         _check(lib().rick_plan_bin_counts(self._h, out.ctypes.data, n_bins), "rick_plan_bin_counts")
         return out
 
-    def mesh(self):
-        """Copy of the planes: G_k after grid(), F_k after fft(); complex [N_w, N, N] on the device."""
+    def _device_view(self, ptr, shape):
         import torch
-        inf = self.info()
-        shape = (self.n_wplanes, self.grid_n, self.grid_n)
 
         class _View:
             __cuda_array_interface__ = {"shape": shape, "typestr": "<c16" if self.precision == "fp64" else "<c8",
-                                        "data": (inf["mesh_ptr"], False), "version": 2, "strides": None}
-        return torch.as_tensor(_View(), device=f"cuda:{self.device}").clone()
+                                        "data": (ptr, False), "version": 2, "strides": None}
+        return torch.as_tensor(_View(), device=f"cuda:{self.device}")
+
+    def mesh(self):
+        """Copy of the planes: G_k after grid(), F_k after fft() (G_k with the fused
+        screen); complex [N_w, N, N] on the device."""
+        inf = self.info()
+        return self._device_view(inf["mesh_ptr"], (self.n_wplanes, self.grid_n, self.grid_n)).clone()
+
+    def row_mesh(self):
+        """With the fused screen, copy of the row transforms H_k written by fft(),
+        reordered from column panels to [N_w, N, N] (row-major); None otherwise."""
+        inf = self.info()
+        if not inf["row_mesh_ptr"]:
+            return None
+        pw, n = inf["panel"], self.grid_n
+        v = self._device_view(inf["row_mesh_ptr"], (self.n_wplanes, n // pw, n, pw))
+        return v.permute(0, 2, 1, 3).reshape(self.n_wplanes, n, n).clone()
 
     def close(self):
         if getattr(self, "_h", None):

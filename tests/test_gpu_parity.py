@@ -30,8 +30,8 @@ FP64_IMG = 1e-10
 
 
 def run_gpu(ds, precision="fp32", **kw):
-    """Grid, transform and image through the C ABI; with fused=True the mesh
-    after rick_fft_planes holds the row transforms only (returned as F)."""
+    """Grid, transform and image through the C ABI; with fused=True rick_fft_planes
+    writes the row transforms only, into the column-panel buffer (returned as F)."""
     import torch
     uvw, vis, wt = to_device(ds, precision)
     p = rick.Plan.for_dataset(ds, precision=precision, **kw)
@@ -44,7 +44,12 @@ def run_gpu(ds, precision="fp32", **kw):
     counts = p.bin_counts(ds.n_wplanes * nt * nt)
     p.fft()
     torch.cuda.synchronize()
-    F = p.mesh().cpu().numpy()
+    if p.fused:
+        # the mesh keeps G_k; the row transforms went to the column-panel buffer
+        assert np.array_equal(p.mesh().cpu().numpy(), G)
+        F = p.row_mesh().cpu().numpy()
+    else:
+        F = p.mesh().cpu().numpy()
     img = p.image().double().cpu().numpy()
     torch.cuda.synchronize()
     p.close()
