@@ -123,7 +123,7 @@ KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_l
                 "k_l2_totals": "fine_scan", "k_scan_partials": "fine_scan", "k_scan_top": "fine_scan",
                 "k_scan_apply": "fine_scan", "k_l2_bases": "fine_scan", "k_l2_scatter": "fine_scatter",
                 "k_zero_heavy": "zero_heavy",
-                "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_cols": "fft_cols",
+                "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_rows_panel": "fft_rows", "k_fft_cols": "fft_cols",
                 "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen"}
 
 
