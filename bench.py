@@ -332,11 +332,126 @@ def make_workload(name, device):
     import synth
     if name == "ska_low_share":
         return synth.ska_low_share(device=device)
+    if name == "ska_low_precision":
+        return synth.ska_low_precision(device=device)
     if name == "tiny":
         return synth.tiny(device=device)
     if name == "ska_low_small":
         return synth.ska_low_small(device=device)
     raise SystemExit(f"unknown workload {name}")
+
+
+def precision_report(args):
+    """Image error of each precision mode on one workload: every mode's image
+    against the all-float64 GPU image (whole image), against the float64
+    oracle at sampled pixels, and against the direct Fourier sum at the same
+    pixels beside the oracle's own distance to it; plus each mode's step
+    time.  Prints one JSON line."""
+    import torch
+    from paper_2504_00959_amd import rick
+    import oracle.dft
+    import oracle.pixels
+    from oracle import wstack as ow
+
+    dev = "cuda:0"
+    t0 = time.time()
+    ds = make_workload(args.workload, dev)
+    print(f"[report] generated {describe(ds)} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    N = ds.grid_n
+    uvw = torch.as_tensor(ds.uvw, dtype=torch.float64).to(dev)
+    vis_host = ds.vis.cpu().numpy()
+    corr = ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param), N)
+    stream = torch.cuda.current_stream()
+    images, runs = {}, {}
+    for prec in ("fp32", "fp32_kahan", "fp64"):
+        # float64 runs unfused: its fused form would need a second mesh-sized buffer
+        fused = prec != "fp64"
+        vis = ds.vis if prec != "fp64" else ds.vis.to(torch.complex128)
+        plan = rick.Plan.for_dataset(ds, precision=prec, fused=fused)
+        img = torch.empty((N, N), dtype=plan.real_dtype, device=dev)
+
+        def step():
+            plan.reset(stream)
+            plan.grid(uvw, vis, None, ds.freq, stream)
+            plan.fft(stream)
+            plan.image(img, stream)
+
+        step()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        info = plan.info()
+        runs[prec] = {"ms_per_step": round(ms, 3), "mvis_per_s": round(ds.nvis / (ms * 1e-3) / 1e6, 1),
+                      "fused_screen": fused, "n_gridded": info["n_gridded"]}
+        images[prec] = img.double().cpu().numpy()
+        print(f"[report] {prec}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+        plan.close()
+        del vis, img, plan
+        torch.cuda.empty_cache()
+
+    # whole-image comparisons against the float64 GPU image
+    c2 = np.outer(corr, corr)
+    ref = images["fp64"]
+    central = c2 >= 0.1
+    for prec in ("fp32", "fp32_kahan"):
+        d = images[prec] - ref
+        runs[prec]["vs_fp64_gpu"] = {
+            "apparent_rel_rms": float(np.linalg.norm(d * c2) / np.linalg.norm(ref * c2)),
+            "central_rel_rms": float(np.linalg.norm(d[central]) / np.linalg.norm(ref[central])),
+            "image_rel_rms": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+        }
+
+    # sampled pixels: a patch at the phase centre and the brightest sources
+    half = args.patch // 2
+    qq, pp = np.meshgrid(np.arange(N // 2 - half, N // 2 - half + args.patch),
+                         np.arange(N // 2 - half, N // 2 - half + args.patch), indexing="ij")
+    pp, qq = pp.ravel(), qq.ravel()
+    src = ds.sources
+    order = np.argsort(-np.asarray(src["flux"]))[:8]
+    dl = ds.fov / N
+    sp = np.rint(np.asarray(src["l"])[order] / dl).astype(np.int64) + N // 2
+    sq = np.rint(np.asarray(src["m"])[order] / dl).astype(np.int64) + N // 2
+    pp, qq = np.r_[pp, sp], np.r_[qq, sq]
+    t0 = time.time()
+    orc, _, kept, sw = oracle.pixels.wstack_pixels(ds.uvw, ds.freq, vis_host, ds.weight, pp, qq,
+                                                   **ds.plan_kwargs())
+    t_orc = time.time() - t0
+    cp = corr[pp] * corr[qq]
+    dft = None
+    t0 = time.time()
+    if kept == ds.nvis:
+        sc = np.asarray(ds.freq) / 299_792_458.0
+        u = (ds.uvw[:, 0:1] * sc[None, :]).ravel()
+        v = (ds.uvw[:, 1:2] * sc[None, :]).ravel()
+        w = (ds.uvw[:, 2:3] * sc[None, :]).ravel()
+        lm = ow.pixel_lm(N, ds.fov)
+        L, M = lm[pp], lm[qq]
+        nm1 = ow.nm1_of(L, M)
+        D = oracle.dft.dft_sum(u, v, w, vis_host.reshape(-1), L, M, nm1)
+        dft = (1.0 + nm1) * D.real / float(ds.nvis)
+        del u, v, w
+    t_dft = time.time() - t0
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    for prec in runs:
+        got = images[prec][qq, pp]
+        runs[prec]["vs_oracle_pixels"] = {"apparent_rel_rms": rel(got * cp, orc * cp),
+                                          "image_rel_rms": rel(got, orc)}
+        if dft is not None:
+            runs[prec]["vs_dft_pixels"] = rel(got, dft)
+    out = {"report": "precision", "workload": describe(ds), "n_vis": ds.nvis, "steps": args.steps,
+           "pixels": {"patch": f"{args.patch}x{args.patch} at the phase centre", "sources": int(len(sp)),
+                      "count": int(len(pp))},
+           "oracle_vs_dft_pixels": rel(orc, dft) if dft is not None else None,
+           "oracle_seconds": round(t_orc, 1), "dft_seconds": round(t_dft, 1), "runs": runs}
+    print(json.dumps(out), flush=True)
 
 
 def describe(ds):
@@ -365,12 +480,19 @@ def main():
                     help="run the rocprofv3 passes (kernel trace, HBM byte counters with copy calibration, SQ "
                          "counters) on this workload as child processes and summarise them in OUT/summary")
     ap.add_argument("--summarize", metavar="OUT", help="only rewrite the summaries of an earlier --profile OUT")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="run fp32, fp32_kahan and fp64 on the workload and report each image's error against the "
+                         "float64 GPU image, the oracle and the direct Fourier sum at sampled pixels")
+    ap.add_argument("--patch", type=int, default=8, help="edge of the centre pixel patch of --precision-report")
     args = ap.parse_args()
     if args.profile:
         run_profiles(os.path.abspath(args.profile), args.workload)
         return
     if args.summarize:
         summarize_profiles(os.path.abspath(args.summarize), args.workload)
+        return
+    if args.precision_report:
+        precision_report(args)
         return
     if args.copy_calibration:
         import torch

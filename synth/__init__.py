@@ -234,6 +234,15 @@ def ska_low_share(device: Optional[str] = None, with_vis: bool = True) -> Datase
     return ska_low(device=device, with_vis=with_vis)
 
 
+def ska_low_precision(device: Optional[str] = None, with_vis: bool = True) -> Dataset:
+    """The precision-form workload: the same array, time slice and sources,
+    32 channels over the same 20 MHz band -> 418,611,200 visibilities,
+    8192^2 grid, 128 w-planes, support 7, oversample 64."""
+    ds = ska_low(n_chan=32, grid_n=8192, n_wplanes=128, device=device, with_vis=with_vis)
+    ds.name = "ska_low_precision"
+    return ds
+
+
 def ska_low_small(seed: int = 3, device: Optional[str] = None, **kw) -> Dataset:
     """Same generator at a size the oracle finishes in seconds."""
     args = dict(seed=seed, n_stations=48, n_times=24, dump_s=60.0, n_chan=4, n_src=20,

@@ -118,6 +118,20 @@ def test_fused_screen_fp64():
     assert rel_rms(gpu["img"], oracle_of(ds).image) <= FP64_IMG
 
 
+@pytest.mark.parametrize("N,fused", [(1024, False), (8192, False), (4096, True)])
+def test_fp64_grid_sizes(N, fused):
+    """All-float64 path at large meshes (the precision form's comparison run)."""
+    ds = synth.tiny(nrow=5000, seed=17, grid_n=N, n_wplanes=2, uv_radius=120.0 * N / 256)
+    if N == 8192:
+        # a float64 column strip of 8192 does not fit in LDS beside its screen table
+        with pytest.raises(rick.RickError, match="UNSUPPORTED"):
+            rick.Plan.for_dataset(ds, precision="fp64", fused=True)
+    gpu = run_gpu(ds, precision="fp64", fused=fused)
+    ref = oracle_of(ds)
+    assert rel_rms(gpu["G"], ref.planes) <= 1e-12
+    assert rel_rms(gpu["img"], ref.image) <= FP64_IMG
+
+
 def test_tiny_fp64_mode():
     ds = synth.tiny()
     gpu = run_gpu(ds, precision="fp64")
