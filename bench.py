@@ -32,20 +32,28 @@ METRIC = "Mvis/s through grid+iFFT+w-stack at fixed image RMS vs FP64 DFT oracle
 def algorithmic_bytes(name, ds, info):
     """Bytes the method must move per launch of kernel `name` (records are
     12 B: packed position + complex64 W V; replicas of tile-straddling
-    records are not counted)."""
+    records are not counted).  Only tiles that received visibilities hold
+    gridded values: the gridder writes those tiles, the row pass reads them
+    and (fused) writes the rows of tile rows holding any, which the fused
+    column pass reads."""
     nvis, nrow = ds.nvis, ds.nrow
-    cells = ds.n_wplanes * ds.grid_n * ds.grid_n
+    n2 = ds.grid_n * ds.grid_n
+    cells = ds.n_wplanes * n2
+    T = info["tile"]
+    set_cells = info["tiles_set"] * T * T                  # cells of tiles holding gridded values
+    row_cells = info["tile_rows_set"] * T * ds.grid_n      # cells of rows in tile rows holding any
+    fused = bool(info.get("row_mesh_ptr"))
     wbytes = 4 * nvis if ds.weight is not None else 0
     table = {
         "bin_count": 24 * nrow + 8 * nvis + wbytes,     # the drop test reads the visibilities too
         "bin_scatter": 24 * nrow + 8 * nvis + wbytes + 16 * nvis,   # writes 16-byte level-1 records
         "fine_count": 8 * nvis,                                    # reads their positions
         "fine_scatter": 16 * nvis + 12 * nvis,                     # reads them, writes 12-byte records
-        "grid": 12 * nvis + 8 * cells,
-        "fft_rows": 16 * cells,
+        "grid": 12 * nvis + 8 * set_cells,
+        "fft_rows": 8 * set_cells + 8 * (row_cells if fused else cells),
         "fft_cols": 16 * cells,
-        "wscreen": 8 * cells + 4 * ds.grid_n * ds.grid_n,
-        "fft_cols_screen": 8 * cells + 4 * ds.grid_n * ds.grid_n,
+        "wscreen": 8 * cells + 4 * n2,
+        "fft_cols_screen": 8 * row_cells + 4 * n2,
     }
     return table.get(name)
 
@@ -124,7 +132,8 @@ KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_l
                 "k_scan_apply": "fine_scan", "k_l2_bases": "fine_scan", "k_l2_scatter": "fine_scatter",
                 "k_zero_heavy": "zero_heavy",
                 "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_rows_panel": "fft_rows", "k_fft_cols": "fft_cols",
-                "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen"}
+                "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen", "k_mark_tiles": "mark_tiles",
+                "k_clear_bits": "reset"}
 
 
 def kernel_sources_digest():

@@ -110,13 +110,21 @@ typedef struct rick_plan_info_t {
     double du, dl, dw;       /* cell size [wavelengths], pixel size [rad], plane width [wavelengths] */
     void *mesh;              /* device pointer to the planes, [N_w][N][N] complex64 (complex128 in FP64
                                 mode), interleaved (re, im): G_k after rick_grid, F_k after rick_fft_planes
-                                (with RICK_FLAG_FUSED_SCREEN it keeps G_k) */
+                                (with RICK_FLAG_FUSED_SCREEN it keeps G_k).  G_k is held only in the tiles
+                                set in tile_bits; every other tile holds stale values and stands for zeros
+                                (F_k is complete) */
     int64_t mesh_bytes;
     void *row_mesh;          /* with RICK_FLAG_FUSED_SCREEN (else NULL): the row transforms H_k written by
                                 rick_fft_planes, mesh_bytes long, in column-panel order: element (plane k,
-                                row q, column p) at k N^2 + (p / panel) N panel + q panel + p % panel */
+                                row q, column p) at k N^2 + (p / panel) N panel + q panel + p % panel.
+                                Rows of a tile row with no set tile are not written and stand for zeros */
     int32_t panel;           /* columns per panel of row_mesh (0 without RICK_FLAG_FUSED_SCREEN) */
-    int32_t pad0;
+    int32_t occ_words;       /* 64-bit words of tile_bits per tile row: ceil(N / tile / 64) */
+    const uint64_t *tile_bits; /* device bitmap of the tiles gridded onto since the last reset: tile (plane
+                                k, tile row ty, tile column tx) is set iff bit tx % 64 of word
+                                (k N / tile + ty) occ_words + tx / 64 is */
+    int64_t tiles_set;       /* tiles set in tile_bits */
+    int64_t tile_rows_set;   /* tile rows (plane, ty) with at least one set tile */
     int32_t tile, chunk;     /* effective tile edge and chunk size */
     int32_t state;           /* 0 = empty, 1 = gridded, 2 = transformed */
     int32_t n_timers;        /* number of valid entries in kernel_ms / kernel_calls / kernel_names */
@@ -165,9 +173,9 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
  *   F_k[q][p] = sum_{j,i} G_k[j][i] exp(+2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
  * (unnormalised).  With RICK_FLAG_FUSED_SCREEN only the sum over i (the row
  * transform) is done here, into row_mesh (see rick_plan_info_t; the mesh
- * keeps G_k), and the sum over j happens in rick_wstack_image.  Requires a
- * gridded mesh (RICK_E_STATE otherwise; a mesh
- * that nothing was gridded onto since the reset is transformed as zeros).
+ * keeps G_k), and the sum over j happens in rick_wstack_image.  Tiles that
+ * nothing was gridded onto since the reset are taken as zeros without being
+ * read (a plan with nothing gridded transforms to zeros).
  * Errors: RICK_E_BAD_PLAN, RICK_E_STATE, RICK_E_HIP.
  */
 rick_status rick_fft_planes(rick_plan_t *p, void *stream);
@@ -185,8 +193,9 @@ rick_status rick_fft_planes(rick_plan_t *p, void *stream);
 rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream);
 
 /*
- * rick_reset -- begin a new image: zero the weight sum and the counters;
- * the next rick_grid overwrites the mesh instead of accumulating.
+ * rick_reset -- begin a new image: zero the weight sum and the counters and
+ * clear the tile bitmap, so the next rick_grid stores its tiles instead of
+ * adding to them and every other tile reads as zero.
  * Errors: RICK_E_BAD_PLAN, RICK_E_HIP.
  */
 rick_status rick_reset(rick_plan_t *p, void *stream);

@@ -577,8 +577,9 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
 }
 
 // ---- scan of per-bin record counts in bin order ----
+// gridding work items of a bin: none for an empty bin (its tile is not written)
 __device__ __forceinline__ int32_t chunks_of(int32_t count, int32_t CH) {
-    return count <= CH ? 1 : (count + CH - 1) / CH;
+    return (count + CH - 1) / CH;
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_partials(const int32_t *__restrict__ counts, int32_t n,

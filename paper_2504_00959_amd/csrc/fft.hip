@@ -24,6 +24,11 @@
 //
 // LDS element e is stored at e + e / 16, which keeps the stride-16 writes of
 // the first exchange on distinct banks.
+//
+// Tile occupancy: the gridder writes only the tiles that received records,
+// so the row passes read a row segment only where its tile is set and take
+// zeros elsewhere; rows of an empty tile row are written as zeros (in place)
+// or not at all (fused path, whose column pass then takes them as zeros).
 #include "rick_internal.h"
 
 namespace rick {
@@ -235,6 +240,22 @@ __device__ __forceinline__ int in_elem(int tb, int i) {
     using SH = Shape<N>;
     return (tb + (i / SH::R0) * SH::NT) + (i % SH::R0) * (N / SH::R0);
 }
+// Occupancy word of slot i.  Slot i of thread tb is element tb + c NT (c
+// fixed by i, tb < NT), and NT = N / 16 <= 64 T, so the element's tile index
+// divided by 64 -- its word in a tile-row or row bitmap -- is the same for
+// every thread: the word is a uniform load.
+template <int N>
+__device__ __forceinline__ int occ_word(int i, int log2T) {
+    return in_elem<N>(0, i) >> (log2T + 6);
+}
+__device__ __forceinline__ bool bit_of(uint64_t word, int idx) { return (word >> (idx & 63)) & 1ull; }
+// A bitmap word at a wave-uniform index, read through the scalar cache (the
+// bitmaps are not written while the FFT kernels run).
+typedef __attribute__((address_space(4))) const uint64_t const_u64;
+__device__ __forceinline__ uint64_t uniform_word(const uint64_t *bits, int64_t i) {
+    return ((const_u64 *)bits)[i];
+}
+
 // last-stage output element of slot q for thread tb
 template <int N>
 __device__ __forceinline__ int out_elem(int tb, int q) {
@@ -256,9 +277,11 @@ __device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t nblk) {
 // stages them in LDS, and writes each panel's RB x PW values as one line;
 // blocks are taken in an XCD-aware order.
 template <typename real, int N, int RB, int PW>
-__global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(const real *__restrict__ in,
+__global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(Geom g, const real *__restrict__ in,
                                                                   real *__restrict__ out,
-                                                                  const real *__restrict__ twr) {
+                                                                  const real *__restrict__ twr,
+                                                                  const uint64_t *__restrict__ tile_bits,
+                                                                  const uint64_t *__restrict__ row_bits) {
     using C = typename R2T<real>::t;
     using SH = Shape<N>;
     constexpr int NT = SH::NT;
@@ -269,13 +292,20 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(const real *__
     const int rb = threadIdx.x / NT, tb = threadIdx.x % NT;
     const int64_t blk = xcd_order(blockIdx.x, gridDim.x);
     const int64_t row0 = blk * RB;                   // RB divides N
+    // the RB rows lie in one tile row (RB <= 4 <= T); an empty one is not
+    // written: the fused column pass reads it as zeros
+    const int32_t kp = (int32_t)(row0 / N), ty = (int32_t)(row0 % N) >> g.log2T;
+    if (!row_set(row_bits, g, kp, ty)) return;
     C *buf = reinterpret_cast<C *>(smem) + rb * SH::PADN;
     const C *gi = reinterpret_cast<const C *>(in) + (row0 + rb) * N;
+    const uint64_t *tb_row = tile_bits + ((int64_t)kp * g.nt + ty) * g.occw;
     C x[16][1];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = in_elem<N>(tb, i);
-        x[i][0] = cneg_if(gi[e], e & 1);
+        // a clear tile holds no gridded values: zeros, not read
+        const bool on = bit_of(uniform_word(tb_row, occ_word<N>(i, g.log2T)), e >> g.log2T);
+        x[i][0] = on ? cneg_if(gi[e], e & 1) : C{0, 0};
     }
     fft_regs<N, 1, 1>(x, buf, tb, 0, tw);
     __syncthreads();   // every thread has read the last exchange
@@ -300,26 +330,34 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(const real *__
 
 // ---- rows: B rows per block, NT threads per row ----
 template <typename real, int N, int B>
-__global__ __launch_bounds__((N / 16) * B) void k_fft_rows(real *__restrict__ mesh, const real *__restrict__ twr) {
+__global__ __launch_bounds__((N / 16) * B) void k_fft_rows(Geom g, real *__restrict__ mesh,
+                                                           const real *__restrict__ twr,
+                                                           const uint64_t *__restrict__ tile_bits,
+                                                           const uint64_t *__restrict__ row_bits) {
     using C = typename R2T<real>::t;
     using SH = Shape<N>;
     extern __shared__ __align__(16) unsigned char smem[];
     const C *tw = reinterpret_cast<const C *>(twr);
     const int rb = threadIdx.x / SH::NT, tb = threadIdx.x % SH::NT;
     const int64_t row = (int64_t)blockIdx.x * B + rb;   // B divides the row count N_w N
+    const int32_t kp = (int32_t)(row / N), ty = (int32_t)(row % N) >> g.log2T;
     C *buf = reinterpret_cast<C *>(smem) + rb * SH::PADN;
-    C *g = reinterpret_cast<C *>(mesh) + row * N;
+    C *gm = reinterpret_cast<C *>(mesh) + row * N;
+    // clear tiles (and every tile of an empty tile row) are zeros, not read;
+    // the transform is written in full
+    const bool any = row_set(row_bits, g, kp, ty);
+    const uint64_t *tb_row = tile_bits + ((int64_t)kp * g.nt + ty) * g.occw;
     C x[16][1];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = in_elem<N>(tb, i);
-        x[i][0] = cneg_if(g[e], e & 1);
+        x[i][0] = any && bit_of(tb_row[occ_word<N>(i, g.log2T)], e >> g.log2T) ? cneg_if(gm[e], e & 1) : C{0, 0};
     }
     fft_regs<N, 1, 1>(x, buf, tb, 0, tw);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int e = out_elem<N>(tb, q);
-        g[e] = cneg_if(x[q][0], e & 1);
+        gm[e] = cneg_if(x[q][0], e & 1);
     }
 }
 
@@ -399,6 +437,7 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
                                                                          const double *__restrict__ wk,
                                                                          const double *__restrict__ corr,
                                                                          const Stats *__restrict__ st,
+                                                                         const uint64_t *__restrict__ row_bits,
                                                                          real *__restrict__ image) {
     using C = typename R2T<real>::t;
     using SH = Shape<N>;
@@ -426,16 +465,18 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
             s_nm1[e * V + v0 + v] = r2 < 1.0 ? -r2 / (1.0 + sqrt(1.0 - r2)) : 0.0;
         }
     }
+    // rows of an empty tile row were not written by the row pass: zeros
     real acc[16][VC], comp[16][VC];
     C pre[16][VC];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = in_elem<N>(tb, i);
+        const bool on = bit_of(uniform_word(row_bits, occ_word<N>(i, g.log2T)), e >> g.log2T);
 #pragma unroll
         for (int v = 0; v < VC; ++v) {
             acc[i][v] = 0;
             comp[i][v] = 0;
-            pre[i][v] = gbase[(int64_t)e * PW + v];
+            pre[i][v] = on ? gbase[(int64_t)e * PW + v] : C{0, 0};
         }
     }
     for (int k = 0; k < g.Nw; ++k) {
@@ -451,8 +492,10 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int e = in_elem<N>(tb, i);
+                const bool on =
+                    bit_of(uniform_word(row_bits, (int64_t)(k + 1) * g.occw + occ_word<N>(i, g.log2T)), e >> g.log2T);
 #pragma unroll
-                for (int v = 0; v < VC; ++v) pre[i][v] = gk[(int64_t)e * PW + v];
+                for (int v = 0; v < VC; ++v) pre[i][v] = on ? gk[(int64_t)e * PW + v] : C{0, 0};
             }
         }
         // the LDS strip is reused plane after plane: every thread must have
@@ -507,7 +550,8 @@ struct ColShape {
 };
 
 template <typename real, int N>
-hipError_t rows_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
+hipError_t rows_n(const Geom &g, real *mesh, const real *tw, const uint64_t *tile_bits, const uint64_t *row_bits,
+                  hipStream_t s) {
     using C = typename R2T<real>::t;
     constexpr int NT = Shape<N>::NT;
     constexpr int B = NT >= 256 ? 1 : 256 / NT;
@@ -519,7 +563,8 @@ hipError_t rows_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
                                   (int)lds);
         attr = true;
     }
-    hipLaunchKernelGGL((k_fft_rows<real, N, B>), dim3((unsigned)(nrows / B)), dim3(NT * B), lds, s, mesh, tw);
+    hipLaunchKernelGGL((k_fft_rows<real, N, B>), dim3((unsigned)(nrows / B)), dim3(NT * B), lds, s, g, mesh, tw,
+                       tile_bits, row_bits);
     return hipGetLastError();
 }
 
@@ -554,7 +599,8 @@ struct PanelShape {
 };
 
 template <typename real, int N>
-hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw, hipStream_t s) {
+hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw, const uint64_t *tile_bits,
+                        const uint64_t *row_bits, hipStream_t s) {
     using C = typename R2T<real>::t;
     using PS = PanelShape<real, N>;
     const int64_t nrows = (int64_t)g.Nw * N;
@@ -566,13 +612,13 @@ hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw
         attr = true;
     }
     hipLaunchKernelGGL((k_fft_rows_panel<real, N, PS::RB, PS::PW>), dim3((unsigned)(nrows / PS::RB)),
-                       dim3(PS::NT * PS::RB), lds, s, in, out, tw);
+                       dim3(PS::NT * PS::RB), lds, s, g, in, out, tw, tile_bits, row_bits);
     return hipGetLastError();
 }
 
 template <typename real, int N>
 hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const double *wk, const double *corr,
-                         const Stats *st, real *image, int kahan, hipStream_t s) {
+                         const Stats *st, const uint64_t *row_bits, real *image, int kahan, hipStream_t s) {
     using CS = ColShape<real, N>;
     constexpr int PW = PanelShape<real, N>::PW;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
@@ -586,10 +632,10 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
     }
     if (kahan)
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>), dim3(N / CS::V), dim3(CS::THREADS),
-                           lds, s, g, mesh, tw, wk, corr, st, image);
+                           lds, s, g, mesh, tw, wk, corr, st, row_bits, image);
     else
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>), dim3(N / CS::V),
-                           dim3(CS::THREADS), lds, s, g, mesh, tw, wk, corr, st, image);
+                           dim3(CS::THREADS), lds, s, g, mesh, tw, wk, corr, st, row_bits, image);
     return hipGetLastError();
 }
 
@@ -605,10 +651,11 @@ size_t fused_screen_lds_bytes(int N, size_t real_bytes) {
 }
 
 template <typename real>
-hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
+hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *tw, const uint64_t *tile_bits,
+                           const uint64_t *row_bits, hipStream_t s) {
     switch (g.N) {
 #define CASE(n) \
-    case n: return rows_n<real, n>(g, mesh, tw, s);
+    case n: return rows_n<real, n>(g, mesh, tw, tile_bits, row_bits, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -626,10 +673,11 @@ int fused_panel_width(int N, size_t real_bytes) {
 }
 
 template <typename real>
-hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *tw, hipStream_t s) {
+hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *tw,
+                                 const uint64_t *tile_bits, const uint64_t *row_bits, hipStream_t s) {
     switch (g.N) {
 #define CASE(n) \
-    case n: return rows_panel_n<real, n>(g, in, out, tw, s);
+    case n: return rows_panel_n<real, n>(g, in, out, tw, tile_bits, row_bits, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -649,26 +697,32 @@ hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *tw, hipStream_
 
 template <typename real>
 hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *wk,
-                                  const double *corr, const Stats *st, real *image, int kahan, hipStream_t s) {
+                                  const double *corr, const Stats *st, const uint64_t *row_bits, real *image,
+                                  int kahan, hipStream_t s) {
     switch (g.N) {
 #define CASE(n) \
-    case n: return cols_screen_n<real, n>(g, mesh, tw, wk, corr, st, image, kahan, s);
+    case n: return cols_screen_n<real, n>(g, mesh, tw, wk, corr, st, row_bits, image, kahan, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_fft_rows<float>(const Geom &, float *, const float *, hipStream_t);
-template hipError_t launch_fft_rows<double>(const Geom &, double *, const double *, hipStream_t);
-template hipError_t launch_fft_rows_panel<float>(const Geom &, const float *, float *, const float *, hipStream_t);
+template hipError_t launch_fft_rows<float>(const Geom &, float *, const float *, const uint64_t *, const uint64_t *,
+                                           hipStream_t);
+template hipError_t launch_fft_rows<double>(const Geom &, double *, const double *, const uint64_t *,
+                                            const uint64_t *, hipStream_t);
+template hipError_t launch_fft_rows_panel<float>(const Geom &, const float *, float *, const float *,
+                                                 const uint64_t *, const uint64_t *, hipStream_t);
 template hipError_t launch_fft_rows_panel<double>(const Geom &, const double *, double *, const double *,
-                                                  hipStream_t);
+                                                  const uint64_t *, const uint64_t *, hipStream_t);
 template hipError_t launch_fft_cols<float>(const Geom &, float *, const float *, hipStream_t);
 template hipError_t launch_fft_cols<double>(const Geom &, double *, const double *, hipStream_t);
 template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, const float *, const double *,
-                                                  const double *, const Stats *, float *, int, hipStream_t);
+                                                  const double *, const Stats *, const uint64_t *, float *, int,
+                                                  hipStream_t);
 template hipError_t launch_fft_cols_screen<double>(const Geom &, const double *, const double *, const double *,
-                                                   const double *, const Stats *, double *, int, hipStream_t);
+                                                   const double *, const Stats *, const uint64_t *, double *, int,
+                                                   hipStream_t);
 
 }  // namespace rick

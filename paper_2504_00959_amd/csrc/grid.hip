@@ -24,11 +24,14 @@
 // tile edges was binned into every tile it touches.
 //
 // After the records the tile is written to HBM once, row-coalesced:
-//   - bins with a single chunk own their tile and store it (empty bins store
-//     zeros, so the mesh needs no clearing);
+//   - bins with a single chunk own their tile and store it, or add it to the
+//     tile's contents if an earlier rick_grid since the reset wrote that tile;
 //   - bins split over several chunks (the dense uv centre) add their partial
-//     tiles with atomics onto a tile zeroed beforehand.
-// On a rick_grid that accumulates onto an earlier one, every tile is added.
+//     tiles with atomics onto a tile zeroed beforehand (unless an earlier
+//     rick_grid wrote it).
+// Empty bins have no work item and write nothing: a bitmap of written tiles
+// (set after gridding, cleared by rick_reset) tells the FFT which tiles hold
+// values; the others stand for zeros and are never read.
 #include "rick_internal.h"
 
 namespace rick {
@@ -63,10 +66,13 @@ __device__ __forceinline__ double bcast(double v, int j) {
 __device__ __forceinline__ void atomic_add_real(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_real(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-// Heavy bins (several chunks) are zeroed before gridding; the scan lists them.
+// Heavy bins (several chunks) are zeroed before gridding, unless an earlier
+// rick_grid wrote the tile; the scan lists them.
 template <typename real>
 __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t *__restrict__ heavy_bins,
-                                                           const Stats *__restrict__ st, real *__restrict__ mesh) {
+                                                           const Stats *__restrict__ st,
+                                                           const uint64_t *__restrict__ tile_bits,
+                                                           real *__restrict__ mesh) {
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
     const int32_t nheavy = (int32_t)st->n_heavy;
@@ -74,6 +80,7 @@ __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t
         const int32_t b = heavy_bins[hb];
         const int32_t k = b / (g.nt * g.nt);
         const int32_t rem = b - k * g.nt * g.nt;
+        if (tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt)) continue;
         const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
         for (int32_t c = threadIdx.x; c < g.T * g.T; c += kZeroBlock) {
             const int32_t y = c >> g.log2T, x = c & (g.T - 1);
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
-                                                     real *__restrict__ mesh, int accumulate) {
+                                                     real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits) {
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
@@ -125,16 +132,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
-    if (n == 0) {
-        // empty bin: a single chunk that owns its tile; store zeros unless accumulating
-        if (!accumulate) {
-            for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
-                const int32_t y = c >> g.log2T, x = c & (T - 1);
-                m[((int64_t)k * g.N + y0 + y) * g.N + x0 + x] = r2{0, 0};
-            }
-        }
-        return;
-    }
+    if (n <= 0) return;   // (empty bins have no work item)
     // LDS: real plane at byte 0, imaginary plane KOFF doubles further, then the tap table
     double *acc_re = reinterpret_cast<double *>(smem);
     double *acc_im = acc_re + KOFF;
@@ -270,6 +268,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     __syncthreads();
 
     const bool shared_tile = nchunk > 1;
+    const bool accumulate = tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
     for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
         const int32_t y = c >> g.log2T, x = c & (T - 1);
         const real re = (real)acc_re[y * P + x], im = (real)acc_im[y * P + x];
@@ -292,9 +291,52 @@ __global__ void k_zero_mesh(real *__restrict__ a, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0;
 }
 
+// After gridding: one block per plane, one wave per tile row at a time.
+// Lane l of a wave takes tiles l, l + 64, ... of its row; a tile is set if it
+// was set before or received records now (the ballot is the bitmap word).
+// The row bits are rebuilt from the tile bits, in LDS.
+constexpr int kMarkBlock = 256;
+constexpr int kMaxOccWords = 8;   // tiles per axis <= 512
+__global__ __launch_bounds__(kMarkBlock) void k_mark_tiles(Geom g, const BinScan *__restrict__ scan,
+                                                           uint64_t *__restrict__ tile_bits,
+                                                           uint64_t *__restrict__ row_bits) {
+    __shared__ unsigned long long s_row[kMaxOccWords];
+    const int32_t k = blockIdx.x;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x < kMaxOccWords) s_row[threadIdx.x] = 0;
+    __syncthreads();
+    for (int32_t ty = wave; ty < g.nt; ty += kMarkBlock / 64) {
+        bool any = false;
+        for (int32_t j = 0; j < g.occw; ++j) {
+            const int32_t tx = lane + 64 * j;
+            bool got = false;
+            if (tx < g.nt) {
+                const int64_t b = ((int64_t)k * g.nt + ty) * g.nt + tx;
+                got = scan[b + 1].rec > scan[b].rec;
+            }
+            const int64_t wi = ((int64_t)k * g.nt + ty) * g.occw + j;
+            const uint64_t word = tile_bits[wi] | __ballot(got);
+            if (lane == 0) tile_bits[wi] = word;
+            any = any || word != 0;
+        }
+        if (lane == 0 && any) atomicOr(&s_row[ty >> 6], 1ull << (ty & 63));
+    }
+    __syncthreads();
+    if (threadIdx.x < g.occw) row_bits[(int64_t)k * g.occw + threadIdx.x] = s_row[threadIdx.x];
+}
+
+__global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, uint64_t *__restrict__ row_bits,
+                             int64_t n_row) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tile + n_row; i += stride) {
+        if (i < n_tile) tile_bits[i] = 0;
+        else row_bits[i - n_tile] = 0;
+    }
+}
+
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                  const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
+                  const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, int32_t max_items,
                   hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static bool attr = false;
@@ -304,7 +346,7 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
         attr = true;
     }
     hipLaunchKernelGGL((k_grid<real, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin, rec_pos,
-                       rec_vis, lut, mesh, accumulate);
+                       rec_vis, lut, mesh, tile_bits);
     return hipGetLastError();
 }
 
@@ -323,18 +365,34 @@ hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
 }
 
 template <typename real>
-hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, real *mesh, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, mesh);
+hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, const uint64_t *tile_bits,
+                             real *mesh, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, tile_bits, mesh);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_tiles(const Geom &g, const BinScan *scan, uint64_t *tile_bits, uint64_t *row_bits,
+                             hipStream_t s) {
+    if (g.occw > kMaxOccWords) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mark_tiles, dim3(g.Nw), dim3(kMarkBlock), 0, s, g, scan, tile_bits, row_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s) {
+    const int64_t n_row = (int64_t)g.Nw * g.occw, n_tile = n_row * g.nt;
+    const int64_t blocks = (n_tile + n_row + 255) / 256;
+    hipLaunchKernelGGL(k_clear_bits, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, tile_bits,
+                       n_tile, row_bits, n_row);
     return hipGetLastError();
 }
 
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                       const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
-                       hipStream_t s) {
+                       const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits,
+                       int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
-    case w: return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, accumulate, max_items, s);
+    case w: return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -343,11 +401,15 @@ hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_b
 
 template hipError_t launch_zero_mesh<float>(float *, int64_t, hipStream_t);
 template hipError_t launch_zero_mesh<double>(double *, int64_t, hipStream_t);
-template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, const Stats *, float *, hipStream_t);
-template hipError_t launch_zero_heavy<double>(const Geom &, const int32_t *, const Stats *, double *, hipStream_t);
+template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, const Stats *, const uint64_t *, float *,
+                                             hipStream_t);
+template hipError_t launch_zero_heavy<double>(const Geom &, const int32_t *, const Stats *, const uint64_t *,
+                                              double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
-                                       const float *, const float *, float *, int, int32_t, hipStream_t);
+                                       const float *, const float *, float *, const uint64_t *, int32_t,
+                                       hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
-                                        const double *, const double *, double *, int, int32_t, hipStream_t);
+                                        const double *, const double *, double *, const uint64_t *, int32_t,
+                                        hipStream_t);
 
 }  // namespace rick

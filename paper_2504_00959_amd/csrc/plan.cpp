@@ -85,7 +85,6 @@ struct rick_plan_s {
     Geom g;
     bool fp64;
     int state;               // 0 empty, 1 gridded, 2 transformed
-    bool mesh_written;       // a rick_grid since the last reset wrote every tile
     double du, dl;
     int64_t max_items;       // gridding launch bound per visibility (items <= nbins + 4 nvis / CH)
     size_t real_bytes;
@@ -93,6 +92,8 @@ struct rick_plan_s {
     void *mesh = nullptr;
     size_t mesh_bytes = 0;
     void *row_mesh = nullptr;   // fused: row transforms in column-panel order
+    uint64_t *tile_bits = nullptr;   // tiles written since the reset, [N_w][nt][occw] words
+    uint64_t *row_bits = nullptr;    // tile rows with a written tile, [N_w][occw] words
     int32_t panel = 0;
     void *lut = nullptr;
     void *twiddle = nullptr;
@@ -141,7 +142,8 @@ struct DeviceGuard {
 };
 
 void free_all(rick_plan_t *p) {
-    void *bufs[] = {p->mesh,      p->row_mesh,  p->lut,        p->twiddle,   p->corr,   p->wk,       p->scales,
+    void *bufs[] = {p->mesh,      p->row_mesh,  p->tile_bits,  p->row_bits,  p->lut,    p->twiddle,  p->corr,
+                    p->wk,        p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
                     p->rec_pos,   p->rec_vis};
@@ -202,7 +204,7 @@ void timer_end(rick_plan_t *p, int slot, hipStream_t s) {
 
 enum TimerSlot {
     T_COUNT = 0, T_SCAN, T_SCATTER, T_ZERO_HEAVY, T_GRID, T_FFT_ROWS, T_FFT_COLS, T_SCREEN, T_RESET,
-    T_FINE_COUNT, T_FINE_SCAN, T_FINE_SCATTER
+    T_FINE_COUNT, T_FINE_SCAN, T_FINE_SCATTER, T_MARK
 };
 
 }  // namespace
@@ -261,6 +263,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     if (g.T < g.W) g.T = 16 >= g.W ? 16 : 32;
     g.log2T = ilog2(g.T);
     g.nt = g.N / g.T;
+    g.occw = (g.nt + 63) / 64;
     const int64_t nbins64 = int64_t(g.Nw) * g.nt * g.nt;
     if (nbins64 >= (int64_t(1) << 26)) {
         delete p;
@@ -364,8 +367,10 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_cnt2 = size_t(p->max_chunks) * g.C * g.C * sizeof(int32_t);
     const size_t sz_pos = size_t(p->rec_cap) * sizeof(uint32_t);
     const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
+    const size_t sz_rbits = size_t(g.Nw) * g.occw * sizeof(uint64_t);
+    const size_t sz_tbits = sz_rbits * g.nt;
     const size_t total = p->mesh_bytes * (p->fused ? 2 : 1) + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
-                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis;
+                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis + sz_tbits + sz_rbits;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) {
@@ -391,6 +396,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         p->panel = fused_panel_width(g.N, rb);
         ALLOC(p->row_mesh, p->mesh_bytes);
     }
+    ALLOC(p->tile_bits, sz_tbits);
+    ALLOC(p->row_bits, sz_rbits);
     ALLOC(p->lut, sz_lut);
     ALLOC(p->twiddle, sz_tw);
     ALLOC(p->corr, size_t(g.N) * 8);
@@ -445,6 +452,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     }
     e = hipMemset(p->stats, 0, sizeof(Stats));
     if (e == hipSuccess) e = hipMemset(p->mesh, 0, p->mesh_bytes);
+    if (e == hipSuccess) e = hipMemset(p->tile_bits, 0, sz_tbits);
+    if (e == hipSuccess) e = hipMemset(p->row_bits, 0, sz_rbits);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_all(p);
@@ -464,7 +473,6 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         }
     }
     p->state = 0;
-    p->mesh_written = false;
     *out = p;
     return RICK_OK;
 }
@@ -484,10 +492,10 @@ rick_status rick_reset(rick_plan_t *p, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     timer_begin(p, T_RESET, "reset", s);
     hipError_t e = launch_zero_stats(p->stats, s);
+    if (e == hipSuccess) e = launch_clear_bits(p->g, p->tile_bits, p->row_bits, s);
     timer_end(p, T_RESET, s);
     if (e != hipSuccess) return hip_fail(e, "reset");
     p->state = 0;
-    p->mesh_written = false;
     return RICK_OK;
 }
 
@@ -518,9 +526,11 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     hipError_t e = launch_set_scales(p->scales, sc.data(), nchan, s);
     if (e != hipSuccess) return hip_fail(e, "channel scales upload");
     const Geom &g = p->g;
-    const int accumulate = p->mesh_written ? 1 : 0;
     const int64_t nvis = nrow * nchan;
-    const int32_t max_items = int32_t(g.nbins + (4 * nvis + g.CH - 1) / g.CH);
+    // work items: one per chunk of a non-empty bin; at most 4 records per visibility
+    const int64_t max_records = 4 * nvis;
+    const int32_t max_items =
+        int32_t((max_records < g.nbins ? max_records : g.nbins) + (max_records + g.CH - 1) / g.CH + 1);
 
     const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2,
                      p->counts,   p->scan,       p->item_bin, p->heavy_bins, p->rec_pos,  p->rec_vis};
@@ -545,23 +555,24 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
         timer_end(p, ps.slot, s);
         if (e != hipSuccess) return hip_fail(e, ps.name);
     }
-    if (!accumulate) {
-        timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
-        if (p->fp64) e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, (double *)p->mesh, s);
-        else e = launch_zero_heavy<float>(g, p->heavy_bins, p->stats, (float *)p->mesh, s);
-        timer_end(p, T_ZERO_HEAVY, s);
-        if (e != hipSuccess) return hip_fail(e, "zero_heavy");
-    }
+    timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
+    if (p->fp64) e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, p->tile_bits, (double *)p->mesh, s);
+    else e = launch_zero_heavy<float>(g, p->heavy_bins, p->stats, p->tile_bits, (float *)p->mesh, s);
+    timer_end(p, T_ZERO_HEAVY, s);
+    if (e != hipSuccess) return hip_fail(e, "zero_heavy");
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
         e = launch_grid<double>(g, p->scan, p->item_bin, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
-                                (double *)p->mesh, accumulate, max_items, s);
+                                (double *)p->mesh, p->tile_bits, max_items, s);
     else
         e = launch_grid<float>(g, p->scan, p->item_bin, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
-                               (float *)p->mesh, accumulate, max_items, s);
+                               (float *)p->mesh, p->tile_bits, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
-    p->mesh_written = true;
+    timer_begin(p, T_MARK, "mark_tiles", s);
+    e = launch_mark_tiles(g, p->scan, p->tile_bits, p->row_bits, s);
+    timer_end(p, T_MARK, s);
+    if (e != hipSuccess) return hip_fail(e, "mark_tiles");
     p->state = 1;
     return RICK_OK;
 }
@@ -572,23 +583,18 @@ rick_status rick_fft_planes(rick_plan_t *p, void *stream) {
     DeviceGuard guard(p->d.device);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    if (!p->mesh_written) {
-        // nothing gridded since the reset: the planes are zero
-        if (p->fp64) e = launch_zero_mesh<double>((double *)p->mesh, int64_t(p->mesh_bytes / 8), s);
-        else e = launch_zero_mesh<float>((float *)p->mesh, int64_t(p->mesh_bytes / 4), s);
-        if (e != hipSuccess) return hip_fail(e, "zero mesh");
-        p->mesh_written = true;
-    }
+    // tiles nothing was gridded onto since the reset are read as zeros
     timer_begin(p, T_FFT_ROWS, "fft_rows", s);
     if (p->fused)
         e = p->fp64 ? launch_fft_rows_panel<double>(p->g, (const double *)p->mesh, (double *)p->row_mesh,
-                                                    (const double *)p->twiddle, s)
+                                                    (const double *)p->twiddle, p->tile_bits, p->row_bits, s)
                     : launch_fft_rows_panel<float>(p->g, (const float *)p->mesh, (float *)p->row_mesh,
-                                                   (const float *)p->twiddle, s);
+                                                   (const float *)p->twiddle, p->tile_bits, p->row_bits, s);
     else if (p->fp64)
-        e = launch_fft_rows<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, s);
+        e = launch_fft_rows<double>(p->g, (double *)p->mesh, (const double *)p->twiddle, p->tile_bits, p->row_bits,
+                                    s);
     else
-        e = launch_fft_rows<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, s);
+        e = launch_fft_rows<float>(p->g, (float *)p->mesh, (const float *)p->twiddle, p->tile_bits, p->row_bits, s);
     timer_end(p, T_FFT_ROWS, s);
     if (e != hipSuccess) return hip_fail(e, "fft_rows");
     if (!p->fused) {
@@ -615,10 +621,10 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
         timer_begin(p, T_SCREEN, "fft_cols_screen", s);
         if (p->fp64)
             e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle, p->wk,
-                                               p->corr, p->stats, (double *)image, 0, s);
+                                               p->corr, p->stats, p->row_bits, (double *)image, 0, s);
         else
             e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle, p->wk,
-                                              p->corr, p->stats, (float *)image, kahan, s);
+                                              p->corr, p->stats, p->row_bits, (float *)image, kahan, s);
         timer_end(p, T_SCREEN, s);
         if (e != hipSuccess) return hip_fail(e, "fft_cols_screen");
         return RICK_OK;
@@ -652,6 +658,23 @@ rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
     out->dw = p->g.dw;
     out->mesh = p->mesh;
     out->row_mesh = p->row_mesh;
+    out->tile_bits = p->tile_bits;
+    out->occ_words = p->g.occw;
+    {
+        const Geom &g = p->g;
+        std::vector<uint64_t> bits(size_t(g.Nw) * g.nt * g.occw);
+        e = hipMemcpy(bits.data(), p->tile_bits, bits.size() * sizeof(uint64_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "read tile bitmap");
+        int64_t tiles = 0, rows = 0;
+        for (size_t r = 0; r < size_t(g.Nw) * g.nt; ++r) {
+            int64_t c = 0;
+            for (int j = 0; j < g.occw; ++j) c += __builtin_popcountll(bits[r * g.occw + j]);
+            tiles += c;
+            rows += c > 0;
+        }
+        out->tiles_set = tiles;
+        out->tile_rows_set = rows;
+    }
     out->panel = p->panel;
     out->mesh_bytes = (int64_t)p->mesh_bytes;
     out->tile = p->g.T;

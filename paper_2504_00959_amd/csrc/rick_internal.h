@@ -42,7 +42,7 @@ struct Geom {
     int32_t nct;        // coarse tiles per axis, nt / C
     int32_t n1;         // coarse bins, Nw * nct * nct
     int32_t CHK;        // level-1 records per level-2 chunk
-    int32_t pad0;
+    int32_t occw;       // 64-bit words of tile occupancy per tile row, ceil(nt / 64)
     double fov;
     double half;        // N * OS / 2
     double w_min;
@@ -66,6 +66,20 @@ struct BinScan {
     int32_t rec;
     int32_t item;
 };
+
+// Tile occupancy.  Tile (plane k, tile row ty, tile column tx) holds gridded
+// values since the last reset iff bit tx % 64 of tile_bits[(k nt + ty) occw +
+// tx / 64] is set; the mesh contents of a clear tile are never read and stand
+// for zeros (the gridder writes only tiles that receive records).  Bit ty % 64
+// of row_bits[k occw + ty / 64] is set iff any tile of tile row (k, ty) is.
+__device__ __forceinline__ bool tile_set(const uint64_t *__restrict__ tile_bits, const Geom &g, int32_t k,
+                                         int32_t ty, int32_t tx) {
+    return (tile_bits[((int64_t)k * g.nt + ty) * g.occw + (tx >> 6)] >> (tx & 63)) & 1ull;
+}
+__device__ __forceinline__ bool row_set(const uint64_t *__restrict__ row_bits, const Geom &g, int32_t k,
+                                        int32_t ty) {
+    return (row_bits[(int64_t)k * g.occw + (ty >> 6)] >> (ty & 63)) & 1ull;
+}
 
 // ---- kernel launchers (each returns hipGetLastError() of its launches) ----
 hipError_t launch_zero_stats(Stats *st, hipStream_t s);
@@ -103,31 +117,43 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
 template <typename real>
 hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int32_t nchan, Stats *st, int phase,
                              hipStream_t s);
-// Gridding: zero heavy tiles, then one block per (bin, chunk) item.
+// Gridding: zero the heavy tiles that hold nothing yet, then one block per
+// (bin, chunk) item; tiles set in tile_bits are added to, others stored.
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                       const real *rec_vis, const real *lut, real *mesh, int accumulate, int32_t max_items,
-                       hipStream_t s);
+                       const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits,
+                       int32_t max_items, hipStream_t s);
 // LDS bytes of one gridding block (float64 accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 template <typename real>
-hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, real *mesh, hipStream_t s);
-// Batched centred 2-D inverse FFT, in place, all planes.
+hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, const uint64_t *tile_bits,
+                             real *mesh, hipStream_t s);
+// After gridding: set the bits of the tiles that received records, and the row bits.
+hipError_t launch_mark_tiles(const Geom &g, const BinScan *scan, uint64_t *tile_bits, uint64_t *row_bits,
+                             hipStream_t s);
+// Clear both occupancy bitmaps (a fill kernel; no memset node in captured work).
+hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
+// Batched centred 2-D inverse FFT, in place, all planes.  Rows of an empty
+// tile row are written as zeros; clear tiles are read as zeros.
 template <typename real>
-hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
+hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, const uint64_t *tile_bits,
+                           const uint64_t *row_bits, hipStream_t s);
 template <typename real>
 hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
 // Row pass of the fused path: from the mesh into `out` in column-panel order
-// (panels of fused_panel_width(N) columns, each stored row after row).
+// (panels of fused_panel_width(N) columns, each stored row after row).  Rows
+// of an empty tile row are not written (the fused column pass reads them as zeros).
 template <typename real>
-hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *twiddle, hipStream_t s);
+hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *twiddle,
+                                 const uint64_t *tile_bits, const uint64_t *row_bits, hipStream_t s);
 int fused_panel_width(int N, size_t real_bytes);
 bool fft_supported(int N);
 // Column transform fused with the w-correction, plane sum and normalisation.
 size_t fused_screen_lds_bytes(int N, size_t real_bytes);
 template <typename real>
 hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *wk,
-                                  const double *corr, const Stats *st, real *image, int kahan, hipStream_t s);
+                                  const double *corr, const Stats *st, const uint64_t *row_bits, real *image,
+                                  int kahan, hipStream_t s);
 // Phase screen + plane sum + normalisation.
 template <typename real>
 hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *wk, const double *corr,

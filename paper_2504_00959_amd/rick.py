@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_gridded", ctypes.c_int64), ("n_dropped", ctypes.c_int64), ("n_records", ctypes.c_int64),
                 ("sum_weights", ctypes.c_double), ("du", ctypes.c_double), ("dl", ctypes.c_double),
                 ("dw", ctypes.c_double), ("mesh", ctypes.c_void_p), ("mesh_bytes", ctypes.c_int64),
-                ("row_mesh", ctypes.c_void_p), ("panel", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("row_mesh", ctypes.c_void_p), ("panel", ctypes.c_int32), ("occ_words", ctypes.c_int32),
+                ("tile_bits", ctypes.c_void_p), ("tiles_set", ctypes.c_int64), ("tile_rows_set", ctypes.c_int64),
                 ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("state", ctypes.c_int32),
                 ("n_timers", ctypes.c_int32), ("kernel_ms", ctypes.c_float * 16),
                 ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16)]
@@ -215,7 +216,9 @@ class Plan:
                 timers[name.decode()] = (float(inf.kernel_ms[i]), int(inf.kernel_calls[i]))
         return dict(n_gridded=inf.n_gridded, n_dropped=inf.n_dropped, n_records=inf.n_records,
                     sum_weights=inf.sum_weights, du=inf.du, dl=inf.dl, dw=inf.dw, mesh_ptr=inf.mesh,
-                    mesh_bytes=inf.mesh_bytes, row_mesh_ptr=inf.row_mesh, panel=inf.panel, tile=inf.tile,
+                    mesh_bytes=inf.mesh_bytes, row_mesh_ptr=inf.row_mesh, panel=inf.panel,
+                    tile_bits_ptr=inf.tile_bits, occ_words=inf.occ_words, tiles_set=inf.tiles_set,
+                    tile_rows_set=inf.tile_rows_set, tile=inf.tile,
                     chunk=inf.chunk, state=inf.state, timers=timers)
 
     def bin_counts(self, n_bins: int) -> np.ndarray:
@@ -224,29 +227,57 @@ class Plan:
         _check(lib().rick_plan_bin_counts(self._h, out.ctypes.data, n_bins), "rick_plan_bin_counts")
         return out
 
-    def _device_view(self, ptr, shape):
+    def _device_view(self, ptr, shape, typestr=None):
         import torch
+        ts = typestr or ("<c16" if self.precision == "fp64" else "<c8")
 
         class _View:
-            __cuda_array_interface__ = {"shape": shape, "typestr": "<c16" if self.precision == "fp64" else "<c8",
-                                        "data": (ptr, False), "version": 2, "strides": None}
+            __cuda_array_interface__ = {"shape": shape, "typestr": ts, "data": (ptr, False), "version": 2,
+                                        "strides": None}
         return torch.as_tensor(_View(), device=f"cuda:{self.device}")
 
-    def mesh(self):
-        """Copy of the planes: G_k after grid(), F_k after fft() (G_k with the fused
-        screen); complex [N_w, N, N] on the device."""
+    def tile_mask(self):
+        """Host bool array [N_w, nt, nt]: tiles gridded onto since the last reset."""
         inf = self.info()
-        return self._device_view(inf["mesh_ptr"], (self.n_wplanes, self.grid_n, self.grid_n)).clone()
+        nt, ow = self.grid_n // inf["tile"], inf["occ_words"]
+        words = self._device_view(inf["tile_bits_ptr"], (self.n_wplanes * nt * ow,), "<i8")
+        w = words.cpu().numpy().view(np.uint64).reshape(self.n_wplanes, nt, ow)
+        bits = (w[..., :, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)
+        return bits.reshape(self.n_wplanes, nt, ow * 64)[..., :nt].astype(bool)
+
+    def _cell_mask(self, rows_only=False):
+        """Device bool [N_w, N, N] of the cells the planes hold (tile-row
+        granularity with rows_only)."""
+        import torch
+        t = self.tile_mask()
+        if rows_only:
+            t = np.repeat(t.any(axis=2, keepdims=True), t.shape[2], axis=2)
+        T = self.grid_n // t.shape[1]
+        m = torch.as_tensor(t, device=f"cuda:{self.device}")
+        return m.repeat_interleave(T, dim=1).repeat_interleave(T, dim=2)
+
+    def mesh(self):
+        """Copy of the planes: G_k after grid() (tiles not gridded onto since
+        the reset read as zeros), F_k after fft() (G_k with the fused screen);
+        complex [N_w, N, N] on the device."""
+        inf = self.info()
+        v = self._device_view(inf["mesh_ptr"], (self.n_wplanes, self.grid_n, self.grid_n)).clone()
+        if inf["state"] == 1 or (inf["state"] == 2 and self.fused):
+            v[~self._cell_mask()] = 0
+        return v
 
     def row_mesh(self):
         """With the fused screen, copy of the row transforms H_k written by fft(),
-        reordered from column panels to [N_w, N, N] (row-major); None otherwise."""
+        reordered from column panels to [N_w, N, N] (row-major; rows of empty
+        tile rows read as zeros); None otherwise."""
         inf = self.info()
         if not inf["row_mesh_ptr"]:
             return None
         pw, n = inf["panel"], self.grid_n
         v = self._device_view(inf["row_mesh_ptr"], (self.n_wplanes, n // pw, n, pw))
-        return v.permute(0, 2, 1, 3).reshape(self.n_wplanes, n, n).clone()
+        v = v.permute(0, 2, 1, 3).reshape(self.n_wplanes, n, n).clone()
+        v[~self._cell_mask(rows_only=True)] = 0
+        return v
 
     def close(self):
         if getattr(self, "_h", None):
