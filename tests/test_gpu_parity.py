@@ -245,6 +245,53 @@ def test_accumulating_two_grid_calls_equals_one(tile, chunk):
         assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_tile_bitmap_across_calls_and_resets(fused):
+    """Tiles are written only where records land and a bitmap says which:
+    a second rick_grid over other tiles stores those and adds to shared ones,
+    and after a reset the first image's tiles must not leak into the next."""
+    import torch
+    ds = synth.tiny(nrow=20000, seed=18)
+    uvw, vis, _ = to_device(ds)
+    east = np.nonzero(ds.uvw[:, 0] > 20.0)[0]      # first call: one half-plane of u
+    west = np.nonzero(ds.uvw[:, 0] <= 20.0)[0]
+    e_t = torch.as_tensor(east, device=uvw.device)
+    w_t = torch.as_tensor(west, device=uvw.device)
+    with rick.Plan.for_dataset(ds, fused=fused) as p:
+        p.reset()
+        p.grid(uvw[e_t].contiguous(), vis[e_t].contiguous())
+        nt = ds.grid_n // p.info()["tile"]
+        t_east = p.tile_mask()
+        p.grid(uvw[w_t].contiguous(), vis[w_t].contiguous())
+        t_all = p.tile_mask()
+        assert t_east.sum() > 0 and t_all.sum() > t_east.sum() and np.all(t_all[t_east])
+        p.fft()
+        img_two = p.image().double().cpu().numpy()
+        # a new image of the west half only: the east tiles still sit in the
+        # mesh and must read as zeros
+        p.reset()
+        assert p.tile_mask().sum() == 0
+        p.grid(uvw[w_t].contiguous(), vis[w_t].contiguous())
+        p.fft()
+        img_west = p.image().double().cpu().numpy()
+        # nothing gridded since the reset: a zero image
+        p.reset()
+        p.fft()
+        img_none = p.image().double().cpu().numpy()
+        torch.cuda.synchronize()
+    assert t_all.shape == (ds.n_wplanes, nt, nt)
+    ref = oracle_of(ds)
+    err = image_errors(img_two, ref.image, ref.corr)
+    assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+    dsw = synth.tiny(nrow=20000, seed=18)
+    dsw.uvw = ds.uvw[west]
+    dsw.vis = np.asarray(ds.vis)[west]
+    refw = oracle_of(dsw)
+    err = image_errors(img_west, refw.image, refw.corr)
+    assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+    assert float(np.abs(img_none).max()) == 0.0
+
+
 def test_empty_and_all_dropped_give_zero_image():
     import torch
     ds = synth.tiny(nrow=100, seed=11)
