@@ -31,11 +31,11 @@ METRIC = "Mvis/s through grid+iFFT+w-stack at fixed image RMS vs FP64 DFT oracle
 
 def algorithmic_bytes(name, ds, info):
     """Bytes the method must move per launch of kernel `name` (records are
-    12 B: packed position + complex64 W V; replicas of tile-straddling
-    records are not counted).  Only tiles that received visibilities hold
-    gridded values: the gridder writes those tiles, the row pass reads them
-    and (fused) writes the rows of tile rows holding any, which the fused
-    column pass reads."""
+    12 B: packed position + complex64 W V, one per visibility).  Only tiles
+    that received visibilities (or their neighbours' margins) hold gridded
+    values: the gridder writes those tiles, the row pass reads them and
+    (fused) writes the rows of tile rows holding any, which the fused column
+    pass reads."""
     nvis, nrow = ds.nvis, ds.nrow
     n2 = ds.grid_n * ds.grid_n
     cells = ds.n_wplanes * n2
@@ -132,7 +132,7 @@ KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_l
                 "k_scan_apply": "fine_scan", "k_l2_bases": "fine_scan", "k_l2_scatter": "fine_scatter",
                 "k_zero_heavy": "zero_heavy",
                 "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_rows_panel": "fft_rows", "k_fft_cols": "fft_cols",
-                "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen", "k_mark_tiles": "mark_tiles",
+                "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen", "k_merge_margins": "merge_margins", "k_row_bits": "merge_margins",
                 "k_clear_bits": "reset"}
 
 

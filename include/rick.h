@@ -104,8 +104,8 @@ typedef struct rick_plan_info_t {
     int64_t n_gridded;       /* visibilities gridded since the last reset */
     int64_t n_dropped;       /* visibilities dropped since the last reset (non-finite input, weight <= 0,
                                 kernel footprint leaving the mesh) */
-    int64_t n_records;       /* binned records written by the last rick_grid (a visibility whose footprint
-                                straddles tile edges is binned once per tile it touches) */
+    int64_t n_records;       /* binned records written by the last rick_grid: one per gridded visibility,
+                                in the tile holding the top-left cell of its footprint */
     double sum_weights;      /* sum of the weights of gridded visibilities since the last reset */
     double du, dl, dw;       /* cell size [wavelengths], pixel size [rad], plane width [wavelengths] */
     void *mesh;              /* device pointer to the planes, [N_w][N][N] complex64 (complex128 in FP64

@@ -1,10 +1,10 @@
 /* Whole-input statistics of the oracle's binning -- TEST INFRASTRUCTURE ONLY.
  *
  * For every kept visibility (decisions as in oracle/wstack.py): count one
- * record in every (plane, tile) bin its W x W footprint [c - h, c + h]^2
- * touches, and add W V to its plane's sum (the sum of a plane's gridded
- * cells equals it, because tap rows sum to 1).  Linear in the number of
- * visibilities, for full-size checks.
+ * record in the (plane, tile) bin holding the top-left cell (c - h) of its
+ * W x W footprint, and add W V to its plane's sum (the sum of a plane's
+ * gridded cells equals it, because tap rows sum to 1).  Linear in the number
+ * of visibilities, for full-size checks.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -40,10 +40,8 @@ int64_t oracle_bin_stats(int64_t nrow, int32_t nchan, const double *uvw, const d
                 sumw += o.wt;
                 lp[2 * o.k] += o.ar;
                 lp[2 * o.k + 1] += o.ai;
-                const int64_t tx0 = (o.cx - h) / T, tx1 = (o.cx + h) / T;
-                const int64_t ty0 = (o.cy - h) / T, ty1 = (o.cy + h) / T;
-                for (int64_t ty = ty0; ty <= ty1; ++ty)
-                    for (int64_t tx = tx0; tx <= tx1; ++tx) lc[(o.k * nt + ty) * nt + tx] += 1;
+                const int64_t tx = (o.cx - h) / T, ty = (o.cy - h) / T;   /* kept: c - h >= 0 */
+                lc[(o.k * nt + ty) * nt + tx] += 1;
             }
         }
         #pragma omp critical

@@ -7,9 +7,10 @@
 //   level 1  coarse bins = (plane, coarse tile of C x C tiles), at most 8192.
 //     bin_count    each block takes a contiguous range of visibilities:
 //                  position quantised to 1/OS cell, nearest cell, closest
-//                  w-plane, drop test; counts per coarse bin the footprint
-//                  touches, in an LDS histogram; writes its column of the
-//                  (coarse bin, block) count table; weight sum and counters.
+//                  w-plane, drop test; counts per coarse bin (that of the
+//                  footprint's origin) in an LDS histogram; writes its column
+//                  of the (coarse bin, block) count table; weight sum and
+//                  counters.
 //     bin_scan     exclusive scan of that table (coarse-bin major), then the
 //                  level-2 chunk list (each coarse bin cut into chunks).
 //     bin_scatter  repeats the quantisation; slots from LDS cursors seeded
@@ -17,12 +18,18 @@
 //                  records {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}.
 //   level 2  bins = (plane, tile) inside each coarse bin, at most C^2 = 16384.
 //     fine_count   one block per chunk: LDS histogram over the tiles of the
-//                  coarse tile that each record's footprint touches.
+//                  coarse tile (that of each record's footprint origin).
 //     fine_scan    per bin, the total over its coarse bin's chunks; exclusive
 //                  scan of records and gridding chunks in bin order (item and
 //                  heavy-bin lists); per (chunk, tile) record offsets.
 //     fine_scatter one block per chunk: slots from LDS cursors; writes the
 //                  12-byte records {packed position in the tile, W V}.
+//
+// A visibility is binned once, into the tile holding the top-left cell
+// (c_x - h, c_y - h) of its W x W footprint: the gridder keeps a tile plus a
+// (W - 1)-cell margin right and below in LDS, so every footprint of the tile
+// lies inside its accumulator (the margins are added to the neighbouring
+// tiles after gridding).
 //
 // Counts and slots in LDS are taken per run: consecutive records of a wave
 // whose footprints cover the same bins form a run, found without loops by
@@ -99,24 +106,12 @@ __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, doub
     return true;
 }
 
-// Tiles of edge 2^shift cells that the W x W footprint of cell (cx, cy)
-// touches: the top-left one (x0, y0) and whether it also reaches the next
-// column (dx) and row (dy).  A tile is at least W cells wide, so at most two
-// per axis.
+// Tile of edge 2^shift cells holding the footprint origin (c - h) of cell (cx, cy).
 struct Span {
-    int32_t x0, y0, dx, dy;
+    int32_t x0, y0;
 };
 __device__ __forceinline__ Span span_of(const Quant &q, int32_t h, int32_t shift) {
-    Span s;
-    s.x0 = (q.cx - h) >> shift;
-    s.y0 = (q.cy - h) >> shift;
-    s.dx = ((q.cx + h) >> shift) - s.x0;
-    s.dy = ((q.cy + h) >> shift) - s.y0;
-    return s;
-}
-// member j of a span (j = 0: top-left, 1: right, 2: below, 3: below right), if present
-__device__ __forceinline__ bool in_span(int32_t dx, int32_t dy, int j) {
-    return (j & 1) <= dx && (j >> 1) <= dy;
+    return Span{(q.cx - h) >> shift, (q.cy - h) >> shift};
 }
 
 __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
@@ -223,12 +218,8 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
         }
         const Span cs = span_of(q, g.h, cshift);
         const int32_t base = (q.k * g.nct + cs.y0) * g.nct + cs.x0;
-        const Run run = runs_of(keep ? base * 4 + cs.dx * 2 + cs.dy : -1);
-        if (keep && run.head) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (in_span(cs.dx, cs.dy, j)) atomicAdd(&s_cnt[base + (j & 1) + (j >> 1) * g.nct], run.len);
-        }
+        const Run run = runs_of(keep ? base : -1);
+        if (keep && run.head) atomicAdd(&s_cnt[base], run.len);
     }
     // block reduction of the counters, one atomic per block and counter
     for (int off = 32; off > 0; off >>= 1) {
@@ -290,24 +281,17 @@ __global__ __launch_bounds__(kL1Block) void k_l1_scatter(Geom g, const double *_
         }
         const Span cs = span_of(q, g.h, cshift);
         const int32_t base = (q.k * g.nct + cs.y0) * g.nct + cs.x0;
-        const Run run = runs_of(keep ? base * 4 + cs.dx * 2 + cs.dy : -1);
-        // the run's first lane takes the slots of the whole run in each coarse bin
-        int32_t b4[4] = {0, 0, 0, 0};
-        if (keep && run.head) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (in_span(cs.dx, cs.dy, j)) b4[j] = atomicAdd(&s_cur[base + (j & 1) + (j >> 1) * g.nct], run.len);
-        }
+        const Run run = runs_of(keep ? base : -1);
+        // the run's first lane takes the slots of the whole run
+        int32_t b0 = 0;
+        if (keep && run.head) b0 = atomicAdd(&s_cur[base], run.len);
         const int32_t rank = (int32_t)__lane_id() - run.leader;
         const Rec1<real> r1{(uint32_t)q.cx | (uint32_t)q.cy << 16,
                             (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
                                 (uint32_t)q.k << 16,
                             ar, ai};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t slot = __shfl(b4[j], run.leader) + rank;
-            if (keep && in_span(cs.dx, cs.dy, j)) rec1[slot] = r1;
-        }
+        const int32_t slot = __shfl(b0, run.leader) + rank;
+        if (keep) rec1[slot] = r1;
     }
 }
 
@@ -443,21 +427,14 @@ __device__ __forceinline__ Chunk chunk_of(const Geom &g, const int32_t *__restri
     return c;
 }
 
-// Tiles of the coarse tile (ctx, cty) that a level-1 record's footprint
-// touches: local columns fx0..fx0+dfx, rows fy0..fy0+dfy.
+// Tile of the coarse tile (ctx, cty) holding a level-1 record's footprint
+// origin: local column fx0, row fy0 (in [0, C): the coarse bin is the origin's).
 struct Local {
-    int32_t fx0, fy0, dfx, dfy;
+    int32_t fx0, fy0;
 };
 __device__ __forceinline__ Local local_span(const Geom &g, uint32_t cxy, int32_t ctx, int32_t cty) {
     const int32_t cx = (int32_t)(cxy & 0xffffu), cy = (int32_t)(cxy >> 16);
-    const int32_t lo_x = ctx << g.log2C, lo_y = cty << g.log2C, hi = g.C - 1;
-    int32_t x0 = ((cx - g.h) >> g.log2T) - lo_x, x1 = ((cx + g.h) >> g.log2T) - lo_x;
-    int32_t y0 = ((cy - g.h) >> g.log2T) - lo_y, y1 = ((cy + g.h) >> g.log2T) - lo_y;
-    x0 = x0 < 0 ? 0 : x0;
-    y0 = y0 < 0 ? 0 : y0;
-    x1 = x1 > hi ? hi : x1;
-    y1 = y1 > hi ? hi : y1;
-    return Local{x0, y0, x1 - x0, y1 - y0};
+    return Local{((cx - g.h) >> g.log2T) - (ctx << g.log2C), ((cy - g.h) >> g.log2T) - (cty << g.log2C)};
 }
 
 __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
@@ -475,15 +452,11 @@ __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__re
     for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
         const int32_t r = r00 + threadIdx.x;
         const bool valid = r < ck.r1;
-        Local ls{0, 0, 0, 0};
+        Local ls{0, 0};
         if (valid) ls = local_span(g, rec1[(int64_t)r * rec1_words], ck.ctx, ck.cty);
-        const Run run = runs_of(valid ? ((ls.fy0 * g.C + ls.fx0) * 2 + ls.dfx) * 2 + ls.dfy : -1);
-        if (valid && run.head) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (in_span(ls.dfx, ls.dfy, j))
-                    atomicAdd(&s_h[(ls.fy0 + (j >> 1)) * g.C + ls.fx0 + (j & 1)], run.len);
-        }
+        const int32_t f = ls.fy0 * g.C + ls.fx0;
+        const Run run = runs_of(valid ? f : -1);
+        if (valid && run.head) atomicAdd(&s_h[f], run.len);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < C2; i += kBlock) cnt2[(int64_t)chunk * C2 + i] = s_h[i];
@@ -546,32 +519,25 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
     for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
         const int32_t r = r00 + threadIdx.x;
         const bool valid = r < ck.r1;
-        Local ls{0, 0, 0, 0};
+        Local ls{0, 0};
         Rec1<real> p{0u, 0u, 0, 0};
         if (valid) {
             p = rec1[r];
             ls = local_span(g, p.cxy, ck.ctx, ck.cty);
         }
-        const Run run = runs_of(valid ? ((ls.fy0 * g.C + ls.fx0) * 2 + ls.dfx) * 2 + ls.dfy : -1);
-        int32_t b4[4] = {0, 0, 0, 0};
-        if (valid && run.head) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (in_span(ls.dfx, ls.dfy, j))
-                    b4[j] = atomicAdd(&s_cur[(ls.fy0 + (j >> 1)) * g.C + ls.fx0 + (j & 1)], run.len);
-        }
+        const int32_t f = ls.fy0 * g.C + ls.fx0;
+        const Run run = runs_of(valid ? f : -1);
+        int32_t b0 = 0;
+        if (valid && run.head) b0 = atomicAdd(&s_cur[f], run.len);
         const int32_t rank = (int32_t)__lane_id() - run.leader;
         const int32_t cx = (int32_t)(p.cxy & 0xffffu), cy = (int32_t)(p.cxy >> 16);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t slot = __shfl(b4[j], run.leader) + rank;
-            if (valid && in_span(ls.dfx, ls.dfy, j)) {
-                const int32_t tx = tx_lo + ls.fx0 + (j & 1), ty = ty_lo + ls.fy0 + (j >> 1);
-                const int32_t ox = cx - g.h - (tx << g.log2T) + 2 * g.h;   // in [0, T + 2h)
-                const int32_t oy = cy - g.h - (ty << g.log2T) + 2 * g.h;
-                rec_pos[slot] = (uint32_t)ox | (uint32_t)oy << 8 | (p.sub & 0xffffu) << 16;
-                store2(rec_vis + 2 * (int64_t)slot, p.vr, p.vi);
-            }
+        const int32_t slot = __shfl(b0, run.leader) + rank;
+        if (valid) {
+            const int32_t tx = tx_lo + ls.fx0, ty = ty_lo + ls.fy0;
+            const int32_t ox = cx - g.h - (tx << g.log2T);   // footprint origin in the tile, [0, T)
+            const int32_t oy = cy - g.h - (ty << g.log2T);
+            rec_pos[slot] = (uint32_t)ox | (uint32_t)oy << 8 | (p.sub & 0xffffu) << 16;
+            store2(rec_vis + 2 * (int64_t)slot, p.vr, p.vi);
         }
     }
 }
@@ -715,8 +681,8 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
                              hipStream_t s) {
     const int64_t nvis = nrow * nchan;
     const L1Part part = l1_part(nvis);
-    // chunks of this call: at most one per coarse bin plus one per CHK level-1 records (<= 4 per visibility)
-    const int32_t nchunk = bin_max_chunks(g, 4 * nvis);
+    // chunks of this call: at most one per coarse bin plus one per CHK level-1 records (one per visibility)
+    const int32_t nchunk = bin_max_chunks(g, nvis);
     const size_t lds = size_t(g.C) * g.C * sizeof(int32_t);
     const int32_t nbb = (g.nbins + kBlock - 1) / kBlock;
     if (phase == 0) {

@@ -2,12 +2,14 @@
 // the w-plane stack.
 //
 // One block takes one work item: a chunk of at most CH records of one
-// (plane, tile) bin.  The tile's T x T accumulator (float64 re and im planes)
-// lives in LDS; each wave takes one record at a time with one lane per kernel
-// tap (lane t < W*W is tap (t / W, t % W)), so one record costs two LDS
-// atomic adds and no lane pair of an instruction shares an address.  The LDS
-// row pitch is congruent to W modulo 32 elements, which spreads the W x W
-// footprint over the banks.
+// (plane, tile) bin.  A record is binned into the tile holding its
+// footprint's top-left cell, so the block's accumulator (float64 re and im
+// planes in LDS) covers the tile plus a margin of W - 1 cells right and below:
+// (T + W - 1)^2 cells, and every footprint lies inside it.  Each wave takes
+// one record at a time with one lane per kernel tap (lane t < W*W is tap
+// (t / W, t % W)), so one record costs two LDS atomic adds and no lane pair
+// of an instruction shares an address.  The LDS row pitch is congruent to W
+// modulo 32 elements, which spreads the W x W footprint over the banks.
 //
 // Accumulators are float64 in every precision mode: float64 LDS atomic adds
 // run at the rate of plain LDS traffic on gfx950, float32 ones several times
@@ -18,10 +20,8 @@
 // while these are gridded); each lane decodes the record it loaded (footprint
 // origin, tap-table rows), and the decoded fields are broadcast with readlane.
 // Per record and lane the work is two table reads, three multiplies, two
-// conversions, a three-instruction in-tile test and two atomics; the table
-// reads of the next four records are issued before the atomics of the current
-// four.  Taps outside the tile are skipped: a record whose footprint straddles
-// tile edges was binned into every tile it touches.
+// conversions and two atomics; the table reads of the next four records are
+// issued before the atomics of the current four.
 //
 // After the records the tile is written to HBM once, row-coalesced:
 //   - bins with a single chunk own their tile and store it, or add it to the
@@ -29,9 +29,13 @@
 //   - bins split over several chunks (the dense uv centre) add their partial
 //     tiles with atomics onto a tile zeroed beforehand (unless an earlier
 //     rick_grid wrote it).
-// Empty bins have no work item and write nothing: a bitmap of written tiles
-// (set after gridding, cleared by rick_reset) tells the FFT which tiles hold
-// values; the others stand for zeros and are never read.
+// The margins (a strip W - 1 wide right of the tile, including the corner,
+// and one W - 1 high below it) go to a per-bin margin buffer, stored (or added
+// with atomics for split bins); a merge kernel then adds them to the
+// neighbouring tiles, one block per tile row, each target tile written by one
+// block.  Empty bins have no work item and write nothing: a bitmap of tiles
+// holding values (set by the merge, cleared by rick_reset) tells the FFT which
+// tiles to read; the others stand for zeros and are never read.
 #include "rick_internal.h"
 
 namespace rick {
@@ -66,18 +70,29 @@ __device__ __forceinline__ double bcast(double v, int j) {
 __device__ __forceinline__ void atomic_add_real(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_real(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Margin buffer of a bin, in complex values: the right strip, rows
+// 0 .. T + W - 2 by columns T .. T + W - 2 (row-major, W - 1 per row), then
+// the bottom strip, rows T .. T + W - 2 by columns 0 .. T - 1.
+__host__ __device__ inline int64_t margin_len(int32_t T, int32_t W) {
+    return (int64_t)(T + W - 1) * (W - 1) + (int64_t)(W - 1) * T;
+}
+
 // Heavy bins (several chunks) are zeroed before gridding, unless an earlier
 // rick_grid wrote the tile; the scan lists them.
 template <typename real>
 __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t *__restrict__ heavy_bins,
                                                            const Stats *__restrict__ st,
                                                            const uint64_t *__restrict__ tile_bits,
-                                                           real *__restrict__ mesh) {
+                                                           real *__restrict__ mesh, real *__restrict__ margin) {
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
     const int32_t nheavy = (int32_t)st->n_heavy;
+    const int64_t mlen = margin_len(g.T, g.W);
     for (int32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
         const int32_t b = heavy_bins[hb];
+        // the margin buffer is filled anew by every rick_grid
+        r2 *mb = reinterpret_cast<r2 *>(margin) + (int64_t)b * mlen;
+        for (int64_t c = threadIdx.x; c < mlen; c += kZeroBlock) mb[c] = r2{0, 0};
         const int32_t k = b / (g.nt * g.nt);
         const int32_t rem = b - k * g.nt * g.nt;
         if (tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt)) continue;
@@ -90,12 +105,14 @@ __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t
 }
 
 // Offset (in doubles) of the imaginary accumulator plane from the real one:
-// the size of a 64-row plane, a compile-time constant so that the second
-// atomic of a tap reuses the first one's address register with an immediate
-// offset.  It is a multiple of 32 doubles, so both planes map a footprint to
-// the same LDS banks.
+// the size of the largest plane (T = 64: 63 + W rows of pitch 64 + W), a
+// compile-time constant so that the second atomic of a tap reuses the first
+// one's address register with an immediate offset.  It is a multiple of 32
+// doubles, so both planes map a footprint to the same LDS banks.
+constexpr int plane_offset(int W) { return ((63 + W) * (64 + W) + 31) / 32 * 32; }
 template <int W>
-constexpr int im_plane_offset() { return 64 * (64 + W % 32); }
+constexpr int im_plane_offset() { return plane_offset(W); }
+
 
 // Records per group.  The tap-table reads of the next group are issued before
 // the atomics of this one, so a wait for table values never waits for the
@@ -107,7 +124,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
-                                                     real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits) {
+                                                     real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
+                                                     real *__restrict__ margin) {
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
@@ -133,12 +151,15 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
     if (n <= 0) return;   // (empty bins have no work item)
-    // LDS: real plane at byte 0, imaginary plane KOFF doubles further, then the tap table
+    // LDS: real plane at byte 0, imaginary plane KOFF doubles further, then
+    // the tap table; a plane is R = T + W - 1 rows of pitch P
+    constexpr int R_PAD = W - 1;
+    const int32_t R = T + R_PAD;
     double *acc_re = reinterpret_cast<double *>(smem);
     double *acc_im = acc_re + KOFF;
-    const int32_t lut_byte = (KOFF + T * P) * (int32_t)sizeof(double);
+    const int32_t lut_byte = (KOFF + R * P) * (int32_t)sizeof(double);
     real *s_lut = reinterpret_cast<real *>(smem + lut_byte);
-    for (int i = threadIdx.x; i < T * P; i += kGridBlock) {
+    for (int i = threadIdx.x; i < R * P; i += kGridBlock) {
         acc_re[i] = 0.0;
         acc_im[i] = 0.0;
     }
@@ -178,37 +199,17 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     for (; bt < nbatch; bt += nwave) {
         const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
         // decode this lane's record: byte offset of the footprint origin in
-        // the real plane (negative for origins left of or above the tile),
-        // tap-table row byte offsets, visibility, and the mask of its taps
-        // that fall inside the tile (bit t of group t / 64 for tap t =
-        // ty W + tx: the rectangle of tx, ty with ox + tx, oy + ty in [0, T))
+        // the real plane, tap-table row byte offsets and visibility (lanes
+        // past the batch keep zeros: they add 0 at the region's origin)
         int32_t d_base8 = 0, d_lxy = 0;
         real d_vr = 0, d_vi = 0;
-        uint64_t d_mask[NG];
-#pragma unroll
-        for (int gi = 0; gi < NG; ++gi) d_mask[gi] = 0;
         if (lane < cnt) {
-            const int ox = (int)(raw_pos & 0xffu) - 2 * H;
-            const int oy = (int)((raw_pos >> 8) & 0xffu) - 2 * H;
+            const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
             const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
             d_base8 = (oy * P + ox) * (int)sizeof(double);
             d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
             d_vr = raw_vr;
             d_vi = raw_vi;
-            const int tx_lo = ox < 0 ? -ox : 0, tx_hi = T - 1 - ox < W - 1 ? T - 1 - ox : W - 1;
-            const int ty_lo = oy < 0 ? -oy : 0, ty_hi = T - 1 - oy < W - 1 ? T - 1 - oy : W - 1;
-            const uint64_t row = ((2ull << tx_hi) - 1) & ~((1ull << tx_lo) - 1);
-#pragma unroll
-            for (int ty = 0; ty < W; ++ty) {
-                if (ty >= ty_lo && ty <= ty_hi) {
-#pragma unroll
-                    for (int gi = 0; gi < NG; ++gi) {
-                        const int rel = ty * W - 64 * gi;   // bit of the row's first tap in group gi
-                        if (rel >= 0 && rel < 64) d_mask[gi] |= row << rel;
-                        else if (rel < 0 && rel > -W) d_mask[gi] |= row >> (-rel);
-                    }
-                }
-            }
         }
         if (bt + nwave < nbatch) fetch(bt + nwave);
 
@@ -234,15 +235,14 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                 const real vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
-                    const uint64_t m = (uint64_t)(uint32_t)bcast((int32_t)(d_mask[gi] >> 32), (j + q) & 63) << 32 |
-                                       (uint32_t)bcast((int32_t)d_mask[gi], (j + q) & 63);
+                    // lanes holding a tap of group gi (a compile-time mask)
+                    constexpr uint64_t kAll = ~0ull;
+                    const uint64_t m = W2 - 64 * gi >= 64 ? kAll : (1ull << (W2 - 64 * gi)) - 1;
                     // the products are formed outside the branch, so the wait
                     // for the table values is the same on every path
                     const real wgt = gy[q][gi] * gx[q][gi];
                     double tr = (double)(wgt * vr), ti = (double)(wgt * vi);
                     __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
-                    // lanes whose tap of this record lies in the tile (the mask
-                    // is wave-uniform and becomes the execution mask directly)
                     if (__builtin_amdgcn_inverse_ballot_w64(m)) {
                         double *a = reinterpret_cast<double *>(smem + (base8 + tap_off8[gi]));
                         atomicAdd(a, tr);
@@ -283,6 +283,29 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
             *dst = r2{re, im};
         }
     }
+    // margins to the bin's margin buffer (the merge adds them to the neighbours)
+    if constexpr (R_PAD > 0) {
+        r2 *mb = reinterpret_cast<r2 *>(margin) + (int64_t)b * margin_len(T, W);
+        const int32_t n_right = R * R_PAD, n_all = n_right + R_PAD * T;
+        for (int32_t c = threadIdx.x; c < n_all; c += kGridBlock) {
+            int32_t y, x;
+            if (c < n_right) {
+                y = c / R_PAD;
+                x = T + (c - y * R_PAD);
+            } else {
+                const int32_t d = c - n_right;
+                y = T + (d >> g.log2T);
+                x = d & (T - 1);
+            }
+            const real re = (real)acc_re[y * P + x], im = (real)acc_im[y * P + x];
+            if (shared_tile) {
+                if (re != 0) atomic_add_real(&mb[c].x, re);
+                if (im != 0) atomic_add_real(&mb[c].y, im);
+            } else {
+                mb[c] = r2{re, im};
+            }
+        }
+    }
 }
 
 template <typename real>
@@ -291,38 +314,97 @@ __global__ void k_zero_mesh(real *__restrict__ a, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0;
 }
 
-// After gridding: one block per plane, one wave per tile row at a time.
-// Lane l of a wave takes tiles l, l + 64, ... of its row; a tile is set if it
-// was set before or received records now (the ballot is the bitmap word).
-// The row bits are rebuilt from the tile bits, in LDS.
-constexpr int kMarkBlock = 256;
+// After gridding: one block per tile row (plane k, row ty).  A tile ends up
+// set if it was set before, received records now, or receives margins now
+// from its left, upper or upper-left neighbour (records in those bins).  Each
+// tile receiving margins is written by this block only: cells are read (or
+// taken as zero for a tile that held nothing, whose stale contents are
+// replaced) and the margin pieces added; the row's bitmap words are then
+// written.  The gridder has finished, so every margin buffer is complete.
+constexpr int kMergeBlock = 256;
 constexpr int kMaxOccWords = 8;   // tiles per axis <= 512
-__global__ __launch_bounds__(kMarkBlock) void k_mark_tiles(Geom g, const BinScan *__restrict__ scan,
-                                                           uint64_t *__restrict__ tile_bits,
-                                                           uint64_t *__restrict__ row_bits) {
-    __shared__ unsigned long long s_row[kMaxOccWords];
-    const int32_t k = blockIdx.x;
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    if (threadIdx.x < kMaxOccWords) s_row[threadIdx.x] = 0;
+template <typename real>
+__global__ __launch_bounds__(kMergeBlock) void k_merge_margins(Geom g, const BinScan *__restrict__ scan,
+                                                               const real *__restrict__ margin,
+                                                               uint64_t *__restrict__ tile_bits,
+                                                               real *__restrict__ mesh) {
+    using r2 = typename real2_t<real>::type;
+    __shared__ unsigned long long s_word[kMaxOccWords];
+    __shared__ int32_t s_list[512], s_n;
+    const int32_t k = blockIdx.x / g.nt, ty = blockIdx.x % g.nt;
+    const int32_t T = g.T, W1 = g.W - 1;
+    if (threadIdx.x < kMaxOccWords) s_word[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    for (int32_t ty = wave; ty < g.nt; ty += kMarkBlock / 64) {
-        bool any = false;
-        for (int32_t j = 0; j < g.occw; ++j) {
-            const int32_t tx = lane + 64 * j;
-            bool got = false;
-            if (tx < g.nt) {
-                const int64_t b = ((int64_t)k * g.nt + ty) * g.nt + tx;
-                got = scan[b + 1].rec > scan[b].rec;
-            }
-            const int64_t wi = ((int64_t)k * g.nt + ty) * g.occw + j;
-            const uint64_t word = tile_bits[wi] | __ballot(got);
-            if (lane == 0) tile_bits[wi] = word;
-            any = any || word != 0;
-        }
-        if (lane == 0 && any) atomicOr(&s_row[ty >> 6], 1ull << (ty & 63));
+    auto has = [&](int32_t yy, int32_t xx) {
+        const int64_t b = ((int64_t)k * g.nt + yy) * g.nt + xx;
+        return scan[b + 1].rec > scan[b].rec;
+    };
+    const int64_t row_w = ((int64_t)k * g.nt + ty) * g.occw;
+    for (int32_t tx = threadIdx.x; tx < g.nt; tx += kMergeBlock) {
+        const bool old = (tile_bits[row_w + (tx >> 6)] >> (tx & 63)) & 1ull;
+        const bool set = old || has(ty, tx);
+        const bool l = W1 > 0 && tx > 0 && has(ty, tx - 1);
+        const bool u = W1 > 0 && ty > 0 && has(ty - 1, tx);
+        const bool ul = W1 > 0 && tx > 0 && ty > 0 && has(ty - 1, tx - 1);
+        if (l || u || ul) s_list[atomicAdd(&s_n, 1)] = tx | (int32_t)set << 16 | (int32_t)l << 17 |
+                                                         (int32_t)u << 18 | (int32_t)ul << 19;
+        if (set || l || u || ul) atomicOr(&s_word[tx >> 6], 1ull << (tx & 63));
     }
     __syncthreads();
-    if (threadIdx.x < g.occw) row_bits[(int64_t)k * g.occw + threadIdx.x] = s_row[threadIdx.x];
+    const int64_t mlen = margin_len(T, g.W);
+    const int32_t R = T + W1;
+    r2 *m = reinterpret_cast<r2 *>(mesh);
+    const r2 *mg = reinterpret_cast<const r2 *>(margin);
+    for (int32_t i = 0; i < s_n; ++i) {
+        const int32_t e = s_list[i];
+        const int32_t tx = e & 0xffff;
+        const bool set = (e >> 16) & 1, l = (e >> 17) & 1, u = (e >> 18) & 1, ul = (e >> 19) & 1;
+        // margin buffers of the left (right strip), upper (bottom strip) and
+        // upper-left (corner rows of the right strip) neighbours
+        const int32_t txl = l || ul ? tx - 1 : tx, tyu = u || ul ? ty - 1 : ty;
+        const r2 *ml = mg + (((int64_t)k * g.nt + ty) * g.nt + txl) * mlen;
+        const r2 *mu = mg + (((int64_t)k * g.nt + tyu) * g.nt + tx) * mlen + R * W1;
+        const r2 *mul = mg + (((int64_t)k * g.nt + tyu) * g.nt + txl) * mlen;
+        for (int32_t c = threadIdx.x; c < T * T; c += kMergeBlock) {
+            const int32_t y = c >> g.log2T, x = c & (T - 1);
+            const bool hl = l && x < W1, hu = u && y < W1, hul = ul && x < W1 && y < W1;
+            if (set && !(hl || hu || hul)) continue;   // a cell no margin reaches keeps its value
+            r2 *dst = m + ((int64_t)k * g.N + ((int64_t)ty << g.log2T) + y) * g.N + ((int64_t)tx << g.log2T) + x;
+            r2 v = set ? *dst : r2{0, 0};
+            if (hl) {
+                const r2 a = ml[y * W1 + x];
+                v.x += a.x;
+                v.y += a.y;
+            }
+            if (hu) {
+                const r2 a = mu[y * T + x];
+                v.x += a.x;
+                v.y += a.y;
+            }
+            if (hul) {
+                const r2 a = mul[(T + y) * W1 + x];
+                v.x += a.x;
+                v.y += a.y;
+            }
+            *dst = v;
+        }
+    }
+    if (threadIdx.x < g.occw) tile_bits[row_w + threadIdx.x] = s_word[threadIdx.x];
+}
+
+// Row bitmap from the tile bitmap: one block per plane, one lane per tile row.
+__global__ __launch_bounds__(64) void k_row_bits(Geom g, const uint64_t *__restrict__ tile_bits,
+                                                 uint64_t *__restrict__ row_bits) {
+    const int32_t k = blockIdx.x;
+    for (int32_t j = 0; j < g.occw; ++j) {
+        const int32_t ty = 64 * j + (int32_t)threadIdx.x;
+        bool any = false;
+        if (ty < g.nt)
+            for (int32_t w = 0; w < g.occw; ++w) any = any || tile_bits[((int64_t)k * g.nt + ty) * g.occw + w] != 0;
+        const uint64_t word = __ballot(any);
+        if (threadIdx.x == 0) row_bits[(int64_t)k * g.occw + j] = word;
+    }
 }
 
 __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, uint64_t *__restrict__ row_bits,
@@ -336,8 +418,8 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
 
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                  const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, int32_t max_items,
-                  hipStream_t s) {
+                  const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
+                  int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static bool attr = false;
     if (!attr) {
@@ -346,17 +428,20 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
         attr = true;
     }
     hipLaunchKernelGGL((k_grid<real, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin, rec_pos,
-                       rec_vis, lut, mesh, tile_bits);
+                       rec_vis, lut, mesh, tile_bits, margin);
     return hipGetLastError();
 }
 
 }  // namespace
 
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
-    // the imaginary plane starts 64 (64 + W % 32) doubles after the real one
-    const size_t koff = size_t(64) * (64 + g.W % 32);
-    return (koff + size_t(g.T) * g.pitch) * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
+    // real plane, imaginary plane at plane_offset(W) doubles, each T + W - 1
+    // rows of the pitch; then the tap table
+    const size_t koff = size_t(plane_offset(g.W));
+    return (koff + size_t(g.T + g.W - 1) * g.pitch) * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
 }
+
+int64_t grid_margin_len(const Geom &g) { return margin_len(g.T, g.W); }
 
 template <typename real>
 hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
@@ -366,15 +451,19 @@ hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
 
 template <typename real>
 hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, const uint64_t *tile_bits,
-                             real *mesh, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, tile_bits, mesh);
+                             real *mesh, real *margin, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, tile_bits, mesh,
+                       margin);
     return hipGetLastError();
 }
 
-hipError_t launch_mark_tiles(const Geom &g, const BinScan *scan, uint64_t *tile_bits, uint64_t *row_bits,
-                             hipStream_t s) {
-    if (g.occw > kMaxOccWords) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mark_tiles, dim3(g.Nw), dim3(kMarkBlock), 0, s, g, scan, tile_bits, row_bits);
+template <typename real>
+hipError_t launch_merge_margins(const Geom &g, const BinScan *scan, const real *margin, uint64_t *tile_bits,
+                                uint64_t *row_bits, real *mesh, hipStream_t s) {
+    if (g.occw > kMaxOccWords || g.nt > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_merge_margins<real>, dim3(g.Nw * g.nt), dim3(kMergeBlock), 0, s, g, scan, margin, tile_bits,
+                       mesh);
+    hipLaunchKernelGGL(k_row_bits, dim3(g.Nw), dim3(64), 0, s, g, tile_bits, row_bits);
     return hipGetLastError();
 }
 
@@ -388,11 +477,11 @@ hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_b
 
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                       const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits,
+                       const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                        int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
-    case w: return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, max_items, s);
+    case w: return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -402,14 +491,18 @@ hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_b
 template hipError_t launch_zero_mesh<float>(float *, int64_t, hipStream_t);
 template hipError_t launch_zero_mesh<double>(double *, int64_t, hipStream_t);
 template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, const Stats *, const uint64_t *, float *,
-                                             hipStream_t);
+                                             float *, hipStream_t);
 template hipError_t launch_zero_heavy<double>(const Geom &, const int32_t *, const Stats *, const uint64_t *,
-                                              double *, hipStream_t);
+                                              double *, double *, hipStream_t);
+template hipError_t launch_merge_margins<float>(const Geom &, const BinScan *, const float *, uint64_t *, uint64_t *,
+                                                float *, hipStream_t);
+template hipError_t launch_merge_margins<double>(const Geom &, const BinScan *, const double *, uint64_t *,
+                                                 uint64_t *, double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
-                                       const float *, const float *, float *, const uint64_t *, int32_t,
+                                       const float *, const float *, float *, const uint64_t *, float *, int32_t,
                                        hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
-                                        const double *, const double *, double *, const uint64_t *, int32_t,
-                                        hipStream_t);
+                                        const double *, const double *, double *, const uint64_t *, double *,
+                                        int32_t, hipStream_t);
 
 }  // namespace rick

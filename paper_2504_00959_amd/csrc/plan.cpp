@@ -94,6 +94,7 @@ struct rick_plan_s {
     void *row_mesh = nullptr;   // fused: row transforms in column-panel order
     uint64_t *tile_bits = nullptr;   // tiles written since the reset, [N_w][nt][occw] words
     uint64_t *row_bits = nullptr;    // tile rows with a written tile, [N_w][occw] words
+    void *margin = nullptr;          // per bin: the accumulator margins right of and below the tile
     int32_t panel = 0;
     void *lut = nullptr;
     void *twiddle = nullptr;
@@ -142,7 +143,8 @@ struct DeviceGuard {
 };
 
 void free_all(rick_plan_t *p) {
-    void *bufs[] = {p->mesh,      p->row_mesh,  p->tile_bits,  p->row_bits,  p->lut,    p->twiddle,  p->corr,
+    void *bufs[] = {p->mesh,      p->row_mesh,  p->tile_bits,  p->row_bits,  p->margin, p->lut,     p->twiddle,
+                    p->corr,
                     p->wk,        p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
@@ -287,14 +289,15 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         }
     }
     {
-        // LDS row pitch congruent to W mod 32 floats: a W x W footprint then
-        // spreads over distinct banks (one tap per lane, see grid.hip)
-        int pitch = g.T;
+        // LDS row pitch: at least the tile plus its W - 1 margin, congruent to W
+        // mod 32, so a W x W footprint spreads over distinct banks (one tap per
+        // lane, see grid.hip)
+        int pitch = g.T + g.W - 1;
         while ((pitch - g.W) % 32 != 0) ++pitch;
         g.pitch = pitch;
     }
     {
-        // the gridding block keeps two T x pitch float64 accumulators and the tap table in LDS
+        // the gridding block keeps two (T + W - 1) x pitch float64 accumulators and the tap table in LDS
         const size_t lds = grid_lds_bytes(g, p->fp64 ? 8 : 4);
         if (lds > size_t(160) * 1024) {
             delete p;
@@ -308,7 +311,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     g.dw = (d->w_max - d->w_min) / double(g.Nw);
     p->du = 1.0 / d->fov_rad;
     p->dl = d->fov_rad / g.N;
-    p->rec_cap = 4 * d->max_vis;
+    p->rec_cap = d->max_vis;   // one record per visibility (the tile of its footprint origin)
     p->max_items = g.nbins + (p->rec_cap + g.CH - 1) / g.CH;
 
     // ---- float64 tables on the host ----
@@ -369,8 +372,9 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_rvis = size_t(p->rec_cap) * 2 * rb;
     const size_t sz_rbits = size_t(g.Nw) * g.occw * sizeof(uint64_t);
     const size_t sz_tbits = sz_rbits * g.nt;
+    const size_t sz_margin = size_t(g.nbins) * size_t(grid_margin_len(g)) * 2 * rb + 64;
     const size_t total = p->mesh_bytes * (p->fused ? 2 : 1) + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
-                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis + sz_tbits + sz_rbits;
+                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis + sz_tbits + sz_rbits + sz_margin;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) {
@@ -398,6 +402,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     }
     ALLOC(p->tile_bits, sz_tbits);
     ALLOC(p->row_bits, sz_rbits);
+    ALLOC(p->margin, sz_margin);
     ALLOC(p->lut, sz_lut);
     ALLOC(p->twiddle, sz_tw);
     ALLOC(p->corr, size_t(g.N) * 8);
@@ -528,7 +533,7 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     const Geom &g = p->g;
     const int64_t nvis = nrow * nchan;
     // work items: one per chunk of a non-empty bin; at most 4 records per visibility
-    const int64_t max_records = 4 * nvis;
+    const int64_t max_records = nvis;
     const int32_t max_items =
         int32_t((max_records < g.nbins ? max_records : g.nbins) + (max_records + g.CH - 1) / g.CH + 1);
 
@@ -556,23 +561,30 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
         if (e != hipSuccess) return hip_fail(e, ps.name);
     }
     timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
-    if (p->fp64) e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, p->tile_bits, (double *)p->mesh, s);
-    else e = launch_zero_heavy<float>(g, p->heavy_bins, p->stats, p->tile_bits, (float *)p->mesh, s);
+    if (p->fp64)
+        e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, p->tile_bits, (double *)p->mesh,
+                                      (double *)p->margin, s);
+    else
+        e = launch_zero_heavy<float>(g, p->heavy_bins, p->stats, p->tile_bits, (float *)p->mesh, (float *)p->margin,
+                                     s);
     timer_end(p, T_ZERO_HEAVY, s);
     if (e != hipSuccess) return hip_fail(e, "zero_heavy");
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
         e = launch_grid<double>(g, p->scan, p->item_bin, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
-                                (double *)p->mesh, p->tile_bits, max_items, s);
+                                (double *)p->mesh, p->tile_bits, (double *)p->margin, max_items, s);
     else
         e = launch_grid<float>(g, p->scan, p->item_bin, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
-                               (float *)p->mesh, p->tile_bits, max_items, s);
+                               (float *)p->mesh, p->tile_bits, (float *)p->margin, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
-    timer_begin(p, T_MARK, "mark_tiles", s);
-    e = launch_mark_tiles(g, p->scan, p->tile_bits, p->row_bits, s);
+    timer_begin(p, T_MARK, "merge_margins", s);
+    e = p->fp64 ? launch_merge_margins<double>(g, p->scan, (const double *)p->margin, p->tile_bits, p->row_bits,
+                                               (double *)p->mesh, s)
+                : launch_merge_margins<float>(g, p->scan, (const float *)p->margin, p->tile_bits, p->row_bits,
+                                              (float *)p->mesh, s);
     timer_end(p, T_MARK, s);
-    if (e != hipSuccess) return hip_fail(e, "mark_tiles");
+    if (e != hipSuccess) return hip_fail(e, "merge_margins");
     p->state = 1;
     return RICK_OK;
 }

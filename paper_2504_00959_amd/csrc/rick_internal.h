@@ -117,20 +117,25 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
 template <typename real>
 hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int32_t nchan, Stats *st, int phase,
                              hipStream_t s);
-// Gridding: zero the heavy tiles that hold nothing yet, then one block per
-// (bin, chunk) item; tiles set in tile_bits are added to, others stored.
+// Gridding: zero the heavy tiles that hold nothing yet (and the margin
+// buffers of heavy bins), then one block per (bin, chunk) item; tiles set in
+// tile_bits are added to, others stored; each bin's margins go to its margin
+// buffer (grid_margin_len complex values per bin).
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
-                       const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits,
+                       const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                        int32_t max_items, hipStream_t s);
 // LDS bytes of one gridding block (float64 accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
+int64_t grid_margin_len(const Geom &g);
 template <typename real>
 hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, const uint64_t *tile_bits,
-                             real *mesh, hipStream_t s);
-// After gridding: set the bits of the tiles that received records, and the row bits.
-hipError_t launch_mark_tiles(const Geom &g, const BinScan *scan, uint64_t *tile_bits, uint64_t *row_bits,
-                             hipStream_t s);
+                             real *mesh, real *margin, hipStream_t s);
+// After gridding: add the margins to the neighbouring tiles, set the tile
+// bits (records or margins received) and rebuild the row bits.
+template <typename real>
+hipError_t launch_merge_margins(const Geom &g, const BinScan *scan, const real *margin, uint64_t *tile_bits,
+                                uint64_t *row_bits, real *mesh, hipStream_t s);
 // Clear both occupancy bitmaps (a fill kernel; no memset node in captured work).
 hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
 // Batched centred 2-D inverse FFT, in place, all planes.  Rows of an empty

@@ -11,25 +11,14 @@ def rel_rms(a, b):
 
 def oracle_bin_counts(b, grid_n, n_wplanes, support, tile):
     """Records per (plane, tile) bin implied by the oracle's per-visibility
-    decisions: a kept visibility adds one record to each tile its footprint
-    [c - h, c + h]^2 touches."""
+    decisions: a kept visibility adds one record to the tile holding the
+    top-left cell c - h of its footprint."""
     h = (support - 1) // 2
     nt = grid_n // tile
     idx = np.nonzero(b.keep)[0]
     cx, cy, k = b.cx[idx], b.cy[idx], b.k[idx]
     counts = np.zeros(n_wplanes * nt * nt, dtype=np.int64)
-    tx0, tx1 = (cx - h) // tile, (cx + h) // tile
-    ty0, ty1 = (cy - h) // tile, (cy + h) // tile
-    for second_y in (False, True):
-        for second_x in (False, True):
-            ty = ty1 if second_y else ty0
-            tx = tx1 if second_x else tx0
-            sel = np.ones(idx.size, bool)
-            if second_y:
-                sel &= ty1 != ty0
-            if second_x:
-                sel &= tx1 != tx0
-            np.add.at(counts, (k[sel] * nt + ty[sel]) * nt + tx[sel], 1)
+    np.add.at(counts, (k * nt + (cy - h) // tile) * nt + (cx - h) // tile, 1)
     return counts
 
 
