@@ -577,12 +577,13 @@ def main():
     roofline["traffic"], roofline["traffic_note"] = measured_traffic(args.workload, dominant)
     if dominant == "grid" and info["n_records"] > 0:
         # the gridder is bound by LDS instruction issue, not HBM: per record
-        # two ds_add_f64 and two ds_read_b32, at the per-CU rates measured on
-        # gfx950 (8.31 and 2.37 clocks per wave instruction)
-        floor_clk = 2 * 8.31 + 2 * 2.37
+        # two 64-bit atomic adds (integer in float32 mode, float64 in float64
+        # mode) and two ds_read_b32, at the per-CU rates measured on gfx950
+        # (6.22, 8.31 and 2.37 clocks per wave instruction)
+        floor_clk = 2 * (8.31 if args.precision == "fp64" else 6.22) + 2 * 2.37
         clk = kernels["grid"]["ms"] * 1e-3 * CU_COUNT * CLOCK_HZ / info["n_records"]
         roofline["lds_issue"] = {"records": int(info["n_records"]), "clk_per_record": round(clk, 2),
-                                 "floor_clk_per_record": floor_clk, "frac": round(floor_clk / clk, 3)}
+                                 "floor_clk_per_record": round(floor_clk, 2), "frac": round(floor_clk / clk, 3)}
     if roofline["traffic"] is not None:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / dbytes, 3)
 

@@ -63,6 +63,7 @@ __global__ void k_zero_stats(Stats *st) {
         st->n_records = 0;
         st->n_heavy = 0;
         st->sum_w = 0.0;
+        st->vmax_bits = 0u;
     }
 }
 
@@ -192,6 +193,7 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
     extern __shared__ int32_t s_cnt[];   // g.n1 counters
     __shared__ double s_w[kL1Block / 64];
     __shared__ unsigned long long s_kept[kL1Block / 64], s_drop[kL1Block / 64];
+    __shared__ float s_vmax[kL1Block / 64];
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cnt[i] = 0;
     __syncthreads();
     const int64_t v0 = (int64_t)blockIdx.x * part.per;
@@ -199,6 +201,7 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
     const int32_t cshift = g.log2T + g.log2C;
     double sum_w = 0.0;
     unsigned long long kept = 0, dropped = 0;
+    float vmax = 0.0f;   // largest |W V| kept (float32 mode), as the scatter pass forms W V
     VisWalk vw((uint32_t)(v0 + threadIdx.x), kL1Block, (uint32_t)nchan);
     for (int32_t it = 0; it < part.per / kL1Block; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
@@ -212,6 +215,8 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
             if (keep) {
                 ++kept;
                 sum_w += (double)wt;
+                if constexpr (sizeof(real) == 4)
+                    vmax = fmaxf(vmax, fmaxf(fabsf((real)wt * vr), fabsf((real)wt * vi)));
             } else {
                 ++dropped;
             }
@@ -226,25 +231,31 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
         sum_w += __shfl_down(sum_w, off);
         kept += __shfl_down(kept, off);
         dropped += __shfl_down(dropped, off);
+        vmax = fmaxf(vmax, __shfl_down(vmax, off));
     }
     const int wid = threadIdx.x >> 6;
     if (__lane_id() == 0) {
         s_w[wid] = sum_w;
         s_kept[wid] = kept;
         s_drop[wid] = dropped;
+        s_vmax[wid] = vmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double tw = 0.0;
         unsigned long long tk = 0, td = 0;
+        float tv = 0.0f;
         for (int k = 0; k < kL1Block / 64; ++k) {
             tw += s_w[k];
             tk += s_kept[k];
             td += s_drop[k];
+            tv = fmaxf(tv, s_vmax[k]);
         }
         if (tk) {
             atomicAdd(&st->n_gridded, tk);
             unsafeAtomicAdd(&st->sum_w, tw);
+            // non-negative floats order as their bit patterns
+            if (tv > 0.0f) atomicMax(&st->vmax_bits, __float_as_uint(tv));
         }
         if (td) atomicAdd(&st->n_dropped, td);
     }

@@ -11,10 +11,19 @@
 // of an instruction shares an address.  The LDS row pitch is congruent to W
 // modulo 32 elements, which spreads the W x W footprint over the banks.
 //
-// Accumulators are float64 in every precision mode: float64 LDS atomic adds
-// run at the rate of plain LDS traffic on gfx950, float32 ones several times
-// slower, and dense cells collect thousands of terms, which float32
-// accumulation would round to ~1e-5 of image RMS.
+// Accumulators are 64-bit: float32 LDS atomic adds are many times slower than
+// 64-bit ones on gfx950, and dense cells collect thousands of terms, which
+// float32 accumulation would round to ~1e-5 of image RMS.  In float64 mode
+// they are float64.  In float32 mode they are 64-bit fixed point: each term
+// W V g_y g_x is scaled by a power of two 2^s, rounded to an integer and
+// added with an integer atomic (cheaper than the float64 one).  s is chosen
+// per block so that every term stays below 2^50 and any cell's sum of the
+// block's n terms below 2^61 (from the largest |W V| since the reset and the
+// largest tap), so nothing overflows; a term is rounded at 2^-50 of the
+// largest possible term, far below its own float32 rounding, and integer
+// sums do not depend on the order of the adds.  The rounding uses the
+// float64 adder: fma(g, V 2^s, 1.5 2^52) holds round(g V 2^s) in its low
+// mantissa bits.
 //
 // Records arrive 64 at a time in one coalesced load (the next 64 are loaded
 // while these are gridded); each lane decodes the record it loaded (footprint
@@ -36,6 +45,8 @@
 // block.  Empty bins have no work item and write nothing: a bitmap of tiles
 // holding values (set by the merge, cleared by rick_reset) tells the FFT which
 // tiles to read; the others stand for zeros and are never read.
+#include <type_traits>
+
 #include "rick_internal.h"
 
 namespace rick {
@@ -119,13 +130,21 @@ constexpr int im_plane_offset() { return plane_offset(W); }
 // atomics just issued (LDS operations complete in order).
 constexpr int kGroup = 4;
 
+// Fixed-point terms: x + 1.5 2^52 (|x| < 2^51, rounded to an integer) has
+// bit pattern 0x4338000000000000 + round(x); the constant's low word is zero,
+// so the integer is the high word minus 0x43380000 over the low word.
+constexpr double kRoundMagic = 6755399441055744.0;   // 1.5 2^52
+__device__ __forceinline__ unsigned long long fixed_of(double t) {
+    return (unsigned long long)(uint32_t)(__double2hiint(t) - 0x43380000) << 32 | (uint32_t)__double2loint(t);
+}
+
 template <typename real, int W>
 __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__restrict__ scan,
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
                                                      real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
-                                                     real *__restrict__ margin) {
+                                                     real *__restrict__ margin, const Stats *__restrict__ st) {
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
@@ -151,17 +170,36 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
     if (n <= 0) return;   // (empty bins have no work item)
+    // float32 mode: 64-bit fixed point with scale 2^s (see the file comment)
+    constexpr bool FIX = std::is_same<real, float>::value;
+    using acc_t = typename std::conditional<FIX, unsigned long long, double>::type;
+    double scale = 1.0, unscale = 1.0;
+    if (FIX) {
+        const double vmax = (double)__uint_as_float(st->vmax_bits);   // largest |W V| since the reset
+        const double bt = vmax * (double)g.gmax2;                      // largest |term|
+        if (bt > 0.0 && bt < 1e300) {
+            const int et = ilogb(bt) + 1, en = ilogb((double)n) + 1;   // bt < 2^et, n < 2^en
+            const int sh = min(50 - et, 61 - et - en);
+            scale = ldexp(1.0, sh);
+            unscale = ldexp(1.0, -sh);
+        }
+    }
+    // accumulated value of LDS word i of a plane
+    auto acc_value = [&](const acc_t *a, int32_t i) -> real {
+        if constexpr (FIX) return (real)((double)(long long)a[i] * unscale);
+        else return (real)a[i];
+    };
     // LDS: real plane at byte 0, imaginary plane KOFF doubles further, then
     // the tap table; a plane is R = T + W - 1 rows of pitch P
     constexpr int R_PAD = W - 1;
     const int32_t R = T + R_PAD;
-    double *acc_re = reinterpret_cast<double *>(smem);
-    double *acc_im = acc_re + KOFF;
+    acc_t *acc_re = reinterpret_cast<acc_t *>(smem);
+    acc_t *acc_im = acc_re + KOFF;
     const int32_t lut_byte = (KOFF + R * P) * (int32_t)sizeof(double);
     real *s_lut = reinterpret_cast<real *>(smem + lut_byte);
     for (int i = threadIdx.x; i < R * P; i += kGridBlock) {
-        acc_re[i] = 0.0;
-        acc_im[i] = 0.0;
+        acc_re[i] = 0;
+        acc_im[i] = 0;
     }
     for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
     __syncthreads();
@@ -202,14 +240,14 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
         // the real plane, tap-table row byte offsets and visibility (lanes
         // past the batch keep zeros: they add 0 at the region's origin)
         int32_t d_base8 = 0, d_lxy = 0;
-        real d_vr = 0, d_vi = 0;
+        double d_vr = 0, d_vi = 0;   // W V (times 2^s in float32 mode; exact)
         if (lane < cnt) {
             const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
             const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
             d_base8 = (oy * P + ox) * (int)sizeof(double);
             d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
-            d_vr = raw_vr;
-            d_vi = raw_vi;
+            d_vr = (double)raw_vr * scale;
+            d_vi = (double)raw_vi * scale;
         }
         if (bt + nwave < nbatch) fetch(bt + nwave);
 
@@ -232,7 +270,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 const int32_t base8 = bcast(d_base8, (j + q) & 63);
-                const real vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
+                const double vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     // lanes holding a tap of group gi (a compile-time mask)
@@ -241,12 +279,25 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                     // the products are formed outside the branch, so the wait
                     // for the table values is the same on every path
                     const real wgt = gy[q][gi] * gx[q][gi];
-                    double tr = (double)(wgt * vr), ti = (double)(wgt * vi);
+                    double tr, ti;
+                    if constexpr (FIX) {
+                        // round(g V 2^s) in the low mantissa bits (exact product, one rounding)
+                        tr = fma((double)wgt, vr, kRoundMagic);
+                        ti = fma((double)wgt, vi, kRoundMagic);
+                    } else {
+                        tr = wgt * vr;
+                        ti = wgt * vi;
+                    }
                     __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
                     if (__builtin_amdgcn_inverse_ballot_w64(m)) {
-                        double *a = reinterpret_cast<double *>(smem + (base8 + tap_off8[gi]));
-                        atomicAdd(a, tr);
-                        atomicAdd(a + KOFF, ti);
+                        acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
+                        if constexpr (FIX) {
+                            atomicAdd(a, fixed_of(tr));
+                            atomicAdd(a + KOFF, fixed_of(ti));
+                        } else {
+                            atomicAdd(a, tr);
+                            atomicAdd(a + KOFF, ti);
+                        }
                     }
                 }
             }
@@ -271,7 +322,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     const bool accumulate = tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
     for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
         const int32_t y = c >> g.log2T, x = c & (T - 1);
-        const real re = (real)acc_re[y * P + x], im = (real)acc_im[y * P + x];
+        const real re = acc_value(acc_re, y * P + x), im = acc_value(acc_im, y * P + x);
         r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
         if (shared_tile) {
             if (re != 0) atomic_add_real(&dst->x, re);
@@ -297,7 +348,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                 y = T + (d >> g.log2T);
                 x = d & (T - 1);
             }
-            const real re = (real)acc_re[y * P + x], im = (real)acc_im[y * P + x];
+            const real re = acc_value(acc_re, y * P + x), im = acc_value(acc_im, y * P + x);
             if (shared_tile) {
                 if (re != 0) atomic_add_real(&mb[c].x, re);
                 if (im != 0) atomic_add_real(&mb[c].y, im);
@@ -419,7 +470,7 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                  int32_t max_items, hipStream_t s) {
+                  const Stats *st, int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static bool attr = false;
     if (!attr) {
@@ -428,7 +479,7 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
         attr = true;
     }
     hipLaunchKernelGGL((k_grid<real, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin, rec_pos,
-                       rec_vis, lut, mesh, tile_bits, margin);
+                       rec_vis, lut, mesh, tile_bits, margin, st);
     return hipGetLastError();
 }
 
@@ -478,10 +529,11 @@ hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_b
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       int32_t max_items, hipStream_t s) {
+                       const Stats *st, int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
-    case w: return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, max_items, s);
+    case w: \
+        return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, st, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -499,10 +551,10 @@ template hipError_t launch_merge_margins<float>(const Geom &, const BinScan *, c
 template hipError_t launch_merge_margins<double>(const Geom &, const BinScan *, const double *, uint64_t *,
                                                  uint64_t *, double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
-                                       const float *, const float *, float *, const uint64_t *, float *, int32_t,
-                                       hipStream_t);
+                                       const float *, const float *, float *, const uint64_t *, float *,
+                                       const Stats *, int32_t, hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                         const double *, const double *, double *, const uint64_t *, double *,
-                                        int32_t, hipStream_t);
+                                        const Stats *, int32_t, hipStream_t);
 
 }  // namespace rick

@@ -6,6 +6,7 @@
 // lost most of its time to per-sector hipMalloc/hipFree, Sec. 4.2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -331,6 +332,12 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         }
         for (int t = 0; t < g.W; ++t) p->lut_host[size_t(r) * g.W + t] /= sum;
     }
+    {
+        // largest tap as the device holds it; its square bounds |g_y g_x|
+        double gm = 0.0;
+        for (double v : p->lut_host) gm = std::max(gm, p->fp64 ? v : double(float(v)));
+        g.gmax2 = float(gm * gm * (1.0 + 1e-6));
+    }
     // taper C(l') = (1/OS) sum_s sum_t g_s[t] cos(2 pi (t - h - s/OS) l'), l' = (p - N/2)/N
     p->corr_host.assign(g.N, 0.0);
     for (int px = 0; px < g.N; ++px) {
@@ -572,10 +579,10 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
         e = launch_grid<double>(g, p->scan, p->item_bin, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
-                                (double *)p->mesh, p->tile_bits, (double *)p->margin, max_items, s);
+                                (double *)p->mesh, p->tile_bits, (double *)p->margin, p->stats, max_items, s);
     else
         e = launch_grid<float>(g, p->scan, p->item_bin, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
-                               (float *)p->mesh, p->tile_bits, (float *)p->margin, max_items, s);
+                               (float *)p->mesh, p->tile_bits, (float *)p->margin, p->stats, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
     timer_begin(p, T_MARK, "merge_margins", s);

@@ -43,6 +43,8 @@ struct Geom {
     int32_t n1;         // coarse bins, Nw * nct * nct
     int32_t CHK;        // level-1 records per level-2 chunk
     int32_t occw;       // 64-bit words of tile occupancy per tile row, ceil(nt / 64)
+    float gmax2;        // square of the largest tap of the tap table (as the device holds it)
+    int32_t pad1;
     double fov;
     double half;        // N * OS / 2
     double w_min;
@@ -57,7 +59,9 @@ struct Stats {
     unsigned long long n_heavy;     // bins of the last rick_grid split over several chunks
     double sum_w;
     unsigned long long n_chunks;    // level-2 binning chunks of the last rick_grid
-    double pad2[2];
+    unsigned int vmax_bits;         // float bits of the largest |W V| gridded since the reset (float32 mode)
+    unsigned int pad3;
+    double pad2;
 };
 
 // Binning bookkeeping written by the scan: per bin, exclusive prefix sums of
@@ -124,7 +128,7 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       int32_t max_items, hipStream_t s);
+                       const Stats *st, int32_t max_items, hipStream_t s);
 // LDS bytes of one gridding block (float64 accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 int64_t grid_margin_len(const Geom &g);
