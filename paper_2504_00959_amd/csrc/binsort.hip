@@ -63,7 +63,6 @@ __global__ void k_zero_stats(Stats *st) {
         st->n_records = 0;
         st->n_heavy = 0;
         st->sum_w = 0.0;
-        st->vmax_bits = 0u;
     }
 }
 
@@ -193,7 +192,6 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
     extern __shared__ int32_t s_cnt[];   // g.n1 counters
     __shared__ double s_w[kL1Block / 64];
     __shared__ unsigned long long s_kept[kL1Block / 64], s_drop[kL1Block / 64];
-    __shared__ float s_vmax[kL1Block / 64];
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cnt[i] = 0;
     __syncthreads();
     const int64_t v0 = (int64_t)blockIdx.x * part.per;
@@ -201,7 +199,6 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
     const int32_t cshift = g.log2T + g.log2C;
     double sum_w = 0.0;
     unsigned long long kept = 0, dropped = 0;
-    float vmax = 0.0f;   // largest |W V| kept (float32 mode), as the scatter pass forms W V
     VisWalk vw((uint32_t)(v0 + threadIdx.x), kL1Block, (uint32_t)nchan);
     for (int32_t it = 0; it < part.per / kL1Block; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
@@ -215,8 +212,6 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
             if (keep) {
                 ++kept;
                 sum_w += (double)wt;
-                if constexpr (sizeof(real) == 4)
-                    vmax = fmaxf(vmax, fmaxf(fabsf((real)wt * vr), fabsf((real)wt * vi)));
             } else {
                 ++dropped;
             }
@@ -231,31 +226,25 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
         sum_w += __shfl_down(sum_w, off);
         kept += __shfl_down(kept, off);
         dropped += __shfl_down(dropped, off);
-        vmax = fmaxf(vmax, __shfl_down(vmax, off));
     }
     const int wid = threadIdx.x >> 6;
     if (__lane_id() == 0) {
         s_w[wid] = sum_w;
         s_kept[wid] = kept;
         s_drop[wid] = dropped;
-        s_vmax[wid] = vmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double tw = 0.0;
         unsigned long long tk = 0, td = 0;
-        float tv = 0.0f;
         for (int k = 0; k < kL1Block / 64; ++k) {
             tw += s_w[k];
             tk += s_kept[k];
             td += s_drop[k];
-            tv = fmaxf(tv, s_vmax[k]);
         }
         if (tk) {
             atomicAdd(&st->n_gridded, tk);
             unsafeAtomicAdd(&st->sum_w, tw);
-            // non-negative floats order as their bit patterns
-            if (tv > 0.0f) atomicMax(&st->vmax_bits, __float_as_uint(tv));
         }
         if (td) atomicAdd(&st->n_dropped, td);
     }
@@ -448,29 +437,53 @@ __device__ __forceinline__ Local local_span(const Geom &g, uint32_t cxy, int32_t
     return Local{((cx - g.h) >> g.log2T) - (ctx << g.log2C), ((cy - g.h) >> g.log2T) - (cty << g.log2C)};
 }
 
+// Per (chunk, tile): record count and, for float32 records, the largest
+// |W V| (the gridder's fixed-point scale; non-negative floats order as their
+// bit patterns, so an integer max on the bits is a float max).
 __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                      const int32_t *__restrict__ key_chunk0,
                                                      const int32_t *__restrict__ chunk_key,
                                                      const Stats *__restrict__ st, const uint32_t *__restrict__ rec1,
-                                                     int32_t rec1_words, int32_t *__restrict__ cnt2) {
-    extern __shared__ int32_t s_h[];   // C^2 counters
+                                                     int32_t rec1_words, int32_t *__restrict__ cnt2,
+                                                     uint32_t *__restrict__ vmax2) {
+    extern __shared__ int32_t s_h[];   // C^2 counters, then C^2 maxima
     const int32_t chunk = blockIdx.x;
     if (chunk >= (int32_t)st->n_chunks) return;
     const int32_t C2 = g.C * g.C;
-    for (int i = threadIdx.x; i < C2; i += kBlock) s_h[i] = 0;
+    uint32_t *s_m = reinterpret_cast<uint32_t *>(s_h + C2);
+    for (int i = threadIdx.x; i < C2; i += kBlock) {
+        s_h[i] = 0;
+        s_m[i] = 0u;
+    }
     __syncthreads();
+    const bool f32 = rec1_words == 4;   // {cxy, sub, float W V}
     const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
     for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
         const int32_t r = r00 + threadIdx.x;
         const bool valid = r < ck.r1;
         Local ls{0, 0};
-        if (valid) ls = local_span(g, rec1[(int64_t)r * rec1_words], ck.ctx, ck.cty);
+        uint32_t mbits = 0u;
+        if (valid) {
+            const uint32_t *w = rec1 + (int64_t)r * rec1_words;
+            ls = local_span(g, w[0], ck.ctx, ck.cty);
+            if (f32) mbits = __float_as_uint(fmaxf(fabsf(__uint_as_float(w[2])), fabsf(__uint_as_float(w[3]))));
+        }
         const int32_t f = ls.fy0 * g.C + ls.fx0;
         const Run run = runs_of(valid ? f : -1);
         if (valid && run.head) atomicAdd(&s_h[f], run.len);
+        // maximum over the run (a segmented scan), taken by the run's last lane
+        const int lane = (int)__lane_id();
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(mbits, off);
+            if (lane - off >= run.leader) mbits = max(mbits, o);
+        }
+        if (valid && run.len == 1 && mbits) atomicMax(&s_m[f], mbits);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < C2; i += kBlock) cnt2[(int64_t)chunk * C2 + i] = s_h[i];
+    for (int i = threadIdx.x; i < C2; i += kBlock) {
+        cnt2[(int64_t)chunk * C2 + i] = s_h[i];
+        vmax2[(int64_t)chunk * C2 + i] = s_m[i];
+    }
 }
 
 // bin b = (plane, tile y, tile x) -> its coarse bin and its index inside it
@@ -482,17 +495,24 @@ __device__ __forceinline__ void bin_place(const Geom &g, int32_t b, int32_t &key
     f = (ty & (g.C - 1)) * g.C + (tx & (g.C - 1));
 }
 
-// records per bin: the sum over its coarse bin's chunks
+// records per bin (the sum over its coarse bin's chunks) and their largest |W V|
 __global__ __launch_bounds__(kBlock) void k_l2_totals(Geom g, const int32_t *__restrict__ key_chunk0,
-                                                      const int32_t *__restrict__ cnt2, int32_t *__restrict__ counts) {
+                                                      const int32_t *__restrict__ cnt2,
+                                                      const uint32_t *__restrict__ vmax2, int32_t *__restrict__ counts,
+                                                      uint32_t *__restrict__ bin_vmax) {
     const int32_t b = blockIdx.x * kBlock + threadIdx.x;
     if (b >= g.nbins) return;
     int32_t key, f;
     bin_place(g, b, key, f);
     const int64_t C2 = (int64_t)g.C * g.C;
     int32_t t = 0;
-    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) t += cnt2[c * C2 + f];
+    uint32_t m = 0u;
+    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) {
+        t += cnt2[c * C2 + f];
+        m = max(m, vmax2[c * C2 + f]);
+    }
     counts[b] = t;
+    bin_vmax[b] = m;
 }
 
 // per (chunk, tile) record offsets, in place over the counts
@@ -697,10 +717,12 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
     const size_t lds = size_t(g.C) * g.C * sizeof(int32_t);
     const int32_t nbb = (g.nbins + kBlock - 1) / kBlock;
     if (phase == 0) {
-        hipLaunchKernelGGL(k_l2_count, dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
-                           bb.chunk_key, st, (const uint32_t *)bb.rec1, (int32_t)(sizeof(Rec1<real>) / 4), bb.cnt2);
+        hipLaunchKernelGGL(k_l2_count, dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
+                           bb.chunk_key, st, (const uint32_t *)bb.rec1, (int32_t)(sizeof(Rec1<real>) / 4), bb.cnt2,
+                           bb.vmax2);
     } else if (phase == 1) {
-        hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.counts);
+        hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.vmax2,
+                           bb.counts, bb.bin_vmax);
         const int32_t n = g.nbins;
         const int32_t nblk = (n + 1 + kScanTile - 1) / kScanTile;
         hipLaunchKernelGGL(k_scan_partials, dim3(nblk), dim3(kScanBlock), 0, s, bb.counts, n, g.CH, bb.bsum);

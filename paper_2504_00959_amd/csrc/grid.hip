@@ -18,8 +18,8 @@
 // W V g_y g_x is scaled by a power of two 2^s, rounded to an integer and
 // added with an integer atomic (cheaper than the float64 one).  s is chosen
 // per block so that every term stays below 2^50 and any cell's sum of the
-// block's n terms below 2^61 (from the largest |W V| since the reset and the
-// largest tap), so nothing overflows; a term is rounded at 2^-50 of the
+// block's n terms below 2^61 (from the largest |W V| of the bin, found by the
+// binning, and the largest tap), so nothing overflows; a term is rounded at 2^-50 of the
 // largest possible term, far below its own float32 rounding, and integer
 // sums do not depend on the order of the adds.  The rounding uses the
 // float64 adder: fma(g, V 2^s, 1.5 2^52) holds round(g V 2^s) in its low
@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
                                                      real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
-                                                     real *__restrict__ margin, const Stats *__restrict__ st) {
+                                                     real *__restrict__ margin,
+                                                     const uint32_t *__restrict__ bin_vmax) {
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     using acc_t = typename std::conditional<FIX, unsigned long long, double>::type;
     double scale = 1.0, unscale = 1.0;
     if (FIX) {
-        const double vmax = (double)__uint_as_float(st->vmax_bits);   // largest |W V| since the reset
+        const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
         const double bt = vmax * (double)g.gmax2;                      // largest |term|
         if (bt > 0.0 && bt < 1e300) {
             const int et = ilogb(bt) + 1, en = ilogb((double)n) + 1;   // bt < 2^et, n < 2^en
@@ -470,7 +471,7 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                  const Stats *st, int32_t max_items, hipStream_t s) {
+                  const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static bool attr = false;
     if (!attr) {
@@ -479,7 +480,7 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
         attr = true;
     }
     hipLaunchKernelGGL((k_grid<real, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin, rec_pos,
-                       rec_vis, lut, mesh, tile_bits, margin, st);
+                       rec_vis, lut, mesh, tile_bits, margin, bin_vmax);
     return hipGetLastError();
 }
 
@@ -529,11 +530,12 @@ hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_b
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const Stats *st, int32_t max_items, hipStream_t s) {
+                       const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
     case w: \
-        return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, st, max_items, s);
+        return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
+                               max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -552,9 +554,9 @@ template hipError_t launch_merge_margins<double>(const Geom &, const BinScan *, 
                                                  uint64_t *, double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                        const float *, const float *, float *, const uint64_t *, float *,
-                                       const Stats *, int32_t, hipStream_t);
+                                       const uint32_t *, int32_t, hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                         const double *, const double *, double *, const uint64_t *, double *,
-                                        const Stats *, int32_t, hipStream_t);
+                                        const uint32_t *, int32_t, hipStream_t);
 
 }  // namespace rick

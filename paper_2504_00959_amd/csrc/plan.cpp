@@ -111,6 +111,8 @@ struct rick_plan_s {
     int32_t *key_chunk0 = nullptr;
     int32_t *chunk_key = nullptr;
     int32_t *cnt2 = nullptr;
+    uint32_t *vmax2 = nullptr;
+    uint32_t *bin_vmax = nullptr;
     int32_t max_chunks = 0;
     int32_t *item_bin = nullptr;
     int32_t *heavy_bins = nullptr;
@@ -148,7 +150,7 @@ void free_all(rick_plan_t *p) {
                     p->corr,
                     p->wk,        p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
-                    p->key_chunk0, p->chunk_key, p->cnt2,   p->item_bin, p->heavy_bins,
+                    p->key_chunk0, p->chunk_key, p->cnt2,   p->vmax2,    p->bin_vmax, p->item_bin, p->heavy_bins,
                     p->rec_pos,   p->rec_vis};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -381,7 +383,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_tbits = sz_rbits * g.nt;
     const size_t sz_margin = size_t(g.nbins) * size_t(grid_margin_len(g)) * 2 * rb + 64;
     const size_t total = p->mesh_bytes * (p->fused ? 2 : 1) + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
-                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + sz_cnt2 + sz_items + sz_heavy + sz_pos + sz_rvis + sz_tbits + sz_rbits + sz_margin;
+                         size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + 2 * sz_cnt2 + sz_counts + sz_items + sz_heavy + sz_pos + sz_rvis + sz_tbits + sz_rbits + sz_margin;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
     if (e != hipSuccess) {
@@ -424,6 +426,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->key_chunk0, sz_kc0);
     ALLOC(p->chunk_key, sz_ckey);
     ALLOC(p->cnt2, sz_cnt2);
+    ALLOC(p->vmax2, sz_cnt2);
+    ALLOC(p->bin_vmax, sz_counts);
     ALLOC(p->item_bin, sz_items);
     ALLOC(p->heavy_bins, sz_heavy);
     ALLOC(p->rec_pos, sz_pos);
@@ -544,8 +548,8 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     const int32_t max_items =
         int32_t((max_records < g.nbins ? max_records : g.nbins) + (max_records + g.CH - 1) / g.CH + 1);
 
-    const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2,
-                     p->counts,   p->scan,       p->item_bin, p->heavy_bins, p->rec_pos,  p->rec_vis};
+    const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2, p->vmax2,
+                     p->counts,   p->bin_vmax,   p->scan,    p->item_bin,   p->heavy_bins, p->rec_pos, p->rec_vis};
     struct Pass {
         int slot;
         const char *name;
@@ -579,10 +583,10 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
         e = launch_grid<double>(g, p->scan, p->item_bin, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
-                                (double *)p->mesh, p->tile_bits, (double *)p->margin, p->stats, max_items, s);
+                                (double *)p->mesh, p->tile_bits, (double *)p->margin, p->bin_vmax, max_items, s);
     else
         e = launch_grid<float>(g, p->scan, p->item_bin, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
-                               (float *)p->mesh, p->tile_bits, (float *)p->margin, p->stats, max_items, s);
+                               (float *)p->mesh, p->tile_bits, (float *)p->margin, p->bin_vmax, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
     timer_begin(p, T_MARK, "merge_margins", s);

@@ -59,9 +59,7 @@ struct Stats {
     unsigned long long n_heavy;     // bins of the last rick_grid split over several chunks
     double sum_w;
     unsigned long long n_chunks;    // level-2 binning chunks of the last rick_grid
-    unsigned int vmax_bits;         // float bits of the largest |W V| gridded since the reset (float32 mode)
-    unsigned int pad3;
-    double pad2;
+    double pad2[2];
 };
 
 // Binning bookkeeping written by the scan: per bin, exclusive prefix sums of
@@ -101,7 +99,9 @@ struct BinBufs {
     int32_t *key_chunk0;  // [n1 + 1] first level-2 chunk of each coarse bin
     int32_t *chunk_key;   // [max chunks] coarse bin of each level-2 chunk
     int32_t *cnt2;        // [max chunks][C^2] per (chunk, tile) counts, then record offsets
+    uint32_t *vmax2;      // [max chunks][C^2] per (chunk, tile) largest |W V| (float bits; float32 records)
     int32_t *counts;      // [nbins] records per bin
+    uint32_t *bin_vmax;   // [nbins] largest |W V| of the bin's records (float bits; float32 records)
     BinScan *scan;        // [nbins + 1]
     int32_t *item_bin;    // gridding work items
     int32_t *heavy_bins;  // bins split over several gridding chunks
@@ -128,7 +128,7 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const Stats *st, int32_t max_items, hipStream_t s);
+                       const uint32_t *bin_vmax, int32_t max_items, hipStream_t s);
 // LDS bytes of one gridding block (float64 accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 int64_t grid_margin_len(const Geom &g);

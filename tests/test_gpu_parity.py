@@ -292,6 +292,27 @@ def test_tile_bitmap_across_calls_and_resets(fused):
     assert float(np.abs(img_none).max()) == 0.0
 
 
+def test_fixed_point_scale_follows_each_bin():
+    """Float32-mode gridding sums in 64-bit fixed point scaled per bin by the
+    bin's largest |W V|: tiles of faint visibilities keep their relative
+    precision next to tiles 1e10 times brighter."""
+    ds = synth.tiny(nrow=20000, seed=19)
+    u = ds.uvw[:, 0]
+    keep = np.abs(u) > 25.0          # faint (u < -25) and bright (u > 25) never share a tile
+    ds.uvw = ds.uvw[keep]
+    vis = np.asarray(ds.vis)[keep].copy()
+    vis[ds.uvw[:, 0] > 0] *= np.float32(1e10)
+    ds.vis = vis
+    gpu = run_gpu(ds)
+    ref = oracle_of(ds)
+    N = ds.grid_n
+    faint = (slice(None), slice(None), slice(0, N // 2))              # cells x < 128: faint tiles only
+    bright = (slice(None), slice(None), slice(N // 2 + 8, None))
+    assert rel_rms(gpu["G"][faint], ref.planes[faint]) <= FP32_STAGE
+    assert rel_rms(gpu["G"][bright], ref.planes[bright]) <= FP32_STAGE
+    assert np.abs(ref.planes[faint]).max() > 0 and np.abs(ref.planes[bright]).max() > 1e8 * np.abs(ref.planes[faint]).max()
+
+
 def test_empty_and_all_dropped_give_zero_image():
     import torch
     ds = synth.tiny(nrow=100, seed=11)
