@@ -290,7 +290,8 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
                         ti = wgt * vi;
                     }
                     __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
-                    if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+                    // (with one tap group the whole record loop already runs on the tap lanes)
+                    if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(m)) {
                         acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
                         if constexpr (FIX) {
                             atomicAdd(a, fixed_of(tr));
@@ -304,17 +305,22 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
             }
         };
         // two table buffers used in turn: the reads for group j + kGroup are
-        // issued before the atomics of group j, and no value is copied
-        real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
-        lut_reads(0, ay, ax);
+        // issued before the atomics of group j, and no value is copied.  With
+        // one tap group (W <= 7) the loop runs on the tap lanes only: the
+        // execution mask is set once per batch, not per record (readlane
+        // reads the records of the other lanes regardless).
+        if (NG > 1 || lane < W2) {
+            real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
+            lut_reads(0, ay, ax);
 #pragma unroll
-        for (int j = 0; j < 64; j += 2 * kGroup) {
-            lut_reads(j + kGroup, by, bx);
-            add_group(j, ay, ax);
-            if (j + kGroup >= cnt) break;
-            lut_reads(j + 2 * kGroup, ay, ax);
-            add_group(j + kGroup, by, bx);
-            if (j + 2 * kGroup >= cnt) break;
+            for (int j = 0; j < 64; j += 2 * kGroup) {
+                lut_reads(j + kGroup, by, bx);
+                add_group(j, ay, ax);
+                if (j + kGroup >= cnt) break;
+                lut_reads(j + 2 * kGroup, ay, ax);
+                add_group(j + kGroup, by, bx);
+                if (j + 2 * kGroup >= cnt) break;
+            }
         }
     }
     __syncthreads();
