@@ -289,42 +289,59 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(Geom g, const 
     constexpr int CPP = RB * PW / CE;                // chunks per panel line
     extern __shared__ __align__(16) unsigned char smem[];
     const C *tw = reinterpret_cast<const C *>(twr);
-    const int rb = threadIdx.x / NT, tb = threadIdx.x % NT;
-    const int64_t blk = xcd_order(blockIdx.x, gridDim.x);
-    const int64_t row0 = blk * RB;                   // RB divides N
-    // the RB rows lie in one tile row (RB <= 4 <= T); an empty one is not
-    // written: the fused column pass reads it as zeros
-    const int32_t kp = (int32_t)(row0 / N), ty = (int32_t)(row0 % N) >> g.log2T;
-    if (!row_set(row_bits, g, kp, ty)) return;
-    C *buf = reinterpret_cast<C *>(smem) + rb * SH::PADN;
-    const C *gi = reinterpret_cast<const C *>(in) + (row0 + rb) * N;
-    const uint64_t *tb_row = tile_bits + ((int64_t)kp * g.nt + ty) * g.occw;
-    C x[16][1];
+    // Persistent: the block takes groups of RB rows q = blockIdx.x, + gridDim.x, ...
+    // (RB divides N, so a group lies in one tile row, RB <= 4 <= T), skipping
+    // groups of an empty tile row (not written: the fused column pass reads
+    // them as zeros); the copy-out of one group overlaps the next one's loads.
+    const int64_t ngroup = (int64_t)g.Nw * N / RB;
+    auto next = [&](int64_t q) {
+        for (; q < ngroup; q += gridDim.x) {
+            const int64_t row0 = q * RB;
+            if (row_set(row_bits, g, (int32_t)(row0 / N), (int32_t)(row0 % N) >> g.log2T)) break;
+        }
+        return q;
+    };
+    for (int64_t q = next(blockIdx.x); q < ngroup; q = next(q + gridDim.x)) {
+        // the lane's index arithmetic and the twiddle loads are redone per
+        // group (L1 hits) rather than held in registers across groups, which
+        // would not fit beside the transform
+        const C *twq = tw;
+        int tid = (int)threadIdx.x;
+        __asm__ volatile("" : "+s"(twq), "+v"(tid));
+        const int rb = tid / NT, tb = tid % NT;
+        C *buf = reinterpret_cast<C *>(smem) + rb * SH::PADN;
+        const int64_t row0 = q * RB;
+        const int32_t kp = (int32_t)(row0 / N), ty = (int32_t)(row0 % N) >> g.log2T;
+        const C *gi = reinterpret_cast<const C *>(in) + (row0 + rb) * N;
+        const uint64_t *tb_row = tile_bits + ((int64_t)kp * g.nt + ty) * g.occw;
+        C x[16][1];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = in_elem<N>(tb, i);
-        // a clear tile holds no gridded values: zeros, not read
-        const bool on = bit_of(uniform_word(tb_row, occ_word<N>(i, g.log2T)), e >> g.log2T);
-        x[i][0] = on ? cneg_if(gi[e], e & 1) : C{0, 0};
-    }
-    fft_regs<N, 1, 1>(x, buf, tb, 0, tw);
-    __syncthreads();   // every thread has read the last exchange
+        for (int i = 0; i < 16; ++i) {
+            const int e = in_elem<N>(tb, i);
+            // a clear tile holds no gridded values: zeros, not read
+            const bool on = bit_of(uniform_word(tb_row, occ_word<N>(i, g.log2T)), e >> g.log2T);
+            x[i][0] = on ? cneg_if(gi[e], e & 1) : C{0, 0};
+        }
+        __syncthreads();   // the previous group's copy-out has read the staging buffer
+        fft_regs<N, 1, 1>(x, buf, tb, 0, twq);
+        __syncthreads();   // every thread has read the last exchange
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int e = out_elem<N>(tb, q);
-        buf[padi(e)] = cneg_if(x[q][0], e & 1);
-    }
-    __syncthreads();
-    const int64_t k = row0 / N, r0 = row0 % N;
-    C *go = reinterpret_cast<C *>(out) + k * N * N + r0 * PW;
-    const C *stage = reinterpret_cast<const C *>(smem);
-    for (int c = threadIdx.x; c < N / PW * CPP; c += RB * NT) {
-        const int pnl = c / CPP, part = c % CPP;
-        const int r = (part * CE) / PW, col = pnl * PW + (part * CE) % PW;
-        const C *src = stage + r * SH::PADN + padi(col);   // CE values, contiguous (col even when CE = 2)
-        C *dst = go + (int64_t)pnl * N * PW + r * PW + (part * CE) % PW;
+        for (int j = 0; j < 16; ++j) {
+            const int e = out_elem<N>(tb, j);
+            buf[padi(e)] = cneg_if(x[j][0], e & 1);
+        }
+        __syncthreads();
+        const int64_t k = row0 / N, r0 = row0 % N;
+        C *go = reinterpret_cast<C *>(out) + k * N * N + r0 * PW;
+        const C *stage = reinterpret_cast<const C *>(smem);
+        for (int c = tid; c < N / PW * CPP; c += RB * NT) {
+            const int pnl = c / CPP, part = c % CPP;
+            const int r = (part * CE) / PW, col = pnl * PW + (part * CE) % PW;
+            const C *src = stage + r * SH::PADN + padi(col);   // CE values, contiguous (col even when CE = 2)
+            C *dst = go + (int64_t)pnl * N * PW + r * PW + (part * CE) % PW;
 #pragma unroll
-        for (int j = 0; j < CE; ++j) dst[j] = src[j];
+            for (int j = 0; j < CE; ++j) dst[j] = src[j];
+        }
     }
 }
 
@@ -611,8 +628,21 @@ hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
-    hipLaunchKernelGGL((k_fft_rows_panel<real, N, PS::RB, PS::PW>), dim3((unsigned)(nrows / PS::RB)),
-                       dim3(PS::NT * PS::RB), lds, s, g, in, out, tw, tile_bits, row_bits);
+    // persistent blocks: as many as fit on the device at once
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    }
+    int per_cu = int((160 * 1024) / lds);
+    const int by_threads = 2048 / (PS::NT * PS::RB);
+    per_cu = per_cu < by_threads ? per_cu : by_threads;
+    per_cu = per_cu < 1 ? 1 : per_cu;
+    const int64_t ngroup = nrows / PS::RB;
+    const int64_t nblk = (int64_t)cus * per_cu < ngroup ? (int64_t)cus * per_cu : ngroup;
+    hipLaunchKernelGGL((k_fft_rows_panel<real, N, PS::RB, PS::PW>), dim3((unsigned)nblk), dim3(PS::NT * PS::RB), lds,
+                       s, g, in, out, tw, tile_bits, row_bits);
     return hipGetLastError();
 }
 
