@@ -292,7 +292,7 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(Geom g, const 
     // Persistent: the block takes groups of RB rows q = blockIdx.x, + gridDim.x, ...
     // (RB divides N, so a group lies in one tile row, RB <= 4 <= T), skipping
     // groups of an empty tile row (not written: the fused column pass reads
-    // them as zeros); the copy-out of one group overlaps the next one's loads.
+    // them as zeros); the next group is loaded while this one is transformed.
     const int64_t ngroup = (int64_t)g.Nw * N / RB;
     auto next = [&](int64_t q) {
         for (; q < ngroup; q += gridDim.x) {
@@ -301,7 +301,23 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(Geom g, const 
         }
         return q;
     };
-    for (int64_t q = next(blockIdx.x); q < ngroup; q = next(q + gridDim.x)) {
+    // a group's input (zeros where its tile is clear, which is not read)
+    auto load = [&](int64_t q, int tb, int rb, C (&v)[16][1]) {
+        const int64_t row0 = q * RB;
+        const int32_t kp = (int32_t)(row0 / N), ty = (int32_t)(row0 % N) >> g.log2T;
+        const C *gi = reinterpret_cast<const C *>(in) + (row0 + rb) * N;
+        const uint64_t *tb_row = tile_bits + ((int64_t)kp * g.nt + ty) * g.occw;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = in_elem<N>(tb, i);
+            const bool on = bit_of(uniform_word(tb_row, occ_word<N>(i, g.log2T)), e >> g.log2T);
+            v[i][0] = on ? cneg_if(gi[e], e & 1) : C{0, 0};
+        }
+    };
+    int64_t q = next(blockIdx.x);
+    C pre[16][1];   // the next group's input, loaded while this one is transformed
+    if (q < ngroup) load(q, (int)threadIdx.x % NT, (int)threadIdx.x / NT, pre);
+    while (q < ngroup) {
         // the lane's index arithmetic and the twiddle loads are redone per
         // group (L1 hits) rather than held in registers across groups, which
         // would not fit beside the transform
@@ -311,17 +327,11 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(Geom g, const 
         const int rb = tid / NT, tb = tid % NT;
         C *buf = reinterpret_cast<C *>(smem) + rb * SH::PADN;
         const int64_t row0 = q * RB;
-        const int32_t kp = (int32_t)(row0 / N), ty = (int32_t)(row0 % N) >> g.log2T;
-        const C *gi = reinterpret_cast<const C *>(in) + (row0 + rb) * N;
-        const uint64_t *tb_row = tile_bits + ((int64_t)kp * g.nt + ty) * g.occw;
         C x[16][1];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = in_elem<N>(tb, i);
-            // a clear tile holds no gridded values: zeros, not read
-            const bool on = bit_of(uniform_word(tb_row, occ_word<N>(i, g.log2T)), e >> g.log2T);
-            x[i][0] = on ? cneg_if(gi[e], e & 1) : C{0, 0};
-        }
+        for (int i = 0; i < 16; ++i) x[i][0] = pre[i][0];
+        const int64_t qn = next(q + gridDim.x);
+        if (qn < ngroup) load(qn, tb, rb, pre);
         __syncthreads();   // the previous group's copy-out has read the staging buffer
         fft_regs<N, 1, 1>(x, buf, tb, 0, twq);
         __syncthreads();   // every thread has read the last exchange
@@ -342,6 +352,7 @@ __global__ __launch_bounds__((N / 16) * RB) void k_fft_rows_panel(Geom g, const 
 #pragma unroll
             for (int j = 0; j < CE; ++j) dst[j] = src[j];
         }
+        q = qn;
     }
 }
 
