@@ -75,35 +75,37 @@ struct Quant {
     int32_t cx, cy, sx, sy, k;
 };
 
-// Position, plane and drop decision of one visibility.
+// Position, plane and drop decision of one visibility, evaluated without
+// branches (every lane computes every step; the decisions are combined at
+// the end), which keeps the loop free of execution-mask changes.
 template <typename real>
 __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, double w, real vr, real vi, float wt,
                                          Quant &q) {
 #pragma clang fp contract(off)
-    if (!(isfinite(u) && isfinite(v) && isfinite(w) && isfinite((double)vr) && isfinite((double)vi) &&
-          isfinite(wt)))
-        return false;
+    // (bitwise & on purpose: no short-circuit branches)
+    bool ok = isfinite(u) & isfinite(v) & isfinite(w) & isfinite((double)vr) & isfinite((double)vi) & isfinite(wt);
     double xs = u * g.fov;
     xs = xs * (double)g.OS;
     xs = xs + g.half;
     double ys = v * g.fov;
     ys = ys * (double)g.OS;
     ys = ys + g.half;
-    if (!(fabs(xs) <= 1073741824.0 && fabs(ys) <= 1073741824.0)) return false;
-    const int32_t X = (int32_t)rint(xs);
-    const int32_t Y = (int32_t)rint(ys);
+    ok = ok & (fabs(xs) <= 1073741824.0) & (fabs(ys) <= 1073741824.0);
+    const int32_t X = ok ? (int32_t)rint(xs) : 0;
+    const int32_t Y = ok ? (int32_t)rint(ys) : 0;
     q.cx = (X + (g.OS >> 1)) >> g.log2OS;   // floor division by OS (arithmetic shift)
     q.cy = (Y + (g.OS >> 1)) >> g.log2OS;
     q.sx = X - (q.cx << g.log2OS);
     q.sy = Y - (q.cy << g.log2OS);
-    if (!(wt > 0.0f)) return false;
-    if (q.cx - g.h < 0 || q.cx + g.h > g.N - 1 || q.cy - g.h < 0 || q.cy + g.h > g.N - 1) return false;
+    ok = ok & (wt > 0.0f);
+    ok = ok & (q.cx - g.h >= 0) & (q.cx + g.h <= g.N - 1) & (q.cy - g.h >= 0) & (q.cy + g.h <= g.N - 1);
     double kf = floor((w - g.w_min) / g.dw);
     if (isnan(kf)) kf = 0.0;
     kf = kf < 0.0 ? 0.0 : kf;
     kf = kf > (double)(g.Nw - 1) ? (double)(g.Nw - 1) : kf;
     q.k = (int32_t)kf;
-    return true;
+    if (!ok) q = Quant{0, 0, 0, 0, 0};
+    return ok;
 }
 
 // Tile of edge 2^shift cells holding the footprint origin (c - h) of cell (cx, cy).
