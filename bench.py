@@ -44,11 +44,12 @@ def algorithmic_bytes(name, ds, info):
     row_cells = info["tile_rows_set"] * T * ds.grid_n      # cells of rows in tile rows holding any
     fused = bool(info.get("row_mesh_ptr"))
     wbytes = 4 * nvis if ds.weight is not None else 0
+    r1 = info.get("rec1_bytes") or 16                     # bytes per level-1 record
     table = {
         "bin_count": 24 * nrow + 8 * nvis + wbytes,     # the drop test reads the visibilities too
-        "bin_scatter": 24 * nrow + 8 * nvis + wbytes + 16 * nvis,   # writes 16-byte level-1 records
-        "fine_count": 8 * nvis,                                    # reads their positions
-        "fine_scatter": 16 * nvis + 12 * nvis,                     # reads them, writes 12-byte records
+        "bin_scatter": 24 * nrow + 8 * nvis + wbytes + r1 * nvis,   # writes the level-1 records
+        "fine_count": r1 * nvis,                                    # reads them (position and W V)
+        "fine_scatter": r1 * nvis + 12 * nvis,                      # reads them, writes 12-byte records
         "grid": 12 * nvis + 8 * set_cells,
         "fft_rows": 8 * set_cells + 8 * (row_cells if fused else cells),
         "fft_cols": 16 * cells,

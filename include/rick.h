@@ -125,6 +125,8 @@ typedef struct rick_plan_info_t {
                                 (k N / tile + ty) occ_words + tx / 64 is */
     int64_t tiles_set;       /* tiles set in tile_bits */
     int64_t tile_rows_set;   /* tile rows (plane, ty) with at least one set tile */
+    int32_t rec1_bytes;      /* bytes of a first-level binning record (12, 16 or 24) */
+    int32_t pad1;
     int32_t tile, chunk;     /* effective tile edge and chunk size */
     int32_t state;           /* 0 = empty, 1 = gridded, 2 = transformed */
     int32_t n_timers;        /* number of valid entries in kernel_ms / kernel_calls / kernel_names */

@@ -14,8 +14,8 @@
 //     bin_scan     exclusive scan of that table (coarse-bin major), then the
 //                  level-2 chunk list (each coarse bin cut into chunks).
 //     bin_scatter  repeats the quantisation; slots from LDS cursors seeded
-//                  with the block's scanned offsets; writes 16-byte level-1
-//                  records {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}.
+//                  with the block's scanned offsets; writes the level-1
+//                  records (12 or 16 bytes, formats below).
 //   level 2  bins = (plane, tile) inside each coarse bin, at most C^2 = 16384.
 //     fine_count   one block per chunk: LDS histogram over the tiles of the
 //                  coarse tile (that of each record's footprint origin).
@@ -49,12 +49,31 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kL1Block = 1024;   // threads of a level-1 block (one contiguous range of visibilities)
 
-// A level-1 record: cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V.
+// Level-1 records, in one of two formats:
+//   full (16 B with float32 W V, 24 B with float64): cell x | y << 16,
+//     sub-cell x | y << 8 | plane << 16, W V;
+//   compact (12 B, float32 W V, when 2 (log2(C T) + log2(OS)) <= 32): one word
+//     holding the footprint origin inside the coarse tile and the sub-cell
+//     indices, then W V -- the plane and coarse tile are those of the bin.
+template <typename real, bool CPT>
+struct Rec1;
 template <typename real>
-struct Rec1 {
+struct Rec1<real, false> {
     uint32_t cxy, sub;
     real vr, vi;
 };
+template <typename real>
+struct Rec1<real, true> {
+    uint32_t pos;
+    real vr, vi;
+};
+
+// Footprint origin inside its coarse tile (ox1, oy1, in cells) and sub-cell
+// indices s + OS/2 in [0, OS) (sx, sy).
+struct Pos1 {
+    int32_t ox1, oy1, sx, sy;
+};
+__device__ __forceinline__ int32_t coarse_shift(const Geom &g) { return g.log2C + g.log2T; }
 
 __global__ void k_zero_stats(Stats *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -75,6 +94,37 @@ struct Quant {
     int32_t cx, cy, sx, sy, k;
 };
 
+template <typename real>
+__device__ __forceinline__ Rec1<real, false> make_rec1(const Geom &g, const Quant &q, real ar, real ai,
+                                                      Rec1<real, false> *) {
+    return Rec1<real, false>{(uint32_t)q.cx | (uint32_t)q.cy << 16,
+                             (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
+                                 (uint32_t)q.k << 16,
+                             ar, ai};
+}
+template <typename real>
+__device__ __forceinline__ Rec1<real, true> make_rec1(const Geom &g, const Quant &q, real ar, real ai,
+                                                     Rec1<real, true> *) {
+    const int32_t lb = coarse_shift(g), m = (1 << lb) - 1;
+    const uint32_t ox1 = (uint32_t)((q.cx - g.h) & m), oy1 = (uint32_t)((q.cy - g.h) & m);
+    const uint32_t sx = (uint32_t)(q.sx + (g.OS >> 1)), sy = (uint32_t)(q.sy + (g.OS >> 1));
+    return Rec1<real, true>{ox1 | sx << lb | oy1 << (lb + g.log2OS) | sy << (2 * lb + g.log2OS), ar, ai};
+}
+template <typename real>
+__device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, false> &r, int32_t ctx, int32_t cty) {
+    const int32_t lb = coarse_shift(g);
+    const int32_t cx = (int32_t)(r.cxy & 0xffffu), cy = (int32_t)(r.cxy >> 16);
+    return Pos1{cx - g.h - (ctx << lb), cy - g.h - (cty << lb), (int32_t)(r.sub & 0xffu),
+                (int32_t)((r.sub >> 8) & 0xffu)};
+}
+template <typename real>
+__device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, true> &r, int32_t, int32_t) {
+    const int32_t lb = coarse_shift(g), sb = g.log2OS;
+    const uint32_t ml = (1u << lb) - 1, ms = (1u << sb) - 1;
+    return Pos1{(int32_t)(r.pos & ml), (int32_t)((r.pos >> (lb + sb)) & ml), (int32_t)((r.pos >> lb) & ms),
+                (int32_t)(r.pos >> (2 * lb + sb))};
+}
+
 // Position, plane and drop decision of one visibility, evaluated without
 // branches (every lane computes every step; the decisions are combined at
 // the end), which keeps the loop free of execution-mask changes.
@@ -82,30 +132,32 @@ template <typename real>
 __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, double w, real vr, real vi, float wt,
                                          Quant &q) {
 #pragma clang fp contract(off)
-    // (bitwise & on purpose: no short-circuit branches)
-    bool ok = isfinite(u) & isfinite(v) & isfinite(w) & isfinite((double)vr) & isfinite((double)vi) & isfinite(wt);
+    // (bitwise & on 0/1 integers on purpose: no short-circuit branches)
+    unsigned ok = (unsigned)isfinite(u) & (unsigned)isfinite(v) & (unsigned)isfinite(w) &
+                  (unsigned)isfinite((double)vr) & (unsigned)isfinite((double)vi) & (unsigned)isfinite(wt);
     double xs = u * g.fov;
     xs = xs * (double)g.OS;
     xs = xs + g.half;
     double ys = v * g.fov;
     ys = ys * (double)g.OS;
     ys = ys + g.half;
-    ok = ok & (fabs(xs) <= 1073741824.0) & (fabs(ys) <= 1073741824.0);
+    ok &= (unsigned)(fabs(xs) <= 1073741824.0) & (unsigned)(fabs(ys) <= 1073741824.0);
     const int32_t X = ok ? (int32_t)rint(xs) : 0;
     const int32_t Y = ok ? (int32_t)rint(ys) : 0;
     q.cx = (X + (g.OS >> 1)) >> g.log2OS;   // floor division by OS (arithmetic shift)
     q.cy = (Y + (g.OS >> 1)) >> g.log2OS;
     q.sx = X - (q.cx << g.log2OS);
     q.sy = Y - (q.cy << g.log2OS);
-    ok = ok & (wt > 0.0f);
-    ok = ok & (q.cx - g.h >= 0) & (q.cx + g.h <= g.N - 1) & (q.cy - g.h >= 0) & (q.cy + g.h <= g.N - 1);
+    ok &= (unsigned)(wt > 0.0f);
+    ok &= (unsigned)(q.cx - g.h >= 0) & (unsigned)(q.cx + g.h <= g.N - 1) & (unsigned)(q.cy - g.h >= 0) &
+          (unsigned)(q.cy + g.h <= g.N - 1);
     double kf = floor((w - g.w_min) / g.dw);
     if (isnan(kf)) kf = 0.0;
     kf = kf < 0.0 ? 0.0 : kf;
     kf = kf > (double)(g.Nw - 1) ? (double)(g.Nw - 1) : kf;
     q.k = (int32_t)kf;
     if (!ok) q = Quant{0, 0, 0, 0, 0};
-    return ok;
+    return ok != 0u;
 }
 
 // Tile of edge 2^shift cells holding the footprint origin (c - h) of cell (cx, cy).
@@ -254,13 +306,13 @@ __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__r
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) cnt1[(int64_t)i * part.nb1 + blockIdx.x] = s_cnt[i];
 }
 
-template <typename real>
+template <typename real, bool CPT>
 __global__ __launch_bounds__(kL1Block) void k_l1_scatter(Geom g, const double *__restrict__ uvw,
                                                          const double *__restrict__ scales,
                                                          const real *__restrict__ vis, const float *__restrict__ weight,
                                                          int64_t nvis, int32_t nchan, L1Part part,
                                                          const int32_t *__restrict__ base1,
-                                                         Rec1<real> *__restrict__ rec1) {
+                                                         Rec1<real, CPT> *__restrict__ rec1) {
     extern __shared__ int32_t s_cur[];   // g.n1 cursors
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cur[i] = base1[(int64_t)i * part.nb1 + blockIdx.x];
     __syncthreads();
@@ -288,10 +340,7 @@ __global__ __launch_bounds__(kL1Block) void k_l1_scatter(Geom g, const double *_
         int32_t b0 = 0;
         if (keep && run.head) b0 = atomicAdd(&s_cur[base], run.len);
         const int32_t rank = (int32_t)__lane_id() - run.leader;
-        const Rec1<real> r1{(uint32_t)q.cx | (uint32_t)q.cy << 16,
-                            (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
-                                (uint32_t)q.k << 16,
-                            ar, ai};
+        const Rec1<real, CPT> r1 = make_rec1<real>(g, q, ar, ai, (Rec1<real, CPT> *)nullptr);
         const int32_t slot = __shfl(b0, run.leader) + rank;
         if (keep) rec1[slot] = r1;
     }
@@ -429,25 +478,25 @@ __device__ __forceinline__ Chunk chunk_of(const Geom &g, const int32_t *__restri
     return c;
 }
 
-// Tile of the coarse tile (ctx, cty) holding a level-1 record's footprint
-// origin: local column fx0, row fy0 (in [0, C): the coarse bin is the origin's).
+// Tile of the coarse tile holding a level-1 record's footprint origin: local
+// column fx0, row fy0 (in [0, C): the coarse bin is the origin's).
 struct Local {
     int32_t fx0, fy0;
 };
-__device__ __forceinline__ Local local_span(const Geom &g, uint32_t cxy, int32_t ctx, int32_t cty) {
-    const int32_t cx = (int32_t)(cxy & 0xffffu), cy = (int32_t)(cxy >> 16);
-    return Local{((cx - g.h) >> g.log2T) - (ctx << g.log2C), ((cy - g.h) >> g.log2T) - (cty << g.log2C)};
+__device__ __forceinline__ Local local_span(const Geom &g, const Pos1 &p) {
+    return Local{p.ox1 >> g.log2T, p.oy1 >> g.log2T};
 }
 
 // Per (chunk, tile): record count and, for float32 records, the largest
 // |W V| (the gridder's fixed-point scale; non-negative floats order as their
 // bit patterns, so an integer max on the bits is a float max).
+template <typename real, bool CPT>
 __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                      const int32_t *__restrict__ key_chunk0,
                                                      const int32_t *__restrict__ chunk_key,
-                                                     const Stats *__restrict__ st, const uint32_t *__restrict__ rec1,
-                                                     int32_t rec1_words, int32_t *__restrict__ cnt2,
-                                                     uint32_t *__restrict__ vmax2) {
+                                                     const Stats *__restrict__ st,
+                                                     const Rec1<real, CPT> *__restrict__ rec1,
+                                                     int32_t *__restrict__ cnt2, uint32_t *__restrict__ vmax2) {
     extern __shared__ int32_t s_h[];   // C^2 counters, then C^2 maxima
     const int32_t chunk = blockIdx.x;
     if (chunk >= (int32_t)st->n_chunks) return;
@@ -458,7 +507,6 @@ __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__re
         s_m[i] = 0u;
     }
     __syncthreads();
-    const bool f32 = rec1_words == 4;   // {cxy, sub, float W V}
     const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
     for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
         const int32_t r = r00 + threadIdx.x;
@@ -466,9 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__re
         Local ls{0, 0};
         uint32_t mbits = 0u;
         if (valid) {
-            const uint32_t *w = rec1 + (int64_t)r * rec1_words;
-            ls = local_span(g, w[0], ck.ctx, ck.cty);
-            if (f32) mbits = __float_as_uint(fmaxf(fabsf(__uint_as_float(w[2])), fabsf(__uint_as_float(w[3]))));
+            const Rec1<real, CPT> p = rec1[r];
+            ls = local_span(g, pos_of<real>(g, p, ck.ctx, ck.cty));
+            if constexpr (sizeof(real) == 4) mbits = __float_as_uint(fmaxf(fabsf(p.vr), fabsf(p.vi)));
         }
         const int32_t f = ls.fy0 * g.C + ls.fx0;
         const Run run = runs_of(valid ? f : -1);
@@ -533,12 +581,12 @@ __global__ __launch_bounds__(kBlock) void k_l2_bases(Geom g, const int32_t *__re
     }
 }
 
-template <typename real>
+template <typename real, bool CPT>
 __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                        const int32_t *__restrict__ key_chunk0,
                                                        const int32_t *__restrict__ chunk_key,
                                                        const Stats *__restrict__ st,
-                                                       const Rec1<real> *__restrict__ rec1,
+                                                       const Rec1<real, CPT> *__restrict__ rec1,
                                                        const int32_t *__restrict__ base2,
                                                        uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
     extern __shared__ int32_t s_cur[];   // C^2 cursors
@@ -548,29 +596,28 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
     for (int i = threadIdx.x; i < C2; i += kBlock) s_cur[i] = base2[(int64_t)chunk * C2 + i];
     __syncthreads();
     const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
-    const int32_t tx_lo = ck.ctx << g.log2C, ty_lo = ck.cty << g.log2C;
     for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
         const int32_t r = r00 + threadIdx.x;
         const bool valid = r < ck.r1;
-        Local ls{0, 0};
-        Rec1<real> p{0u, 0u, 0, 0};
+        Pos1 ps{0, 0, 0, 0};
+        real vr = 0, vi = 0;
         if (valid) {
-            p = rec1[r];
-            ls = local_span(g, p.cxy, ck.ctx, ck.cty);
+            const Rec1<real, CPT> p = rec1[r];
+            ps = pos_of<real>(g, p, ck.ctx, ck.cty);
+            vr = p.vr;
+            vi = p.vi;
         }
+        const Local ls = local_span(g, ps);
         const int32_t f = ls.fy0 * g.C + ls.fx0;
         const Run run = runs_of(valid ? f : -1);
         int32_t b0 = 0;
         if (valid && run.head) b0 = atomicAdd(&s_cur[f], run.len);
         const int32_t rank = (int32_t)__lane_id() - run.leader;
-        const int32_t cx = (int32_t)(p.cxy & 0xffffu), cy = (int32_t)(p.cxy >> 16);
         const int32_t slot = __shfl(b0, run.leader) + rank;
         if (valid) {
-            const int32_t tx = tx_lo + ls.fx0, ty = ty_lo + ls.fy0;
-            const int32_t ox = cx - g.h - (tx << g.log2T);   // footprint origin in the tile, [0, T)
-            const int32_t oy = cy - g.h - (ty << g.log2T);
-            rec_pos[slot] = (uint32_t)ox | (uint32_t)oy << 8 | (p.sub & 0xffffu) << 16;
-            store2(rec_vis + 2 * (int64_t)slot, p.vr, p.vi);
+            const uint32_t ox = (uint32_t)(ps.ox1 & (g.T - 1)), oy = (uint32_t)(ps.oy1 & (g.T - 1));   // in the tile
+            rec_pos[slot] = ox | oy << 8 | (uint32_t)ps.sx << 16 | (uint32_t)ps.sy << 24;
+            store2(rec_vis + 2 * (int64_t)slot, vr, vi);
         }
     }
 }
@@ -702,9 +749,12 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
         hipLaunchKernelGGL(k_flat_apply, dim3(nblk), dim3(kScanBlock), 0, s, bb.cnt1, n, bb.bsum);
         hipLaunchKernelGGL(k_l2_chunks, dim3(1), dim3(kScanBlock), 0, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
                            bb.chunk_key, st);
+    } else if (g.cpt1 && sizeof(real) == 4) {
+        hipLaunchKernelGGL((k_l1_scatter<real, true>), dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev,
+                           vis, weight, nvis, nchan, part, bb.cnt1, (Rec1<real, true> *)bb.rec1);
     } else {
-        hipLaunchKernelGGL(k_l1_scatter<real>, dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev, vis,
-                           weight, nvis, nchan, part, bb.cnt1, (Rec1<real> *)bb.rec1);
+        hipLaunchKernelGGL((k_l1_scatter<real, false>), dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev,
+                           vis, weight, nvis, nchan, part, bb.cnt1, (Rec1<real, false> *)bb.rec1);
     }
     return hipGetLastError();
 }
@@ -718,10 +768,15 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
     const int32_t nchunk = bin_max_chunks(g, nvis);
     const size_t lds = size_t(g.C) * g.C * sizeof(int32_t);
     const int32_t nbb = (g.nbins + kBlock - 1) / kBlock;
+    const bool cpt = g.cpt1 && sizeof(real) == 4;
     if (phase == 0) {
-        hipLaunchKernelGGL(k_l2_count, dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
-                           bb.chunk_key, st, (const uint32_t *)bb.rec1, (int32_t)(sizeof(Rec1<real>) / 4), bb.cnt2,
-                           bb.vmax2);
+        if (cpt)
+            hipLaunchKernelGGL((k_l2_count<real, true>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1,
+                               bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, true> *)bb.rec1, bb.cnt2, bb.vmax2);
+        else
+            hipLaunchKernelGGL((k_l2_count<real, false>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1,
+                               part.nb1, bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, false> *)bb.rec1, bb.cnt2,
+                               bb.vmax2);
     } else if (phase == 1) {
         hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.vmax2,
                            bb.counts, bb.bin_vmax);
@@ -732,9 +787,13 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
         hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanBlock), 0, s, bb.counts, n, g.CH, bb.bsum, bb.scan,
                            bb.item_bin, bb.heavy_bins, st);
         hipLaunchKernelGGL(k_l2_bases, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.scan, bb.cnt2);
+    } else if (cpt) {
+        hipLaunchKernelGGL((k_l2_scatter<real, true>), dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+                           bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, true> *)bb.rec1, bb.cnt2, bb.rec_pos,
+                           (real *)bb.rec_vis);
     } else {
-        hipLaunchKernelGGL(k_l2_scatter<real>, dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
-                           bb.key_chunk0, bb.chunk_key, st, (const Rec1<real> *)bb.rec1, bb.cnt2, bb.rec_pos,
+        hipLaunchKernelGGL((k_l2_scatter<real, false>), dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+                           bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, false> *)bb.rec1, bb.cnt2, bb.rec_pos,
                            (real *)bb.rec_vis);
     }
     return hipGetLastError();

@@ -308,6 +308,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
                         g.T, g.W, g.OS, lds);
         }
     }
+    // compact level-1 records: origin in the coarse tile and sub-cell in one word
+    g.cpt1 = (!p->fp64 && 2 * (g.log2C + g.log2T + g.log2OS) <= 32) ? 1 : 0;
     g.fov = d->fov_rad;
     g.half = double(int64_t(g.N) * g.OS) / 2.0;
     g.w_min = d->w_min;
@@ -697,6 +699,7 @@ rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
         }
         out->tiles_set = tiles;
         out->tile_rows_set = rows;
+        out->rec1_bytes = p->g.cpt1 ? 12 : int32_t(8 + 2 * p->real_bytes);
     }
     out->panel = p->panel;
     out->mesh_bytes = (int64_t)p->mesh_bytes;

@@ -44,7 +44,7 @@ struct Geom {
     int32_t CHK;        // level-1 records per level-2 chunk
     int32_t occw;       // 64-bit words of tile occupancy per tile row, ceil(nt / 64)
     float gmax2;        // square of the largest tap of the tap table (as the device holds it)
-    int32_t pad1;
+    int32_t cpt1;       // level-1 records in the compact 12-byte format (float32 mode, when it fits)
     double fov;
     double half;        // N * OS / 2
     double w_min;

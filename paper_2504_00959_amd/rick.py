@@ -47,6 +47,7 @@ class PlanInfo(ctypes.Structure):
                 ("dw", ctypes.c_double), ("mesh", ctypes.c_void_p), ("mesh_bytes", ctypes.c_int64),
                 ("row_mesh", ctypes.c_void_p), ("panel", ctypes.c_int32), ("occ_words", ctypes.c_int32),
                 ("tile_bits", ctypes.c_void_p), ("tiles_set", ctypes.c_int64), ("tile_rows_set", ctypes.c_int64),
+                ("rec1_bytes", ctypes.c_int32), ("pad1", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("state", ctypes.c_int32),
                 ("n_timers", ctypes.c_int32), ("kernel_ms", ctypes.c_float * 16),
                 ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16)]
@@ -218,7 +219,7 @@ class Plan:
                     sum_weights=inf.sum_weights, du=inf.du, dl=inf.dl, dw=inf.dw, mesh_ptr=inf.mesh,
                     mesh_bytes=inf.mesh_bytes, row_mesh_ptr=inf.row_mesh, panel=inf.panel,
                     tile_bits_ptr=inf.tile_bits, occ_words=inf.occ_words, tiles_set=inf.tiles_set,
-                    tile_rows_set=inf.tile_rows_set, tile=inf.tile,
+                    tile_rows_set=inf.tile_rows_set, rec1_bytes=inf.rec1_bytes, tile=inf.tile,
                     chunk=inf.chunk, state=inf.state, timers=timers)
 
     def bin_counts(self, n_bins: int) -> np.ndarray:
