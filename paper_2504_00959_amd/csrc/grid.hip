@@ -53,7 +53,9 @@ namespace rick {
 
 namespace {
 
-constexpr int kGridBlock = 512;   // 8 waves share one tile
+// Threads of a gridding block: 16 waves share a 64-cell tile (its 80 KB of
+// accumulators allow two blocks per CU), 8 waves a smaller one (more blocks fit).
+constexpr int grid_threads(int T) { return T >= 64 ? 1024 : 512; }
 constexpr int kZeroBlock = 256;
 
 template <typename real>
@@ -116,13 +118,18 @@ __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t
 }
 
 // Offset (in doubles) of the imaginary accumulator plane from the real one:
-// the size of the largest plane (T = 64: 63 + W rows of pitch 64 + W), a
-// compile-time constant so that the second atomic of a tap reuses the first
-// one's address register with an immediate offset.  It is a multiple of 32
+// the size of a plane (T + W - 1 rows of the pitch), a compile-time constant
+// (the kernel is instantiated per tile size) so that the second atomic of a
+// tap reuses the first one's address register with an immediate offset.  It is a multiple of 32
 // doubles, so both planes map a footprint to the same LDS banks.
-constexpr int plane_offset(int W) { return ((63 + W) * (64 + W) + 31) / 32 * 32; }
-template <int W>
-constexpr int im_plane_offset() { return plane_offset(W); }
+constexpr int acc_pitch(int T, int W) {
+    int p = T + W - 1;   // at least the tile and its margin, congruent to W mod 32
+    while ((p - W) % 32 != 0) ++p;
+    return p;
+}
+constexpr int plane_offset(int W, int T) { return ((T + W - 1) * acc_pitch(T, W) + 31) / 32 * 32; }
+template <int W, int T>
+constexpr int im_plane_offset() { return plane_offset(W, T); }
 
 
 // Records per group.  The tap-table reads of the next group are issued before
@@ -138,8 +145,8 @@ __device__ __forceinline__ unsigned long long fixed_of(double t) {
     return (unsigned long long)(uint32_t)(__double2hiint(t) - 0x43380000) << 32 | (uint32_t)__double2loint(t);
 }
 
-template <typename real, int W>
-__global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__restrict__ scan,
+template <typename real, int W, int TT>
+__global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan *__restrict__ scan,
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
@@ -149,8 +156,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geom g, const BinScan *__re
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
+    constexpr int kGridBlock = grid_threads(TT);
     constexpr int nwave = kGridBlock / 64;
-    constexpr int KOFF = im_plane_offset<W>();
+    constexpr int KOFF = im_plane_offset<W, TT>();   // TT == g.T
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t total = scan[g.nbins].item;
     const int32_t item = blockIdx.x;
@@ -474,28 +482,46 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
     }
 }
 
+template <typename real, int W, int TT>
+hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
+                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
+                   const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
+    const size_t lds = grid_lds_bytes(g, sizeof(real));
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(160 * 1024));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_grid<real, W, TT>), dim3(max_items), dim3(grid_threads(TT)), lds, s, g, scan, item_bin,
+                       rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax);
+    return hipGetLastError();
+}
+
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                   const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
-    const size_t lds = grid_lds_bytes(g, sizeof(real));
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_grid<real, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(160 * 1024));
-        attr = true;
+    switch (g.T) {
+        case 16:
+            return grid_wt<real, W, 16>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                        max_items, s);
+        case 32:
+            return grid_wt<real, W, 32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                        max_items, s);
+        case 64:
+            return grid_wt<real, W, 64>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                        max_items, s);
+        default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_grid<real, W>), dim3(max_items), dim3(kGridBlock), lds, s, g, scan, item_bin, rec_pos,
-                       rec_vis, lut, mesh, tile_bits, margin, bin_vmax);
-    return hipGetLastError();
 }
 
 }  // namespace
 
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
-    // real plane, imaginary plane at plane_offset(W) doubles, each T + W - 1
+    // real plane, imaginary plane at plane_offset(W, T) doubles, each T + W - 1
     // rows of the pitch; then the tap table
-    const size_t koff = size_t(plane_offset(g.W));
+    const size_t koff = size_t(plane_offset(g.W, g.T));
     return (koff + size_t(g.T + g.W - 1) * g.pitch) * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
 }
 
