@@ -581,6 +581,45 @@ __global__ __launch_bounds__(kBlock) void k_l2_bases(Geom g, const int32_t *__re
     }
 }
 
+// Level-2 scatter, staged: the chunk is taken kSub records at a time; slots
+// come from the LDS cursors as above, and within a sub-chunk the records of
+// one tile have consecutive slots.  They are placed in LDS grouped by tile
+// (each tile's group in slot order) and written out from there, so that
+// consecutive threads write consecutive slots: whole lines instead of the
+// short runs of the load order.
+constexpr int kSubPer = 4;                   // records per thread per sub-chunk
+constexpr int kSub = kBlock * kSubPer;       // records per sub-chunk
+
+// inclusive scan of a[0..n) in place by one block of kBlock threads; returns the total
+__device__ __forceinline__ int32_t block_scan_incl(int32_t *a, int32_t n) {
+    __shared__ int32_t s_wave[kBlock / 64];
+    const int per = (n + kBlock - 1) / kBlock, lo = threadIdx.x * per;
+    int32_t sum = 0;
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) sum += a[lo + i];
+    const int lane = (int)__lane_id(), wid = threadIdx.x >> 6;
+    int32_t x = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) before += s_wave[w];
+        total += s_wave[w];
+    }
+    int32_t run = before + x - sum;   // exclusive prefix of this thread's entries
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) {
+            run += a[lo + i];
+            a[lo + i] = run;
+        }
+    __syncthreads();
+    return total;
+}
+
 template <typename real, bool CPT>
 __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                        const int32_t *__restrict__ key_chunk0,
@@ -589,36 +628,72 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
                                                        const Rec1<real, CPT> *__restrict__ rec1,
                                                        const int32_t *__restrict__ base2,
                                                        uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
-    extern __shared__ int32_t s_cur[];   // C^2 cursors
+    extern __shared__ int32_t s_cur[];   // C^2 cursors, then C^2 per-tile placement offsets
+    __shared__ int32_t s_slot[kSub];
+    __shared__ uint32_t s_pos[kSub];
+    __shared__ real s_v[2 * kSub];
     const int32_t chunk = blockIdx.x;
     if (chunk >= (int32_t)st->n_chunks) return;
     const int32_t C2 = g.C * g.C;
+    int32_t *s_adj = s_cur + C2;
     for (int i = threadIdx.x; i < C2; i += kBlock) s_cur[i] = base2[(int64_t)chunk * C2 + i];
     __syncthreads();
     const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
-    for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
-        const int32_t r = r00 + threadIdx.x;
-        const bool valid = r < ck.r1;
-        Pos1 ps{0, 0, 0, 0};
-        real vr = 0, vi = 0;
-        if (valid) {
-            const Rec1<real, CPT> p = rec1[r];
-            ps = pos_of<real>(g, p, ck.ctx, ck.cty);
-            vr = p.vr;
-            vi = p.vi;
-        }
-        const Local ls = local_span(g, ps);
-        const int32_t f = ls.fy0 * g.C + ls.fx0;
-        const Run run = runs_of(valid ? f : -1);
-        int32_t b0 = 0;
-        if (valid && run.head) b0 = atomicAdd(&s_cur[f], run.len);
-        const int32_t rank = (int32_t)__lane_id() - run.leader;
-        const int32_t slot = __shfl(b0, run.leader) + rank;
-        if (valid) {
+    for (int32_t r0 = ck.r0; r0 < ck.r1; r0 += kSub) {
+        for (int i = threadIdx.x; i < C2; i += kBlock) s_adj[i] = s_cur[i];   // cursors at the sub-chunk start
+        __syncthreads();
+        int32_t slot[kSubPer], tile[kSubPer];
+        uint32_t pos[kSubPer];
+        real vr[kSubPer], vi[kSubPer];
+#pragma unroll
+        for (int j = 0; j < kSubPer; ++j) {
+            const int32_t r = r0 + j * kBlock + (int32_t)threadIdx.x;
+            const bool valid = r < ck.r1;
+            Pos1 ps{0, 0, 0, 0};
+            vr[j] = 0;
+            vi[j] = 0;
+            if (valid) {
+                const Rec1<real, CPT> p = rec1[r];
+                ps = pos_of<real>(g, p, ck.ctx, ck.cty);
+                vr[j] = p.vr;
+                vi[j] = p.vi;
+            }
+            const Local ls = local_span(g, ps);
+            const int32_t f = ls.fy0 * g.C + ls.fx0;
+            const Run run = runs_of(valid ? f : -1);
+            int32_t b0 = 0;
+            if (valid && run.head) b0 = atomicAdd(&s_cur[f], run.len);
+            slot[j] = valid ? __shfl(b0, run.leader) + ((int32_t)__lane_id() - run.leader) : -1;
+            tile[j] = f;
             const uint32_t ox = (uint32_t)(ps.ox1 & (g.T - 1)), oy = (uint32_t)(ps.oy1 & (g.T - 1));   // in the tile
-            rec_pos[slot] = ox | oy << 8 | (uint32_t)ps.sx << 16 | (uint32_t)ps.sy << 24;
-            store2(rec_vis + 2 * (int64_t)slot, vr, vi);
+            pos[j] = ox | oy << 8 | (uint32_t)ps.sx << 16 | (uint32_t)ps.sy << 24;
         }
+        __syncthreads();   // every slot of the sub-chunk is taken
+        // placement: tile f's records go to [base_f, base_f + n_f) in slot order,
+        // n_f = cursor now - cursor at the start, base_f the exclusive scan of n_f;
+        // the offset slot - start_f + base_f = slot + (inclusive scan_f - cursor now)
+        for (int i = threadIdx.x; i < C2; i += kBlock) s_adj[i] = s_cur[i] - s_adj[i];
+        __syncthreads();
+        const int32_t n_sub = block_scan_incl(s_adj, C2);
+        for (int i = threadIdx.x; i < C2; i += kBlock) s_adj[i] -= s_cur[i];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSubPer; ++j) {
+            if (slot[j] >= 0) {
+                const int32_t e = slot[j] + s_adj[tile[j]];
+                s_slot[e] = slot[j];
+                s_pos[e] = pos[j];
+                s_v[2 * e] = vr[j];
+                s_v[2 * e + 1] = vi[j];
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n_sub; e += kBlock) {
+            const int32_t sl = s_slot[e];
+            rec_pos[sl] = s_pos[e];
+            store2(rec_vis + 2 * (int64_t)sl, s_v[2 * e], s_v[2 * e + 1]);
+        }
+        __syncthreads();   // the staging arrays and placement offsets are reused
     }
 }
 
@@ -788,11 +863,11 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
                            bb.item_bin, bb.heavy_bins, st);
         hipLaunchKernelGGL(k_l2_bases, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.scan, bb.cnt2);
     } else if (cpt) {
-        hipLaunchKernelGGL((k_l2_scatter<real, true>), dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+        hipLaunchKernelGGL((k_l2_scatter<real, true>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1,
                            bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, true> *)bb.rec1, bb.cnt2, bb.rec_pos,
                            (real *)bb.rec_vis);
     } else {
-        hipLaunchKernelGGL((k_l2_scatter<real, false>), dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+        hipLaunchKernelGGL((k_l2_scatter<real, false>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1,
                            bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, false> *)bb.rec1, bb.cnt2, bb.rec_pos,
                            (real *)bb.rec_vis);
     }
