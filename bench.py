@@ -464,6 +464,118 @@ def precision_report(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_report(args):
+    """The batched form: many independent jobs of uneven size (grid, planes,
+    visibility count, field) recorded once into a graph and replayed.  One
+    plan per (grid, planes) shape, its tile and chunk picked by the autotuner
+    on the shape's largest job and retargeted to each job's field.  Reports
+    jobs/s, per-job latency percentiles (device timestamps between the jobs),
+    the same jobs run eagerly, and the graph images against the eager ones.
+    Prints one JSON line."""
+    import torch
+    import synth
+    from paper_2504_00959_amd import rick
+
+    dev = "cuda:0"
+    t0 = time.time()
+    jobs = synth.batched_jobs(n_jobs=args.jobs, device=dev)
+    n = len(jobs)
+    nvis = sum(ds.nvis for ds in jobs)
+    print(f"[batch] generated {n} jobs, {nvis:,} visibilities in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    uvw = [ds.uvw.contiguous() for ds in jobs]
+    vis = [ds.vis.contiguous() for ds in jobs]
+    shapes = {}
+    for i, ds in enumerate(jobs):
+        shapes.setdefault((ds.grid_n, ds.n_wplanes), []).append(i)
+    stream = torch.cuda.Stream()
+    tuned, plans = {}, {}
+    t0 = time.time()
+    for key, idx in sorted(shapes.items()):
+        big = max(idx, key=lambda i: jobs[i].nvis)
+        tile, chunk, ms = rick.autotune(jobs[big], uvw[big], vis[big], fused=True, stream=stream)
+        tuned[key] = (tile, chunk, ms)
+        plans[key] = rick.Plan.for_dataset(jobs[big], max_vis=max(jobs[i].nvis for i in idx), tile=tile,
+                                           chunk=chunk, fused=True)
+    print(f"[batch] autotuned {len(shapes)} shapes in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    imgs = [torch.empty((ds.grid_n, ds.grid_n), dtype=torch.float32, device=dev) for ds in jobs]
+
+    def issue(i, s):
+        ds = jobs[i]
+        p = plans[(ds.grid_n, ds.n_wplanes)]
+        p.retarget(ds.fov, ds.w_min, ds.w_max)
+        p.reset(s)
+        p.grid(uvw[i], vis[i], None, ds.freq, s)
+        p.fft(s)
+        p.image(imgs[i], s)
+
+    stamps = rick.Stamps(n + 1)
+    # eager runs: reference images and timing
+    eager_ms = []
+    for rep in range(max(1, args.warmup)):
+        stamps.stamp(0, stream)
+        for i in range(n):
+            issue(i, stream)
+            stamps.stamp(i + 1, stream)
+        eager_ms.append(stamps.elapsed(0, n))
+    eager = [im.clone() for im in imgs]
+    with rick.Graph.record(stream) as graph:
+        stamps.stamp(0, stream)
+        for i in range(n):
+            issue(i, stream)
+            stamps.stamp(i + 1, stream)
+    totals, lat = [], []
+    for rep in range(args.steps):
+        for im in imgs:
+            im.fill_(0.0)
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        totals.append(stamps.elapsed(0, n))
+        lat = [stamps.elapsed(i, i + 1) for i in range(n)]
+    diffs = []
+    for a, b in zip(imgs, eager):
+        diffs.append(float(torch.linalg.vector_norm((a - b).double()) /
+                           max(float(torch.linalg.vector_norm(b.double())), 1e-300)))
+    worst = max(diffs)
+    # the smallest job against the oracle at sampled pixels
+    small = min(range(n), key=lambda i: jobs[i].nvis)
+    ds = jobs[small]
+    import oracle.pixels
+    rng = np.random.default_rng(0)
+    N = ds.grid_n
+    pp = np.r_[N // 2, rng.integers(N // 4, 3 * N // 4, 5)]
+    qq = np.r_[N // 2, rng.integers(N // 4, 3 * N // 4, 5)]
+    dsh = synth.Dataset(uvw=ds.uvw.cpu().numpy(), freq=ds.freq, vis=ds.vis.cpu().numpy(), weight=None,
+                        grid_n=ds.grid_n, n_wplanes=ds.n_wplanes, support=ds.support, oversample=ds.oversample,
+                        fov=ds.fov, w_min=ds.w_min, w_max=ds.w_max)
+    ref, _, kept, _ = oracle.pixels.wstack_pixels(dsh.uvw, dsh.freq, dsh.vis, None, pp, qq, **dsh.plan_kwargs())
+    got = imgs[small].double().cpu().numpy()[qq, pp]
+    from oracle import wstack as ow
+    corr = ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param), N)
+    c2 = corr[pp] * corr[qq]
+    ocheck = float(np.linalg.norm((got - ref) * c2) / np.linalg.norm(ref * c2))
+    med = float(np.median(totals))
+    lat_sorted = np.sort(np.asarray(lat))
+    out = {"report": "batch", "jobs": n, "n_vis": nvis, "steps": args.steps,
+           "jobs_per_s": round(n / (med * 1e-3), 2), "batch_ms": round(med, 3),
+           "mvis_per_s": round(nvis / (med * 1e-3) / 1e6, 1),
+           "latency_ms": {"p50": round(float(np.percentile(lat_sorted, 50)), 3),
+                          "p99": round(float(np.percentile(lat_sorted, 99)), 3),
+                          "max": round(float(lat_sorted[-1]), 3)},
+           "eager_batch_ms": round(float(np.median(eager_ms)), 3),
+           "graph_vs_eager_max_rel_rms": worst,
+           "graph_vs_eager_rel_rms": [float("%.3g" % d) for d in diffs],
+           "job_shapes": [f"{ds.grid_n}x{ds.n_wplanes}:{ds.nvis}" for ds in jobs],
+           "oracle_check": {"job": small, "pixels": int(len(pp)), "apparent_rel_rms": ocheck},
+           "shapes": {f"{k[0]}x{k[1]}": {"jobs": len(shapes[k]), "tile": v[0], "chunk": v[1],
+                                         "tuned_ms": round(v[2], 3)} for k, v in sorted(tuned.items())}}
+    print(json.dumps(out), flush=True)
+    graph.close()
+    stamps.close()
+    for p in plans.values():
+        p.close()
+
+
 def describe(ds):
     return (f"{ds.name}: {ds.nrow:,} rows x {ds.nchan} channels = {ds.nvis:,} visibilities, "
             f"{ds.grid_n}^2 x {ds.n_wplanes} w-planes, support {ds.support}, oversample {ds.oversample}, "
@@ -494,6 +606,9 @@ def main():
                     help="run fp32, fp32_kahan and fp64 on the workload and report each image's error against the "
                          "float64 GPU image, the oracle and the direct Fourier sum at sampled pixels")
     ap.add_argument("--patch", type=int, default=8, help="edge of the centre pixel patch of --precision-report")
+    ap.add_argument("--batch", action="store_true",
+                    help="the batched form: many uneven jobs recorded into a graph and replayed (jobs/s, latency)")
+    ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
     args = ap.parse_args()
     if args.profile:
         run_profiles(os.path.abspath(args.profile), args.workload)
@@ -503,6 +618,9 @@ def main():
         return
     if args.precision_report:
         precision_report(args)
+        return
+    if args.batch:
+        batch_report(args)
         return
     if args.copy_calibration:
         import torch

@@ -203,6 +203,17 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream);
 rick_status rick_reset(rick_plan_t *p, void *stream);
 
 /*
+ * rick_plan_retarget -- give the plan another field of view and w range
+ * (fov_rad, w_min, w_max as in rick_plan_desc) for the work issued after this
+ * call: the cell size, pixel size and plane centres follow; the grid size,
+ * planes, kernel, precision and buffers stay.  Host-side only (no device work),
+ * so it may be called while recording a graph: each recorded job keeps the
+ * field it was recorded with.  Call rick_reset before gridding a new field.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (as for rick_plan).
+ */
+rick_status rick_plan_retarget(rick_plan_t *p, double fov_rad, double w_min, double w_max);
+
+/*
  * rick_plan_info -- fill *out.  Synchronises the plan's device (it copies
  * counters back), so call it outside timed regions.
  * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL out), RICK_E_HIP.
@@ -219,11 +230,68 @@ rick_status rick_plan_destroy(rick_plan_t *p);
 /*
  * rick_plan_bin_counts -- copy the per-bin record counts of the last
  * rick_grid to HOST memory `counts` [n], n = N_w * (N/T)^2, bin index
- * (k * (N/T) + tile_row) * (N/T) + tile_col.  A visibility adds one record
- * to every tile its W x W footprint touches.  Synchronises the device.
+ * (k * (N/T) + tile_row) * (N/T) + tile_col.  A gridded visibility adds
+ * one record, to the tile holding the top-left cell of its W x W footprint.
+ * Synchronises the device.
  * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL counts, wrong n), RICK_E_HIP.
  */
 rick_status rick_plan_bin_counts(rick_plan_t *p, int32_t *counts, int64_t n);
+
+/*
+ * Batches of imaging jobs (Sec. 2.2 processes the data in independent
+ * chunks; here many independent jobs are recorded once and replayed).
+ *
+ * rick_capture_begin -- start recording the work the library (and anything
+ * else) issues on `stream` into a graph instead of running it: rick_reset,
+ * rick_grid, rick_fft_planes, rick_wstack_image and rick_stamp on any plans,
+ * each with the same stream.  None of them allocates or synchronises, so a
+ * whole sequence of jobs can be recorded.  rick_plan_info,
+ * rick_plan_bin_counts, rick_autotune and plan creation synchronise and must
+ * not be called while recording.
+ * rick_capture_end -- stop recording and instantiate the graph; *out
+ * receives it (NULL on failure).
+ * rick_graph_launch -- run the recorded work once on `stream` (asynchronous;
+ * may be launched again: every launch redoes the recorded work with the
+ * buffers as they are then).  The plans, inputs and outputs used while
+ * recording must stay alive while the graph is used.
+ * rick_graph_destroy -- free the graph (after its launches completed).
+ * Errors: RICK_E_INVALID_ARG (NULL stream handle pointer or graph), RICK_E_HIP.
+ */
+typedef struct rick_graph_s rick_graph_t;
+rick_status rick_capture_begin(void *stream);
+rick_status rick_capture_end(void *stream, rick_graph_t **out);
+rick_status rick_graph_launch(rick_graph_t *g, void *stream);
+rick_status rick_graph_destroy(rick_graph_t *g);
+
+/*
+ * Device timestamps for per-job latencies inside a graph.
+ * rick_stamps_create -- n timestamp slots; rick_stamp -- a one-thread kernel
+ * on `stream` writes the device's constant-rate clock into slot i when the
+ * preceding work on the stream has finished (may be recorded into a graph);
+ * rick_stamps_elapsed -- synchronise the device and give, in *ms, the time
+ * from slot i to slot j of their last writes; rick_stamps_destroy.
+ * Errors: RICK_E_INVALID_ARG (n < 1, index out of range, NULL pointer), RICK_E_HIP.
+ */
+typedef struct rick_stamps_s rick_stamps_t;
+rick_status rick_stamps_create(int32_t n, rick_stamps_t **out);
+rick_status rick_stamp(rick_stamps_t *t, int32_t i, void *stream);
+rick_status rick_stamps_elapsed(rick_stamps_t *t, int32_t i, int32_t j, float *ms);
+rick_status rick_stamps_destroy(rick_stamps_t *t);
+
+/*
+ * rick_autotune -- pick the uv tile edge and gridding chunk for plan
+ * parameters `d` and one job's inputs (same meaning as rick_grid): each
+ * candidate (tile 16, 32 or 64 where it holds the footprint and fits LDS;
+ * chunk 2048, 8192 or 32768 records) gets a plan of its own, one untimed and
+ * two timed runs of reset + grid + fft + image on `stream`, and is freed;
+ * *tile, *chunk receive the fastest and *ms its time per run.  Synchronises;
+ * needs memory for one plan of `d` at a time.  d->tile and d->chunk are
+ * ignored.
+ * Errors: as rick_plan and rick_grid; RICK_E_INVALID_ARG (NULL outputs).
+ */
+rick_status rick_autotune(const rick_plan_desc *d, const double *uvw, const double *freq_hz, const void *vis,
+                          const float *weight, int64_t nrow, int32_t nchan, void *stream, int32_t *tile,
+                          int32_t *chunk, float *ms);
 
 /* Static message for a status code (never NULL). */
 const char *rick_status_str(rick_status s);

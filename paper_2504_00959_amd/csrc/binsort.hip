@@ -774,6 +774,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int32_t *__rest
 
 }  // namespace
 
+__global__ void k_stamp(uint64_t *slot) {
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
+
+hipError_t launch_stamp(uint64_t *slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_stats(Stats *st, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, s, st);
     return hipGetLastError();

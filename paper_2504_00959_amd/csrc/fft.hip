@@ -462,7 +462,6 @@ __device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
 template <typename real, int N, int V, int VC, int PW, bool KAHAN>
 __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
                                                                          const real *__restrict__ twr,
-                                                                         const double *__restrict__ wk,
                                                                          const double *__restrict__ corr,
                                                                          const Stats *__restrict__ st,
                                                                          const uint64_t *__restrict__ row_bits,
@@ -530,7 +529,7 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         // read the previous plane's last exchange before this plane's first
         __syncthreads();
         fft_regs<N, V, VC>(x, buf, tb, v0, tw);
-        const double w2 = 2.0 * wk[k];
+        const double w2 = 2.0 * plane_centre(g, k);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = out_elem<N>(tb, q);
@@ -658,8 +657,8 @@ hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw
 }
 
 template <typename real, int N>
-hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const double *wk, const double *corr,
-                         const Stats *st, const uint64_t *row_bits, real *image, int kahan, hipStream_t s) {
+hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const double *corr, const Stats *st,
+                         const uint64_t *row_bits, real *image, int kahan, hipStream_t s) {
     using CS = ColShape<real, N>;
     constexpr int PW = PanelShape<real, N>::PW;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
@@ -673,10 +672,10 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
     }
     if (kahan)
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>), dim3(N / CS::V), dim3(CS::THREADS),
-                           lds, s, g, mesh, tw, wk, corr, st, row_bits, image);
+                           lds, s, g, mesh, tw, corr, st, row_bits, image);
     else
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>), dim3(N / CS::V),
-                           dim3(CS::THREADS), lds, s, g, mesh, tw, wk, corr, st, row_bits, image);
+                           dim3(CS::THREADS), lds, s, g, mesh, tw, corr, st, row_bits, image);
     return hipGetLastError();
 }
 
@@ -737,12 +736,11 @@ hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *tw, hipStream_
 }
 
 template <typename real>
-hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *wk,
-                                  const double *corr, const Stats *st, const uint64_t *row_bits, real *image,
-                                  int kahan, hipStream_t s) {
+hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *corr,
+                                  const Stats *st, const uint64_t *row_bits, real *image, int kahan, hipStream_t s) {
     switch (g.N) {
 #define CASE(n) \
-    case n: return cols_screen_n<real, n>(g, mesh, tw, wk, corr, st, row_bits, image, kahan, s);
+    case n: return cols_screen_n<real, n>(g, mesh, tw, corr, st, row_bits, image, kahan, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -760,10 +758,8 @@ template hipError_t launch_fft_rows_panel<double>(const Geom &, const double *, 
 template hipError_t launch_fft_cols<float>(const Geom &, float *, const float *, hipStream_t);
 template hipError_t launch_fft_cols<double>(const Geom &, double *, const double *, hipStream_t);
 template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, const float *, const double *,
-                                                  const double *, const Stats *, const uint64_t *, float *, int,
-                                                  hipStream_t);
+                                                  const Stats *, const uint64_t *, float *, int, hipStream_t);
 template hipError_t launch_fft_cols_screen<double>(const Geom &, const double *, const double *, const double *,
-                                                   const double *, const Stats *, const uint64_t *, double *, int,
-                                                   hipStream_t);
+                                                   const Stats *, const uint64_t *, double *, int, hipStream_t);
 
 }  // namespace rick

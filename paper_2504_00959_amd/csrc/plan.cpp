@@ -100,7 +100,6 @@ struct rick_plan_s {
     void *lut = nullptr;
     void *twiddle = nullptr;
     double *corr = nullptr;
-    double *wk = nullptr;
     double *scales = nullptr;
     Stats *stats = nullptr;
     int32_t *counts = nullptr;
@@ -120,7 +119,7 @@ struct rick_plan_s {
     void *rec_vis = nullptr;
     int64_t rec_cap = 0;
     // host copies of tables (for tests and info)
-    std::vector<double> lut_host, corr_host, wk_host;
+    std::vector<double> lut_host, corr_host;
     // timing: per kernel slot a ring of (start, stop) event pairs
     hipEvent_t ev[kMaxTimers][2 * kTimerRing] = {};
     const char *ev_name[kMaxTimers] = {};
@@ -148,7 +147,7 @@ struct DeviceGuard {
 void free_all(rick_plan_t *p) {
     void *bufs[] = {p->mesh,      p->row_mesh,  p->tile_bits,  p->row_bits,  p->margin, p->lut,     p->twiddle,
                     p->corr,
-                    p->wk,        p->scales,
+                    p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->vmax2,    p->bin_vmax, p->item_bin, p->heavy_bins,
                     p->rec_pos,   p->rec_vis};
@@ -356,8 +355,6 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         }
         p->corr_host[px] = c / g.OS;
     }
-    p->wk_host.resize(g.Nw);
-    for (int k = 0; k < g.Nw; ++k) p->wk_host[k] = d->w_min + (double(k) + 0.5) * g.dw;
 
     // ---- device allocation, once ----
     DeviceGuard guard(d->device);
@@ -417,7 +414,6 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->lut, sz_lut);
     ALLOC(p->twiddle, sz_tw);
     ALLOC(p->corr, size_t(g.N) * 8);
-    ALLOC(p->wk, size_t(g.Nw) * 8);
     ALLOC(p->scales, size_t(kMaxChan) * 8);
     ALLOC(p->stats, sizeof(Stats));
     ALLOC(p->counts, sz_counts);
@@ -458,7 +454,6 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         {p->lut, lut_dev.data(), sz_lut},
         {p->twiddle, tw_dev.data(), sz_tw},
         {p->corr, p->corr_host.data(), size_t(g.N) * 8},
-        {p->wk, p->wk_host.data(), size_t(g.Nw) * 8},
     };
     for (auto &c : cps) {
         e = hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
@@ -645,10 +640,10 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
     if (p->fused) {
         timer_begin(p, T_SCREEN, "fft_cols_screen", s);
         if (p->fp64)
-            e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle, p->wk,
+            e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle,
                                                p->corr, p->stats, p->row_bits, (double *)image, 0, s);
         else
-            e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle, p->wk,
+            e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle,
                                               p->corr, p->stats, p->row_bits, (float *)image, kahan, s);
         timer_end(p, T_SCREEN, s);
         if (e != hipSuccess) return hip_fail(e, "fft_cols_screen");
@@ -656,9 +651,9 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
     }
     timer_begin(p, T_SCREEN, "wscreen", s);
     if (p->fp64)
-        e = launch_wscreen<double>(p->g, (const double *)p->mesh, p->wk, p->corr, p->stats, (double *)image, 0, s);
+        e = launch_wscreen<double>(p->g, (const double *)p->mesh, p->corr, p->stats, (double *)image, 0, s);
     else
-        e = launch_wscreen<float>(p->g, (const float *)p->mesh, p->wk, p->corr, p->stats, (float *)image, kahan, s);
+        e = launch_wscreen<float>(p->g, (const float *)p->mesh, p->corr, p->stats, (float *)image, kahan, s);
     timer_end(p, T_SCREEN, s);
     if (e != hipSuccess) return hip_fail(e, "wscreen");
     return RICK_OK;
@@ -743,6 +738,190 @@ rick_status rick_plan_bin_counts(rick_plan_t *p, int32_t *counts, int64_t n) {
     if (e == hipSuccess) e = hipMemcpy(sc.data(), p->scan, (size_t(n) + 1) * sizeof(BinScan), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read bin counts");
     for (int64_t i = 0; i < n; ++i) counts[i] = sc[i + 1].rec - sc[i].rec;
+    return RICK_OK;
+}
+
+rick_status rick_plan_retarget(rick_plan_t *p, double fov_rad, double w_min, double w_max) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    rick_plan_desc d = p->d;
+    d.fov_rad = fov_rad;
+    d.w_min = w_min;
+    d.w_max = w_max;
+    const rick_status st = validate(&d);
+    if (st != RICK_OK) return st;
+    p->d = d;
+    p->g.fov = fov_rad;
+    p->g.w_min = w_min;
+    p->g.dw = (w_max - w_min) / double(p->g.Nw);
+    p->du = 1.0 / fov_rad;
+    p->dl = fov_rad / p->g.N;
+    return RICK_OK;
+}
+
+// ---- batches: graph recording, timestamps, autotuning ----
+
+struct rick_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct rick_stamps_s {
+    uint64_t *dev = nullptr;   // device clock values, one per slot
+    int32_t n = 0;
+    double khz = 0.0;          // device clock rate
+};
+
+rick_status rick_capture_begin(void *stream) {
+    hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal);
+    return e == hipSuccess ? RICK_OK : hip_fail(e, "hipStreamBeginCapture");
+}
+
+rick_status rick_capture_end(void *stream, rick_graph_t **out) {
+    if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    rick_graph_t *g = new (std::nothrow) rick_graph_t;
+    if (!g) return fail(RICK_E_OOM, "graph handle");
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return hip_fail(e, "graph capture");
+    }
+    *out = g;
+    return RICK_OK;
+}
+
+rick_status rick_graph_launch(rick_graph_t *g, void *stream) {
+    if (!g || !g->exec) return fail(RICK_E_INVALID_ARG, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    return e == hipSuccess ? RICK_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+rick_status rick_graph_destroy(rick_graph_t *g) {
+    if (!g) return fail(RICK_E_INVALID_ARG, "graph is NULL");
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return RICK_OK;
+}
+
+rick_status rick_stamps_create(int32_t n, rick_stamps_t **out) {
+    if (!out || n < 1) return fail(RICK_E_INVALID_ARG, "n=%d", n);
+    *out = nullptr;
+    rick_stamps_t *t = new (std::nothrow) rick_stamps_t;
+    if (!t) return fail(RICK_E_OOM, "stamps handle");
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess && khz <= 0) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipMalloc((void **)&t->dev, size_t(n) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(t->dev, 0, size_t(n) * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        if (t->dev) (void)hipFree(t->dev);
+        delete t;
+        return hip_fail(e, "stamps");
+    }
+    t->n = n;
+    t->khz = double(khz);
+    *out = t;
+    return RICK_OK;
+}
+
+rick_status rick_stamp(rick_stamps_t *t, int32_t i, void *stream) {
+    if (!t || i < 0 || i >= t->n) return fail(RICK_E_INVALID_ARG, "stamp %d", i);
+    hipError_t e = launch_stamp(t->dev + i, (hipStream_t)stream);
+    return e == hipSuccess ? RICK_OK : hip_fail(e, "stamp");
+}
+
+rick_status rick_stamps_elapsed(rick_stamps_t *t, int32_t i, int32_t j, float *ms) {
+    if (!t || !ms || i < 0 || j < 0 || i >= t->n || j >= t->n) return fail(RICK_E_INVALID_ARG, "stamps %d, %d", i, j);
+    uint64_t a = 0, b = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&a, t->dev + i, sizeof a, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&b, t->dev + j, sizeof b, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read stamps");
+    *ms = float(double(int64_t(b - a)) / t->khz);
+    return RICK_OK;
+}
+
+rick_status rick_stamps_destroy(rick_stamps_t *t) {
+    if (!t) return fail(RICK_E_INVALID_ARG, "stamps is NULL");
+    if (t->dev) (void)hipFree(t->dev);
+    delete t;
+    return RICK_OK;
+}
+
+rick_status rick_autotune(const rick_plan_desc *d, const double *uvw, const double *freq_hz, const void *vis,
+                          const float *weight, int64_t nrow, int32_t nchan, void *stream, int32_t *tile,
+                          int32_t *chunk, float *ms) {
+    if (!d || !tile || !chunk || !ms) return fail(RICK_E_INVALID_ARG, "NULL argument");
+    rick_status st = validate(d);
+    if (st != RICK_OK) return st;
+    DeviceGuard guard(d->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t real_bytes = d->precision == RICK_PREC_FP64 ? 8 : 4;
+    void *image = nullptr;
+    hipError_t e = hipMalloc(&image, size_t(d->grid_n) * d->grid_n * real_bytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(RICK_E_OOM, "autotune image") : hip_fail(e, "hipMalloc");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = -1.0f;
+    int32_t best_t = 0, best_c = 0;
+    rick_status result = RICK_OK;
+    const int32_t tiles[] = {16, 32, 64}, chunks[] = {2048, 8192, 32768};
+    for (int32_t T : tiles) {
+        if (e != hipSuccess || result != RICK_OK) break;
+        if (T < d->support || T > d->grid_n) continue;
+        for (int32_t CH : chunks) {
+            rick_plan_desc dd = *d;
+            dd.tile = T;
+            dd.chunk = CH;
+            dd.flags &= ~RICK_FLAG_TIMING;
+            rick_plan_t *p = nullptr;
+            st = rick_plan(&dd, &p);
+            if (st == RICK_E_INVALID_ARG) continue;   // tile does not fit this support / LDS
+            if (st != RICK_OK) {
+                result = st;
+                break;
+            }
+            float t_ms = 0.0f;
+            for (int it = 0; it < 3 && st == RICK_OK; ++it) {
+                if (it == 1) e = hipEventRecord(e0, s);
+                st = rick_reset(p, stream);
+                if (st == RICK_OK) st = rick_grid(p, uvw, freq_hz, vis, weight, nrow, nchan, stream);
+                if (st == RICK_OK) st = rick_fft_planes(p, stream);
+                if (st == RICK_OK) st = rick_wstack_image(p, image, stream);
+            }
+            if (st == RICK_OK) {
+                e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+                t_ms *= 0.5f;
+            }
+            (void)rick_plan_destroy(p);
+            if (st != RICK_OK) {
+                result = st;
+                break;
+            }
+            if (e != hipSuccess) break;
+            if (best < 0.0f || t_ms < best) {
+                best = t_ms;
+                best_t = T;
+                best_c = CH;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(image);
+    if (result != RICK_OK) return result;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    if (best < 0.0f) return fail(RICK_E_INVALID_ARG, "no tile fits support %d", d->support);
+    *tile = best_t;
+    *chunk = best_c;
+    *ms = best;
     return RICK_OK;
 }
 

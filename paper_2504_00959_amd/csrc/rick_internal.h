@@ -83,6 +83,12 @@ __device__ __forceinline__ bool row_set(const uint64_t *__restrict__ row_bits, c
     return (row_bits[(int64_t)k * g.occw + (ty >> 6)] >> (ty & 63)) & 1ull;
 }
 
+// Centre of plane k: w_k = w_min + (k + 1/2) dw, in float64, multiply then
+// add, each rounded (no contraction), as on the host.
+__device__ __forceinline__ double plane_centre(const Geom &g, int32_t k) {
+    return __dadd_rn(g.w_min, __dmul_rn((double)k + 0.5, g.dw));
+}
+
 // ---- kernel launchers (each returns hipGetLastError() of its launches) ----
 hipError_t launch_zero_stats(Stats *st, hipStream_t s);
 template <typename real>
@@ -140,6 +146,8 @@ hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Sta
 template <typename real>
 hipError_t launch_merge_margins(const Geom &g, const BinScan *scan, const real *margin, uint64_t *tile_bits,
                                 uint64_t *row_bits, real *mesh, hipStream_t s);
+// Device clock value (constant rate) into *slot once the stream's preceding work is done.
+hipError_t launch_stamp(uint64_t *slot, hipStream_t s);
 // Clear both occupancy bitmaps (a fill kernel; no memset node in captured work).
 hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
 // Batched centred 2-D inverse FFT, in place, all planes.  Rows of an empty
@@ -160,12 +168,11 @@ bool fft_supported(int N);
 // Column transform fused with the w-correction, plane sum and normalisation.
 size_t fused_screen_lds_bytes(int N, size_t real_bytes);
 template <typename real>
-hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *wk,
-                                  const double *corr, const Stats *st, const uint64_t *row_bits, real *image,
-                                  int kahan, hipStream_t s);
+hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *corr,
+                                  const Stats *st, const uint64_t *row_bits, real *image, int kahan, hipStream_t s);
 // Phase screen + plane sum + normalisation.
 template <typename real>
-hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *wk, const double *corr,
+hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *corr,
                           const Stats *st, real *image, int kahan, hipStream_t s);
 
 }  // namespace rick

@@ -32,7 +32,6 @@ __device__ __forceinline__ void sincospi_r(double x, double *s, double *c) { sin
 
 template <typename real, bool KAHAN>
 __global__ __launch_bounds__(kScreenBlock) void k_wscreen(Geom g, const real *__restrict__ mesh,
-                                                          const double *__restrict__ wk,
                                                           const double *__restrict__ corr,
                                                           const Stats *__restrict__ st, real *__restrict__ image) {
     using C = typename R2T<real>::t;
@@ -54,7 +53,7 @@ __global__ __launch_bounds__(kScreenBlock) void k_wscreen(Geom g, const real *__
 #pragma unroll 4
     for (int k = 0; k < g.Nw; ++k) {
         const C v = f[(int64_t)k * npix];
-        const double tau = wk[k] * nm1;
+        const double tau = plane_centre(g, k) * nm1;
         const double tr = tau - rint(tau);
         real sn, cs;
         sincospi_r((real)(2.0 * tr), &sn, &cs);
@@ -76,22 +75,21 @@ __global__ __launch_bounds__(kScreenBlock) void k_wscreen(Geom g, const real *__
 }  // namespace
 
 template <typename real>
-hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *wk, const double *corr, const Stats *st,
-                          real *image, int kahan, hipStream_t s) {
+hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *corr, const Stats *st, real *image,
+                          int kahan, hipStream_t s) {
     const int64_t npix = (int64_t)g.N * g.N;
     const unsigned blocks = (unsigned)((npix + kScreenBlock - 1) / kScreenBlock);
     if (kahan)
-        hipLaunchKernelGGL((k_wscreen<real, true>), dim3(blocks), dim3(kScreenBlock), 0, s, g, mesh, wk, corr, st,
-                           image);
+        hipLaunchKernelGGL((k_wscreen<real, true>), dim3(blocks), dim3(kScreenBlock), 0, s, g, mesh, corr, st, image);
     else
-        hipLaunchKernelGGL((k_wscreen<real, false>), dim3(blocks), dim3(kScreenBlock), 0, s, g, mesh, wk, corr, st,
+        hipLaunchKernelGGL((k_wscreen<real, false>), dim3(blocks), dim3(kScreenBlock), 0, s, g, mesh, corr, st,
                            image);
     return hipGetLastError();
 }
 
-template hipError_t launch_wscreen<float>(const Geom &, const float *, const double *, const double *, const Stats *,
-                                          float *, int, hipStream_t);
-template hipError_t launch_wscreen<double>(const Geom &, const double *, const double *, const double *,
-                                           const Stats *, double *, int, hipStream_t);
+template hipError_t launch_wscreen<float>(const Geom &, const float *, const double *, const Stats *, float *, int,
+                                          hipStream_t);
+template hipError_t launch_wscreen<double>(const Geom &, const double *, const double *, const Stats *, double *, int,
+                                           hipStream_t);
 
 }  // namespace rick

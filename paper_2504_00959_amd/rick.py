@@ -74,8 +74,22 @@ def lib() -> ctypes.CDLL:
     L.rick_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     L.rick_plan_destroy.argtypes = [P]
     L.rick_plan_bin_counts.argtypes = [P, P, ctypes.c_int64]
+    L.rick_plan_retarget.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.rick_capture_begin.argtypes = [P]
+    L.rick_capture_end.argtypes = [P, ctypes.POINTER(P)]
+    L.rick_graph_launch.argtypes = [P, P]
+    L.rick_graph_destroy.argtypes = [P]
+    L.rick_stamps_create.argtypes = [ctypes.c_int32, ctypes.POINTER(P)]
+    L.rick_stamp.argtypes = [P, ctypes.c_int32, P]
+    L.rick_stamps_elapsed.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]
+    L.rick_stamps_destroy.argtypes = [P]
+    L.rick_autotune.argtypes = [ctypes.POINTER(PlanDesc), P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64,
+                                ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_float)]
     for f in ("rick_plan", "rick_grid", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
-              "rick_plan_destroy", "rick_plan_bin_counts"):
+              "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
+              "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
+              "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget"):
         getattr(L, f).restype = ctypes.c_int32
     L.rick_status_str.argtypes = [ctypes.c_int32]
     L.rick_status_str.restype = ctypes.c_char_p
@@ -204,6 +218,10 @@ class Plan:
         _check(lib().rick_wstack_image(self._h, out.data_ptr(), _stream_handle(stream)), "rick_wstack_image")
         return out
 
+    def retarget(self, fov: float, w_min: float, w_max: float):
+        """Field of view and w range for the work issued next (host-side only)."""
+        _check(lib().rick_plan_retarget(self._h, fov, w_min, w_max), "rick_plan_retarget")
+
     def reset(self, stream=None):
         _check(lib().rick_reset(self._h, _stream_handle(stream)), "rick_reset")
 
@@ -296,6 +314,94 @@ class Plan:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Graph:
+    """Work recorded from a stream (``rick_capture_begin`` / ``rick_capture_end``)
+    and replayed with ``launch``.  Use ``with Graph.record(stream) as g:`` and
+    issue the plan calls on that stream inside the block."""
+
+    def __init__(self):
+        self._h = None
+
+    @classmethod
+    def record(cls, stream=None):
+        return _Recording(cls(), stream)
+
+    def launch(self, stream=None):
+        _check(lib().rick_graph_launch(self._h, _stream_handle(stream)), "rick_graph_launch")
+
+    def close(self):
+        if self._h:
+            _check(lib().rick_graph_destroy(self._h), "rick_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Recording:
+    def __init__(self, graph, stream):
+        self.graph, self.stream = graph, stream
+
+    def __enter__(self):
+        _check(lib().rick_capture_begin(_stream_handle(self.stream)), "rick_capture_begin")
+        return self.graph
+
+    def __exit__(self, exc_type, *a):
+        h = ctypes.c_void_p()
+        st = lib().rick_capture_end(_stream_handle(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            _check(st, "rick_capture_end")
+            self.graph._h = h
+        elif st == RICK_OK:
+            lib().rick_graph_destroy(h)
+
+
+class Stamps:
+    """Device timestamp slots (``rick_stamp`` may be recorded into a graph)."""
+
+    def __init__(self, n: int):
+        h = ctypes.c_void_p()
+        _check(lib().rick_stamps_create(n, ctypes.byref(h)), "rick_stamps_create")
+        self._h, self.n = h, n
+
+    def stamp(self, i: int, stream=None):
+        _check(lib().rick_stamp(self._h, i, _stream_handle(stream)), "rick_stamp")
+
+    def elapsed(self, i: int, j: int) -> float:
+        ms = ctypes.c_float()
+        _check(lib().rick_stamps_elapsed(self._h, i, j, ctypes.byref(ms)), "rick_stamps_elapsed")
+        return float(ms.value)
+
+    def close(self):
+        if self._h:
+            _check(lib().rick_stamps_destroy(self._h), "rick_stamps_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ds, uvw, vis, weight=None, precision="fp32", device=0, fused=True, stream=None):
+    """Fastest (tile, chunk) for a job, by ``rick_autotune``; returns (tile, chunk, ms)."""
+    args = dict(ds.plan_kwargs())
+    args.setdefault("max_vis", max(1, ds.nvis))
+    desc = make_desc(precision=precision, device=device, fused=fused, **args)
+    nrow = int(uvw.shape[0])
+    nchan = 1 if ds.freq is None else len(ds.freq)
+    freq = None if ds.freq is None else (ctypes.c_double * nchan)(*[float(f) for f in ds.freq])
+    t, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(lib().rick_autotune(ctypes.byref(desc), uvw.data_ptr(), freq, vis.data_ptr(),
+                               None if weight is None else weight.data_ptr(), nrow, nchan, _stream_handle(stream),
+                               ctypes.byref(t), ctypes.byref(c), ctypes.byref(ms)), "rick_autotune")
+    return int(t.value), int(c.value), float(ms.value)
 
 
 def wstack_image(ds, device: int = 0, precision: str = "fp32", **kw):

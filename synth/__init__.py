@@ -243,6 +243,90 @@ def ska_low_precision(device: Optional[str] = None, with_vis: bool = True) -> Da
     return ds
 
 
+def _xyz_to_uvw_torch(bxyz: np.ndarray, ha_rad: np.ndarray, dec_rad: float, device: str):
+    """``xyz_to_uvw`` in float64 on a torch device (same formulas and row order)."""
+    import torch
+    sd, cd = math.sin(dec_rad), math.cos(dec_rad)
+    h = torch.as_tensor(ha_rad, dtype=torch.float64, device=device)[:, None]
+    sh, ch = torch.sin(h), torch.cos(h)
+    b = torch.as_tensor(bxyz, dtype=torch.float64, device=device)
+    X, Y, Z = b[None, :, 0], b[None, :, 1], b[None, :, 2]
+    u = sh * X + ch * Y
+    v = -sd * ch * X + sd * sh * Y + cd * Z
+    w = cd * ch * X - cd * sh * Y + sd * Z
+    return torch.stack([u, v, w], dim=-1).reshape(-1, 3)
+
+
+def batched_jobs(seed: int = 4, n_jobs: int = 64, grid_sizes=(512, 1024, 2048, 4096), nvis_range=(1e5, 5e7),
+                 n_src: int = 20, n_stations: int = 512, sigma_m: float = 3000.0, dump_s: float = 10.0,
+                 n_dumps: int = 1440, ha_start_h: float = -2.0, freq_hz: float = 150e6, support: int = 7,
+                 oversample: int = 64, uv_fill: float = 0.45, min_planes: int = 4, max_planes: int = 64,
+                 lat_deg: float = -26.7, dec_deg: float = -30.0, device: Optional[str] = None,
+                 with_vis: bool = True) -> list:
+    """Many independent imaging jobs of uneven size (the batched form).
+
+    The SKA-LOW-like array of ``ska_low`` observed for 4 h at 10 s (1440
+    dumps, time-major rows) at one channel.  Job j: grid N_j uniform over
+    ``grid_sizes``; visibility count log-uniform over ``nvis_range``; a
+    contiguous run of that many rows from a uniform start; FoV = uv_fill N /
+    u_max over its rows; w range from its data; planes
+    N_w = clamp(2^ceil(log2(4 (w_max - w_min) max|n - 1|)), 4, 64) with
+    max|n - 1| at the image corner (a w phase error of at most pi/4 there);
+    ``n_src`` point sources as in ``ska_low``.  Draw order: stations E, N;
+    then per job N_j, count, start row, source l, m, flux-U.  With a device,
+    uvw and visibilities are generated there (uvw then is a device tensor).
+    """
+    rng = np.random.default_rng(seed)
+    enu = station_layout(rng, n_stations, sigma_m)
+    xyz = enu_to_xyz(enu, math.radians(lat_deg))
+    i, j = np.triu_indices(n_stations, k=1)
+    bxyz = xyz[j] - xyz[i]
+    nbl = bxyz.shape[0]
+    total_rows = n_dumps * nbl
+    scale = freq_hz / C0
+    jobs = []
+    for jj in range(n_jobs):
+        N = int(grid_sizes[int(rng.integers(0, len(grid_sizes)))])
+        nv = int(round(math.exp(rng.uniform(math.log(nvis_range[0]), math.log(nvis_range[1])))))
+        nv = min(nv, total_rows)
+        r0 = int(rng.integers(0, total_rows - nv + 1))
+        t0, t1 = r0 // nbl, (r0 + nv - 1) // nbl
+        ha = (ha_start_h * 3600.0 + dump_s * np.arange(t0, t1 + 1)) * (2.0 * math.pi / SIDEREAL_DAY_S)
+        if device is None:
+            uvw = xyz_to_uvw(bxyz, ha, math.radians(dec_deg))[r0 - t0 * nbl:r0 - t0 * nbl + nv].copy()
+            umax = float(np.max(np.abs(uvw[:, :2]))) * scale
+            w_lo, w_hi = float(uvw[:, 2].min()) * scale, float(uvw[:, 2].max()) * scale
+        else:
+            uvw = _xyz_to_uvw_torch(bxyz, ha, math.radians(dec_deg), device)[r0 - t0 * nbl:r0 - t0 * nbl + nv]
+            uvw = uvw.contiguous()
+            umax = float(uvw[:, :2].abs().max()) * scale
+            w_lo, w_hi = float(uvw[:, 2].min()) * scale, float(uvw[:, 2].max()) * scale
+        fov = uv_fill * N / umax
+        if not w_hi > w_lo:
+            w_hi = w_lo + 1.0
+        r2 = 2.0 * (0.5 * fov) ** 2
+        nm1_max = r2 / (1.0 + math.sqrt(1.0 - r2))
+        x = 4.0 * (w_hi - w_lo) * nm1_max
+        nw = 1 << max(0, math.ceil(math.log2(x))) if x > 1.0 else 1
+        nw = int(min(max(nw, min_planes), max_planes))
+        l = rng.uniform(-0.4 * fov, 0.4 * fov, n_src)
+        m = rng.uniform(-0.4 * fov, 0.4 * fov, n_src)
+        a, b = 10.0 ** -1.5, 0.01 ** -1.5
+        flux = (a + rng.uniform(0.0, 1.0, n_src) * (b - a)) ** (-1.0 / 1.5)
+        freq = np.array([freq_hz])
+        vis = None
+        if with_vis:
+            if device is None:
+                vis = point_source_vis_np(uvw[:, 0] * scale, uvw[:, 1] * scale, uvw[:, 2] * scale, l, m,
+                                          flux)[:, None].astype(np.complex64)
+            else:
+                vis = point_source_vis_torch(uvw, np.array([scale]), l, m, flux, device)
+        jobs.append(Dataset(uvw=uvw, freq=freq, vis=vis, weight=None, grid_n=N, n_wplanes=nw, support=support,
+                            oversample=oversample, fov=fov, w_min=w_lo, w_max=w_hi,
+                            sources=dict(l=l, m=m, flux=flux), name=f"batch_job{jj}"))
+    return jobs
+
+
 def ska_low_small(seed: int = 3, device: Optional[str] = None, **kw) -> Dataset:
     """Same generator at a size the oracle finishes in seconds."""
     args = dict(seed=seed, n_stations=48, n_times=24, dump_s=60.0, n_chan=4, n_src=20,
