@@ -532,15 +532,22 @@ def batch_report(args):
         graph.launch(stream)
         totals.append(stamps.elapsed(0, n))
         lat = [stamps.elapsed(i, i + 1) for i in range(n)]
+    # graph against eager in the apparent image (both multiplied by C_p C_q): the
+    # shared-tile float atomics add in no fixed order, and dividing by the taper
+    # magnifies that rounding in the outermost pixels of the corrected image
+    import oracle.pixels
+    from oracle import wstack as ow
     diffs = []
-    for a, b in zip(imgs, eager):
-        diffs.append(float(torch.linalg.vector_norm((a - b).double()) /
-                           max(float(torch.linalg.vector_norm(b.double())), 1e-300)))
+    for ds, a, b in zip(jobs, imgs, eager):
+        c = torch.as_tensor(ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel,
+                                                            ds.kernel_param), ds.grid_n), device=dev)
+        c2 = c[:, None] * c[None, :]
+        diffs.append(float(torch.linalg.vector_norm((a - b).double() * c2) /
+                           max(float(torch.linalg.vector_norm(b.double() * c2)), 1e-300)))
     worst = max(diffs)
     # the smallest job against the oracle at sampled pixels
     small = min(range(n), key=lambda i: jobs[i].nvis)
     ds = jobs[small]
-    import oracle.pixels
     rng = np.random.default_rng(0)
     N = ds.grid_n
     pp = np.r_[N // 2, rng.integers(N // 4, 3 * N // 4, 5)]
@@ -550,7 +557,6 @@ def batch_report(args):
                         fov=ds.fov, w_min=ds.w_min, w_max=ds.w_max)
     ref, _, kept, _ = oracle.pixels.wstack_pixels(dsh.uvw, dsh.freq, dsh.vis, None, pp, qq, **dsh.plan_kwargs())
     got = imgs[small].double().cpu().numpy()[qq, pp]
-    from oracle import wstack as ow
     corr = ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param), N)
     c2 = corr[pp] * corr[qq]
     ocheck = float(np.linalg.norm((got - ref) * c2) / np.linalg.norm(ref * c2))
@@ -563,8 +569,8 @@ def batch_report(args):
                           "p99": round(float(np.percentile(lat_sorted, 99)), 3),
                           "max": round(float(lat_sorted[-1]), 3)},
            "eager_batch_ms": round(float(np.median(eager_ms)), 3),
-           "graph_vs_eager_max_rel_rms": worst,
-           "graph_vs_eager_rel_rms": [float("%.3g" % d) for d in diffs],
+           "graph_vs_eager_max_apparent_rel_rms": worst,
+           "graph_vs_eager_apparent_rel_rms": [float("%.3g" % d) for d in diffs],
            "job_shapes": [f"{ds.grid_n}x{ds.n_wplanes}:{ds.nvis}" for ds in jobs],
            "oracle_check": {"job": small, "pixels": int(len(pp)), "apparent_rel_rms": ocheck},
            "shapes": {f"{k[0]}x{k[1]}": {"jobs": len(shapes[k]), "tile": v[0], "chunk": v[1],
