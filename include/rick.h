@@ -14,6 +14,9 @@
  *   rick_fft_planes    batched, centred 2-D inverse FFT of every plane
  *   rick_wstack_image  phase screen + sum over planes + normalisation
  *   rick_reset         start a new image (clears the weight sum and counters)
+ *   rick_predict_planes, rick_degrid
+ *                      prediction: model image -> visibilities (Eq. 2), the
+ *                      adjoint of the imaging steps
  *
  * Conventions shared by every call:
  *   - All entry points return a rick_status; no exception, abort or exit
@@ -128,7 +131,7 @@ typedef struct rick_plan_info_t {
     int32_t rec1_bytes;      /* bytes of a first-level binning record (12, 16 or 24) */
     int32_t pad1;
     int32_t tile, chunk;     /* effective tile edge and chunk size */
-    int32_t state;           /* 0 = empty, 1 = gridded, 2 = transformed */
+    int32_t state;           /* 0 = empty, 1 = gridded, 2 = transformed, 3 = predicted planes */
     int32_t n_timers;        /* number of valid entries in kernel_ms / kernel_calls / kernel_names */
     float kernel_ms[16];     /* with RICK_FLAG_TIMING: mean device time per launch of each kernel over the
                                 launches since the previous rick_plan_info (the last 64 at most) */
@@ -193,6 +196,43 @@ rick_status rick_fft_planes(rick_plan_t *p, void *stream);
  * (planes not transformed), RICK_E_HIP.
  */
 rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream);
+
+/*
+ * rick_predict_planes -- the first half of prediction (degridding): the
+ * visibility model of Eq. 2 discretised by w-stacking, Sec. 2.1 run the other
+ * way.  For every plane k of the plan's w range, the mesh receives the
+ * centred forward DFT H_k of the plane image
+ *   P_k[q][p] = M[q][p] exp(-2 pi i w_k (n_pq - 1)) / (n_pq C(l'_p) C(l'_q))
+ *   H_k[j][i] = sum_{q,p} P_k[q][p] exp(-2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
+ * (zero outside the unit circle; phase and n - 1 in float64 as in
+ * rick_wstack_image).  The mesh holds conj(H_k) afterwards (the forward DFT
+ * runs as the inverse DFT of the conjugate) and every tile is marked set.
+ *   model  device float32 [N][N] (float64 in FP64 mode), indexed [q = m][p = l],
+ *          the sky brightness per pixel; read only, owned by the caller
+ * Overwrites what was gridded; call rick_reset before gridding again.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (NULL or misaligned model), RICK_E_HIP.
+ */
+rick_status rick_predict_planes(rick_plan_t *p, const void *model, void *stream);
+
+/*
+ * rick_degrid -- the second half of prediction: every visibility is
+ * interpolated from its closest plane with the gridding kernel's tap table
+ * (Eq. 3 read backwards),
+ *   V = sum_{t_y, t_x} g_{s_y}[t_y] g_{s_x}[t_x] H_k[c_y + t_y - h][c_x + t_x - h],
+ * with cell, sub-cell offset, plane and drop decision exactly those of
+ * rick_grid (a visibility rick_grid would drop for its position is predicted
+ * as 0), so that prediction is the adjoint of the imaging steps.
+ *   uvw      device, float64 [nrow][3]: metres if freq_hz != NULL, else wavelengths
+ *   freq_hz  HOST, float64 [nchan] channel frequencies, or NULL (then nchan must be 1)
+ *   vis_out  device complex [nrow][nchan] (interleaved float32 re, im; float64 in
+ *            FP64 mode), written completely; owned by the caller
+ * May be called any number of times on the same predicted planes.  Not
+ * limited by max_vis.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG, RICK_E_STATE (no
+ * rick_predict_planes since the last reset or gridding), RICK_E_HIP.
+ */
+rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz, void *vis_out, int64_t nrow,
+                        int32_t nchan, void *stream);
 
 /*
  * rick_reset -- begin a new image: zero the weight sum and the counters and

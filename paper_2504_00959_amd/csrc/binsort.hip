@@ -41,6 +41,7 @@
 // contraction off, so that cell, sub-cell offset, plane and drop decisions are
 // bit-identical to a plain float64 evaluation of the same steps.
 #include "rick_internal.h"
+#include "quant.h"
 
 namespace rick {
 
@@ -90,10 +91,6 @@ __global__ void k_set_scales(double *__restrict__ dst, ChanScales cs, int32_t n)
     if (t < n) dst[t] = cs.s[t];
 }
 
-struct Quant {
-    int32_t cx, cy, sx, sy, k;
-};
-
 template <typename real>
 __device__ __forceinline__ Rec1<real, false> make_rec1(const Geom &g, const Quant &q, real ar, real ai,
                                                       Rec1<real, false> *) {
@@ -123,41 +120,6 @@ __device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, true> &r,
     const uint32_t ml = (1u << lb) - 1, ms = (1u << sb) - 1;
     return Pos1{(int32_t)(r.pos & ml), (int32_t)((r.pos >> (lb + sb)) & ml), (int32_t)((r.pos >> lb) & ms),
                 (int32_t)(r.pos >> (2 * lb + sb))};
-}
-
-// Position, plane and drop decision of one visibility, evaluated without
-// branches (every lane computes every step; the decisions are combined at
-// the end), which keeps the loop free of execution-mask changes.
-template <typename real>
-__device__ __forceinline__ bool quantise(const Geom &g, double u, double v, double w, real vr, real vi, float wt,
-                                         Quant &q) {
-#pragma clang fp contract(off)
-    // (bitwise & on 0/1 integers on purpose: no short-circuit branches)
-    unsigned ok = (unsigned)isfinite(u) & (unsigned)isfinite(v) & (unsigned)isfinite(w) &
-                  (unsigned)isfinite((double)vr) & (unsigned)isfinite((double)vi) & (unsigned)isfinite(wt);
-    double xs = u * g.fov;
-    xs = xs * (double)g.OS;
-    xs = xs + g.half;
-    double ys = v * g.fov;
-    ys = ys * (double)g.OS;
-    ys = ys + g.half;
-    ok &= (unsigned)(fabs(xs) <= 1073741824.0) & (unsigned)(fabs(ys) <= 1073741824.0);
-    const int32_t X = ok ? (int32_t)rint(xs) : 0;
-    const int32_t Y = ok ? (int32_t)rint(ys) : 0;
-    q.cx = (X + (g.OS >> 1)) >> g.log2OS;   // floor division by OS (arithmetic shift)
-    q.cy = (Y + (g.OS >> 1)) >> g.log2OS;
-    q.sx = X - (q.cx << g.log2OS);
-    q.sy = Y - (q.cy << g.log2OS);
-    ok &= (unsigned)(wt > 0.0f);
-    ok &= (unsigned)(q.cx - g.h >= 0) & (unsigned)(q.cx + g.h <= g.N - 1) & (unsigned)(q.cy - g.h >= 0) &
-          (unsigned)(q.cy + g.h <= g.N - 1);
-    double kf = floor((w - g.w_min) / g.dw);
-    if (isnan(kf)) kf = 0.0;
-    kf = kf < 0.0 ? 0.0 : kf;
-    kf = kf > (double)(g.Nw - 1) ? (double)(g.Nw - 1) : kf;
-    q.k = (int32_t)kf;
-    if (!ok) q = Quant{0, 0, 0, 0, 0};
-    return ok != 0u;
 }
 
 // Tile of edge 2^shift cells holding the footprint origin (c - h) of cell (cx, cy).

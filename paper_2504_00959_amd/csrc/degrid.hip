@@ -1,0 +1,201 @@
+// Prediction (degridding): visibilities of a model sky image by the
+// w-stacking discretisation of Sec. 2.1 run the other way, i.e. Eq. 2
+// evaluated plane by plane:
+//   plane images   P_k[q][p] = M[q][p] exp(-2 pi i w_k (n_pq - 1)) / (n_pq C(l'_p) C(l'_q))
+//   forward DFT    H_k[j][i] = sum_{q,p} P_k[q][p] exp(-2 pi i ((i-N/2)(p-N/2) + (j-N/2)(q-N/2)) / N)
+//   interpolation  V = sum_{t_y,t_x} g_{s_y}[t_y] g_{s_x}[t_x] H_k[c_y + t_y - h][c_x + t_x - h]
+// with the visibility's cell, sub-cell offset, plane and drop decision taken
+// exactly as imaging takes them (quant.h), so that prediction is the adjoint
+// of the imaging steps.
+//
+// The forward DFT runs through the library's centred inverse FFT: the screen
+// kernel writes the complex conjugate of P_k, the inverse transform of
+// conj(P_k) is conj(H_k), and the interpolation conjugates what it reads.
+#include "rick_internal.h"
+#include "quant.h"
+
+namespace rick {
+
+namespace {
+
+constexpr int kPredBlock = 256;
+constexpr int kDegridBlock = 256;
+
+template <typename real>
+struct Cplx;
+template <>
+struct Cplx<float> {
+    using t = float2;
+};
+template <>
+struct Cplx<double> {
+    using t = double2;
+};
+
+__device__ __forceinline__ void sincospi_p(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_p(double x, double *s, double *c) { sincospi(x, s, c); }
+
+// conj(P_k) for every plane, one thread per pixel (each plane's write is
+// row-coalesced).  n - 1 and the phase w_k (n - 1) in turns are formed in
+// float64 and reduced to [-1/2, 1/2] before the trigonometric evaluation, as
+// in imaging; pixels outside the unit circle are zero.
+template <typename real>
+__global__ __launch_bounds__(kPredBlock) void k_predict_screen(Geom g, const real *__restrict__ model,
+                                                               const double *__restrict__ corr,
+                                                               real *__restrict__ mesh) {
+    using C = typename Cplx<real>::t;
+    const int64_t npix = (int64_t)g.N * g.N;
+    const int64_t pix = (int64_t)blockIdx.x * kPredBlock + threadIdx.x;
+    if (pix >= npix) return;
+    const int q = (int)(pix / g.N), p = (int)(pix % g.N);
+    const double dl = g.fov / g.N;
+    const double l = (double)(p - g.N / 2) * dl;
+    const double m = (double)(q - g.N / 2) * dl;
+    const double r2 = l * l + m * m;
+    const bool inside = r2 < 1.0;
+    const double nm1 = inside ? -r2 / (1.0 + sqrt(1.0 - r2)) : 0.0;
+    const real base = inside ? (real)((double)model[pix] / ((1.0 + nm1) * corr[p] * corr[q])) : (real)0;
+    C *out = reinterpret_cast<C *>(mesh) + pix;
+    for (int k = 0; k < g.Nw; ++k) {
+        const double tau = plane_centre(g, k) * nm1;
+        const double tr = tau - rint(tau);
+        real sn, cs;
+        sincospi_p((real)(2.0 * tr), &sn, &cs);
+        C v;
+        v.x = base * cs;   // conj(exp(-2 pi i tau)) = exp(+2 pi i tau)
+        v.y = base * sn;
+        out[(int64_t)k * npix] = v;
+    }
+}
+
+// Every tile and tile row of every plane marked as holding values (the FFT
+// then reads the whole of each plane).
+__global__ void k_fill_bits(Geom g, uint64_t *__restrict__ tile_bits, uint64_t *__restrict__ row_bits) {
+    const int64_t n_tile_words = (int64_t)g.Nw * g.nt * g.occw;
+    const int64_t n_row_words = (int64_t)g.Nw * g.occw;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tile_words + n_row_words; i += stride) {
+        const int32_t word = (int32_t)((i < n_tile_words ? i : i - n_tile_words) % g.occw);
+        const int32_t left = g.nt - 64 * word;   // tiles (or tile rows) covered by this word
+        const uint64_t bits = left >= 64 ? ~0ull : ((1ull << left) - 1ull);
+        if (i < n_tile_words) tile_bits[i] = bits;
+        else row_bits[i - n_tile_words] = bits;
+    }
+}
+
+// One thread per visibility (row r, channel c at index r * nchan + c): the
+// position, plane and drop decision of imaging, then the W x W taps read
+// from the plane (conjugated) and weighted by the tap-table rows of the
+// sub-cell offsets.  Dropped visibilities are predicted as 0.
+template <typename real, int W>
+__global__ __launch_bounds__(kDegridBlock) void k_degrid(Geom g, const double *__restrict__ uvw,
+                                                         const double *__restrict__ scales, int64_t nrow,
+                                                         int32_t nchan, const real *__restrict__ lut,
+                                                         const real *__restrict__ mesh, real *__restrict__ out) {
+    using C = typename Cplx<real>::t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    real *s_lut = reinterpret_cast<real *>(smem);
+    for (int i = threadIdx.x; i < g.OS * W; i += kDegridBlock) s_lut[i] = lut[i];
+    __syncthreads();
+    const int64_t nvis = nrow * nchan;
+    const int64_t npix = (int64_t)g.N * g.N;
+    const C *planes = reinterpret_cast<const C *>(mesh);
+    C *vout = reinterpret_cast<C *>(out);
+    const int64_t stride = (int64_t)gridDim.x * kDegridBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kDegridBlock + threadIdx.x; i < nvis; i += stride) {
+        const int64_t r = i / nchan;
+        const int32_t c = (int32_t)(i - r * nchan);
+        double u, v, w;
+        {
+#pragma clang fp contract(off)
+            const double sc = scales[c];
+            u = uvw[3 * r] * sc;
+            v = uvw[3 * r + 1] * sc;
+            w = uvw[3 * r + 2] * sc;
+        }
+        Quant qq;
+        const bool keep = quantise<real>(g, u, v, w, (real)0, (real)0, 1.0f, qq);
+        real vr = 0, vi = 0;
+        if (keep) {
+            const real *gx = s_lut + (qq.sx + (g.OS >> 1)) * W;
+            const real *gy = s_lut + (qq.sy + (g.OS >> 1)) * W;
+            const C *base = planes + (int64_t)qq.k * npix + (int64_t)(qq.cy - g.h) * g.N + (qq.cx - g.h);
+#pragma unroll
+            for (int ty = 0; ty < W; ++ty) {
+                const C *row = base + (int64_t)ty * g.N;
+                real rr = 0, ri = 0;
+#pragma unroll
+                for (int tx = 0; tx < W; ++tx) {
+                    const C h = row[tx];
+                    rr += gx[tx] * h.x;
+                    ri += gx[tx] * h.y;
+                }
+                vr += gy[ty] * rr;
+                vi += gy[ty] * ri;
+            }
+        }
+        C o;
+        o.x = vr;
+        o.y = -vi;   // the plane holds conj(H_k)
+        vout[i] = o;
+    }
+}
+
+template <typename real, int W>
+hipError_t degrid_w(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
+                    const real *lut, const real *mesh, real *out, hipStream_t s) {
+    const int64_t nvis = nrow * nchan;
+    if (nvis == 0) return hipSuccess;
+    int64_t blocks = (nvis + kDegridBlock - 1) / kDegridBlock;
+    if (blocks > 65536) blocks = 65536;
+    const size_t lds = (size_t)g.OS * W * sizeof(real);
+    hipLaunchKernelGGL((k_degrid<real, W>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, uvw, scales,
+                       nrow, nchan, lut, mesh, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename real>
+hipError_t launch_predict_screen(const Geom &g, const real *model, const double *corr, real *mesh,
+                                 uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s) {
+    const int64_t npix = (int64_t)g.N * g.N;
+    const unsigned blocks = (unsigned)((npix + kPredBlock - 1) / kPredBlock);
+    hipLaunchKernelGGL((k_predict_screen<real>), dim3(blocks), dim3(kPredBlock), 0, s, g, model, corr, mesh);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t words = (int64_t)g.Nw * (g.nt + 1) * g.occw;
+    const unsigned fb = (unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_bits, dim3(fb), dim3(256), 0, s, g, tile_bits, row_bits);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
+                         const real *lut, const real *mesh, real *out, hipStream_t s) {
+    switch (g.W) {
+#define RICK_DEGRID_W(w) \
+    case w: return degrid_w<real, w>(g, uvw, scales, nrow, nchan, lut, mesh, out, s);
+        RICK_DEGRID_W(1)
+        RICK_DEGRID_W(3)
+        RICK_DEGRID_W(5)
+        RICK_DEGRID_W(7)
+        RICK_DEGRID_W(9)
+        RICK_DEGRID_W(11)
+        RICK_DEGRID_W(13)
+        RICK_DEGRID_W(15)
+#undef RICK_DEGRID_W
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_predict_screen<float>(const Geom &, const float *, const double *, float *, uint64_t *,
+                                                 uint64_t *, hipStream_t);
+template hipError_t launch_predict_screen<double>(const Geom &, const double *, const double *, double *,
+                                                  uint64_t *, uint64_t *, hipStream_t);
+template hipError_t launch_degrid<float>(const Geom &, const double *, const double *, int64_t, int32_t,
+                                         const float *, const float *, float *, hipStream_t);
+template hipError_t launch_degrid<double>(const Geom &, const double *, const double *, int64_t, int32_t,
+                                          const double *, const double *, double *, hipStream_t);
+
+}  // namespace rick

@@ -85,7 +85,7 @@ struct rick_plan_s {
     rick_plan_desc d;
     Geom g;
     bool fp64;
-    int state;               // 0 empty, 1 gridded, 2 transformed
+    int state;               // 0 empty, 1 gridded, 2 transformed, 3 predicted planes (conj(H_k))
     double du, dl;
     int64_t max_items;       // gridding launch bound per visibility (items <= nbins + 4 nvis / CH)
     size_t real_bytes;
@@ -208,7 +208,7 @@ void timer_end(rick_plan_t *p, int slot, hipStream_t s) {
 
 enum TimerSlot {
     T_COUNT = 0, T_SCAN, T_SCATTER, T_ZERO_HEAVY, T_GRID, T_FFT_ROWS, T_FFT_COLS, T_SCREEN, T_RESET,
-    T_FINE_COUNT, T_FINE_SCAN, T_FINE_SCATTER, T_MARK
+    T_FINE_COUNT, T_FINE_SCAN, T_FINE_SCATTER, T_MARK, T_PRED_SCREEN, T_PRED_FFT, T_DEGRID
 };
 
 }  // namespace
@@ -526,6 +526,7 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
         return fail(RICK_E_CAPACITY, "nrow*nchan=%lld > max_vis=%lld", (long long)(nrow * nchan),
                     (long long)p->d.max_vis);
     if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed; call rick_reset first");
+    if (p->state == 3) return fail(RICK_E_STATE, "mesh holds predicted planes; call rick_reset first");
     std::vector<double> sc(nchan, 1.0);
     if (freq_hz) {
         for (int c = 0; c < nchan; ++c) {
@@ -600,6 +601,7 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
 rick_status rick_fft_planes(rick_plan_t *p, void *stream) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
     if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed");
+    if (p->state == 3) return fail(RICK_E_STATE, "mesh holds predicted planes; call rick_reset first");
     DeviceGuard guard(p->d.device);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
@@ -656,6 +658,74 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
         e = launch_wscreen<float>(p->g, (const float *)p->mesh, p->corr, p->stats, (float *)image, kahan, s);
     timer_end(p, T_SCREEN, s);
     if (e != hipSuccess) return hip_fail(e, "wscreen");
+    return RICK_OK;
+}
+
+rick_status rick_predict_planes(rick_plan_t *p, const void *model, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!model) return fail(RICK_E_INVALID_ARG, "model is NULL");
+    if (((uintptr_t)model) & (p->fp64 ? 7 : 3)) return fail(RICK_E_INVALID_ARG, "misaligned model");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const Geom &g = p->g;
+    hipError_t e;
+    timer_begin(p, T_PRED_SCREEN, "predict_screen", s);
+    if (p->fp64)
+        e = launch_predict_screen<double>(g, (const double *)model, p->corr, (double *)p->mesh, p->tile_bits,
+                                          p->row_bits, s);
+    else
+        e = launch_predict_screen<float>(g, (const float *)model, p->corr, (float *)p->mesh, p->tile_bits,
+                                         p->row_bits, s);
+    timer_end(p, T_PRED_SCREEN, s);
+    if (e != hipSuccess) return hip_fail(e, "predict_screen");
+    // the inverse transform of conj(P_k) is conj(H_k); rows then columns, in place
+    timer_begin(p, T_PRED_FFT, "predict_fft", s);
+    if (p->fp64) {
+        e = launch_fft_rows<double>(g, (double *)p->mesh, (const double *)p->twiddle, p->tile_bits, p->row_bits, s);
+        if (e == hipSuccess) e = launch_fft_cols<double>(g, (double *)p->mesh, (const double *)p->twiddle, s);
+    } else {
+        e = launch_fft_rows<float>(g, (float *)p->mesh, (const float *)p->twiddle, p->tile_bits, p->row_bits, s);
+        if (e == hipSuccess) e = launch_fft_cols<float>(g, (float *)p->mesh, (const float *)p->twiddle, s);
+    }
+    timer_end(p, T_PRED_FFT, s);
+    if (e != hipSuccess) return hip_fail(e, "predict_fft");
+    p->state = 3;
+    return RICK_OK;
+}
+
+rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz, void *vis_out, int64_t nrow,
+                        int32_t nchan, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
+    if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
+    if (!freq_hz && nchan != 1) return fail(RICK_E_INVALID_ARG, "nchan=%d without freq_hz", nchan);
+    if (nchan > kMaxChan) return fail(RICK_E_INVALID_ARG, "nchan=%d > %d", nchan, kMaxChan);
+    if (nrow > (int64_t(1) << 40) / nchan) return fail(RICK_E_INVALID_ARG, "nrow*nchan too large");
+    if (nrow > 0 && (!uvw || !vis_out)) return fail(RICK_E_INVALID_ARG, "uvw or vis_out is NULL");
+    if (((uintptr_t)uvw & 7) || ((uintptr_t)vis_out & (p->fp64 ? 15 : 7)))
+        return fail(RICK_E_INVALID_ARG, "misaligned pointer");
+    if (p->state != 3) return fail(RICK_E_STATE, "no predicted planes; call rick_predict_planes first");
+    std::vector<double> sc(nchan, 1.0);
+    if (freq_hz) {
+        for (int c = 0; c < nchan; ++c) {
+            if (!std::isfinite(freq_hz[c]) || !(freq_hz[c] > 0.0))
+                return fail(RICK_E_INVALID_ARG, "freq_hz[%d]=%g", c, freq_hz[c]);
+            sc[c] = freq_hz[c] / kC0;
+        }
+    }
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_set_scales(p->scales, sc.data(), nchan, s);
+    if (e != hipSuccess) return hip_fail(e, "channel scales upload");
+    timer_begin(p, T_DEGRID, "degrid", s);
+    if (p->fp64)
+        e = launch_degrid<double>(p->g, uvw, p->scales, nrow, nchan, (const double *)p->lut, (const double *)p->mesh,
+                                  (double *)vis_out, s);
+    else
+        e = launch_degrid<float>(p->g, uvw, p->scales, nrow, nchan, (const float *)p->lut, (const float *)p->mesh,
+                                 (float *)vis_out, s);
+    timer_end(p, T_DEGRID, s);
+    if (e != hipSuccess) return hip_fail(e, "degrid");
     return RICK_OK;
 }
 

@@ -175,4 +175,15 @@ template <typename real>
 hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *corr,
                           const Stats *st, real *image, int kahan, hipStream_t s);
 
+// Prediction: conj(P_k) of the model image into every plane of the mesh, and
+// every tile bit and row bit set (the FFT then reads whole planes).
+template <typename real>
+hipError_t launch_predict_screen(const Geom &g, const real *model, const double *corr, real *mesh,
+                                 uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
+
+// Prediction: interpolate visibilities from planes holding conj(H_k).
+template <typename real>
+hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
+                         const real *lut, const real *mesh, real *out, hipStream_t s);
+
 }  // namespace rick

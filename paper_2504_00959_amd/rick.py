@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
     L.rick_fft_planes.argtypes = [P, P]
     L.rick_wstack_image.argtypes = [P, P, P]
     L.rick_reset.argtypes = [P, P]
+    L.rick_predict_planes.argtypes = [P, P, P]
+    L.rick_degrid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int64, ctypes.c_int32, P]
     L.rick_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     L.rick_plan_destroy.argtypes = [P]
     L.rick_plan_bin_counts.argtypes = [P, P, ctypes.c_int64]
@@ -89,7 +91,7 @@ def lib() -> ctypes.CDLL:
     for f in ("rick_plan", "rick_grid", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
-              "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget"):
+              "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid"):
         getattr(L, f).restype = ctypes.c_int32
     L.rick_status_str.argtypes = [ctypes.c_int32]
     L.rick_status_str.restype = ctypes.c_char_p
@@ -216,6 +218,39 @@ class Plan:
         if out.numel() != self.grid_n * self.grid_n:
             raise ValueError("out must be [N, N]")
         _check(lib().rick_wstack_image(self._h, out.data_ptr(), _stream_handle(stream)), "rick_wstack_image")
+        return out
+
+    def predict_planes(self, model, stream=None):
+        """Prediction, first half: the model image (device [N, N], the plan's
+        real dtype) to the planes' forward transforms (held conjugated)."""
+        self._device_tensor(model, "model", self.real_dtype)
+        if model.numel() != self.grid_n * self.grid_n:
+            raise ValueError("model must be [N, N]")
+        _check(lib().rick_predict_planes(self._h, model.data_ptr(), _stream_handle(stream)), "rick_predict_planes")
+
+    def degrid(self, uvw, freq: Optional[Sequence[float]] = None, out=None, stream=None):
+        """Prediction, second half: visibilities [nrow, nchan] (complex, the
+        plan's precision) at uvw (float64 [nrow, 3], metres if freq is given,
+        else wavelengths) from the predicted planes."""
+        import torch
+        self._device_tensor(uvw, "uvw", torch.float64)
+        if uvw.dim() != 2 or uvw.shape[1] != 3:
+            raise ValueError("uvw must be [nrow, 3]")
+        nrow = uvw.shape[0]
+        fptr = None
+        nchan = 1
+        if freq is not None:
+            f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).reshape(-1))
+            nchan = f.shape[0]
+            self._freq_keep = f
+            fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if out is None:
+            out = torch.empty((nrow, nchan), dtype=self.complex_dtype, device=f"cuda:{self.device}")
+        self._device_tensor(out, "out", self.complex_dtype)
+        if out.numel() != nrow * nchan:
+            raise ValueError("out must be [nrow, nchan]")
+        _check(lib().rick_degrid(self._h, uvw.data_ptr(), fptr, out.data_ptr(), nrow, nchan, _stream_handle(stream)),
+               "rick_degrid")
         return out
 
     def retarget(self, fov: float, w_min: float, w_max: float):
