@@ -137,14 +137,20 @@ KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_l
                 "k_clear_bits": "reset"}
 
 
+# Sources whose kernels the imaging step never launches (prediction): they do
+# not change what the imaging counters describe.
+NOT_IN_IMAGING_STEP = ("degrid.hip",)
+
+
 def kernel_sources_digest():
-    """sha256 over the library's kernel and plan sources: counters taken on
-    other sources do not describe the kernels that run now."""
+    """sha256 over the sources of the kernels the imaging step launches and of
+    the plan: counters taken on other sources do not describe the kernels that
+    run now."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_00959_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".h")):
+        if f.endswith((".hip", ".cpp", ".h")) and f not in NOT_IN_IMAGING_STEP:
             h.update(f.encode())
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
@@ -582,6 +588,81 @@ def batch_report(args):
         p.close()
 
 
+def predict_report(args):
+    """Prediction (degridding): the workload's visibility positions predicted
+    from a model image holding its point sources on pixels.  One step is
+    rick_predict_planes (screened model planes, centred FFT) plus rick_degrid
+    over every visibility, inputs resident on the device.  Reports Mvis/s,
+    per-kernel times and rates, and sampled visibilities against the oracle's
+    sparse-model prediction.  Prints one JSON line."""
+    import torch
+    import synth
+    from paper_2504_00959_amd import rick
+
+    dev = "cuda:0"
+    ds = make_workload(args.workload, dev) if args.workload != "ska_low_share" else \
+        synth.ska_low_share(device=dev, with_vis=False)
+    print(f"[predict] {describe(ds)}", file=sys.stderr, flush=True)
+    N = ds.grid_n
+    dl = ds.fov / N
+    pp = np.rint(np.asarray(ds.sources["l"]) / dl).astype(np.int64) + N // 2
+    qq = np.rint(np.asarray(ds.sources["m"]) / dl).astype(np.int64) + N // 2
+    fl = np.asarray(ds.sources["flux"], dtype=np.float64)
+    uvw = torch.as_tensor(ds.uvw, dtype=torch.float64).to(dev).contiguous()
+    nrow = uvw.shape[0]
+    nchan = 1 if ds.freq is None else len(ds.freq)
+    nvis = nrow * nchan
+    with rick.Plan.for_dataset(ds, precision=args.precision, fused=False, timing=True, max_vis=1) as p:
+        M = torch.zeros((N, N), dtype=p.real_dtype, device=dev)
+        M.index_put_((torch.as_tensor(qq, device=dev), torch.as_tensor(pp, device=dev)),
+                     torch.as_tensor(fl, dtype=p.real_dtype, device=dev), accumulate=True)
+        out = torch.empty((nrow, nchan), dtype=p.complex_dtype, device=dev)
+
+        def step():
+            p.predict_planes(M)
+            p.degrid(uvw, ds.freq, out)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        p.info()                      # restart the kernel timers
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        timers = p.info()["timers"]
+        rng = np.random.default_rng(62)
+        rows = np.sort(rng.choice(nrow, min(40, nrow), replace=False))
+        got = out[torch.as_tensor(rows, device=dev)].cpu().numpy().astype(np.complex128).reshape(-1)
+        uvw_s = uvw[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    import oracle.predict
+    t1 = time.time()
+    ref = oracle.predict.wstack_predict_sparse(pp, qq, fl, uvw_s, ds.freq, **ds.plan_kwargs())
+    chk = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    rb = 8 if args.precision == "fp64" else 4
+    mesh_b = 2 * rb * ds.n_wplanes * N * N
+    kern = {}
+    for name, (kms, calls) in timers.items():
+        e = {"ms": round(kms, 4), "calls": calls}
+        byt = {"predict_screen": mesh_b + rb * N * N,
+               "predict_fft": 4 * mesh_b,
+               "degrid": 24 * nrow + 2 * rb * nvis}.get(name)
+        if byt:
+            e["bytes"] = int(byt)
+            e["GBps"] = round(byt / (kms * 1e-3) / 1e9, 1)
+        if name == "degrid":
+            e["tap_bytes_gathered"] = int(2 * rb * ds.support ** 2 * nvis)
+        kern[name] = e
+    out_line = {"report": "predict", "workload": describe(ds), "n_vis": nvis, "steps": args.steps,
+                "ms_per_step": round(ms, 4), "mvis_per_s": round(nvis / (ms * 1e-3) / 1e6, 1),
+                "precision": args.precision, "model": f"{len(fl)} point sources on pixels",
+                "kernels": kern,
+                "check": {"rows": int(len(rows)), "visibilities": int(got.size), "rel_rms_vs_oracle": chk,
+                          "oracle_seconds": round(time.time() - t1, 1)}}
+    print(json.dumps(out_line), flush=True)
+
+
 def describe(ds):
     return (f"{ds.name}: {ds.nrow:,} rows x {ds.nchan} channels = {ds.nvis:,} visibilities, "
             f"{ds.grid_n}^2 x {ds.n_wplanes} w-planes, support {ds.support}, oversample {ds.oversample}, "
@@ -615,6 +696,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the batched form: many uneven jobs recorded into a graph and replayed (jobs/s, latency)")
     ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
+    ap.add_argument("--predict", action="store_true",
+                    help="prediction (degridding) of the workload's visibilities from a point-source model image")
     args = ap.parse_args()
     if args.profile:
         run_profiles(os.path.abspath(args.profile), args.workload)
@@ -627,6 +710,9 @@ def main():
         return
     if args.batch:
         batch_report(args)
+        return
+    if args.predict:
+        predict_report(args)
         return
     if args.copy_calibration:
         import torch
