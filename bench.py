@@ -618,24 +618,41 @@ def predict_report(args):
                      torch.as_tensor(fl, dtype=p.real_dtype, device=dev), accumulate=True)
         out = torch.empty((nrow, nchan), dtype=p.complex_dtype, device=dev)
 
-        def step():
+        def timed(step):
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            p.info()                      # restart the kernel timers
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / args.steps, p.info()["timers"]
+
+        def step_direct():
             p.predict_planes(M)
             p.degrid(uvw, ds.freq, out)
 
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        p.info()                      # restart the kernel timers
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        timers = p.info()["timers"]
+        ms_direct, timers_direct = timed(step_direct)
         rng = np.random.default_rng(62)
         rows = np.sort(rng.choice(nrow, min(40, nrow), replace=False))
         got = out[torch.as_tensor(rows, device=dev)].cpu().numpy().astype(np.complex128).reshape(-1)
         uvw_s = uvw[torch.as_tensor(rows, device=dev)].cpu().numpy()
+        # the same positions quantised and sorted once (repeated prediction)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        order = p.degrid_order(uvw, ds.freq)
+        order_ms = (time.perf_counter() - t0) * 1e3
+        out2 = torch.empty_like(out)
+
+        def step_sorted():
+            p.predict_planes(M)
+            p.degrid_sorted(order, out2)
+
+        ms, timers = timed(step_sorted)
+        sorted_vs_direct = float((out2 - out).abs().max() / out.abs().max())
+        got = out2[torch.as_tensor(rows, device=dev)].cpu().numpy().astype(np.complex128).reshape(-1)
+        order.close()
     import oracle.predict
     t1 = time.time()
     ref = oracle.predict.wstack_predict_sparse(pp, qq, fl, uvw_s, ds.freq, **ds.plan_kwargs())
@@ -643,19 +660,25 @@ def predict_report(args):
     rb = 8 if args.precision == "fp64" else 4
     mesh_b = 2 * rb * ds.n_wplanes * N * N
     kern = {}
-    for name, (kms, calls) in timers.items():
+    for name, (kms, calls) in list(timers.items()) + [("degrid_direct", timers_direct["degrid"])]:
         e = {"ms": round(kms, 4), "calls": calls}
         byt = {"predict_screen": mesh_b + rb * N * N,
                "predict_fft": 4 * mesh_b,
-               "degrid": 24 * nrow + 2 * rb * nvis}.get(name)
+               "degrid": 16 * nvis + 2 * rb * nvis,
+               "degrid_direct": 24 * nrow + 2 * rb * nvis}.get(name)
         if byt:
             e["bytes"] = int(byt)
             e["GBps"] = round(byt / (kms * 1e-3) / 1e9, 1)
-        if name == "degrid":
+        if name.startswith("degrid"):
             e["tap_bytes_gathered"] = int(2 * rb * ds.support ** 2 * nvis)
         kern[name] = e
     out_line = {"report": "predict", "workload": describe(ds), "n_vis": nvis, "steps": args.steps,
                 "ms_per_step": round(ms, 4), "mvis_per_s": round(nvis / (ms * 1e-3) / 1e6, 1),
+                "order": "sorted once (rick_degrid_order_create), interpolation in sorted order",
+                "order_create_ms": round(order_ms, 2),
+                "direct_ms_per_step": round(ms_direct, 4),
+                "direct_mvis_per_s": round(nvis / (ms_direct * 1e-3) / 1e6, 1),
+                "sorted_vs_direct_max_rel": sorted_vs_direct,
                 "precision": args.precision, "model": f"{len(fl)} point sources on pixels",
                 "kernels": kern,
                 "check": {"rows": int(len(rows)), "visibilities": int(got.size), "rel_rms_vs_oracle": chk,

@@ -235,6 +235,37 @@ rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz
                         int32_t nchan, void *stream);
 
 /*
+ * Prediction at fixed positions (the same observation predicted again and
+ * again, e.g. every cycle of a deconvolution): the positions are quantised
+ * and sorted once by the flat mesh offset of their footprint origin (plane,
+ * row, column), so that neighbouring threads of rick_degrid_sorted read
+ * neighbouring footprints.
+ *
+ * rick_degrid_order_create -- quantise (exactly as rick_grid and rick_degrid
+ * do, for the plan's current grid, field and w range) and sort.  uvw and
+ * freq_hz as for rick_degrid; nrow * nchan < 2^32.  Allocates device memory
+ * (16 B per visibility kept, 32 B per visibility plus the sort's scratch
+ * during the call) and synchronises `stream`.  *out receives the handle.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG, RICK_E_OOM, RICK_E_HIP.
+ */
+typedef struct rick_degrid_order_s rick_degrid_order_t;
+rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const double *freq_hz, int64_t nrow,
+                                     int32_t nchan, rick_degrid_order_t **out, void *stream);
+
+/*
+ * rick_degrid_sorted -- rick_degrid over the order's visibilities, walked in
+ * sorted order; vis_out [nrow][nchan] as for rick_degrid (each visibility
+ * written at its own index).  The plan must hold predicted planes and have
+ * the grid, field and w range the order was made with.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (bad order, other geometry,
+ * NULL or misaligned vis_out), RICK_E_STATE, RICK_E_HIP.
+ */
+rick_status rick_degrid_sorted(rick_plan_t *p, const rick_degrid_order_t *o, void *vis_out, void *stream);
+
+/* rick_degrid_order_destroy -- free the order.  Errors: RICK_E_INVALID_ARG. */
+rick_status rick_degrid_order_destroy(rick_degrid_order_t *o);
+
+/*
  * rick_reset -- begin a new image: zero the weight sum and the counters and
  * clear the tile bitmap, so the next rick_grid stores its tiles instead of
  * adding to them and every other tile reads as zero.

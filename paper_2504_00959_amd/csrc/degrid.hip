@@ -11,6 +11,8 @@
 // The forward DFT runs through the library's centred inverse FFT: the screen
 // kernel writes the complex conjugate of P_k, the inverse transform of
 // conj(P_k) is conj(H_k), and the interpolation conjugates what it reads.
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "rick_internal.h"
 #include "quant.h"
 
@@ -83,10 +85,33 @@ __global__ void k_fill_bits(Geom g, uint64_t *__restrict__ tile_bits, uint64_t *
     }
 }
 
+// The W x W taps of a footprint read from plane k (origin cell (x0, y0)),
+// conjugated, weighted by tap-table rows gx, gy; one complex result.
+template <typename real, int W>
+__device__ __forceinline__ void interp(const typename Cplx<real>::t *__restrict__ base, int32_t N,
+                                       const real *gx, const real *gy, real &vr, real &vi) {
+    using C = typename Cplx<real>::t;
+    real ar = 0, ai = 0;
+#pragma unroll
+    for (int ty = 0; ty < W; ++ty) {
+        const C *row = base + (int64_t)ty * N;
+        real rr = 0, ri = 0;
+#pragma unroll
+        for (int tx = 0; tx < W; ++tx) {
+            const C h = row[tx];
+            rr += gx[tx] * h.x;
+            ri += gx[tx] * h.y;
+        }
+        ar += gy[ty] * rr;
+        ai += gy[ty] * ri;
+    }
+    vr = ar;
+    vi = -ai;   // the plane holds conj(H_k)
+}
+
 // One thread per visibility (row r, channel c at index r * nchan + c): the
-// position, plane and drop decision of imaging, then the W x W taps read
-// from the plane (conjugated) and weighted by the tap-table rows of the
-// sub-cell offsets.  Dropped visibilities are predicted as 0.
+// position, plane and drop decision of imaging, then the footprint read from
+// the plane.  Dropped visibilities are predicted as 0.
 template <typename real, int W>
 __global__ __launch_bounds__(kDegridBlock) void k_degrid(Geom g, const double *__restrict__ uvw,
                                                          const double *__restrict__ scales, int64_t nrow,
@@ -115,28 +140,72 @@ __global__ __launch_bounds__(kDegridBlock) void k_degrid(Geom g, const double *_
         }
         Quant qq;
         const bool keep = quantise<real>(g, u, v, w, (real)0, (real)0, 1.0f, qq);
-        real vr = 0, vi = 0;
-        if (keep) {
-            const real *gx = s_lut + (qq.sx + (g.OS >> 1)) * W;
-            const real *gy = s_lut + (qq.sy + (g.OS >> 1)) * W;
-            const C *base = planes + (int64_t)qq.k * npix + (int64_t)(qq.cy - g.h) * g.N + (qq.cx - g.h);
-#pragma unroll
-            for (int ty = 0; ty < W; ++ty) {
-                const C *row = base + (int64_t)ty * g.N;
-                real rr = 0, ri = 0;
-#pragma unroll
-                for (int tx = 0; tx < W; ++tx) {
-                    const C h = row[tx];
-                    rr += gx[tx] * h.x;
-                    ri += gx[tx] * h.y;
-                }
-                vr += gy[ty] * rr;
-                vi += gy[ty] * ri;
-            }
-        }
         C o;
-        o.x = vr;
-        o.y = -vi;   // the plane holds conj(H_k)
+        o.x = 0;
+        o.y = 0;
+        if (keep)
+            interp<real, W>(planes + (int64_t)qq.k * npix + (int64_t)(qq.cy - g.h) * g.N + (qq.cx - g.h), g.N,
+                            s_lut + (qq.sx + (g.OS >> 1)) * W, s_lut + (qq.sy + (g.OS >> 1)) * W, o.x, o.y);
+        vout[i] = o;
+    }
+}
+
+// Sort order for repeated prediction at fixed positions: per visibility a
+// key (plane, footprint-origin row, footprint-origin column), all ones for a
+// dropped one (sorted last), and a value (index | sub-cell x << 32 | sub-cell
+// y << 40, sub-cells as s + OS/2).
+template <typename real>
+__global__ __launch_bounds__(kDegridBlock) void k_order_keys(Geom g, const double *__restrict__ uvw,
+                                                             const double *__restrict__ scales, int64_t nrow,
+                                                             int32_t nchan, uint64_t *__restrict__ keys,
+                                                             uint64_t *__restrict__ vals) {
+    const int64_t nvis = nrow * nchan;
+    const int64_t stride = (int64_t)gridDim.x * kDegridBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kDegridBlock + threadIdx.x; i < nvis; i += stride) {
+        const int64_t r = i / nchan;
+        const int32_t c = (int32_t)(i - r * nchan);
+        double u, v, w;
+        {
+#pragma clang fp contract(off)
+            const double sc = scales[c];
+            u = uvw[3 * r] * sc;
+            v = uvw[3 * r + 1] * sc;
+            w = uvw[3 * r + 2] * sc;
+        }
+        Quant qq;
+        const bool keep = quantise<real>(g, u, v, w, (real)0, (real)0, 1.0f, qq);
+        keys[i] = keep ? ((uint64_t)qq.k * g.N + (uint64_t)(qq.cy - g.h)) * g.N + (uint64_t)(qq.cx - g.h) : ~0ull;
+        vals[i] = (uint64_t)i | (uint64_t)(qq.sx + (g.OS >> 1)) << 32 | (uint64_t)(qq.sy + (g.OS >> 1)) << 40;
+    }
+}
+
+// Interpolation in sorted order: neighbouring threads read neighbouring
+// footprints, so a wave's loads share cache lines; results are written to
+// each visibility's own index.
+template <typename real, int W>
+__global__ __launch_bounds__(kDegridBlock) void k_degrid_sorted(Geom g, const uint64_t *__restrict__ keys,
+                                                                const uint64_t *__restrict__ vals, int64_t nvis,
+                                                                const real *__restrict__ lut,
+                                                                const real *__restrict__ mesh,
+                                                                real *__restrict__ out) {
+    using C = typename Cplx<real>::t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    real *s_lut = reinterpret_cast<real *>(smem);
+    for (int i = threadIdx.x; i < g.OS * W; i += kDegridBlock) s_lut[i] = lut[i];
+    __syncthreads();
+    const C *planes = reinterpret_cast<const C *>(mesh);
+    C *vout = reinterpret_cast<C *>(out);
+    const int64_t stride = (int64_t)gridDim.x * kDegridBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kDegridBlock + threadIdx.x; j < nvis; j += stride) {
+        const uint64_t key = keys[j], val = vals[j];
+        const int64_t i = (int64_t)(val & 0xffffffffull);
+        C o;
+        o.x = 0;
+        o.y = 0;
+        if (key != ~0ull) {
+            const int32_t sx = (int32_t)((val >> 32) & 0xffu), sy = (int32_t)((val >> 40) & 0xffu);
+            interp<real, W>(planes + (int64_t)key, g.N, s_lut + sx * W, s_lut + sy * W, o.x, o.y);
+        }
         vout[i] = o;
     }
 }
@@ -151,6 +220,18 @@ hipError_t degrid_w(const Geom &g, const double *uvw, const double *scales, int6
     const size_t lds = (size_t)g.OS * W * sizeof(real);
     hipLaunchKernelGGL((k_degrid<real, W>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, uvw, scales,
                        nrow, nchan, lut, mesh, out);
+    return hipGetLastError();
+}
+
+template <typename real, int W>
+hipError_t degrid_sorted_w(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis, const real *lut,
+                           const real *mesh, real *out, hipStream_t s) {
+    if (nvis == 0) return hipSuccess;
+    int64_t blocks = (nvis + kDegridBlock - 1) / kDegridBlock;
+    if (blocks > 65536) blocks = 65536;
+    const size_t lds = (size_t)g.OS * W * sizeof(real);
+    hipLaunchKernelGGL((k_degrid_sorted<real, W>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, keys, vals,
+                       nvis, lut, mesh, out);
     return hipGetLastError();
 }
 
@@ -189,6 +270,51 @@ hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales,
     }
 }
 
+template <typename real>
+hipError_t launch_order_keys(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
+                             uint64_t *keys, uint64_t *vals, hipStream_t s) {
+    const int64_t nvis = nrow * nchan;
+    if (nvis == 0) return hipSuccess;
+    int64_t blocks = (nvis + kDegridBlock - 1) / kDegridBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_order_keys<real>), dim3((unsigned)blocks), dim3(kDegridBlock), 0, s, g, uvw, scales, nrow,
+                       nchan, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t sort_order(void *temp, size_t &temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                      const uint64_t *vals_in, uint64_t *vals_out, int64_t n, int end_bit, hipStream_t s) {
+    return rocprim::radix_sort_pairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0,
+                                     (unsigned)end_bit, s);
+}
+
+template <typename real>
+hipError_t launch_degrid_sorted(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis,
+                                const real *lut, const real *mesh, real *out, hipStream_t s) {
+    switch (g.W) {
+#define RICK_DEGRID_SW(w) \
+    case w: return degrid_sorted_w<real, w>(g, keys, vals, nvis, lut, mesh, out, s);
+        RICK_DEGRID_SW(1)
+        RICK_DEGRID_SW(3)
+        RICK_DEGRID_SW(5)
+        RICK_DEGRID_SW(7)
+        RICK_DEGRID_SW(9)
+        RICK_DEGRID_SW(11)
+        RICK_DEGRID_SW(13)
+        RICK_DEGRID_SW(15)
+#undef RICK_DEGRID_SW
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_order_keys<float>(const Geom &, const double *, const double *, int64_t, int32_t,
+                                             uint64_t *, uint64_t *, hipStream_t);
+template hipError_t launch_order_keys<double>(const Geom &, const double *, const double *, int64_t, int32_t,
+                                              uint64_t *, uint64_t *, hipStream_t);
+template hipError_t launch_degrid_sorted<float>(const Geom &, const uint64_t *, const uint64_t *, int64_t,
+                                                const float *, const float *, float *, hipStream_t);
+template hipError_t launch_degrid_sorted<double>(const Geom &, const uint64_t *, const uint64_t *, int64_t,
+                                                 const double *, const double *, double *, hipStream_t);
 template hipError_t launch_predict_screen<float>(const Geom &, const float *, const double *, float *, uint64_t *,
                                                  uint64_t *, hipStream_t);
 template hipError_t launch_predict_screen<double>(const Geom &, const double *, const double *, double *,

@@ -729,6 +729,132 @@ rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz
     return RICK_OK;
 }
 
+}  // extern "C"
+
+struct rick_degrid_order_s {
+    uint32_t magic;
+    int device;
+    int64_t nrow, nvis;
+    int32_t nchan;
+    uint64_t *keys, *vals;
+    Geom g;   // geometry the positions were quantised with
+};
+
+namespace {
+constexpr uint32_t kOrderMagic = 0x4f524452u, kOrderDead = 0x44454144u;
+bool same_geometry(const Geom &a, const Geom &b) {
+    return a.N == b.N && a.Nw == b.Nw && a.W == b.W && a.OS == b.OS && a.fov == b.fov && a.half == b.half &&
+           a.w_min == b.w_min && a.dw == b.dw;
+}
+}  // namespace
+
+extern "C" {
+
+rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const double *freq_hz, int64_t nrow,
+                                     int32_t nchan, rick_degrid_order_t **out, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
+    if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
+    if (!freq_hz && nchan != 1) return fail(RICK_E_INVALID_ARG, "nchan=%d without freq_hz", nchan);
+    if (nchan > kMaxChan) return fail(RICK_E_INVALID_ARG, "nchan=%d > %d", nchan, kMaxChan);
+    if (nrow > ((int64_t(1) << 32) - 1) / nchan) return fail(RICK_E_INVALID_ARG, "nrow*nchan >= 2^32");
+    if (nrow > 0 && !uvw) return fail(RICK_E_INVALID_ARG, "uvw is NULL");
+    if ((uintptr_t)uvw & 7) return fail(RICK_E_INVALID_ARG, "misaligned uvw");
+    std::vector<double> sc(nchan, 1.0);
+    if (freq_hz) {
+        for (int c = 0; c < nchan; ++c) {
+            if (!std::isfinite(freq_hz[c]) || !(freq_hz[c] > 0.0))
+                return fail(RICK_E_INVALID_ARG, "freq_hz[%d]=%g", c, freq_hz[c]);
+            sc[c] = freq_hz[c] / kC0;
+        }
+    }
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const Geom &g = p->g;
+    const int64_t nvis = nrow * nchan;
+    const size_t n = size_t(nvis > 0 ? nvis : 1);
+    uint64_t *kin = nullptr, *vin = nullptr, *kout = nullptr, *vout = nullptr;
+    void *temp = nullptr;
+    auto release = [&]() {
+        if (kin) (void)hipFree(kin);
+        if (vin) (void)hipFree(vin);
+        if (temp) (void)hipFree(temp);
+    };
+    hipError_t e = hipMalloc(&kin, n * 8);
+    if (e == hipSuccess) e = hipMalloc(&vin, n * 8);
+    if (e == hipSuccess) e = hipMalloc(&kout, n * 8);
+    if (e == hipSuccess) e = hipMalloc(&vout, n * 8);
+    if (e != hipSuccess) {
+        release();
+        if (kout) (void)hipFree(kout);
+        if (vout) (void)hipFree(vout);
+        return fail(RICK_E_OOM, "sort order buffers for %lld visibilities", (long long)nvis);
+    }
+    // keys are flat mesh offsets of the footprint origin: below N_w N^2
+    int end_bit = 1;
+    while ((uint64_t(1) << end_bit) < uint64_t(g.Nw) * uint64_t(g.N) * uint64_t(g.N)) ++end_bit;
+    size_t temp_bytes = 0;
+    e = launch_set_scales(p->scales, sc.data(), nchan, s);
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_order_keys<double>(g, uvw, p->scales, nrow, nchan, kin, vin, s)
+                    : launch_order_keys<float>(g, uvw, p->scales, nrow, nchan, kin, vin, s);
+    if (e == hipSuccess && nvis > 0) e = sort_order(nullptr, temp_bytes, kin, kout, vin, vout, nvis, end_bit, s);
+    if (e == hipSuccess && nvis > 0) e = hipMalloc(&temp, temp_bytes > 0 ? temp_bytes : 1);
+    if (e == hipSuccess && nvis > 0) e = sort_order(temp, temp_bytes, kin, kout, vin, vout, nvis, end_bit, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) {
+        (void)hipFree(kout);
+        (void)hipFree(vout);
+        return hip_fail(e, "degrid order");
+    }
+    rick_degrid_order_t *o = new rick_degrid_order_t;
+    o->magic = kOrderMagic;
+    o->device = p->d.device;
+    o->nrow = nrow;
+    o->nchan = nchan;
+    o->nvis = nvis;
+    o->keys = kout;
+    o->vals = vout;
+    o->g = g;
+    *out = o;
+    return RICK_OK;
+}
+
+rick_status rick_degrid_order_destroy(rick_degrid_order_t *o) {
+    if (!o || o->magic != kOrderMagic) return fail(RICK_E_INVALID_ARG, "invalid degrid order");
+    DeviceGuard guard(o->device);
+    (void)hipFree(o->keys);
+    (void)hipFree(o->vals);
+    o->magic = kOrderDead;
+    delete o;
+    return RICK_OK;
+}
+
+rick_status rick_degrid_sorted(rick_plan_t *p, const rick_degrid_order_t *o, void *vis_out, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!o || o->magic != kOrderMagic) return fail(RICK_E_INVALID_ARG, "invalid degrid order");
+    if (o->device != p->d.device) return fail(RICK_E_INVALID_ARG, "order and plan on different devices");
+    if (!same_geometry(o->g, p->g))
+        return fail(RICK_E_INVALID_ARG, "order was made for another grid, field or w range");
+    if (o->nvis > 0 && !vis_out) return fail(RICK_E_INVALID_ARG, "vis_out is NULL");
+    if ((uintptr_t)vis_out & (p->fp64 ? 15 : 7)) return fail(RICK_E_INVALID_ARG, "misaligned vis_out");
+    if (p->state != 3) return fail(RICK_E_STATE, "no predicted planes; call rick_predict_planes first");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    timer_begin(p, T_DEGRID, "degrid", s);
+    hipError_t e =
+        p->fp64 ? launch_degrid_sorted<double>(p->g, o->keys, o->vals, o->nvis, (const double *)p->lut,
+                                               (const double *)p->mesh, (double *)vis_out, s)
+                : launch_degrid_sorted<float>(p->g, o->keys, o->vals, o->nvis, (const float *)p->lut,
+                                              (const float *)p->mesh, (float *)vis_out, s);
+    timer_end(p, T_DEGRID, s);
+    if (e != hipSuccess) return hip_fail(e, "degrid_sorted");
+    return RICK_OK;
+}
+
 rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
     if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");

@@ -181,6 +181,18 @@ template <typename real>
 hipError_t launch_predict_screen(const Geom &g, const real *model, const double *corr, real *mesh,
                                  uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
 
+// Prediction at fixed positions: sort keys and values of every visibility,
+// their radix sort (temp == nullptr queries temp_bytes), and interpolation in
+// sorted order.
+template <typename real>
+hipError_t launch_order_keys(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
+                             uint64_t *keys, uint64_t *vals, hipStream_t s);
+hipError_t sort_order(void *temp, size_t &temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                      const uint64_t *vals_in, uint64_t *vals_out, int64_t n, int end_bit, hipStream_t s);
+template <typename real>
+hipError_t launch_degrid_sorted(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis,
+                                const real *lut, const real *mesh, real *out, hipStream_t s);
+
 // Prediction: interpolate visibilities from planes holding conj(H_k).
 template <typename real>
 hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,

@@ -33,6 +33,31 @@ class RickError(RuntimeError):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
 
 
+class DegridOrder:
+    """Sorted positions of one set of visibilities (rick_degrid_order_t)."""
+
+    def __init__(self, handle, nrow: int, nchan: int):
+        self._h = handle
+        self.nrow, self.nchan = nrow, nchan
+
+    def close(self):
+        if self._h:
+            _check(lib().rick_degrid_order_destroy(self._h), "rick_degrid_order_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("grid_n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -73,6 +98,10 @@ def lib() -> ctypes.CDLL:
     L.rick_reset.argtypes = [P, P]
     L.rick_predict_planes.argtypes = [P, P, P]
     L.rick_degrid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int64, ctypes.c_int32, P]
+    L.rick_degrid_order_create.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.POINTER(P), P]
+    L.rick_degrid_sorted.argtypes = [P, P, P, P]
+    L.rick_degrid_order_destroy.argtypes = [P]
     L.rick_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     L.rick_plan_destroy.argtypes = [P]
     L.rick_plan_bin_counts.argtypes = [P, P, ctypes.c_int64]
@@ -91,7 +120,8 @@ def lib() -> ctypes.CDLL:
     for f in ("rick_plan", "rick_grid", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
-              "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid"):
+              "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid",
+              "rick_degrid_order_create", "rick_degrid_sorted", "rick_degrid_order_destroy"):
         getattr(L, f).restype = ctypes.c_int32
     L.rick_status_str.argtypes = [ctypes.c_int32]
     L.rick_status_str.restype = ctypes.c_char_p
@@ -251,6 +281,36 @@ class Plan:
             raise ValueError("out must be [nrow, nchan]")
         _check(lib().rick_degrid(self._h, uvw.data_ptr(), fptr, out.data_ptr(), nrow, nchan, _stream_handle(stream)),
                "rick_degrid")
+        return out
+
+    def degrid_order(self, uvw, freq: Optional[Sequence[float]] = None, stream=None) -> "DegridOrder":
+        """Quantise and sort the positions once for repeated prediction
+        (valid for this plan's current grid, field and w range)."""
+        import torch
+        self._device_tensor(uvw, "uvw", torch.float64)
+        if uvw.dim() != 2 or uvw.shape[1] != 3:
+            raise ValueError("uvw must be [nrow, 3]")
+        nrow = uvw.shape[0]
+        fptr, nchan, f = None, 1, None
+        if freq is not None:
+            f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).reshape(-1))
+            nchan = f.shape[0]
+            fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        _check(lib().rick_degrid_order_create(self._h, uvw.data_ptr(), fptr, nrow, nchan, ctypes.byref(h),
+                                              _stream_handle(stream)), "rick_degrid_order_create")
+        return DegridOrder(h, nrow, nchan)
+
+    def degrid_sorted(self, order: "DegridOrder", out=None, stream=None):
+        """rick_degrid over a sort order's visibilities; returns [nrow, nchan]."""
+        import torch
+        if out is None:
+            out = torch.empty((order.nrow, order.nchan), dtype=self.complex_dtype, device=f"cuda:{self.device}")
+        self._device_tensor(out, "out", self.complex_dtype)
+        if out.numel() != order.nrow * order.nchan:
+            raise ValueError("out must be [nrow, nchan]")
+        _check(lib().rick_degrid_sorted(self._h, order._h, out.data_ptr(), _stream_handle(stream)),
+               "rick_degrid_sorted")
         return out
 
     def retarget(self, fov: float, w_min: float, w_max: float):

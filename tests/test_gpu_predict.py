@@ -177,6 +177,57 @@ def test_call_order_with_imaging():
     assert np.array_equal(first, second)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sorted_order_equals_direct_order(precision):
+    """Prediction through a sort order (quantised and sorted once) gives each
+    visibility the same value as the direct walk, at its own index; dropped
+    visibilities are 0; channels in metres."""
+    import torch
+    ds = synth.ska_low_small()
+    uvw_h = ds.uvw.copy()
+    uvw_h[:5, 0] = 1e9
+    M = _model(ds.grid_n, 63, n_src=40)
+    with rick.Plan.for_dataset(ds, precision=precision) as p:
+        uvw = torch.as_tensor(uvw_h).to("cuda:0")
+        p.predict_planes(torch.as_tensor(M, dtype=p.real_dtype).to("cuda:0"))
+        direct = p.degrid(uvw, ds.freq).cpu().numpy()
+        with p.degrid_order(uvw, ds.freq) as order:
+            out = torch.full((ds.nrow, len(ds.freq)), 7.0, dtype=p.complex_dtype, device="cuda:0")
+            srt = p.degrid_sorted(order, out).cpu().numpy()
+            again = p.degrid_sorted(order).cpu().numpy()
+        torch.cuda.synchronize()
+    assert np.all(srt[:5] == 0)
+    assert np.max(np.abs(srt - direct)) <= 1e-6 * np.max(np.abs(direct))
+    assert np.array_equal(srt, again)
+    ref = op.wstack_predict(M, uvw_h, ds.freq, **ds.plan_kwargs(), keep_planes=False)
+    kept = ref.binned.keep
+    assert rel_rms(srt.reshape(-1)[kept], ref.vis[kept]) <= _tol(precision, M, ds)
+
+
+def test_sorted_order_checks_geometry_and_empty():
+    import torch
+    ds = synth.tiny(nrow=4000, seed=64)
+    uvw = torch.as_tensor(ds.uvw).to("cuda:0")
+    M = torch.as_tensor(_model(ds.grid_n, 65), dtype=torch.float32).to("cuda:0")
+    with rick.Plan.for_dataset(ds) as p:
+        order = p.degrid_order(uvw)
+        with pytest.raises(rick.RickError):
+            p.degrid_sorted(order)                 # nothing predicted yet
+        p.retarget(ds.fov * 1.1, ds.w_min, ds.w_max)
+        p.predict_planes(M)
+        with pytest.raises(rick.RickError):
+            p.degrid_sorted(order)                 # order made for another field
+        p.retarget(ds.fov, ds.w_min, ds.w_max)
+        p.predict_planes(M)
+        a = p.degrid_sorted(order)
+        b = p.degrid(uvw)
+        with p.degrid_order(torch.zeros((0, 3), dtype=torch.float64, device="cuda:0")) as empty:
+            assert p.degrid_sorted(empty).numel() == 0
+        torch.cuda.synchronize()
+        order.close()
+    assert torch.equal(a, b) or float((a - b).abs().max()) <= 1e-6 * float(b.abs().max())
+
+
 @pytest.fixture(scope="module")
 def share_predict():
     import torch
@@ -194,7 +245,11 @@ def share_predict():
     with rick.Plan.for_dataset(ds, fused=True) as p:
         p.predict_planes(M)
         vis = p.degrid(uvw, ds.freq)
+        with p.degrid_order(uvw, ds.freq) as order:
+            vis_sorted = p.degrid_sorted(order)
         torch.cuda.synchronize()
+        sorted_diff = float((vis_sorted - vis).abs().max() / vis.abs().max())
+        del vis_sorted
         rng = np.random.default_rng(62)
         rows = np.sort(rng.choice(ds.nrow, 40, replace=False))
         got = vis[torch.as_tensor(rows).cuda()].cpu().numpy().astype(np.complex128).reshape(-1)
@@ -204,7 +259,7 @@ def share_predict():
     ref = op.wstack_predict_sparse(pp, qq, fl, uvw_h, ds.freq, **ds.plan_kwargs())
     Mh = np.zeros((N, N))
     np.add.at(Mh, (qq, pp), fl)
-    return dict(got=got, ref=ref, finite=finite, tol=_tol("fp32", Mh, ds))
+    return dict(got=got, ref=ref, finite=finite, tol=_tol("fp32", Mh, ds), sorted_diff=sorted_diff)
 
 
 def test_fullsize_sampled_visibilities(share_predict):
@@ -213,3 +268,4 @@ def test_fullsize_sampled_visibilities(share_predict):
     got, ref = share_predict["got"], share_predict["ref"]
     assert share_predict["finite"]
     assert rel_rms(got, ref) <= share_predict["tol"]
+    assert share_predict["sorted_diff"] <= 1e-6
