@@ -612,7 +612,8 @@ def predict_report(args):
     nrow = uvw.shape[0]
     nchan = 1 if ds.freq is None else len(ds.freq)
     nvis = nrow * nchan
-    with rick.Plan.for_dataset(ds, precision=args.precision, fused=False, timing=True, max_vis=1) as p:
+    with rick.Plan.for_dataset(ds, precision=args.precision, fused=not args.unfused, timing=True,
+                               max_vis=1) as p:
         M = torch.zeros((N, N), dtype=p.real_dtype, device=dev)
         M.index_put_((torch.as_tensor(qq, device=dev), torch.as_tensor(pp, device=dev)),
                      torch.as_tensor(fl, dtype=p.real_dtype, device=dev), accumulate=True)

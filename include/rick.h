@@ -205,8 +205,10 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream);
  *   P_k[q][p] = M[q][p] exp(-2 pi i w_k (n_pq - 1)) / (n_pq C(l'_p) C(l'_q))
  *   H_k[j][i] = sum_{q,p} P_k[q][p] exp(-2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
  * (zero outside the unit circle; phase and n - 1 in float64 as in
- * rick_wstack_image).  The mesh holds conj(H_k) afterwards (the forward DFT
- * runs as the inverse DFT of the conjugate) and every tile is marked set.
+ * rick_wstack_image).  The forward DFT runs as the inverse DFT of the
+ * conjugate, so conj(H_k) is what is held afterwards: in the mesh, or with
+ * RICK_FLAG_FUSED_SCREEN in row_mesh in column-panel order (the mesh then
+ * holds conj(P_k)); every tile is marked set.
  *   model  device float32 [N][N] (float64 in FP64 mode), indexed [q = m][p = l],
  *          the sky brightness per pixel; read only, owned by the caller
  * Overwrites what was gridded; call rick_reset before gridding again.
@@ -237,9 +239,10 @@ rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz
 /*
  * Prediction at fixed positions (the same observation predicted again and
  * again, e.g. every cycle of a deconvolution): the positions are quantised
- * and sorted once by the flat mesh offset of their footprint origin (plane,
- * row, column), so that neighbouring threads of rick_degrid_sorted read
- * neighbouring footprints.
+ * and sorted once by the offset of their footprint origin in the layout the
+ * plan holds predicted planes in (plane, then row and column: row order, or
+ * column panels with RICK_FLAG_FUSED_SCREEN), so that neighbouring threads
+ * of rick_degrid_sorted read neighbouring footprints.
  *
  * rick_degrid_order_create -- quantise (exactly as rick_grid and rick_degrid
  * do, for the plan's current grid, field and w range) and sort.  uvw and
@@ -256,7 +259,7 @@ rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const do
  * rick_degrid_sorted -- rick_degrid over the order's visibilities, walked in
  * sorted order; vis_out [nrow][nchan] as for rick_degrid (each visibility
  * written at its own index).  The plan must hold predicted planes and have
- * the grid, field and w range the order was made with.
+ * the grid, field, w range and plane layout the order was made with.
  * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG (bad order, other geometry,
  * NULL or misaligned vis_out), RICK_E_STATE, RICK_E_HIP.
  */

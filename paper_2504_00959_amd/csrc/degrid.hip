@@ -85,20 +85,32 @@ __global__ void k_fill_bits(Geom g, uint64_t *__restrict__ tile_bits, uint64_t *
     }
 }
 
-// The W x W taps of a footprint read from plane k (origin cell (x0, y0)),
-// conjugated, weighted by tap-table rows gx, gy; one complex result.
-template <typename real, int W>
-__device__ __forceinline__ void interp(const typename Cplx<real>::t *__restrict__ base, int32_t N,
-                                       const real *gx, const real *gy, real &vr, real &vi) {
+// Element (row j, column i) of a plane: row order (j N + i), or column-panel
+// order ((i / PW) N PW + j PW + i % PW, PW = 2^log2pw) when PANEL.
+template <bool PANEL>
+struct PlaneLayout {
+    int32_t N, log2pw;
+    __device__ __forceinline__ int64_t at(int32_t j, int32_t i) const {
+        if (PANEL)
+            return (((int64_t)(i >> log2pw) * N + j) << log2pw) + (i & ((1 << log2pw) - 1));
+        return (int64_t)j * N + i;
+    }
+};
+
+// The W x W taps of a footprint with origin cell (x0, y0) read from one
+// plane, conjugated, weighted by tap-table rows gx, gy; one complex result.
+template <typename real, int W, bool PANEL>
+__device__ __forceinline__ void interp(const typename Cplx<real>::t *__restrict__ plane, PlaneLayout<PANEL> L,
+                                       int32_t x0, int32_t y0, const real *gx, const real *gy, real &vr,
+                                       real &vi) {
     using C = typename Cplx<real>::t;
     real ar = 0, ai = 0;
 #pragma unroll
     for (int ty = 0; ty < W; ++ty) {
-        const C *row = base + (int64_t)ty * N;
         real rr = 0, ri = 0;
 #pragma unroll
         for (int tx = 0; tx < W; ++tx) {
-            const C h = row[tx];
+            const C h = plane[L.at(y0 + ty, x0 + tx)];
             rr += gx[tx] * h.x;
             ri += gx[tx] * h.y;
         }
@@ -112,11 +124,12 @@ __device__ __forceinline__ void interp(const typename Cplx<real>::t *__restrict_
 // One thread per visibility (row r, channel c at index r * nchan + c): the
 // position, plane and drop decision of imaging, then the footprint read from
 // the plane.  Dropped visibilities are predicted as 0.
-template <typename real, int W>
+template <typename real, int W, bool PANEL>
 __global__ __launch_bounds__(kDegridBlock) void k_degrid(Geom g, const double *__restrict__ uvw,
                                                          const double *__restrict__ scales, int64_t nrow,
                                                          int32_t nchan, const real *__restrict__ lut,
-                                                         const real *__restrict__ mesh, real *__restrict__ out) {
+                                                         const real *__restrict__ mesh, int32_t log2pw,
+                                                         real *__restrict__ out) {
     using C = typename Cplx<real>::t;
     extern __shared__ __align__(16) unsigned char smem[];
     real *s_lut = reinterpret_cast<real *>(smem);
@@ -124,6 +137,7 @@ __global__ __launch_bounds__(kDegridBlock) void k_degrid(Geom g, const double *_
     __syncthreads();
     const int64_t nvis = nrow * nchan;
     const int64_t npix = (int64_t)g.N * g.N;
+    const PlaneLayout<PANEL> L{g.N, log2pw};
     const C *planes = reinterpret_cast<const C *>(mesh);
     C *vout = reinterpret_cast<C *>(out);
     const int64_t stride = (int64_t)gridDim.x * kDegridBlock;
@@ -144,20 +158,22 @@ __global__ __launch_bounds__(kDegridBlock) void k_degrid(Geom g, const double *_
         o.x = 0;
         o.y = 0;
         if (keep)
-            interp<real, W>(planes + (int64_t)qq.k * npix + (int64_t)(qq.cy - g.h) * g.N + (qq.cx - g.h), g.N,
-                            s_lut + (qq.sx + (g.OS >> 1)) * W, s_lut + (qq.sy + (g.OS >> 1)) * W, o.x, o.y);
+            interp<real, W, PANEL>(planes + (int64_t)qq.k * npix, L, qq.cx - g.h, qq.cy - g.h,
+                                   s_lut + (qq.sx + (g.OS >> 1)) * W, s_lut + (qq.sy + (g.OS >> 1)) * W, o.x, o.y);
         vout[i] = o;
     }
 }
 
 // Sort order for repeated prediction at fixed positions: per visibility a
-// key (plane, footprint-origin row, footprint-origin column), all ones for a
-// dropped one (sorted last), and a value (index | sub-cell x << 32 | sub-cell
-// y << 40, sub-cells as s + OS/2).
+// key, the offset of its footprint origin in the planes' layout (k N^2 plus
+// the row-order or column-panel offset of (x0, y0)), all ones for a dropped
+// one (sorted last), and a value (index | sub-cell x << 32 | sub-cell y << 40,
+// sub-cells as s + OS/2).
 template <typename real>
 __global__ __launch_bounds__(kDegridBlock) void k_order_keys(Geom g, const double *__restrict__ uvw,
                                                              const double *__restrict__ scales, int64_t nrow,
-                                                             int32_t nchan, uint64_t *__restrict__ keys,
+                                                             int32_t nchan, int32_t log2pw,
+                                                             uint64_t *__restrict__ keys,
                                                              uint64_t *__restrict__ vals) {
     const int64_t nvis = nrow * nchan;
     const int64_t stride = (int64_t)gridDim.x * kDegridBlock;
@@ -174,25 +190,31 @@ __global__ __launch_bounds__(kDegridBlock) void k_order_keys(Geom g, const doubl
         }
         Quant qq;
         const bool keep = quantise<real>(g, u, v, w, (real)0, (real)0, 1.0f, qq);
-        keys[i] = keep ? ((uint64_t)qq.k * g.N + (uint64_t)(qq.cy - g.h)) * g.N + (uint64_t)(qq.cx - g.h) : ~0ull;
+        const int32_t x0 = qq.cx - g.h, y0 = qq.cy - g.h;
+        const int64_t off = log2pw > 0 ? PlaneLayout<true>{g.N, log2pw}.at(y0, x0)
+                                       : PlaneLayout<false>{g.N, 0}.at(y0, x0);
+        keys[i] = keep ? (uint64_t)qq.k * (uint64_t)g.N * (uint64_t)g.N + (uint64_t)off : ~0ull;
         vals[i] = (uint64_t)i | (uint64_t)(qq.sx + (g.OS >> 1)) << 32 | (uint64_t)(qq.sy + (g.OS >> 1)) << 40;
     }
 }
 
 // Interpolation in sorted order: neighbouring threads read neighbouring
 // footprints, so a wave's loads share cache lines; results are written to
-// each visibility's own index.
-template <typename real, int W>
+// each visibility's own index.  The key is the footprint origin's offset in
+// the planes' layout (N and PW powers of two).
+template <typename real, int W, bool PANEL>
 __global__ __launch_bounds__(kDegridBlock) void k_degrid_sorted(Geom g, const uint64_t *__restrict__ keys,
                                                                 const uint64_t *__restrict__ vals, int64_t nvis,
                                                                 const real *__restrict__ lut,
-                                                                const real *__restrict__ mesh,
+                                                                const real *__restrict__ mesh, int32_t log2pw,
                                                                 real *__restrict__ out) {
     using C = typename Cplx<real>::t;
     extern __shared__ __align__(16) unsigned char smem[];
     real *s_lut = reinterpret_cast<real *>(smem);
     for (int i = threadIdx.x; i < g.OS * W; i += kDegridBlock) s_lut[i] = lut[i];
     __syncthreads();
+    const int log2n = __builtin_ctz((unsigned)g.N);
+    const PlaneLayout<PANEL> L{g.N, log2pw};
     const C *planes = reinterpret_cast<const C *>(mesh);
     C *vout = reinterpret_cast<C *>(out);
     const int64_t stride = (int64_t)gridDim.x * kDegridBlock;
@@ -204,7 +226,18 @@ __global__ __launch_bounds__(kDegridBlock) void k_degrid_sorted(Geom g, const ui
         o.y = 0;
         if (key != ~0ull) {
             const int32_t sx = (int32_t)((val >> 32) & 0xffu), sy = (int32_t)((val >> 40) & 0xffu);
-            interp<real, W>(planes + (int64_t)key, g.N, s_lut + sx * W, s_lut + sy * W, o.x, o.y);
+            const int64_t k = (int64_t)(key >> (2 * log2n));
+            const uint64_t off = key & (((uint64_t)1 << (2 * log2n)) - 1);
+            int32_t x0, y0;
+            if (PANEL) {
+                y0 = (int32_t)((off >> log2pw) & (uint64_t)(g.N - 1));
+                x0 = (int32_t)(((off >> (log2n + log2pw)) << log2pw) | (off & (((uint64_t)1 << log2pw) - 1)));
+            } else {
+                y0 = (int32_t)(off >> log2n);
+                x0 = (int32_t)(off & (uint64_t)(g.N - 1));
+            }
+            interp<real, W, PANEL>(planes + (k << (2 * log2n)), L, x0, y0, s_lut + sx * W, s_lut + sy * W, o.x,
+                                   o.y);
         }
         vout[i] = o;
     }
@@ -212,26 +245,36 @@ __global__ __launch_bounds__(kDegridBlock) void k_degrid_sorted(Geom g, const ui
 
 template <typename real, int W>
 hipError_t degrid_w(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
-                    const real *lut, const real *mesh, real *out, hipStream_t s) {
+                    const real *lut, const real *mesh, int32_t panel, real *out, hipStream_t s) {
     const int64_t nvis = nrow * nchan;
     if (nvis == 0) return hipSuccess;
     int64_t blocks = (nvis + kDegridBlock - 1) / kDegridBlock;
     if (blocks > 65536) blocks = 65536;
     const size_t lds = (size_t)g.OS * W * sizeof(real);
-    hipLaunchKernelGGL((k_degrid<real, W>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, uvw, scales,
-                       nrow, nchan, lut, mesh, out);
+    const int32_t log2pw = panel > 0 ? __builtin_ctz((unsigned)panel) : 0;
+    if (panel > 0)
+        hipLaunchKernelGGL((k_degrid<real, W, true>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, uvw,
+                           scales, nrow, nchan, lut, mesh, log2pw, out);
+    else
+        hipLaunchKernelGGL((k_degrid<real, W, false>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, uvw,
+                           scales, nrow, nchan, lut, mesh, log2pw, out);
     return hipGetLastError();
 }
 
 template <typename real, int W>
 hipError_t degrid_sorted_w(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis, const real *lut,
-                           const real *mesh, real *out, hipStream_t s) {
+                           const real *mesh, int32_t panel, real *out, hipStream_t s) {
     if (nvis == 0) return hipSuccess;
     int64_t blocks = (nvis + kDegridBlock - 1) / kDegridBlock;
     if (blocks > 65536) blocks = 65536;
     const size_t lds = (size_t)g.OS * W * sizeof(real);
-    hipLaunchKernelGGL((k_degrid_sorted<real, W>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g, keys, vals,
-                       nvis, lut, mesh, out);
+    const int32_t log2pw = panel > 0 ? __builtin_ctz((unsigned)panel) : 0;
+    if (panel > 0)
+        hipLaunchKernelGGL((k_degrid_sorted<real, W, true>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g,
+                           keys, vals, nvis, lut, mesh, log2pw, out);
+    else
+        hipLaunchKernelGGL((k_degrid_sorted<real, W, false>), dim3((unsigned)blocks), dim3(kDegridBlock), lds, s, g,
+                           keys, vals, nvis, lut, mesh, log2pw, out);
     return hipGetLastError();
 }
 
@@ -253,10 +296,10 @@ hipError_t launch_predict_screen(const Geom &g, const real *model, const double 
 
 template <typename real>
 hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
-                         const real *lut, const real *mesh, real *out, hipStream_t s) {
+                         const real *lut, const real *mesh, int32_t panel, real *out, hipStream_t s) {
     switch (g.W) {
 #define RICK_DEGRID_W(w) \
-    case w: return degrid_w<real, w>(g, uvw, scales, nrow, nchan, lut, mesh, out, s);
+    case w: return degrid_w<real, w>(g, uvw, scales, nrow, nchan, lut, mesh, panel, out, s);
         RICK_DEGRID_W(1)
         RICK_DEGRID_W(3)
         RICK_DEGRID_W(5)
@@ -272,13 +315,14 @@ hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales,
 
 template <typename real>
 hipError_t launch_order_keys(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
-                             uint64_t *keys, uint64_t *vals, hipStream_t s) {
+                             int32_t panel, uint64_t *keys, uint64_t *vals, hipStream_t s) {
     const int64_t nvis = nrow * nchan;
     if (nvis == 0) return hipSuccess;
     int64_t blocks = (nvis + kDegridBlock - 1) / kDegridBlock;
     if (blocks > 65536) blocks = 65536;
+    const int32_t log2pw = panel > 0 ? __builtin_ctz((unsigned)panel) : 0;
     hipLaunchKernelGGL((k_order_keys<real>), dim3((unsigned)blocks), dim3(kDegridBlock), 0, s, g, uvw, scales, nrow,
-                       nchan, keys, vals);
+                       nchan, log2pw, keys, vals);
     return hipGetLastError();
 }
 
@@ -290,10 +334,10 @@ hipError_t sort_order(void *temp, size_t &temp_bytes, const uint64_t *keys_in, u
 
 template <typename real>
 hipError_t launch_degrid_sorted(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis,
-                                const real *lut, const real *mesh, real *out, hipStream_t s) {
+                                const real *lut, const real *mesh, int32_t panel, real *out, hipStream_t s) {
     switch (g.W) {
 #define RICK_DEGRID_SW(w) \
-    case w: return degrid_sorted_w<real, w>(g, keys, vals, nvis, lut, mesh, out, s);
+    case w: return degrid_sorted_w<real, w>(g, keys, vals, nvis, lut, mesh, panel, out, s);
         RICK_DEGRID_SW(1)
         RICK_DEGRID_SW(3)
         RICK_DEGRID_SW(5)
@@ -308,20 +352,20 @@ hipError_t launch_degrid_sorted(const Geom &g, const uint64_t *keys, const uint6
 }
 
 template hipError_t launch_order_keys<float>(const Geom &, const double *, const double *, int64_t, int32_t,
-                                             uint64_t *, uint64_t *, hipStream_t);
+                                             int32_t, uint64_t *, uint64_t *, hipStream_t);
 template hipError_t launch_order_keys<double>(const Geom &, const double *, const double *, int64_t, int32_t,
-                                              uint64_t *, uint64_t *, hipStream_t);
+                                              int32_t, uint64_t *, uint64_t *, hipStream_t);
 template hipError_t launch_degrid_sorted<float>(const Geom &, const uint64_t *, const uint64_t *, int64_t,
-                                                const float *, const float *, float *, hipStream_t);
+                                                const float *, const float *, int32_t, float *, hipStream_t);
 template hipError_t launch_degrid_sorted<double>(const Geom &, const uint64_t *, const uint64_t *, int64_t,
-                                                 const double *, const double *, double *, hipStream_t);
+                                                 const double *, const double *, int32_t, double *, hipStream_t);
 template hipError_t launch_predict_screen<float>(const Geom &, const float *, const double *, float *, uint64_t *,
                                                  uint64_t *, hipStream_t);
 template hipError_t launch_predict_screen<double>(const Geom &, const double *, const double *, double *,
                                                   uint64_t *, uint64_t *, hipStream_t);
 template hipError_t launch_degrid<float>(const Geom &, const double *, const double *, int64_t, int32_t,
-                                         const float *, const float *, float *, hipStream_t);
+                                         const float *, const float *, int32_t, float *, hipStream_t);
 template hipError_t launch_degrid<double>(const Geom &, const double *, const double *, int64_t, int32_t,
-                                          const double *, const double *, double *, hipStream_t);
+                                          const double *, const double *, int32_t, double *, hipStream_t);
 
 }  // namespace rick

@@ -391,12 +391,15 @@ __global__ __launch_bounds__((N / 16) * B) void k_fft_rows(Geom g, real *__restr
 
 // ---- columns: one block per (plane, strip of V columns) ----
 // thread tid: vector group vg = tid % (V / VC) (fastest: adjacent columns),
-// butterfly lane tb = tid / (V / VC)
-template <typename real, int N, int V, int VC>
+// butterfly lane tb = tid / (V / VC).  PW = 0: rows of N elements; PW > 0:
+// column-panel order (row e of column c at (c / PW) N PW + e PW + c % PW, the
+// strip inside one panel), so that a strip's row segments fill whole lines.
+template <typename real, int N, int V, int VC, int PW>
 __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols(real *__restrict__ mesh,
                                                                   const real *__restrict__ twr, int32_t nw) {
     using C = typename R2T<real>::t;
     constexpr int NSTRIP = N / V;
+    constexpr int64_t RS = PW > 0 ? PW : N;   // element stride between rows of a column
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
     const C *tw = reinterpret_cast<const C *>(twr);
@@ -404,20 +407,21 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols(real *__restri
     const int64_t plane = logical / NSTRIP;
     const int c0 = (int)(logical % NSTRIP) * V;
     const int vg = threadIdx.x % (V / VC), tb = threadIdx.x / (V / VC), v0 = vg * VC;
-    C *g = reinterpret_cast<C *>(mesh) + plane * (int64_t)N * N + c0 + v0;
+    const int64_t col_off = PW > 0 ? (int64_t)(c0 / PW) * N * PW + c0 % PW : c0;
+    C *g = reinterpret_cast<C *>(mesh) + plane * (int64_t)N * N + col_off + v0;
     C x[16][VC];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = in_elem<N>(tb, i);
 #pragma unroll
-        for (int v = 0; v < VC; ++v) x[i][v] = cneg_if(g[(int64_t)e * N + v], e & 1);
+        for (int v = 0; v < VC; ++v) x[i][v] = cneg_if(g[(int64_t)e * RS + v], e & 1);
     }
     fft_regs<N, V, VC>(x, buf, tb, v0, tw);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int e = out_elem<N>(tb, q);
 #pragma unroll
-        for (int v = 0; v < VC; ++v) g[(int64_t)e * N + v] = cneg_if(x[q][v], e & 1);
+        for (int v = 0; v < VC; ++v) g[(int64_t)e * RS + v] = cneg_if(x[q][v], e & 1);
     }
 }
 
@@ -595,19 +599,19 @@ hipError_t rows_n(const Geom &g, real *mesh, const real *tw, const uint64_t *til
     return hipGetLastError();
 }
 
-template <typename real, int N>
+template <typename real, int N, int PW>
 hipError_t cols_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     using CS = ColShape<real, N>;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_fft_cols<real, N, CS::V, CS::VC>,
+        (void)hipFuncSetAttribute((const void *)k_fft_cols<real, N, CS::V, CS::VC, PW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
     const int64_t nblk = (int64_t)g.Nw * (N / CS::V);
-    hipLaunchKernelGGL((k_fft_cols<real, N, CS::V, CS::VC>), dim3((unsigned)nblk), dim3(CS::THREADS), lds, s, mesh,
-                       tw, g.Nw);
+    hipLaunchKernelGGL((k_fft_cols<real, N, CS::V, CS::VC, PW>), dim3((unsigned)nblk), dim3(CS::THREADS), lds, s,
+                       mesh, tw, g.Nw);
     return hipGetLastError();
 }
 
@@ -728,7 +732,18 @@ template <typename real>
 hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     switch (g.N) {
 #define CASE(n) \
-    case n: return cols_n<real, n>(g, mesh, tw, s);
+    case n: return cols_n<real, n, 0>(g, mesh, tw, s);
+        CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename real>
+hipError_t launch_fft_cols_panel(const Geom &g, real *row_mesh, const real *tw, hipStream_t s) {
+    switch (g.N) {
+#define CASE(n) \
+    case n: return cols_n<real, n, PanelShape<real, n>::PW>(g, row_mesh, tw, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -757,6 +772,8 @@ template hipError_t launch_fft_rows_panel<double>(const Geom &, const double *, 
                                                   const uint64_t *, const uint64_t *, hipStream_t);
 template hipError_t launch_fft_cols<float>(const Geom &, float *, const float *, hipStream_t);
 template hipError_t launch_fft_cols<double>(const Geom &, double *, const double *, hipStream_t);
+template hipError_t launch_fft_cols_panel<float>(const Geom &, float *, const float *, hipStream_t);
+template hipError_t launch_fft_cols_panel<double>(const Geom &, double *, const double *, hipStream_t);
 template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, const float *, const double *,
                                                   const Stats *, const uint64_t *, float *, int, hipStream_t);
 template hipError_t launch_fft_cols_screen<double>(const Geom &, const double *, const double *, const double *,

@@ -678,9 +678,24 @@ rick_status rick_predict_planes(rick_plan_t *p, const void *model, void *stream)
                                          p->row_bits, s);
     timer_end(p, T_PRED_SCREEN, s);
     if (e != hipSuccess) return hip_fail(e, "predict_screen");
-    // the inverse transform of conj(P_k) is conj(H_k); rows then columns, in place
+    // the inverse transform of conj(P_k) is conj(H_k): rows then columns, in
+    // place in the mesh, or (plans with a row_mesh) rows into row_mesh in
+    // column-panel order and columns in place there, whose strips then read
+    // and write whole lines
     timer_begin(p, T_PRED_FFT, "predict_fft", s);
-    if (p->fp64) {
+    if (p->fused) {
+        if (p->fp64) {
+            e = launch_fft_rows_panel<double>(g, (const double *)p->mesh, (double *)p->row_mesh,
+                                              (const double *)p->twiddle, p->tile_bits, p->row_bits, s);
+            if (e == hipSuccess)
+                e = launch_fft_cols_panel<double>(g, (double *)p->row_mesh, (const double *)p->twiddle, s);
+        } else {
+            e = launch_fft_rows_panel<float>(g, (const float *)p->mesh, (float *)p->row_mesh,
+                                             (const float *)p->twiddle, p->tile_bits, p->row_bits, s);
+            if (e == hipSuccess)
+                e = launch_fft_cols_panel<float>(g, (float *)p->row_mesh, (const float *)p->twiddle, s);
+        }
+    } else if (p->fp64) {
         e = launch_fft_rows<double>(g, (double *)p->mesh, (const double *)p->twiddle, p->tile_bits, p->row_bits, s);
         if (e == hipSuccess) e = launch_fft_cols<double>(g, (double *)p->mesh, (const double *)p->twiddle, s);
     } else {
@@ -718,12 +733,14 @@ rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz
     hipError_t e = launch_set_scales(p->scales, sc.data(), nchan, s);
     if (e != hipSuccess) return hip_fail(e, "channel scales upload");
     timer_begin(p, T_DEGRID, "degrid", s);
+    const void *planes = p->fused ? p->row_mesh : p->mesh;
+    const int32_t panel = p->fused ? p->panel : 0;
     if (p->fp64)
-        e = launch_degrid<double>(p->g, uvw, p->scales, nrow, nchan, (const double *)p->lut, (const double *)p->mesh,
-                                  (double *)vis_out, s);
+        e = launch_degrid<double>(p->g, uvw, p->scales, nrow, nchan, (const double *)p->lut, (const double *)planes,
+                                  panel, (double *)vis_out, s);
     else
-        e = launch_degrid<float>(p->g, uvw, p->scales, nrow, nchan, (const float *)p->lut, (const float *)p->mesh,
-                                 (float *)vis_out, s);
+        e = launch_degrid<float>(p->g, uvw, p->scales, nrow, nchan, (const float *)p->lut, (const float *)planes,
+                                 panel, (float *)vis_out, s);
     timer_end(p, T_DEGRID, s);
     if (e != hipSuccess) return hip_fail(e, "degrid");
     return RICK_OK;
@@ -736,6 +753,7 @@ struct rick_degrid_order_s {
     int device;
     int64_t nrow, nvis;
     int32_t nchan;
+    int32_t panel;   // layout the keys address: 0 row order, else column panels of this width
     uint64_t *keys, *vals;
     Geom g;   // geometry the positions were quantised with
 };
@@ -792,14 +810,16 @@ rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const do
         if (vout) (void)hipFree(vout);
         return fail(RICK_E_OOM, "sort order buffers for %lld visibilities", (long long)nvis);
     }
-    // keys are flat mesh offsets of the footprint origin: below N_w N^2
+    // keys are offsets of the footprint origin in the layout the planes will
+    // be held in (row_mesh's column panels for plans that have one): below N_w N^2
+    const int32_t panel = p->fused ? p->panel : 0;
     int end_bit = 1;
     while ((uint64_t(1) << end_bit) < uint64_t(g.Nw) * uint64_t(g.N) * uint64_t(g.N)) ++end_bit;
     size_t temp_bytes = 0;
     e = launch_set_scales(p->scales, sc.data(), nchan, s);
     if (e == hipSuccess)
-        e = p->fp64 ? launch_order_keys<double>(g, uvw, p->scales, nrow, nchan, kin, vin, s)
-                    : launch_order_keys<float>(g, uvw, p->scales, nrow, nchan, kin, vin, s);
+        e = p->fp64 ? launch_order_keys<double>(g, uvw, p->scales, nrow, nchan, panel, kin, vin, s)
+                    : launch_order_keys<float>(g, uvw, p->scales, nrow, nchan, panel, kin, vin, s);
     if (e == hipSuccess && nvis > 0) e = sort_order(nullptr, temp_bytes, kin, kout, vin, vout, nvis, end_bit, s);
     if (e == hipSuccess && nvis > 0) e = hipMalloc(&temp, temp_bytes > 0 ? temp_bytes : 1);
     if (e == hipSuccess && nvis > 0) e = sort_order(temp, temp_bytes, kin, kout, vin, vout, nvis, end_bit, s);
@@ -816,6 +836,7 @@ rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const do
     o->nrow = nrow;
     o->nchan = nchan;
     o->nvis = nvis;
+    o->panel = panel;
     o->keys = kout;
     o->vals = vout;
     o->g = g;
@@ -837,19 +858,21 @@ rick_status rick_degrid_sorted(rick_plan_t *p, const rick_degrid_order_t *o, voi
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
     if (!o || o->magic != kOrderMagic) return fail(RICK_E_INVALID_ARG, "invalid degrid order");
     if (o->device != p->d.device) return fail(RICK_E_INVALID_ARG, "order and plan on different devices");
-    if (!same_geometry(o->g, p->g))
-        return fail(RICK_E_INVALID_ARG, "order was made for another grid, field or w range");
+    if (!same_geometry(o->g, p->g) || o->panel != (p->fused ? p->panel : 0))
+        return fail(RICK_E_INVALID_ARG, "order was made for another grid, field, w range or plane layout");
     if (o->nvis > 0 && !vis_out) return fail(RICK_E_INVALID_ARG, "vis_out is NULL");
     if ((uintptr_t)vis_out & (p->fp64 ? 15 : 7)) return fail(RICK_E_INVALID_ARG, "misaligned vis_out");
     if (p->state != 3) return fail(RICK_E_STATE, "no predicted planes; call rick_predict_planes first");
     DeviceGuard guard(p->d.device);
     hipStream_t s = (hipStream_t)stream;
     timer_begin(p, T_DEGRID, "degrid", s);
+    const void *planes = p->fused ? p->row_mesh : p->mesh;
+    const int32_t panel = p->fused ? p->panel : 0;
     hipError_t e =
         p->fp64 ? launch_degrid_sorted<double>(p->g, o->keys, o->vals, o->nvis, (const double *)p->lut,
-                                               (const double *)p->mesh, (double *)vis_out, s)
+                                               (const double *)planes, panel, (double *)vis_out, s)
                 : launch_degrid_sorted<float>(p->g, o->keys, o->vals, o->nvis, (const float *)p->lut,
-                                              (const float *)p->mesh, (float *)vis_out, s);
+                                              (const float *)planes, panel, (float *)vis_out, s);
     timer_end(p, T_DEGRID, s);
     if (e != hipSuccess) return hip_fail(e, "degrid_sorted");
     return RICK_OK;

@@ -157,6 +157,9 @@ hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *twiddle, const
                            const uint64_t *row_bits, hipStream_t s);
 template <typename real>
 hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *twiddle, hipStream_t s);
+// Column pass in place on column-panel order (the row pass's panel output).
+template <typename real>
+hipError_t launch_fft_cols_panel(const Geom &g, real *row_mesh, const real *tw, hipStream_t s);
 // Row pass of the fused path: from the mesh into `out` in column-panel order
 // (panels of fused_panel_width(N) columns, each stored row after row).  Rows
 // of an empty tile row are not written (the fused column pass reads them as zeros).
@@ -186,16 +189,18 @@ hipError_t launch_predict_screen(const Geom &g, const real *model, const double 
 // sorted order.
 template <typename real>
 hipError_t launch_order_keys(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
-                             uint64_t *keys, uint64_t *vals, hipStream_t s);
+                             int32_t panel, uint64_t *keys, uint64_t *vals, hipStream_t s);
 hipError_t sort_order(void *temp, size_t &temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
                       const uint64_t *vals_in, uint64_t *vals_out, int64_t n, int end_bit, hipStream_t s);
 template <typename real>
 hipError_t launch_degrid_sorted(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis,
-                                const real *lut, const real *mesh, real *out, hipStream_t s);
+                                const real *lut, const real *mesh, int32_t panel, real *out, hipStream_t s);
 
 // Prediction: interpolate visibilities from planes holding conj(H_k).
+// panel = 0: planes in row order (the mesh); panel = PW: column-panel order
+// (the fused plan's row_mesh), element (k, j, i) at k N^2 + (i / PW) N PW + j PW + i % PW.
 template <typename real>
 hipError_t launch_degrid(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
-                         const real *lut, const real *mesh, real *out, hipStream_t s);
+                         const real *lut, const real *mesh, int32_t panel, real *out, hipStream_t s);
 
 }  // namespace rick

@@ -57,12 +57,15 @@ def _predict_gpu(ds, M, precision="fp32", fused=False, freq=None, **plan_kw):
         return vis.cpu().numpy().astype(np.complex128).reshape(-1)
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("dense", [False, True])
-def test_tiny_predict_matches_oracle(precision, dense):
+def test_tiny_predict_matches_oracle(precision, dense, fused):
+    """fused: planes transformed into the plan's row_mesh in column-panel
+    order and interpolated from there."""
     ds = synth.tiny(nrow=20000, seed=51)
     M = _model(ds.grid_n, 52, dense=dense)
-    got = _predict_gpu(ds, M, precision)
+    got = _predict_gpu(ds, M, precision, fused=fused)
     ref = op.wstack_predict(M, ds.uvw, None, **ds.plan_kwargs(), keep_planes=False)
     kept = ref.binned.keep
     assert np.all(got[~kept] == 0)
@@ -81,14 +84,15 @@ def test_multichannel_metres_matches_oracle(fused):
     assert rel_rms(got[kept], ref.vis[kept]) <= _tol("fp32", M, ds)
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("kernel,W,OS,N", [("kaiser_bessel", 5, 16, 512), ("gaussian", 9, 128, 128),
                                            ("gaussian", 1, 1, 64)])
-def test_kernels_supports_and_sizes(kernel, W, OS, N):
+def test_kernels_supports_and_sizes(kernel, W, OS, N, fused):
     ds = synth.tiny(nrow=6000, seed=54, grid_n=N)
     kw = {**ds.plan_kwargs(), "kernel": kernel, "support": W, "oversample": OS}
     ds.kernel, ds.support, ds.oversample = kernel, W, OS
     M = _model(N, 55, dense=True)
-    got = _predict_gpu(ds, M, "fp64")
+    got = _predict_gpu(ds, M, "fp64", fused=fused)
     ref = op.wstack_predict(M, ds.uvw, None, **kw, keep_planes=False)
     kept = ref.binned.keep
     assert np.all(got[~kept] == 0)
@@ -177,8 +181,9 @@ def test_call_order_with_imaging():
     assert np.array_equal(first, second)
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_sorted_order_equals_direct_order(precision):
+def test_sorted_order_equals_direct_order(precision, fused):
     """Prediction through a sort order (quantised and sorted once) gives each
     visibility the same value as the direct walk, at its own index; dropped
     visibilities are 0; channels in metres."""
@@ -187,7 +192,7 @@ def test_sorted_order_equals_direct_order(precision):
     uvw_h = ds.uvw.copy()
     uvw_h[:5, 0] = 1e9
     M = _model(ds.grid_n, 63, n_src=40)
-    with rick.Plan.for_dataset(ds, precision=precision) as p:
+    with rick.Plan.for_dataset(ds, precision=precision, fused=fused) as p:
         uvw = torch.as_tensor(uvw_h).to("cuda:0")
         p.predict_planes(torch.as_tensor(M, dtype=p.real_dtype).to("cuda:0"))
         direct = p.degrid(uvw, ds.freq).cpu().numpy()
