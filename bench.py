@@ -538,19 +538,85 @@ def batch_report(args):
         graph.launch(stream)
         totals.append(stamps.elapsed(0, n))
         lat = [stamps.elapsed(i, i + 1) for i in range(n)]
+    seq_imgs = [im.clone() for im in imgs]
+    # the same jobs on several streams: each plan (shape) stays on one stream,
+    # so its jobs keep their order; shapes are spread over the streams by total
+    # visibility count, and the streams fork from and join the first one
+    S = max(1, min(args.streams, len(shapes)))
+    conc = None
+    if S > 1:
+        streams = [stream] + [torch.cuda.Stream() for _ in range(S - 1)]
+        load, shape_stream = [0] * S, {}
+        for key in sorted(shapes, key=lambda k: -sum(jobs[i].nvis for i in shapes[k])):
+            j = min(range(S), key=lambda x: load[x])
+            shape_stream[key] = j
+            load[j] += sum(jobs[i].nvis for i in shapes[key])
+        per_stream = [[i for i in range(n) if shape_stream[(jobs[i].grid_n, jobs[i].n_wplanes)] == j]
+                      for j in range(S)]
+        order = [lst[r] for r in range(max(len(x) for x in per_stream)) for lst in per_stream if r < len(lst)]
+        cstamps = rick.Stamps(2 * n + 2)
+
+        def issue_concurrent():
+            cstamps.stamp(0, streams[0])
+            ev = torch.cuda.Event()
+            ev.record(streams[0])
+            for st in streams[1:]:
+                st.wait_event(ev)
+            for i in order:
+                st = streams[shape_stream[(jobs[i].grid_n, jobs[i].n_wplanes)]]
+                cstamps.stamp(2 + 2 * i, st)
+                issue(i, st)
+                cstamps.stamp(3 + 2 * i, st)
+            for st in streams[1:]:
+                e = torch.cuda.Event()
+                e.record(st)
+                streams[0].wait_event(e)
+            cstamps.stamp(1, streams[0])
+
+        ceager = []
+        for rep in range(max(1, args.warmup)):
+            issue_concurrent()
+            ceager.append(cstamps.elapsed(0, 1))
+        with rick.Graph.record(stream) as cgraph:
+            issue_concurrent()
+        ctot, clat = [], []
+        for rep in range(args.steps):
+            for im in imgs:
+                im.fill_(0.0)
+            torch.cuda.synchronize()
+            cgraph.launch(stream)
+            ctot.append(cstamps.elapsed(0, 1))
+            clat = [cstamps.elapsed(2 + 2 * i, 3 + 2 * i) for i in range(n)]
+        torch.cuda.synchronize()
+        conc_imgs = [im.clone() for im in imgs]
+        cmed = float(np.median(ctot))
+        cl = np.sort(np.asarray(clat))
+        conc = {"streams": S, "jobs_per_s": round(n / (cmed * 1e-3), 2), "batch_ms": round(cmed, 3),
+                "mvis_per_s": round(nvis / (cmed * 1e-3) / 1e6, 1),
+                "eager_batch_ms": round(float(np.median(ceager)), 3),
+                "latency_ms": {"p50": round(float(np.percentile(cl, 50)), 3),
+                               "p99": round(float(np.percentile(cl, 99)), 3), "max": round(float(cl[-1]), 3)}}
+        cgraph.close()
+        cstamps.close()
+        for i in range(n):
+            imgs[i].copy_(seq_imgs[i])
     # graph against eager in the apparent image (both multiplied by C_p C_q): the
     # shared-tile float atomics add in no fixed order, and dividing by the taper
     # magnifies that rounding in the outermost pixels of the corrected image
     import oracle.pixels
     from oracle import wstack as ow
-    diffs = []
-    for ds, a, b in zip(jobs, imgs, eager):
+    def apparent_rel(ds, a, b):
         c = torch.as_tensor(ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel,
                                                             ds.kernel_param), ds.grid_n), device=dev)
         c2 = c[:, None] * c[None, :]
-        diffs.append(float(torch.linalg.vector_norm((a - b).double() * c2) /
-                           max(float(torch.linalg.vector_norm(b.double() * c2)), 1e-300)))
+        return float(torch.linalg.vector_norm((a - b).double() * c2) /
+                     max(float(torch.linalg.vector_norm(b.double() * c2)), 1e-300))
+
+    diffs = [apparent_rel(ds, a, b) for ds, a, b in zip(jobs, imgs, eager)]
     worst = max(diffs)
+    if conc is not None:
+        conc["vs_one_stream_max_apparent_rel_rms"] = max(
+            apparent_rel(ds, a, b) for ds, a, b in zip(jobs, conc_imgs, seq_imgs))
     # the smallest job against the oracle at sampled pixels
     small = min(range(n), key=lambda i: jobs[i].nvis)
     ds = jobs[small]
@@ -579,6 +645,7 @@ def batch_report(args):
            "graph_vs_eager_apparent_rel_rms": [float("%.3g" % d) for d in diffs],
            "job_shapes": [f"{ds.grid_n}x{ds.n_wplanes}:{ds.nvis}" for ds in jobs],
            "oracle_check": {"job": small, "pixels": int(len(pp)), "apparent_rel_rms": ocheck},
+           "concurrent": conc,
            "shapes": {f"{k[0]}x{k[1]}": {"jobs": len(shapes[k]), "tile": v[0], "chunk": v[1],
                                          "tuned_ms": round(v[2], 3)} for k, v in sorted(tuned.items())}}
     print(json.dumps(out), flush=True)
@@ -720,6 +787,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the batched form: many uneven jobs recorded into a graph and replayed (jobs/s, latency)")
     ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="streams of the concurrent run of --batch (1 = only the one-stream run)")
     ap.add_argument("--predict", action="store_true",
                     help="prediction (degridding) of the workload's visibilities from a point-source model image")
     args = ap.parse_args()
