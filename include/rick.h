@@ -17,6 +17,14 @@
  *   rick_predict_planes, rick_degrid
  *                      prediction: model image -> visibilities (Eq. 2), the
  *                      adjoint of the imaging steps
+ *   rick_degrid_order_create, rick_degrid_sorted, rick_degrid_order_destroy
+ *                      prediction at fixed positions: quantise and sort once,
+ *                      interpolate in sorted order every time
+ *   rick_plan_retarget, rick_capture_begin/_end, rick_graph_launch/_destroy,
+ *   rick_stamps_create/_stamp/_elapsed/_destroy, rick_autotune
+ *                      many jobs: one plan per shape retargeted per job, work
+ *                      recorded into a graph and replayed, device timestamps,
+ *                      tile and chunk chosen by measurement
  *
  * Conventions shared by every call:
  *   - All entry points return a rick_status; no exception, abort or exit
@@ -29,7 +37,10 @@
  *   - A plan is used by one host thread and one stream at a time; distinct
  *     plans are independent.
  *   - The plan owns every device buffer it allocates; rick_plan allocates
- *     them all once, the other calls allocate nothing.
+ *     them all once, and the calls on a plan allocate nothing.  The calls
+ *     that create other objects (rick_degrid_order_create, rick_capture_end,
+ *     rick_stamps_create) and rick_autotune (trial plans) allocate, and say
+ *     so.
  *
  * Coordinates (the paper leaves them implicit; these are this library's):
  *   cell i of the N-cell axis sits at u_i = (i - N/2) du, du = 1 / FoV;
@@ -317,11 +328,12 @@ rick_status rick_plan_bin_counts(rick_plan_t *p, int32_t *counts, int64_t n);
  *
  * rick_capture_begin -- start recording the work the library (and anything
  * else) issues on `stream` into a graph instead of running it: rick_reset,
- * rick_grid, rick_fft_planes, rick_wstack_image and rick_stamp on any plans,
- * each with the same stream.  None of them allocates or synchronises, so a
- * whole sequence of jobs can be recorded.  rick_plan_info,
- * rick_plan_bin_counts, rick_autotune and plan creation synchronise and must
- * not be called while recording.
+ * rick_grid, rick_fft_planes, rick_wstack_image, rick_predict_planes,
+ * rick_degrid, rick_degrid_sorted and rick_stamp on any plans, each with the
+ * same stream.  None of them allocates or synchronises, so a whole sequence
+ * of jobs can be recorded.  rick_plan_info, rick_plan_bin_counts,
+ * rick_autotune, rick_degrid_order_create and plan creation synchronise and
+ * must not be called while recording.
  * rick_capture_end -- stop recording and instantiate the graph; *out
  * receives it (NULL on failure).
  * rick_graph_launch -- run the recorded work once on `stream` (asynchronous;
@@ -339,7 +351,8 @@ rick_status rick_graph_destroy(rick_graph_t *g);
 
 /*
  * Device timestamps for per-job latencies inside a graph.
- * rick_stamps_create -- n timestamp slots; rick_stamp -- a one-thread kernel
+ * rick_stamps_create -- n timestamp slots (allocates 8 n bytes of device
+ * memory); rick_stamp -- a one-thread kernel
  * on `stream` writes the device's constant-rate clock into slot i when the
  * preceding work on the stream has finished (may be recorded into a graph);
  * rick_stamps_elapsed -- synchronise the device and give, in *ms, the time
