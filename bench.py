@@ -818,8 +818,8 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the plane-sharded multi-GPU path is a design, not code)", file=sys.stderr)
+        print(f"bench.py: the imager runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding the planes over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
