@@ -238,12 +238,15 @@ def run_profiles(out, workload):
         results = [f for f in os.listdir(os.path.join(out, name))] if os.path.isdir(os.path.join(out, name)) else []
         print(f"[profile] {name}: rc={rc}, files {sorted(results)}", file=sys.stderr, flush=True)
         if rc != 0:
-            # the profiler can end with a fault of its own after a complete run;
-            # accept only when the program printed its last line and results exist
+            # any nonzero exit fails the pass, also after a complete-looking run:
+            # a fault at teardown (the library's or the profiler's) is not told
+            # apart here, so the pass's rc and the end of its log are kept
             with open(os.path.join(out, f"{name}.log")) as fh:
-                done = any(l.startswith('{"') for l in fh)
-            if not (done and results):
-                raise SystemExit(f"[profile] {name} failed (rc={rc}); later passes not started")
+                tail = fh.readlines()[-15:]
+            with open(os.path.join(out, f"{name}.failed.txt"), "w") as fh:
+                fh.write(f"rc={rc}\n" + "".join(tail))
+            raise SystemExit(f"[profile] {name} failed (rc={rc}); later passes not started; "
+                             f"log tail in {name}.failed.txt")
     summarize_profiles(out, workload)
 
 

@@ -588,12 +588,11 @@ hipError_t rows_n(const Geom &g, real *mesh, const real *tw, const uint64_t *til
     constexpr int B = NT >= 256 ? 1 : 256 / NT;
     const int64_t nrows = (int64_t)g.Nw * N;
     const size_t lds = size_t(B) * Shape<N>::PADN * sizeof(C);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
         (void)hipFuncSetAttribute((const void *)k_fft_rows<real, N, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL((k_fft_rows<real, N, B>), dim3((unsigned)(nrows / B)), dim3(NT * B), lds, s, g, mesh, tw,
                        tile_bits, row_bits);
     return hipGetLastError();
@@ -603,12 +602,11 @@ template <typename real, int N, int PW>
 hipError_t cols_n(const Geom &g, real *mesh, const real *tw, hipStream_t s) {
     using CS = ColShape<real, N>;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
         (void)hipFuncSetAttribute((const void *)k_fft_cols<real, N, CS::V, CS::VC, PW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    });
     const int64_t nblk = (int64_t)g.Nw * (N / CS::V);
     hipLaunchKernelGGL((k_fft_cols<real, N, CS::V, CS::VC, PW>), dim3((unsigned)nblk), dim3(CS::THREADS), lds, s,
                        mesh, tw, g.Nw);
@@ -636,12 +634,11 @@ hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw
     using PS = PanelShape<real, N>;
     const int64_t nrows = (int64_t)g.Nw * N;
     const size_t lds = size_t(PS::RB) * Shape<N>::PADN * sizeof(C);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
         (void)hipFuncSetAttribute((const void *)k_fft_rows_panel<real, N, PS::RB, PS::PW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    });
     // persistent blocks: as many as fit on the device at once
     static int cus = 0;
     if (!cus) {
@@ -666,14 +663,13 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
     using CS = ColShape<real, N>;
     constexpr int PW = PanelShape<real, N>::PW;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
         (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
+    });
     if (kahan)
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>), dim3(N / CS::V), dim3(CS::THREADS),
                            lds, s, g, mesh, tw, corr, st, row_bits, image);

@@ -487,12 +487,11 @@ hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, 
                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                    const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
         (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(160 * 1024));
-        attr = true;
-    }
+    });
     hipLaunchKernelGGL((k_grid<real, W, TT>), dim3(max_items), dim3(grid_threads(TT)), lds, s, g, scan, item_bin,
                        rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax);
     return hipGetLastError();

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <utility>
+
 #include "../../include/rick.h"
 
 namespace rick {
@@ -17,6 +20,22 @@ constexpr int kL1Blocks = 512;           // blocks of the level-1 binning passes
 constexpr int kMaxCoarse = 8192;         // coarse bins of level-1 binning (LDS counters per block)
 constexpr int kMaxPlanes = 8192;         // w-planes per plan
 constexpr int kTimerRing = 64;         // launches per kernel whose times are kept between reads
+
+constexpr int kMaxDevices = 64;          // device ordinals with their own once-per-device set-up
+
+// Runs f once per device for one call site (the site keeps one flag per
+// device ordinal): kernel attributes are per device, so a plan on a second
+// GPU sets them there too.  Concurrent first callers on one device wait until
+// the first has finished.
+template <class F>
+inline void once_per_device(std::once_flag (&flags)[kMaxDevices], F &&f) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        f();
+        return;
+    }
+    std::call_once(flags[dev], std::forward<F>(f));
+}
 
 // A batch of channel scale factors nu_c / c0, passed by value.
 struct ChanScales {

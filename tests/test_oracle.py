@@ -397,3 +397,77 @@ def test_bin_stats_match_python_oracle(maker):
             sel = b.keep & (b.k == k)
             assert abs(psum[k] - b.wv[sel].sum()) <= 1e-9 * max(1.0, np.abs(b.wv[sel]).sum())
         assert abs(sw - r.sum_w) <= 1e-9 * r.sum_w
+
+
+# ---------------------------------------------------------------------------
+# n - 1 of Eq. 1-2, pinned without calling the oracle's own formula
+# ---------------------------------------------------------------------------
+def _nm1_decimal(l: float, m: float) -> float:
+    """sqrt(1 - l^2 - m^2) - 1 in 60-digit decimal arithmetic from the exact
+    binary values of l and m: no cancellation survives at this precision."""
+    import decimal
+    with decimal.localcontext() as ctx:
+        ctx.prec = 60
+        dl, dm = decimal.Decimal(l), decimal.Decimal(m)
+        return float((1 - dl * dl - dm * dm).sqrt() - 1)
+
+
+def test_nm1_closed_forms():
+    """Pythagorean direction cosines give n exactly: (0.6, 0) -> n = 0.8,
+    (0, 0.8) -> 0.6, (0.36, 0.48) -> 0.8, (0.48, 0.64) -> 0.6,
+    (0.6, 0.6) -> sqrt(0.28)."""
+    cases = [((0.6, 0.0), -0.2), ((0.0, 0.8), -0.4), ((0.0, 0.6), -0.2),
+             ((0.36, 0.48), -0.2), ((0.48, 0.64), -0.4), ((0.6, 0.6), math.sqrt(0.28) - 1.0), ((0.0, 0.0), 0.0)]
+    for (l, m), want in cases:
+        got = float(ow.nm1_of(np.array(l), np.array(m)))
+        assert abs(got - want) <= 4e-16 * max(1.0, abs(want)), (l, m, got, want)
+    assert np.isnan(ow.nm1_of(np.array(0.8), np.array(0.6)))      # r^2 = 1: outside the sky
+    assert np.isnan(ow.nm1_of(np.array(1.0), np.array(0.5)))
+
+
+def test_nm1_matches_high_precision_everywhere():
+    """n - 1 agrees with a 60-digit evaluation of sqrt(1 - r^2) - 1 to a few
+    ulps of relative error from r^2 = 1e-14 up to r^2 = 0.999 (a flipped sign,
+    or the small-angle form -r^2/2, is off by up to 100 % there)."""
+    rng = np.random.default_rng(41)
+    r = np.sqrt(10.0 ** rng.uniform(-14, np.log10(0.999), 400))
+    phi = rng.uniform(0, 2 * np.pi, 400)
+    l, m = r * np.cos(phi), r * np.sin(phi)
+    got = ow.nm1_of(l, m)
+    want = np.array([_nm1_decimal(a, b) for a, b in zip(l, m)])
+    assert np.all(want < 0)
+    assert np.max(np.abs(got - want) / np.abs(want)) < 4e-15
+
+
+def test_off_centre_large_w_source_recovered_by_dft_and_wstacking():
+    """A point source far from the centre (r^2 = 0.46) seen with |w| up to 2000
+    wavelengths, its visibilities built with an n - 1 from 60-digit decimal
+    arithmetic (not the oracle's formula): the direct sum gives exactly S at its
+    pixel, and w-stacking in the exact configuration (W = 1, OS = 1, cell-centred
+    (u, v), plane-centred w) gives S there too.  A wrong n - 1 in the oracle
+    leaves a phase error of w times the mistake (hundreds of turns) and the
+    pixel decorrelates."""
+    rng = np.random.default_rng(42)
+    N, Nw, fov = 64, 8, 1.2
+    w_min, w_max = -2000.0, 2000.0
+    dw = (w_max - w_min) / Nw
+    lm = ow.pixel_lm(N, fov)
+    p, q = 55, 4                                  # l = 0.43125, m = -0.525
+    l0, m0 = float(lm[p]), float(lm[q])
+    nm10 = _nm1_decimal(l0, m0)
+    assert 0.25 < l0 * l0 + m0 * m0 < 0.5
+    n = 4000
+    i = rng.integers(1, N - 1, n)
+    j = rng.integers(1, N - 1, n)
+    k = rng.integers(0, Nw, n)
+    u, v, w = (i - N // 2) / fov, (j - N // 2) / fov, w_min + (k + 0.5) * dw
+    S = 1.5
+    V = (S / (1.0 + nm10)) * np.exp(-2j * np.pi * (u * l0 + v * m0 + w * nm10))
+    W = rng.uniform(0.5, 2.0, n)
+    img = od.dft_image(u, v, w, W * V, W.sum(), fov, N, rows=slice(q, q + 1), cols=slice(p, p + 1))
+    assert abs(img[0, 0] - S) < 1e-9
+    r = ow.wstack_image(np.stack([u, v, w], 1), None, V.reshape(-1, 1), W.reshape(-1, 1),
+                        grid_n=N, n_wplanes=Nw, support=1, oversample=1, fov=fov,
+                        w_min=w_min, w_max=w_max)
+    assert r.binned.keep.all()
+    assert abs(r.image[q, p] - S) < 1e-9
