@@ -30,12 +30,16 @@ METRIC = "Mvis/s through grid+iFFT+w-stack at fixed image RMS vs FP64 DFT oracle
 
 
 def algorithmic_bytes(name, ds, info):
-    """Bytes the method must move per launch of kernel `name` (records are
-    12 B: packed position + complex64 W V, one per visibility).  Only tiles
-    that received visibilities (or their neighbours' margins) hold gridded
-    values: the gridder writes those tiles, the row pass reads them and
-    (fused) writes the rows of tile rows holding any, which the fused column
-    pass reads."""
+    """Bytes the method must move per launch of kernel `name`.  The gridder's
+    unit figures are the method's: a 16-byte record {int32 X, int32 Y,
+    complex64 W V} read per gridded visibility (this library packs it into
+    12 bytes; the difference is its own gain, not counted) and 8 bytes
+    written per cell that holds gridded values.  Only tiles that received
+    visibilities (or their neighbours' margins) hold gridded values: the
+    gridder writes those tiles, the row pass reads them and (fused) writes
+    the rows of tile rows holding any, which the fused column pass reads.
+    The binning kernels are counted with the records this library writes
+    (level-1 records of rec1_bytes, 12-byte gridding records)."""
     nvis, nrow = ds.nvis, ds.nrow
     n2 = ds.grid_n * ds.grid_n
     cells = ds.n_wplanes * n2
@@ -50,7 +54,7 @@ def algorithmic_bytes(name, ds, info):
         "bin_scatter": 24 * nrow + 8 * nvis + wbytes + r1 * nvis,   # writes the level-1 records
         "fine_count": r1 * nvis,                                    # reads them (position and W V)
         "fine_scatter": r1 * nvis + 12 * nvis,                      # reads them, writes 12-byte records
-        "grid": 12 * nvis + 8 * set_cells,
+        "grid": 16 * nvis + 8 * set_cells,                         # 16 B {X, Y, W V} per visibility
         "fft_rows": 8 * set_cells + 8 * (row_cells if fused else cells),
         "fft_cols": 16 * cells,
         "wscreen": 8 * cells + 4 * n2,
@@ -59,11 +63,47 @@ def algorithmic_bytes(name, ds, info):
     return table.get(name)
 
 
-def cpu_baseline(ds, vis_host, n_rows_sample=4_194_304, n_grid_target=8_000_000, n_planes_fft=4):
-    """The float64 oracle, as it stands, timed stage by stage on a bounded sample
-    of the same workload (10-30 s of one host core) and scaled to the whole job:
-      T = t_bin / n_binned * N_vis + t_grid / n_gridded * N_kept + N_w * (t_fft + t_screen) / n_planes."""
-    import oracle
+def host_threads():
+    """Threads the host share of this process offers: the CPU affinity set,
+    capped by OMP_NUM_THREADS when that is set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_model():
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ds, vis_host, threads, n_rows_sample=1_048_576, n_grid_target=8_000_000, n_planes_fft=4):
+    """The float64 oracle, as it stands, timed stage by stage on a bounded
+    sample of the same workload and scaled to the whole job:
+      T = t_bin / n_binned * N_vis + t_grid / n_gridded * N_kept + N_w * t_plane / n_planes.
+    `threads` workers run the oracle's own functions on independent pieces
+    (row blocks for binning, w-planes for gridding, FFT and screen), the
+    method's natural parallelism; numpy releases the interpreter lock inside
+    its array loops, so the pieces overlap."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import wstack as ow
     kw = ds.plan_kwargs()
     geo = {k: kw[k] for k in ("grid_n", "n_wplanes", "support", "oversample", "fov", "w_min", "w_max")}
@@ -74,45 +114,109 @@ def cpu_baseline(ds, vis_host, n_rows_sample=4_194_304, n_grid_target=8_000_000,
     vis_s = vis_host[sel]
     wt_s = None if ds.weight is None else ds.weight[sel]
     n_s = uvw_s.shape[0] * ds.nchan
-    t0 = time.perf_counter()
-    b = ow.bin_visibilities(uvw_s, ds.freq, vis_s, wt_s, **geo)
-    t_bin = time.perf_counter() - t0
+    blocks = np.array_split(np.arange(uvw_s.shape[0]), max(1, threads))
     table = ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param)
-    keep = np.nonzero(b.keep)[0]
-    kk = b.k[keep]
-    G = np.zeros((1, ds.grid_n, ds.grid_n), np.complex128)
-    t_grid, n_grid, n_planes = 0.0, 0, 0
-    for k in np.argsort(-np.bincount(kk, minlength=ds.n_wplanes)):
-        if n_grid >= n_grid_target:
-            break
-        idx = keep[kk == k]
-        G[0] = 0
-        t0 = time.perf_counter()
-        ow.grid_plane(G[0], b, idx, table)
-        t_grid += time.perf_counter() - t0
-        n_grid += idx.size
-        n_planes += 1
-    t_fft = t_screen = 0.0
     corr = ow.grid_correction(table, ds.grid_n)
     wk = ow.plane_centres(ds.w_min, ds.w_max, ds.n_wplanes)
-    for j in range(n_planes_fft):
+    with ThreadPoolExecutor(max_workers=threads) as ex:
         t0 = time.perf_counter()
-        F = ow.ifft_planes(G)
-        t_fft += time.perf_counter() - t0
+        parts = list(ex.map(lambda ix: ow.bin_visibilities(uvw_s[ix], ds.freq, vis_s[ix],
+                                                           None if wt_s is None else wt_s[ix], **geo), blocks))
+        t_bin = time.perf_counter() - t0
+        # gridding: the fullest planes of the first row block's binning, one task per plane
+        b = parts[0]
+        keep = np.nonzero(b.keep)[0]
+        kk = b.k[keep]
+        todo, n_grid = [], 0
+        for k in np.argsort(-np.bincount(kk, minlength=ds.n_wplanes)):
+            if n_grid >= n_grid_target // max(1, len(blocks)) or len(todo) >= max(threads, 2):
+                break
+            idx = keep[kk == k]
+            todo.append(idx)
+            n_grid += idx.size
+
+        def grid_one(idx):
+            G = np.zeros((ds.grid_n, ds.grid_n), np.complex128)
+            ow.grid_plane(G, b, idx, table)
+            return G
+
         t0 = time.perf_counter()
-        S = ow.screen_sum(F, wk[j:j + 1], ds.fov)
-        ow.normalise(S, corr, 1.0, ds.fov)
-        t_screen += time.perf_counter() - t0
-    kept_frac = float(b.keep.mean()) if n_s else 0.0
+        planes = list(ex.map(grid_one, todo))
+        t_grid = time.perf_counter() - t0
+        src = [planes[j % len(planes)] for j in range(n_planes_fft)]
+
+        def plane_one(j):
+            F = ow.ifft_planes(src[j][None])
+            S = ow.screen_sum(F, wk[j:j + 1], ds.fov)
+            return ow.normalise(S, corr, 1.0, ds.fov)
+
+        t0 = time.perf_counter()
+        list(ex.map(plane_one, range(n_planes_fft)))
+        t_plane = time.perf_counter() - t0
+        del planes, src
+    kept_frac = float(np.mean([p.keep.mean() for p in parts])) if n_s else 0.0
     total = (t_bin / n_s * ds.nvis + (t_grid / n_grid if n_grid else 0.0) * kept_frac * ds.nvis +
-             ds.n_wplanes * (t_fft + t_screen) / n_planes_fft)
-    spent = t_bin + t_grid + t_fft + t_screen
-    sample = (f"oracle stages timed on {n_s:,} visibilities binned ({uvw_s.shape[0]:,} rows x {ds.nchan} channels, "
-              f"every {step}th row), {n_grid:,} of them gridded onto {n_planes} plane(s), {n_planes_fft} "
-              f"{ds.grid_n}^2 planes transformed and screened ({spent:.1f} s); per-visibility and per-plane costs "
-              f"scaled to {ds.nvis:,} visibilities and {ds.n_wplanes} planes (est. {total:.0f} s per image)")
-    return {"value": ds.nvis / total / 1e6, "unit": "Mvis/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "sample_seconds": round(spent, 2)}
+             ds.n_wplanes * t_plane / n_planes_fft)
+    spent = t_bin + t_grid + t_plane
+    sample = (f"oracle stages on {threads} thread(s): {n_s:,} visibilities binned ({uvw_s.shape[0]:,} rows x "
+              f"{ds.nchan} channels, every {step}th row), {n_grid:,} of them gridded onto {len(todo)} plane(s), "
+              f"{n_planes_fft} {ds.grid_n}^2 planes transformed, screened and normalised ({spent:.1f} s); "
+              f"per-visibility and per-plane costs scaled to {ds.nvis:,} visibilities and {ds.n_wplanes} planes "
+              f"(est. {total:.0f} s per image)")
+    return {"value": ds.nvis / total / 1e6, "unit": "Mvis/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "sample_seconds": round(spent, 2), "est_seconds_per_image": round(total, 1)}
+
+
+def check_pixels(ds, n_patch=8, n_sources=8):
+    """Pixels the benchmark checks: an n_patch x n_patch patch at the phase
+    centre and the n_sources brightest sources."""
+    N = ds.grid_n
+    half = n_patch // 2
+    qq, pp = np.meshgrid(np.arange(N // 2 - half, N // 2 - half + n_patch),
+                         np.arange(N // 2 - half, N // 2 - half + n_patch), indexing="ij")
+    pp, qq = pp.ravel(), qq.ravel()
+    src = ds.sources
+    order = np.argsort(-np.asarray(src["flux"]))[:n_sources]
+    dl = ds.fov / N
+    sp = np.rint(np.asarray(src["l"])[order] / dl).astype(np.int64) + N // 2
+    sq = np.rint(np.asarray(src["m"])[order] / dl).astype(np.int64) + N // 2
+    return np.r_[pp, sp], np.r_[qq, sq]
+
+
+# image tolerances of the benchmark's check (the parity bar of the tests):
+# float32 modes within 1e-5 of the float64 oracle (apparent image), and the
+# distance to the direct Fourier sum equal to the oracle's own within 1 %
+TOL_ORACLE = 1e-5
+TOL_DFT = 0.01
+
+
+def oracle_leg(ds, vis_host, img_pix, pp, qq, corr):
+    """The float64 oracle (per-pixel w-stacking over every visibility) and
+    the direct Fourier sum at the checked pixels, against the GPU image
+    values img_pix there."""
+    import oracle.dft
+    import oracle.pixels
+    t0 = time.perf_counter()
+    orc, _, kept, sw = oracle.pixels.wstack_pixels(ds.uvw, ds.freq, vis_host, ds.weight, pp, qq,
+                                                   **ds.plan_kwargs())
+    t_orc = time.perf_counter() - t0
+    cp = corr[pp] * corr[qq]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {"pixels": int(len(pp)), "oracle_kept": int(kept),
+           "gpu_vs_oracle": {"apparent_rel_rms": rel(img_pix * cp, orc * cp), "image_rel_rms": rel(img_pix, orc)},
+           "oracle_seconds": round(t_orc, 1)}
+    if kept == ds.nvis and ds.freq is not None:
+        t0 = time.perf_counter()
+        dft = oracle.dft.dft_pixels_rows(ds.uvw, ds.freq, vis_host, ds.weight, pp, qq, grid_n=ds.grid_n,
+                                         fov=ds.fov, sum_w=sw)
+        out["dft_seconds"] = round(time.perf_counter() - t0, 1)
+        out["gpu_vs_dft"] = rel(img_pix, dft)
+        out["oracle_vs_dft"] = rel(orc, dft)
+        out["dft_gate"] = abs(out["gpu_vs_dft"] / out["oracle_vs_dft"] - 1.0)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -121,7 +225,7 @@ def cpu_baseline(ds, vis_host, n_rows_sample=4_194_304, n_grid_target=8_000_000,
 # own time limit, stops at the first pass that fails, and writes the summaries
 # into OUT/summary; those are the files kept under profiles/.
 # ---------------------------------------------------------------------------
-PROFILE_BENCH = ["--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--check-pixels", "0"]
+PROFILE_BENCH = ["--steps", "3", "--warmup", "1", "--no-cpu-baseline", "--no-check"]
 COPY_MIB = 1024
 SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS",
                "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"]
@@ -768,15 +872,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ska_low_share")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_kahan", "fp64"])
+    ap.add_argument("--workload", default="ska_low_precision",
+                    help="ska_low_precision (418.6M visibilities, 8192^2 x 128 planes; the default) or "
+                         "ska_low_share (209.3M, 4096^2 x 64), tiny, ska_low_small")
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp32_kahan", "fp64"],
+                    help="default: fp32_kahan for ska_low_precision, fp32 otherwise")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--unfused", action="store_true",
                     help="column FFT and w-screen as separate kernels (F_k written to HBM)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check-pixels", type=int, default=6,
-                    help="pixels of the timed image checked against the float64 oracle (0 = skip)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the image check (oracle and direct sum at sampled pixels, float64 GPU image)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
     ap.add_argument("--profile", metavar="OUT",
@@ -795,6 +902,8 @@ def main():
     ap.add_argument("--predict", action="store_true",
                     help="prediction (degridding) of the workload's visibilities from a point-source model image")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = "fp32_kahan" if args.workload == "ska_low_precision" else "fp32"
     if args.profile:
         run_profiles(os.path.abspath(args.profile), args.workload)
         return
@@ -894,35 +1003,75 @@ def main():
     if roofline["traffic"] is not None:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / dbytes, 3)
 
+    img_host = img.double().cpu().numpy()
+    plan.close()
+    del plan, img, vis
+    torch.cuda.empty_cache()
+
+    # ---- checks and the CPU baseline (after the timed region) ----
+    from oracle import wstack as ow
+    N = ds.grid_n
+    corr = ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param), N)
     check = None
     vis_host = None
-    if args.check_pixels > 0 or not args.no_cpu_baseline:
+    if not args.no_check or not args.no_cpu_baseline:
         vis_host = ds.vis.cpu().numpy()
-    if args.check_pixels > 0:
-        import oracle.pixels
-        rng = np.random.default_rng(0)
-        N = ds.grid_n
-        pp = np.r_[N // 2, rng.integers(N // 4, 3 * N // 4, args.check_pixels - 1)]
-        qq = np.r_[N // 2, rng.integers(N // 4, 3 * N // 4, args.check_pixels - 1)]
-        t0 = time.time()
-        ref, _, kept, sw = oracle.pixels.wstack_pixels(ds.uvw, ds.freq, vis_host, ds.weight, pp, qq,
-                                                       **ds.plan_kwargs())
-        got = img.double().cpu().numpy()[qq, pp]
-        from oracle import wstack as ow
-        corr = ow.grid_correction(ow.tap_table(ds.support, ds.oversample, ds.kernel, ds.kernel_param), N)
-        c2 = corr[pp] * corr[qq]
-        err = float(np.linalg.norm((got - ref) * c2) / np.linalg.norm(ref * c2))
-        check = {"pixels": int(len(pp)), "apparent_rel_rms": err, "n_gridded": info["n_gridded"],
-                 "oracle_kept": kept, "seconds": round(time.time() - t0, 1)}
-        print(f"[bench] sampled-pixel check: apparent-image rel-RMS = {err:.2e} ({time.time() - t0:.1f} s)",
-              file=sys.stderr, flush=True)
+    if not args.no_check:
+        check = {"n_gridded": info["n_gridded"]}
+        if args.precision != "fp64":
+            # the same image in the all-float64 mode of the library (unfused: its
+            # fused form needs a second mesh-sized buffer), whole-image errors
+            t0 = time.time()
+            p64 = rick.Plan.for_dataset(ds, precision="fp64", fused=False)
+            i64 = torch.empty((N, N), dtype=torch.float64, device=dev)
+            v64 = ds.vis.to(torch.complex128)
+            p64.reset(stream)
+            p64.grid(uvw, v64, wt, ds.freq, stream)
+            p64.fft(stream)
+            p64.image(i64, stream)
+            torch.cuda.synchronize()
+            ref = i64.cpu().numpy()
+            p64.close()
+            del p64, i64, v64
+            torch.cuda.empty_cache()
+            c2 = np.outer(corr, corr)
+            d = img_host - ref
+            central = c2 >= 0.1
+            check["vs_fp64_gpu"] = {
+                "apparent_rel_rms": float(np.linalg.norm(d * c2) / np.linalg.norm(ref * c2)),
+                "central_rel_rms": float(np.linalg.norm(d[central]) / np.linalg.norm(ref[central])),
+                "image_rel_rms": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                "seconds": round(time.time() - t0, 1)}
+            del ref, d, c2
+            print(f"[bench] vs float64 GPU image: {check['vs_fp64_gpu']}", file=sys.stderr, flush=True)
+        pp, qq = check_pixels(ds)
+        check.update(oracle_leg(ds, vis_host, img_host[qq, pp], pp, qq, corr))
+        check["tolerances"] = {"gpu_vs_oracle_apparent": TOL_ORACLE, "dft_gate": TOL_DFT,
+                               "vs_fp64_gpu_apparent": TOL_ORACLE}
+        ok = check["gpu_vs_oracle"]["apparent_rel_rms"] <= TOL_ORACLE
+        if "dft_gate" in check:
+            ok = ok and check["dft_gate"] <= TOL_DFT
+        if "vs_fp64_gpu" in check:
+            ok = ok and check["vs_fp64_gpu"]["apparent_rel_rms"] <= TOL_ORACLE
+        check["pass"] = bool(ok)
+        print(f"[bench] check: gpu vs oracle {check['gpu_vs_oracle']}, gpu vs dft {check.get('gpu_vs_dft')}, "
+              f"oracle vs dft {check.get('oracle_vs_dft')}, pass={ok}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
+        nthr = host_threads()
         t0 = time.time()
-        cpu = cpu_baseline(ds, vis_host)
-        print(f"[bench] cpu baseline {cpu['value']:.3f} Mvis/s ({time.time() - t0:.1f} s)", file=sys.stderr,
-              flush=True)
+        one = cpu_baseline(ds, vis_host, 1)
+        print(f"[bench] cpu baseline, 1 thread: {one['value']:.3f} Mvis/s ({time.time() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+        cpu = one
+        if nthr > 1:
+            t0 = time.time()
+            cpu = cpu_baseline(ds, vis_host, nthr)
+            print(f"[bench] cpu baseline, {nthr} threads: {cpu['value']:.3f} Mvis/s ({time.time() - t0:.1f} s)",
+                  file=sys.stderr, flush=True)
+            cpu["single_thread"] = {k: one[k] for k in ("value", "sample_seconds", "est_seconds_per_image")}
+        cpu["cpu_model"] = cpu_model()
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1, "steps": args.steps,
@@ -938,7 +1087,9 @@ def main():
         "check": check,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
+    if check is not None and not check["pass"]:
+        print("[bench] image check failed: the throughput above is not valid", file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

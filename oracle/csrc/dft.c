@@ -13,7 +13,9 @@
  * check).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 void oracle_dft(int64_t nvis, const double *u, const double *v, const double *w,
                 const double *are, const double *aim,
@@ -35,5 +37,64 @@ void oracle_dft(int64_t nvis, const double *u, const double *v, const double *w,
         }
         out_re[p] = sr;
         out_im[p] = si;
+    }
+}
+
+/* The same direct sum for visibilities laid out [row][channel] with equally
+ * spaced channels, uvw in metres.  Visibility (r, c) sits at
+ * (u, v, w) = uvw_r * s_c in wavelengths, s_c = s0 + c ds, so its phase at
+ * direction (l, m, nm1) is phi_r s_c with phi_r = uvw_r . (l, m, nm1), and
+ *     exp(+2 pi i phi_r s_c) = exp(+2 pi i phi_r s0) * exp(+2 pi i phi_r ds)^c,
+ * a geometric progression over the channels of a row (two trigonometric
+ * calls per row instead of one per visibility; the rounding it adds grows by
+ * about one ulp per channel).  A_rc = W_rc V_rc with V complex64 and W
+ * float32 (NULL = 1).  Rows are shared out over OpenMP threads in contiguous
+ * ranges; each thread keeps its own partial sum of every pixel and the
+ * partial sums are added in thread order.
+ */
+void oracle_dft_rows(int64_t nrow, int32_t nchan, const double *uvw, double s0, double ds,
+                     const float *vis, const float *weight,
+                     int64_t npix, const double *l, const double *m, const double *nm1,
+                     double *out_re, double *out_im)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t p = 0; p < npix; ++p) out_re[p] = out_im[p] = 0.0;
+    #pragma omp parallel
+    {
+        double *acc = (double *)calloc((size_t)(2 * npix), sizeof(double));
+        #pragma omp for schedule(static)
+        for (int64_t r = 0; r < nrow; ++r) {
+            const double *x = uvw + 3 * r;
+            for (int64_t p = 0; p < npix; ++p) {
+                const double phi = x[0] * l[p] + x[1] * m[p] + x[2] * nm1[p];
+                double t0 = phi * s0, td = phi * ds;
+                t0 -= rint(t0);
+                td -= rint(td);
+                const double dr = cos(two_pi * td), di = sin(two_pi * td);
+                double zr = cos(two_pi * t0), zi = sin(two_pi * t0);
+                double sr = 0.0, si = 0.0;
+                for (int32_t c = 0; c < nchan; ++c) {
+                    const int64_t j = r * nchan + c;
+                    const double wt = weight ? (double)weight[j] : 1.0;
+                    const double ar = wt * (double)vis[2 * j], ai = wt * (double)vis[2 * j + 1];
+                    sr += ar * zr - ai * zi;
+                    si += ar * zi + ai * zr;
+                    const double nr = zr * dr - zi * di;
+                    zi = zr * di + zi * dr;
+                    zr = nr;
+                }
+                acc[2 * p] += sr;
+                acc[2 * p + 1] += si;
+            }
+        }
+        #pragma omp for ordered schedule(static, 1)
+        for (int t = 0; t < omp_get_num_threads(); ++t) {
+            #pragma omp ordered
+            for (int64_t p = 0; p < npix; ++p) {
+                out_re[p] += acc[2 * p];
+                out_im[p] += acc[2 * p + 1];
+            }
+        }
+        free(acc);
     }
 }

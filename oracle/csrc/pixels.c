@@ -40,12 +40,31 @@ int64_t oracle_wstack_pixels(
         cs[2 * j] = cos(two_pi * (double)j / (double)N);
         cs[2 * j + 1] = sin(two_pi * (double)j / (double)N);
     }
+    /* X_j(p) depends on the pixel column only and Y_j(q) on the row only:
+     * they are evaluated once per distinct column and row of the requested
+     * pixels (ux[], uy[]), and each pixel multiplies its pair. */
+    int32_t *col_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)(npix > 0 ? npix : 1));
+    int32_t *row_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)(npix > 0 ? npix : 1));
+    int64_t *ux = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npix > 0 ? npix : 1));
+    int64_t *uy = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npix > 0 ? npix : 1));
+    int64_t nux = 0, nuy = 0;
+    for (int64_t ip = 0; ip < npix; ++ip) {
+        int64_t a = 0, b = 0;
+        while (a < nux && ux[a] != pix_p[ip]) ++a;
+        if (a == nux) ux[nux++] = pix_p[ip];
+        while (b < nuy && uy[b] != pix_q[ip]) ++b;
+        if (b == nuy) uy[nuy++] = pix_q[ip];
+        col_of[ip] = (int32_t)a;
+        row_of[ip] = (int32_t)b;
+    }
     memset(acc, 0, sizeof(double) * 2 * npix * nw);
     int64_t kept_total = 0;
     double sumw_total = 0.0;
     #pragma omp parallel
     {
         double *lacc = (double *)calloc((size_t)(2 * npix * nw), sizeof(double));
+        double *X = (double *)malloc(sizeof(double) * 2 * (size_t)(nux > 0 ? nux : 1));
+        double *Y = (double *)malloc(sizeof(double) * 2 * (size_t)(nuy > 0 ? nuy : 1));
         int64_t kept = 0;
         double sumw = 0.0;
         #pragma omp for schedule(static)
@@ -60,15 +79,33 @@ int64_t oracle_wstack_pixels(
                 const double ar = o.ar, ai = o.ai;
                 const double *gx = table + (sx + OS / 2) * support;
                 const double *gy = table + (sy + OS / 2) * support;
-                for (int64_t ip = 0; ip < npix; ++ip) {
-                    const int64_t pp = pix_p[ip] - N / 2, qq = pix_q[ip] - N / 2;
-                    double xr = 0, xi = 0, yr = 0, yi = 0;
+                /* residue of (cell - N/2) * (pixel - N/2) modulo N, tap by tap:
+                 * the first tap's residue exactly, then + (pixel - N/2) per tap */
+                for (int64_t a = 0; a < nux; ++a) {
+                    const int64_t pp = ux[a] - N / 2;
+                    const int64_t step = ((pp % N) + N) % N;
+                    int64_t jx = ((cx - h - N / 2) * pp) % N; if (jx < 0) jx += N;
+                    double xr = 0, xi = 0;
                     for (int64_t t = 0; t < support; ++t) {
-                        int64_t jx = ((cx + t - h - N / 2) * pp) % N; if (jx < 0) jx += N;
-                        int64_t jy = ((cy + t - h - N / 2) * qq) % N; if (jy < 0) jy += N;
                         xr += gx[t] * cs[2 * jx]; xi += gx[t] * cs[2 * jx + 1];
-                        yr += gy[t] * cs[2 * jy]; yi += gy[t] * cs[2 * jy + 1];
+                        jx += step; if (jx >= N) jx -= N;
                     }
+                    X[2 * a] = xr; X[2 * a + 1] = xi;
+                }
+                for (int64_t b = 0; b < nuy; ++b) {
+                    const int64_t qq = uy[b] - N / 2;
+                    const int64_t step = ((qq % N) + N) % N;
+                    int64_t jy = ((cy - h - N / 2) * qq) % N; if (jy < 0) jy += N;
+                    double yr = 0, yi = 0;
+                    for (int64_t t = 0; t < support; ++t) {
+                        yr += gy[t] * cs[2 * jy]; yi += gy[t] * cs[2 * jy + 1];
+                        jy += step; if (jy >= N) jy -= N;
+                    }
+                    Y[2 * b] = yr; Y[2 * b + 1] = yi;
+                }
+                for (int64_t ip = 0; ip < npix; ++ip) {
+                    const double xr = X[2 * col_of[ip]], xi = X[2 * col_of[ip] + 1];
+                    const double yr = Y[2 * row_of[ip]], yi = Y[2 * row_of[ip] + 1];
                     const double er = xr * yr - xi * yi, ei = xr * yi + xi * yr;
                     double *dst = lacc + 2 * (ip * nw + k);
                     dst[0] += ar * er - ai * ei;
@@ -83,7 +120,13 @@ int64_t oracle_wstack_pixels(
             sumw_total += sumw;
         }
         free(lacc);
+        free(X);
+        free(Y);
     }
+    free(col_of);
+    free(row_of);
+    free(ux);
+    free(uy);
     free(cs);
     *sum_w_out = sumw_total;
     return kept_total;

@@ -97,3 +97,45 @@ def dft_of_binned(b, fov: float, grid_n: int, **kw) -> np.ndarray:
     """Direct-DFT image over the visibilities that binning kept."""
     idx = np.nonzero(b.keep)[0]
     return dft_image(b.u[idx], b.v[idx], b.w[idx], b.wv[idx], float(b.wt[idx].sum()), fov, grid_n, **kw)
+
+
+def dft_pixels_rows(uvw_m, freq_hz, vis, weight, pix_p, pix_q, *, grid_n: int, fov: float,
+                    sum_w: float) -> np.ndarray:
+    """Dirty-image values by the direct sum at chosen pixels (p, q), for
+    visibilities laid out [row][channel] with equally spaced channels and uvw
+    in metres (``csrc/dft.c``, ``oracle_dft_rows``: the channel phases of a
+    row advance as a geometric progression).  ``sum_w`` is the weight sum of
+    the visibilities summed; every visibility given is summed, so the caller
+    passes only workloads where the imager keeps them all.  Returns
+    n Re(D) / sum_w per pixel; pixels with l^2 + m^2 >= 1 give 0."""
+    from .wstack import pixel_lm, nm1_of, C0
+    uvw = np.ascontiguousarray(uvw_m, dtype=np.float64)
+    nrow = uvw.shape[0]
+    s = np.asarray(freq_hz, dtype=np.float64) / C0
+    nchan = s.shape[0]
+    s0 = float(s[0])
+    ds = float(s[1] - s[0]) if nchan > 1 else 0.0
+    if nchan > 2 and np.max(np.abs(s - (s0 + np.arange(nchan) * ds))) > 1e-12 * np.max(np.abs(s)):
+        raise ValueError("channels are not equally spaced")
+    visf = np.ascontiguousarray(np.asarray(vis).reshape(nrow, nchan), dtype=np.complex64).view(np.float32)
+    wt = None if weight is None else np.ascontiguousarray(weight, dtype=np.float32).reshape(nrow, nchan)
+    lm = pixel_lm(grid_n, fov)
+    L = np.ascontiguousarray(lm[np.asarray(pix_p)], dtype=np.float64)
+    M = np.ascontiguousarray(lm[np.asarray(pix_q)], dtype=np.float64)
+    nm1 = nm1_of(L, M)
+    inside = np.isfinite(nm1)
+    nm1z = np.ascontiguousarray(np.where(inside, nm1, 0.0))
+    out_re = np.empty(L.shape[0])
+    out_im = np.empty(L.shape[0])
+    fp = ctypes.POINTER(ctypes.c_float)
+    L_ = lib()
+    L_.oracle_dft_rows.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_double, ctypes.c_double, fp, fp, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+    L_.oracle_dft_rows.restype = None
+    L_.oracle_dft_rows(nrow, nchan, _p(uvw), s0, ds, visf.ctypes.data_as(fp),
+                       None if wt is None else wt.ctypes.data_as(fp), L.shape[0], _p(L), _p(M), _p(nm1z),
+                       _p(out_re), _p(out_im))
+    return np.where(inside, (1.0 + nm1z) * out_re / sum_w, 0.0)

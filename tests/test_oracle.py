@@ -471,3 +471,28 @@ def test_off_centre_large_w_source_recovered_by_dft_and_wstacking():
                         w_min=w_min, w_max=w_max)
     assert r.binned.keep.all()
     assert abs(r.image[q, p] - S) < 1e-9
+
+
+def test_dft_channel_progression_equals_plain_sum():
+    """The row-and-channel form of the direct sum (channel phases advanced as a
+    geometric progression) equals the plain per-visibility sum of Eq. 1 over
+    the same samples, with weights, at pixels all over the field."""
+    rng = np.random.default_rng(43)
+    nrow, nchan, N, fov = 3000, 24, 128, 0.5
+    uvw = np.stack([rng.normal(0, 900, nrow), rng.normal(0, 900, nrow), rng.normal(0, 200, nrow)], 1)
+    freq = 140e6 + np.arange(nchan) * 0.625e6
+    vis = (rng.normal(size=(nrow, nchan)) + 1j * rng.normal(size=(nrow, nchan))).astype(np.complex64)
+    wt = rng.uniform(0.2, 2.0, (nrow, nchan)).astype(np.float32)
+    pp = rng.integers(0, N, 40)
+    qq = rng.integers(0, N, 40)
+    got = od.dft_pixels_rows(uvw, freq, vis, wt, pp, qq, grid_n=N, fov=fov, sum_w=float(wt.sum(dtype=np.float64)))
+    sc = freq / ow.C0
+    u = (uvw[:, 0:1] * sc[None, :]).ravel()
+    v = (uvw[:, 1:2] * sc[None, :]).ravel()
+    w = (uvw[:, 2:3] * sc[None, :]).ravel()
+    lm = ow.pixel_lm(N, fov)
+    L, M = lm[pp], lm[qq]
+    nm1 = ow.nm1_of(L, M)
+    D = od.dft_sum(u, v, w, (wt.astype(np.float64) * vis.astype(np.complex128)).ravel(), L, M, nm1)
+    want = (1 + nm1) * D.real / float(wt.sum(dtype=np.float64))
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
