@@ -103,7 +103,9 @@ typedef struct rick_plan_desc {
     double w_min, w_max;   /* w range in wavelengths covered by the planes; w_max > w_min.  Plane k
                               spans [w_min + k dw, w_min + (k+1) dw), dw = (w_max - w_min) / N_w, with
                               centre w_k; w outside the range goes to the nearest end plane. */
-    int64_t max_vis;       /* largest nrow * nchan one rick_grid call accepts; 1..2^29 */
+    int64_t max_vis;       /* largest nrow * nchan one rick_grid call accepts; 0..2^29.  0: the plan
+                              allocates no per-visibility sort buffers and grids only through
+                              rick_grid_static */
     int32_t device;        /* HIP device ordinal */
     int32_t flags;         /* RICK_FLAG_* */
     int32_t tile;          /* uv tile edge T in cells for binning and gridding: 0 = default (64), else a
@@ -182,6 +184,34 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out);
  */
 rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
                       const float *weight, int64_t nrow, int32_t nchan, void *stream);
+
+/*
+ * rick_grid_static -- rick_grid for callers that cannot allocate device
+ * memory (work recorded into a graph, tight serving loops, hosts that forbid
+ * hipMalloc).  Same arguments, result and errors as rick_grid, but the
+ * buffers of bin-and-sort that grow with the number of visibilities (level-1
+ * and gridding records, chunk tables, work items) live in the library's
+ * static device scratch of RICK_STATIC_SCRATCH_BYTES (256 MiB) per device,
+ * allocated when the library's device code is loaded and held until the
+ * process ends, instead of in the plan; the plan's max_vis does not apply
+ * (a plan made with max_vis = 0 holds no such buffers).  This call allocates
+ * nothing, host or device.
+ *   - nrow * nchan is limited by the scratch: about 9.5 M visibilities in
+ *     FP32 modes and 6 M in FP64 (28 and 44 bytes per visibility plus
+ *     per-chunk tables); a larger call returns RICK_E_CAPACITY before any
+ *     device work.
+ *   - Every call on one device shares that device's scratch, and the scratch
+ *     keeps the last call's contents (nothing in it needs to start at zero).
+ *     Calls whose device work overlaps on one device -- on different streams,
+ *     from different threads, or on different plans -- race on the scratch
+ *     and give wrong results: order them on one stream or synchronise between
+ *     them.  rick_grid is unaffected (its buffers are the plan's).
+ * Errors: as rick_grid, and RICK_E_HIP if the scratch's address could not be
+ * taken on this device.
+ */
+#define RICK_STATIC_SCRATCH_BYTES (256ull << 20)
+rick_status rick_grid_static(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                             const float *weight, int64_t nrow, int32_t nchan, void *stream);
 
 /*
  * rick_fft_planes -- in place, every plane becomes its centred inverse DFT

@@ -43,6 +43,12 @@
 #include "rick_internal.h"
 #include "quant.h"
 
+// Scratch of rick_grid_static: sort buffers of one call, carved per call.
+// Each device holds its own copy at its own address; host code never uses
+// the array's name as a device address, only the address that
+// hipGetSymbolAddress returns on that device (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[rick::kStaticScratchBytes];
+
 namespace rick {
 
 namespace {
@@ -771,6 +777,39 @@ static L1Part l1_part(int64_t nvis) {
     nb = (nvis + per - 1) / per;
     if (nb < 1) nb = 1;
     return L1Part{(int32_t)nb, (int32_t)per};
+}
+
+namespace {
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+std::once_flag g_scratch_once[kMaxDevices];
+}  // namespace
+
+hipError_t static_scratch_setup() {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *ptr = nullptr;
+        const hipError_t r = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[dev] = r;
+        g_scratch_ptr[dev] = r == hipSuccess ? ptr : nullptr;
+    });
+    return g_scratch_err[dev];
+}
+
+hipError_t static_scratch(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    e = static_scratch_setup();
+    if (e != hipSuccess) return e;
+    *out = g_scratch_ptr[device];
+    return *out ? hipSuccess : hipErrorInvalidSymbol;
 }
 
 int32_t bin_max_chunks(const Geom &g, int64_t max_records) {

@@ -178,8 +178,8 @@ rick_status validate(const rick_plan_desc *d) {
         return fail(RICK_E_INVALID_ARG, "fov_rad=%g: need 0 < fov and fov^2/2 < 1", d->fov_rad);
     if (!std::isfinite(d->w_min) || !std::isfinite(d->w_max) || !(d->w_max > d->w_min))
         return fail(RICK_E_INVALID_ARG, "w range [%g, %g]: need finite w_min < w_max", d->w_min, d->w_max);
-    if (d->max_vis < 1 || d->max_vis >= (int64_t(1) << 29))
-        return fail(RICK_E_INVALID_ARG, "max_vis=%lld: must be in [1, 2^29)", (long long)d->max_vis);
+    if (d->max_vis < 0 || d->max_vis >= (int64_t(1) << 29))
+        return fail(RICK_E_INVALID_ARG, "max_vis=%lld: must be in [0, 2^29)", (long long)d->max_vis);
     if (d->device < 0) return fail(RICK_E_INVALID_ARG, "device=%d", d->device);
     if (d->flags & ~int32_t(RICK_FLAG_TIMING | RICK_FLAG_FUSED_SCREEN))
         return fail(RICK_E_INVALID_ARG, "flags=%d: unknown bits", d->flags);
@@ -358,6 +358,10 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
 
     // ---- device allocation, once ----
     DeviceGuard guard(d->device);
+    // address of the library's static scratch on this device, taken once per
+    // device; a failure is kept and reported by rick_grid_static, the only
+    // call that uses the scratch
+    (void)static_scratch_setup();
     const size_t rb = p->real_bytes;
     p->mesh_bytes = size_t(g.Nw) * g.N * g.N * 2 * rb;
     const size_t sz_lut = size_t(g.OS) * g.W * rb;
@@ -395,7 +399,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     }
 #define ALLOC(ptr, bytes)                                        \
     do {                                                         \
-        e = hipMalloc((void **)&(ptr), (bytes));                 \
+        e = hipMalloc((void **)&(ptr), (bytes) > 256 ? (bytes) : 256); \
         if (e != hipSuccess) {                                   \
             free_all(p);                                         \
             delete p;                                            \
@@ -512,8 +516,13 @@ rick_status rick_reset(rick_plan_t *p, void *stream) {
     return RICK_OK;
 }
 
-rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
-                      const float *weight, int64_t nrow, int32_t nchan, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by rick_grid and rick_grid_static (before any device work).
+rick_status check_grid_args(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                            const float *weight, int64_t nrow, int32_t nchan) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
     if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
     if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
@@ -522,32 +531,41 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     if (nrow > 0 && (!uvw || !vis)) return fail(RICK_E_INVALID_ARG, "uvw or vis is NULL");
     if (((uintptr_t)uvw & 7) || ((uintptr_t)vis & (p->fp64 ? 15 : 7)) || ((uintptr_t)weight & 3))
         return fail(RICK_E_INVALID_ARG, "misaligned input pointer");
-    if (nrow * int64_t(nchan) > p->d.max_vis)
-        return fail(RICK_E_CAPACITY, "nrow*nchan=%lld > max_vis=%lld", (long long)(nrow * nchan),
-                    (long long)p->d.max_vis);
+    if (nrow > (int64_t(1) << 40) / nchan) return fail(RICK_E_CAPACITY, "nrow*nchan too large");
     if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed; call rick_reset first");
     if (p->state == 3) return fail(RICK_E_STATE, "mesh holds predicted planes; call rick_reset first");
-    std::vector<double> sc(nchan, 1.0);
     if (freq_hz) {
-        for (int c = 0; c < nchan; ++c) {
+        for (int c = 0; c < nchan; ++c)
             if (!std::isfinite(freq_hz[c]) || !(freq_hz[c] > 0.0))
                 return fail(RICK_E_INVALID_ARG, "freq_hz[%d]=%g", c, freq_hz[c]);
-            sc[c] = freq_hz[c] / kC0;
-        }
     }
-    DeviceGuard guard(p->d.device);
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_set_scales(p->scales, sc.data(), nchan, s);
+    return RICK_OK;
+}
+
+// Channel scales nu_c / c0 into the plan's device buffer, in batches of
+// kMaxInlineChan passed as kernel arguments (no host or device allocation).
+hipError_t upload_scales(rick_plan_t *p, const double *freq_hz, int32_t nchan, hipStream_t s) {
+    double sc[kMaxInlineChan];
+    for (int32_t c0 = 0; c0 < nchan; c0 += kMaxInlineChan) {
+        const int32_t n = nchan - c0 < kMaxInlineChan ? nchan - c0 : kMaxInlineChan;
+        for (int32_t j = 0; j < n; ++j) sc[j] = freq_hz ? freq_hz[c0 + j] / kC0 : 1.0;
+        const hipError_t e = launch_set_scales(p->scales + c0, sc, n, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Bin-and-sort, gridding and margin merge of one call, with the sort buffers in bb.
+rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, const double *freq_hz, const void *vis,
+                      const float *weight, int64_t nrow, int32_t nchan, hipStream_t s) {
+    hipError_t e = upload_scales(p, freq_hz, nchan, s);
     if (e != hipSuccess) return hip_fail(e, "channel scales upload");
     const Geom &g = p->g;
     const int64_t nvis = nrow * nchan;
-    // work items: one per chunk of a non-empty bin; at most 4 records per visibility
+    // work items: one per chunk of a non-empty bin (one record per visibility)
     const int64_t max_records = nvis;
     const int32_t max_items =
         int32_t((max_records < g.nbins ? max_records : g.nbins) + (max_records + g.CH - 1) / g.CH + 1);
-
-    const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2, p->vmax2,
-                     p->counts,   p->bin_vmax,   p->scan,    p->item_bin,   p->heavy_bins, p->rec_pos, p->rec_vis};
     struct Pass {
         int slot;
         const char *name;
@@ -571,31 +589,112 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
     }
     timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
     if (p->fp64)
-        e = launch_zero_heavy<double>(g, p->heavy_bins, p->stats, p->tile_bits, (double *)p->mesh,
+        e = launch_zero_heavy<double>(g, bb.heavy_bins, p->stats, p->tile_bits, (double *)p->mesh,
                                       (double *)p->margin, s);
     else
-        e = launch_zero_heavy<float>(g, p->heavy_bins, p->stats, p->tile_bits, (float *)p->mesh, (float *)p->margin,
+        e = launch_zero_heavy<float>(g, bb.heavy_bins, p->stats, p->tile_bits, (float *)p->mesh, (float *)p->margin,
                                      s);
     timer_end(p, T_ZERO_HEAVY, s);
     if (e != hipSuccess) return hip_fail(e, "zero_heavy");
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
-        e = launch_grid<double>(g, p->scan, p->item_bin, p->rec_pos, (const double *)p->rec_vis, (const double *)p->lut,
-                                (double *)p->mesh, p->tile_bits, (double *)p->margin, p->bin_vmax, max_items, s);
+        e = launch_grid<double>(g, bb.scan, bb.item_bin, bb.rec_pos, (const double *)bb.rec_vis,
+                                (const double *)p->lut, (double *)p->mesh, p->tile_bits, (double *)p->margin,
+                                bb.bin_vmax, max_items, s);
     else
-        e = launch_grid<float>(g, p->scan, p->item_bin, p->rec_pos, (const float *)p->rec_vis, (const float *)p->lut,
-                               (float *)p->mesh, p->tile_bits, (float *)p->margin, p->bin_vmax, max_items, s);
+        e = launch_grid<float>(g, bb.scan, bb.item_bin, bb.rec_pos, (const float *)bb.rec_vis, (const float *)p->lut,
+                               (float *)p->mesh, p->tile_bits, (float *)p->margin, bb.bin_vmax, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
     timer_begin(p, T_MARK, "merge_margins", s);
-    e = p->fp64 ? launch_merge_margins<double>(g, p->scan, (const double *)p->margin, p->tile_bits, p->row_bits,
+    e = p->fp64 ? launch_merge_margins<double>(g, bb.scan, (const double *)p->margin, p->tile_bits, p->row_bits,
                                                (double *)p->mesh, s)
-                : launch_merge_margins<float>(g, p->scan, (const float *)p->margin, p->tile_bits, p->row_bits,
+                : launch_merge_margins<float>(g, bb.scan, (const float *)p->margin, p->tile_bits, p->row_bits,
                                               (float *)p->mesh, s);
     timer_end(p, T_MARK, s);
     if (e != hipSuccess) return hip_fail(e, "merge_margins");
     p->state = 1;
     return RICK_OK;
+}
+
+// Byte offsets, in the static scratch, of the per-visibility sort buffers of
+// one rick_grid_static call of nvis visibilities (each 256-byte aligned).
+struct StaticLayout {
+    size_t rec1, chunk_key, cnt2, vmax2, item_bin, heavy, rec_pos, rec_vis, total;
+};
+StaticLayout static_layout(const Geom &g, size_t rb, int64_t nvis) {
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t chunks = size_t(bin_max_chunks(g, nvis));
+    const size_t items = size_t((nvis < g.nbins ? nvis : g.nbins) + (nvis + g.CH - 1) / g.CH + 2);
+    StaticLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += up(bytes > 0 ? bytes : 1);
+        return at;
+    };
+    L.rec1 = take(size_t(nvis) * (8 + 2 * rb));
+    L.chunk_key = take(chunks * sizeof(int32_t));
+    L.cnt2 = take(chunks * g.C * g.C * sizeof(int32_t));
+    L.vmax2 = take(chunks * g.C * g.C * sizeof(uint32_t));
+    L.item_bin = take(items * sizeof(int32_t));
+    L.heavy = take((size_t(nvis) / (g.CH + 1) + 2) * sizeof(int32_t));
+    L.rec_pos = take(size_t(nvis) * sizeof(uint32_t));
+    L.rec_vis = take(size_t(nvis) * 2 * rb);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                      const float *weight, int64_t nrow, int32_t nchan, void *stream) {
+    const rick_status st = check_grid_args(p, uvw, freq_hz, vis, weight, nrow, nchan);
+    if (st != RICK_OK) return st;
+    if (nrow * int64_t(nchan) > p->d.max_vis)
+        return fail(RICK_E_CAPACITY, "nrow*nchan=%lld > max_vis=%lld", (long long)(nrow * nchan),
+                    (long long)p->d.max_vis);
+    DeviceGuard guard(p->d.device);
+    const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2, p->vmax2,
+                     p->counts,   p->bin_vmax,   p->scan,    p->item_bin,   p->heavy_bins, p->rec_pos, p->rec_vis};
+    return grid_impl(p, bb, uvw, freq_hz, vis, weight, nrow, nchan, (hipStream_t)stream);
+}
+
+rick_status rick_grid_static(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                             const float *weight, int64_t nrow, int32_t nchan, void *stream) {
+    const rick_status st = check_grid_args(p, uvw, freq_hz, vis, weight, nrow, nchan);
+    if (st != RICK_OK) return st;
+    const int64_t nvis = nrow * int64_t(nchan);
+    const StaticLayout L = static_layout(p->g, p->real_bytes, nvis);
+    if (L.total > kStaticScratchBytes)
+        return fail(RICK_E_CAPACITY,
+                    "nrow*nchan=%lld needs %zu B of sort scratch; the static scratch holds %zu B "
+                    "(use rick_grid with a plan's max_vis for larger calls)",
+                    (long long)nvis, L.total, kStaticScratchBytes);
+    DeviceGuard guard(p->d.device);
+    void *base = nullptr;
+    const hipError_t e = static_scratch(p->d.device, &base);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    unsigned char *b = static_cast<unsigned char *>(base);
+    // per-bin tables stay the plan's (sized by the mesh shape at rick_plan);
+    // the buffers that grow with the number of visibilities come from the scratch
+    const BinBufs bb{p->cnt1,
+                     p->block_sums,
+                     b + L.rec1,
+                     p->key_chunk0,
+                     reinterpret_cast<int32_t *>(b + L.chunk_key),
+                     reinterpret_cast<int32_t *>(b + L.cnt2),
+                     reinterpret_cast<uint32_t *>(b + L.vmax2),
+                     p->counts,
+                     p->bin_vmax,
+                     p->scan,
+                     reinterpret_cast<int32_t *>(b + L.item_bin),
+                     reinterpret_cast<int32_t *>(b + L.heavy),
+                     reinterpret_cast<uint32_t *>(b + L.rec_pos),
+                     b + L.rec_vis};
+    return grid_impl(p, bb, uvw, freq_hz, vis, weight, nrow, nchan, (hipStream_t)stream);
 }
 
 rick_status rick_fft_planes(rick_plan_t *p, void *stream) {

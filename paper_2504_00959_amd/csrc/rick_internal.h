@@ -165,6 +165,14 @@ hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Sta
 template <typename real>
 hipError_t launch_merge_margins(const Geom &g, const BinScan *scan, const real *margin, uint64_t *tile_bits,
                                 uint64_t *row_bits, real *mesh, hipStream_t s);
+// The library's static device scratch (rick_grid_static): kStaticScratchBytes
+// per device, in a file-scope __device__ array.  static_scratch_setup takes
+// its address on the current device, once per device (plan creation calls
+// it); static_scratch returns that address for `device`, or an error when
+// the setup failed or never ran there.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+hipError_t static_scratch_setup();
+hipError_t static_scratch(int device, void **out);
 // Device clock value (constant rate) into *slot once the stream's preceding work is done.
 hipError_t launch_stamp(uint64_t *slot, hipStream_t s);
 // Clear both occupancy bitmaps (a fill kernel; no memset node in captured work).

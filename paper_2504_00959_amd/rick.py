@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
     P = ctypes.c_void_p
     L.rick_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]
     L.rick_grid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
+    L.rick_grid_static.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
     L.rick_fft_planes.argtypes = [P, P]
     L.rick_wstack_image.argtypes = [P, P, P]
     L.rick_reset.argtypes = [P, P]
@@ -117,7 +118,7 @@ def lib() -> ctypes.CDLL:
     L.rick_autotune.argtypes = [ctypes.POINTER(PlanDesc), P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64,
                                 ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_float)]
-    for f in ("rick_plan", "rick_grid", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
+    for f in ("rick_plan", "rick_grid", "rick_grid_static", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
               "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid",
@@ -207,9 +208,12 @@ class Plan:
             raise ValueError(f"{name} must be contiguous")
         return t
 
-    def grid(self, uvw, vis, weight=None, freq: Optional[Sequence[float]] = None, stream=None):
+    def grid(self, uvw, vis, weight=None, freq: Optional[Sequence[float]] = None, stream=None,
+             static_scratch: bool = False):
         """Bin-and-sort + grid.  uvw float64 [R,3] (metres if freq given, else wavelengths),
-        vis complex [R,C], weight float32 [R,C] or None, freq host sequence [C] in Hz or None."""
+        vis complex [R,C], weight float32 [R,C] or None, freq host sequence [C] in Hz or None.
+        static_scratch: call rick_grid_static (sort buffers in the library's static
+        device scratch; nothing allocated) instead of rick_grid."""
         import torch
         self._device_tensor(uvw, "uvw", torch.float64)
         self._device_tensor(vis, "vis", self.complex_dtype)
@@ -234,8 +238,8 @@ class Plan:
                 raise ValueError("freq must have nchan entries")
             self._freq_keep = f
             fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        _check(lib().rick_grid(self._h, uvw.data_ptr(), fptr, vis.data_ptr(), wptr, nrow, nchan,
-                               _stream_handle(stream)), "rick_grid")
+        fn, name = (lib().rick_grid_static, "rick_grid_static") if static_scratch else (lib().rick_grid, "rick_grid")
+        _check(fn(self._h, uvw.data_ptr(), fptr, vis.data_ptr(), wptr, nrow, nchan, _stream_handle(stream)), name)
 
     def fft(self, stream=None):
         _check(lib().rick_fft_planes(self._h, _stream_handle(stream)), "rick_fft_planes")

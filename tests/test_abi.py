@@ -36,7 +36,7 @@ def _plan_status(**over):
 @pytest.mark.parametrize("over", [
     dict(grid_n=100), dict(grid_n=32), dict(grid_n=16384), dict(n_wplanes=0), dict(support=4),
     dict(support=17), dict(oversample=3), dict(oversample=512), dict(fov=0.0), dict(fov=1.5),
-    dict(w_min=1.0, w_max=1.0), dict(w_min=float("nan")), dict(max_vis=0), dict(max_vis=1 << 29),
+    dict(w_min=1.0, w_max=1.0), dict(w_min=float("nan")), dict(max_vis=-1), dict(max_vis=1 << 29),
     dict(tile=48), dict(tile=8), dict(tile=128), dict(tile=256),
     dict(device=-1), dict(kernel_param=float("inf")), dict(chunk=-1),
 ])
