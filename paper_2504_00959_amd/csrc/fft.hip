@@ -511,6 +511,17 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         }
     }
     for (int k = 0; k < g.Nw; ++k) {
+        // at N >= 8192 the lane indices and the twiddle pointer are laundered
+        // per plane, so that the compiler recomputes addresses and reloads
+        // twiddles (L1 hits) instead of keeping every stage's values live
+        // across the plane loop: kept live they spill (36 registers with the
+        // compensated sum), which took 47.6 ms instead of 42.7 for 128 planes
+        // of 8192^2; at N <= 4096 they fit and keeping them is faster
+        // (2.50 ms against 2.88 for 64 planes of 4096^2)
+        const C *twk = tw;
+        int tid = (int)threadIdx.x;
+        if (N >= 8192) __asm__ volatile("" : "+s"(twk), "+v"(tid));
+        const int vg = tid % (V / VC), tb = tid / (V / VC), v0 = vg * VC;
         C x[16][VC];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -532,7 +543,7 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         // the LDS strip is reused plane after plane: every thread must have
         // read the previous plane's last exchange before this plane's first
         __syncthreads();
-        fft_regs<N, V, VC>(x, buf, tb, v0, tw);
+        fft_regs<N, V, VC>(x, buf, tb, v0, twk);
         const double w2 = 2.0 * plane_centre(g, k);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
