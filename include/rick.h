@@ -73,7 +73,11 @@ enum {
     RICK_E_UNSUPPORTED = 8    /* valid but not built (e.g. a grid size without an FFT kernel) */
 };
 
-enum { RICK_KERNEL_GAUSSIAN = 0, RICK_KERNEL_KAISER_BESSEL = 1 };
+enum {
+    RICK_KERNEL_GAUSSIAN = 0,
+    RICK_KERNEL_KAISER_BESSEL = 1,
+    RICK_KERNEL_USER_LUT = 2   /* a non-separable table T[lut_wbins][OS][OS][W][W] installed with rick_plan_set_lut */
+};
 
 enum {
     RICK_PREC_FP32 = 0,        /* float mesh, FFT and plane sum; float64 phase argument and normalisation */
@@ -91,7 +95,7 @@ enum {
 
 /* Plan parameters (Sec. 2.1: mesh N_u x N_v x N_w, kernel type and support). */
 typedef struct rick_plan_desc {
-    int32_t grid_n;        /* N = N_u = N_v: power of two, 64..8192 */
+    int32_t grid_n;        /* N = N_u = N_v: power of two, 64..16384 (16384: without RICK_FLAG_FUSED_SCREEN) */
     int32_t n_wplanes;     /* N_w >= 1 */
     int32_t support;       /* kernel support W in cells: odd, 1..15 */
     int32_t oversample;    /* OS sub-cell positions per cell: power of two, 1..256 */
@@ -111,6 +115,8 @@ typedef struct rick_plan_desc {
     int32_t tile;          /* uv tile edge T in cells for binning and gridding: 0 = default (64), else a
                               power of two 16..64 with T >= W */
     int32_t chunk;         /* largest number of binned records one gridding block takes: 0 = default */
+    int32_t lut_wbins;     /* RICK_KERNEL_USER_LUT: w-fraction bins N_f of the table, 1, 2, 4 or 8 (ignored
+                              otherwise) */
 } rick_plan_desc;
 
 typedef struct rick_plan_s rick_plan_t;   /* opaque plan handle */
@@ -150,6 +156,11 @@ typedef struct rick_plan_info_t {
                                 launches since the previous rick_plan_info (the last 64 at most) */
     int32_t kernel_calls[16];/* launches the mean covers */
     const char *kernel_names[16];
+    const double *w_k;       /* HOST [N_w]: plane centres w_k = w_min + (k + 1/2) dw, owned by the plan */
+    const double *taper;     /* device: the taper the image is divided by, C(l') [N] for a separable kernel
+                                (pixel (q, p) divided by C[p] C[q]), or [N][N] for a user table */
+    int32_t lut_wbins;       /* w-fraction bins of the installed user table (0 for a separable kernel) */
+    int32_t pad2;
 } rick_plan_info_t;
 
 /*
@@ -411,6 +422,93 @@ rick_status rick_autotune(const rick_plan_desc *d, const double *uvw, const doub
                           int32_t *chunk, float *ms);
 
 /* Static message for a status code (never NULL). */
+/*
+ * Learned gridding kernel.  The paper convolves with a Gaussian or
+ * Kaiser-Bessel kernel (Sec. 2.1, Eq. 3); these calls let a kernel be learned
+ * instead and used through a plan with kernel = RICK_KERNEL_USER_LUT:
+ *   - the kernel is a table T[iw][s_y + OS/2][s_x + OS/2][t_y][t_x] (float32,
+ *     row-major) of the tap at cell offset (t_x - h - s_x / OS, t_y - h - s_y / OS)
+ *     for a visibility whose w-fraction bin is iw: with r = (w - w_min) / dw and
+ *     plane k = clamp(floor(r), 0, N_w - 1), iw = clamp(floor((r - k) N_f), 0, N_f - 1);
+ *   - the image is divided by the table's 2-D taper C(l', m') = (1 / (N_f OS^2))
+ *     sum over every entry of T cos(2 pi (dx l' + dy m')), computed on the device
+ *     when the table is installed.
+ * A 3 -> 32 -> 32 -> 1 MLP (tanh after both hidden layers, linear output)
+ * tabulates such a table, K = exp(mlp(dx / (W/2), dy / (W/2), f_iw)) inside
+ * |dx|, |dy| < W/2 (0 outside), f_iw = (iw + 1/2) / N_f - 1/2, each
+ * (iw, s_y, s_x) row normalised to sum 1.  Its RICK_MLP_PARAMS float32
+ * parameters are packed W1 [32][3], b1 [32], W2 [32][32], b2 [32], w3 [32], b3.
+ * Training against the direct Fourier sum (Eq. 1) chains rick_image_loss,
+ * rick_table_gradient (the adjoint of the imaging steps: a degridding of the
+ * loss gradient) and rick_mlp_backward, then rick_adam_step.
+ */
+#define RICK_MLP_PARAMS 1217
+
+/* rick_plan_set_lut -- install the table (host or device float32, N_f OS^2 W^2
+ * values, every entry finite) into a RICK_KERNEL_USER_LUT plan and compute its
+ * taper; a host table is copied before the call returns, a device table is
+ * read on `stream`.  The plan grids with it from then on.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_STATE (not a user-table plan),
+ * RICK_E_INVALID_ARG (NULL, misaligned, non-finite host entry), RICK_E_HIP. */
+rick_status rick_plan_set_lut(rick_plan_t *p, const float *table, int32_t on_device, void *stream);
+
+/* rick_mlp_tabulate -- table [n_wbins][OS][OS][W][W] (device float32) of the MLP
+ * with parameters theta (device float32 [RICK_MLP_PARAMS]), on the current
+ * device.  Errors: RICK_E_INVALID_ARG (shape as in rick_plan_desc, NULL,
+ * misaligned), RICK_E_HIP. */
+rick_status rick_mlp_tabulate(const float *theta, int32_t support, int32_t oversample, int32_t n_wbins,
+                              float *table, void *stream);
+
+/* rick_mlp_backward -- dtheta (device float32 [RICK_MLP_PARAMS], overwritten) =
+ * gradient of sum(dtable T) with respect to theta, T the table rick_mlp_tabulate
+ * made from theta (device, same shape) and dtable device float64 of that shape
+ * (through the row normalisation, exp and the MLP).  Errors as rick_mlp_tabulate. */
+rick_status rick_mlp_backward(const float *theta, int32_t support, int32_t oversample, int32_t n_wbins,
+                              const float *table, const double *dtable, float *dtheta, void *stream);
+
+/* rick_adam_step -- one Adam update (Kingma & Ba 2015, Algorithm 1: bias-corrected
+ * moments, theta -= lr m_hat / (sqrt(v_hat) + eps)) of theta [n] with gradient
+ * grad and moment buffers m, v (device float32, m and v zero before step 1);
+ * step counts from 1.  Errors: RICK_E_INVALID_ARG, RICK_E_HIP. */
+rick_status rick_adam_step(float *theta, const float *grad, float *m, float *v, int32_t n, int32_t step, float lr,
+                           float beta1, float beta2, float eps, void *stream);
+
+/* rick_image_loss -- for the plan's image I (device [N][N], plan's real type) and
+ * a target D (device float64 [N][N], the direct sum): sums[0] = sum_Omega (I - D)^2,
+ * sums[1] = sum_Omega D^2 over Omega = {|q - N/2| < N/4, |p - N/2| < N/4} (the loss
+ * is sums[0] / sums[1]); dimage = dL/dA for the apparent image A = I C and
+ * dtaper = dL/dC (device float64 [N][N], zero outside Omega), C the plan's taper.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG, RICK_E_HIP. */
+rick_status rick_image_loss(rick_plan_t *p, const void *image, const double *target, double *dimage,
+                            double *dtaper, double *sums, void *stream);
+
+/* rick_table_gradient -- dtable (device float64, N_f OS^2 W^2, overwritten) =
+ * dL/dT for a RICK_KERNEL_USER_LUT plan that has just gridded (rick_grid) and
+ * transformed (rick_fft_planes) exactly these visibilities, given dimage and
+ * dtaper from rick_image_loss: the planes dA n exp(-2 pi i w_k (n - 1)) / sum W
+ * go through the centred forward transform (the adjoint of imaging, as in
+ * prediction), each visibility adds Re(dL/dG_k[cell] conj(W V)) to the entries
+ * its taps read, and the taper's dependence on T is added.  The mesh is used
+ * as scratch: the plan needs rick_reset afterwards.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_STATE (not a user-table plan, or its planes
+ * not transformed), RICK_E_INVALID_ARG, RICK_E_HIP. */
+rick_status rick_table_gradient(rick_plan_t *p, const double *dimage, const double *dtaper, const double *uvw,
+                                const double *freq_hz, const void *vis, const float *weight, int64_t nrow,
+                                int32_t nchan, double *dtable, void *stream);
+
+/* rick_dft_image -- the direct Fourier sum (Eq. 1 over the measured samples)
+ * at the pixels q0 <= q < q0 + nq, p0 <= p < p0 + np of the plan's image:
+ *   out[q - q0][p - p0] = n Re(sum W V exp(+2 pi i (u l_p + v m_q + w (n - 1)))) / sum W
+ * over the visibilities the plan keeps (its drop rule; inputs as rick_grid),
+ * exact (unquantised) u, v, w; phase and sums in float64, sin and cos of the
+ * phase reduced to half a turn in float32 (about 2.5e-7 per term).  out:
+ * device float64 [nq][np]; at most 65535 * 16384 visibilities per call.  The
+ * plan's state is unchanged.  Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG,
+ * RICK_E_CAPACITY, RICK_E_HIP. */
+rick_status rick_dft_image(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                           const float *weight, int64_t nrow, int32_t nchan, int32_t q0, int32_t p0, int32_t nq,
+                           int32_t np, double *out, void *stream);
+
 const char *rick_status_str(rick_status s);
 
 /* Detail of the last failing call on this host thread (static storage, never NULL). */

@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librick.so")
-SOURCES = ["plan.cpp", "binsort.hip", "grid.hip", "fft.hip", "wscreen.hip", "degrid.hip"]
+SOURCES = ["plan.cpp", "binsort.hip", "grid.hip", "fft.hip", "wscreen.hip", "degrid.hip", "learned.hip"]
 ARCH = os.environ.get("RICK_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

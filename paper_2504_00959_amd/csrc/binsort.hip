@@ -79,6 +79,7 @@ struct Rec1<real, true> {
 // indices s + OS/2 in [0, OS) (sx, sy).
 struct Pos1 {
     int32_t ox1, oy1, sx, sy;
+    int32_t iw;   // w-fraction bin (full format only; 0 otherwise)
 };
 __device__ __forceinline__ int32_t coarse_shift(const Geom &g) { return g.log2C + g.log2T; }
 
@@ -100,9 +101,10 @@ __global__ void k_set_scales(double *__restrict__ dst, ChanScales cs, int32_t n)
 template <typename real>
 __device__ __forceinline__ Rec1<real, false> make_rec1(const Geom &g, const Quant &q, real ar, real ai,
                                                       Rec1<real, false> *) {
+    // plane in bits 16..28 (< 8192 planes), w-fraction bin in bits 29..31
     return Rec1<real, false>{(uint32_t)q.cx | (uint32_t)q.cy << 16,
                              (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
-                                 (uint32_t)q.k << 16,
+                                 (uint32_t)q.k << 16 | (uint32_t)q.iw << 29,
                              ar, ai};
 }
 template <typename real>
@@ -118,14 +120,14 @@ __device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, false> &r
     const int32_t lb = coarse_shift(g);
     const int32_t cx = (int32_t)(r.cxy & 0xffffu), cy = (int32_t)(r.cxy >> 16);
     return Pos1{cx - g.h - (ctx << lb), cy - g.h - (cty << lb), (int32_t)(r.sub & 0xffu),
-                (int32_t)((r.sub >> 8) & 0xffu)};
+                (int32_t)((r.sub >> 8) & 0xffu), (int32_t)(r.sub >> 29)};
 }
 template <typename real>
 __device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, true> &r, int32_t, int32_t) {
     const int32_t lb = coarse_shift(g), sb = g.log2OS;
     const uint32_t ml = (1u << lb) - 1, ms = (1u << sb) - 1;
     return Pos1{(int32_t)(r.pos & ml), (int32_t)((r.pos >> (lb + sb)) & ml), (int32_t)((r.pos >> lb) & ms),
-                (int32_t)(r.pos >> (2 * lb + sb))};
+                (int32_t)(r.pos >> (2 * lb + sb)), 0};
 }
 
 // Tile of edge 2^shift cells holding the footprint origin (c - h) of cell (cx, cy).
@@ -617,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
         for (int j = 0; j < kSubPer; ++j) {
             const int32_t r = r0 + j * kBlock + (int32_t)threadIdx.x;
             const bool valid = r < ck.r1;
-            Pos1 ps{0, 0, 0, 0};
+            Pos1 ps{0, 0, 0, 0, 0};
             vr[j] = 0;
             vi[j] = 0;
             if (valid) {
@@ -634,7 +636,10 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
             slot[j] = valid ? __shfl(b0, run.leader) + ((int32_t)__lane_id() - run.leader) : -1;
             tile[j] = f;
             const uint32_t ox = (uint32_t)(ps.ox1 & (g.T - 1)), oy = (uint32_t)(ps.oy1 & (g.T - 1));   // in the tile
-            pos[j] = ox | oy << 8 | (uint32_t)ps.sx << 16 | (uint32_t)ps.sy << 24;
+            // tile offsets take 6 bits (T <= 64); bits 6-7 and 14 carry the
+            // w-fraction bin of a non-separable table
+            const uint32_t iw = (uint32_t)ps.iw;
+            pos[j] = ox | (iw & 3u) << 6 | oy << 8 | (iw >> 2) << 14 | (uint32_t)ps.sx << 16 | (uint32_t)ps.sy << 24;
         }
         __syncthreads();   // every slot of the sub-chunk is taken
         // placement: tile f's records go to [base_f, base_f + n_f) in slot order,

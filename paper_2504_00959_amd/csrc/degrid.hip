@@ -280,6 +280,13 @@ hipError_t degrid_sorted_w(const Geom &g, const uint64_t *keys, const uint64_t *
 
 }  // namespace
 
+hipError_t launch_fill_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s) {
+    const int64_t words = (int64_t)g.Nw * (g.nt + 1) * g.occw;
+    const unsigned fb = (unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_bits, dim3(fb), dim3(256), 0, s, g, tile_bits, row_bits);
+    return hipGetLastError();
+}
+
 template <typename real>
 hipError_t launch_predict_screen(const Geom &g, const real *model, const double *corr, real *mesh,
                                  uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s) {

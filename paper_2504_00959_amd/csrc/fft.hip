@@ -427,23 +427,12 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols(real *__restri
 
 // Re(exp(+i pi t2) f) (-1)^flip for a phase t2 in float64 half turns.
 // t2 = q + g with q the nearest integer, so exp(+i pi t2) = (-1)^q exp(+i pi g),
-// |g| <= 1/2.  float32: sin(pi g) = g P(g^2), cos(pi g) = Q(g^2), minimax
-// polynomials fitted on [-1/2, 1/2] (Horner form, float32 fma; abs error
-// below 2.5e-7).  float64: sincospi of the float64 remainder.
+// |g| <= 1/2.  float32: sincospi_half (rick_internal.h).  float64: sincospi
+// of the float64 remainder.
 __device__ __forceinline__ float screen_term(double t2, float2 f, int flip) {
     const double qd = rint(t2);
-    const float g = (float)(t2 - qd);
-    const float g2 = g * g;
-    float ps = fmaf(g2, 0.07805382838216549f, -0.5985074114168937f);
-    ps = fmaf(g2, ps, 2.5501159030870695f);
-    ps = fmaf(g2, ps, -5.167712346356822f);
-    ps = fmaf(g2, ps, 3.141592653446274f);
-    const float sn = g * ps;
-    float pc = fmaf(g2, -0.02468992584886284f, 0.23511454480404714f);
-    pc = fmaf(g2, pc, -1.3352479005812146f);
-    pc = fmaf(g2, pc, 4.05871189644457f);
-    pc = fmaf(g2, pc, -4.934802200064621f);
-    pc = fmaf(g2, pc, 1.0f);
+    float sn, pc;
+    sincospi_half((float)(t2 - qd), sn, pc);
     const float t = fmaf(pc, f.x, -sn * f.y);
     return (((int)qd ^ flip) & 1) ? -t : t;
 }
@@ -573,7 +562,7 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
             const bool in_sky = l * l + m * m < 1.0;
             const double nm1 = s_nm1[e * V + v0 + v];
             const double val =
-                (sw > 0.0 && in_sky) ? (1.0 + nm1) * (double)acc[q][v] / (corr[p] * corr[e] * sw) : 0.0;
+                (sw > 0.0 && in_sky) ? (1.0 + nm1) * (double)acc[q][v] / (taper_at(g, corr, e, p) * sw) : 0.0;
             image[(int64_t)e * N + p] = (real)val;
         }
     }
@@ -587,7 +576,8 @@ struct ColShape {
     static constexpr int VRAW = (8192 * 8 / (int)sizeof(C)) / N;
     static constexpr int V = VRAW < 1 ? 1 : (VRAW > 16 ? 16 : VRAW);
     static constexpr int NT = N / 16;
-    static constexpr int VC = (NT * V > 512) ? (NT * V) / 512 : 1;   // at most 512 threads
+    static constexpr int VC0 = (NT * V > 512) ? (NT * V) / 512 : 1;   // at most 512 threads
+    static constexpr int VC = VC0 < V ? VC0 : V;                       // (N = 16384: 1024 threads, V = VC = 1)
     static constexpr int THREADS = NT * (V / VC);
 };
 
@@ -692,7 +682,9 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
 
 }  // namespace
 
-bool fft_supported(int N) { return N >= 64 && N <= 8192 && (N & (N - 1)) == 0; }
+bool fft_supported(int N, size_t real_bytes) {
+    return (N & (N - 1)) == 0 && N >= 64 && (N <= 8192 || (N == 16384 && real_bytes == 4));
+}
 
 size_t fused_screen_lds_bytes(int N, size_t real_bytes) {
     const int cbytes = (int)(2 * real_bytes);
@@ -709,6 +701,9 @@ hipError_t launch_fft_rows(const Geom &g, real *mesh, const real *tw, const uint
     case n: return rows_n<real, n>(g, mesh, tw, tile_bits, row_bits, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
+        case 16384:   // float32 only: a float64 row does not fit in LDS
+            if constexpr (sizeof(real) == 4) return rows_n<real, 16384>(g, mesh, tw, tile_bits, row_bits, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -742,6 +737,9 @@ hipError_t launch_fft_cols(const Geom &g, real *mesh, const real *tw, hipStream_
     case n: return cols_n<real, n, 0>(g, mesh, tw, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
+        case 16384:
+            if constexpr (sizeof(real) == 4) return cols_n<real, 16384, 0>(g, mesh, tw, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -145,14 +145,19 @@ __device__ __forceinline__ unsigned long long fixed_of(double t) {
     return (unsigned long long)(uint32_t)(__double2hiint(t) - 0x43380000) << 32 | (uint32_t)__double2loint(t);
 }
 
-template <typename real, int W, int TT>
+// L3: the taps come from a non-separable table in device memory,
+// T[iw][s_y][s_x][t_y][t_x] (w-fraction bin iw in bits 6-7 and 14 of the
+// packed position), one value per tap instead of the product of two
+// separable rows held in LDS; tapmax points at the table's largest |value|.
+template <typename real, int W, int TT, bool L3>
 __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan *__restrict__ scan,
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
                                                      real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
                                                      real *__restrict__ margin,
-                                                     const uint32_t *__restrict__ bin_vmax) {
+                                                     const uint32_t *__restrict__ bin_vmax,
+                                                     const float *__restrict__ tapmax) {
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int H = (W - 1) / 2;
@@ -185,7 +190,9 @@ __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan
     double scale = 1.0, unscale = 1.0;
     if (FIX) {
         const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
-        const double bt = vmax * (double)g.gmax2;                      // largest |term|
+        // largest |term|: |W V| times the largest |tap| (the square of the
+        // largest separable row value, or the largest entry of the table)
+        const double bt = vmax * (L3 ? (double)*tapmax * (1.0 + 1e-6) : (double)g.gmax2);
         if (bt > 0.0 && bt < 1e300) {
             const int et = ilogb(bt) + 1, en = ilogb((double)n) + 1;   // bt < 2^et, n < 2^en
             const int sh = min(50 - et, 61 - et - en);
@@ -210,7 +217,8 @@ __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan
         acc_re[i] = 0;
         acc_im[i] = 0;
     }
-    for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
+    if (!L3)
+        for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
     __syncthreads();
 
     const int lane = __lane_id();
@@ -224,8 +232,10 @@ __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan
         const bool on = t < W2;
         const int ty = on ? t / W : 0, tx = on ? t - (t / W) * W : 0;
         tap_off8[gi] = (ty * P + tx) * (int)sizeof(double);
+        // L3: lut_y holds the tap's index in a table row (lanes past the
+        // footprint read the row's last tap; their values go unused)
         lut_x[gi] = lut_byte + tx * (int)sizeof(real);
-        lut_y[gi] = lut_byte + ty * (int)sizeof(real);
+        lut_y[gi] = L3 ? (on ? t : W2 - 1) : lut_byte + ty * (int)sizeof(real);
     }
 
     // this wave's batches of 64 records, one record per lane; the next
@@ -251,10 +261,17 @@ __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan
         int32_t d_base8 = 0, d_lxy = 0;
         double d_vr = 0, d_vi = 0;   // W V (times 2^s in float32 mode; exact)
         if (lane < cnt) {
-            const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
             const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
-            d_base8 = (oy * P + ox) * (int)sizeof(double);
-            d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
+            if constexpr (L3) {
+                const int ox = (int)(raw_pos & 0x3fu), oy = (int)((raw_pos >> 8) & 0x3fu);   // in [0, T)
+                const int iw = (int)((raw_pos >> 6) & 3u) | (int)((raw_pos >> 14) & 1u) << 2;
+                d_base8 = (oy * P + ox) * (int)sizeof(double);
+                d_lxy = ((iw * g.OS + sy) * g.OS + sx) * W2;   // first entry of the record's table row
+            } else {
+                const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
+                d_base8 = (oy * P + ox) * (int)sizeof(double);
+                d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
+            }
             d_vr = (double)raw_vr * scale;
             d_vi = (double)raw_vi * scale;
         }
@@ -267,11 +284,19 @@ __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 const int32_t lxy = bcast(d_lxy, (j + q) & 63);
-                const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
+                if constexpr (L3) {
 #pragma unroll
-                for (int gi = 0; gi < NG; ++gi) {
-                    gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
-                    gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
+                    for (int gi = 0; gi < NG; ++gi) {
+                        gy[q][gi] = lut[lxy + lut_y[gi]];
+                        gx[q][gi] = (real)1;
+                    }
+                } else {
+                    const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
+#pragma unroll
+                    for (int gi = 0; gi < NG; ++gi) {
+                        gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
+                        gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
+                    }
                 }
             }
         };
@@ -482,35 +507,46 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
     }
 }
 
-template <typename real, int W, int TT>
+template <typename real, int W, int TT, bool L3>
 hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                   const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
+                   const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static std::once_flag attr_once[kMaxDevices];
     once_per_device(attr_once, [&] {
-        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT, L3>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(160 * 1024));
     });
-    hipLaunchKernelGGL((k_grid<real, W, TT>), dim3(max_items), dim3(grid_threads(TT)), lds, s, g, scan, item_bin,
-                       rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax);
+    hipLaunchKernelGGL((k_grid<real, W, TT, L3>), dim3(max_items), dim3(grid_threads(TT)), lds, s, g, scan, item_bin,
+                       rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, tapmax);
     return hipGetLastError();
+}
+
+template <typename real, int W, int TT>
+hipError_t grid_wt2(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
+                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
+                    const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
+    if (tapmax)
+        return grid_wt<real, W, TT, true>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                          tapmax, max_items, s);
+    return grid_wt<real, W, TT, false>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                       tapmax, max_items, s);
 }
 
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                  const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
+                  const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
     switch (g.T) {
         case 16:
-            return grid_wt<real, W, 16>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                        max_items, s);
+            return grid_wt2<real, W, 16>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                         tapmax, max_items, s);
         case 32:
-            return grid_wt<real, W, 32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                        max_items, s);
+            return grid_wt2<real, W, 32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                         tapmax, max_items, s);
         case 64:
-            return grid_wt<real, W, 64>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                        max_items, s);
+            return grid_wt2<real, W, 64>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                         tapmax, max_items, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -561,12 +597,12 @@ hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_b
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const uint32_t *bin_vmax, int32_t max_items, hipStream_t s) {
+                       const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
     case w: \
         return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
-                               max_items, s);
+                               tapmax, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -585,9 +621,9 @@ template hipError_t launch_merge_margins<double>(const Geom &, const BinScan *, 
                                                  uint64_t *, double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                        const float *, const float *, float *, const uint64_t *, float *,
-                                       const uint32_t *, int32_t, hipStream_t);
+                                       const uint32_t *, const float *, int32_t, hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                         const double *, const double *, double *, const uint64_t *, double *,
-                                        const uint32_t *, int32_t, hipStream_t);
+                                        const uint32_t *, const float *, int32_t, hipStream_t);
 
 }  // namespace rick

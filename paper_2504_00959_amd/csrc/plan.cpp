@@ -118,6 +118,16 @@ struct rick_plan_s {
     uint32_t *rec_pos = nullptr;
     void *rec_vis = nullptr;
     int64_t rec_cap = 0;
+    // non-separable table (RICK_KERNEL_USER_LUT): lut holds T[N_f][OS][OS][W][W],
+    // corr2 its 2-D taper [N][N], tapmax its largest |entry|
+    bool lut3 = false;
+    bool lut_ready = false;
+    size_t lut_bytes = 0;
+    float *tapmax = nullptr;
+    double *corr2 = nullptr;
+    TaperBufs taper_bufs{};
+    double *dft_wsum = nullptr;   // weight sum of the last rick_dft_image
+    std::vector<double> w_k_host;
     // host copies of tables (for tests and info)
     std::vector<double> lut_host, corr_host;
     // timing: per kernel slot a ring of (start, stop) event pairs
@@ -131,6 +141,10 @@ struct rick_plan_s {
 namespace {
 
 bool plan_ok(const rick_plan_t *p) { return p != nullptr && p->magic == kMagic; }
+
+// The image-plane taper the screens divide by: the 1-D taper of the
+// separable kernel, or the 2-D taper [N][N] of a user table.
+const double *taper_of(const rick_plan_t *p) { return p->lut3 ? p->corr2 : p->corr; }
 
 struct DeviceGuard {
     int prev = -1;
@@ -150,7 +164,7 @@ void free_all(rick_plan_t *p) {
                     p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->vmax2,    p->bin_vmax, p->item_bin, p->heavy_bins,
-                    p->rec_pos,   p->rec_vis};
+                    p->rec_pos,   p->rec_vis,   p->dft_wsum,  p->tapmax,    p->corr2,     p->taper_bufs.A};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < kMaxTimers; ++i)
@@ -160,16 +174,19 @@ void free_all(rick_plan_t *p) {
 
 rick_status validate(const rick_plan_desc *d) {
     if (!d) return fail(RICK_E_INVALID_ARG, "desc is NULL");
-    if (!is_pow2(d->grid_n) || d->grid_n < 64 || d->grid_n > 8192)
-        return fail(RICK_E_INVALID_ARG, "grid_n=%d: must be a power of two in [64, 8192]", d->grid_n);
+    if (!is_pow2(d->grid_n) || d->grid_n < 64 || d->grid_n > 16384)
+        return fail(RICK_E_INVALID_ARG, "grid_n=%d: must be a power of two in [64, 16384]", d->grid_n);
     if (d->n_wplanes < 1 || d->n_wplanes > kMaxPlanes)
         return fail(RICK_E_INVALID_ARG, "n_wplanes=%d: must be in [1, %d]", d->n_wplanes, kMaxPlanes);
     if (d->support < 1 || d->support > 15 || (d->support & 1) == 0)
         return fail(RICK_E_INVALID_ARG, "support=%d: must be odd in [1, 15]", d->support);
     if (!is_pow2(d->oversample) || d->oversample > 256)
         return fail(RICK_E_INVALID_ARG, "oversample=%d: must be a power of two in [1, 256]", d->oversample);
-    if (d->kernel != RICK_KERNEL_GAUSSIAN && d->kernel != RICK_KERNEL_KAISER_BESSEL)
+    if (d->kernel != RICK_KERNEL_GAUSSIAN && d->kernel != RICK_KERNEL_KAISER_BESSEL &&
+        d->kernel != RICK_KERNEL_USER_LUT)
         return fail(RICK_E_INVALID_ARG, "kernel=%d: unknown", d->kernel);
+    if (d->kernel == RICK_KERNEL_USER_LUT && (!is_pow2(d->lut_wbins) || d->lut_wbins > 8))
+        return fail(RICK_E_INVALID_ARG, "lut_wbins=%d: must be 1, 2, 4 or 8 with RICK_KERNEL_USER_LUT", d->lut_wbins);
     if (d->precision < RICK_PREC_FP32 || d->precision > RICK_PREC_FP64)
         return fail(RICK_E_INVALID_ARG, "precision=%d: unknown", d->precision);
     if (!std::isfinite(d->kernel_param))
@@ -237,7 +254,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     *out = nullptr;
     rick_status st = validate(d);
     if (st != RICK_OK) return st;
-    if (!fft_supported(d->grid_n)) return fail(RICK_E_UNSUPPORTED, "no FFT kernel for N=%d", d->grid_n);
+    if (!fft_supported(d->grid_n, d->precision == RICK_PREC_FP64 ? 8 : 4))
+        return fail(RICK_E_UNSUPPORTED, "no FFT kernel for N=%d in this precision", d->grid_n);
     if ((d->flags & RICK_FLAG_FUSED_SCREEN) &&
         fused_screen_lds_bytes(d->grid_n, d->precision == RICK_PREC_FP64 ? 8 : 4) > size_t(160) * 1024)
         return fail(RICK_E_UNSUPPORTED, "fused screen: a column strip of N=%d does not fit in LDS", d->grid_n);
@@ -307,8 +325,13 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
                         g.T, g.W, g.OS, lds);
         }
     }
+    // a non-separable table: the w-fraction bin rides in spare bits of the
+    // full-format level-1 records and of the gridding records
+    p->lut3 = d->kernel == RICK_KERNEL_USER_LUT;
+    g.lut3 = p->lut3 ? 1 : 0;
+    g.nwf = p->lut3 ? d->lut_wbins : 1;
     // compact level-1 records: origin in the coarse tile and sub-cell in one word
-    g.cpt1 = (!p->fp64 && 2 * (g.log2C + g.log2T + g.log2OS) <= 32) ? 1 : 0;
+    g.cpt1 = (!p->fp64 && !p->lut3 && 2 * (g.log2C + g.log2T + g.log2OS) <= 32) ? 1 : 0;
     g.fov = d->fov_rad;
     g.half = double(int64_t(g.N) * g.OS) / 2.0;
     g.w_min = d->w_min;
@@ -319,8 +342,11 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     p->max_items = g.nbins + (p->rec_cap + g.CH - 1) / g.CH;
 
     // ---- float64 tables on the host ----
-    const double param = d->kernel_param > 0 ? d->kernel_param : default_param(g.W, d->kernel);
-    if (!(param > 0.0) && d->kernel == RICK_KERNEL_GAUSSIAN) {
+    // (a plan with a user table keeps a Gaussian separable table here, which
+    // no kernel of that plan reads: its taps and taper come with the table)
+    const int kind = p->lut3 ? RICK_KERNEL_GAUSSIAN : d->kernel;
+    const double param = (d->kernel_param > 0 && !p->lut3) ? d->kernel_param : default_param(g.W, kind);
+    if (!(param > 0.0) && kind == RICK_KERNEL_GAUSSIAN) {
         delete p;
         return fail(RICK_E_INVALID_ARG, "Gaussian width must be positive");
     }
@@ -330,7 +356,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         double sum = 0.0;
         for (int t = 0; t < g.W; ++t) {
             const double dist = double(t - g.h) - double(s) / g.OS;
-            p->lut_host[size_t(r) * g.W + t] = kernel_at(dist, g.W, d->kernel, param);
+            p->lut_host[size_t(r) * g.W + t] = kernel_at(dist, g.W, kind, param);
             sum += p->lut_host[size_t(r) * g.W + t];
         }
         for (int t = 0; t < g.W; ++t) p->lut_host[size_t(r) * g.W + t] /= sum;
@@ -364,7 +390,11 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     (void)static_scratch_setup();
     const size_t rb = p->real_bytes;
     p->mesh_bytes = size_t(g.Nw) * g.N * g.N * 2 * rb;
-    const size_t sz_lut = size_t(g.OS) * g.W * rb;
+    const size_t sz_lut = p->lut3 ? size_t(g.nwf) * g.OS * g.OS * g.W * g.W * rb : size_t(g.OS) * g.W * rb;
+    const size_t taper_m = size_t(g.OS) * g.W;
+    const size_t sz_taper = p->lut3 ? (taper_m * taper_m + 4 * taper_m * g.N) * sizeof(double) : 0;
+    const size_t sz_corr2 = p->lut3 ? size_t(g.N) * g.N * sizeof(double) : 0;
+    p->lut_bytes = sz_lut;
     const size_t sz_tw = size_t(g.N) * 2 * rb;
     const size_t sz_counts = size_t(g.nbins + 1) * sizeof(int32_t);
     const size_t sz_items = size_t(p->max_items + 1) * sizeof(int32_t);
@@ -385,7 +415,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_rbits = size_t(g.Nw) * g.occw * sizeof(uint64_t);
     const size_t sz_tbits = sz_rbits * g.nt;
     const size_t sz_margin = size_t(g.nbins) * size_t(grid_margin_len(g)) * 2 * rb + 64;
-    const size_t total = p->mesh_bytes * (p->fused ? 2 : 1) + sz_lut + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
+    const size_t total = p->mesh_bytes * (p->fused ? 2 : 1) + sz_lut + sz_taper + sz_corr2 + sz_tw + size_t(g.N) * 8 + size_t(g.Nw) * 8 +
                          size_t(kMaxChan) * 8 + sizeof(Stats) + sz_counts + sz_scan + sz_bsum + sz_cnt1 + sz_rec1 + sz_kc0 + sz_ckey + 2 * sz_cnt2 + sz_counts + sz_items + sz_heavy + sz_pos + sz_rvis + sz_tbits + sz_rbits + sz_margin;
     size_t free_b = 0, total_b = 0;
     hipError_t e = hipMemGetInfo(&free_b, &total_b);
@@ -434,6 +464,18 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->heavy_bins, sz_heavy);
     ALLOC(p->rec_pos, sz_pos);
     ALLOC(p->rec_vis, sz_rvis);
+    ALLOC(p->dft_wsum, sizeof(double));
+    if (p->lut3) {
+        ALLOC(p->tapmax, sizeof(float));
+        ALLOC(p->corr2, sz_corr2);
+        double *tb = nullptr;
+        ALLOC(tb, sz_taper);
+        p->taper_bufs.A = tb;
+        p->taper_bufs.Ec = tb + taper_m * taper_m;
+        p->taper_bufs.Es = p->taper_bufs.Ec + taper_m * g.N;
+        p->taper_bufs.Uc = p->taper_bufs.Es + taper_m * g.N;
+        p->taper_bufs.Us = p->taper_bufs.Uc + taper_m * g.N;
+    }
 #undef ALLOC
 
     // tables: tap LUT and twiddles rounded to the plan's real type
@@ -444,9 +486,10 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         tw[2 * i] = (double)std::cos(a);
         tw[2 * i + 1] = (double)std::sin(a);
     }
-    std::vector<char> lut_dev(sz_lut), tw_dev(sz_tw);
+    const size_t sz_lut_sep = size_t(g.OS) * g.W * rb;   // the separable table's bytes
+    std::vector<char> lut_dev(sz_lut_sep), tw_dev(sz_tw);
     if (p->fp64) {
-        std::memcpy(lut_dev.data(), p->lut_host.data(), sz_lut);
+        std::memcpy(lut_dev.data(), p->lut_host.data(), sz_lut_sep);
         std::memcpy(tw_dev.data(), tw.data(), sz_tw);
     } else {
         float *lf = reinterpret_cast<float *>(lut_dev.data());
@@ -455,11 +498,12 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         for (size_t i = 0; i < tw.size(); ++i) tf[i] = float(tw[i]);
     }
     struct Cp { void *dst; const void *src; size_t n; } cps[] = {
-        {p->lut, lut_dev.data(), sz_lut},
         {p->twiddle, tw_dev.data(), sz_tw},
         {p->corr, p->corr_host.data(), size_t(g.N) * 8},
+        {p->lut, lut_dev.data(), sz_lut_sep},   // (a user table arrives with rick_plan_set_lut)
     };
     for (auto &c : cps) {
+        if (c.dst == p->lut && p->lut3) continue;
         e = hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             free_all(p);
@@ -520,9 +564,9 @@ rick_status rick_reset(rick_plan_t *p, void *stream) {
 
 namespace {
 
-// Argument checks shared by rick_grid and rick_grid_static (before any device work).
-rick_status check_grid_args(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
-                            const float *weight, int64_t nrow, int32_t nchan) {
+// Checks of a call's visibility arguments (before any device work).
+rick_status check_vis_args(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                           const float *weight, int64_t nrow, int32_t nchan) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
     if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
     if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
@@ -532,13 +576,22 @@ rick_status check_grid_args(rick_plan_t *p, const double *uvw, const double *fre
     if (((uintptr_t)uvw & 7) || ((uintptr_t)vis & (p->fp64 ? 15 : 7)) || ((uintptr_t)weight & 3))
         return fail(RICK_E_INVALID_ARG, "misaligned input pointer");
     if (nrow > (int64_t(1) << 40) / nchan) return fail(RICK_E_CAPACITY, "nrow*nchan too large");
-    if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed; call rick_reset first");
-    if (p->state == 3) return fail(RICK_E_STATE, "mesh holds predicted planes; call rick_reset first");
     if (freq_hz) {
         for (int c = 0; c < nchan; ++c)
             if (!std::isfinite(freq_hz[c]) || !(freq_hz[c] > 0.0))
                 return fail(RICK_E_INVALID_ARG, "freq_hz[%d]=%g", c, freq_hz[c]);
     }
+    return RICK_OK;
+}
+
+// Argument checks shared by rick_grid and rick_grid_static (before any device work).
+rick_status check_grid_args(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                            const float *weight, int64_t nrow, int32_t nchan) {
+    const rick_status st = check_vis_args(p, uvw, freq_hz, vis, weight, nrow, nchan);
+    if (st != RICK_OK) return st;
+    if (p->state == 2) return fail(RICK_E_STATE, "planes already transformed; call rick_reset first");
+    if (p->state == 3) return fail(RICK_E_STATE, "mesh holds predicted planes; call rick_reset first");
+    if (p->lut3 && !p->lut_ready) return fail(RICK_E_STATE, "no table installed; call rick_plan_set_lut first");
     return RICK_OK;
 }
 
@@ -600,10 +653,11 @@ rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, cons
     if (p->fp64)
         e = launch_grid<double>(g, bb.scan, bb.item_bin, bb.rec_pos, (const double *)bb.rec_vis,
                                 (const double *)p->lut, (double *)p->mesh, p->tile_bits, (double *)p->margin,
-                                bb.bin_vmax, max_items, s);
+                                bb.bin_vmax, p->lut3 ? p->tapmax : nullptr, max_items, s);
     else
         e = launch_grid<float>(g, bb.scan, bb.item_bin, bb.rec_pos, (const float *)bb.rec_vis, (const float *)p->lut,
-                               (float *)p->mesh, p->tile_bits, (float *)p->margin, bb.bin_vmax, max_items, s);
+                               (float *)p->mesh, p->tile_bits, (float *)p->margin, bb.bin_vmax,
+                               p->lut3 ? p->tapmax : nullptr, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
     timer_begin(p, T_MARK, "merge_margins", s);
@@ -742,19 +796,19 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
         timer_begin(p, T_SCREEN, "fft_cols_screen", s);
         if (p->fp64)
             e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle,
-                                               p->corr, p->stats, p->row_bits, (double *)image, 0, s);
+                                               taper_of(p), p->stats, p->row_bits, (double *)image, 0, s);
         else
             e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle,
-                                              p->corr, p->stats, p->row_bits, (float *)image, kahan, s);
+                                              taper_of(p), p->stats, p->row_bits, (float *)image, kahan, s);
         timer_end(p, T_SCREEN, s);
         if (e != hipSuccess) return hip_fail(e, "fft_cols_screen");
         return RICK_OK;
     }
     timer_begin(p, T_SCREEN, "wscreen", s);
     if (p->fp64)
-        e = launch_wscreen<double>(p->g, (const double *)p->mesh, p->corr, p->stats, (double *)image, 0, s);
+        e = launch_wscreen<double>(p->g, (const double *)p->mesh, taper_of(p), p->stats, (double *)image, 0, s);
     else
-        e = launch_wscreen<float>(p->g, (const float *)p->mesh, p->corr, p->stats, (float *)image, kahan, s);
+        e = launch_wscreen<float>(p->g, (const float *)p->mesh, taper_of(p), p->stats, (float *)image, kahan, s);
     timer_end(p, T_SCREEN, s);
     if (e != hipSuccess) return hip_fail(e, "wscreen");
     return RICK_OK;
@@ -762,6 +816,7 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
 
 rick_status rick_predict_planes(rick_plan_t *p, const void *model, void *stream) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (p->lut3) return fail(RICK_E_UNSUPPORTED, "prediction with a user table is not built");
     if (!model) return fail(RICK_E_INVALID_ARG, "model is NULL");
     if (((uintptr_t)model) & (p->fp64 ? 7 : 3)) return fail(RICK_E_INVALID_ARG, "misaligned model");
     DeviceGuard guard(p->d.device);
@@ -810,6 +865,7 @@ rick_status rick_predict_planes(rick_plan_t *p, const void *model, void *stream)
 rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz, void *vis_out, int64_t nrow,
                         int32_t nchan, void *stream) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (p->lut3) return fail(RICK_E_UNSUPPORTED, "prediction with a user table is not built");
     if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
     if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
     if (!freq_hz && nchan != 1) return fail(RICK_E_INVALID_ARG, "nchan=%d without freq_hz", nchan);
@@ -870,6 +926,7 @@ extern "C" {
 rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const double *freq_hz, int64_t nrow,
                                      int32_t nchan, rick_degrid_order_t **out, void *stream) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (p->lut3) return fail(RICK_E_UNSUPPORTED, "prediction with a user table is not built");
     if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (nrow < 0) return fail(RICK_E_INVALID_ARG, "nrow=%lld", (long long)nrow);
@@ -1016,6 +1073,13 @@ rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
     }
     out->panel = p->panel;
     out->mesh_bytes = (int64_t)p->mesh_bytes;
+    if (p->w_k_host.size() != size_t(p->g.Nw)) {
+        p->w_k_host.resize(p->g.Nw);
+        for (int k = 0; k < p->g.Nw; ++k) p->w_k_host[k] = p->g.w_min + (double(k) + 0.5) * p->g.dw;
+    }
+    out->w_k = p->w_k_host.data();
+    out->taper = taper_of(p);
+    out->lut_wbins = p->lut3 ? p->g.nwf : 0;
     out->tile = p->g.T;
     out->chunk = p->g.CH;
     out->state = p->state;
@@ -1240,6 +1304,173 @@ rick_status rick_autotune(const rick_plan_desc *d, const double *uvw, const doub
     *tile = best_t;
     *chunk = best_c;
     *ms = best;
+    return RICK_OK;
+}
+
+
+rick_status rick_plan_set_lut(rick_plan_t *p, const float *table, int32_t on_device, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!p->lut3) return fail(RICK_E_STATE, "the plan's kernel is not RICK_KERNEL_USER_LUT");
+    if (!table) return fail(RICK_E_INVALID_ARG, "table is NULL");
+    if (on_device && ((uintptr_t)table & 3)) return fail(RICK_E_INVALID_ARG, "misaligned table");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const Geom &g = p->g;
+    const int64_t n = int64_t(g.nwf) * g.OS * g.OS * g.W * g.W;
+    hipError_t e = hipSuccess;
+    if (on_device) {
+        e = p->fp64 ? launch_table_install<double>(table, (double *)p->lut, n, p->tapmax, s)
+                    : launch_table_install<float>(table, (float *)p->lut, n, p->tapmax, s);
+    } else {
+        // a host table: converted and its largest |entry| found here, copied
+        // synchronously (the caller's buffer may go away after the call)
+        float mx = 0.0f;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!std::isfinite(table[i])) return fail(RICK_E_INVALID_ARG, "table[%lld] is not finite", (long long)i);
+            mx = std::max(mx, std::fabs(table[i]));
+        }
+        if (p->fp64) {
+            std::vector<double> t(table, table + n);
+            e = hipMemcpy(p->lut, t.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(p->lut, table, size_t(n) * sizeof(float), hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess) e = hipMemcpy(p->tapmax, &mx, sizeof mx, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_taper2d<double>(g, (const double *)p->lut, p->taper_bufs, p->corr2, s)
+                    : launch_taper2d<float>(g, (const float *)p->lut, p->taper_bufs, p->corr2, s);
+    if (e != hipSuccess) return hip_fail(e, "install table");
+    p->lut_ready = true;
+    return RICK_OK;
+}
+
+static rick_status check_table_shape(int32_t support, int32_t oversample, int32_t n_wbins) {
+    if (support < 1 || support > 15 || (support & 1) == 0)
+        return fail(RICK_E_INVALID_ARG, "support=%d: must be odd in [1, 15]", support);
+    if (!is_pow2(oversample) || oversample > 256)
+        return fail(RICK_E_INVALID_ARG, "oversample=%d: must be a power of two in [1, 256]", oversample);
+    if (!is_pow2(n_wbins) || n_wbins > 8) return fail(RICK_E_INVALID_ARG, "n_wbins=%d: must be 1, 2, 4 or 8", n_wbins);
+    return RICK_OK;
+}
+
+rick_status rick_mlp_tabulate(const float *theta, int32_t support, int32_t oversample, int32_t n_wbins,
+                              float *table, void *stream) {
+    const rick_status st = check_table_shape(support, oversample, n_wbins);
+    if (st != RICK_OK) return st;
+    if (!theta || !table) return fail(RICK_E_INVALID_ARG, "theta or table is NULL");
+    if (((uintptr_t)theta & 3) || ((uintptr_t)table & 3)) return fail(RICK_E_INVALID_ARG, "misaligned pointer");
+    const hipError_t e = launch_mlp_table(theta, support, oversample, n_wbins, table, nullptr, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp tabulate");
+    return RICK_OK;
+}
+
+rick_status rick_mlp_backward(const float *theta, int32_t support, int32_t oversample, int32_t n_wbins,
+                              const float *table, const double *dtable, float *dtheta, void *stream) {
+    const rick_status st = check_table_shape(support, oversample, n_wbins);
+    if (st != RICK_OK) return st;
+    if (!theta || !table || !dtable || !dtheta) return fail(RICK_E_INVALID_ARG, "NULL pointer");
+    if (((uintptr_t)theta & 3) || ((uintptr_t)table & 3) || ((uintptr_t)dtable & 7) || ((uintptr_t)dtheta & 3))
+        return fail(RICK_E_INVALID_ARG, "misaligned pointer");
+    const hipError_t e = launch_mlp_backward(theta, support, oversample, n_wbins, table, dtable, dtheta,
+                                             (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp backward");
+    return RICK_OK;
+}
+
+rick_status rick_adam_step(float *theta, const float *grad, float *m, float *v, int32_t n, int32_t step, float lr,
+                           float beta1, float beta2, float eps, void *stream) {
+    if (!theta || !grad || !m || !v) return fail(RICK_E_INVALID_ARG, "NULL pointer");
+    if (n < 1 || step < 1) return fail(RICK_E_INVALID_ARG, "n=%d, step=%d", n, step);
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(RICK_E_INVALID_ARG, "Adam hyper-parameters");
+    const hipError_t e = launch_adam(theta, grad, m, v, n, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adam");
+    return RICK_OK;
+}
+
+rick_status rick_image_loss(rick_plan_t *p, const void *image, const double *target, double *dimage,
+                            double *dtaper, double *sums, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!image || !target || !dimage || !dtaper || !sums) return fail(RICK_E_INVALID_ARG, "NULL pointer");
+    if (((uintptr_t)image & (p->fp64 ? 7 : 3)) || ((uintptr_t)target & 7) || ((uintptr_t)dimage & 7) ||
+        ((uintptr_t)dtaper & 7) || ((uintptr_t)sums & 7))
+        return fail(RICK_E_INVALID_ARG, "misaligned pointer");
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const hipError_t e =
+        p->fp64 ? launch_image_loss<double>(p->g, (const double *)image, target, taper_of(p), dimage, dtaper, sums, s)
+                : launch_image_loss<float>(p->g, (const float *)image, target, taper_of(p), dimage, dtaper, sums, s);
+    if (e != hipSuccess) return hip_fail(e, "image loss");
+    return RICK_OK;
+}
+
+rick_status rick_table_gradient(rick_plan_t *p, const double *dimage, const double *dtaper, const double *uvw,
+                                const double *freq_hz, const void *vis, const float *weight, int64_t nrow,
+                                int32_t nchan, double *dtable, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!p->lut3) return fail(RICK_E_STATE, "the plan's kernel is not RICK_KERNEL_USER_LUT");
+    if (p->state != 2) return fail(RICK_E_STATE, "the planes of the imaged visibilities are not transformed");
+    if (!dimage || !dtaper || !dtable) return fail(RICK_E_INVALID_ARG, "NULL pointer");
+    if (((uintptr_t)dimage & 7) || ((uintptr_t)dtaper & 7) || ((uintptr_t)dtable & 7))
+        return fail(RICK_E_INVALID_ARG, "misaligned pointer");
+    const rick_status st = check_vis_args(p, uvw, freq_hz, vis, weight, nrow, nchan);
+    if (st != RICK_OK) return st;
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const Geom &g = p->g;
+    const int64_t n_table = int64_t(g.nwf) * g.OS * g.OS * g.W * g.W;
+    hipError_t e = upload_scales(p, freq_hz, nchan, s);
+    // dL/dG_k of every plane (conjugated, then inverse-transformed in place:
+    // the mesh then holds the conjugate of the forward transform)
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_grad_screen<double>(g, dimage, p->stats, (double *)p->mesh, s)
+                    : launch_grad_screen<float>(g, dimage, p->stats, (float *)p->mesh, s);
+    if (e == hipSuccess) e = launch_fill_bits(g, p->tile_bits, p->row_bits, s);
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_fft_rows<double>(g, (double *)p->mesh, (const double *)p->twiddle, p->tile_bits,
+                                              p->row_bits, s)
+                    : launch_fft_rows<float>(g, (float *)p->mesh, (const float *)p->twiddle, p->tile_bits,
+                                             p->row_bits, s);
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_fft_cols<double>(g, (double *)p->mesh, (const double *)p->twiddle, s)
+                    : launch_fft_cols<float>(g, (float *)p->mesh, (const float *)p->twiddle, s);
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_table_grad<double>(g, uvw, p->scales, (const double *)vis, weight, nrow, nchan,
+                                                (const double *)p->mesh, dtable, n_table, s)
+                    : launch_table_grad<float>(g, uvw, p->scales, (const float *)vis, weight, nrow, nchan,
+                                               (const float *)p->mesh, dtable, n_table, s);
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_taper2d_adjoint<double>(g, dtaper, p->taper_bufs, dtable, s)
+                    : launch_taper2d_adjoint<float>(g, dtaper, p->taper_bufs, dtable, s);
+    if (e != hipSuccess) return hip_fail(e, "table gradient");
+    p->state = 3;   // the mesh holds gradient planes: a reset comes next
+    return RICK_OK;
+}
+
+rick_status rick_dft_image(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
+                           const float *weight, int64_t nrow, int32_t nchan, int32_t q0, int32_t p0, int32_t nq,
+                           int32_t np, double *out, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (!out || ((uintptr_t)out & 7)) return fail(RICK_E_INVALID_ARG, "out is NULL or misaligned");
+    const int32_t N = p->g.N;
+    if (nq < 1 || np < 1 || q0 < 0 || p0 < 0 || q0 > N - nq || p0 > N - np)
+        return fail(RICK_E_INVALID_ARG, "pixel rectangle (%d, %d) + (%d, %d) outside the %d^2 image", q0, p0, nq, np,
+                    N);
+    const rick_status st = check_vis_args(p, uvw, freq_hz, vis, weight, nrow, nchan);
+    if (st != RICK_OK) return st;
+    if (nrow * int64_t(nchan) > int64_t(65535) * 16384)
+        return fail(RICK_E_CAPACITY, "nrow*nchan=%lld: at most %lld visibilities per call",
+                    (long long)(nrow * nchan), (long long)(int64_t(65535) * 16384));
+    DeviceGuard guard(p->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = upload_scales(p, freq_hz, nchan, s);
+    if (e == hipSuccess)
+        e = p->fp64 ? launch_dft<double>(p->g, uvw, p->scales, (const double *)vis, weight, nrow, nchan, q0, p0, nq,
+                                         np, out, p->dft_wsum, s)
+                    : launch_dft<float>(p->g, uvw, p->scales, (const float *)vis, weight, nrow, nchan, q0, p0, nq, np,
+                                        out, p->dft_wsum, s);
+    if (e != hipSuccess) return hip_fail(e, "direct sum");
     return RICK_OK;
 }
 

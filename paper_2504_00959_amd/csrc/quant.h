@@ -3,6 +3,8 @@
 // (prediction), so that both directions place a visibility identically.
 //   X = rint((u FoV) OS + N OS / 2), c_x = floor((X + OS/2) / OS), s_x = X - c_x OS
 //   k = clamp(floor((w - w_min) / dw), 0, N_w - 1)
+//   with a non-separable table of N_f w-fraction bins:
+//   iw = clamp(floor(((w - w_min) / dw - k) N_f), 0, N_f - 1)
 //   dropped if any input is non-finite, the position is beyond 2^30
 //   sub-cells, the weight is <= 0, or the W x W footprint leaves the grid.
 #pragma once
@@ -12,6 +14,7 @@ namespace rick {
 
 struct Quant {
     int32_t cx, cy, sx, sy, k;
+    int32_t iw;   // w-fraction bin (0 with a separable tap table)
 };
 
 // Position, plane and drop decision of one visibility, evaluated without
@@ -40,12 +43,23 @@ __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, doub
     ok &= (unsigned)(wt > 0.0f);
     ok &= (unsigned)(q.cx - g.h >= 0) & (unsigned)(q.cx + g.h <= g.N - 1) & (unsigned)(q.cy - g.h >= 0) &
           (unsigned)(q.cy + g.h <= g.N - 1);
-    double kf = floor((w - g.w_min) / g.dw);
+    const double rw = (w - g.w_min) / g.dw;
+    double kf = floor(rw);
     if (isnan(kf)) kf = 0.0;
     kf = kf < 0.0 ? 0.0 : kf;
     kf = kf > (double)(g.Nw - 1) ? (double)(g.Nw - 1) : kf;
     q.k = (int32_t)kf;
-    if (!ok) q = Quant{0, 0, 0, 0, 0};
+    // w-fraction bin of a non-separable table: floor((r - k) N_f), clamped
+    // (r - k leaves [0, 1) only for w outside the planes' range)
+    q.iw = 0;
+    if (g.nwf > 1) {
+        double fb = floor((rw - kf) * (double)g.nwf);
+        if (!isfinite(fb)) fb = 0.0;
+        fb = fb < 0.0 ? 0.0 : fb;
+        fb = fb > (double)(g.nwf - 1) ? (double)(g.nwf - 1) : fb;
+        q.iw = (int32_t)fb;
+    }
+    if (!ok) q = Quant{0, 0, 0, 0, 0, 0};
     return ok != 0u;
 }
 

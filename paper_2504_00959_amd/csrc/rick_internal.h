@@ -64,6 +64,8 @@ struct Geom {
     int32_t occw;       // 64-bit words of tile occupancy per tile row, ceil(nt / 64)
     float gmax2;        // square of the largest tap of the tap table (as the device holds it)
     int32_t cpt1;       // level-1 records in the compact 12-byte format (float32 mode, when it fits)
+    int32_t nwf;        // w-fraction bins of a non-separable tap table (1 otherwise)
+    int32_t lut3;       // 1: the taps come from a non-separable table T[nwf][OS][OS][W][W]
     double fov;
     double half;        // N * OS / 2
     double w_min;
@@ -100,6 +102,30 @@ __device__ __forceinline__ bool tile_set(const uint64_t *__restrict__ tile_bits,
 __device__ __forceinline__ bool row_set(const uint64_t *__restrict__ row_bits, const Geom &g, int32_t k,
                                         int32_t ty) {
     return (row_bits[(int64_t)k * g.occw + (ty >> 6)] >> (ty & 63)) & 1ull;
+}
+
+// sin(pi g) and cos(pi g) for |g| <= 1/2 in float32: sin(pi g) = g P(g^2),
+// cos(pi g) = Q(g^2), minimax polynomials fitted on [-1/2, 1/2] (Horner form,
+// float32 fma; absolute error below 2.5e-7).
+__device__ __forceinline__ void sincospi_half(float g, float &sn, float &cs) {
+    const float g2 = g * g;
+    float ps = fmaf(g2, 0.07805382838216549f, -0.5985074114168937f);
+    ps = fmaf(g2, ps, 2.5501159030870695f);
+    ps = fmaf(g2, ps, -5.167712346356822f);
+    ps = fmaf(g2, ps, 3.141592653446274f);
+    sn = g * ps;
+    float pc = fmaf(g2, -0.02468992584886284f, 0.23511454480404714f);
+    pc = fmaf(g2, pc, -1.3352479005812146f);
+    pc = fmaf(g2, pc, 4.05871189644457f);
+    pc = fmaf(g2, pc, -4.934802200064621f);
+    cs = fmaf(g2, pc, 1.0f);
+}
+
+// Image-plane taper of pixel (q, p): C(l'_p) C(m'_q) for a separable
+// kernel (corr holds the 1-D taper), or the 2-D taper corr[q][p] of a
+// non-separable table.
+__device__ __forceinline__ double taper_at(const Geom &g, const double *__restrict__ corr, int64_t q, int64_t p) {
+    return g.lut3 ? corr[q * g.N + p] : corr[p] * corr[q];
 }
 
 // Centre of plane k: w_k = w_min + (k + 1/2) dw, in float64, multiply then
@@ -150,10 +176,12 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
 // buffers of heavy bins), then one block per (bin, chunk) item; tiles set in
 // tile_bits are added to, others stored; each bin's margins go to its margin
 // buffer (grid_margin_len complex values per bin).
+// With tapmax non-NULL, lut is a non-separable table T[N_f][OS][OS][W][W]
+// in device memory and *tapmax its largest |entry|.
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const uint32_t *bin_vmax, int32_t max_items, hipStream_t s);
+                       const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s);
 // LDS bytes of one gridding block (float64 accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 int64_t grid_margin_len(const Geom &g);
@@ -194,7 +222,7 @@ template <typename real>
 hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *twiddle,
                                  const uint64_t *tile_bits, const uint64_t *row_bits, hipStream_t s);
 int fused_panel_width(int N, size_t real_bytes);
-bool fft_supported(int N);
+bool fft_supported(int N, size_t real_bytes);   // N = 16384 in float32 modes only
 // Column transform fused with the w-correction, plane sum and normalisation.
 size_t fused_screen_lds_bytes(int N, size_t real_bytes);
 template <typename real>
@@ -204,6 +232,41 @@ hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *t
 template <typename real>
 hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *corr,
                           const Stats *st, real *image, int kahan, hipStream_t s);
+
+// ---- learned gridding kernel (learned.hip) ----
+// Scratch of the 2-D taper of a non-separable table: A [M][M] (the table
+// averaged over w-fraction bins, M = OS W offsets per axis), Ec/Es [M][N]
+// (cos/sin of 2 pi d l'), Uc/Us [M][N] (row-pass results).
+struct TaperBufs {
+    double *A, *Ec, *Es, *Uc, *Us;
+};
+int mlp_param_count();
+template <typename real>
+hipError_t launch_table_install(const float *src, real *dst, int64_t n, float *tapmax, hipStream_t s);
+template <typename real>
+hipError_t launch_taper2d(const Geom &g, const real *T, const TaperBufs &tb, double *C, hipStream_t s);
+template <typename real>
+hipError_t launch_taper2d_adjoint(const Geom &g, const double *dC, const TaperBufs &tb, double *dT, hipStream_t s);
+template <typename real>
+hipError_t launch_image_loss(const Geom &g, const real *I, const double *D, const double *taper, double *dA,
+                             double *dC, double *sums, hipStream_t s);
+template <typename real>
+hipError_t launch_grad_screen(const Geom &g, const double *dA, const Stats *st, real *mesh, hipStream_t s);
+template <typename real>
+hipError_t launch_table_grad(const Geom &g, const double *uvw, const double *scales, const real *vis,
+                             const float *weight, int64_t nrow, int32_t nchan, const real *mesh, double *dT,
+                             int64_t n_table, hipStream_t s);
+hipError_t launch_mlp_table(const float *theta, int W, int OS, int nwf, float *T, float *rowsum, hipStream_t s);
+hipError_t launch_mlp_backward(const float *theta, int W, int OS, int nwf, const float *T, const double *dT,
+                               float *dtheta, hipStream_t s);
+hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int n, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t s);
+template <typename real>
+hipError_t launch_dft(const Geom &g, const double *uvw, const double *scales, const real *vis, const float *weight,
+                      int64_t nrow, int32_t nchan, int q0, int p0, int nq, int np, double *out, double *wsum,
+                      hipStream_t s);
+// Every tile bit and row bit of every plane set (degrid.hip).
+hipError_t launch_fill_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
 
 // Prediction: conj(P_k) of the model image into every plane of the mesh, and
 // every tile bit and row bit set (the FFT then reads whole planes).

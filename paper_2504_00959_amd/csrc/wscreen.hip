@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kScreenBlock) void k_wscreen(Geom g, const real *__
         }
     }
     const double sw = st->sum_w;
-    const double val = sw > 0.0 ? (1.0 + nm1) * (double)sum / (corr[p] * corr[q] * sw) : 0.0;
+    const double val = sw > 0.0 ? (1.0 + nm1) * (double)sum / (taper_at(g, corr, q, p) * sw) : 0.0;
     image[pix] = (real)val;
 }
 

@@ -21,7 +21,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "rick.h")
 RICK_OK = 0
 STATUS_NAMES = {0: "RICK_OK", 1: "RICK_E_INVALID_ARG", 2: "RICK_E_NO_DEVICE", 3: "RICK_E_OOM", 4: "RICK_E_HIP",
                 5: "RICK_E_CAPACITY", 6: "RICK_E_BAD_PLAN", 7: "RICK_E_STATE", 8: "RICK_E_UNSUPPORTED"}
-KERNELS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1}
+KERNELS = {"gaussian": 0, "kaiser_bessel": 1, "kb": 1, "user_lut": 2}
+MLP_PARAMS = 1217
 PRECISIONS = {"fp32": 0, "fp32_kahan": 1, "fp64": 2}
 FLAG_TIMING = 1
 FLAG_FUSED_SCREEN = 2
@@ -63,7 +64,8 @@ class PlanDesc(ctypes.Structure):
                 ("oversample", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("kernel_param", ctypes.c_double), ("fov_rad", ctypes.c_double), ("w_min", ctypes.c_double),
                 ("w_max", ctypes.c_double), ("max_vis", ctypes.c_int64), ("device", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("lut_wbins", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -75,7 +77,9 @@ class PlanInfo(ctypes.Structure):
                 ("rec1_bytes", ctypes.c_int32), ("pad1", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("state", ctypes.c_int32),
                 ("n_timers", ctypes.c_int32), ("kernel_ms", ctypes.c_float * 16),
-                ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16)]
+                ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16),
+                ("w_k", ctypes.POINTER(ctypes.c_double)), ("taper", ctypes.c_void_p), ("lut_wbins", ctypes.c_int32),
+                ("pad2", ctypes.c_int32)]
 
 
 _lib = None
@@ -94,6 +98,15 @@ def lib() -> ctypes.CDLL:
     L.rick_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]
     L.rick_grid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
     L.rick_grid_static.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.rick_plan_set_lut.argtypes = [P, P, i32, P]
+    L.rick_mlp_tabulate.argtypes = [P, i32, i32, i32, P, P]
+    L.rick_mlp_backward.argtypes = [P, i32, i32, i32, P, P, P, P]
+    L.rick_adam_step.argtypes = [P, P, P, P, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, P]
+    L.rick_image_loss.argtypes = [P, P, P, P, P, P, P]
+    L.rick_table_gradient.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_double), P, P, i64, i32, P, P]
+    L.rick_dft_image.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, i64, i32, i32, i32, i32, i32, P, P]
     L.rick_fft_planes.argtypes = [P, P]
     L.rick_wstack_image.argtypes = [P, P, P]
     L.rick_reset.argtypes = [P, P]
@@ -118,7 +131,9 @@ def lib() -> ctypes.CDLL:
     L.rick_autotune.argtypes = [ctypes.POINTER(PlanDesc), P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64,
                                 ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_float)]
-    for f in ("rick_plan", "rick_grid", "rick_grid_static", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
+    for f in ("rick_plan_set_lut", "rick_mlp_tabulate", "rick_mlp_backward", "rick_adam_step", "rick_image_loss",
+              "rick_table_gradient", "rick_dft_image",
+              "rick_plan", "rick_grid", "rick_grid_static", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
               "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid",
@@ -153,12 +168,12 @@ def _stream_handle(stream) -> Optional[int]:
 
 def make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel="gaussian", kernel_param=0.0,
               precision="fp32", max_vis=1 << 20, device=0, timing=False, tile=0, chunk=0,
-              fused=False) -> PlanDesc:
+              fused=False, lut_wbins=0) -> PlanDesc:
     flags = (FLAG_TIMING if timing else 0) | (FLAG_FUSED_SCREEN if fused else 0)
     return PlanDesc(grid_n=grid_n, n_wplanes=n_wplanes, support=support, oversample=oversample,
                     kernel=KERNELS[kernel], precision=PRECISIONS[precision], kernel_param=kernel_param,
                     fov_rad=fov, w_min=w_min, w_max=w_max, max_vis=max_vis, device=device,
-                    flags=flags, tile=tile, chunk=chunk)
+                    flags=flags, tile=tile, chunk=chunk, lut_wbins=lut_wbins)
 
 
 class Plan:
@@ -167,9 +182,10 @@ class Plan:
     def __init__(self, grid_n: int, n_wplanes: int, support: int, oversample: int, fov: float, w_min: float,
                  w_max: float, kernel: str = "gaussian", kernel_param: float = 0.0, precision: str = "fp32",
                  max_vis: int = 1 << 20, device: int = 0, timing: bool = False, tile: int = 0, chunk: int = 0,
-                 fused: bool = False):
+                 fused: bool = False, lut_wbins: int = 0):
         self.desc = make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel, kernel_param,
-                              precision, max_vis, device, timing, tile, chunk, fused)
+                              precision, max_vis, device, timing, tile, chunk, fused, lut_wbins)
+        self.support, self.oversample, self.lut_wbins = support, oversample, lut_wbins
         self.fused = fused
         self.precision = precision
         self.grid_n = grid_n
@@ -317,6 +333,86 @@ class Plan:
                "rick_degrid_sorted")
         return out
 
+    # ---- learned gridding kernel ----
+    def set_lut(self, table, stream=None):
+        """Install a table [N_f, OS, OS, W, W] (float32: device tensor, or host
+        numpy array) into a user-table plan and compute its taper."""
+        import torch
+        if isinstance(table, torch.Tensor):
+            self._device_tensor(table, "table", torch.float32)
+            _check(lib().rick_plan_set_lut(self._h, table.data_ptr(), 1, _stream_handle(stream)), "rick_plan_set_lut")
+        else:
+            t = np.ascontiguousarray(np.asarray(table, dtype=np.float32))
+            _check(lib().rick_plan_set_lut(self._h, t.ctypes.data, 0, _stream_handle(stream)), "rick_plan_set_lut")
+
+    def taper(self):
+        """Device float64 view of the taper the image is divided by: [N] (separable) or [N, N] (user table)."""
+        inf = self.info()
+        shape = (self.grid_n, self.grid_n) if inf["lut_wbins"] else (self.grid_n,)
+        return self._device_view(inf["taper_ptr"], shape, "<f8")
+
+    def image_loss(self, image, target, dimage, dtaper, sums, stream=None):
+        """rick_image_loss: sums[0] / sums[1] is the loss; dimage, dtaper its gradients (float64 [N, N])."""
+        import torch
+        self._device_tensor(image, "image", self.real_dtype)
+        for t, n in ((target, "target"), (dimage, "dimage"), (dtaper, "dtaper")):
+            self._device_tensor(t, n, torch.float64)
+            if t.numel() != self.grid_n * self.grid_n:
+                raise ValueError(f"{n} must be [N, N]")
+        self._device_tensor(sums, "sums", torch.float64)
+        if sums.numel() < 2:
+            raise ValueError("sums must hold 2 values")
+        _check(lib().rick_image_loss(self._h, image.data_ptr(), target.data_ptr(), dimage.data_ptr(),
+                                     dtaper.data_ptr(), sums.data_ptr(), _stream_handle(stream)), "rick_image_loss")
+
+    def table_gradient(self, dimage, dtaper, uvw, vis, weight, freq, dtable, stream=None):
+        """rick_table_gradient: dL/dT (float64 [N_f, OS, OS, W, W]) for the visibilities just imaged."""
+        import torch
+        self._device_tensor(dimage, "dimage", torch.float64)
+        self._device_tensor(dtaper, "dtaper", torch.float64)
+        self._device_tensor(dtable, "dtable", torch.float64)
+        self._device_tensor(uvw, "uvw", torch.float64)
+        self._device_tensor(vis, "vis", self.complex_dtype)
+        nrow = uvw.shape[0]
+        nchan = vis.numel() // max(1, nrow)
+        if dtable.numel() != self.lut_wbins * self.oversample ** 2 * self.support ** 2:
+            raise ValueError("dtable has the wrong size")
+        wptr = None
+        if weight is not None:
+            self._device_tensor(weight, "weight", torch.float32)
+            wptr = weight.data_ptr()
+        fptr, f = None, None
+        if freq is not None:
+            f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).reshape(-1))
+            fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(lib().rick_table_gradient(self._h, dimage.data_ptr(), dtaper.data_ptr(), uvw.data_ptr(), fptr,
+                                         vis.data_ptr(), wptr, nrow, nchan, dtable.data_ptr(),
+                                         _stream_handle(stream)), "rick_table_gradient")
+
+    def dft_image(self, uvw, vis, weight=None, freq=None, q0=0, p0=0, nq=None, np_=None, out=None, stream=None):
+        """rick_dft_image: the direct Fourier sum at pixels [q0, q0 + nq) x [p0, p0 + np) (float64)."""
+        import torch
+        nq = self.grid_n if nq is None else nq
+        np_ = self.grid_n if np_ is None else np_
+        self._device_tensor(uvw, "uvw", torch.float64)
+        self._device_tensor(vis, "vis", self.complex_dtype)
+        nrow = uvw.shape[0]
+        nchan = vis.numel() // max(1, nrow)
+        wptr = None
+        if weight is not None:
+            self._device_tensor(weight, "weight", torch.float32)
+            wptr = weight.data_ptr()
+        fptr, f = None, None
+        if freq is not None:
+            f = np.ascontiguousarray(np.asarray(freq, dtype=np.float64).reshape(-1))
+            fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if out is None:
+            out = torch.empty((nq, np_), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._device_tensor(out, "out", torch.float64)
+        _check(lib().rick_dft_image(self._h, uvw.data_ptr(), fptr, vis.data_ptr(), wptr, nrow, nchan, q0, p0, nq, np_,
+                                    out.data_ptr(), _stream_handle(stream)), "rick_dft_image")
+        return out
+
     def retarget(self, fov: float, w_min: float, w_max: float):
         """Field of view and w range for the work issued next (host-side only)."""
         _check(lib().rick_plan_retarget(self._h, fov, w_min, w_max), "rick_plan_retarget")
@@ -337,7 +433,9 @@ class Plan:
                     mesh_bytes=inf.mesh_bytes, row_mesh_ptr=inf.row_mesh, panel=inf.panel,
                     tile_bits_ptr=inf.tile_bits, occ_words=inf.occ_words, tiles_set=inf.tiles_set,
                     tile_rows_set=inf.tile_rows_set, rec1_bytes=inf.rec1_bytes, tile=inf.tile,
-                    chunk=inf.chunk, state=inf.state, timers=timers)
+                    chunk=inf.chunk, state=inf.state, timers=timers,
+                    w_k=np.array([inf.w_k[k] for k in range(self.n_wplanes)]), taper_ptr=inf.taper,
+                    lut_wbins=inf.lut_wbins)
 
     def bin_counts(self, n_bins: int) -> np.ndarray:
         """Per-(plane, tile) record counts of the last grid() (host int32 array)."""
@@ -413,6 +511,45 @@ class Plan:
 
     def __exit__(self, *a):
         self.close()
+
+
+def mlp_tabulate(theta, support: int, oversample: int, n_wbins: int, out=None, stream=None):
+    """rick_mlp_tabulate: table [N_f, OS, OS, W, W] (float32, device) of the MLP parameters theta."""
+    import torch
+    if not (isinstance(theta, torch.Tensor) and theta.is_cuda and theta.dtype == torch.float32
+            and theta.is_contiguous() and theta.numel() == MLP_PARAMS):
+        raise TypeError(f"theta must be a contiguous float32 device tensor of {MLP_PARAMS}")
+    shape = (n_wbins, oversample, oversample, support, support)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=theta.device)
+    if out.dtype != torch.float32 or not out.is_contiguous() or tuple(out.shape) != shape:
+        raise ValueError("out must be a contiguous float32 tensor of the table's shape")
+    _check(lib().rick_mlp_tabulate(theta.data_ptr(), support, oversample, n_wbins, out.data_ptr(),
+                                   _stream_handle(stream)), "rick_mlp_tabulate")
+    return out
+
+
+def mlp_backward(theta, table, dtable, dtheta=None, stream=None):
+    """rick_mlp_backward: gradient of sum(dtable * table) with respect to theta (float32, device)."""
+    import torch
+    n_wbins, os_, _, w, _ = table.shape
+    if dtable.dtype != torch.float64 or tuple(dtable.shape) != tuple(table.shape) or not dtable.is_contiguous():
+        raise ValueError("dtable must be a contiguous float64 tensor of the table's shape")
+    if dtheta is None:
+        dtheta = torch.empty(MLP_PARAMS, dtype=torch.float32, device=theta.device)
+    _check(lib().rick_mlp_backward(theta.data_ptr(), w, os_, n_wbins, table.data_ptr(), dtable.data_ptr(),
+                                   dtheta.data_ptr(), _stream_handle(stream)), "rick_mlp_backward")
+    return dtheta
+
+
+def adam_step(theta, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """rick_adam_step on float32 device tensors of equal size."""
+    n = theta.numel()
+    for t in (grad, m, v):
+        if t.numel() != n or not t.is_contiguous():
+            raise ValueError("Adam buffers must match theta")
+    _check(lib().rick_adam_step(theta.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), n, step, lr, beta1,
+                                beta2, eps, _stream_handle(stream)), "rick_adam_step")
 
 
 class Graph:

@@ -34,7 +34,8 @@ def _plan_status(**over):
 
 
 @pytest.mark.parametrize("over", [
-    dict(grid_n=100), dict(grid_n=32), dict(grid_n=16384), dict(n_wplanes=0), dict(support=4),
+    dict(grid_n=100), dict(grid_n=32), dict(grid_n=32768),
+    dict(kernel="user_lut", lut_wbins=0), dict(kernel="user_lut", lut_wbins=3), dict(kernel="user_lut", lut_wbins=16), dict(n_wplanes=0), dict(support=4),
     dict(support=17), dict(oversample=3), dict(oversample=512), dict(fov=0.0), dict(fov=1.5),
     dict(w_min=1.0, w_max=1.0), dict(w_min=float("nan")), dict(max_vis=-1), dict(max_vis=1 << 29),
     dict(tile=48), dict(tile=8), dict(tile=128), dict(tile=256),
@@ -71,3 +72,21 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(rick, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         rick.lib()
+
+
+def test_learned_calls_validate_on_the_host():
+    """The learned-kernel calls reject bad shapes, NULL pointers and bad
+    handles before any device work (no GPU needed)."""
+    L = rick.lib()
+    fake = ctypes.c_void_p(16)
+    assert L.rick_mlp_tabulate(fake, 4, 16, 2, fake, None) == 1          # even support
+    assert L.rick_mlp_tabulate(fake, 7, 12, 2, fake, None) == 1          # oversample not a power of two
+    assert L.rick_mlp_tabulate(fake, 7, 16, 3, fake, None) == 1          # w-fraction bins
+    assert L.rick_mlp_tabulate(None, 7, 16, 2, fake, None) == 1
+    assert L.rick_mlp_backward(fake, 7, 16, 2, fake, None, fake, None) == 1
+    assert L.rick_adam_step(fake, fake, fake, fake, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == 1
+    assert L.rick_adam_step(fake, fake, fake, fake, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == 1
+    assert L.rick_plan_set_lut(None, fake, 1, None) == 6                 # RICK_E_BAD_PLAN
+    assert L.rick_image_loss(None, fake, fake, fake, fake, fake, None) == 6
+    assert L.rick_table_gradient(None, fake, fake, fake, None, fake, None, 1, 1, fake, None) == 6
+    assert L.rick_dft_image(None, fake, None, fake, None, 1, 1, 0, 0, 1, 1, fake, None) == 6

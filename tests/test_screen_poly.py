@@ -4,8 +4,8 @@ The w phase screen of Eq. 1 multiplies plane k by exp(+2 pi i w_k (n - 1)).
 The kernel forms the argument in float64 half turns, takes the nearest
 integer out (a sign), and evaluates sin(pi g) and cos(pi g) for the float32
 remainder g in [-1/2, 1/2] by two polynomials in g^2 (Horner form, float32
-fused multiply-adds).  This test reads the coefficients from the kernel
-source, evaluates the same Horner steps with float32 rounding after every
+fused multiply-adds; sincospi_half, also used by the direct-sum kernel).
+This test reads the coefficients from the kernel source, evaluates the same Horner steps with float32 rounding after every
 fused step, and checks the stated bound of 2.5e-7 absolute error against
 numpy's float64 sin and cos over every float32 g in a dense sweep.
 """
@@ -14,16 +14,16 @@ import re
 
 import numpy as np
 
-SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2504_00959_amd", "csrc", "fft.hip")
+SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2504_00959_amd", "csrc", "rick_internal.h")
 
 
 def _coeffs():
     body = open(SRC).read()
-    fn = body[body.index("__device__ __forceinline__ float screen_term("):]
+    fn = body[body.index("__device__ __forceinline__ void sincospi_half("):]
     fn = fn[:fn.index("\n}\n")]
     sin_c = [float(x) for x in re.findall(r"ps = fmaf\(g2, (?:ps|[-0-9.e]+f), ([-0-9.e]+)f\)", fn)]
     first_s = re.search(r"ps = fmaf\(g2, ([-0-9.e]+)f,", fn).group(1)
-    cos_c = [float(x) for x in re.findall(r"pc = fmaf\(g2, (?:pc|[-0-9.e]+f), ([-0-9.e]+)f\)", fn)]
+    cos_c = [float(x) for x in re.findall(r"(?:pc|cs) = fmaf\(g2, (?:pc|[-0-9.e]+f), ([-0-9.e]+)f\)", fn)]
     first_c = re.search(r"pc = fmaf\(g2, ([-0-9.e]+)f,", fn).group(1)
     return [float(first_s)] + sin_c, [float(first_c)] + cos_c
 
