@@ -861,6 +861,141 @@ def predict_report(args):
     print(json.dumps(out_line), flush=True)
 
 
+def learned_report(args):
+    """The learned-kernel form: train the MLP kernel on generated scenes
+    against the direct Fourier sum (256^2 grids, 16 planes, support 7,
+    oversample 64), then image the SKA-LOW-like 209.3M-visibility workload
+    with the Gaussian, Kaiser-Bessel and learned kernels at equal support and
+    report each one's distance to the direct sum on two 128^2 patches and its
+    Mvis/s.  Prints one JSON line."""
+    import torch
+    import synth
+    from paper_2504_00959_amd import rick
+    from paper_2504_00959_amd.learned import LearnedKernel
+
+    dev = "cuda:0"
+    n_train, n_eval = args.scenes, args.eval_scenes
+    t0 = time.time()
+    s0 = synth.learned_scene(0, nvis=args.scene_vis)
+    lk = LearnedKernel(grid_n=s0.grid_n, n_wplanes=s0.n_wplanes, support=s0.support, oversample=s0.oversample,
+                       fov=s0.fov, w_min=s0.w_min, w_max=s0.w_max, max_vis=args.scene_vis, n_wbins=args.wbins,
+                       seed=args.seed)
+    data = []
+    for i in range(n_train + n_eval):
+        ds = synth.learned_scene(i, nvis=args.scene_vis, device=dev)
+        uvw = torch.as_tensor(ds.uvw, dtype=torch.float64, device=dev)
+        data.append((uvw, ds.vis, lk.target(uvw, ds.vis)))
+        if i % 50 == 0:
+            print(f"[learned] scene {i}: {len(ds.sources['l'])} sources ({time.time() - t0:.1f} s)", file=sys.stderr,
+                  flush=True)
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    geo = lk.geo
+    kb = rick.Plan(**geo, max_vis=args.scene_vis, kernel="kb")
+
+    def held_out(plan):
+        sums = torch.zeros((n_eval, 2), dtype=torch.float64, device=dev)
+        for j in range(n_eval):
+            uvw, vis, D = data[n_train + j]
+            lk.loss(plan, uvw, vis, D, sums[j])
+        s = sums.cpu().numpy()
+        return float(np.mean(s[:, 0] / s[:, 1]))
+
+    res = {"gaussian": held_out(lk.gauss), "kaiser_bessel": held_out(kb)}
+    t0 = time.time()
+    fit = lk.fit_table(lk.gaussian_table(), steps=args.fit_steps, lr=3e-3)
+    lk.install()
+    res["learned_start"] = held_out(lk.plan)
+    print(f"[learned] start from the Gaussian table: fit mse {fit:.3e}, held-out loss {res['learned_start']:.4e} "
+          f"(Gaussian {res['gaussian']:.4e}, KB {res['kaiser_bessel']:.4e})", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(args.seed)
+    curve = []
+    # the parameters kept are those of the epoch with the lowest held-out loss
+    # (the start, fitted to the Gaussian table, included)
+    best, best_loss, best_epoch = lk.snapshot(), res["learned_start"], 0
+    t1 = time.time()
+    for ep in range(args.epochs):
+        sums = torch.zeros((n_train, 2), dtype=torch.float64, device=dev)
+        for i in rng.permutation(n_train):
+            uvw, vis, D = data[i]
+            lk.step(uvw, vis, D, sums[i], args.lr)
+        s = sums.cpu().numpy()
+        lk.install()
+        curve.append({"epoch": ep + 1, "train_loss": float(np.mean(s[:, 0] / s[:, 1])),
+                      "held_out_loss": held_out(lk.plan)})
+        if curve[-1]["held_out_loss"] < best_loss:
+            best, best_loss, best_epoch = lk.snapshot(), curve[-1]["held_out_loss"], ep + 1
+        print(f"[learned] epoch {ep + 1}: {curve[-1]}", file=sys.stderr, flush=True)
+    t_train = time.time() - t1
+    steps = args.epochs * n_train
+    lk.restore(best)
+    lk.install()
+    res["learned"] = best_loss
+    res["learned_epoch"] = best_epoch
+    table = lk.table.clone()
+    kb.close()
+
+    # evaluation at the SKA-LOW-like shape
+    ds = synth.ska_low_share(device=dev)
+    uvw = torch.as_tensor(ds.uvw, dtype=torch.float64).to(dev)
+    N = ds.grid_n
+    off = int(round(0.3 * N))
+    patches = {"centre": (N // 2 - 64, N // 2 - 64), "offset": (N // 2 - 64 + off, N // 2 - 64 + off)}
+    t0 = time.time()
+    with rick.Plan.for_dataset(ds) as pg:
+        dft = {k: pg.dft_image(uvw, ds.vis, None, ds.freq, q0=q0, p0=p0, nq=128, np_=128).cpu().numpy()
+               for k, (q0, p0) in patches.items()}
+    t_dft = time.time() - t0
+    evals = {}
+    for name, kw in (("gaussian", {}), ("kaiser_bessel", {"kernel": "kb"}),
+                     ("learned", {"kernel": "user_lut", "lut_wbins": args.wbins})):
+        plan = rick.Plan.for_dataset(ds, fused=True, **kw)
+        if name == "learned":
+            plan.set_lut(table)
+        img = torch.empty((N, N), dtype=torch.float32, device=dev)
+        stream = torch.cuda.current_stream()
+
+        def one():
+            plan.reset(stream)
+            plan.grid(uvw, ds.vis, None, ds.freq, stream)
+            plan.fft(stream)
+            plan.image(img, stream)
+
+        one()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            one()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        im = img.double().cpu().numpy()
+        ev = {"ms_per_step": round(ms, 3), "mvis_per_s": round(ds.nvis / (ms * 1e-3) / 1e6, 1)}
+        for k, (q0, p0) in patches.items():
+            d = dft[k]
+            ev[f"vs_dft_{k}"] = float(np.linalg.norm(im[q0:q0 + 128, p0:p0 + 128] - d) / np.linalg.norm(d))
+        evals[name] = ev
+        print(f"[learned] {name} at {N}^2 x {ds.n_wplanes}: {ev}", file=sys.stderr, flush=True)
+        plan.close()
+        del img, plan
+        torch.cuda.empty_cache()
+    out = {"report": "learned_kernel",
+           "training": {"scenes": n_train, "held_out_scenes": n_eval, "vis_per_scene": args.scene_vis,
+                        "grid": f"{geo['grid_n']}^2 x {geo['n_wplanes']} planes", "support": geo["support"],
+                        "oversample": geo["oversample"], "w_fraction_bins": args.wbins, "epochs": args.epochs,
+                        "steps": steps, "lr": args.lr, "start": "MLP fitted to the Gaussian table",
+                        "fit_steps": args.fit_steps, "fit_mse": fit, "seconds": round(t_train, 1),
+                        "ms_per_step": round(1e3 * t_train / max(1, steps), 2),
+                        "data_and_targets_seconds": round(t_data, 1)},
+           "held_out_loss": res, "curve": curve,
+           "evaluation": {"workload": describe(ds), "patches": {k: [q0, p0, 128, 128] for k, (q0, p0) in
+                                                                 patches.items()},
+                          "dft_seconds": round(t_dft, 1), "kernels": evals}}
+    lk.close()
+    print(json.dumps(out), flush=True)
+
+
 def describe(ds):
     return (f"{ds.name}: {ds.nrow:,} rows x {ds.nchan} channels = {ds.nvis:,} visibilities, "
             f"{ds.grid_n}^2 x {ds.n_wplanes} w-planes, support {ds.support}, oversample {ds.oversample}, "
@@ -899,6 +1034,17 @@ def main():
     ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
     ap.add_argument("--streams", type=int, default=4,
                     help="streams of the concurrent run of --batch (1 = only the one-stream run)")
+    ap.add_argument("--learned", action="store_true",
+                    help="the learned-kernel form: train on generated scenes against the direct sum, then compare "
+                         "with the Gaussian and Kaiser-Bessel kernels on the SKA-LOW-like workload")
+    ap.add_argument("--scenes", type=int, default=200, help="training scenes of --learned")
+    ap.add_argument("--eval-scenes", type=int, default=16, help="held-out scenes of --learned")
+    ap.add_argument("--scene-vis", type=int, default=1_000_000, help="visibilities per scene of --learned")
+    ap.add_argument("--epochs", type=int, default=10, help="passes over the training scenes of --learned")
+    ap.add_argument("--lr", type=float, default=2e-4, help="Adam step of --learned")
+    ap.add_argument("--fit-steps", type=int, default=1500, help="steps fitting the MLP to the Gaussian table")
+    ap.add_argument("--wbins", type=int, default=4, help="w-fraction bins of the learned table")
+    ap.add_argument("--seed", type=int, default=0, help="initial MLP parameters of --learned")
     ap.add_argument("--predict", action="store_true",
                     help="prediction (degridding) of the workload's visibilities from a point-source model image")
     args = ap.parse_args()
@@ -918,6 +1064,9 @@ def main():
         return
     if args.predict:
         predict_report(args)
+        return
+    if args.learned:
+        learned_report(args)
         return
     if args.copy_calibration:
         import torch

@@ -509,6 +509,21 @@ rick_status rick_dft_image(rick_plan_t *p, const double *uvw, const double *freq
                            const float *weight, int64_t nrow, int32_t nchan, int32_t q0, int32_t p0, int32_t nq,
                            int32_t np, double *out, void *stream);
 
+/* rick_separable_table -- the plan's separable tap table (Gaussian or
+ * Kaiser-Bessel) in the user-table layout: table[iw][s_y][s_x][t_y][t_x] =
+ * g[s_y][t_y] g[s_x][t_x] for every iw < n_wbins (device float32).  For
+ * comparing kernels at equal support and as a starting point for learning.
+ * Errors: RICK_E_BAD_PLAN, RICK_E_STATE (a user-table plan), RICK_E_INVALID_ARG, RICK_E_HIP. */
+rick_status rick_separable_table(rick_plan_t *p, int32_t n_wbins, float *table, void *stream);
+
+/* rick_table_residual -- least-squares fit of a table to a target (device
+ * float32, n entries each): dtable = 2 (table - target) / n (device float64) and
+ * sums[0] = sum (table - target)^2 / n (device float64).  With
+ * rick_mlp_backward it fits the MLP to a given table.
+ * Errors: RICK_E_INVALID_ARG, RICK_E_HIP. */
+rick_status rick_table_residual(const float *table, const float *target, int64_t n, double *dtable, double *sums,
+                                void *stream);
+
 const char *rick_status_str(rick_status s);
 
 /* Detail of the last failing call on this host thread (static storage, never NULL). */

@@ -476,6 +476,33 @@ __global__ void k_adam(float *__restrict__ th, const float *__restrict__ gr, flo
     th[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
+// ---- a separable table in the non-separable layout, and a table residual ----
+// out[iw][s_y][s_x][t_y][t_x] = g[s_y][t_y] g[s_x][t_x] (g the plan's separable rows)
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_separable_table(const real *__restrict__ g, int nwf, int OS, int W,
+                                                           float *__restrict__ out) {
+    const int64_t n = (int64_t)nwf * OS * OS * W * W;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int tx = (int)(i % W), ty = (int)((i / W) % W);
+    const int sx = (int)((i / (W * W)) % OS), sy = (int)((i / ((int64_t)W * W * OS)) % OS);
+    out[i] = (float)((double)g[sy * W + ty] * (double)g[sx * W + tx]);
+}
+
+// dT = 2 (T - R) / n and sums[0] = sum (T - R)^2 / n (a least-squares fit of a table to R)
+__global__ __launch_bounds__(kBlock) void k_table_residual(const float *__restrict__ T, const float *__restrict__ R,
+                                                          int64_t n, double *__restrict__ dT,
+                                                          double *__restrict__ sums) {
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double d = (double)T[i] - (double)R[i];
+        dT[i] = 2.0 * d / (double)n;
+        a = fma(d, d, a);
+    }
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&sums[0], a / (double)n);
+}
+
 // ---- direct Fourier sum at a rectangle of pixels ----
 constexpr int kDftPix = 256;      // pixels per block (one per thread)
 constexpr int kDftVis = 16384;    // visibilities per block
@@ -675,7 +702,21 @@ hipError_t launch_dft(const Geom &g, const double *uvw, const double *scales, co
     return hipGetLastError();
 }
 
+template <typename real>
+hipError_t launch_separable_table(const real *g, int nwf, int OS, int W, float *out, hipStream_t s) {
+    const int64_t n = (int64_t)nwf * OS * OS * W * W;
+    hipLaunchKernelGGL((k_separable_table<real>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, nwf, OS, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_residual(const float *T, const float *R, int64_t n, double *dT, double *sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, sums, 0.0, (int64_t)1);
+    hipLaunchKernelGGL(k_table_residual, dim3(blocks_for(n, kBlock, 2048)), dim3(kBlock), 0, s, T, R, n, dT, sums);
+    return hipGetLastError();
+}
+
 #define INST(real)                                                                                                  \
+    template hipError_t launch_separable_table<real>(const real *, int, int, int, float *, hipStream_t);           \
     template hipError_t launch_table_install<real>(const float *, real *, int64_t, float *, hipStream_t);            \
     template hipError_t launch_taper2d<real>(const Geom &, const real *, const TaperBufs &, double *, hipStream_t);   \
     template hipError_t launch_taper2d_adjoint<real>(const Geom &, const double *, const TaperBufs &, double *,       \

@@ -1474,4 +1474,30 @@ rick_status rick_dft_image(rick_plan_t *p, const double *uvw, const double *freq
     return RICK_OK;
 }
 
+
+rick_status rick_separable_table(rick_plan_t *p, int32_t n_wbins, float *table, void *stream) {
+    if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
+    if (p->lut3) return fail(RICK_E_STATE, "the plan's kernel is a user table, not a separable one");
+    if (!is_pow2(n_wbins) || n_wbins > 8) return fail(RICK_E_INVALID_ARG, "n_wbins=%d: must be 1, 2, 4 or 8", n_wbins);
+    if (!table || ((uintptr_t)table & 3)) return fail(RICK_E_INVALID_ARG, "table is NULL or misaligned");
+    DeviceGuard guard(p->d.device);
+    const hipError_t e =
+        p->fp64 ? launch_separable_table<double>((const double *)p->lut, n_wbins, p->g.OS, p->g.W, table,
+                                                 (hipStream_t)stream)
+                : launch_separable_table<float>((const float *)p->lut, n_wbins, p->g.OS, p->g.W, table,
+                                                (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "separable table");
+    return RICK_OK;
+}
+
+rick_status rick_table_residual(const float *table, const float *target, int64_t n, double *dtable, double *sums,
+                                void *stream) {
+    if (!table || !target || !dtable || !sums || n < 1) return fail(RICK_E_INVALID_ARG, "NULL pointer or n < 1");
+    if (((uintptr_t)table & 3) || ((uintptr_t)target & 3) || ((uintptr_t)dtable & 7) || ((uintptr_t)sums & 7))
+        return fail(RICK_E_INVALID_ARG, "misaligned pointer");
+    const hipError_t e = launch_table_residual(table, target, n, dtable, sums, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "table residual");
+    return RICK_OK;
+}
+
 }  // extern "C"

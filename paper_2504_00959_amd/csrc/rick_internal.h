@@ -265,6 +265,9 @@ template <typename real>
 hipError_t launch_dft(const Geom &g, const double *uvw, const double *scales, const real *vis, const float *weight,
                       int64_t nrow, int32_t nchan, int q0, int p0, int nq, int np, double *out, double *wsum,
                       hipStream_t s);
+template <typename real>
+hipError_t launch_separable_table(const real *g, int nwf, int OS, int W, float *out, hipStream_t s);
+hipError_t launch_table_residual(const float *T, const float *R, int64_t n, double *dT, double *sums, hipStream_t s);
 // Every tile bit and row bit of every plane set (degrid.hip).
 hipError_t launch_fill_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
 

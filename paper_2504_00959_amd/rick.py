@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.c_float, P]
     L.rick_image_loss.argtypes = [P, P, P, P, P, P, P]
     L.rick_table_gradient.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_double), P, P, i64, i32, P, P]
+    L.rick_separable_table.argtypes = [P, i32, P, P]
+    L.rick_table_residual.argtypes = [P, P, i64, P, P, P]
     L.rick_dft_image.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, i64, i32, i32, i32, i32, i32, P, P]
     L.rick_fft_planes.argtypes = [P, P]
     L.rick_wstack_image.argtypes = [P, P, P]
@@ -132,7 +134,7 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_float)]
     for f in ("rick_plan_set_lut", "rick_mlp_tabulate", "rick_mlp_backward", "rick_adam_step", "rick_image_loss",
-              "rick_table_gradient", "rick_dft_image",
+              "rick_table_gradient", "rick_dft_image", "rick_separable_table", "rick_table_residual",
               "rick_plan", "rick_grid", "rick_grid_static", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
@@ -345,6 +347,20 @@ class Plan:
             t = np.ascontiguousarray(np.asarray(table, dtype=np.float32))
             _check(lib().rick_plan_set_lut(self._h, t.ctypes.data, 0, _stream_handle(stream)), "rick_plan_set_lut")
 
+    def separable_table(self, n_wbins: int, out=None, stream=None):
+        """rick_separable_table: this (Gaussian or Kaiser-Bessel) plan's taps as a
+        user table [n_wbins, OS, OS, W, W] (float32, device)."""
+        import torch
+        shape = (n_wbins, self.oversample, self.oversample, self.support, self.support)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=f"cuda:{self.device}")
+        self._device_tensor(out, "out", torch.float32)
+        if tuple(out.shape) != shape:
+            raise ValueError("out has the wrong shape")
+        _check(lib().rick_separable_table(self._h, n_wbins, out.data_ptr(), _stream_handle(stream)),
+               "rick_separable_table")
+        return out
+
     def taper(self):
         """Device float64 view of the taper the image is divided by: [N] (separable) or [N, N] (user table)."""
         inf = self.info()
@@ -540,6 +556,15 @@ def mlp_backward(theta, table, dtable, dtheta=None, stream=None):
     _check(lib().rick_mlp_backward(theta.data_ptr(), w, os_, n_wbins, table.data_ptr(), dtable.data_ptr(),
                                    dtheta.data_ptr(), _stream_handle(stream)), "rick_mlp_backward")
     return dtheta
+
+
+def table_residual(table, target, dtable, sums, stream=None):
+    """rick_table_residual: dtable = 2 (table - target) / n, sums[0] = mean squared difference."""
+    n = table.numel()
+    if target.numel() != n or dtable.numel() != n or sums.numel() < 1:
+        raise ValueError("sizes do not match")
+    _check(lib().rick_table_residual(table.data_ptr(), target.data_ptr(), n, dtable.data_ptr(), sums.data_ptr(),
+                                     _stream_handle(stream)), "rick_table_residual")
 
 
 def adam_step(theta, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -333,3 +333,35 @@ def ska_low_small(seed: int = 3, device: Optional[str] = None, **kw) -> Dataset:
                 grid_n=256, n_wplanes=12, oversample=32)
     args.update(kw)
     return ska_low(device=device, **args)
+
+
+# --------------------------------------------------------------------------
+# learned-kernel training scenes: tiny-style, 1..20 sources each
+# --------------------------------------------------------------------------
+def learned_scene(index: int, seed: int = 5, nvis: int = 1_000_000, grid_n: int = 256, n_wplanes: int = 16,
+                  fov: float = 0.2, uv_fill: float = 0.45, w_ratio: float = 50.0 / 120.0, max_src: int = 20,
+                  support: int = 7, oversample: int = 64, device: Optional[str] = None) -> Dataset:
+    """Scene ``index`` of the learned-kernel training set: the tiny workload's
+    generator (uniform-disk u, v in wavelengths, uniform w, unit weights) with
+    the disk radius u_max = uv_fill N / FoV, |w| <= w_ratio u_max (the tiny
+    workload's ratio), and 1..max_src point sources with |l|, |m| < FoV / 4 and
+    flux U[0.1, 1].  Each scene has its own generator, seeded (seed, index).
+    Draw order: source count, l, m, flux; then radius U, angle U, w U."""
+    rng = np.random.default_rng([seed, index])
+    n_src = int(rng.integers(1, max_src + 1))
+    l = rng.uniform(-0.25 * fov, 0.25 * fov, n_src)
+    m = rng.uniform(-0.25 * fov, 0.25 * fov, n_src)
+    flux = rng.uniform(0.1, 1.0, n_src)
+    umax = uv_fill * grid_n / fov
+    wmax = w_ratio * umax
+    r = umax * np.sqrt(rng.uniform(0.0, 1.0, nvis))
+    phi = 2.0 * np.pi * rng.uniform(0.0, 1.0, nvis)
+    w = rng.uniform(-wmax, wmax, nvis)
+    uvw = np.stack([r * np.cos(phi), r * np.sin(phi), w], axis=1)
+    if device is None:
+        vis = point_source_vis_np(uvw[:, 0], uvw[:, 1], uvw[:, 2], l, m, flux).astype(np.complex64).reshape(-1, 1)
+    else:
+        vis = point_source_vis_torch(uvw, [1.0], l, m, flux, device)
+    return Dataset(uvw=uvw, freq=None, vis=vis, weight=None, grid_n=grid_n, n_wplanes=n_wplanes,
+                   support=support, oversample=oversample, fov=fov, w_min=-wmax, w_max=wmax,
+                   sources=dict(l=l, m=m, flux=flux), name=f"learned_scene{index}")

@@ -261,3 +261,37 @@ def test_grid_16384():
     assert rel_rms(got * c2, ref * c2) <= 1e-5
     with pytest.raises(rick.RickError, match="RICK_E_UNSUPPORTED"):
         rick.Plan(**geo, max_vis=nrow, precision="fp64")
+
+
+def test_training_steps_reduce_the_loss():
+    """The training driver (library calls only): fitting the MLP to the
+    Gaussian table reproduces the Gaussian image's loss, and steps on one
+    scene lower its loss against the direct sum."""
+    import torch
+    import synth
+    from paper_2504_00959_amd.learned import LearnedKernel
+    kw = dict(nvis=30000, grid_n=64, n_wplanes=4, support=5, oversample=8)
+    s0 = synth.learned_scene(0, **kw)
+    lk = LearnedKernel(grid_n=64, n_wplanes=4, support=5, oversample=8, fov=s0.fov, w_min=s0.w_min, w_max=s0.w_max,
+                       max_vis=s0.nvis, n_wbins=2, seed=1)
+    try:
+        ds = synth.learned_scene(3, device="cuda:0", **kw)
+        uvw = torch.as_tensor(ds.uvw, dtype=torch.float64, device="cuda:0")
+        D = lk.target(uvw, ds.vis)
+        sums = torch.zeros((3, 2), dtype=torch.float64, device="cuda:0")
+        lk.loss(lk.gauss, uvw, ds.vis, D, sums[0])
+        mse = lk.fit_table(lk.gaussian_table(), steps=800, lr=3e-3)
+        lk.install()
+        lk.loss(lk.plan, uvw, ds.vis, D, sums[1])
+        for _ in range(40):
+            lk.step(uvw, ds.vis, D, sums[2], 1e-3)
+        lk.install()
+        lk.loss(lk.plan, uvw, ds.vis, D, sums[2])
+        s = sums.cpu().numpy()
+        L = s[:, 0] / s[:, 1]
+        print(f"[learned] fit mse {mse:.2e}; loss gaussian {L[0]:.4e}, fitted {L[1]:.4e}, after 40 steps {L[2]:.4e}")
+        assert mse < 1e-5
+        assert abs(L[1] - L[0]) < 0.1 * L[0]
+        assert L[2] < L[1]
+    finally:
+        lk.close()
