@@ -91,15 +91,17 @@ __host__ __device__ inline int64_t margin_len(int32_t T, int32_t W) {
 }
 
 // Heavy bins (several chunks) are zeroed before gridding, unless an earlier
-// rick_grid wrote the tile; the scan lists them.
+// rick_grid wrote the tile; the scan lists them.  Also zeroes the gridder's
+// work-item counter.
 template <typename real>
 __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t *__restrict__ heavy_bins,
-                                                           const Stats *__restrict__ st,
+                                                           Stats *__restrict__ st,
                                                            const uint64_t *__restrict__ tile_bits,
                                                            real *__restrict__ mesh, real *__restrict__ margin) {
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
     const int32_t nheavy = (int32_t)st->n_heavy;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->grid_next = 0;
     const int64_t mlen = margin_len(g.T, g.W);
     for (int32_t hb = blockIdx.x; hb < nheavy; hb += gridDim.x) {
         const int32_t b = heavy_bins[hb];
@@ -145,81 +147,81 @@ __device__ __forceinline__ unsigned long long fixed_of(double t) {
     return (unsigned long long)(uint32_t)(__double2hiint(t) - 0x43380000) << 32 | (uint32_t)__double2loint(t);
 }
 
+// Packed float32 accumulation (pk32): re and im of a cell share one 64-bit
+// LDS word, re in the low and im in the high 32 bits, as the integer
+// im 2^32 + re; one ds_add_u64 then adds both.  Each term is rounded to an
+// integer below 2^21 (the scale 2^s follows the bin's largest possible
+// term), and the block drains the LDS words into 64-bit integer sums held in
+// registers (each thread owns a fixed set of cells) after every round of at
+// most 1024 records, so a half never sums more than 1024 terms and stays
+// inside its signed 32 bits: re is the sign-extended low word, im the rest
+// shifted down by 32, exactly.  A term is rounded by one float32 fma against
+// 1.5 2^23, which leaves 1.5 2^23 + round(x) with bit pattern
+// 0x4B400000 + round(x) for |x| < 2^22; subtracting that constant from both
+// halves of the pair at once gives im 2^32 + re.  The precision is that of
+// the rounding, 2^-21 of the bin's largest possible term, whatever the
+// number of records.
+constexpr float kRoundMagic32 = 12582912.0f;   // 1.5 2^23
+constexpr unsigned long long kPackBias = 0x4B4000004B400000ull;
+constexpr int kPackTermBits = 21;
+__device__ __forceinline__ unsigned long long pack_terms(float tr, float ti) {
+    return (((unsigned long long)__float_as_uint(ti) << 32) | __float_as_uint(tr)) - kPackBias;
+}
+__device__ __forceinline__ void unpack_terms(unsigned long long s, long long &re, long long &im) {
+    const int32_t lo = (int32_t)(uint32_t)s;
+    re = lo;
+    im = ((long long)s - (long long)lo) >> 32;
+}
+
 // L3: the taps come from a non-separable table in device memory,
 // T[iw][s_y][s_x][t_y][t_x] (w-fraction bin iw in bits 6-7 and 14 of the
 // packed position), one value per tap instead of the product of two
 // separable rows held in LDS; tapmax points at the table's largest |value|.
-template <typename real, int W, int TT, bool L3>
-__global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan *__restrict__ scan,
+// P32: packed float32 accumulation (above); float64 re and im planes otherwise.
+// Persistent: a block takes work items blockIdx.x, then the next unclaimed
+// one from st->grid_next (claimed while the current one is gridded), until
+// the device-side item count is reached.
+template <typename real, int W, int TT, bool L3, bool P32>
+__global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom g, const BinScan *__restrict__ scan,
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
                                                      const real *__restrict__ rec_vis, const real *__restrict__ lut,
                                                      real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
                                                      real *__restrict__ margin,
                                                      const uint32_t *__restrict__ bin_vmax,
-                                                     const float *__restrict__ tapmax) {
+                                                     const float *__restrict__ tapmax, Stats *__restrict__ st) {
+    static_assert(!P32 || std::is_same<real, float>::value, "packed accumulation is a float32 mode");
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
-    constexpr int H = (W - 1) / 2;
     constexpr int kGridBlock = grid_threads(TT);
     constexpr int nwave = kGridBlock / 64;
     constexpr int KOFF = im_plane_offset<W, TT>();   // TT == g.T
+    // packed mode: LDS cells owned per thread (cell i by thread i mod the block size)
+    constexpr int CPT = ((TT + W - 1) * acc_pitch(TT, W) + kGridBlock - 1) / kGridBlock;
+    static_assert(kGridBlock <= (1 << (31 - kPackTermBits)), "a drain round must stay within 32-bit halves");
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t s_next[2];
     const int32_t total = scan[g.nbins].item;
-    const int32_t item = blockIdx.x;
-    if (item >= total) return;
-    const int32_t b = item_bin[item];
-    const int32_t first = scan[b].item;
-    const int32_t nchunk = scan[b + 1].item - first;
-    const int32_t chunk = item - first;
-    const int32_t r_begin = scan[b].rec + chunk * g.CH;
-    int32_t r_end = r_begin + g.CH;
-    if (r_end > scan[b + 1].rec) r_end = scan[b + 1].rec;
-    const int32_t n = r_end - r_begin;
+    if ((int32_t)blockIdx.x >= total) return;
 
     const int32_t T = g.T, P = g.pitch;
-    const int32_t k = b / (g.nt * g.nt);
-    const int32_t rem = b - k * g.nt * g.nt;
-    const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
-    if (n <= 0) return;   // (empty bins have no work item)
-    // float32 mode: 64-bit fixed point with scale 2^s (see the file comment)
+    // float32 modes: 64-bit fixed point with scale 2^s (see the file comment)
     constexpr bool FIX = std::is_same<real, float>::value;
     using acc_t = typename std::conditional<FIX, unsigned long long, double>::type;
-    double scale = 1.0, unscale = 1.0;
-    if (FIX) {
-        const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
-        // largest |term|: |W V| times the largest |tap| (the square of the
-        // largest separable row value, or the largest entry of the table)
-        const double bt = vmax * (L3 ? (double)*tapmax * (1.0 + 1e-6) : (double)g.gmax2);
-        if (bt > 0.0 && bt < 1e300) {
-            const int et = ilogb(bt) + 1, en = ilogb((double)n) + 1;   // bt < 2^et, n < 2^en
-            const int sh = min(50 - et, 61 - et - en);
-            scale = ldexp(1.0, sh);
-            unscale = ldexp(1.0, -sh);
-        }
-    }
-    // accumulated value of LDS word i of a plane
-    auto acc_value = [&](const acc_t *a, int32_t i) -> real {
-        if constexpr (FIX) return (real)((double)(long long)a[i] * unscale);
-        else return (real)a[i];
-    };
-    // LDS: real plane at byte 0, imaginary plane KOFF doubles further, then
-    // the tap table; a plane is R = T + W - 1 rows of pitch P
+    using vreg_t = typename std::conditional<P32, float, double>::type;   // W V as the taps multiply it
+    // LDS: real plane at byte 0, imaginary plane KOFF doubles further (not
+    // with P32), then the tap table; a plane is R = T + W - 1 rows of pitch P
     constexpr int R_PAD = W - 1;
     const int32_t R = T + R_PAD;
     acc_t *acc_re = reinterpret_cast<acc_t *>(smem);
     acc_t *acc_im = acc_re + KOFF;
-    const int32_t lut_byte = (KOFF + R * P) * (int32_t)sizeof(double);
+    const int32_t lut_byte = ((P32 ? 0 : KOFF) + R * P) * (int32_t)sizeof(double);
     real *s_lut = reinterpret_cast<real *>(smem + lut_byte);
-    for (int i = threadIdx.x; i < R * P; i += kGridBlock) {
-        acc_re[i] = 0;
-        acc_im[i] = 0;
-    }
     if (!L3)
         for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
-    __syncthreads();
+    // (visible after the first item's barrier)
 
     const int lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -238,164 +240,265 @@ __global__ __launch_bounds__(grid_threads(TT)) void k_grid(Geom g, const BinScan
         lut_y[gi] = L3 ? (on ? t : W2 - 1) : lut_byte + ty * (int)sizeof(real);
     }
 
-    // this wave's batches of 64 records, one record per lane; the next
-    // batch's raw fields are loaded while the current one is gridded
-    const int32_t nbatch = (n + 63) >> 6;
-    int32_t bt = wave;
-    uint32_t raw_pos = 0;
-    real raw_vr = 0, raw_vi = 0;
-    auto fetch = [&](int32_t bi) {
-        const int32_t r = r_begin + (bi << 6) + lane;
-        if (r < r_end) {
-            raw_pos = rec_pos[r];
-            raw_vr = rec_vis[2 * (int64_t)r];
-            raw_vi = rec_vis[2 * (int64_t)r + 1];
-        }
-    };
-    if (bt < nbatch) fetch(bt);
-    for (; bt < nbatch; bt += nwave) {
-        const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
-        // decode this lane's record: byte offset of the footprint origin in
-        // the real plane, tap-table row byte offsets and visibility (lanes
-        // past the batch keep zeros: they add 0 at the region's origin)
-        int32_t d_base8 = 0, d_lxy = 0;
-        double d_vr = 0, d_vi = 0;   // W V (times 2^s in float32 mode; exact)
-        if (lane < cnt) {
-            const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
-            if constexpr (L3) {
-                const int ox = (int)(raw_pos & 0x3fu), oy = (int)((raw_pos >> 8) & 0x3fu);   // in [0, T)
-                const int iw = (int)((raw_pos >> 6) & 3u) | (int)((raw_pos >> 14) & 1u) << 2;
-                d_base8 = (oy * P + ox) * (int)sizeof(double);
-                d_lxy = ((iw * g.OS + sy) * g.OS + sx) * W2;   // first entry of the record's table row
-            } else {
-                const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
-                d_base8 = (oy * P + ox) * (int)sizeof(double);
-                d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
+    int32_t item = blockIdx.x;
+    for (int it = 0; item < total; ++it) {
+        // claim the next item now; it is read after this one's last barrier
+        if (threadIdx.x == 0) s_next[it & 1] = (int32_t)gridDim.x + (int32_t)atomicAdd(&st->grid_next, 1ull);
+        const int32_t b = item_bin[item];
+        const int32_t first = scan[b].item;
+        const int32_t nchunk = scan[b + 1].item - first;
+        const int32_t chunk = item - first;
+        const int32_t r_begin = scan[b].rec + chunk * g.CH;
+        int32_t r_end = r_begin + g.CH;
+        if (r_end > scan[b + 1].rec) r_end = scan[b + 1].rec;
+        const int32_t n = r_end - r_begin;   // > 0: empty bins have no work item
+        const int32_t k = b / (g.nt * g.nt);
+        const int32_t rem = b - k * g.nt * g.nt;
+        const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
+        double scale = 1.0, unscale = 1.0;
+        if (FIX) {
+            const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
+            // largest |term|: |W V| times the largest |tap| (the square of the
+            // largest separable row value, or the largest entry of the table)
+            const double bt = vmax * (L3 ? (double)*tapmax * (1.0 + 1e-6) : (double)g.gmax2);
+            if (bt > 0.0 && bt < 1e300) {
+                const int et = ilogb(bt) + 1, en = ilogb((double)n) + 1;   // bt < 2^et, n < 2^en
+                int sh = P32 ? kPackTermBits - et : min(50 - et, 61 - et - en);
+                if (P32) sh = min(sh, 120);   // 2^s stays a normal float32
+                scale = ldexp(1.0, sh);
+                unscale = ldexp(1.0, -sh);
             }
-            d_vr = (double)raw_vr * scale;
-            d_vi = (double)raw_vi * scale;
         }
-        if (bt + nwave < nbatch) fetch(bt + nwave);
-
-        // tap-table values of one group of records (indices past the batch
-        // wrap to lanes holding a switched-off record: the reads stay in the
-        // table and their values go unused)
-        auto lut_reads = [&](int j, real (&gy)[kGroup][NG], real (&gx)[kGroup][NG]) {
+        // packed mode: this thread's cells' sums (cell threadIdx.x + j kGridBlock)
+        long long own_re[P32 ? CPT : 1], own_im[P32 ? CPT : 1];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const int32_t lxy = bcast(d_lxy, (j + q) & 63);
-                if constexpr (L3) {
+        for (int j = 0; j < (P32 ? CPT : 1); ++j) own_re[j] = own_im[j] = 0;
+        auto drain = [&]() {
 #pragma unroll
-                    for (int gi = 0; gi < NG; ++gi) {
-                        gy[q][gi] = lut[lxy + lut_y[gi]];
-                        gx[q][gi] = (real)1;
-                    }
-                } else {
-                    const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
-#pragma unroll
-                    for (int gi = 0; gi < NG; ++gi) {
-                        gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
-                        gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
-                    }
+            for (int j = 0; j < CPT; ++j) {
+                const int32_t i = (int32_t)threadIdx.x + j * kGridBlock;
+                if (i < R * P) {
+                    long long re, im;
+                    unpack_terms(acc_re[i], re, im);
+                    acc_re[i] = 0;
+                    own_re[j] += re;
+                    own_im[j] += im;
                 }
             }
         };
-        auto add_group = [&](int j, const real (&gy)[kGroup][NG], const real (&gx)[kGroup][NG]) {
+        // accumulated value of LDS cell i (packed mode: the float32 pair the
+        // owners stored there after the last drain)
+        auto cell = [&](int32_t i, real &re, real &im) {
+            if constexpr (P32) {
+                const float2 v = reinterpret_cast<const float2 *>(acc_re)[i];
+                re = v.x;
+                im = v.y;
+            } else if constexpr (FIX) {
+                re = (real)((double)(long long)acc_re[i] * unscale);
+                im = (real)((double)(long long)acc_im[i] * unscale);
+            } else {
+                re = (real)acc_re[i];
+                im = (real)acc_im[i];
+            }
+        };
+        for (int i = threadIdx.x; i < R * P; i += kGridBlock) {
+            acc_re[i] = 0;
+            if (!P32) acc_im[i] = 0;
+        }
+        __syncthreads();
+
+        // this wave's batches of 64 records, one record per lane; the next
+        // batch's raw fields are loaded while the current one is gridded
+        const int32_t nbatch = (n + 63) >> 6;
+        uint32_t raw_pos = 0;
+        real raw_vr = 0, raw_vi = 0;
+        auto fetch = [&](int32_t bi) {
+            const int32_t r = r_begin + (bi << 6) + lane;
+            if (r < r_end) {
+                raw_pos = rec_pos[r];
+                raw_vr = rec_vis[2 * (int64_t)r];
+                raw_vi = rec_vis[2 * (int64_t)r + 1];
+            }
+        };
+        if (wave < nbatch) fetch(wave);
+        // rounds of one batch per wave (packed mode: drained after each round)
+        for (int32_t round0 = 0; round0 < nbatch; round0 += nwave) {
+          const int32_t bt = round0 + wave;
+          if (bt < nbatch) {
+            const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
+            // decode this lane's record: byte offset of the footprint origin in
+            // the real plane, tap-table row byte offsets and visibility (lanes
+            // past the batch keep zeros: they add 0 at the region's origin)
+            int32_t d_base8 = 0, d_lxy = 0;
+            vreg_t d_vr = 0, d_vi = 0;   // W V times 2^s in float32 modes (exact)
+            if (lane < cnt) {
+                const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
+                if constexpr (L3) {
+                    const int ox = (int)(raw_pos & 0x3fu), oy = (int)((raw_pos >> 8) & 0x3fu);   // in [0, T)
+                    const int iw = (int)((raw_pos >> 6) & 3u) | (int)((raw_pos >> 14) & 1u) << 2;
+                    d_base8 = (oy * P + ox) * (int)sizeof(double);
+                    d_lxy = ((iw * g.OS + sy) * g.OS + sx) * W2;   // first entry of the record's table row
+                } else {
+                    const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
+                    d_base8 = (oy * P + ox) * (int)sizeof(double);
+                    d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
+                }
+                d_vr = (vreg_t)((double)raw_vr * scale);
+                d_vi = (vreg_t)((double)raw_vi * scale);
+            }
+            if (bt + nwave < nbatch) fetch(bt + nwave);
+
+            // tap-table values of one group of records (indices past the batch
+            // wrap to lanes holding a switched-off record: the reads stay in the
+            // table and their values go unused)
+            auto lut_reads = [&](int j, real (&gy)[kGroup][NG], real (&gx)[kGroup][NG]) {
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const int32_t base8 = bcast(d_base8, (j + q) & 63);
-                const double vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
+                for (int q = 0; q < kGroup; ++q) {
+                    const int32_t lxy = bcast(d_lxy, (j + q) & 63);
+                    if constexpr (L3) {
 #pragma unroll
-                for (int gi = 0; gi < NG; ++gi) {
-                    // lanes holding a tap of group gi (a compile-time mask)
-                    constexpr uint64_t kAll = ~0ull;
-                    const uint64_t m = W2 - 64 * gi >= 64 ? kAll : (1ull << (W2 - 64 * gi)) - 1;
-                    // the products are formed outside the branch, so the wait
-                    // for the table values is the same on every path
-                    const real wgt = gy[q][gi] * gx[q][gi];
-                    double tr, ti;
-                    if constexpr (FIX) {
-                        // round(g V 2^s) in the low mantissa bits (exact product, one rounding)
-                        tr = fma((double)wgt, vr, kRoundMagic);
-                        ti = fma((double)wgt, vi, kRoundMagic);
+                        for (int gi = 0; gi < NG; ++gi) {
+                            gy[q][gi] = lut[lxy + lut_y[gi]];
+                            gx[q][gi] = (real)1;
+                        }
                     } else {
-                        tr = wgt * vr;
-                        ti = wgt * vi;
-                    }
-                    __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
-                    // (with one tap group the whole record loop already runs on the tap lanes)
-                    if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(m)) {
-                        acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
-                        if constexpr (FIX) {
-                            atomicAdd(a, fixed_of(tr));
-                            atomicAdd(a + KOFF, fixed_of(ti));
-                        } else {
-                            atomicAdd(a, tr);
-                            atomicAdd(a + KOFF, ti);
+                        const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
+#pragma unroll
+                        for (int gi = 0; gi < NG; ++gi) {
+                            gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
+                            gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
                         }
                     }
                 }
-            }
-        };
-        // two table buffers used in turn: the reads for group j + kGroup are
-        // issued before the atomics of group j, and no value is copied.  With
-        // one tap group (W <= 7) the loop runs on the tap lanes only: the
-        // execution mask is set once per batch, not per record (readlane
-        // reads the records of the other lanes regardless).
-        if (NG > 1 || lane < W2) {
-            real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
-            lut_reads(0, ay, ax);
+            };
+            auto add_group = [&](int j, const real (&gy)[kGroup][NG], const real (&gx)[kGroup][NG]) {
 #pragma unroll
-            for (int j = 0; j < 64; j += 2 * kGroup) {
-                lut_reads(j + kGroup, by, bx);
-                add_group(j, ay, ax);
-                if (j + kGroup >= cnt) break;
-                lut_reads(j + 2 * kGroup, ay, ax);
-                add_group(j + kGroup, by, bx);
-                if (j + 2 * kGroup >= cnt) break;
+                for (int q = 0; q < kGroup; ++q) {
+                    const int32_t base8 = bcast(d_base8, (j + q) & 63);
+                    const vreg_t vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
+#pragma unroll
+                    for (int gi = 0; gi < NG; ++gi) {
+                        // lanes holding a tap of group gi (a compile-time mask)
+                        constexpr uint64_t kAll = ~0ull;
+                        const uint64_t msk = W2 - 64 * gi >= 64 ? kAll : (1ull << (W2 - 64 * gi)) - 1;
+                        // the products are formed outside the branch, so the wait
+                        // for the table values is the same on every path
+                        const real wgt = gy[q][gi] * gx[q][gi];
+                        if constexpr (P32) {
+                            // round(g V 2^s) of re and im, then both as one 64-bit word
+                            float tr = fmaf(wgt, vr, kRoundMagic32);
+                            float ti = fmaf(wgt, vi, kRoundMagic32);
+                            __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
+                            if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
+                                acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
+                                atomicAdd(a, pack_terms(tr, ti));
+                            }
+                        } else {
+                            double tr, ti;
+                            if constexpr (FIX) {
+                                // round(g V 2^s) in the low mantissa bits (exact product, one rounding)
+                                tr = fma((double)wgt, vr, kRoundMagic);
+                                ti = fma((double)wgt, vi, kRoundMagic);
+                            } else {
+                                tr = wgt * vr;
+                                ti = wgt * vi;
+                            }
+                            __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
+                            // (with one tap group the whole record loop already runs on the tap lanes)
+                            if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
+                                acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
+                                if constexpr (FIX) {
+                                    atomicAdd(a, fixed_of(tr));
+                                    atomicAdd(a + KOFF, fixed_of(ti));
+                                } else {
+                                    atomicAdd(a, tr);
+                                    atomicAdd(a + KOFF, ti);
+                                }
+                            }
+                        }
+                    }
+                }
+            };
+            // two table buffers used in turn: the reads for group j + kGroup are
+            // issued before the atomics of group j, and no value is copied.  With
+            // one tap group (W <= 7) the loop runs on the tap lanes only: the
+            // execution mask is set once per batch, not per record (readlane
+            // reads the records of the other lanes regardless).
+            if (NG > 1 || lane < W2) {
+                real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
+                lut_reads(0, ay, ax);
+#pragma unroll
+                for (int j = 0; j < 64; j += 2 * kGroup) {
+                    lut_reads(j + kGroup, by, bx);
+                    add_group(j, ay, ax);
+                    if (j + kGroup >= cnt) break;
+                    lut_reads(j + 2 * kGroup, ay, ax);
+                    add_group(j + kGroup, by, bx);
+                    if (j + 2 * kGroup >= cnt) break;
+                }
+            }
+          }
+          if constexpr (P32) {
+              __syncthreads();   // the round's atomics are done
+              drain();
+              __syncthreads();   // the cells are zero again
+          }
+        }
+        if constexpr (P32) {
+            // the sums as float32 pairs in the cells, for the row-coalesced flush
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int32_t i = (int32_t)threadIdx.x + j * kGridBlock;
+                if (i < R * P)
+                    reinterpret_cast<float2 *>(acc_re)[i] =
+                        float2{(float)((double)own_re[j] * unscale), (float)((double)own_im[j] * unscale)};
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    const bool shared_tile = nchunk > 1;
-    const bool accumulate = tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
-    for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
-        const int32_t y = c >> g.log2T, x = c & (T - 1);
-        const real re = acc_value(acc_re, y * P + x), im = acc_value(acc_im, y * P + x);
-        r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
-        if (shared_tile) {
-            if (re != 0) atomic_add_real(&dst->x, re);
-            if (im != 0) atomic_add_real(&dst->y, im);
-        } else if (accumulate) {
-            const r2 old = *dst;
-            *dst = r2{old.x + re, old.y + im};
-        } else {
-            *dst = r2{re, im};
-        }
-    }
-    // margins to the bin's margin buffer (the merge adds them to the neighbours)
-    if constexpr (R_PAD > 0) {
-        r2 *mb = reinterpret_cast<r2 *>(margin) + (int64_t)b * margin_len(T, W);
-        const int32_t n_right = R * R_PAD, n_all = n_right + R_PAD * T;
-        for (int32_t c = threadIdx.x; c < n_all; c += kGridBlock) {
-            int32_t y, x;
-            if (c < n_right) {
-                y = c / R_PAD;
-                x = T + (c - y * R_PAD);
-            } else {
-                const int32_t d = c - n_right;
-                y = T + (d >> g.log2T);
-                x = d & (T - 1);
-            }
-            const real re = acc_value(acc_re, y * P + x), im = acc_value(acc_im, y * P + x);
+        const bool shared_tile = nchunk > 1;
+        const bool accumulate = tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
+        for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
+            const int32_t y = c >> g.log2T, x = c & (T - 1);
+            real re, im;
+            cell(y * P + x, re, im);
+            r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
             if (shared_tile) {
-                if (re != 0) atomic_add_real(&mb[c].x, re);
-                if (im != 0) atomic_add_real(&mb[c].y, im);
+                if (re != 0) atomic_add_real(&dst->x, re);
+                if (im != 0) atomic_add_real(&dst->y, im);
+            } else if (accumulate) {
+                const r2 old = *dst;
+                *dst = r2{old.x + re, old.y + im};
             } else {
-                mb[c] = r2{re, im};
+                *dst = r2{re, im};
             }
         }
+        // margins to the bin's margin buffer (the merge adds them to the neighbours)
+        if constexpr (R_PAD > 0) {
+            r2 *mb = reinterpret_cast<r2 *>(margin) + (int64_t)b * margin_len(T, W);
+            const int32_t n_right = R * R_PAD, n_all = n_right + R_PAD * T;
+            for (int32_t c = threadIdx.x; c < n_all; c += kGridBlock) {
+                int32_t y, x;
+                if (c < n_right) {
+                    y = c / R_PAD;
+                    x = T + (c - y * R_PAD);
+                } else {
+                    const int32_t d = c - n_right;
+                    y = T + (d >> g.log2T);
+                    x = d & (T - 1);
+                }
+                real re, im;
+                cell(y * P + x, re, im);
+                if (shared_tile) {
+                    if (re != 0) atomic_add_real(&mb[c].x, re);
+                    if (im != 0) atomic_add_real(&mb[c].y, im);
+                } else {
+                    mb[c] = r2{re, im};
+                }
+            }
+        }
+        __syncthreads();   // the accumulators are read out; s_next is written
+        item = s_next[it & 1];
     }
 }
 
@@ -507,46 +610,73 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
     }
 }
 
-template <typename real, int W, int TT, bool L3>
+// CUs of the current device (queried once per device)
+int device_cus() {
+    static int cus[kMaxDevices];
+    static std::once_flag once[kMaxDevices];
+    once_per_device(once, [&] {
+        int dev = 0, n = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        if (dev >= 0 && dev < kMaxDevices) cus[dev] = n;
+    });
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return (dev >= 0 && dev < kMaxDevices && cus[dev] > 0) ? cus[dev] : 256;
+}
+
+template <typename real, int W, int TT, bool L3, bool P32>
 hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                   const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
+                   const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static std::once_flag attr_once[kMaxDevices];
     once_per_device(attr_once, [&] {
-        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT, L3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(160 * 1024));
+        // (the kernel's own 8 bytes of static LDS come on top of the dynamic size)
+        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT, L3, P32>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - 64));
     });
-    hipLaunchKernelGGL((k_grid<real, W, TT, L3>), dim3(max_items), dim3(grid_threads(TT)), lds, s, g, scan, item_bin,
-                       rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, tapmax);
+    // persistent blocks: as many as the CUs hold at once (LDS and 32 waves per CU)
+    int per_cu = int((160 * 1024) / (lds + 64));
+    const int by_waves = 2048 / grid_threads(TT);
+    per_cu = per_cu < by_waves ? per_cu : by_waves;
+    per_cu = per_cu < 1 ? 1 : per_cu;
+    const int64_t want = int64_t(device_cus()) * per_cu;
+    const int64_t nblk = want < max_items ? want : max_items;
+    hipLaunchKernelGGL((k_grid<real, W, TT, L3, P32>), dim3((unsigned)(nblk > 0 ? nblk : 1)), dim3(grid_threads(TT)),
+                       lds, s, g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, tapmax,
+                       st);
     return hipGetLastError();
 }
 
 template <typename real, int W, int TT>
 hipError_t grid_wt2(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                     const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                    const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
-    if (tapmax)
-        return grid_wt<real, W, TT, true>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                          tapmax, max_items, s);
-    return grid_wt<real, W, TT, false>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                       tapmax, max_items, s);
+                    const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
+#define GRID_WT(L3, P32) \
+    grid_wt<real, W, TT, L3, P32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
+                                  tapmax, st, max_items, s)
+    if constexpr (std::is_same<real, float>::value) {
+        if (g.pk32) return tapmax ? GRID_WT(true, true) : GRID_WT(false, true);
+    }
+    return tapmax ? GRID_WT(true, false) : GRID_WT(false, false);
+#undef GRID_WT
 }
 
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                  const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
+                  const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
     switch (g.T) {
         case 16:
             return grid_wt2<real, W, 16>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                         tapmax, max_items, s);
+                                         tapmax, st, max_items, s);
         case 32:
             return grid_wt2<real, W, 32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                         tapmax, max_items, s);
+                                         tapmax, st, max_items, s);
         case 64:
             return grid_wt2<real, W, 64>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                         tapmax, max_items, s);
+                                         tapmax, st, max_items, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -554,9 +684,9 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
 }  // namespace
 
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
-    // real plane, imaginary plane at plane_offset(W, T) doubles, each T + W - 1
-    // rows of the pitch; then the tap table
-    const size_t koff = size_t(plane_offset(g.W, g.T));
+    // real plane, imaginary plane at plane_offset(W, T) doubles (packed mode:
+    // one plane of 64-bit words), each T + W - 1 rows of the pitch; then the tap table
+    const size_t koff = (g.pk32 && real_bytes == 4) ? 0 : size_t(plane_offset(g.W, g.T));
     return (koff + size_t(g.T + g.W - 1) * g.pitch) * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
 }
 
@@ -569,7 +699,7 @@ hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
 }
 
 template <typename real>
-hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, const uint64_t *tile_bits,
+hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, Stats *st, const uint64_t *tile_bits,
                              real *mesh, real *margin, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, tile_bits, mesh,
                        margin);
@@ -597,12 +727,12 @@ hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_b
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s) {
+                       const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
     case w: \
         return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
-                               tapmax, max_items, s);
+                               tapmax, st, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -611,9 +741,9 @@ hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_b
 
 template hipError_t launch_zero_mesh<float>(float *, int64_t, hipStream_t);
 template hipError_t launch_zero_mesh<double>(double *, int64_t, hipStream_t);
-template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, const Stats *, const uint64_t *, float *,
+template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, Stats *, const uint64_t *, float *,
                                              float *, hipStream_t);
-template hipError_t launch_zero_heavy<double>(const Geom &, const int32_t *, const Stats *, const uint64_t *,
+template hipError_t launch_zero_heavy<double>(const Geom &, const int32_t *, Stats *, const uint64_t *,
                                               double *, double *, hipStream_t);
 template hipError_t launch_merge_margins<float>(const Geom &, const BinScan *, const float *, uint64_t *, uint64_t *,
                                                 float *, hipStream_t);
@@ -621,9 +751,9 @@ template hipError_t launch_merge_margins<double>(const Geom &, const BinScan *, 
                                                  uint64_t *, double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                        const float *, const float *, float *, const uint64_t *, float *,
-                                       const uint32_t *, const float *, int32_t, hipStream_t);
+                                       const uint32_t *, const float *, Stats *, int32_t, hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                         const double *, const double *, double *, const uint64_t *, double *,
-                                        const uint32_t *, const float *, int32_t, hipStream_t);
+                                        const uint32_t *, const float *, Stats *, int32_t, hipStream_t);
 
 }  // namespace rick

@@ -277,6 +277,9 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     Geom &g = p->g;
     g.N = d->grid_n;
     g.Nw = d->n_wplanes;
+    // float32 without the compensated sum: re and im accumulate as the two
+    // 32-bit halves of one 64-bit fixed-point word (one LDS atomic per tap)
+    g.pk32 = d->precision == RICK_PREC_FP32 ? 1 : 0;
     g.W = d->support;
     g.h = (d->support - 1) / 2;
     g.OS = d->oversample;
@@ -317,9 +320,9 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         g.pitch = pitch;
     }
     {
-        // the gridding block keeps two (T + W - 1) x pitch float64 accumulators and the tap table in LDS
+        // the gridding block keeps its (T + W - 1) x pitch 64-bit accumulators and the tap table in LDS
         const size_t lds = grid_lds_bytes(g, p->fp64 ? 8 : 4);
-        if (lds > size_t(160) * 1024) {
+        if (lds > size_t(160) * 1024 - 64) {   // (64 bytes stay for the kernel's static LDS)
             delete p;
             return fail(RICK_E_INVALID_ARG, "tile=%d with support %d, oversample %d needs %zu B of LDS (> 160 KB)",
                         g.T, g.W, g.OS, lds);
@@ -653,11 +656,11 @@ rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, cons
     if (p->fp64)
         e = launch_grid<double>(g, bb.scan, bb.item_bin, bb.rec_pos, (const double *)bb.rec_vis,
                                 (const double *)p->lut, (double *)p->mesh, p->tile_bits, (double *)p->margin,
-                                bb.bin_vmax, p->lut3 ? p->tapmax : nullptr, max_items, s);
+                                bb.bin_vmax, p->lut3 ? p->tapmax : nullptr, p->stats, max_items, s);
     else
         e = launch_grid<float>(g, bb.scan, bb.item_bin, bb.rec_pos, (const float *)bb.rec_vis, (const float *)p->lut,
                                (float *)p->mesh, p->tile_bits, (float *)p->margin, bb.bin_vmax,
-                               p->lut3 ? p->tapmax : nullptr, max_items, s);
+                               p->lut3 ? p->tapmax : nullptr, p->stats, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
     timer_begin(p, T_MARK, "merge_margins", s);

@@ -66,6 +66,7 @@ struct Geom {
     int32_t cpt1;       // level-1 records in the compact 12-byte format (float32 mode, when it fits)
     int32_t nwf;        // w-fraction bins of a non-separable tap table (1 otherwise)
     int32_t lut3;       // 1: the taps come from a non-separable table T[nwf][OS][OS][W][W]
+    int32_t pk32;       // 1: gridding sums re and im as two 32-bit fixed-point halves of one 64-bit word
     double fov;
     double half;        // N * OS / 2
     double w_min;
@@ -80,7 +81,8 @@ struct Stats {
     unsigned long long n_heavy;     // bins of the last rick_grid split over several chunks
     double sum_w;
     unsigned long long n_chunks;    // level-2 binning chunks of the last rick_grid
-    double pad2[2];
+    unsigned long long grid_next;   // gridding work items handed out (zeroed before each gridding launch)
+    double pad2;
 };
 
 // Binning bookkeeping written by the scan: per bin, exclusive prefix sums of
@@ -173,7 +175,8 @@ template <typename real>
 hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int32_t nchan, Stats *st, int phase,
                              hipStream_t s);
 // Gridding: zero the heavy tiles that hold nothing yet (and the margin
-// buffers of heavy bins), then one block per (bin, chunk) item; tiles set in
+// buffers of heavy bins, and the work-item counter), then persistent blocks
+// that take (bin, chunk) items from the counter; tiles set in
 // tile_bits are added to, others stored; each bin's margins go to its margin
 // buffer (grid_margin_len complex values per bin).
 // With tapmax non-NULL, lut is a non-separable table T[N_f][OS][OS][W][W]
@@ -181,12 +184,12 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const uint32_t *bin_vmax, const float *tapmax, int32_t max_items, hipStream_t s);
-// LDS bytes of one gridding block (float64 accumulators + tap table)
+                       const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s);
+// LDS bytes of one gridding block (64-bit accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 int64_t grid_margin_len(const Geom &g);
 template <typename real>
-hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, const Stats *st, const uint64_t *tile_bits,
+hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, Stats *st, const uint64_t *tile_bits,
                              real *mesh, real *margin, hipStream_t s);
 // After gridding: add the margins to the neighbouring tiles, set the tile
 // bits (records or margins received) and rebuild the row bits.

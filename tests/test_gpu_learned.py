@@ -2,8 +2,8 @@
 sum kernel, and the 16384^2 grid, through the C ABI, against the float64
 oracle (``oracle.learned``, ``oracle.dft``, ``oracle.pixels``).
 
-Tolerances: float32 stages 1e-6 relative RMS (planes, taper exact to 1e-12
-as it is float64 on both sides), end-to-end float32 image 1e-5 on the
+Tolerances: float32 stages 1e-6 relative RMS (planes 5e-6: packed 32-bit
+fixed-point sums; taper exact to 1e-12 as it is float64 on both sides), end-to-end float32 image 1e-5 on the
 apparent image and the central region (as in the other parity tests), the
 float32 MLP 2e-6 absolute on table entries (each row sums to 1) and 1e-4
 relative on parameter gradients, the direct sum 2e-6 relative (float32
@@ -73,8 +73,10 @@ def test_separable_table_matches_gaussian_plan(precision):
         C2 = pu.taper().cpu().numpy()
         c1 = pg.taper().cpu().numpy()
     # the float32 table entries are the float32 rounding of g_y g_x, not the
-    # product of the rounded rows: agreement to float32 rounding
-    tol = 1e-6 if precision == "fp32" else 1e-7
+    # product of the rounded rows: agreement to float32 rounding, and in the
+    # float32 mode to the packed sums' rounding of each term (2^-21 of the
+    # bin's largest), which a one-ulp difference in a tap can move by one step
+    tol = 5e-6 if precision == "fp32" else 1e-7
     assert rel_rms(Gu, Gg) <= tol
     assert np.max(np.abs(C2 - np.outer(c1, c1))) < 1e-7
     assert image_errors(iu, ig, c1)["apparent"] <= tol
@@ -98,7 +100,8 @@ def test_learned_table_image_parity(precision, tol):
         info = pu.info()
     assert info["n_gridded"] == int(ref.binned.keep.sum())
     assert np.max(np.abs(C2 - ref.corr2)) < 1e-12
-    assert rel_rms(G, ref.planes) <= (1e-6 if precision == "fp32" else 1e-12)
+    # float32: packed 32-bit fixed-point sums (terms rounded at 2^-21 of the bin's largest)
+    assert rel_rms(G, ref.planes) <= (5e-6 if precision == "fp32" else 1e-12)
     err = image_errors(img, ref.image, np.ones(geo["grid_n"]))   # compare with the 2-D taper below
     app = rel_rms(img * ref.corr2, ref.apparent)
     print(f"[learned] {precision}: planes {rel_rms(G, ref.planes):.2e}, apparent {app:.2e}, image {err['full']:.2e}")
