@@ -606,10 +606,11 @@ def batch_report(args):
     t0 = time.time()
     for key, idx in sorted(shapes.items()):
         big = max(idx, key=lambda i: jobs[i].nvis)
-        tile, chunk, ms = rick.autotune(jobs[big], uvw[big], vis[big], fused=True, stream=stream)
+        tile, chunk, ms = rick.autotune(jobs[big], uvw[big], vis[big], fused=True, stream=stream,
+                                        orient=not args.no_orient)
         tuned[key] = (tile, chunk, ms)
         plans[key] = rick.Plan.for_dataset(jobs[big], max_vis=max(jobs[i].nvis for i in idx), tile=tile,
-                                           chunk=chunk, fused=True)
+                                           chunk=chunk, fused=True, orient=not args.no_orient)
     print(f"[batch] autotuned {len(shapes)} shapes in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     imgs = [torch.empty((ds.grid_n, ds.grid_n), dtype=torch.float32, device=dev) for ds in jobs]
 
@@ -1032,6 +1033,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the batched form: many uneven jobs recorded into a graph and replayed (jobs/s, latency)")
     ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
+    ap.add_argument("--no-orient", action="store_true",
+                    help="--batch: keep every plane in its own orientation (no transposed planes)")
     ap.add_argument("--streams", type=int, default=4,
                     help="streams of the concurrent run of --batch (1 = only the one-stream run)")
     ap.add_argument("--learned", action="store_true",

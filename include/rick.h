@@ -87,10 +87,18 @@ enum {
 
 enum {
     RICK_FLAG_TIMING = 1,       /* record per-kernel HIP events; read them with rick_plan_info */
-    RICK_FLAG_FUSED_SCREEN = 2  /* rick_fft_planes transforms rows only, into a second buffer (row_mesh,
+    RICK_FLAG_FUSED_SCREEN = 2, /* rick_fft_planes transforms rows only, into a second buffer (row_mesh,
                                    in column-panel order); rick_wstack_image transforms the columns plane by
                                    plane and screens and sums them in the same pass, so F_k is never
                                    written to HBM.  The mesh keeps G_k.  Needs a second mesh-sized buffer. */
+    RICK_FLAG_PLANE_ORIENT = 4  /* with RICK_FLAG_FUSED_SCREEN (not with RICK_KERNEL_USER_LUT): the first
+                                   rick_grid after a reset stores a plane transposed (cell (y, x) of G_k at
+                                   row x, column y) when its visibilities reach fewer tile columns than tile
+                                   rows, so that the row pass of rick_fft_planes transforms the fewer lines;
+                                   rick_wstack_image then takes such planes in a second column pass whose
+                                   strips are image rows.  tile_bits, the row transforms and the mesh
+                                   follow the stored orientation (rick_plan_info_t.plane_transposed).
+                                   The image is the same up to float rounding. */
 };
 
 /* Plan parameters (Sec. 2.1: mesh N_u x N_v x N_w, kernel type and support). */
@@ -161,6 +169,9 @@ typedef struct rick_plan_info_t {
                                 (pixel (q, p) divided by C[p] C[q]), or [N][N] for a user table */
     int32_t lut_wbins;       /* w-fraction bins of the installed user table (0 for a separable kernel) */
     int32_t pad2;
+    const int32_t *plane_transposed; /* device [N_w] with RICK_FLAG_PLANE_ORIENT (else NULL): 1 if plane k
+                                is stored transposed (tile_bits, mesh and row_mesh then hold G_k^T and its
+                                row transforms), 0 if not */
 } rick_plan_info_t;
 
 /*

@@ -445,20 +445,26 @@ __device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
 }
 
 // ---- columns fused with the w-correction and the plane sum ----
-// One block per strip of V columns loops over all planes: the strip of plane
+// One block per strip of V columns loops over the planes: the strip of plane
 // k (already transformed along rows) is transformed along columns in
 // registers, and each thread adds Re(exp(+2 pi i w_k (n - 1)) F_k) for the 16
-// x VC pixels it owns; plane k + 1 is fetched into registers meanwhile.  The
-// transformed planes are never written back, and the image is written once.
-// n - 1 of the strip's pixels is kept in LDS in float64; the phase
-// 2 w_k (n - 1) is formed in float64 half turns.
+// x VC pixels it owns; the next plane is fetched into registers meanwhile.
+// The transformed planes are never written back, and the image is written
+// once.  n - 1 of the strip's pixels is kept in LDS in float64; the phase
+// 2 w_k (n - 1) is formed in float64 half turns.  Planes without a set tile
+// are skipped (their F_k is zero).  Pass 0 takes the planes stored as they
+// are and writes the image; pass 1 takes the planes stored transposed, whose
+// strip of columns is a strip of image rows (n - 1 and the taper are
+// symmetric in l and m, so the same values serve), and adds its sums to the
+// image there, unless no plane was taken.
 template <typename real, int N, int V, int VC, int PW, bool KAHAN>
 __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
                                                                          const real *__restrict__ twr,
                                                                          const double *__restrict__ corr,
                                                                          const Stats *__restrict__ st,
                                                                          const uint64_t *__restrict__ row_bits,
-                                                                         real *__restrict__ image) {
+                                                                         const int32_t *__restrict__ plane_tr,
+                                                                         int pass, real *__restrict__ image) {
     using C = typename R2T<real>::t;
     using SH = Shape<N>;
     constexpr int NSTRIP = N / V;
@@ -485,21 +491,37 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
             s_nm1[e * V + v0 + v] = r2 < 1.0 ? -r2 / (1.0 + sqrt(1.0 - r2)) : 0.0;
         }
     }
+    // the planes of this pass holding a set tile, in order (uniform loads)
+    typedef __attribute__((address_space(4))) const int32_t const_i32;
+    auto taken = [&](int32_t k) {
+        if (plane_tr != nullptr && (((const_i32 *)plane_tr)[k] != 0) != (pass != 0)) return false;
+        uint64_t any = 0;
+        for (int32_t w = 0; w < g.occw; ++w) any |= uniform_word(row_bits, (int64_t)k * g.occw + w);
+        return any != 0;
+    };
+    auto next_plane = [&](int32_t k) {
+        while (k < g.Nw && !taken(k)) ++k;
+        return k;
+    };
     // rows of an empty tile row were not written by the row pass: zeros
     real acc[16][VC], comp[16][VC];
     C pre[16][VC];
+    int32_t k = next_plane(0);
+    const bool any_plane = k < g.Nw;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = in_elem<N>(tb, i);
-        const bool on = bit_of(uniform_word(row_bits, occ_word<N>(i, g.log2T)), e >> g.log2T);
+        const bool on = k < g.Nw &&
+                        bit_of(uniform_word(row_bits, (int64_t)k * g.occw + occ_word<N>(i, g.log2T)), e >> g.log2T);
+        const C *gk = gbase + (int64_t)k * plane_stride;
 #pragma unroll
         for (int v = 0; v < VC; ++v) {
             acc[i][v] = 0;
             comp[i][v] = 0;
-            pre[i][v] = on ? gbase[(int64_t)e * PW + v] : C{0, 0};
+            pre[i][v] = on ? gk[(int64_t)e * PW + v] : C{0, 0};
         }
     }
-    for (int k = 0; k < g.Nw; ++k) {
+    while (k < g.Nw) {
         // at N >= 8192 the lane indices and the twiddle pointer are laundered
         // per plane, so that the compiler recomputes addresses and reloads
         // twiddles (L1 hits) instead of keeping every stage's values live
@@ -518,13 +540,14 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
 #pragma unroll
             for (int v = 0; v < VC; ++v) x[i][v] = cneg_if(pre[i][v], e & 1);
         }
-        if (k + 1 < g.Nw) {
-            const C *gk = gbase + (int64_t)(k + 1) * plane_stride;
+        const int32_t kn = next_plane(k + 1);
+        if (kn < g.Nw) {
+            const C *gk = gbase + (int64_t)kn * plane_stride;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int e = in_elem<N>(tb, i);
                 const bool on =
-                    bit_of(uniform_word(row_bits, (int64_t)(k + 1) * g.occw + occ_word<N>(i, g.log2T)), e >> g.log2T);
+                    bit_of(uniform_word(row_bits, (int64_t)kn * g.occw + occ_word<N>(i, g.log2T)), e >> g.log2T);
 #pragma unroll
                 for (int v = 0; v < VC; ++v) pre[i][v] = on ? gk[(int64_t)e * PW + v] : C{0, 0};
             }
@@ -550,7 +573,9 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
                 }
             }
         }
+        k = kn;
     }
+    if (pass != 0 && !any_plane) return;   // (uniform) nothing to add
     const double sw = st->sum_w;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -561,9 +586,12 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
             const double l = (double)(p - N / 2) * dl, m = (double)(e - N / 2) * dl;
             const bool in_sky = l * l + m * m < 1.0;
             const double nm1 = s_nm1[e * V + v0 + v];
+            // pass 1: the strip's column p is image row p, its row e image column e
+            const int64_t row = pass ? p : e, col = pass ? e : p;
             const double val =
-                (sw > 0.0 && in_sky) ? (1.0 + nm1) * (double)acc[q][v] / (taper_at(g, corr, e, p) * sw) : 0.0;
-            image[(int64_t)e * N + p] = (real)val;
+                (sw > 0.0 && in_sky) ? (1.0 + nm1) * (double)acc[q][v] / (taper_at(g, corr, row, col) * sw) : 0.0;
+            if (pass) image[row * N + col] += (real)val;
+            else image[row * N + col] = (real)val;
         }
     }
 }
@@ -660,7 +688,8 @@ hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw
 
 template <typename real, int N>
 hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const double *corr, const Stats *st,
-                         const uint64_t *row_bits, real *image, int kahan, hipStream_t s) {
+                         const uint64_t *row_bits, const int32_t *plane_tr, int pass, real *image, int kahan,
+                         hipStream_t s) {
     using CS = ColShape<real, N>;
     constexpr int PW = PanelShape<real, N>::PW;
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
@@ -673,10 +702,10 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
     });
     if (kahan)
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>), dim3(N / CS::V), dim3(CS::THREADS),
-                           lds, s, g, mesh, tw, corr, st, row_bits, image);
+                           lds, s, g, mesh, tw, corr, st, row_bits, plane_tr, pass, image);
     else
         hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>), dim3(N / CS::V),
-                           dim3(CS::THREADS), lds, s, g, mesh, tw, corr, st, row_bits, image);
+                           dim3(CS::THREADS), lds, s, g, mesh, tw, corr, st, row_bits, plane_tr, pass, image);
     return hipGetLastError();
 }
 
@@ -757,10 +786,11 @@ hipError_t launch_fft_cols_panel(const Geom &g, real *row_mesh, const real *tw, 
 
 template <typename real>
 hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *corr,
-                                  const Stats *st, const uint64_t *row_bits, real *image, int kahan, hipStream_t s) {
+                                  const Stats *st, const uint64_t *row_bits, const int32_t *plane_tr, int pass,
+                                  real *image, int kahan, hipStream_t s) {
     switch (g.N) {
 #define CASE(n) \
-    case n: return cols_screen_n<real, n>(g, mesh, tw, corr, st, row_bits, image, kahan, s);
+    case n: return cols_screen_n<real, n>(g, mesh, tw, corr, st, row_bits, plane_tr, pass, image, kahan, s);
         CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -780,8 +810,10 @@ template hipError_t launch_fft_cols<double>(const Geom &, double *, const double
 template hipError_t launch_fft_cols_panel<float>(const Geom &, float *, const float *, hipStream_t);
 template hipError_t launch_fft_cols_panel<double>(const Geom &, double *, const double *, hipStream_t);
 template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, const float *, const double *,
-                                                  const Stats *, const uint64_t *, float *, int, hipStream_t);
+                                                  const Stats *, const uint64_t *, const int32_t *, int, float *,
+                                                  int, hipStream_t);
 template hipError_t launch_fft_cols_screen<double>(const Geom &, const double *, const double *, const double *,
-                                                   const Stats *, const uint64_t *, double *, int, hipStream_t);
+                                                   const Stats *, const uint64_t *, const int32_t *, int, double *,
+                                                   int, hipStream_t);
 
 }  // namespace rick

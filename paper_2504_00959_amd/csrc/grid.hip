@@ -97,6 +97,7 @@ template <typename real>
 __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t *__restrict__ heavy_bins,
                                                            Stats *__restrict__ st,
                                                            const uint64_t *__restrict__ tile_bits,
+                                                           const int32_t *__restrict__ plane_tr,
                                                            real *__restrict__ mesh, real *__restrict__ margin) {
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
@@ -110,8 +111,11 @@ __global__ __launch_bounds__(kZeroBlock) void k_zero_heavy(Geom g, const int32_t
         for (int64_t c = threadIdx.x; c < mlen; c += kZeroBlock) mb[c] = r2{0, 0};
         const int32_t k = b / (g.nt * g.nt);
         const int32_t rem = b - k * g.nt * g.nt;
-        if (tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt)) continue;
-        const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
+        // the tile in the stored orientation of its plane
+        const bool tr = plane_transposed(plane_tr, k);
+        const int32_t sty = tr ? rem % g.nt : rem / g.nt, stx = tr ? rem / g.nt : rem % g.nt;
+        if (tile_set(tile_bits, g, k, sty, stx)) continue;
+        const int32_t y0 = sty << g.log2T, x0 = stx << g.log2T;
         for (int32_t c = threadIdx.x; c < g.T * g.T; c += kZeroBlock) {
             const int32_t y = c >> g.log2T, x = c & (g.T - 1);
             m[((int64_t)k * g.N + y0 + y) * g.N + x0 + x] = r2{0, 0};
@@ -189,7 +193,8 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
                                                      real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
                                                      real *__restrict__ margin,
                                                      const uint32_t *__restrict__ bin_vmax,
-                                                     const float *__restrict__ tapmax, Stats *__restrict__ st) {
+                                                     const float *__restrict__ tapmax, Stats *__restrict__ st,
+                                                     const int32_t *__restrict__ plane_tr) {
     static_assert(!P32 || std::is_same<real, float>::value, "packed accumulation is a float32 mode");
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
@@ -457,12 +462,18 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
         __syncthreads();
 
         const bool shared_tile = nchunk > 1;
-        const bool accumulate = tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
+        // a transposed plane: cell (y, x) at row x, column y, and the tile's bit
+        // at (tile column, tile row); consecutive threads take consecutive
+        // stored columns either way
+        const bool tr = plane_transposed(plane_tr, k);
+        const bool accumulate =
+            tr ? tile_set(tile_bits, g, k, rem % g.nt, rem / g.nt) : tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
         for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
-            const int32_t y = c >> g.log2T, x = c & (T - 1);
+            const int32_t hi = c >> g.log2T, lo = c & (T - 1);
+            const int32_t y = tr ? lo : hi, x = tr ? hi : lo;
             real re, im;
             cell(y * P + x, re, im);
-            r2 *dst = m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
+            r2 *dst = tr ? m + ((int64_t)k * g.N + x0 + x) * g.N + y0 + y : m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
             if (shared_tile) {
                 if (re != 0) atomic_add_real(&dst->x, re);
                 if (im != 0) atomic_add_real(&dst->y, im);
@@ -521,12 +532,16 @@ template <typename real>
 __global__ __launch_bounds__(kMergeBlock) void k_merge_margins(Geom g, const BinScan *__restrict__ scan,
                                                                const real *__restrict__ margin,
                                                                uint64_t *__restrict__ tile_bits,
+                                                               const int32_t *__restrict__ plane_tr,
                                                                real *__restrict__ mesh) {
     using r2 = typename real2_t<real>::type;
     __shared__ unsigned long long s_word[kMaxOccWords];
     __shared__ int32_t s_list[512], s_n;
     const int32_t k = blockIdx.x / g.nt, ty = blockIdx.x % g.nt;
     const int32_t T = g.T, W1 = g.W - 1;
+    // a transposed plane keeps cell (y, x) at row x, column y, and the bit of
+    // tile (ty, tx) at (tx, ty): bits of other blocks share its words
+    const bool tr = plane_transposed(plane_tr, k);
     if (threadIdx.x < kMaxOccWords) s_word[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
@@ -536,7 +551,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_margins(Geom g, const Bin
     };
     const int64_t row_w = ((int64_t)k * g.nt + ty) * g.occw;
     for (int32_t tx = threadIdx.x; tx < g.nt; tx += kMergeBlock) {
-        const bool old = (tile_bits[row_w + (tx >> 6)] >> (tx & 63)) & 1ull;
+        const bool old = tr ? tile_set(tile_bits, g, k, tx, ty) : ((tile_bits[row_w + (tx >> 6)] >> (tx & 63)) & 1ull);
         const bool set = old || has(ty, tx);
         const bool l = W1 > 0 && tx > 0 && has(ty, tx - 1);
         const bool u = W1 > 0 && ty > 0 && has(ty - 1, tx);
@@ -561,10 +576,12 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_margins(Geom g, const Bin
         const r2 *mu = mg + (((int64_t)k * g.nt + tyu) * g.nt + tx) * mlen + R * W1;
         const r2 *mul = mg + (((int64_t)k * g.nt + tyu) * g.nt + txl) * mlen;
         for (int32_t c = threadIdx.x; c < T * T; c += kMergeBlock) {
-            const int32_t y = c >> g.log2T, x = c & (T - 1);
+            const int32_t hi = c >> g.log2T, lo = c & (T - 1);
+            const int32_t y = tr ? lo : hi, x = tr ? hi : lo;
             const bool hl = l && x < W1, hu = u && y < W1, hul = ul && x < W1 && y < W1;
             if (set && !(hl || hu || hul)) continue;   // a cell no margin reaches keeps its value
-            r2 *dst = m + ((int64_t)k * g.N + ((int64_t)ty << g.log2T) + y) * g.N + ((int64_t)tx << g.log2T) + x;
+            const int64_t gy = ((int64_t)ty << g.log2T) + y, gx = ((int64_t)tx << g.log2T) + x;
+            r2 *dst = tr ? m + ((int64_t)k * g.N + gx) * g.N + gy : m + ((int64_t)k * g.N + gy) * g.N + gx;
             r2 v = set ? *dst : r2{0, 0};
             if (hl) {
                 const r2 a = ml[y * W1 + x];
@@ -584,7 +601,55 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_margins(Geom g, const Bin
             *dst = v;
         }
     }
-    if (threadIdx.x < g.occw) tile_bits[row_w + threadIdx.x] = s_word[threadIdx.x];
+    if (!tr) {
+        if (threadIdx.x < g.occw) tile_bits[row_w + threadIdx.x] = s_word[threadIdx.x];
+    } else {
+        for (int32_t tx = threadIdx.x; tx < g.nt; tx += kMergeBlock)
+            if ((s_word[tx >> 6] >> (tx & 63)) & 1ull)
+                atomicOr((unsigned long long *)&tile_bits[((int64_t)k * g.nt + tx) * g.occw + (ty >> 6)],
+                         1ull << (ty & 63));
+    }
+}
+
+// Orientation of each plane that holds no set tile: one block per plane
+// marks the tile rows and tile columns its records reach (a record's bin and,
+// through the margins, the bins right of, below and diagonally below-right of
+// it) and stores the plane transposed iff fewer tile columns than tile rows
+// are reached.
+constexpr int kOrientBlock = 256;
+__global__ __launch_bounds__(kOrientBlock) void k_orient(Geom g, const BinScan *__restrict__ scan,
+                                                        const uint64_t *__restrict__ row_bits,
+                                                        int32_t *__restrict__ plane_tr) {
+    __shared__ int32_t s_rows[512], s_cols[512];
+    __shared__ int32_t s_nr, s_nc;
+    const int32_t k = blockIdx.x;
+    bool held = false;
+    for (int32_t w = 0; w < g.occw; ++w) held = held || row_bits[(int64_t)k * g.occw + w] != 0;
+    if (held) return;   // (uniform) tiles already stored keep their orientation
+    for (int32_t i = threadIdx.x; i < g.nt; i += kOrientBlock) s_rows[i] = s_cols[i] = 0;
+    if (threadIdx.x == 0) s_nr = s_nc = 0;
+    __syncthreads();
+    const int32_t spill = g.W > 1 ? 1 : 0;
+    for (int32_t t = threadIdx.x; t < g.nt * g.nt; t += kOrientBlock) {
+        const int64_t b = (int64_t)k * g.nt * g.nt + t;
+        if (scan[b + 1].rec > scan[b].rec) {
+            const int32_t ty = t / g.nt, tx = t % g.nt;
+            s_rows[ty] = 1;
+            s_cols[tx] = 1;
+            if (spill && ty + 1 < g.nt) s_rows[ty + 1] = 1;
+            if (spill && tx + 1 < g.nt) s_cols[tx + 1] = 1;
+        }
+    }
+    __syncthreads();
+    int32_t nr = 0, nc = 0;
+    for (int32_t i = threadIdx.x; i < g.nt; i += kOrientBlock) {
+        nr += s_rows[i];
+        nc += s_cols[i];
+    }
+    atomicAdd(&s_nr, nr);
+    atomicAdd(&s_nc, nc);
+    __syncthreads();
+    if (threadIdx.x == 0) plane_tr[k] = s_nc < s_nr ? 1 : 0;
 }
 
 // Row bitmap from the tile bitmap: one block per plane, one lane per tile row.
@@ -628,7 +693,8 @@ int device_cus() {
 template <typename real, int W, int TT, bool L3, bool P32>
 hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                   const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
+                   const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
+                   int32_t max_items, hipStream_t s) {
     const size_t lds = grid_lds_bytes(g, sizeof(real));
     static std::once_flag attr_once[kMaxDevices];
     once_per_device(attr_once, [&] {
@@ -645,17 +711,18 @@ hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, 
     const int64_t nblk = want < max_items ? want : max_items;
     hipLaunchKernelGGL((k_grid<real, W, TT, L3, P32>), dim3((unsigned)(nblk > 0 ? nblk : 1)), dim3(grid_threads(TT)),
                        lds, s, g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, tapmax,
-                       st);
+                       st, plane_tr);
     return hipGetLastError();
 }
 
 template <typename real, int W, int TT>
 hipError_t grid_wt2(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                     const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                    const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
+                    const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
+                    int32_t max_items, hipStream_t s) {
 #define GRID_WT(L3, P32) \
     grid_wt<real, W, TT, L3, P32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
-                                  tapmax, st, max_items, s)
+                                  tapmax, st, plane_tr, max_items, s)
     if constexpr (std::is_same<real, float>::value) {
         if (g.pk32) return tapmax ? GRID_WT(true, true) : GRID_WT(false, true);
     }
@@ -666,17 +733,18 @@ hipError_t grid_wt2(const Geom &g, const BinScan *scan, const int32_t *item_bin,
 template <typename real, int W>
 hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                   const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                  const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
+                  const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
+                  int32_t max_items, hipStream_t s) {
     switch (g.T) {
         case 16:
             return grid_wt2<real, W, 16>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                         tapmax, st, max_items, s);
+                                         tapmax, st, plane_tr, max_items, s);
         case 32:
             return grid_wt2<real, W, 32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                         tapmax, st, max_items, s);
+                                         tapmax, st, plane_tr, max_items, s);
         case 64:
             return grid_wt2<real, W, 64>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
-                                         tapmax, st, max_items, s);
+                                         tapmax, st, plane_tr, max_items, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -700,19 +768,26 @@ hipError_t launch_zero_mesh(real *mesh, int64_t n_real, hipStream_t s) {
 
 template <typename real>
 hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, Stats *st, const uint64_t *tile_bits,
-                             real *mesh, real *margin, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, tile_bits, mesh,
-                       margin);
+                             const int32_t *plane_tr, real *mesh, real *margin, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_heavy<real>, dim3(1024), dim3(kZeroBlock), 0, s, g, heavy_bins, st, tile_bits, plane_tr,
+                       mesh, margin);
     return hipGetLastError();
 }
 
 template <typename real>
 hipError_t launch_merge_margins(const Geom &g, const BinScan *scan, const real *margin, uint64_t *tile_bits,
-                                uint64_t *row_bits, real *mesh, hipStream_t s) {
+                                uint64_t *row_bits, const int32_t *plane_tr, real *mesh, hipStream_t s) {
     if (g.occw > kMaxOccWords || g.nt > 512) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_merge_margins<real>, dim3(g.Nw * g.nt), dim3(kMergeBlock), 0, s, g, scan, margin, tile_bits,
-                       mesh);
+                       plane_tr, mesh);
     hipLaunchKernelGGL(k_row_bits, dim3(g.Nw), dim3(64), 0, s, g, tile_bits, row_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_orient(const Geom &g, const BinScan *scan, const uint64_t *row_bits, int32_t *plane_tr,
+                         hipStream_t s) {
+    if (g.nt > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_orient, dim3(g.Nw), dim3(kOrientBlock), 0, s, g, scan, row_bits, plane_tr);
     return hipGetLastError();
 }
 
@@ -727,12 +802,13 @@ hipError_t launch_clear_bits(const Geom &g, uint64_t *tile_bits, uint64_t *row_b
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s) {
+                       const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
+                       int32_t max_items, hipStream_t s) {
     switch (g.W) {
 #define CASE(w) \
     case w: \
         return grid_w<real, w>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
-                               tapmax, st, max_items, s);
+                               tapmax, st, plane_tr, max_items, s);
         CASE(1) CASE(3) CASE(5) CASE(7) CASE(9) CASE(11) CASE(13) CASE(15)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -741,19 +817,21 @@ hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_b
 
 template hipError_t launch_zero_mesh<float>(float *, int64_t, hipStream_t);
 template hipError_t launch_zero_mesh<double>(double *, int64_t, hipStream_t);
-template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, Stats *, const uint64_t *, float *,
-                                             float *, hipStream_t);
+template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, Stats *, const uint64_t *,
+                                             const int32_t *, float *, float *, hipStream_t);
 template hipError_t launch_zero_heavy<double>(const Geom &, const int32_t *, Stats *, const uint64_t *,
-                                              double *, double *, hipStream_t);
+                                              const int32_t *, double *, double *, hipStream_t);
 template hipError_t launch_merge_margins<float>(const Geom &, const BinScan *, const float *, uint64_t *, uint64_t *,
-                                                float *, hipStream_t);
+                                                const int32_t *, float *, hipStream_t);
 template hipError_t launch_merge_margins<double>(const Geom &, const BinScan *, const double *, uint64_t *,
-                                                 uint64_t *, double *, hipStream_t);
+                                                 uint64_t *, const int32_t *, double *, hipStream_t);
 template hipError_t launch_grid<float>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                        const float *, const float *, float *, const uint64_t *, float *,
-                                       const uint32_t *, const float *, Stats *, int32_t, hipStream_t);
+                                       const uint32_t *, const float *, Stats *, const int32_t *, int32_t,
+                                       hipStream_t);
 template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int32_t *, const uint32_t *,
                                         const double *, const double *, double *, const uint64_t *, double *,
-                                        const uint32_t *, const float *, Stats *, int32_t, hipStream_t);
+                                        const uint32_t *, const float *, Stats *, const int32_t *, int32_t,
+                                       hipStream_t);
 
 }  // namespace rick

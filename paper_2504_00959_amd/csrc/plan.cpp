@@ -95,6 +95,7 @@ struct rick_plan_s {
     void *row_mesh = nullptr;   // fused: row transforms in column-panel order
     uint64_t *tile_bits = nullptr;   // tiles written since the reset, [N_w][nt][occw] words
     uint64_t *row_bits = nullptr;    // tile rows with a written tile, [N_w][occw] words
+    int32_t *plane_tr = nullptr;     // RICK_FLAG_PLANE_ORIENT: per plane, 1 if stored transposed
     void *margin = nullptr;          // per bin: the accumulator margins right of and below the tile
     int32_t panel = 0;
     void *lut = nullptr;
@@ -159,7 +160,7 @@ struct DeviceGuard {
 };
 
 void free_all(rick_plan_t *p) {
-    void *bufs[] = {p->mesh,      p->row_mesh,  p->tile_bits,  p->row_bits,  p->margin, p->lut,     p->twiddle,
+    void *bufs[] = {p->mesh,      p->row_mesh,  p->tile_bits,  p->row_bits,  p->plane_tr, p->margin, p->lut, p->twiddle,
                     p->corr,
                     p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
@@ -198,8 +199,10 @@ rick_status validate(const rick_plan_desc *d) {
     if (d->max_vis < 0 || d->max_vis >= (int64_t(1) << 29))
         return fail(RICK_E_INVALID_ARG, "max_vis=%lld: must be in [0, 2^29)", (long long)d->max_vis);
     if (d->device < 0) return fail(RICK_E_INVALID_ARG, "device=%d", d->device);
-    if (d->flags & ~int32_t(RICK_FLAG_TIMING | RICK_FLAG_FUSED_SCREEN))
+    if (d->flags & ~int32_t(RICK_FLAG_TIMING | RICK_FLAG_FUSED_SCREEN | RICK_FLAG_PLANE_ORIENT))
         return fail(RICK_E_INVALID_ARG, "flags=%d: unknown bits", d->flags);
+    if ((d->flags & RICK_FLAG_PLANE_ORIENT) && !(d->flags & RICK_FLAG_FUSED_SCREEN))
+        return fail(RICK_E_INVALID_ARG, "RICK_FLAG_PLANE_ORIENT needs RICK_FLAG_FUSED_SCREEN");
     if (d->tile != 0) {
         if (!is_pow2(d->tile) || d->tile < 16 || d->tile > 64 || d->tile < d->support || d->tile > d->grid_n)
             return fail(RICK_E_INVALID_ARG, "tile=%d: power of two in [16, 64], >= support, <= grid_n", d->tile);
@@ -259,6 +262,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     if ((d->flags & RICK_FLAG_FUSED_SCREEN) &&
         fused_screen_lds_bytes(d->grid_n, d->precision == RICK_PREC_FP64 ? 8 : 4) > size_t(160) * 1024)
         return fail(RICK_E_UNSUPPORTED, "fused screen: a column strip of N=%d does not fit in LDS", d->grid_n);
+    if ((d->flags & RICK_FLAG_PLANE_ORIENT) && d->kernel == RICK_KERNEL_USER_LUT)
+        return fail(RICK_E_UNSUPPORTED, "transposed planes with a user table are not built");
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -447,6 +452,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     }
     ALLOC(p->tile_bits, sz_tbits);
     ALLOC(p->row_bits, sz_rbits);
+    if (d->flags & RICK_FLAG_PLANE_ORIENT) ALLOC(p->plane_tr, size_t(g.Nw) * sizeof(int32_t));
     ALLOC(p->margin, sz_margin);
     ALLOC(p->lut, sz_lut);
     ALLOC(p->twiddle, sz_tw);
@@ -518,6 +524,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     if (e == hipSuccess) e = hipMemset(p->mesh, 0, p->mesh_bytes);
     if (e == hipSuccess) e = hipMemset(p->tile_bits, 0, sz_tbits);
     if (e == hipSuccess) e = hipMemset(p->row_bits, 0, sz_rbits);
+    if (e == hipSuccess && p->plane_tr) e = hipMemset(p->plane_tr, 0, size_t(g.Nw) * sizeof(int32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_all(p);
@@ -643,31 +650,36 @@ rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, cons
         timer_end(p, ps.slot, s);
         if (e != hipSuccess) return hip_fail(e, ps.name);
     }
+    if (p->plane_tr) {
+        // orientation of the planes this call is the first to grid onto
+        e = launch_orient(g, bb.scan, p->row_bits, p->plane_tr, s);
+        if (e != hipSuccess) return hip_fail(e, "orient");
+    }
     timer_begin(p, T_ZERO_HEAVY, "zero_heavy", s);
     if (p->fp64)
-        e = launch_zero_heavy<double>(g, bb.heavy_bins, p->stats, p->tile_bits, (double *)p->mesh,
+        e = launch_zero_heavy<double>(g, bb.heavy_bins, p->stats, p->tile_bits, p->plane_tr, (double *)p->mesh,
                                       (double *)p->margin, s);
     else
-        e = launch_zero_heavy<float>(g, bb.heavy_bins, p->stats, p->tile_bits, (float *)p->mesh, (float *)p->margin,
-                                     s);
+        e = launch_zero_heavy<float>(g, bb.heavy_bins, p->stats, p->tile_bits, p->plane_tr, (float *)p->mesh,
+                                     (float *)p->margin, s);
     timer_end(p, T_ZERO_HEAVY, s);
     if (e != hipSuccess) return hip_fail(e, "zero_heavy");
     timer_begin(p, T_GRID, "grid", s);
     if (p->fp64)
         e = launch_grid<double>(g, bb.scan, bb.item_bin, bb.rec_pos, (const double *)bb.rec_vis,
                                 (const double *)p->lut, (double *)p->mesh, p->tile_bits, (double *)p->margin,
-                                bb.bin_vmax, p->lut3 ? p->tapmax : nullptr, p->stats, max_items, s);
+                                bb.bin_vmax, p->lut3 ? p->tapmax : nullptr, p->stats, p->plane_tr, max_items, s);
     else
         e = launch_grid<float>(g, bb.scan, bb.item_bin, bb.rec_pos, (const float *)bb.rec_vis, (const float *)p->lut,
                                (float *)p->mesh, p->tile_bits, (float *)p->margin, bb.bin_vmax,
-                               p->lut3 ? p->tapmax : nullptr, p->stats, max_items, s);
+                               p->lut3 ? p->tapmax : nullptr, p->stats, p->plane_tr, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
     timer_begin(p, T_MARK, "merge_margins", s);
     e = p->fp64 ? launch_merge_margins<double>(g, bb.scan, (const double *)p->margin, p->tile_bits, p->row_bits,
-                                               (double *)p->mesh, s)
+                                               p->plane_tr, (double *)p->mesh, s)
                 : launch_merge_margins<float>(g, bb.scan, (const float *)p->margin, p->tile_bits, p->row_bits,
-                                              (float *)p->mesh, s);
+                                              p->plane_tr, (float *)p->mesh, s);
     timer_end(p, T_MARK, s);
     if (e != hipSuccess) return hip_fail(e, "merge_margins");
     p->state = 1;
@@ -797,12 +809,19 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
     const int kahan = p->d.precision == RICK_PREC_FP32_KAHAN;
     if (p->fused) {
         timer_begin(p, T_SCREEN, "fft_cols_screen", s);
-        if (p->fp64)
-            e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle,
-                                               taper_of(p), p->stats, p->row_bits, (double *)image, 0, s);
-        else
-            e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle,
-                                              taper_of(p), p->stats, p->row_bits, (float *)image, kahan, s);
+        // pass 0: planes stored as they are (writes the image); pass 1: planes
+        // stored transposed (adds to it)
+        e = hipSuccess;
+        for (int pass = 0; pass < (p->plane_tr ? 2 : 1) && e == hipSuccess; ++pass) {
+            if (p->fp64)
+                e = launch_fft_cols_screen<double>(p->g, (const double *)p->row_mesh, (const double *)p->twiddle,
+                                                   taper_of(p), p->stats, p->row_bits, p->plane_tr, pass,
+                                                   (double *)image, 0, s);
+            else
+                e = launch_fft_cols_screen<float>(p->g, (const float *)p->row_mesh, (const float *)p->twiddle,
+                                                  taper_of(p), p->stats, p->row_bits, p->plane_tr, pass,
+                                                  (float *)image, kahan, s);
+        }
         timer_end(p, T_SCREEN, s);
         if (e != hipSuccess) return hip_fail(e, "fft_cols_screen");
         return RICK_OK;
@@ -1083,6 +1102,7 @@ rick_status rick_plan_info(rick_plan_t *p, rick_plan_info_t *out) {
     out->w_k = p->w_k_host.data();
     out->taper = taper_of(p);
     out->lut_wbins = p->lut3 ? p->g.nwf : 0;
+    out->plane_transposed = p->plane_tr;
     out->tile = p->g.T;
     out->chunk = p->g.CH;
     out->state = p->state;

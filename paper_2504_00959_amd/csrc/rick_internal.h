@@ -106,6 +106,14 @@ __device__ __forceinline__ bool row_set(const uint64_t *__restrict__ row_bits, c
     return (row_bits[(int64_t)k * g.occw + (ty >> 6)] >> (ty & 63)) & 1ull;
 }
 
+// Plane orientation.  A plan with RICK_FLAG_PLANE_ORIENT may store plane k
+// transposed -- cell (y, x) of G_k at row x, column y of the stored plane --
+// iff plane_tr[k] != 0 (plane_tr NULL: no plane is).  The tile bits, the row
+// bits and the row transforms then follow the stored orientation.
+__device__ __forceinline__ bool plane_transposed(const int32_t *__restrict__ plane_tr, int32_t k) {
+    return plane_tr != nullptr && plane_tr[k] != 0;
+}
+
 // sin(pi g) and cos(pi g) for |g| <= 1/2 in float32: sin(pi g) = g P(g^2),
 // cos(pi g) = Q(g^2), minimax polynomials fitted on [-1/2, 1/2] (Horner form,
 // float32 fma; absolute error below 2.5e-7).
@@ -184,18 +192,24 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
 template <typename real>
 hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
-                       const uint32_t *bin_vmax, const float *tapmax, Stats *st, int32_t max_items, hipStream_t s);
+                       const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
+                       int32_t max_items, hipStream_t s);
+// Orientation of every plane that holds no set tile yet: transposed iff this
+// call's records (with the margins they spill right and down) occupy fewer
+// tile columns than tile rows.  Planes already holding tiles keep theirs.
+hipError_t launch_orient(const Geom &g, const BinScan *scan, const uint64_t *row_bits, int32_t *plane_tr,
+                         hipStream_t s);
 // LDS bytes of one gridding block (64-bit accumulators + tap table)
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes);
 int64_t grid_margin_len(const Geom &g);
 template <typename real>
 hipError_t launch_zero_heavy(const Geom &g, const int32_t *heavy_bins, Stats *st, const uint64_t *tile_bits,
-                             real *mesh, real *margin, hipStream_t s);
+                             const int32_t *plane_tr, real *mesh, real *margin, hipStream_t s);
 // After gridding: add the margins to the neighbouring tiles, set the tile
 // bits (records or margins received) and rebuild the row bits.
 template <typename real>
 hipError_t launch_merge_margins(const Geom &g, const BinScan *scan, const real *margin, uint64_t *tile_bits,
-                                uint64_t *row_bits, real *mesh, hipStream_t s);
+                                uint64_t *row_bits, const int32_t *plane_tr, real *mesh, hipStream_t s);
 // The library's static device scratch (rick_grid_static): kStaticScratchBytes
 // per device, in a file-scope __device__ array.  static_scratch_setup takes
 // its address on the current device, once per device (plan creation calls
@@ -228,9 +242,13 @@ int fused_panel_width(int N, size_t real_bytes);
 bool fft_supported(int N, size_t real_bytes);   // N = 16384 in float32 modes only
 // Column transform fused with the w-correction, plane sum and normalisation.
 size_t fused_screen_lds_bytes(int N, size_t real_bytes);
+// pass 0: the planes stored as they are (all planes without plane_tr), the
+// image written; pass 1: the planes stored transposed, added to the image
+// transposed.  Planes without a set tile are skipped.
 template <typename real>
 hipError_t launch_fft_cols_screen(const Geom &g, const real *mesh, const real *tw, const double *corr,
-                                  const Stats *st, const uint64_t *row_bits, real *image, int kahan, hipStream_t s);
+                                  const Stats *st, const uint64_t *row_bits, const int32_t *plane_tr, int pass,
+                                  real *image, int kahan, hipStream_t s);
 // Phase screen + plane sum + normalisation.
 template <typename real>
 hipError_t launch_wscreen(const Geom &g, const real *mesh, const double *corr,

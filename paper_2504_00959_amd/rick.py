@@ -26,6 +26,7 @@ MLP_PARAMS = 1217
 PRECISIONS = {"fp32": 0, "fp32_kahan": 1, "fp64": 2}
 FLAG_TIMING = 1
 FLAG_FUSED_SCREEN = 2
+FLAG_PLANE_ORIENT = 4
 
 
 class RickError(RuntimeError):
@@ -79,7 +80,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_timers", ctypes.c_int32), ("kernel_ms", ctypes.c_float * 16),
                 ("kernel_calls", ctypes.c_int32 * 16), ("kernel_names", ctypes.c_char_p * 16),
                 ("w_k", ctypes.POINTER(ctypes.c_double)), ("taper", ctypes.c_void_p), ("lut_wbins", ctypes.c_int32),
-                ("pad2", ctypes.c_int32)]
+                ("pad2", ctypes.c_int32), ("plane_transposed", ctypes.c_void_p)]
 
 
 _lib = None
@@ -170,8 +171,8 @@ def _stream_handle(stream) -> Optional[int]:
 
 def make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel="gaussian", kernel_param=0.0,
               precision="fp32", max_vis=1 << 20, device=0, timing=False, tile=0, chunk=0,
-              fused=False, lut_wbins=0) -> PlanDesc:
-    flags = (FLAG_TIMING if timing else 0) | (FLAG_FUSED_SCREEN if fused else 0)
+              fused=False, lut_wbins=0, orient=False) -> PlanDesc:
+    flags = (FLAG_TIMING if timing else 0) | (FLAG_FUSED_SCREEN if fused else 0) | (FLAG_PLANE_ORIENT if orient else 0)
     return PlanDesc(grid_n=grid_n, n_wplanes=n_wplanes, support=support, oversample=oversample,
                     kernel=KERNELS[kernel], precision=PRECISIONS[precision], kernel_param=kernel_param,
                     fov_rad=fov, w_min=w_min, w_max=w_max, max_vis=max_vis, device=device,
@@ -184,9 +185,9 @@ class Plan:
     def __init__(self, grid_n: int, n_wplanes: int, support: int, oversample: int, fov: float, w_min: float,
                  w_max: float, kernel: str = "gaussian", kernel_param: float = 0.0, precision: str = "fp32",
                  max_vis: int = 1 << 20, device: int = 0, timing: bool = False, tile: int = 0, chunk: int = 0,
-                 fused: bool = False, lut_wbins: int = 0):
+                 fused: bool = False, lut_wbins: int = 0, orient: bool = False):
         self.desc = make_desc(grid_n, n_wplanes, support, oversample, fov, w_min, w_max, kernel, kernel_param,
-                              precision, max_vis, device, timing, tile, chunk, fused, lut_wbins)
+                              precision, max_vis, device, timing, tile, chunk, fused, lut_wbins, orient)
         self.support, self.oversample, self.lut_wbins = support, oversample, lut_wbins
         self.fused = fused
         self.precision = precision
@@ -451,7 +452,7 @@ class Plan:
                     tile_rows_set=inf.tile_rows_set, rec1_bytes=inf.rec1_bytes, tile=inf.tile,
                     chunk=inf.chunk, state=inf.state, timers=timers,
                     w_k=np.array([inf.w_k[k] for k in range(self.n_wplanes)]), taper_ptr=inf.taper,
-                    lut_wbins=inf.lut_wbins)
+                    lut_wbins=inf.lut_wbins, plane_transposed_ptr=inf.plane_transposed)
 
     def bin_counts(self, n_bins: int) -> np.ndarray:
         """Per-(plane, tile) record counts of the last grid() (host int32 array)."""
@@ -468,8 +469,14 @@ class Plan:
                                         "strides": None}
         return torch.as_tensor(_View(), device=f"cuda:{self.device}")
 
-    def tile_mask(self):
-        """Host bool array [N_w, nt, nt]: tiles gridded onto since the last reset."""
+    def transposed(self) -> np.ndarray:
+        """Host bool [N_w]: planes stored transposed (all False without orient)."""
+        inf = self.info()
+        if not inf["plane_transposed_ptr"]:
+            return np.zeros(self.n_wplanes, dtype=bool)
+        return self._device_view(inf["plane_transposed_ptr"], (self.n_wplanes,), "<i4").cpu().numpy() != 0
+
+    def _stored_tile_mask(self):
         inf = self.info()
         nt, ow = self.grid_n // inf["tile"], inf["occ_words"]
         words = self._device_view(inf["tile_bits_ptr"], (self.n_wplanes * nt * ow,), "<i8")
@@ -477,11 +484,19 @@ class Plan:
         bits = (w[..., :, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)
         return bits.reshape(self.n_wplanes, nt, ow * 64)[..., :nt].astype(bool)
 
+    def tile_mask(self):
+        """Host bool array [N_w, nt, nt]: tiles gridded onto since the last
+        reset, as (plane, tile row, tile column) of G_k."""
+        t = self._stored_tile_mask()
+        tr = self.transposed()
+        t[tr] = np.transpose(t[tr], (0, 2, 1))
+        return t
+
     def _cell_mask(self, rows_only=False):
-        """Device bool [N_w, N, N] of the cells the planes hold (tile-row
-        granularity with rows_only)."""
+        """Device bool [N_w, N, N] of the cells the stored planes hold
+        (tile-row granularity with rows_only)."""
         import torch
-        t = self.tile_mask()
+        t = self._stored_tile_mask()
         if rows_only:
             t = np.repeat(t.any(axis=2, keepdims=True), t.shape[2], axis=2)
         T = self.grid_n // t.shape[1]
@@ -496,12 +511,17 @@ class Plan:
         v = self._device_view(inf["mesh_ptr"], (self.n_wplanes, self.grid_n, self.grid_n)).clone()
         if inf["state"] == 1 or (inf["state"] == 2 and self.fused):
             v[~self._cell_mask()] = 0
+            tr = self.transposed()
+            if tr.any():          # planes stored transposed, back to G_k
+                idx = np.nonzero(tr)[0]
+                v[idx] = v[idx].transpose(1, 2).contiguous()
         return v
 
     def row_mesh(self):
         """With the fused screen, copy of the row transforms H_k written by fft(),
         reordered from column panels to [N_w, N, N] (row-major; rows of empty
-        tile rows read as zeros); None otherwise."""
+        tile rows read as zeros; a plane stored transposed holds the row
+        transforms of G_k^T); None otherwise."""
         inf = self.info()
         if not inf["row_mesh_ptr"]:
             return None
@@ -650,11 +670,11 @@ class Stamps:
             pass
 
 
-def autotune(ds, uvw, vis, weight=None, precision="fp32", device=0, fused=True, stream=None):
+def autotune(ds, uvw, vis, weight=None, precision="fp32", device=0, fused=True, stream=None, orient=False):
     """Fastest (tile, chunk) for a job, by ``rick_autotune``; returns (tile, chunk, ms)."""
     args = dict(ds.plan_kwargs())
     args.setdefault("max_vis", max(1, ds.nvis))
-    desc = make_desc(precision=precision, device=device, fused=fused, **args)
+    desc = make_desc(precision=precision, device=device, fused=fused, orient=orient, **args)
     nrow = int(uvw.shape[0])
     nchan = 1 if ds.freq is None else len(ds.freq)
     freq = None if ds.freq is None else (ctypes.c_double * nchan)(*[float(f) for f in ds.freq])

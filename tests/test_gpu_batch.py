@@ -126,3 +126,77 @@ def test_autotune_picks_a_valid_shape_that_images_correctly():
     ref = oracle.wstack.wstack_dataset(ds)
     err = image_errors(img, ref.image, ref.corr)
     assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+
+
+def test_sixteen_uneven_jobs_replayed_each_against_the_oracle():
+    """The batched form at a size the oracle follows: 16 jobs of uneven grid
+    (256 to 1024), plane count and visibility count, one fused plan with
+    transposed planes allowed per (grid, planes) shape, recorded into one
+    graph and replayed twice.  Every job of every replay is checked against
+    the oracle at sampled pixels (apparent image: the taper division is the
+    same float64 scale on both sides), and against the eager run."""
+    import torch
+    jobs = synth.batched_jobs(seed=40, n_jobs=16, grid_sizes=(256, 512, 1024), nvis_range=(2e4, 4e5), n_dumps=300,
+                              oversample=32)
+    shapes = {}
+    for i, ds in enumerate(jobs):
+        shapes.setdefault((ds.grid_n, ds.n_wplanes), []).append(i)
+    assert len(shapes) >= 3 and max(ds.nvis for ds in jobs) > 5 * min(ds.nvis for ds in jobs)
+    dev = [to_device(ds)[:2] for ds in jobs]
+    plans = {key: rick.Plan.for_dataset(jobs[idx[0]], max_vis=max(jobs[i].nvis for i in idx), fused=True,
+                                        orient=True)
+             for key, idx in shapes.items()}
+    imgs = [torch.zeros((ds.grid_n, ds.grid_n), dtype=torch.float32, device="cuda:0") for ds in jobs]
+    stream = torch.cuda.Stream()
+    transposed = []
+    with torch.cuda.stream(stream):
+        for i, ds in enumerate(jobs):
+            p = plans[(ds.grid_n, ds.n_wplanes)]
+            _run_eager(p, ds, *dev[i], imgs[i])
+            stream.synchronize()
+            transposed.append(p.transposed())
+        eager = [im.double().cpu().numpy() for im in imgs]
+        stamps = rick.Stamps(len(jobs) + 1)
+        with rick.Graph.record(stream) as graph:
+            stamps.stamp(0, stream)
+            for i, ds in enumerate(jobs):
+                p = plans[(ds.grid_n, ds.n_wplanes)]
+                p.retarget(ds.fov, ds.w_min, ds.w_max)
+                p.reset(stream)
+                p.grid(dev[i][0], dev[i][1], None, ds.freq, stream)
+                p.fft(stream)
+                p.image(imgs[i], stream)
+                stamps.stamp(i + 1, stream)
+    assert any(t.any() for t in transposed) and any((~t).any() for t in transposed)
+    # the oracle at sampled pixels of every job: centre, the brightest source, inner-half pixels
+    rng = np.random.default_rng(41)
+    refs = []
+    for ds in jobs:
+        N = ds.grid_n
+        dl = ds.fov / N
+        b = int(np.argmax(ds.sources["flux"]))
+        pp = np.r_[N // 2, int(np.rint(ds.sources["l"][b] / dl)) + N // 2, rng.integers(N // 4, 3 * N // 4, 6)]
+        qq = np.r_[N // 2, int(np.rint(ds.sources["m"][b] / dl)) + N // 2, rng.integers(N // 4, 3 * N // 4, 6)]
+        ref, _, _, _ = oracle.pixels.wstack_pixels(ds.uvw, ds.freq, np.asarray(ds.vis), None, pp, qq,
+                                                   **ds.plan_kwargs())
+        corr = oracle.wstack.grid_correction(oracle.wstack.tap_table(ds.support, ds.oversample), N)
+        refs.append((pp, qq, ref, corr[pp] * corr[qq], np.outer(corr, corr)))
+    for rep in range(2):
+        for im in imgs:
+            im.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        for i, (pp, qq, ref, c2, C2) in enumerate(refs):
+            got = imgs[i].double().cpu().numpy()
+            # (apparent image: split bins add partial tiles with float atomics in
+            # no fixed order, which the taper division magnifies at the edges)
+            assert rel_rms(got * C2, eager[i] * C2) <= 1e-6, (rep, i)
+            e = rel_rms(got[qq, pp] * c2, ref * c2)
+            assert e <= FP32_IMG, (rep, i, jobs[i].grid_n, jobs[i].n_wplanes, jobs[i].nvis, e)
+        per_job = [stamps.elapsed(i, i + 1) for i in range(len(jobs))]
+        assert all(t >= 0 for t in per_job)
+    graph.close()
+    stamps.close()
+    for p in plans.values():
+        p.close()

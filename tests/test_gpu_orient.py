@@ -1,0 +1,133 @@
+"""Planes stored transposed (RICK_FLAG_PLANE_ORIENT) through the C ABI.
+
+A plane whose visibilities reach fewer tile columns than tile rows is
+gridded transposed, so that the row pass of the FFT transforms the fewer
+lines, and a second column pass takes such planes with image rows as its
+strips.  The inputs here are cut so that the planes of w > 0 hold a narrow
+band of u (few tile columns: stored transposed) and the planes of w <= 0 a
+narrow band of v (few tile rows: stored as they are).  Checked: which planes
+are transposed, the gridded planes and tile bitmap read back as G_k equal
+the plain plan's, the image equals the plain plan's to float rounding and
+the oracle's to the parity tolerance, the orientation survives several
+rick_grid calls and is chosen anew after a reset.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2504_00959_amd import rick
+from tests.helpers import image_errors, rel_rms, to_device
+
+pytestmark = pytest.mark.gpu
+
+FP32_IMG = 1e-5
+FP64_IMG = 1e-10
+
+
+def _striped(seed=30, swap=False, nrow=300000):
+    # uv disk of radius 480 wavelengths: +-96 of the 256 cells; bands of +-20
+    # wavelengths: +-4 cells
+    ds = synth.tiny(nrow=nrow, seed=seed, uv_radius=480.0)
+    u, v, w = ds.uvw[:, 0], ds.uvw[:, 1], ds.uvw[:, 2]
+    a, b = (v, u) if swap else (u, v)
+    keep = ((w > 0) & (np.abs(a) < 20.0)) | ((w <= 0) & (np.abs(b) < 20.0))
+    ds.uvw = ds.uvw[keep].copy()
+    ds.vis = np.asarray(ds.vis)[keep].copy()
+    return ds
+
+
+def _run(ds, precision, orient, calls=1, **kw):
+    import torch
+    uvw, vis, wt = to_device(ds, precision)
+    with rick.Plan.for_dataset(ds, precision=precision, fused=True, orient=orient, **kw) as p:
+        p.reset()
+        n = uvw.shape[0]
+        cuts = np.linspace(0, n, calls + 1).astype(int)
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            p.grid(uvw[a:b].contiguous(), vis[a:b].contiguous(), None if wt is None else wt[a:b].contiguous(),
+                   ds.freq)
+        torch.cuda.synchronize()
+        out = dict(tr=p.transposed(), G=p.mesh().cpu().numpy(), mask=p.tile_mask())
+        p.fft()
+        out["img"] = p.image().double().cpu().numpy()
+        torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan", "fp64"])
+def test_transposed_planes_image_like_plain_planes(precision):
+    ds = _striped()
+    plain = _run(ds, precision, False, tile=32)
+    got = _run(ds, precision, True, tile=32)
+    half = ds.n_wplanes // 2
+    assert not plain["tr"].any()
+    assert got["tr"][half:].all() and not got["tr"][:half].any(), got["tr"]
+    assert np.array_equal(got["mask"], plain["mask"])
+    g_tol, i_tol = (1e-14, 1e-12) if precision == "fp64" else (1e-6, 1e-6)
+    assert rel_rms(got["G"], plain["G"]) <= g_tol
+    ref = oracle.wstack.wstack_dataset(ds)
+    c2 = np.outer(ref.corr, ref.corr)
+    assert rel_rms(got["img"] * c2, plain["img"] * c2) <= i_tol
+    if precision == "fp64":
+        assert rel_rms(got["img"], ref.image) <= FP64_IMG
+    else:
+        err = image_errors(got["img"], ref.image, ref.corr)
+        assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+
+
+@pytest.mark.parametrize("tile,chunk", [(16, 32), (64, 0)])
+def test_transposed_planes_with_split_bins_and_tiles(tile, chunk):
+    """bins split over several chunks (atomic flushes onto transposed tiles)
+    and margins merged into transposed neighbours, at two tile sizes"""
+    ds = _striped(seed=31)
+    plain = _run(ds, "fp32", False, tile=tile, chunk=chunk)
+    got = _run(ds, "fp32", True, tile=tile, chunk=chunk)
+    assert got["tr"].any() and not got["tr"].all()
+    assert np.array_equal(got["mask"], plain["mask"])
+    assert rel_rms(got["G"], plain["G"]) <= 1e-6
+    ref = oracle.wstack.wstack_dataset(ds)
+    err = image_errors(got["img"], ref.image, ref.corr)
+    assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+
+
+def test_orientation_kept_across_calls_and_chosen_anew_after_reset():
+    import torch
+    ds = _striped(seed=32)
+    one = _run(ds, "fp32", True)
+    three = _run(ds, "fp32", True, calls=3)
+    assert np.array_equal(one["tr"], three["tr"]) and np.array_equal(one["mask"], three["mask"])
+    assert rel_rms(three["G"], one["G"]) <= 1e-6
+    c2 = np.outer(*(2 * [oracle.wstack.wstack_dataset(ds).corr]))
+    assert rel_rms(three["img"] * c2, one["img"] * c2) <= 1e-6
+    # the same plan after a reset, with the bands swapped: the orientation flips
+    sw = _striped(seed=32, swap=True)
+    uvw, vis, _ = to_device(ds)
+    uvw2, vis2, _ = to_device(sw)
+    with rick.Plan.for_dataset(ds, fused=True, orient=True, max_vis=max(ds.nvis, sw.nvis)) as p:
+        p.reset()
+        p.grid(uvw, vis)
+        tr1 = p.transposed()
+        p.fft()
+        p.image()
+        p.reset()
+        p.grid(uvw2, vis2)
+        tr2 = p.transposed()
+        p.fft()
+        img2 = p.image().double().cpu().numpy()
+        torch.cuda.synchronize()
+    half = ds.n_wplanes // 2
+    assert tr1[half:].all() and not tr1[:half].any()
+    assert tr2[:half].all() and not tr2[half:].any()
+    ref = oracle.wstack.wstack_dataset(sw)
+    err = image_errors(img2, ref.image, ref.corr)
+    assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+
+
+def test_orient_flag_needs_the_fused_screen():
+    ds = _striped()
+    with pytest.raises(rick.RickError, match="INVALID_ARG"):
+        rick.Plan.for_dataset(ds, orient=True)
+    with pytest.raises(rick.RickError, match="UNSUPPORTED"):
+        rick.Plan(grid_n=256, n_wplanes=4, support=7, oversample=32, fov=0.2, w_min=-1.0, w_max=1.0,
+                  kernel="user_lut", lut_wbins=2, fused=True, orient=True)
