@@ -7,23 +7,28 @@
 //   level 1  coarse bins = (plane, coarse tile of C x C tiles), at most 8192.
 //     bin_count    each block takes a contiguous range of visibilities:
 //                  position quantised to 1/OS cell, nearest cell, closest
-//                  w-plane, drop test; counts per coarse bin (that of the
-//                  footprint's origin) in an LDS histogram; writes its column
-//                  of the (coarse bin, block) count table; weight sum and
-//                  counters.
+//                  w-plane, every drop test but the finiteness of V (so
+//                  the visibilities are not read); counts per coarse bin
+//                  (that of the footprint's origin) in an LDS histogram;
+//                  writes its column of the (coarse bin, block) count table.
 //     bin_scan     exclusive scan of that table (coarse-bin major), then the
 //                  level-2 chunk list (each coarse bin cut into chunks).
 //     bin_scatter  repeats the quantisation; slots from LDS cursors seeded
 //                  with the block's scanned offsets; writes the level-1
-//                  records (12 or 16 bytes, formats below).
+//                  records as two arrays, positions (4 or 8 bytes, formats
+//                  below) and W V; a record whose W V is not finite keeps
+//                  its slot, marked dead (W V = NaN); weight sum and counters.
 //   level 2  bins = (plane, tile) inside each coarse bin, at most C^2 = 16384.
 //     fine_count   one block per chunk: LDS histogram over the tiles of the
-//                  coarse tile (that of each record's footprint origin).
+//                  coarse tile (that of each record's footprint origin),
+//                  from the positions alone (W V too only if a record of
+//                  the call is dead).
 //     fine_scan    per bin, the total over its coarse bin's chunks; exclusive
 //                  scan of records and gridding chunks in bin order (item and
 //                  heavy-bin lists); per (chunk, tile) record offsets.
 //     fine_scatter one block per chunk: slots from LDS cursors; writes the
-//                  12-byte records {packed position in the tile, W V}.
+//                  12-byte records {packed position in the tile, W V}, and
+//                  the largest |W V| per (chunk, tile), then per bin.
 //
 // A visibility is binned once, into the tile holding the top-left cell
 // (c_x - h, c_y - h) of its W x W footprint: the gridder keeps a tile plus a
@@ -56,24 +61,27 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kL1Block = 1024;   // threads of a level-1 block (one contiguous range of visibilities)
 
-// Level-1 records, in one of two formats:
-//   full (16 B with float32 W V, 24 B with float64): cell x | y << 16,
-//     sub-cell x | y << 8 | plane << 16, W V;
-//   compact (12 B, float32 W V, when 2 (log2(C T) + log2(OS)) <= 32): one word
+// Level-1 records: positions in one of two formats, and W V in an array of
+// its own (after the positions, 256-byte aligned):
+//   full (8 B): cell x | y << 16, sub-cell x | y << 8 | plane << 16;
+//   compact (4 B, float32 W V, when 2 (log2(C T) + log2(OS)) <= 32): one word
 //     holding the footprint origin inside the coarse tile and the sub-cell
-//     indices, then W V -- the plane and coarse tile are those of the bin.
-template <typename real, bool CPT>
-struct Rec1;
-template <typename real>
-struct Rec1<real, false> {
+//     indices -- the plane and coarse tile are those of the bin.
+// A record whose W V is not finite is dead: counted by bin_count (which
+// does not read V) and so given a slot, but skipped by level 2.
+template <bool CPT>
+struct P1;
+template <>
+struct P1<false> {
     uint32_t cxy, sub;
-    real vr, vi;
 };
-template <typename real>
-struct Rec1<real, true> {
+template <>
+struct P1<true> {
     uint32_t pos;
-    real vr, vi;
 };
+__host__ __device__ inline size_t l1_vis_offset(int64_t nrec, bool cpt) {
+    return ((size_t)nrec * (cpt ? 4 : 8) + 255) & ~size_t(255);
+}
 
 // Footprint origin inside its coarse tile (ox1, oy1, in cells) and sub-cell
 // indices s + OS/2 in [0, OS) (sx, sy).
@@ -98,32 +106,25 @@ __global__ void k_set_scales(double *__restrict__ dst, ChanScales cs, int32_t n)
     if (t < n) dst[t] = cs.s[t];
 }
 
-template <typename real>
-__device__ __forceinline__ Rec1<real, false> make_rec1(const Geom &g, const Quant &q, real ar, real ai,
-                                                      Rec1<real, false> *) {
+__device__ __forceinline__ P1<false> make_p1(const Geom &g, const Quant &q, P1<false> *) {
     // plane in bits 16..28 (< 8192 planes), w-fraction bin in bits 29..31
-    return Rec1<real, false>{(uint32_t)q.cx | (uint32_t)q.cy << 16,
-                             (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 |
-                                 (uint32_t)q.k << 16 | (uint32_t)q.iw << 29,
-                             ar, ai};
+    return P1<false>{(uint32_t)q.cx | (uint32_t)q.cy << 16,
+                     (uint32_t)(q.sx + (g.OS >> 1)) | (uint32_t)(q.sy + (g.OS >> 1)) << 8 | (uint32_t)q.k << 16 |
+                         (uint32_t)q.iw << 29};
 }
-template <typename real>
-__device__ __forceinline__ Rec1<real, true> make_rec1(const Geom &g, const Quant &q, real ar, real ai,
-                                                     Rec1<real, true> *) {
+__device__ __forceinline__ P1<true> make_p1(const Geom &g, const Quant &q, P1<true> *) {
     const int32_t lb = coarse_shift(g), m = (1 << lb) - 1;
     const uint32_t ox1 = (uint32_t)((q.cx - g.h) & m), oy1 = (uint32_t)((q.cy - g.h) & m);
     const uint32_t sx = (uint32_t)(q.sx + (g.OS >> 1)), sy = (uint32_t)(q.sy + (g.OS >> 1));
-    return Rec1<real, true>{ox1 | sx << lb | oy1 << (lb + g.log2OS) | sy << (2 * lb + g.log2OS), ar, ai};
+    return P1<true>{ox1 | sx << lb | oy1 << (lb + g.log2OS) | sy << (2 * lb + g.log2OS)};
 }
-template <typename real>
-__device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, false> &r, int32_t ctx, int32_t cty) {
+__device__ __forceinline__ Pos1 pos_of(const Geom &g, const P1<false> &r, int32_t ctx, int32_t cty) {
     const int32_t lb = coarse_shift(g);
     const int32_t cx = (int32_t)(r.cxy & 0xffffu), cy = (int32_t)(r.cxy >> 16);
     return Pos1{cx - g.h - (ctx << lb), cy - g.h - (cty << lb), (int32_t)(r.sub & 0xffu),
                 (int32_t)((r.sub >> 8) & 0xffu), (int32_t)(r.sub >> 29)};
 }
-template <typename real>
-__device__ __forceinline__ Pos1 pos_of(const Geom &g, const Rec1<real, true> &r, int32_t, int32_t) {
+__device__ __forceinline__ Pos1 pos_of(const Geom &g, const P1<true> &r, int32_t, int32_t) {
     const int32_t lb = coarse_shift(g), sb = g.log2OS;
     const uint32_t ml = (1u << lb) - 1, ms = (1u << sb) - 1;
     return Pos1{(int32_t)(r.pos & ml), (int32_t)((r.pos >> (lb + sb)) & ml), (int32_t)((r.pos >> lb) & ms),
@@ -208,70 +209,32 @@ struct L1Part {
     int32_t per;   // a multiple of kBlock
 };
 
-template <typename real>
 __global__ __launch_bounds__(kL1Block) void k_l1_count(Geom g, const double *__restrict__ uvw,
-                                                     const double *__restrict__ scales, const real *__restrict__ vis,
+                                                     const double *__restrict__ scales,
                                                      const float *__restrict__ weight, int64_t nvis, int32_t nchan,
-                                                     L1Part part, int32_t *__restrict__ cnt1, Stats *__restrict__ st) {
+                                                     L1Part part, int32_t *__restrict__ cnt1) {
     extern __shared__ int32_t s_cnt[];   // g.n1 counters
-    __shared__ double s_w[kL1Block / 64];
-    __shared__ unsigned long long s_kept[kL1Block / 64], s_drop[kL1Block / 64];
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cnt[i] = 0;
     __syncthreads();
     const int64_t v0 = (int64_t)blockIdx.x * part.per;
     const int64_t v1 = v0 + part.per < nvis ? v0 + part.per : nvis;
     const int32_t cshift = g.log2T + g.log2C;
-    double sum_w = 0.0;
-    unsigned long long kept = 0, dropped = 0;
     VisWalk vw((uint32_t)(v0 + threadIdx.x), kL1Block, (uint32_t)nchan);
     for (int32_t it = 0; it < part.per / kL1Block; ++it, vw.next((uint32_t)nchan)) {
         bool keep = false;
         Quant q{};
         if ((int64_t)vw.i < v1) {
-            double u, v, w;
-            real vr, vi;
-            float wt;
-            load_vis<real>(g, uvw, scales, vis, weight, vw.i, vw.r, vw.c, u, v, w, vr, vi, wt);
-            keep = quantise<real>(g, u, v, w, vr, vi, wt, q);
-            if (keep) {
-                ++kept;
-                sum_w += (double)wt;
-            } else {
-                ++dropped;
-            }
+#pragma clang fp contract(off)
+            const double sc = scales[vw.c];
+            const double u = uvw[3 * vw.r] * sc, v = uvw[3 * vw.r + 1] * sc, w = uvw[3 * vw.r + 2] * sc;
+            keep = quantise_pos(g, u, v, w, weight ? weight[vw.i] : 1.0f, q);
         }
         const Span cs = span_of(q, g.h, cshift);
         const int32_t base = (q.k * g.nct + cs.y0) * g.nct + cs.x0;
         const Run run = runs_of(keep ? base : -1);
         if (keep && run.head) atomicAdd(&s_cnt[base], run.len);
     }
-    // block reduction of the counters, one atomic per block and counter
-    for (int off = 32; off > 0; off >>= 1) {
-        sum_w += __shfl_down(sum_w, off);
-        kept += __shfl_down(kept, off);
-        dropped += __shfl_down(dropped, off);
-    }
-    const int wid = threadIdx.x >> 6;
-    if (__lane_id() == 0) {
-        s_w[wid] = sum_w;
-        s_kept[wid] = kept;
-        s_drop[wid] = dropped;
-    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double tw = 0.0;
-        unsigned long long tk = 0, td = 0;
-        for (int k = 0; k < kL1Block / 64; ++k) {
-            tw += s_w[k];
-            tk += s_kept[k];
-            td += s_drop[k];
-        }
-        if (tk) {
-            atomicAdd(&st->n_gridded, tk);
-            unsafeAtomicAdd(&st->sum_w, tw);
-        }
-        if (td) atomicAdd(&st->n_dropped, td);
-    }
     // this block's column of the (coarse bin, block) table
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) cnt1[(int64_t)i * part.nb1 + blockIdx.x] = s_cnt[i];
 }
@@ -281,17 +244,21 @@ __global__ __launch_bounds__(kL1Block) void k_l1_scatter(Geom g, const double *_
                                                          const double *__restrict__ scales,
                                                          const real *__restrict__ vis, const float *__restrict__ weight,
                                                          int64_t nvis, int32_t nchan, L1Part part,
-                                                         const int32_t *__restrict__ base1,
-                                                         Rec1<real, CPT> *__restrict__ rec1) {
+                                                         const int32_t *__restrict__ base1, P1<CPT> *__restrict__ pos1,
+                                                         real *__restrict__ vis1, Stats *__restrict__ st) {
     extern __shared__ int32_t s_cur[];   // g.n1 cursors
+    __shared__ double s_w[kL1Block / 64];
+    __shared__ unsigned long long s_kept[kL1Block / 64], s_drop[kL1Block / 64], s_dead[kL1Block / 64];
     for (int i = threadIdx.x; i < g.n1; i += kL1Block) s_cur[i] = base1[(int64_t)i * part.nb1 + blockIdx.x];
     __syncthreads();
     const int64_t v0 = (int64_t)blockIdx.x * part.per;
     const int64_t v1 = v0 + part.per < nvis ? v0 + part.per : nvis;
     const int32_t cshift = g.log2T + g.log2C;
+    double sum_w = 0.0;
+    unsigned long long kept = 0, dropped = 0, dead = 0;
     VisWalk vw((uint32_t)(v0 + threadIdx.x), kL1Block, (uint32_t)nchan);
     for (int32_t it = 0; it < part.per / kL1Block; ++it, vw.next((uint32_t)nchan)) {
-        bool keep = false;
+        bool placed = false;   // passed the position tests: counted by bin_count
         Quant q{};
         real ar = 0, ai = 0;
         if ((int64_t)vw.i < v1) {
@@ -299,20 +266,67 @@ __global__ __launch_bounds__(kL1Block) void k_l1_scatter(Geom g, const double *_
             real vr, vi;
             float wt;
             load_vis<real>(g, uvw, scales, vis, weight, vw.i, vw.r, vw.c, u, v, w, vr, vi, wt);
-            keep = quantise<real>(g, u, v, w, vr, vi, wt, q);
+            placed = quantise_pos(g, u, v, w, wt, q);
             ar = (real)wt * vr;
             ai = (real)wt * vi;
+            // kept: placed with a finite W V; a placed record without one is dead
+            const bool live = placed && isfinite((double)ar) && isfinite((double)ai);
+            if (live) {
+                ++kept;
+                sum_w += (double)wt;
+            } else {
+                ++dropped;
+                if (placed) {
+                    ++dead;
+                    ar = __builtin_nan("");
+                    ai = 0;
+                }
+            }
         }
         const Span cs = span_of(q, g.h, cshift);
         const int32_t base = (q.k * g.nct + cs.y0) * g.nct + cs.x0;
-        const Run run = runs_of(keep ? base : -1);
+        const Run run = runs_of(placed ? base : -1);
         // the run's first lane takes the slots of the whole run
         int32_t b0 = 0;
-        if (keep && run.head) b0 = atomicAdd(&s_cur[base], run.len);
+        if (placed && run.head) b0 = atomicAdd(&s_cur[base], run.len);
         const int32_t rank = (int32_t)__lane_id() - run.leader;
-        const Rec1<real, CPT> r1 = make_rec1<real>(g, q, ar, ai, (Rec1<real, CPT> *)nullptr);
+        const P1<CPT> r1 = make_p1(g, q, (P1<CPT> *)nullptr);
         const int32_t slot = __shfl(b0, run.leader) + rank;
-        if (keep) rec1[slot] = r1;
+        if (placed) {
+            pos1[slot] = r1;
+            store2(vis1 + 2 * (int64_t)slot, ar, ai);
+        }
+    }
+    // block reduction of the counters, one atomic per block and counter
+    for (int off = 32; off > 0; off >>= 1) {
+        sum_w += __shfl_down(sum_w, off);
+        kept += __shfl_down(kept, off);
+        dropped += __shfl_down(dropped, off);
+        dead += __shfl_down(dead, off);
+    }
+    const int wid = threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+        s_w[wid] = sum_w;
+        s_kept[wid] = kept;
+        s_drop[wid] = dropped;
+        s_dead[wid] = dead;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tw = 0.0;
+        unsigned long long tk = 0, td = 0, tx = 0;
+        for (int k = 0; k < kL1Block / 64; ++k) {
+            tw += s_w[k];
+            tk += s_kept[k];
+            td += s_drop[k];
+            tx += s_dead[k];
+        }
+        if (tk) {
+            atomicAdd(&st->n_gridded, tk);
+            unsafeAtomicAdd(&st->sum_w, tw);
+        }
+        if (td) atomicAdd(&st->n_dropped, td);
+        if (tx) atomicAdd(&st->n_dead, tx);
     }
 }
 
@@ -424,6 +438,7 @@ __global__ __launch_bounds__(kScanBlock) void k_l2_chunks(Geom g, const int32_t 
         key_chunk0[g.n1] = carry;
         st->n_chunks = (unsigned long long)carry;
         st->n_heavy = 0;
+        st->n_dead = 0;   // (counted by bin_scatter, which runs next)
     }
 }
 
@@ -457,53 +472,36 @@ __device__ __forceinline__ Local local_span(const Geom &g, const Pos1 &p) {
     return Local{p.ox1 >> g.log2T, p.oy1 >> g.log2T};
 }
 
-// Per (chunk, tile): record count and, for float32 records, the largest
-// |W V| (the gridder's fixed-point scale; non-negative floats order as their
-// bit patterns, so an integer max on the bits is a float max).
+// Per (chunk, tile): live record count, from the positions alone unless a
+// record of the call is dead (then W V too).
 template <typename real, bool CPT>
 __global__ __launch_bounds__(kBlock) void k_l2_count(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                      const int32_t *__restrict__ key_chunk0,
                                                      const int32_t *__restrict__ chunk_key,
-                                                     const Stats *__restrict__ st,
-                                                     const Rec1<real, CPT> *__restrict__ rec1,
-                                                     int32_t *__restrict__ cnt2, uint32_t *__restrict__ vmax2) {
-    extern __shared__ int32_t s_h[];   // C^2 counters, then C^2 maxima
+                                                     const Stats *__restrict__ st, const P1<CPT> *__restrict__ pos1,
+                                                     const real *__restrict__ vis1, int32_t *__restrict__ cnt2) {
+    extern __shared__ int32_t s_h[];   // C^2 counters
     const int32_t chunk = blockIdx.x;
     if (chunk >= (int32_t)st->n_chunks) return;
     const int32_t C2 = g.C * g.C;
-    uint32_t *s_m = reinterpret_cast<uint32_t *>(s_h + C2);
-    for (int i = threadIdx.x; i < C2; i += kBlock) {
-        s_h[i] = 0;
-        s_m[i] = 0u;
-    }
+    const bool any_dead = st->n_dead != 0;
+    for (int i = threadIdx.x; i < C2; i += kBlock) s_h[i] = 0;
     __syncthreads();
     const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
     for (int32_t r00 = ck.r0; r00 < ck.r1; r00 += kBlock) {
         const int32_t r = r00 + threadIdx.x;
-        const bool valid = r < ck.r1;
+        bool valid = r < ck.r1;
         Local ls{0, 0};
-        uint32_t mbits = 0u;
         if (valid) {
-            const Rec1<real, CPT> p = rec1[r];
-            ls = local_span(g, pos_of<real>(g, p, ck.ctx, ck.cty));
-            if constexpr (sizeof(real) == 4) mbits = __float_as_uint(fmaxf(fabsf(p.vr), fabsf(p.vi)));
+            ls = local_span(g, pos_of(g, pos1[r], ck.ctx, ck.cty));
+            if (any_dead) valid = !isnan((double)vis1[2 * (int64_t)r]);
         }
         const int32_t f = ls.fy0 * g.C + ls.fx0;
         const Run run = runs_of(valid ? f : -1);
         if (valid && run.head) atomicAdd(&s_h[f], run.len);
-        // maximum over the run (a segmented scan), taken by the run's last lane
-        const int lane = (int)__lane_id();
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(mbits, off);
-            if (lane - off >= run.leader) mbits = max(mbits, o);
-        }
-        if (valid && run.len == 1 && mbits) atomicMax(&s_m[f], mbits);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < C2; i += kBlock) {
-        cnt2[(int64_t)chunk * C2 + i] = s_h[i];
-        vmax2[(int64_t)chunk * C2 + i] = s_m[i];
-    }
+    for (int i = threadIdx.x; i < C2; i += kBlock) cnt2[(int64_t)chunk * C2 + i] = s_h[i];
 }
 
 // bin b = (plane, tile y, tile x) -> its coarse bin and its index inside it
@@ -515,23 +513,31 @@ __device__ __forceinline__ void bin_place(const Geom &g, int32_t b, int32_t &key
     f = (ty & (g.C - 1)) * g.C + (tx & (g.C - 1));
 }
 
-// records per bin (the sum over its coarse bin's chunks) and their largest |W V|
+// records per bin (the sum over its coarse bin's chunks)
 __global__ __launch_bounds__(kBlock) void k_l2_totals(Geom g, const int32_t *__restrict__ key_chunk0,
-                                                      const int32_t *__restrict__ cnt2,
-                                                      const uint32_t *__restrict__ vmax2, int32_t *__restrict__ counts,
-                                                      uint32_t *__restrict__ bin_vmax) {
+                                                      const int32_t *__restrict__ cnt2, int32_t *__restrict__ counts) {
     const int32_t b = blockIdx.x * kBlock + threadIdx.x;
     if (b >= g.nbins) return;
     int32_t key, f;
     bin_place(g, b, key, f);
     const int64_t C2 = (int64_t)g.C * g.C;
     int32_t t = 0;
-    uint32_t m = 0u;
-    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) {
-        t += cnt2[c * C2 + f];
-        m = max(m, vmax2[c * C2 + f]);
-    }
+    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) t += cnt2[c * C2 + f];
     counts[b] = t;
+}
+
+// largest |W V| of each bin's records (float32 records: the gridder's
+// fixed-point scale), the maximum over its coarse bin's chunks
+__global__ __launch_bounds__(kBlock) void k_bin_vmax(Geom g, const int32_t *__restrict__ key_chunk0,
+                                                     const uint32_t *__restrict__ vmax2,
+                                                     uint32_t *__restrict__ bin_vmax) {
+    const int32_t b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= g.nbins) return;
+    int32_t key, f;
+    bin_place(g, b, key, f);
+    const int64_t C2 = (int64_t)g.C * g.C;
+    uint32_t m = 0u;
+    for (int32_t c = key_chunk0[key]; c < key_chunk0[key + 1]; ++c) m = max(m, vmax2[c * C2 + f]);
     bin_vmax[b] = m;
 }
 
@@ -594,11 +600,13 @@ template <typename real, bool CPT>
 __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__restrict__ base1, int32_t nb1,
                                                        const int32_t *__restrict__ key_chunk0,
                                                        const int32_t *__restrict__ chunk_key,
-                                                       const Stats *__restrict__ st,
-                                                       const Rec1<real, CPT> *__restrict__ rec1,
+                                                       const Stats *__restrict__ st, const P1<CPT> *__restrict__ pos1,
+                                                       const real *__restrict__ vis1,
                                                        const int32_t *__restrict__ base2,
-                                                       uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis) {
-    extern __shared__ int32_t s_cur[];   // C^2 cursors, then C^2 per-tile placement offsets
+                                                       uint32_t *__restrict__ rec_pos, real *__restrict__ rec_vis,
+                                                       uint32_t *__restrict__ vmax2) {
+    // C^2 cursors, then C^2 per-tile placement offsets, then (float32) C^2 maxima
+    extern __shared__ int32_t s_cur[];
     __shared__ int32_t s_slot[kSub];
     __shared__ uint32_t s_pos[kSub];
     __shared__ real s_v[2 * kSub];
@@ -606,7 +614,12 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
     if (chunk >= (int32_t)st->n_chunks) return;
     const int32_t C2 = g.C * g.C;
     int32_t *s_adj = s_cur + C2;
-    for (int i = threadIdx.x; i < C2; i += kBlock) s_cur[i] = base2[(int64_t)chunk * C2 + i];
+    uint32_t *s_m = reinterpret_cast<uint32_t *>(s_cur + 2 * C2);
+    constexpr bool VMAX = sizeof(real) == 4;
+    for (int i = threadIdx.x; i < C2; i += kBlock) {
+        s_cur[i] = base2[(int64_t)chunk * C2 + i];
+        if (VMAX) s_m[i] = 0u;
+    }
     __syncthreads();
     const Chunk ck = chunk_of(g, base1, nb1, key_chunk0, chunk_key, chunk);
     for (int32_t r0 = ck.r0; r0 < ck.r1; r0 += kSub) {
@@ -618,21 +631,26 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
 #pragma unroll
         for (int j = 0; j < kSubPer; ++j) {
             const int32_t r = r0 + j * kBlock + (int32_t)threadIdx.x;
-            const bool valid = r < ck.r1;
+            bool valid = r < ck.r1;
             Pos1 ps{0, 0, 0, 0, 0};
             vr[j] = 0;
             vi[j] = 0;
             if (valid) {
-                const Rec1<real, CPT> p = rec1[r];
-                ps = pos_of<real>(g, p, ck.ctx, ck.cty);
-                vr[j] = p.vr;
-                vi[j] = p.vi;
+                ps = pos_of(g, pos1[r], ck.ctx, ck.cty);
+                vr[j] = vis1[2 * (int64_t)r];
+                vi[j] = vis1[2 * (int64_t)r + 1];
+                valid = !isnan((double)vr[j]);   // dead records are skipped
             }
             const Local ls = local_span(g, ps);
             const int32_t f = ls.fy0 * g.C + ls.fx0;
             const Run run = runs_of(valid ? f : -1);
             int32_t b0 = 0;
             if (valid && run.head) b0 = atomicAdd(&s_cur[f], run.len);
+            if constexpr (VMAX) {
+                // largest |W V| per tile (non-negative floats order as their bits)
+                const uint32_t mbits = __float_as_uint(fmaxf(fabsf((float)vr[j]), fabsf((float)vi[j])));
+                if (valid && mbits) atomicMax(&s_m[f], mbits);
+            }
             slot[j] = valid ? __shfl(b0, run.leader) + ((int32_t)__lane_id() - run.leader) : -1;
             tile[j] = f;
             const uint32_t ox = (uint32_t)(ps.ox1 & (g.T - 1)), oy = (uint32_t)(ps.oy1 & (g.T - 1));   // in the tile
@@ -668,6 +686,8 @@ __global__ __launch_bounds__(kBlock) void k_l2_scatter(Geom g, const int32_t *__
         }
         __syncthreads();   // the staging arrays and placement offsets are reused
     }
+    if constexpr (VMAX)
+        for (int i = threadIdx.x; i < C2; i += kBlock) vmax2[(int64_t)chunk * C2 + i] = s_m[i];
 }
 
 // ---- scan of per-bin record counts in bin order ----
@@ -828,9 +848,11 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
     const int64_t nvis = nrow * nchan;
     const L1Part part = l1_part(nvis);
     const size_t lds = size_t(g.n1) * sizeof(int32_t);
+    const bool cpt = g.cpt1 && sizeof(real) == 4;
+    real *vis1 = reinterpret_cast<real *>(static_cast<unsigned char *>(bb.rec1) + l1_vis_offset(nvis, cpt));
     if (phase == 0) {
-        hipLaunchKernelGGL(k_l1_count<real>, dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev, vis,
-                           weight, nvis, nchan, part, bb.cnt1, st);
+        hipLaunchKernelGGL(k_l1_count, dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev, weight, nvis,
+                           nchan, part, bb.cnt1);
     } else if (phase == 1) {
         const int64_t n = (int64_t)g.n1 * part.nb1;
         const int32_t nblk = (int32_t)((n + 1 + kScanTile - 1) / kScanTile);
@@ -839,12 +861,12 @@ hipError_t launch_bin_level1(const Geom &g, const BinBufs &bb, const double *uvw
         hipLaunchKernelGGL(k_flat_apply, dim3(nblk), dim3(kScanBlock), 0, s, bb.cnt1, n, bb.bsum);
         hipLaunchKernelGGL(k_l2_chunks, dim3(1), dim3(kScanBlock), 0, s, g, bb.cnt1, part.nb1, bb.key_chunk0,
                            bb.chunk_key, st);
-    } else if (g.cpt1 && sizeof(real) == 4) {
+    } else if (cpt) {
         hipLaunchKernelGGL((k_l1_scatter<real, true>), dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev,
-                           vis, weight, nvis, nchan, part, bb.cnt1, (Rec1<real, true> *)bb.rec1);
+                           vis, weight, nvis, nchan, part, bb.cnt1, (P1<true> *)bb.rec1, vis1, st);
     } else {
         hipLaunchKernelGGL((k_l1_scatter<real, false>), dim3(part.nb1), dim3(kL1Block), lds, s, g, uvw, scales_dev,
-                           vis, weight, nvis, nchan, part, bb.cnt1, (Rec1<real, false> *)bb.rec1);
+                           vis, weight, nvis, nchan, part, bb.cnt1, (P1<false> *)bb.rec1, vis1, st);
     }
     return hipGetLastError();
 }
@@ -859,17 +881,17 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
     const size_t lds = size_t(g.C) * g.C * sizeof(int32_t);
     const int32_t nbb = (g.nbins + kBlock - 1) / kBlock;
     const bool cpt = g.cpt1 && sizeof(real) == 4;
+    const real *vis1 =
+        reinterpret_cast<const real *>(static_cast<const unsigned char *>(bb.rec1) + l1_vis_offset(nvis, cpt));
     if (phase == 0) {
         if (cpt)
-            hipLaunchKernelGGL((k_l2_count<real, true>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1,
-                               bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, true> *)bb.rec1, bb.cnt2, bb.vmax2);
+            hipLaunchKernelGGL((k_l2_count<real, true>), dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+                               bb.key_chunk0, bb.chunk_key, st, (const P1<true> *)bb.rec1, vis1, bb.cnt2);
         else
-            hipLaunchKernelGGL((k_l2_count<real, false>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1,
-                               part.nb1, bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, false> *)bb.rec1, bb.cnt2,
-                               bb.vmax2);
+            hipLaunchKernelGGL((k_l2_count<real, false>), dim3(nchunk), dim3(kBlock), lds, s, g, bb.cnt1, part.nb1,
+                               bb.key_chunk0, bb.chunk_key, st, (const P1<false> *)bb.rec1, vis1, bb.cnt2);
     } else if (phase == 1) {
-        hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.vmax2,
-                           bb.counts, bb.bin_vmax);
+        hipLaunchKernelGGL(k_l2_totals, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.cnt2, bb.counts);
         const int32_t n = g.nbins;
         const int32_t nblk = (n + 1 + kScanTile - 1) / kScanTile;
         hipLaunchKernelGGL(k_scan_partials, dim3(nblk), dim3(kScanBlock), 0, s, bb.counts, n, g.CH, bb.bsum);
@@ -877,14 +899,19 @@ hipError_t launch_bin_level2(const Geom &g, const BinBufs &bb, int64_t nrow, int
         hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanBlock), 0, s, bb.counts, n, g.CH, bb.bsum, bb.scan,
                            bb.item_bin, bb.heavy_bins, st);
         hipLaunchKernelGGL(k_l2_bases, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.scan, bb.cnt2);
-    } else if (cpt) {
-        hipLaunchKernelGGL((k_l2_scatter<real, true>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1,
-                           bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, true> *)bb.rec1, bb.cnt2, bb.rec_pos,
-                           (real *)bb.rec_vis);
     } else {
-        hipLaunchKernelGGL((k_l2_scatter<real, false>), dim3(nchunk), dim3(kBlock), 2 * lds, s, g, bb.cnt1, part.nb1,
-                           bb.key_chunk0, bb.chunk_key, st, (const Rec1<real, false> *)bb.rec1, bb.cnt2, bb.rec_pos,
-                           (real *)bb.rec_vis);
+        // cursors, placement offsets and (float32 records) the per-tile maxima
+        const size_t lds2 = (sizeof(real) == 4 ? 3 : 2) * lds;
+        if (cpt)
+            hipLaunchKernelGGL((k_l2_scatter<real, true>), dim3(nchunk), dim3(kBlock), lds2, s, g, bb.cnt1, part.nb1,
+                               bb.key_chunk0, bb.chunk_key, st, (const P1<true> *)bb.rec1, vis1, bb.cnt2, bb.rec_pos,
+                               (real *)bb.rec_vis, bb.vmax2);
+        else
+            hipLaunchKernelGGL((k_l2_scatter<real, false>), dim3(nchunk), dim3(kBlock), lds2, s, g, bb.cnt1,
+                               part.nb1, bb.key_chunk0, bb.chunk_key, st, (const P1<false> *)bb.rec1, vis1, bb.cnt2,
+                               bb.rec_pos, (real *)bb.rec_vis, bb.vmax2);
+        if (sizeof(real) == 4)
+            hipLaunchKernelGGL(k_bin_vmax, dim3(nbb), dim3(kBlock), 0, s, g, bb.key_chunk0, bb.vmax2, bb.bin_vmax);
     }
     return hipGetLastError();
 }

@@ -311,7 +311,8 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
         g.nct = g.nt / C;
         g.n1 = g.Nw * g.nct * g.nct;
         g.CHK = 16 * C * C > 16384 ? 16 * C * C : 16384;
-        if (g.n1 > kMaxCoarse || int64_t(C) * C > 16384) {
+        // (a level-2 block keeps three C^2 tables in LDS)
+        if (g.n1 > kMaxCoarse || int64_t(C) * C > 4096) {
             delete p;
             return fail(RICK_E_INVALID_ARG, "no coarse binning fits %d planes of %d x %d tiles", g.Nw, g.nt, g.nt);
         }
@@ -413,7 +414,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     const size_t sz_bsum = (n_scanned + 2047) / 2048 * 2 * sizeof(int32_t) + 64;
     const size_t sz_cnt1 = n_cnt1 * sizeof(int32_t);
     // level-1 records: a footprint touches at most four coarse bins
-    const size_t sz_rec1 = size_t(p->rec_cap) * (8 + 2 * rb);
+    const size_t sz_rec1 = size_t(p->rec_cap) * (8 + 2 * rb) + 256;   // positions, then W V (256-byte aligned)
     p->max_chunks = bin_max_chunks(g, p->rec_cap);
     const size_t sz_kc0 = size_t(g.n1 + 1) * sizeof(int32_t);
     const size_t sz_ckey = size_t(p->max_chunks) * sizeof(int32_t);
@@ -702,7 +703,7 @@ StaticLayout static_layout(const Geom &g, size_t rb, int64_t nvis) {
         off += up(bytes > 0 ? bytes : 1);
         return at;
     };
-    L.rec1 = take(size_t(nvis) * (8 + 2 * rb));
+    L.rec1 = take(size_t(nvis) * (8 + 2 * rb) + 256);
     L.chunk_key = take(chunks * sizeof(int32_t));
     L.cnt2 = take(chunks * g.C * g.C * sizeof(int32_t));
     L.vmax2 = take(chunks * g.C * g.C * sizeof(uint32_t));

@@ -7,6 +7,8 @@
 //   iw = clamp(floor(((w - w_min) / dw - k) N_f), 0, N_f - 1)
 //   dropped if any input is non-finite, the position is beyond 2^30
 //   sub-cells, the weight is <= 0, or the W x W footprint leaves the grid.
+// quantise_pos takes every decision but the finiteness of V, so that the
+// binning's counting pass need not read the visibilities.
 #pragma once
 #include "rick_internal.h"
 
@@ -17,16 +19,14 @@ struct Quant {
     int32_t iw;   // w-fraction bin (0 with a separable tap table)
 };
 
-// Position, plane and drop decision of one visibility, evaluated without
+// Position, plane and drop decision of one visibility from (u, v, w) and its
+// weight alone (every test but the finiteness of V), evaluated without
 // branches (every lane computes every step; the decisions are combined at
 // the end), which keeps the loop free of execution-mask changes.
-template <typename real>
-__device__ __forceinline__ bool quantise(const Geom &g, double u, double v, double w, real vr, real vi, float wt,
-                                         Quant &q) {
+__device__ __forceinline__ bool quantise_pos(const Geom &g, double u, double v, double w, float wt, Quant &q) {
 #pragma clang fp contract(off)
     // (bitwise & on 0/1 integers on purpose: no short-circuit branches)
-    unsigned ok = (unsigned)isfinite(u) & (unsigned)isfinite(v) & (unsigned)isfinite(w) &
-                  (unsigned)isfinite((double)vr) & (unsigned)isfinite((double)vi) & (unsigned)isfinite(wt);
+    unsigned ok = (unsigned)isfinite(u) & (unsigned)isfinite(v) & (unsigned)isfinite(w) & (unsigned)isfinite(wt);
     double xs = u * g.fov;
     xs = xs * (double)g.OS;
     xs = xs + g.half;
@@ -61,6 +61,15 @@ __device__ __forceinline__ bool quantise(const Geom &g, double u, double v, doub
     }
     if (!ok) q = Quant{0, 0, 0, 0, 0, 0};
     return ok != 0u;
+}
+
+// The whole decision: quantise_pos and a finite V.
+template <typename real>
+__device__ __forceinline__ bool quantise(const Geom &g, double u, double v, double w, real vr, real vi, float wt,
+                                         Quant &q) {
+    const bool ok = quantise_pos(g, u, v, w, wt, q) & isfinite((double)vr) & isfinite((double)vi);
+    if (!ok) q = Quant{0, 0, 0, 0, 0, 0};
+    return ok;
 }
 
 }  // namespace rick

@@ -82,7 +82,7 @@ struct Stats {
     double sum_w;
     unsigned long long n_chunks;    // level-2 binning chunks of the last rick_grid
     unsigned long long grid_next;   // gridding work items handed out (zeroed before each gridding launch)
-    double pad2;
+    unsigned long long n_dead;      // level-1 records of the last rick_grid without a finite W V
 };
 
 // Binning bookkeeping written by the scan: per bin, exclusive prefix sums of
@@ -156,7 +156,7 @@ hipError_t launch_set_scales(double *dst, const double *host_scales, int32_t nch
 struct BinBufs {
     int32_t *cnt1;        // [n1 * kL1Blocks + 1] per (coarse bin, block) counts, scanned in place
     int32_t *bsum;        // partial sums of the scans
-    void *rec1;           // level-1 records {cell x | y << 16, sub-cell x | y << 8 | plane << 16, W V}
+    void *rec1;           // level-1 records: positions, then W V at l1_vis_offset (binsort.hip)
     int32_t *key_chunk0;  // [n1 + 1] first level-2 chunk of each coarse bin
     int32_t *chunk_key;   // [max chunks] coarse bin of each level-2 chunk
     int32_t *cnt2;        // [max chunks][C^2] per (chunk, tile) counts, then record offsets

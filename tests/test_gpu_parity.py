@@ -224,6 +224,28 @@ def test_dropped_inputs_match_oracle():
     check_stages(ds, run_gpu(ds), ref)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_many_nonfinite_visibilities(precision):
+    """Visibilities whose position passes every test but whose V is not
+    finite: the binning's counting pass does not read V, so they take level-1
+    slots and are skipped at level 2; counts, sums and image stay the
+    oracle's (every seventh visibility NaN or infinite, small tiles and chunks)"""
+    ds = synth.tiny(nrow=20000, seed=12)
+    vis = np.asarray(ds.vis).copy()
+    vis[::7, 0] = np.nan
+    vis[3::14, 0] = np.complex64(complex(np.inf, 0.0))
+    vis[5::21, 0] = np.complex64(complex(0.0, -np.inf))
+    ds.vis = vis
+    ref = oracle_of(ds)
+    assert (~ref.binned.keep).sum() > 2800
+    gpu = run_gpu(ds, precision=precision, tile=16, chunk=64)
+    if precision == "fp64":
+        assert rel_rms(gpu["G"], ref.planes) <= 1e-12 and rel_rms(gpu["img"], ref.image) <= FP64_IMG
+        assert gpu["info"]["n_gridded"] == int(ref.binned.keep.sum())
+    else:
+        check_stages(ds, gpu, ref)
+
+
 @pytest.mark.parametrize("tile,chunk", [(0, 0), (16, 512), (16, 64)])
 def test_accumulating_two_grid_calls_equals_one(tile, chunk):
     """also with bins split over several chunks (16, 512) and (16, 64)"""
