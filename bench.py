@@ -579,11 +579,13 @@ def precision_report(args):
 
 def batch_report(args):
     """The batched form: many independent jobs of uneven size (grid, planes,
-    visibility count, field) recorded once into a graph and replayed.  One
-    plan per (grid, planes) shape, its tile and chunk picked by the autotuner
-    on the shape's largest job and retargeted to each job's field.  Reports
-    jobs/s, per-job latency percentiles (device timestamps between the jobs),
-    the same jobs run eagerly, and the graph images against the eager ones.
+    visibility count, field) recorded once into a graph and replayed.  Plans
+    per (grid, planes) shape (--replicas of them, the shape's jobs dealt to
+    them in turn), tile and chunk picked by the autotuner on the shape's
+    largest job, retargeted to each job's field.  Reports jobs/s, per-job
+    latency percentiles (device timestamps between the jobs), the same jobs
+    run eagerly, and the graph images against the eager ones; with --streams
+    above 1 also the jobs spread over several streams inside the recording.
     Prints one JSON line."""
     import torch
     import synth
@@ -602,21 +604,27 @@ def batch_report(args):
     for i, ds in enumerate(jobs):
         shapes.setdefault((ds.grid_n, ds.n_wplanes), []).append(i)
     stream = torch.cuda.Stream()
-    tuned, plans = {}, {}
+    tuned, plans, slot_of = {}, {}, {}
     t0 = time.time()
     for key, idx in sorted(shapes.items()):
         big = max(idx, key=lambda i: jobs[i].nvis)
         tile, chunk, ms = rick.autotune(jobs[big], uvw[big], vis[big], fused=True, stream=stream,
                                         orient=not args.no_orient)
         tuned[key] = (tile, chunk, ms)
-        plans[key] = rick.Plan.for_dataset(jobs[big], max_vis=max(jobs[i].nvis for i in idx), tile=tile,
-                                           chunk=chunk, fused=True, orient=not args.no_orient)
-    print(f"[batch] autotuned {len(shapes)} shapes in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+        reps = max(1, min(args.replicas, len(idx)))
+        for r in range(reps):
+            mine = idx[r::reps]
+            plans[(key, r)] = rick.Plan.for_dataset(jobs[big], max_vis=max(jobs[i].nvis for i in mine), tile=tile,
+                                                    chunk=chunk, fused=True, orient=not args.no_orient)
+            for i in mine:
+                slot_of[i] = (key, r)
+    print(f"[batch] autotuned {len(shapes)} shapes in {time.time() - t0:.1f} s; {len(plans)} plans",
+          file=sys.stderr, flush=True)
     imgs = [torch.empty((ds.grid_n, ds.grid_n), dtype=torch.float32, device=dev) for ds in jobs]
 
     def issue(i, s):
         ds = jobs[i]
-        p = plans[(ds.grid_n, ds.n_wplanes)]
+        p = plans[slot_of[i]]
         p.retarget(ds.fov, ds.w_min, ds.w_max)
         p.reset(s)
         p.grid(uvw[i], vis[i], None, ds.freq, s)
@@ -647,20 +655,21 @@ def batch_report(args):
         totals.append(stamps.elapsed(0, n))
         lat = [stamps.elapsed(i, i + 1) for i in range(n)]
     seq_imgs = [im.clone() for im in imgs]
-    # the same jobs on several streams: each plan (shape) stays on one stream,
-    # so its jobs keep their order; shapes are spread over the streams by total
-    # visibility count, and the streams fork from and join the first one
-    S = max(1, min(args.streams, len(shapes)))
+    # the same jobs on several streams: each plan stays on one stream, so its
+    # jobs keep their order; plans are spread over the streams by the total
+    # visibility count of their jobs, and the streams fork from and join the
+    # first one
+    S = max(1, min(args.streams, len(plans)))
     conc = None
     if S > 1:
         streams = [stream] + [torch.cuda.Stream() for _ in range(S - 1)]
-        load, shape_stream = [0] * S, {}
-        for key in sorted(shapes, key=lambda k: -sum(jobs[i].nvis for i in shapes[k])):
+        load, plan_stream = [0] * S, {}
+        plan_jobs = {k: [i for i in range(n) if slot_of[i] == k] for k in plans}
+        for key in sorted(plans, key=lambda k: -sum(jobs[i].nvis for i in plan_jobs[k])):
             j = min(range(S), key=lambda x: load[x])
-            shape_stream[key] = j
-            load[j] += sum(jobs[i].nvis for i in shapes[key])
-        per_stream = [[i for i in range(n) if shape_stream[(jobs[i].grid_n, jobs[i].n_wplanes)] == j]
-                      for j in range(S)]
+            plan_stream[key] = j
+            load[j] += sum(jobs[i].nvis for i in plan_jobs[key])
+        per_stream = [[i for i in range(n) if plan_stream[slot_of[i]] == j] for j in range(S)]
         order = [lst[r] for r in range(max(len(x) for x in per_stream)) for lst in per_stream if r < len(lst)]
         cstamps = rick.Stamps(2 * n + 2)
 
@@ -671,7 +680,7 @@ def batch_report(args):
             for st in streams[1:]:
                 st.wait_event(ev)
             for i in order:
-                st = streams[shape_stream[(jobs[i].grid_n, jobs[i].n_wplanes)]]
+                st = streams[plan_stream[slot_of[i]]]
                 cstamps.stamp(2 + 2 * i, st)
                 issue(i, st)
                 cstamps.stamp(3 + 2 * i, st)
@@ -699,7 +708,8 @@ def batch_report(args):
         conc_imgs = [im.clone() for im in imgs]
         cmed = float(np.median(ctot))
         cl = np.sort(np.asarray(clat))
-        conc = {"streams": S, "jobs_per_s": round(n / (cmed * 1e-3), 2), "batch_ms": round(cmed, 3),
+        conc = {"streams": S, "plans": len(plans), "jobs_per_s": round(n / (cmed * 1e-3), 2),
+                "batch_ms": round(cmed, 3),
                 "mvis_per_s": round(nvis / (cmed * 1e-3) / 1e6, 1),
                 "eager_batch_ms": round(float(np.median(ceager)), 3),
                 "latency_ms": {"p50": round(float(np.percentile(cl, 50)), 3),
@@ -1033,6 +1043,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the batched form: many uneven jobs recorded into a graph and replayed (jobs/s, latency)")
     ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
+    ap.add_argument("--replicas", type=int, default=2,
+                    help="--batch: plans per (grid, planes) shape, the shape's jobs dealt to them in turn")
     ap.add_argument("--no-orient", action="store_true",
                     help="--batch: keep every plane in its own orientation (no transposed planes)")
     ap.add_argument("--streams", type=int, default=4,

@@ -542,6 +542,10 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_margins(Geom g, const Bin
     // a transposed plane keeps cell (y, x) at row x, column y, and the bit of
     // tile (ty, tx) at (tx, ty): bits of other blocks share its words
     const bool tr = plane_transposed(plane_tr, k);
+    // the bins of a tile row are consecutive: no record in this tile row or
+    // the one above means no tile here changes (no records, no margins)
+    const int64_t b_row = ((int64_t)k * g.nt + ty) * g.nt;
+    if (!(scan[b_row + g.nt].rec > scan[b_row].rec) && !(ty > 0 && scan[b_row].rec > scan[b_row - g.nt].rec)) return;
     if (threadIdx.x < kMaxOccWords) s_word[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
