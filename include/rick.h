@@ -80,7 +80,9 @@ enum {
 };
 
 enum {
-    RICK_PREC_FP32 = 0,        /* float mesh, FFT and plane sum; float64 phase argument and normalisation */
+    RICK_PREC_FP32 = 0,        /* float mesh, FFT and plane sum; float64 phase argument and normalisation;
+                                  gridding sums each cell as integers (terms rounded at 2^-21 of the
+                                  largest possible term of their bin) */
     RICK_PREC_FP32_KAHAN = 1,  /* as FP32, compensated (Kahan) summation over w-planes */
     RICK_PREC_FP64 = 2         /* every step in float64 (complex128 mesh) */
 };

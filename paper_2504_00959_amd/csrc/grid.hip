@@ -14,17 +14,12 @@
 // Accumulators are 64-bit: float32 LDS atomic adds are many times slower than
 // 64-bit ones on gfx950, and dense cells collect thousands of terms, which
 // float32 accumulation would round to ~1e-5 of image RMS.  In float64 mode
-// they are float64.  In float32 mode they are 64-bit fixed point: each term
-// W V g_y g_x is scaled by a power of two 2^s, rounded to an integer and
-// added with an integer atomic (cheaper than the float64 one).  s is chosen
-// per block so that every term stays below 2^50 and any cell's sum of the
-// block's n terms below 2^61 (from the largest |W V| of the bin, found by the
-// binning, and the largest tap), so nothing overflows; a term is rounded at 2^-50 of the
-// largest possible term, far below its own float32 rounding, and integer
-// sums do not depend on the order of the adds.  The rounding uses the
-// float64 adder: fma(g, V 2^s, 1.5 2^52) holds round(g V 2^s) in its low
-// mantissa bits.
-//
+// they are float64 (re and im planes).  In the float32 modes a cell is one
+// 64-bit word holding re and im as two 32-bit fixed-point halves (below):
+// each term W V g_y g_x is scaled by a power of two 2^s chosen per bin from
+// the largest |W V| of the bin (found by the binning) and the largest tap,
+// rounded to an integer below 2^21, and both halves are added with one
+// integer atomic; integer sums do not depend on the order of the adds.
 // Records arrive 64 at a time in one coalesced load (the next 64 are loaded
 // while these are gridded); each lane decodes the record it loaded (footprint
 // origin, tap-table rows), and the decoded fields are broadcast with readlane.
@@ -143,15 +138,7 @@ constexpr int im_plane_offset() { return plane_offset(W, T); }
 // atomics just issued (LDS operations complete in order).
 constexpr int kGroup = 4;
 
-// Fixed-point terms: x + 1.5 2^52 (|x| < 2^51, rounded to an integer) has
-// bit pattern 0x4338000000000000 + round(x); the constant's low word is zero,
-// so the integer is the high word minus 0x43380000 over the low word.
-constexpr double kRoundMagic = 6755399441055744.0;   // 1.5 2^52
-__device__ __forceinline__ unsigned long long fixed_of(double t) {
-    return (unsigned long long)(uint32_t)(__double2hiint(t) - 0x43380000) << 32 | (uint32_t)__double2loint(t);
-}
-
-// Packed float32 accumulation (pk32): re and im of a cell share one 64-bit
+// Packed float32 accumulation: re and im of a cell share one 64-bit
 // LDS word, re in the low and im in the high 32 bits, as the integer
 // im 2^32 + re; one ds_add_u64 then adds both.  Each term is rounded to an
 // integer below 2^21 (the scale 2^s follows the bin's largest possible
@@ -181,11 +168,11 @@ __device__ __forceinline__ void unpack_terms(unsigned long long s, long long &re
 // T[iw][s_y][s_x][t_y][t_x] (w-fraction bin iw in bits 6-7 and 14 of the
 // packed position), one value per tap instead of the product of two
 // separable rows held in LDS; tapmax points at the table's largest |value|.
-// P32: packed float32 accumulation (above); float64 re and im planes otherwise.
+// float32: packed accumulation (above); float64: float64 re and im planes.
 // Persistent: a block takes work items blockIdx.x, then the next unclaimed
 // one from st->grid_next (claimed while the current one is gridded), until
 // the device-side item count is reached.
-template <typename real, int W, int TT, bool L3, bool P32>
+template <typename real, int W, int TT, bool L3>
 __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom g, const BinScan *__restrict__ scan,
                                                      const int32_t *__restrict__ item_bin,
                                                      const uint32_t *__restrict__ rec_pos,
@@ -195,7 +182,7 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
                                                      const uint32_t *__restrict__ bin_vmax,
                                                      const float *__restrict__ tapmax, Stats *__restrict__ st,
                                                      const int32_t *__restrict__ plane_tr) {
-    static_assert(!P32 || std::is_same<real, float>::value, "packed accumulation is a float32 mode");
+    constexpr bool P32 = std::is_same<real, float>::value;   // packed fixed point
     constexpr int W2 = W * W;
     constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
     constexpr int kGridBlock = grid_threads(TT);
@@ -212,9 +199,7 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
     const int32_t T = g.T, P = g.pitch;
     using r2 = typename real2_t<real>::type;
     r2 *m = reinterpret_cast<r2 *>(mesh);
-    // float32 modes: 64-bit fixed point with scale 2^s (see the file comment)
-    constexpr bool FIX = std::is_same<real, float>::value;
-    using acc_t = typename std::conditional<FIX, unsigned long long, double>::type;
+    using acc_t = typename std::conditional<P32, unsigned long long, double>::type;
     using vreg_t = typename std::conditional<P32, float, double>::type;   // W V as the taps multiply it
     // LDS: real plane at byte 0, imaginary plane KOFF doubles further (not
     // with P32), then the tap table; a plane is R = T + W - 1 rows of pitch P
@@ -261,15 +246,14 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
         const int32_t rem = b - k * g.nt * g.nt;
         const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
         double scale = 1.0, unscale = 1.0;
-        if (FIX) {
+        if (P32) {
             const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
             // largest |term|: |W V| times the largest |tap| (the square of the
             // largest separable row value, or the largest entry of the table)
             const double bt = vmax * (L3 ? (double)*tapmax * (1.0 + 1e-6) : (double)g.gmax2);
             if (bt > 0.0 && bt < 1e300) {
-                const int et = ilogb(bt) + 1, en = ilogb((double)n) + 1;   // bt < 2^et, n < 2^en
-                int sh = P32 ? kPackTermBits - et : min(50 - et, 61 - et - en);
-                if (P32) sh = min(sh, 120);   // 2^s stays a normal float32
+                const int et = ilogb(bt) + 1;   // bt < 2^et
+                const int sh = min(kPackTermBits - et, 120);   // (2^s stays a normal float32)
                 scale = ldexp(1.0, sh);
                 unscale = ldexp(1.0, -sh);
             }
@@ -298,9 +282,6 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
                 const float2 v = reinterpret_cast<const float2 *>(acc_re)[i];
                 re = v.x;
                 im = v.y;
-            } else if constexpr (FIX) {
-                re = (real)((double)(long long)acc_re[i] * unscale);
-                im = (real)((double)(long long)acc_im[i] * unscale);
             } else {
                 re = (real)acc_re[i];
                 im = (real)acc_im[i];
@@ -399,26 +380,13 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
                                 atomicAdd(a, pack_terms(tr, ti));
                             }
                         } else {
-                            double tr, ti;
-                            if constexpr (FIX) {
-                                // round(g V 2^s) in the low mantissa bits (exact product, one rounding)
-                                tr = fma((double)wgt, vr, kRoundMagic);
-                                ti = fma((double)wgt, vi, kRoundMagic);
-                            } else {
-                                tr = wgt * vr;
-                                ti = wgt * vi;
-                            }
+                            double tr = wgt * vr, ti = wgt * vi;
                             __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
                             // (with one tap group the whole record loop already runs on the tap lanes)
                             if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
                                 acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
-                                if constexpr (FIX) {
-                                    atomicAdd(a, fixed_of(tr));
-                                    atomicAdd(a + KOFF, fixed_of(ti));
-                                } else {
-                                    atomicAdd(a, tr);
-                                    atomicAdd(a + KOFF, ti);
-                                }
+                                atomicAdd(a, tr);
+                                atomicAdd(a + KOFF, ti);
                             }
                         }
                     }
@@ -694,7 +662,7 @@ int device_cus() {
     return (dev >= 0 && dev < kMaxDevices && cus[dev] > 0) ? cus[dev] : 256;
 }
 
-template <typename real, int W, int TT, bool L3, bool P32>
+template <typename real, int W, int TT, bool L3>
 hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                    const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
@@ -703,7 +671,7 @@ hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, 
     static std::once_flag attr_once[kMaxDevices];
     once_per_device(attr_once, [&] {
         // (the kernel's own 8 bytes of static LDS come on top of the dynamic size)
-        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT, L3, P32>,
+        (void)hipFuncSetAttribute((const void *)k_grid<real, W, TT, L3>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - 64));
     });
     // persistent blocks: as many as the CUs hold at once (LDS and 32 waves per CU)
@@ -713,7 +681,7 @@ hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, 
     per_cu = per_cu < 1 ? 1 : per_cu;
     const int64_t want = int64_t(device_cus()) * per_cu;
     const int64_t nblk = want < max_items ? want : max_items;
-    hipLaunchKernelGGL((k_grid<real, W, TT, L3, P32>), dim3((unsigned)(nblk > 0 ? nblk : 1)), dim3(grid_threads(TT)),
+    hipLaunchKernelGGL((k_grid<real, W, TT, L3>), dim3((unsigned)(nblk > 0 ? nblk : 1)), dim3(grid_threads(TT)),
                        lds, s, g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, tapmax,
                        st, plane_tr);
     return hipGetLastError();
@@ -724,13 +692,10 @@ hipError_t grid_wt2(const Geom &g, const BinScan *scan, const int32_t *item_bin,
                     const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                     const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
                     int32_t max_items, hipStream_t s) {
-#define GRID_WT(L3, P32) \
-    grid_wt<real, W, TT, L3, P32>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, \
-                                  tapmax, st, plane_tr, max_items, s)
-    if constexpr (std::is_same<real, float>::value) {
-        if (g.pk32) return tapmax ? GRID_WT(true, true) : GRID_WT(false, true);
-    }
-    return tapmax ? GRID_WT(true, false) : GRID_WT(false, false);
+#define GRID_WT(L3) \
+    grid_wt<real, W, TT, L3>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax, tapmax, \
+                             st, plane_tr, max_items, s)
+    return tapmax ? GRID_WT(true) : GRID_WT(false);
 #undef GRID_WT
 }
 
@@ -758,7 +723,7 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
     // real plane, imaginary plane at plane_offset(W, T) doubles (packed mode:
     // one plane of 64-bit words), each T + W - 1 rows of the pitch; then the tap table
-    const size_t koff = (g.pk32 && real_bytes == 4) ? 0 : size_t(plane_offset(g.W, g.T));
+    const size_t koff = real_bytes == 4 ? 0 : size_t(plane_offset(g.W, g.T));
     return (koff + size_t(g.T + g.W - 1) * g.pitch) * sizeof(double) + size_t(g.OS) * g.W * real_bytes;
 }
 

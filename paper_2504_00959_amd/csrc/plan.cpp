@@ -282,9 +282,6 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     Geom &g = p->g;
     g.N = d->grid_n;
     g.Nw = d->n_wplanes;
-    // float32 modes: re and im accumulate as the two 32-bit halves of one
-    // 64-bit fixed-point word (one LDS atomic per tap)
-    g.pk32 = d->precision != RICK_PREC_FP64 ? 1 : 0;
     g.W = d->support;
     g.h = (d->support - 1) / 2;
     g.OS = d->oversample;

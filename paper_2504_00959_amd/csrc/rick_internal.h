@@ -66,7 +66,6 @@ struct Geom {
     int32_t cpt1;       // level-1 records in the compact 12-byte format (float32 mode, when it fits)
     int32_t nwf;        // w-fraction bins of a non-separable tap table (1 otherwise)
     int32_t lut3;       // 1: the taps come from a non-separable table T[nwf][OS][OS][W][W]
-    int32_t pk32;       // 1: gridding sums re and im as two 32-bit fixed-point halves of one 64-bit word
     double fov;
     double half;        // N * OS / 2
     double w_min;
