@@ -310,10 +310,12 @@ rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz
  * of rick_degrid_sorted read neighbouring footprints.
  *
  * rick_degrid_order_create -- quantise (exactly as rick_grid and rick_degrid
- * do, for the plan's current grid, field and w range) and sort.  uvw and
- * freq_hz as for rick_degrid; nrow * nchan < 2^32.  Allocates device memory
- * (16 B per visibility kept, 32 B per visibility plus the sort's scratch
- * during the call) and synchronises `stream`.  *out receives the handle.
+ * do, for the plan's current grid, field and w range) and sort (the
+ * library's stable LSD radix sort, one pass per 8 bits of the key width).
+ * uvw and freq_hz as for rick_degrid; nrow * nchan < 2^31.  Allocates device
+ * memory (16 B per visibility kept, 32 B per visibility plus the sort's
+ * scratch, about 0.5 B per visibility, during the call) and synchronises
+ * `stream`.  *out receives the handle.
  * Errors: RICK_E_BAD_PLAN, RICK_E_INVALID_ARG, RICK_E_OOM, RICK_E_HIP.
  */
 typedef struct rick_degrid_order_s rick_degrid_order_t;

@@ -837,6 +837,16 @@ hipError_t static_scratch(int device, void **out) {
     return *out ? hipSuccess : hipErrorInvalidSymbol;
 }
 
+int64_t flat_scan_partials(int64_t n) { return (n + 1 + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_flat_scan(int32_t *a, int64_t n, int32_t *bsum, hipStream_t s) {
+    const int32_t nblk = (int32_t)flat_scan_partials(n);
+    hipLaunchKernelGGL(k_flat_partials, dim3(nblk), dim3(kScanBlock), 0, s, a, n, bsum);
+    hipLaunchKernelGGL(k_flat_top, dim3(1), dim3(kScanBlock), 0, s, bsum, nblk);
+    hipLaunchKernelGGL(k_flat_apply, dim3(nblk), dim3(kScanBlock), 0, s, a, n, bsum);
+    return hipGetLastError();
+}
+
 int32_t bin_max_chunks(const Geom &g, int64_t max_records) {
     return (int32_t)(g.n1 + (max_records + g.CHK - 1) / g.CHK);
 }

@@ -11,7 +11,7 @@
 // The forward DFT runs through the library's centred inverse FFT: the screen
 // kernel writes the complex conjugate of P_k, the inverse transform of
 // conj(P_k) is conj(H_k), and the interpolation conjugates what it reads.
-#include <rocprim/device/device_radix_sort.hpp>
+#include <utility>
 
 #include "rick_internal.h"
 #include "quant.h"
@@ -333,10 +333,115 @@ hipError_t launch_order_keys(const Geom &g, const double *uvw, const double *sca
     return hipGetLastError();
 }
 
-hipError_t sort_order(void *temp, size_t &temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
-                      const uint64_t *vals_in, uint64_t *vals_out, int64_t n, int end_bit, hipStream_t s) {
-    return rocprim::radix_sort_pairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0,
-                                     (unsigned)end_bit, s);
+// Stable LSD radix sort of (key, value) pairs, 8 bits per pass.  A block
+// takes a tile of kSortTile consecutive items; per pass a histogram kernel
+// counts the tile's digits in LDS and writes them digit-major into a
+// (digit, block) table, a flat exclusive scan of that table gives every
+// (digit, block) its first output slot, and a scatter kernel walks the tile
+// again in order, one item per thread per round: each wave finds the lanes
+// sharing an item's digit with eight ballots, the rank among them, and the
+// counts of earlier waves of the round come through LDS, so equal digits keep
+// their input order.
+constexpr int kSortThreads = 256;   // = the radix
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortWaves = kSortThreads / 64;
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                            int32_t nblk, int32_t *__restrict__ counts) {
+    __shared__ int32_t h[kSortThreads];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t i = base + j * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & 0xffu)], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t *__restrict__ kin,
+                                                               const uint64_t *__restrict__ vin, int64_t n, int shift,
+                                                               int32_t nblk, const int32_t *__restrict__ first,
+                                                               uint64_t *__restrict__ kout,
+                                                               uint64_t *__restrict__ vout) {
+    __shared__ int32_t s_next[kSortThreads];             // next output slot of each digit
+    __shared__ int32_t s_wc[kSortWaves][kSortThreads];   // per-wave digit counts of the round
+    const int t = (int)threadIdx.x, lane = t & 63, wid = t >> 6;
+    s_next[t] = first[(int64_t)t * nblk + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortItems; ++j) {
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) s_wc[w][t] = 0;
+        __syncthreads();
+        const int64_t i = base + j * kSortThreads + t;
+        const bool valid = i < n;
+        const uint64_t key = valid ? kin[i] : 0ull, val = valid ? vin[i] : 0ull;
+        const int d = (int)((key >> shift) & 0xffu);
+        // lanes of this wave holding an item with the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1;
+            const uint64_t b = __ballot(on);
+            peers &= on ? b : ~b;
+        }
+        const uint64_t below = peers & ((1ull << lane) - 1ull);
+        if (valid && below == 0ull) s_wc[wid][d] = __popcll(peers);   // the group's first lane
+        __syncthreads();
+        if (valid) {
+            int32_t pos = s_next[d] + __popcll(below);
+            for (int w = 0; w < wid; ++w) pos += s_wc[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) add += s_wc[w][t];
+        s_next[t] += add;
+        __syncthreads();
+    }
+}
+
+hipError_t sort_order(void *temp, size_t &temp_bytes, uint64_t *keys_in, uint64_t *keys_out, uint64_t *vals_in,
+                      uint64_t *vals_out, int64_t n, int begin_bit, int end_bit, hipStream_t s) {
+    const int64_t nblk = (n + kSortTile - 1) / kSortTile;
+    const int64_t ncount = (int64_t)kSortThreads * nblk;
+    const size_t count_bytes = ((size_t)(ncount + 1) * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t need = count_bytes + (size_t)flat_scan_partials(ncount) * sizeof(int32_t);
+    if (!temp) {
+        temp_bytes = need;
+        return hipSuccess;
+    }
+    if (temp_bytes < need || n <= 0 || n >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    int32_t *counts = static_cast<int32_t *>(temp);
+    int32_t *bsum = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(temp) + count_bytes);
+    const int passes = (end_bit - begin_bit + 7) / 8;
+    // pass p reads from one buffer pair and writes the other; an odd count
+    // of passes ends in the output pair, an even one is copied there
+    uint64_t *ks = keys_in, *vs = vals_in, *kd = keys_out, *vd = vals_out;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = begin_bit + 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kSortThreads), 0, s, ks, n, shift, (int32_t)nblk,
+                           counts);
+        hipError_t e = launch_flat_scan(counts, ncount, bsum, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kSortThreads), 0, s, ks, vs, n, shift,
+                           (int32_t)nblk, counts, kd, vd);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        std::swap(ks, kd);
+        std::swap(vs, vd);
+    }
+    if (ks != keys_out) {
+        hipError_t e = hipMemcpyAsync(keys_out, ks, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(vals_out, vs, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
+        return e;
+    }
+    return hipSuccess;
 }
 
 template <typename real>

@@ -953,7 +953,7 @@ rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const do
     if (nchan < 1) return fail(RICK_E_INVALID_ARG, "nchan=%d", nchan);
     if (!freq_hz && nchan != 1) return fail(RICK_E_INVALID_ARG, "nchan=%d without freq_hz", nchan);
     if (nchan > kMaxChan) return fail(RICK_E_INVALID_ARG, "nchan=%d > %d", nchan, kMaxChan);
-    if (nrow > ((int64_t(1) << 32) - 1) / nchan) return fail(RICK_E_INVALID_ARG, "nrow*nchan >= 2^32");
+    if (nrow > ((int64_t(1) << 31) - 1) / nchan) return fail(RICK_E_INVALID_ARG, "nrow*nchan >= 2^31");
     if (nrow > 0 && !uvw) return fail(RICK_E_INVALID_ARG, "uvw is NULL");
     if ((uintptr_t)uvw & 7) return fail(RICK_E_INVALID_ARG, "misaligned uvw");
     std::vector<double> sc(nchan, 1.0);
@@ -996,9 +996,9 @@ rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const do
     if (e == hipSuccess)
         e = p->fp64 ? launch_order_keys<double>(g, uvw, p->scales, nrow, nchan, panel, kin, vin, s)
                     : launch_order_keys<float>(g, uvw, p->scales, nrow, nchan, panel, kin, vin, s);
-    if (e == hipSuccess && nvis > 0) e = sort_order(nullptr, temp_bytes, kin, kout, vin, vout, nvis, end_bit, s);
+    if (e == hipSuccess && nvis > 0) e = sort_order(nullptr, temp_bytes, kin, kout, vin, vout, nvis, 0, end_bit, s);
     if (e == hipSuccess && nvis > 0) e = hipMalloc(&temp, temp_bytes > 0 ? temp_bytes : 1);
-    if (e == hipSuccess && nvis > 0) e = sort_order(temp, temp_bytes, kin, kout, vin, vout, nvis, end_bit, s);
+    if (e == hipSuccess && nvis > 0) e = sort_order(temp, temp_bytes, kin, kout, vin, vout, nvis, 0, end_bit, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     release();
     if (e != hipSuccess) {

@@ -170,6 +170,10 @@ struct BinBufs {
 };
 // Upper bound of level-2 chunks for max_records level-1 records.
 int32_t bin_max_chunks(const Geom &g, int64_t max_records);
+// Exclusive scan of a[0..n) in place, a[n] receiving the total (a holds n + 1
+// entries, every partial sum below 2^31); bsum holds flat_scan_partials(n) ints.
+int64_t flat_scan_partials(int64_t n);
+hipError_t launch_flat_scan(int32_t *a, int64_t n, int32_t *bsum, hipStream_t s);
 // Level 1 of bin-and-sort.  phase 0: coarse counts, drop test, weight sum;
 // 1: scan of the count table and level-2 chunk list; 2: level-1 records.
 template <typename real>
@@ -298,13 +302,14 @@ hipError_t launch_predict_screen(const Geom &g, const real *model, const double 
                                  uint64_t *tile_bits, uint64_t *row_bits, hipStream_t s);
 
 // Prediction at fixed positions: sort keys and values of every visibility,
-// their radix sort (temp == nullptr queries temp_bytes), and interpolation in
-// sorted order.
+// their stable LSD radix sort on bits [begin_bit, end_bit) (temp == nullptr
+// queries temp_bytes; keys_in and vals_in are overwritten, being the other
+// half of the ping-pong; n < 2^31), and interpolation in sorted order.
 template <typename real>
 hipError_t launch_order_keys(const Geom &g, const double *uvw, const double *scales, int64_t nrow, int32_t nchan,
                              int32_t panel, uint64_t *keys, uint64_t *vals, hipStream_t s);
-hipError_t sort_order(void *temp, size_t &temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
-                      const uint64_t *vals_in, uint64_t *vals_out, int64_t n, int end_bit, hipStream_t s);
+hipError_t sort_order(void *temp, size_t &temp_bytes, uint64_t *keys_in, uint64_t *keys_out, uint64_t *vals_in,
+                      uint64_t *vals_out, int64_t n, int begin_bit, int end_bit, hipStream_t s);
 template <typename real>
 hipError_t launch_degrid_sorted(const Geom &g, const uint64_t *keys, const uint64_t *vals, int64_t nvis,
                                 const real *lut, const real *mesh, int32_t panel, real *out, hipStream_t s);
