@@ -48,11 +48,12 @@ def algorithmic_bytes(name, ds, info):
     row_cells = info["tile_rows_set"] * T * ds.grid_n      # cells of rows in tile rows holding any
     fused = bool(info.get("row_mesh_ptr"))
     wbytes = 4 * nvis if ds.weight is not None else 0
-    r1 = info.get("rec1_bytes") or 16                     # bytes per level-1 record
+    r1 = info.get("rec1_bytes") or 16                     # bytes per level-1 record (position + W V)
+    p1 = r1 - (16 if r1 == 24 else 8)                      # bytes of its position
     table = {
-        "bin_count": 24 * nrow + 8 * nvis + wbytes,     # the drop test reads the visibilities too
+        "bin_count": 24 * nrow + wbytes,                # uvw (and weights): V is not read
         "bin_scatter": 24 * nrow + 8 * nvis + wbytes + r1 * nvis,   # writes the level-1 records
-        "fine_count": r1 * nvis,                                    # reads them (position and W V)
+        "fine_count": p1 * nvis,                                    # reads their positions
         "fine_scatter": r1 * nvis + 12 * nvis,                      # reads them, writes 12-byte records
         "grid": 16 * nvis + 8 * set_cells,                         # 16 B {X, Y, W V} per visibility
         "fft_rows": 8 * set_cells + 8 * (row_cells if fused else cells),
@@ -238,7 +239,7 @@ KERNEL_TIMER = {"k_zero_stats": "reset", "k_set_scales": "(scales upload)", "k_l
                 "k_zero_heavy": "zero_heavy",
                 "k_grid": "grid", "k_zero_mesh": "zero_mesh", "k_fft_rows": "fft_rows", "k_fft_rows_panel": "fft_rows", "k_fft_cols": "fft_cols",
                 "k_fft_cols_screen": "fft_cols_screen", "k_wscreen": "wscreen", "k_merge_margins": "merge_margins", "k_row_bits": "merge_margins",
-                "k_clear_bits": "reset"}
+                "k_clear_bits": "reset", "k_bin_vmax": "fine_scatter", "k_orient": "(orientation)"}
 
 
 # Sources whose kernels the imaging step never launches (prediction): they do
@@ -283,6 +284,30 @@ def measured_traffic(workload, timer):
     if timer not in rows:
         return None, f"no counters for {timer}"
     return int(rows[timer]), f"FETCH_SIZE + WRITE_SIZE, copy-calibrated ({os.path.basename(path)})"
+
+
+def measured_valu(workload, timer):
+    """VALU wave instructions per launch of the kernels behind `timer`, from
+    the committed SQ counter summary, or None when there is none or the
+    kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    digest, total = None, 0.0
+    nc = len(SQ_COUNTERS)
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# source_sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            elif line.strip() and not line.startswith(("#", "kernel")):
+                # kernel name (spaces inside its template arguments), then one column per counter
+                parts = line.split()
+                name = " ".join(parts[:-nc])
+                if KERNEL_TIMER.get(name.split("<")[0]) == timer:
+                    total += float(parts[-nc:][SQ_COUNTERS.index("SQ_INSTS_VALU")])
+    if digest != kernel_sources_digest() or total == 0.0:
+        return None
+    return total
 
 
 def short_kernel(name):
@@ -439,6 +464,7 @@ def summarize_profiles(out, workload):
         kernels = sorted({k for k, _ in sq})
         lines = [f"# SQ counters per dispatch (summed over the chip), {workload}", "# command:",
                  "#   " + prelude.strip(), "#   " + cmds["sq"],
+                 f"# source_sha256: {kernel_sources_digest()}",
                  f"{'kernel':48s} " + " ".join(f"{c[3:]:>16s}" for c in SQ_COUNTERS)]
         for k in kernels:
             vals = []
@@ -1155,15 +1181,13 @@ def main():
             v["bytes"] = int(ab)
             v["GBps"] = round(ab / (v["ms"] * 1e-3) / 1e9, 1)
     roofline["traffic"], roofline["traffic_note"] = measured_traffic(args.workload, dominant)
-    if dominant == "grid" and info["n_records"] > 0:
-        # the gridder is bound by LDS instruction issue, not HBM: per record
-        # two 64-bit atomic adds (integer in float32 mode, float64 in float64
-        # mode) and two ds_read_b32, at the per-CU rates measured on gfx950
-        # (6.22, 8.31 and 2.37 clocks per wave instruction)
-        floor_clk = 2 * (8.31 if args.precision == "fp64" else 6.22) + 2 * 2.37
-        clk = kernels["grid"]["ms"] * 1e-3 * CU_COUNT * CLOCK_HZ / info["n_records"]
-        roofline["lds_issue"] = {"records": int(info["n_records"]), "clk_per_record": round(clk, 2),
-                                 "floor_clk_per_record": round(floor_clk, 2), "frac": round(floor_clk / clk, 3)}
+    valu = measured_valu(args.workload, dominant)
+    if valu is not None:
+        # the FFT and gridding kernels are bound by instruction issue rather
+        # than HBM: one VALU wave instruction per clock per CU (no packed math)
+        cap = kernels[dominant]["ms"] * 1e-3 * CU_COUNT * CLOCK_HZ
+        roofline["valu_issue"] = {"insts_per_launch": valu, "issue_slots": round(cap),
+                                  "frac": round(valu / cap, 3), "source": "SQ_INSTS_VALU, committed SQ summary"}
     if roofline["traffic"] is not None:
         roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / dbytes, 3)
 
