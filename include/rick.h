@@ -336,6 +336,29 @@ rick_status rick_degrid_sorted(rick_plan_t *p, const rick_degrid_order_t *o, voi
 rick_status rick_degrid_order_destroy(rick_degrid_order_t *o);
 
 /*
+ * rick_degrid_order_info -- the order's sorted arrays, device memory owned by
+ * the order (valid until rick_degrid_order_destroy), n = nrow * nchan
+ * entries each, ascending by key:
+ *   keys[j]  the footprint origin (c_x - h, c_y - h) of the visibility as an
+ *            offset in the planes' layout, plane k times N^2 plus j N + i in
+ *            row order (panel == 0) or (i / panel) N panel + j panel + i % panel
+ *            in column panels; all ones for a dropped visibility;
+ *   vals[j]  its index r * nchan + c in bits 0-31, s_x + OS/2 in bits 32-39,
+ *            s_y + OS/2 in bits 40-47.
+ * These are the decisions of Sec. 2.1's discretisation that rick_grid takes
+ * for the same positions (quant.h): cell, sub-cell offset, plane and drop.
+ * Errors: RICK_E_INVALID_ARG (bad order, NULL out).
+ */
+typedef struct rick_degrid_order_info_t {
+    const uint64_t *keys;
+    const uint64_t *vals;
+    int64_t n;
+    int32_t panel;
+    int32_t pad;
+} rick_degrid_order_info_t;
+rick_status rick_degrid_order_info(const rick_degrid_order_t *o, rick_degrid_order_info_t *out);
+
+/*
  * rick_reset -- begin a new image: zero the weight sum and the counters and
  * clear the tile bitmap, so the next rick_grid stores its tiles instead of
  * adding to them and every other tile reads as zero.

@@ -1030,6 +1030,17 @@ rick_status rick_degrid_order_destroy(rick_degrid_order_t *o) {
     return RICK_OK;
 }
 
+rick_status rick_degrid_order_info(const rick_degrid_order_t *o, rick_degrid_order_info_t *out) {
+    if (!o || o->magic != kOrderMagic) return fail(RICK_E_INVALID_ARG, "invalid degrid order");
+    if (!out) return fail(RICK_E_INVALID_ARG, "out is NULL");
+    out->keys = o->keys;
+    out->vals = o->vals;
+    out->n = o->nvis;
+    out->panel = o->panel;
+    out->pad = 0;
+    return RICK_OK;
+}
+
 rick_status rick_degrid_sorted(rick_plan_t *p, const rick_degrid_order_t *o, void *vis_out, void *stream) {
     if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "invalid plan");
     if (!o || o->magic != kOrderMagic) return fail(RICK_E_INVALID_ARG, "invalid degrid order");

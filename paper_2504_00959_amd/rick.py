@@ -35,12 +35,31 @@ class RickError(RuntimeError):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
 
 
+class OrderInfo(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("panel", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class DegridOrder:
     """Sorted positions of one set of visibilities (rick_degrid_order_t)."""
 
-    def __init__(self, handle, nrow: int, nchan: int):
+    def __init__(self, handle, nrow: int, nchan: int, device: int = 0):
         self._h = handle
-        self.nrow, self.nchan = nrow, nchan
+        self.nrow, self.nchan, self.device = nrow, nchan, device
+
+    def arrays(self):
+        """(keys, vals, panel): host uint64 copies of the order's sorted arrays
+        (rick_degrid_order_info)."""
+        import torch
+        inf = OrderInfo()
+        _check(lib().rick_degrid_order_info(self._h, ctypes.byref(inf)), "rick_degrid_order_info")
+        out = []
+        for ptr in (inf.keys, inf.vals):
+            class _View:
+                __cuda_array_interface__ = {"shape": (int(inf.n),), "typestr": "<i8", "data": (ptr, False),
+                                            "version": 2, "strides": None}
+            out.append(torch.as_tensor(_View(), device=f"cuda:{self.device}").cpu().numpy().view(np.uint64))
+        return out[0], out[1], int(inf.panel)
 
     def close(self):
         if self._h:
@@ -119,6 +138,7 @@ def lib() -> ctypes.CDLL:
                                            ctypes.POINTER(P), P]
     L.rick_degrid_sorted.argtypes = [P, P, P, P]
     L.rick_degrid_order_destroy.argtypes = [P]
+    L.rick_degrid_order_info.argtypes = [P, ctypes.POINTER(OrderInfo)]
     L.rick_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     L.rick_plan_destroy.argtypes = [P]
     L.rick_plan_bin_counts.argtypes = [P, P, ctypes.c_int64]
@@ -140,7 +160,8 @@ def lib() -> ctypes.CDLL:
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
               "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid",
-              "rick_degrid_order_create", "rick_degrid_sorted", "rick_degrid_order_destroy"):
+              "rick_degrid_order_create", "rick_degrid_sorted", "rick_degrid_order_destroy",
+              "rick_degrid_order_info"):
         getattr(L, f).restype = ctypes.c_int32
     L.rick_status_str.argtypes = [ctypes.c_int32]
     L.rick_status_str.restype = ctypes.c_char_p
@@ -322,7 +343,7 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().rick_degrid_order_create(self._h, uvw.data_ptr(), fptr, nrow, nchan, ctypes.byref(h),
                                               _stream_handle(stream)), "rick_degrid_order_create")
-        return DegridOrder(h, nrow, nchan)
+        return DegridOrder(h, nrow, nchan, self.device)
 
     def degrid_sorted(self, order: "DegridOrder", out=None, stream=None):
         """rick_degrid over a sort order's visibilities; returns [nrow, nchan]."""

@@ -397,3 +397,54 @@ def test_phase_centre_source_unit_peak():
     ds.vis = np.full((ds.nrow, 1), 1.5, np.complex64)
     gpu = run_gpu(ds)
     assert abs(gpu["img"][128, 128] - 1.5) < 1e-5
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_per_visibility_decisions_match_oracle(fused):
+    """The discretisation of Sec. 2.1 visibility by visibility: footprint
+    origin cell, sub-cell offsets, plane and drop decision of every
+    visibility, read back through a prediction order (the same quantisation
+    code as gridding, rick_degrid_order_info), equal the oracle's bit for bit.
+    The order is a permutation of the visibilities sorted by its keys (the
+    library's radix sort).  Multichannel positions in metres, with positions
+    that are dropped (non-finite, beyond the grid, footprint leaving it) and
+    w beyond the planes' range."""
+    import torch
+    ds = synth.ska_low_small()
+    uvw = ds.uvw.copy()
+    uvw[0, 0] = np.nan
+    uvw[1, 2] = np.inf
+    uvw[2, 0] = 1e7
+    uvw[3, 1] = -uvw[3, 1] * 50.0
+    uvw[4, 2] = 1e9
+    uvw[5, 2] = -1e9
+    ds.uvw = uvw
+    N, OS, h = ds.grid_n, ds.oversample, (ds.support - 1) // 2
+    zeros = np.zeros((ds.nrow, ds.nchan), dtype=np.complex64)
+    b = ow.bin_visibilities(ds.uvw, ds.freq, zeros, None, grid_n=N, n_wplanes=ds.n_wplanes, support=ds.support,
+                            oversample=OS, fov=ds.fov, w_min=ds.w_min, w_max=ds.w_max)
+    assert (~b.keep).sum() >= 4 * ds.nchan
+    with rick.Plan.for_dataset(ds, fused=fused) as p:
+        plan_panel = p.info()["panel"]
+        with p.degrid_order(torch.as_tensor(ds.uvw).to("cuda:0"), ds.freq) as o:
+            keys, vals, panel = o.arrays()
+    assert panel == plan_panel and (panel > 0) == fused
+    n = ds.nvis
+    assert keys.shape == (n,) and np.all(keys[1:] >= keys[:-1])
+    idx = (vals & np.uint64(0xffffffff)).astype(np.int64)
+    assert np.array_equal(np.sort(idx), np.arange(n))
+    dropped = keys == np.uint64(0xffffffffffffffff)
+    assert np.array_equal(~dropped, b.keep[idx])
+    kk = keys[~dropped].astype(np.uint64)
+    ii = idx[~dropped]
+    k = (kk // np.uint64(N * N)).astype(np.int64)
+    off = (kk % np.uint64(N * N)).astype(np.int64)
+    if panel:
+        y0, x0 = (off // panel) % N, (off // (N * panel)) * panel + off % panel
+    else:
+        y0, x0 = off // N, off % N
+    sx = ((vals[~dropped] >> np.uint64(32)) & np.uint64(0xff)).astype(np.int64) - OS // 2
+    sy = ((vals[~dropped] >> np.uint64(40)) & np.uint64(0xff)).astype(np.int64) - OS // 2
+    assert np.array_equal(k, b.k[ii])
+    assert np.array_equal(x0, b.cx[ii] - h) and np.array_equal(y0, b.cy[ii] - h)
+    assert np.array_equal(sx, b.sx[ii]) and np.array_equal(sy, b.sy[ii])
