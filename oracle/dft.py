@@ -17,7 +17,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+# ORACLE_LIB names another build of the same C sources (a sanitized one)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "_liboracle.so")
 _SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("dft.c", "pixels.c", "binstats.c")]
 _lib = None
 

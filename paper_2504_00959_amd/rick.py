@@ -15,7 +15,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librick.so")
+# RICK_LIB names another build of the same library (for instance one with
+# host-side sanitizers); by default the one built next to this file
+LIB_PATH = os.environ.get("RICK_LIB") or os.path.join(_HERE, "librick.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "rick.h")
 
 RICK_OK = 0
