@@ -669,12 +669,7 @@ hipError_t rows_panel_n(const Geom &g, const real *in, real *out, const real *tw
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     // persistent blocks: as many as fit on the device at once
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    }
+    const int cus = device_cus();
     int per_cu = int((160 * 1024) / lds);
     const int by_threads = 2048 / (PS::NT * PS::RB);
     per_cu = per_cu < by_threads ? per_cu : by_threads;

@@ -647,21 +647,6 @@ __global__ void k_clear_bits(uint64_t *__restrict__ tile_bits, int64_t n_tile, u
     }
 }
 
-// CUs of the current device (queried once per device)
-int device_cus() {
-    static int cus[kMaxDevices];
-    static std::once_flag once[kMaxDevices];
-    once_per_device(once, [&] {
-        int dev = 0, n = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
-        if (dev >= 0 && dev < kMaxDevices) cus[dev] = n;
-    });
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    return (dev >= 0 && dev < kMaxDevices && cus[dev] > 0) ? cus[dev] : 256;
-}
-
 template <typename real, int W, int TT, bool L3>
 hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                    const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
@@ -719,6 +704,21 @@ hipError_t grid_w(const Geom &g, const BinScan *scan, const int32_t *item_bin, c
 }
 
 }  // namespace
+
+// CUs of the current device (queried once per device)
+int device_cus() {
+    static int cus[kMaxDevices];
+    static std::once_flag once[kMaxDevices];
+    once_per_device(once, [&] {
+        int dev = 0, n = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        if (dev >= 0 && dev < kMaxDevices) cus[dev] = n;
+    });
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return (dev >= 0 && dev < kMaxDevices && cus[dev] > 0) ? cus[dev] : 256;
+}
 
 size_t grid_lds_bytes(const Geom &g, size_t real_bytes) {
     // real plane, imaginary plane at plane_offset(W, T) doubles (packed mode:

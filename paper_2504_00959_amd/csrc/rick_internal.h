@@ -242,6 +242,8 @@ template <typename real>
 hipError_t launch_fft_rows_panel(const Geom &g, const real *in, real *out, const real *twiddle,
                                  const uint64_t *tile_bits, const uint64_t *row_bits, hipStream_t s);
 int fused_panel_width(int N, size_t real_bytes);
+// CUs of the current device (queried once per device)
+int device_cus();
 bool fft_supported(int N, size_t real_bytes);   // N = 16384 in float32 modes only
 // Column transform fused with the w-correction, plane sum and normalisation.
 size_t fused_screen_lds_bytes(int N, size_t real_bytes);
