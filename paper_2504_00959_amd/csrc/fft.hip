@@ -522,16 +522,18 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         }
     }
     while (k < g.Nw) {
-        // at N >= 8192 the lane indices and the twiddle pointer are laundered
-        // per plane, so that the compiler recomputes addresses and reloads
-        // twiddles (L1 hits) instead of keeping every stage's values live
-        // across the plane loop: kept live they spill (36 registers with the
-        // compensated sum), which took 47.6 ms instead of 42.7 for 128 planes
-        // of 8192^2; at N <= 4096 they fit and keeping them is faster
-        // (2.50 ms against 2.88 for 64 planes of 4096^2)
+        // at N >= 8192, and at every N with the compensated sum, the lane
+        // indices and the twiddle pointer are laundered per plane, so that
+        // the compiler recomputes addresses and reloads twiddles (L1 hits)
+        // instead of keeping every stage's values live across the plane
+        // loop: kept live they spill (36 registers at 8192 with the
+        // compensated sum: 47.6 ms instead of 42.7 for 128 planes of 8192^2;
+        // 70 at 4096: 4.73 ms instead of 3.02 for 64 planes of 4096^2);
+        // without the compensated sum at N <= 4096 they fit and keeping them
+        // is faster (2.50 ms against 2.88 for 64 planes of 4096^2)
         const C *twk = tw;
         int tid = (int)threadIdx.x;
-        if (N >= 8192) __asm__ volatile("" : "+s"(twk), "+v"(tid));
+        if (N >= 8192 || KAHAN) __asm__ volatile("" : "+s"(twk), "+v"(tid));
         const int vg = tid % (V / VC), tb = tid / (V / VC), v0 = vg * VC;
         C x[16][VC];
 #pragma unroll
