@@ -262,6 +262,114 @@ __device__ __forceinline__ int out_elem(int tb, int q) {
     return tb + q * Shape<N>::NT;
 }
 
+// ---- the same transform with 8 elements per thread ----
+// Radix-8 stages after a first stage of radix R0 in {2, 4, 8}: twice the
+// threads per transform and half the registers per thread of the radix-16
+// form, for the sizes where a transform's block is the only one its CU holds.
+template <int N>
+struct Shape8 {
+    static constexpr int LG = ilog2c(N);
+    static constexpr int R0 = (LG % 3) == 0 ? 8 : (1 << (LG % 3));   // first-stage radix
+    static constexpr int S = 1 + (LG - ilog2c(R0)) / 3;               // number of stages
+    static constexpr int NT = N / 8;                                  // threads per transform
+};
+
+// Multiplies x[1..7] of a radix-8 butterfly by w^j, w = exp(+2 pi i k / (8 L)):
+// three table reads and four products.
+template <int TN, typename C>
+__device__ __forceinline__ void twiddle8(C *x, int k, int L, const C *__restrict__ tw) {
+    const int st = k * (TN / (8 * L));
+    const C w1 = tw[st], w2 = tw[2 * st], w4 = tw[4 * st];
+    const C w3 = cmul(w1, w2);
+    x[1] = cmul(x[1], w1);
+    x[2] = cmul(x[2], w2);
+    x[3] = cmul(x[3], w3);
+    x[4] = cmul(x[4], w4);
+    x[5] = cmul(x[5], cmul(w4, w1));
+    x[6] = cmul(x[6], cmul(w4, w2));
+    x[7] = cmul(x[7], cmul(w4, w3));
+}
+
+// As fft_regs, with slots of 8: x[i R0 + j][v] = element (tb + i NT) + j N/R0
+// on entry, x[q][v] = element tb + q NT on exit (NT = N / 8).
+template <int N, int V, int VC, int TN = N, typename C>
+__device__ __forceinline__ void fft_regs8(C (&x)[8][VC], C *buf, int tb, int v0, const C *__restrict__ tw) {
+    using SH = Shape8<N>;
+    constexpr int NT = SH::NT, R0 = SH::R0, S = SH::S;
+    static_assert(S >= 2, "N >= 16");
+#pragma unroll
+    for (int v = 0; v < VC; ++v) {
+        C tmp[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) tmp[i] = x[i][v];
+#pragma unroll
+        for (int i = 0; i < 8 / R0; ++i) dftR<R0>(tmp + i * R0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i][v] = tmp[i];
+    }
+    int L = R0;
+#pragma unroll
+    for (int s = 1; s < S; ++s) {
+        if (s > 1) __syncthreads();   // every thread has read the previous exchange
+        if (s == 1) {
+#pragma unroll
+            for (int i = 0; i < 8 / R0; ++i) {
+                const int b = tb + i * NT;   // Lp = 1, Rp = R0
+#pragma unroll
+                for (int q = 0; q < R0; ++q)
+#pragma unroll
+                    for (int v = 0; v < VC; ++v) buf[padi(b * R0 + q) * V + v0 + v] = x[i * R0 + q][v];
+            }
+        } else {
+            const int Lp = L / 8;
+            const int b = tb, k = b % Lp;
+            const int base = (b / Lp) * Lp * 8 + k;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int v = 0; v < VC; ++v) buf[padi(base + q * Lp) * V + v0 + v] = x[q][v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int v = 0; v < VC; ++v) x[j][v] = buf[padi(tb + j * NT) * V + v0 + v];
+        const int k = tb % L;
+#pragma unroll
+        for (int v = 0; v < VC; ++v) {
+            C tmp[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) tmp[i] = x[i][v];
+            twiddle8<TN>(tmp, k, L, tw);
+            dft8(tmp);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i][v] = tmp[i];
+        }
+        L *= 8;
+    }
+}
+
+// Slot layouts and transform of E (16 or 8) elements per thread.
+template <int N, int E>
+__device__ __forceinline__ int in_elem_e(int tb, int i) {
+    if constexpr (E == 16) return in_elem<N>(tb, i);
+    else return (tb + (i / Shape8<N>::R0) * Shape8<N>::NT) + (i % Shape8<N>::R0) * (N / Shape8<N>::R0);
+}
+template <int N, int E>
+__device__ __forceinline__ int out_elem_e(int tb, int q) {
+    return tb + q * (N / E);
+}
+// word of slot i in a tile-row bitmap: uniform while N / E <= 64 T
+template <int N, int E>
+__device__ __forceinline__ int occ_word_e(int i, int log2T) {
+    return in_elem_e<N, E>(0, i) >> (log2T + 6);
+}
+template <int N, int E, int V, int VC, typename C>
+__device__ __forceinline__ void fft_regs_e(C (&x)[E][VC], C *buf, int tb, int v0, const C *__restrict__ tw) {
+    if constexpr (E == 16) fft_regs<N, V, VC>(x, buf, tb, v0, tw);
+    else fft_regs8<N, V, VC>(x, buf, tb, v0, tw);
+}
+
 // XCD-aware order: blocks are dealt to the 8 XCDs round-robin; blocks that
 // share an XCD get adjacent strips, so their row segments share L2 lines.
 __device__ __forceinline__ int64_t xcd_order(int64_t bid, int64_t nblk) {
@@ -447,8 +555,10 @@ __device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
 // ---- columns fused with the w-correction and the plane sum ----
 // One block per strip of V columns loops over the planes: the strip of plane
 // k (already transformed along rows) is transformed along columns in
-// registers, and each thread adds Re(exp(+2 pi i w_k (n - 1)) F_k) for the 16
-// x VC pixels it owns; the next plane is fetched into registers meanwhile.
+// registers, and each thread adds Re(exp(+2 pi i w_k (n - 1)) F_k) for the E
+// x VC pixels it owns (E = 16 elements per thread; 8 in the radix-8 form
+// used where a strip's block is the only one its CU holds); the next plane
+// is fetched into registers meanwhile.
 // The transformed planes are never written back, and the image is written
 // once.  n - 1 of the strip's pixels is kept in LDS in float64; the phase
 // 2 w_k (n - 1) is formed in float64 half turns.  Planes without a set tile
@@ -457,8 +567,8 @@ __device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
 // strip of columns is a strip of image rows (n - 1 and the taper are
 // symmetric in l and m, so the same values serve), and adds its sums to the
 // image there, unless no plane was taken.
-template <typename real, int N, int V, int VC, int PW, bool KAHAN>
-__global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
+template <typename real, int N, int V, int VC, int PW, bool KAHAN, int E>
+__global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
                                                                          const real *__restrict__ twr,
                                                                          const double *__restrict__ corr,
                                                                          const Stats *__restrict__ st,
@@ -482,8 +592,8 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
     const double dl = g.fov / N;
     // owned pixels: rows out_elem(tb, q), columns c0 + v0 + v
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int e = out_elem<N>(tb, q);
+    for (int q = 0; q < E; ++q) {
+        const int e = out_elem_e<N, E>(tb, q);
 #pragma unroll
         for (int v = 0; v < VC; ++v) {
             const double l = (double)(c0 + v0 + v - N / 2) * dl, m = (double)(e - N / 2) * dl;
@@ -504,15 +614,15 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         return k;
     };
     // rows of an empty tile row were not written by the row pass: zeros
-    real acc[16][VC], comp[16][VC];
-    C pre[16][VC];
+    real acc[E][VC], comp[E][VC];
+    C pre[E][VC];
     int32_t k = next_plane(0);
     const bool any_plane = k < g.Nw;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = in_elem<N>(tb, i);
+    for (int i = 0; i < E; ++i) {
+        const int e = in_elem_e<N, E>(tb, i);
         const bool on = k < g.Nw &&
-                        bit_of(uniform_word(row_bits, (int64_t)k * g.occw + occ_word<N>(i, g.log2T)), e >> g.log2T);
+                        bit_of(uniform_word(row_bits, (int64_t)k * g.occw + occ_word_e<N, E>(i, g.log2T)), e >> g.log2T);
         const C *gk = gbase + (int64_t)k * plane_stride;
 #pragma unroll
         for (int v = 0; v < VC; ++v) {
@@ -535,10 +645,10 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         int tid = (int)threadIdx.x;
         if (N >= 8192 || KAHAN) __asm__ volatile("" : "+s"(twk), "+v"(tid));
         const int vg = tid % (V / VC), tb = tid / (V / VC), v0 = vg * VC;
-        C x[16][VC];
+        C x[E][VC];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = in_elem<N>(tb, i);
+        for (int i = 0; i < E; ++i) {
+            const int e = in_elem_e<N, E>(tb, i);
 #pragma unroll
             for (int v = 0; v < VC; ++v) x[i][v] = cneg_if(pre[i][v], e & 1);
         }
@@ -546,10 +656,10 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         if (kn < g.Nw) {
             const C *gk = gbase + (int64_t)kn * plane_stride;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int e = in_elem<N>(tb, i);
+            for (int i = 0; i < E; ++i) {
+                const int e = in_elem_e<N, E>(tb, i);
                 const bool on =
-                    bit_of(uniform_word(row_bits, (int64_t)kn * g.occw + occ_word<N>(i, g.log2T)), e >> g.log2T);
+                    bit_of(uniform_word(row_bits, (int64_t)kn * g.occw + occ_word_e<N, E>(i, g.log2T)), e >> g.log2T);
 #pragma unroll
                 for (int v = 0; v < VC; ++v) pre[i][v] = on ? gk[(int64_t)e * PW + v] : C{0, 0};
             }
@@ -557,11 +667,11 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
         // the LDS strip is reused plane after plane: every thread must have
         // read the previous plane's last exchange before this plane's first
         __syncthreads();
-        fft_regs<N, V, VC>(x, buf, tb, v0, twk);
+        fft_regs_e<N, E, V, VC>(x, buf, tb, v0, twk);
         const double w2 = 2.0 * plane_centre(g, k);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = out_elem<N>(tb, q);
+        for (int q = 0; q < E; ++q) {
+            const int e = out_elem_e<N, E>(tb, q);
 #pragma unroll
             for (int v = 0; v < VC; ++v) {
                 const real term = screen_term(w2 * s_nm1[e * V + v0 + v], x[q][v], e & 1);
@@ -580,8 +690,8 @@ __global__ __launch_bounds__((N / 16) * (V / VC)) void k_fft_cols_screen(Geom g,
     if (pass != 0 && !any_plane) return;   // (uniform) nothing to add
     const double sw = st->sum_w;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int e = out_elem<N>(tb, q);
+    for (int q = 0; q < E; ++q) {
+        const int e = out_elem_e<N, E>(tb, q);
 #pragma unroll
         for (int v = 0; v < VC; ++v) {
             const int p = c0 + v0 + v;
@@ -689,20 +799,25 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
                          hipStream_t s) {
     using CS = ColShape<real, N>;
     constexpr int PW = PanelShape<real, N>::PW;
+    // elements per thread: 8 (radix-8 stages, 1024 threads) for the float32
+    // strip of 8192, whose block is alone on its CU; 16 otherwise
+    constexpr int E = (N == 8192 && sizeof(real) == 4) ? 8 : 16;
+    constexpr int THREADS = (N / E) * (CS::V / CS::VC);
+    static_assert(THREADS <= 1024, "one block of at most 1024 threads");
     const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
     static std::once_flag attr_once[kMaxDevices];
     once_per_device(attr_once, [&] {
-        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>,
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false, E>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>,
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true, E>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     if (kahan)
-        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true>), dim3(N / CS::V), dim3(CS::THREADS),
+        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, true, E>), dim3(N / CS::V), dim3(THREADS),
                            lds, s, g, mesh, tw, corr, st, row_bits, plane_tr, pass, image);
     else
-        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false>), dim3(N / CS::V),
-                           dim3(CS::THREADS), lds, s, g, mesh, tw, corr, st, row_bits, plane_tr, pass, image);
+        hipLaunchKernelGGL((k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false, E>), dim3(N / CS::V), dim3(THREADS),
+                           lds, s, g, mesh, tw, corr, st, row_bits, plane_tr, pass, image);
     return hipGetLastError();
 }
 
