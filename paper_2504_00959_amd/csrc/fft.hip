@@ -290,6 +290,12 @@ __device__ __forceinline__ void twiddle8(C *x, int k, int L, const C *__restrict
     x[7] = cmul(x[7], cmul(w4, w3));
 }
 
+// LDS element e of the radix-8 form at e + e / 8 (its first exchange writes
+// at a stride of R0 elements).
+__device__ __forceinline__ int padi8(int e) { return e + (e >> 3); }
+template <int N>
+constexpr int padn8() { return N + N / 8; }
+
 // As fft_regs, with slots of 8: x[i R0 + j][v] = element (tb + i NT) + j N/R0
 // on entry, x[q][v] = element tb + q NT on exit (NT = N / 8).
 template <int N, int V, int VC, int TN = N, typename C>
@@ -318,7 +324,7 @@ __device__ __forceinline__ void fft_regs8(C (&x)[8][VC], C *buf, int tb, int v0,
 #pragma unroll
                 for (int q = 0; q < R0; ++q)
 #pragma unroll
-                    for (int v = 0; v < VC; ++v) buf[padi(b * R0 + q) * V + v0 + v] = x[i * R0 + q][v];
+                    for (int v = 0; v < VC; ++v) buf[padi8(b * R0 + q) * V + v0 + v] = x[i * R0 + q][v];
             }
         } else {
             const int Lp = L / 8;
@@ -327,13 +333,13 @@ __device__ __forceinline__ void fft_regs8(C (&x)[8][VC], C *buf, int tb, int v0,
 #pragma unroll
             for (int q = 0; q < 8; ++q)
 #pragma unroll
-                for (int v = 0; v < VC; ++v) buf[padi(base + q * Lp) * V + v0 + v] = x[q][v];
+                for (int v = 0; v < VC; ++v) buf[padi8(base + q * Lp) * V + v0 + v] = x[q][v];
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 8; ++j)
 #pragma unroll
-            for (int v = 0; v < VC; ++v) x[j][v] = buf[padi(tb + j * NT) * V + v0 + v];
+            for (int v = 0; v < VC; ++v) x[j][v] = buf[padi8(tb + j * NT) * V + v0 + v];
         const int k = tb % L;
 #pragma unroll
         for (int v = 0; v < VC; ++v) {
@@ -580,7 +586,8 @@ __global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen(Geom g, 
     constexpr int NSTRIP = N / V;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
-    double *s_nm1 = reinterpret_cast<double *>(buf + SH::PADN * V);
+    constexpr int PADN = E == 8 ? padn8<N>() : SH::PADN;   // LDS elements of the exchange
+    double *s_nm1 = reinterpret_cast<double *>(buf + PADN * V);
     const C *tw = reinterpret_cast<const C *>(twr);
     const int strip = (int)xcd_order(blockIdx.x, NSTRIP);
     const int c0 = strip * V;
@@ -804,7 +811,8 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
     constexpr int E = (N == 8192 && sizeof(real) == 4) ? 8 : 16;
     constexpr int THREADS = (N / E) * (CS::V / CS::VC);
     static_assert(THREADS <= 1024, "one block of at most 1024 threads");
-    const size_t lds = size_t(Shape<N>::PADN) * CS::V * sizeof(typename CS::C) + size_t(N) * CS::V * sizeof(double);
+    const size_t lds = size_t(E == 8 ? padn8<N>() : Shape<N>::PADN) * CS::V * sizeof(typename CS::C) +
+                       size_t(N) * CS::V * sizeof(double);
     static std::once_flag attr_once[kMaxDevices];
     once_per_device(attr_once, [&] {
         (void)hipFuncSetAttribute((const void *)k_fft_cols_screen<real, N, CS::V, CS::VC, PW, false, E>,
@@ -831,7 +839,9 @@ size_t fused_screen_lds_bytes(int N, size_t real_bytes) {
     const int cbytes = (int)(2 * real_bytes);
     int v = (8192 * 8 / cbytes) / N;
     v = v < 1 ? 1 : (v > 16 ? 16 : v);
-    return size_t(N + N / 16) * v * cbytes + size_t(N) * v * sizeof(double);
+    // (the float32 strip of 8192 runs the radix-8 form, padded every 8 elements)
+    const int padn = (N == 8192 && real_bytes == 4) ? N + N / 8 : N + N / 16;
+    return size_t(padn) * v * cbytes + size_t(N) * v * sizeof(double);
 }
 
 template <typename real>
