@@ -131,3 +131,37 @@ def test_orient_flag_needs_the_fused_screen():
     with pytest.raises(rick.RickError, match="UNSUPPORTED"):
         rick.Plan(grid_n=256, n_wplanes=4, support=7, oversample=32, fov=0.2, w_min=-1.0, w_max=1.0,
                   kernel="user_lut", lut_wbins=2, fused=True, orient=True)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan"])
+def test_transposed_planes_at_8192(precision):
+    """The float32 column strip of 8192 (8 elements per thread, radix-8
+    stages) over planes stored as they are (pass 0) and transposed (pass 1):
+    the orientation chosen, the image equal to a plain plan's, and sampled
+    pixels against the oracle's per-pixel regrouping."""
+    import torch
+    N = 8192
+    ds = synth.tiny(nrow=200000, seed=33, grid_n=N, n_wplanes=4, uv_radius=120.0 * N / 256)
+    u, v, w = ds.uvw[:, 0], ds.uvw[:, 1], ds.uvw[:, 2]
+    keep = ((w > 0) & (np.abs(u) < 40.0)) | ((w <= 0) & (np.abs(v) < 40.0))
+    ds.uvw = ds.uvw[keep].copy()
+    ds.vis = np.asarray(ds.vis)[keep].copy()
+    plain = _run(ds, precision, False)
+    got = _run(ds, precision, True)
+    half = ds.n_wplanes // 2
+    assert not plain["tr"].any()
+    assert got["tr"][half:].all() and not got["tr"][:half].any(), got["tr"]
+    corr = oracle.wstack.grid_correction(oracle.wstack.tap_table(ds.support, ds.oversample), N)
+    c2 = np.outer(corr, corr)
+    assert rel_rms(got["img"] * c2, plain["img"] * c2) <= 1e-6
+    # sampled pixels: the sources, the centre, random ones
+    lm = ds.fov / N
+    ps = np.rint(ds.sources["l"] / lm).astype(int) + N // 2
+    qs = np.rint(ds.sources["m"] / lm).astype(int) + N // 2
+    rng = np.random.default_rng(8)
+    pp = np.r_[ps, N // 2, rng.integers(0, N, 8)]
+    qq = np.r_[qs, N // 2, rng.integers(0, N, 8)]
+    ref, _, _, _ = oracle.pixels.wstack_pixels_dataset(ds, pp, qq)
+    cs = corr[pp] * corr[qq]
+    assert rel_rms(got["img"][qq, pp] * cs, ref * cs) <= 1e-5
+    torch.cuda.synchronize()
