@@ -744,6 +744,65 @@ def batch_report(args):
         cstamps.close()
         for i in range(n):
             imgs[i].copy_(seq_imgs[i])
+    # the jobs in rounds on one stream, each round's gridding ONE persistent
+    # launch over the work items of all its jobs (rick_grid_jobs; one launch
+    # per tile edge among them): round r holds the r-th job of every plan
+    plan_jobs = {k: [i for i in range(n) if slot_of[i] == k] for k in plans}
+    rounds = [[lst[r] for lst in plan_jobs.values() if r < len(lst)]
+              for r in range(max(len(x) for x in plan_jobs.values()))]
+    jstamps = rick.Stamps(len(rounds) + 1)
+
+    # the round's transforms spread over the streams (forked after the joint
+    # gridding, joined before the next round, whose jobs reuse the plans)
+    jstreams = [stream] + [torch.cuda.Stream() for _ in range(max(1, args.streams) - 1)]
+
+    def issue_joint(s):
+        jstamps.stamp(0, s)
+        for ri, rd in enumerate(rounds):
+            for i in rd:
+                p = plans[slot_of[i]]
+                p.retarget(jobs[i].fov, jobs[i].w_min, jobs[i].w_max)
+                p.reset(s)
+            rick.grid_jobs([(plans[slot_of[i]], uvw[i], vis[i], None, jobs[i].freq) for i in rd], s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+            for st in jstreams[1:]:
+                st.wait_event(ev)
+            for k, i in enumerate(sorted(rd, key=lambda i: -jobs[i].grid_n ** 2 * jobs[i].n_wplanes)):
+                st = jstreams[k % len(jstreams)]
+                plans[slot_of[i]].fft(st)
+                plans[slot_of[i]].image(imgs[i], st)
+            for st in jstreams[1:]:
+                e = torch.cuda.Event()
+                e.record(st)
+                s.wait_event(e)
+            jstamps.stamp(ri + 1, s)
+
+    jeager = []
+    for rep in range(max(1, args.warmup)):
+        issue_joint(stream)
+        jeager.append(jstamps.elapsed(0, len(rounds)))
+    with rick.Graph.record(stream) as jgraph:
+        issue_joint(stream)
+    jtot, jround = [], []
+    for rep in range(args.steps):
+        for im in imgs:
+            im.fill_(0.0)
+        torch.cuda.synchronize()
+        jgraph.launch(stream)
+        jtot.append(jstamps.elapsed(0, len(rounds)))
+        jround = [jstamps.elapsed(r, r + 1) for r in range(len(rounds))]
+    torch.cuda.synchronize()
+    joint_imgs = [im.clone() for im in imgs]
+    jgraph.close()
+    jstamps.close()
+    for i in range(n):
+        imgs[i].copy_(seq_imgs[i])
+    jmed = float(np.median(jtot))
+    joint = {"rounds": len(rounds), "streams": len(jstreams), "jobs_per_s": round(n / (jmed * 1e-3), 2),
+             "batch_ms": round(jmed, 3), "mvis_per_s": round(nvis / (jmed * 1e-3) / 1e6, 1),
+             "eager_batch_ms": [round(x, 3) for x in jeager],
+             "round_ms": [round(x, 3) for x in jround]}
     # graph against eager in the apparent image (both multiplied by C_p C_q): the
     # shared-tile float atomics add in no fixed order, and dividing by the taper
     # magnifies that rounding in the outermost pixels of the corrected image
@@ -761,6 +820,8 @@ def batch_report(args):
     if conc is not None:
         conc["vs_one_stream_max_apparent_rel_rms"] = max(
             apparent_rel(ds, a, b) for ds, a, b in zip(jobs, conc_imgs, seq_imgs))
+    joint["vs_one_stream_max_apparent_rel_rms"] = max(
+        apparent_rel(ds, a, b) for ds, a, b in zip(jobs, joint_imgs, seq_imgs))
     # the smallest job against the oracle at sampled pixels
     small = min(range(n), key=lambda i: jobs[i].nvis)
     ds = jobs[small]
@@ -790,6 +851,7 @@ def batch_report(args):
            "job_shapes": [f"{ds.grid_n}x{ds.n_wplanes}:{ds.nvis}" for ds in jobs],
            "oracle_check": {"job": small, "pixels": int(len(pp)), "apparent_rel_rms": ocheck},
            "concurrent": conc,
+           "joint_gridding": joint,
            "shapes": {f"{k[0]}x{k[1]}": {"jobs": len(shapes[k]), "tile": v[0], "chunk": v[1],
                                          "tuned_ms": round(v[2], 3)} for k, v in sorted(tuned.items())}}
     print(json.dumps(out), flush=True)

@@ -20,9 +20,11 @@
  *   rick_degrid_order_create, rick_degrid_sorted, rick_degrid_order_destroy
  *                      prediction at fixed positions: quantise and sort once,
  *                      interpolate in sorted order every time
- *   rick_plan_retarget, rick_capture_begin/_end, rick_graph_launch/_destroy,
- *   rick_stamps_create/_stamp/_elapsed/_destroy, rick_autotune
- *                      many jobs: one plan per shape retargeted per job, work
+ *   rick_plan_retarget, rick_grid_jobs, rick_capture_begin/_end,
+ *   rick_graph_launch/_destroy, rick_stamps_create/_stamp/_elapsed/_destroy,
+ *   rick_autotune
+ *                      many jobs: one plan per shape retargeted per job, the
+ *                      gridding of many jobs in one persistent launch, work
  *                      recorded into a graph and replayed, device timestamps,
  *                      tile and chunk chosen by measurement
  *
@@ -238,6 +240,44 @@ rick_status rick_grid_static(rick_plan_t *p, const double *uvw, const double *fr
                              const float *weight, int64_t nrow, int32_t nchan, void *stream);
 
 /*
+ * rick_grid_jobs -- rick_grid for several independent imaging jobs at once,
+ * each on its own plan: the gridding of Sec. 2.1 (Eq. 3) for a batch of
+ * jobs of uneven grid size and visibility count.  The result on every plan
+ * is that of rick_grid with the job's arguments (planes equal up to the
+ * order of float additions where a bin spans several gridding chunks).  Each
+ * job is binned on its own plan's buffers; then the gridding work items of
+ * all jobs form one device-side queue taken by ONE persistent launch per
+ * (kernel support, uv tile edge) among the jobs: a block claims items from a
+ * shared counter and grids each with its job's plan, so small jobs do not
+ * leave the device idle between launches.  Everything runs on `stream`, in
+ * job order for the binning; nothing is allocated (may be recorded into a
+ * graph).
+ *   jobs   HOST array of n job descriptors (plan and the arguments of
+ *          rick_grid, same meaning, layout and lifetime rules); the array
+ *          itself may be freed when the call returns
+ *   n      1 ... RICK_MAX_GRID_JOBS
+ * Every plan must be a different one, on one device, all in float32 modes
+ * or all in FP64 mode, with a separable kernel (not RICK_KERNEL_USER_LUT).
+ * All arguments are checked before any device work.
+ * Errors: RICK_E_INVALID_ARG (NULL jobs, n out of range, a plan given twice,
+ * plans on different devices or of different precisions, a job's arguments
+ * as for rick_grid), RICK_E_BAD_PLAN, RICK_E_UNSUPPORTED (a user table),
+ * RICK_E_CAPACITY, RICK_E_STATE (as for rick_grid), RICK_E_HIP.
+ */
+#define RICK_MAX_GRID_JOBS 64
+typedef struct rick_grid_job {
+    rick_plan_t *plan;
+    const double *uvw;
+    const double *freq_hz;
+    const void *vis;
+    const float *weight;
+    int64_t nrow;
+    int32_t nchan;
+    int32_t reserved; /* set to 0 */
+} rick_grid_job;
+rick_status rick_grid_jobs(const rick_grid_job *jobs, int32_t n, void *stream);
+
+/*
  * rick_fft_planes -- in place, every plane becomes its centred inverse DFT
  * (the FFT step of Sec. 2.1):
  *   F_k[q][p] = sum_{j,i} G_k[j][i] exp(+2 pi i ((i - N/2)(p - N/2) + (j - N/2)(q - N/2)) / N)
@@ -431,7 +471,7 @@ rick_status rick_graph_destroy(rick_graph_t *g);
 /*
  * Device timestamps for per-job latencies inside a graph.
  * rick_stamps_create -- n timestamp slots (allocates 8 n bytes of device
- * memory); rick_stamp -- a one-thread kernel
+ * memory, zeroed; synchronises the device); rick_stamp -- a one-thread kernel
  * on `stream` writes the device's constant-rate clock into slot i when the
  * preceding work on the stream has finished (may be recorded into a graph);
  * rick_stamps_elapsed -- synchronise the device and give, in *ms, the time

@@ -169,6 +169,318 @@ __device__ __forceinline__ void unpack_terms(unsigned long long s, long long &re
 // packed position), one value per tap instead of the product of two
 // separable rows held in LDS; tapmax points at the table's largest |value|.
 // float32: packed accumulation (above); float64: float64 re and im planes.
+
+// Per-lane tap constants: LDS byte offset of the tap from the footprint
+// origin, and the byte addresses of its tap-table columns (L3: the tap's
+// index in a table row; lanes past the footprint read the row's last tap,
+// whose values go unused).
+template <typename real, int W, bool L3>
+__device__ __forceinline__ void tap_constants(int32_t P, int32_t lut_byte, int (&tap_off8)[(W * W + 63) / 64],
+                                              int (&lut_x)[(W * W + 63) / 64], int (&lut_y)[(W * W + 63) / 64]) {
+    constexpr int W2 = W * W;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int gi = 0; gi < (W2 + 63) / 64; ++gi) {
+        const int t = lane + 64 * gi;
+        const bool on = t < W2;
+        const int ty = on ? t / W : 0, tx = on ? t - (t / W) * W : 0;
+        tap_off8[gi] = (ty * P + tx) * (int)sizeof(double);
+        lut_x[gi] = lut_byte + tx * (int)sizeof(real);
+        lut_y[gi] = L3 ? (on ? t : W2 - 1) : lut_byte + ty * (int)sizeof(real);
+    }
+}
+
+// LDS byte offset of the separable tap table: after the real plane (and the
+// imaginary one in float64 mode), T + W - 1 rows of pitch P each.
+template <typename real, int W, int TT>
+__device__ __forceinline__ int32_t lut_byte_of(int32_t P) {
+    constexpr bool P32 = std::is_same<real, float>::value;
+    return ((P32 ? 0 : im_plane_offset<W, TT>()) + (TT + W - 1) * P) * (int32_t)sizeof(double);
+}
+
+// One work item (a chunk of at most CH records of one bin) through the
+// block: the records accumulated in LDS, then the tile and its margins
+// written out.  The separable tap table is in LDS already (written before
+// this call; the first barrier here makes it visible).  Ends with the
+// accumulators read out but before the block's closing barrier.
+template <typename real, int W, int TT, bool L3>
+__device__ __forceinline__ void grid_item(const Geom &g, const BinScan *__restrict__ scan,
+                                          const int32_t *__restrict__ item_bin, const uint32_t *__restrict__ rec_pos,
+                                          const real *__restrict__ rec_vis, const real *__restrict__ lut,
+                                          real *__restrict__ mesh, const uint64_t *__restrict__ tile_bits,
+                                          real *__restrict__ margin, const uint32_t *__restrict__ bin_vmax,
+                                          const float *__restrict__ tapmax, const int32_t *__restrict__ plane_tr,
+                                          int32_t item, const int (&tap_off8)[(W * W + 63) / 64],
+                                          const int (&lut_x)[(W * W + 63) / 64],
+                                          const int (&lut_y)[(W * W + 63) / 64]) {
+    constexpr bool P32 = std::is_same<real, float>::value;   // packed fixed point
+    constexpr int W2 = W * W;
+    constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
+    constexpr int kGridBlock = grid_threads(TT);
+    constexpr int nwave = kGridBlock / 64;
+    constexpr int KOFF = im_plane_offset<W, TT>();   // TT == g.T
+    // packed mode: LDS cells owned per thread (cell i by thread i mod the block size)
+    constexpr int CPT = ((TT + W - 1) * acc_pitch(TT, W) + kGridBlock - 1) / kGridBlock;
+    static_assert(kGridBlock <= (1 << (31 - kPackTermBits)), "a drain round must stay within 32-bit halves");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t T = g.T, P = g.pitch;
+    using r2 = typename real2_t<real>::type;
+    r2 *m = reinterpret_cast<r2 *>(mesh);
+    using acc_t = typename std::conditional<P32, unsigned long long, double>::type;
+    using vreg_t = typename std::conditional<P32, float, double>::type;   // W V as the taps multiply it
+    // LDS: real plane at byte 0, imaginary plane KOFF doubles further (not
+    // with P32), then the tap table; a plane is R = T + W - 1 rows of pitch P
+    constexpr int R_PAD = W - 1;
+    const int32_t R = T + R_PAD;
+    acc_t *acc_re = reinterpret_cast<acc_t *>(smem);
+    acc_t *acc_im = acc_re + KOFF;
+    const int lane = __lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    const int32_t b = item_bin[item];
+    const int32_t first = scan[b].item;
+    const int32_t nchunk = scan[b + 1].item - first;
+    const int32_t chunk = item - first;
+    const int32_t r_begin = scan[b].rec + chunk * g.CH;
+    int32_t r_end = r_begin + g.CH;
+    if (r_end > scan[b + 1].rec) r_end = scan[b + 1].rec;
+    const int32_t n = r_end - r_begin;   // > 0: empty bins have no work item
+    const int32_t k = b / (g.nt * g.nt);
+    const int32_t rem = b - k * g.nt * g.nt;
+    const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
+    double scale = 1.0, unscale = 1.0;
+    if (P32) {
+        const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
+        // largest |term|: |W V| times the largest |tap| (the square of the
+        // largest separable row value, or the largest entry of the table)
+        const double bt = vmax * (L3 ? (double)*tapmax * (1.0 + 1e-6) : (double)g.gmax2);
+        if (bt > 0.0 && bt < 1e300) {
+            const int et = ilogb(bt) + 1;   // bt < 2^et
+            const int sh = min(kPackTermBits - et, 120);   // (2^s stays a normal float32)
+            scale = ldexp(1.0, sh);
+            unscale = ldexp(1.0, -sh);
+        }
+    }
+    // packed mode: this thread's cells' sums (cell threadIdx.x + j kGridBlock)
+    long long own_re[P32 ? CPT : 1], own_im[P32 ? CPT : 1];
+#pragma unroll
+    for (int j = 0; j < (P32 ? CPT : 1); ++j) own_re[j] = own_im[j] = 0;
+    auto drain = [&]() {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int32_t i = (int32_t)threadIdx.x + j * kGridBlock;
+            if (i < R * P) {
+                long long re, im;
+                unpack_terms(acc_re[i], re, im);
+                acc_re[i] = 0;
+                own_re[j] += re;
+                own_im[j] += im;
+            }
+        }
+    };
+    // accumulated value of LDS cell i (packed mode: the float32 pair the
+    // owners stored there after the last drain)
+    auto cell = [&](int32_t i, real &re, real &im) {
+        if constexpr (P32) {
+            const float2 v = reinterpret_cast<const float2 *>(acc_re)[i];
+            re = v.x;
+            im = v.y;
+        } else {
+            re = (real)acc_re[i];
+            im = (real)acc_im[i];
+        }
+    };
+    for (int i = threadIdx.x; i < R * P; i += kGridBlock) {
+        acc_re[i] = 0;
+        if (!P32) acc_im[i] = 0;
+    }
+    __syncthreads();
+
+    // this wave's batches of 64 records, one record per lane; the next
+    // batch's raw fields are loaded while the current one is gridded
+    const int32_t nbatch = (n + 63) >> 6;
+    uint32_t raw_pos = 0;
+    real raw_vr = 0, raw_vi = 0;
+    auto fetch = [&](int32_t bi) {
+        const int32_t r = r_begin + (bi << 6) + lane;
+        if (r < r_end) {
+            raw_pos = rec_pos[r];
+            raw_vr = rec_vis[2 * (int64_t)r];
+            raw_vi = rec_vis[2 * (int64_t)r + 1];
+        }
+    };
+    if (wave < nbatch) fetch(wave);
+    // rounds of one batch per wave (packed mode: drained after each round)
+    for (int32_t round0 = 0; round0 < nbatch; round0 += nwave) {
+      const int32_t bt = round0 + wave;
+      if (bt < nbatch) {
+        const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
+        // decode this lane's record: byte offset of the footprint origin in
+        // the real plane, tap-table row byte offsets and visibility (lanes
+        // past the batch keep zeros: they add 0 at the region's origin)
+        int32_t d_base8 = 0, d_lxy = 0;
+        vreg_t d_vr = 0, d_vi = 0;   // W V times 2^s in float32 modes (exact)
+        if (lane < cnt) {
+            const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
+            if constexpr (L3) {
+                const int ox = (int)(raw_pos & 0x3fu), oy = (int)((raw_pos >> 8) & 0x3fu);   // in [0, T)
+                const int iw = (int)((raw_pos >> 6) & 3u) | (int)((raw_pos >> 14) & 1u) << 2;
+                d_base8 = (oy * P + ox) * (int)sizeof(double);
+                d_lxy = ((iw * g.OS + sy) * g.OS + sx) * W2;   // first entry of the record's table row
+            } else {
+                const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
+                d_base8 = (oy * P + ox) * (int)sizeof(double);
+                d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
+            }
+            d_vr = (vreg_t)((double)raw_vr * scale);
+            d_vi = (vreg_t)((double)raw_vi * scale);
+        }
+        if (bt + nwave < nbatch) fetch(bt + nwave);
+
+        // tap-table values of one group of records (indices past the batch
+        // wrap to lanes holding a switched-off record: the reads stay in the
+        // table and their values go unused)
+        auto lut_reads = [&](int j, real (&gy)[kGroup][NG], real (&gx)[kGroup][NG]) {
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const int32_t lxy = bcast(d_lxy, (j + q) & 63);
+                if constexpr (L3) {
+#pragma unroll
+                    for (int gi = 0; gi < NG; ++gi) {
+                        gy[q][gi] = lut[lxy + lut_y[gi]];
+                        gx[q][gi] = (real)1;
+                    }
+                } else {
+                    const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
+#pragma unroll
+                    for (int gi = 0; gi < NG; ++gi) {
+                        gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
+                        gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
+                    }
+                }
+            }
+        };
+        auto add_group = [&](int j, const real (&gy)[kGroup][NG], const real (&gx)[kGroup][NG]) {
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const int32_t base8 = bcast(d_base8, (j + q) & 63);
+                const vreg_t vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    // lanes holding a tap of group gi (a compile-time mask)
+                    constexpr uint64_t kAll = ~0ull;
+                    const uint64_t msk = W2 - 64 * gi >= 64 ? kAll : (1ull << (W2 - 64 * gi)) - 1;
+                    // the products are formed outside the branch, so the wait
+                    // for the table values is the same on every path
+                    const real wgt = gy[q][gi] * gx[q][gi];
+                    if constexpr (P32) {
+                        // round(g V 2^s) of re and im, then both as one 64-bit word
+                        float tr = fmaf(wgt, vr, kRoundMagic32);
+                        float ti = fmaf(wgt, vi, kRoundMagic32);
+                        __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
+                        if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
+                            acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
+                            atomicAdd(a, pack_terms(tr, ti));
+                        }
+                    } else {
+                        double tr = wgt * vr, ti = wgt * vi;
+                        __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
+                        // (with one tap group the whole record loop already runs on the tap lanes)
+                        if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
+                            acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
+                            atomicAdd(a, tr);
+                            atomicAdd(a + KOFF, ti);
+                        }
+                    }
+                }
+            }
+        };
+        // two table buffers used in turn: the reads for group j + kGroup are
+        // issued before the atomics of group j, and no value is copied.  With
+        // one tap group (W <= 7) the loop runs on the tap lanes only: the
+        // execution mask is set once per batch, not per record (readlane
+        // reads the records of the other lanes regardless).
+        if (NG > 1 || lane < W2) {
+            real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
+            lut_reads(0, ay, ax);
+#pragma unroll
+            for (int j = 0; j < 64; j += 2 * kGroup) {
+                lut_reads(j + kGroup, by, bx);
+                add_group(j, ay, ax);
+                if (j + kGroup >= cnt) break;
+                lut_reads(j + 2 * kGroup, ay, ax);
+                add_group(j + kGroup, by, bx);
+                if (j + 2 * kGroup >= cnt) break;
+            }
+        }
+      }
+      if constexpr (P32) {
+          __syncthreads();   // the round's atomics are done
+          drain();
+          __syncthreads();   // the cells are zero again
+      }
+    }
+    if constexpr (P32) {
+        // the sums as float32 pairs in the cells, for the row-coalesced flush
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int32_t i = (int32_t)threadIdx.x + j * kGridBlock;
+            if (i < R * P)
+                reinterpret_cast<float2 *>(acc_re)[i] =
+                    float2{(float)((double)own_re[j] * unscale), (float)((double)own_im[j] * unscale)};
+        }
+    }
+    __syncthreads();
+
+    const bool shared_tile = nchunk > 1;
+    // a transposed plane: cell (y, x) at row x, column y, and the tile's bit
+    // at (tile column, tile row); consecutive threads take consecutive
+    // stored columns either way
+    const bool tr = plane_transposed(plane_tr, k);
+    const bool accumulate =
+        tr ? tile_set(tile_bits, g, k, rem % g.nt, rem / g.nt) : tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
+    for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
+        const int32_t hi = c >> g.log2T, lo = c & (T - 1);
+        const int32_t y = tr ? lo : hi, x = tr ? hi : lo;
+        real re, im;
+        cell(y * P + x, re, im);
+        r2 *dst = tr ? m + ((int64_t)k * g.N + x0 + x) * g.N + y0 + y : m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
+        if (shared_tile) {
+            if (re != 0) atomic_add_real(&dst->x, re);
+            if (im != 0) atomic_add_real(&dst->y, im);
+        } else if (accumulate) {
+            const r2 old = *dst;
+            *dst = r2{old.x + re, old.y + im};
+        } else {
+            *dst = r2{re, im};
+        }
+    }
+    // margins to the bin's margin buffer (the merge adds them to the neighbours)
+    if constexpr (R_PAD > 0) {
+        r2 *mb = reinterpret_cast<r2 *>(margin) + (int64_t)b * margin_len(T, W);
+        const int32_t n_right = R * R_PAD, n_all = n_right + R_PAD * T;
+        for (int32_t c = threadIdx.x; c < n_all; c += kGridBlock) {
+            int32_t y, x;
+            if (c < n_right) {
+                y = c / R_PAD;
+                x = T + (c - y * R_PAD);
+            } else {
+                const int32_t d = c - n_right;
+                y = T + (d >> g.log2T);
+                x = d & (T - 1);
+            }
+            real re, im;
+            cell(y * P + x, re, im);
+            if (shared_tile) {
+                if (re != 0) atomic_add_real(&mb[c].x, re);
+                if (im != 0) atomic_add_real(&mb[c].y, im);
+            } else {
+                mb[c] = r2{re, im};
+            }
+        }
+    }
+}
+
 // Persistent: a block takes work items blockIdx.x, then the next unclaimed
 // one from st->grid_next (claimed while the current one is gridded), until
 // the device-side item count is reached.
@@ -182,300 +494,97 @@ __global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid(Geom 
                                                      const uint32_t *__restrict__ bin_vmax,
                                                      const float *__restrict__ tapmax, Stats *__restrict__ st,
                                                      const int32_t *__restrict__ plane_tr) {
-    constexpr bool P32 = std::is_same<real, float>::value;   // packed fixed point
-    constexpr int W2 = W * W;
-    constexpr int NG = (W2 + 63) / 64;   // groups of 64 taps
+    constexpr int NG = (W * W + 63) / 64;
     constexpr int kGridBlock = grid_threads(TT);
-    constexpr int nwave = kGridBlock / 64;
-    constexpr int KOFF = im_plane_offset<W, TT>();   // TT == g.T
-    // packed mode: LDS cells owned per thread (cell i by thread i mod the block size)
-    constexpr int CPT = ((TT + W - 1) * acc_pitch(TT, W) + kGridBlock - 1) / kGridBlock;
-    static_assert(kGridBlock <= (1 << (31 - kPackTermBits)), "a drain round must stay within 32-bit halves");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_next[2];
     const int32_t total = scan[g.nbins].item;
     if ((int32_t)blockIdx.x >= total) return;
-
-    const int32_t T = g.T, P = g.pitch;
-    using r2 = typename real2_t<real>::type;
-    r2 *m = reinterpret_cast<r2 *>(mesh);
-    using acc_t = typename std::conditional<P32, unsigned long long, double>::type;
-    using vreg_t = typename std::conditional<P32, float, double>::type;   // W V as the taps multiply it
-    // LDS: real plane at byte 0, imaginary plane KOFF doubles further (not
-    // with P32), then the tap table; a plane is R = T + W - 1 rows of pitch P
-    constexpr int R_PAD = W - 1;
-    const int32_t R = T + R_PAD;
-    acc_t *acc_re = reinterpret_cast<acc_t *>(smem);
-    acc_t *acc_im = acc_re + KOFF;
-    const int32_t lut_byte = ((P32 ? 0 : KOFF) + R * P) * (int32_t)sizeof(double);
+    const int32_t lut_byte = lut_byte_of<real, W, TT>(g.pitch);
     real *s_lut = reinterpret_cast<real *>(smem + lut_byte);
     if (!L3)
         for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
     // (visible after the first item's barrier)
-
-    const int lane = __lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // Per-lane tap constants: LDS byte offset of the tap from the footprint
-    // origin, and the byte addresses of its tap-table columns.
     int tap_off8[NG], lut_x[NG], lut_y[NG];
-#pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-        const int t = lane + 64 * gi;
-        const bool on = t < W2;
-        const int ty = on ? t / W : 0, tx = on ? t - (t / W) * W : 0;
-        tap_off8[gi] = (ty * P + tx) * (int)sizeof(double);
-        // L3: lut_y holds the tap's index in a table row (lanes past the
-        // footprint read the row's last tap; their values go unused)
-        lut_x[gi] = lut_byte + tx * (int)sizeof(real);
-        lut_y[gi] = L3 ? (on ? t : W2 - 1) : lut_byte + ty * (int)sizeof(real);
-    }
+    tap_constants<real, W, L3>(g.pitch, lut_byte, tap_off8, lut_x, lut_y);
 
     int32_t item = blockIdx.x;
     for (int it = 0; item < total; ++it) {
         // claim the next item now; it is read after this one's last barrier
         if (threadIdx.x == 0) s_next[it & 1] = (int32_t)gridDim.x + (int32_t)atomicAdd(&st->grid_next, 1ull);
-        const int32_t b = item_bin[item];
-        const int32_t first = scan[b].item;
-        const int32_t nchunk = scan[b + 1].item - first;
-        const int32_t chunk = item - first;
-        const int32_t r_begin = scan[b].rec + chunk * g.CH;
-        int32_t r_end = r_begin + g.CH;
-        if (r_end > scan[b + 1].rec) r_end = scan[b + 1].rec;
-        const int32_t n = r_end - r_begin;   // > 0: empty bins have no work item
-        const int32_t k = b / (g.nt * g.nt);
-        const int32_t rem = b - k * g.nt * g.nt;
-        const int32_t y0 = (rem / g.nt) << g.log2T, x0 = (rem % g.nt) << g.log2T;
-        double scale = 1.0, unscale = 1.0;
-        if (P32) {
-            const double vmax = (double)__uint_as_float(bin_vmax[b]);   // largest |W V| of the bin
-            // largest |term|: |W V| times the largest |tap| (the square of the
-            // largest separable row value, or the largest entry of the table)
-            const double bt = vmax * (L3 ? (double)*tapmax * (1.0 + 1e-6) : (double)g.gmax2);
-            if (bt > 0.0 && bt < 1e300) {
-                const int et = ilogb(bt) + 1;   // bt < 2^et
-                const int sh = min(kPackTermBits - et, 120);   // (2^s stays a normal float32)
-                scale = ldexp(1.0, sh);
-                unscale = ldexp(1.0, -sh);
-            }
-        }
-        // packed mode: this thread's cells' sums (cell threadIdx.x + j kGridBlock)
-        long long own_re[P32 ? CPT : 1], own_im[P32 ? CPT : 1];
-#pragma unroll
-        for (int j = 0; j < (P32 ? CPT : 1); ++j) own_re[j] = own_im[j] = 0;
-        auto drain = [&]() {
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int32_t i = (int32_t)threadIdx.x + j * kGridBlock;
-                if (i < R * P) {
-                    long long re, im;
-                    unpack_terms(acc_re[i], re, im);
-                    acc_re[i] = 0;
-                    own_re[j] += re;
-                    own_im[j] += im;
-                }
-            }
-        };
-        // accumulated value of LDS cell i (packed mode: the float32 pair the
-        // owners stored there after the last drain)
-        auto cell = [&](int32_t i, real &re, real &im) {
-            if constexpr (P32) {
-                const float2 v = reinterpret_cast<const float2 *>(acc_re)[i];
-                re = v.x;
-                im = v.y;
-            } else {
-                re = (real)acc_re[i];
-                im = (real)acc_im[i];
-            }
-        };
-        for (int i = threadIdx.x; i < R * P; i += kGridBlock) {
-            acc_re[i] = 0;
-            if (!P32) acc_im[i] = 0;
-        }
-        __syncthreads();
+        grid_item<real, W, TT, L3>(g, scan, item_bin, rec_pos, rec_vis, lut, mesh, tile_bits, margin, bin_vmax,
+                                   tapmax, plane_tr, item, tap_off8, lut_x, lut_y);
+        __syncthreads();   // the accumulators are read out; s_next is written
+        item = s_next[it & 1];
+    }
+}
 
-        // this wave's batches of 64 records, one record per lane; the next
-        // batch's raw fields are loaded while the current one is gridded
-        const int32_t nbatch = (n + 63) >> 6;
-        uint32_t raw_pos = 0;
-        real raw_vr = 0, raw_vi = 0;
-        auto fetch = [&](int32_t bi) {
-            const int32_t r = r_begin + (bi << 6) + lane;
-            if (r < r_end) {
-                raw_pos = rec_pos[r];
-                raw_vr = rec_vis[2 * (int64_t)r];
-                raw_vi = rec_vis[2 * (int64_t)r + 1];
-            }
-        };
-        if (wave < nbatch) fetch(wave);
-        // rounds of one batch per wave (packed mode: drained after each round)
-        for (int32_t round0 = 0; round0 < nbatch; round0 += nwave) {
-          const int32_t bt = round0 + wave;
-          if (bt < nbatch) {
-            const int32_t cnt = min(64, r_end - (r_begin + (bt << 6)));
-            // decode this lane's record: byte offset of the footprint origin in
-            // the real plane, tap-table row byte offsets and visibility (lanes
-            // past the batch keep zeros: they add 0 at the region's origin)
-            int32_t d_base8 = 0, d_lxy = 0;
-            vreg_t d_vr = 0, d_vi = 0;   // W V times 2^s in float32 modes (exact)
-            if (lane < cnt) {
-                const int sx = (int)((raw_pos >> 16) & 0xffu), sy = (int)(raw_pos >> 24);
-                if constexpr (L3) {
-                    const int ox = (int)(raw_pos & 0x3fu), oy = (int)((raw_pos >> 8) & 0x3fu);   // in [0, T)
-                    const int iw = (int)((raw_pos >> 6) & 3u) | (int)((raw_pos >> 14) & 1u) << 2;
-                    d_base8 = (oy * P + ox) * (int)sizeof(double);
-                    d_lxy = ((iw * g.OS + sy) * g.OS + sx) * W2;   // first entry of the record's table row
-                } else {
-                    const int ox = (int)(raw_pos & 0xffu), oy = (int)((raw_pos >> 8) & 0xffu);   // in [0, T)
-                    d_base8 = (oy * P + ox) * (int)sizeof(double);
-                    d_lxy = (sx * W * (int)sizeof(real)) | (sy * W * (int)sizeof(real)) << 16;
-                }
-                d_vr = (vreg_t)((double)raw_vr * scale);
-                d_vi = (vreg_t)((double)raw_vi * scale);
-            }
-            if (bt + nwave < nbatch) fetch(bt + nwave);
+// Gridding of several jobs (plans) in one persistent launch over a
+// device-side queue: the work items of the jobs, in job order, form one
+// sequence; a block takes item blockIdx.x, then the next unclaimed one from
+// the shared counter, finds its job from the prefix of the jobs' item counts
+// (read on the device after their binning) and grids it with that job's
+// operands.  Every job of a launch has the same support and tile edge
+// (instantiation parameters) and a separable tap table; the table is loaded
+// into LDS when a block moves to another job.
+typedef __attribute__((address_space(4))) const GridJob const_job;
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
+// a job's operands, read through the constant address space (the job is the
+// same for the whole block: scalar loads into scalar registers)
+__device__ __forceinline__ GridJob load_job(const GridJob *p) {
+    static_assert(sizeof(GridJob) % 4 == 0, "whole words");
+    GridJob v;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+    const const_u32 *src = (const const_u32 *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(GridJob) / 4); ++i) dst[i] = src[i];
+    return v;
+}
+template <typename real, int W, int TT>
+__global__ __launch_bounds__(grid_threads(TT), W <= 7 ? 8 : 1) void k_grid_jobs(GridJobList list,
+                                                                                unsigned long long *__restrict__ next) {
+    constexpr int NG = (W * W + 63) / 64;
+    constexpr int kGridBlock = grid_threads(TT);
+    constexpr int32_t P = acc_pitch(TT, W);   // the pitch of every job of the launch
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t s_next[2];
+    __shared__ int32_t s_pre[kMaxGridJobs + 1];   // first item of each job; total at [n]
+    const int32_t n = list.n;
+    if ((int)threadIdx.x < n) {
+        const const_job *J = (const const_job *)list.job[threadIdx.x];
+        s_pre[threadIdx.x + 1] = J->scan[J->g.nbins].item;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_pre[0] = 0;
+        for (int32_t j = 0; j < n; ++j) s_pre[j + 1] += s_pre[j];
+    }
+    __syncthreads();
+    const int32_t total = s_pre[n];
+    if ((int32_t)blockIdx.x >= total) return;
+    const int32_t lut_byte = lut_byte_of<real, W, TT>(P);
+    real *s_lut = reinterpret_cast<real *>(smem + lut_byte);
+    int tap_off8[NG], lut_x[NG], lut_y[NG];
+    tap_constants<real, W, false>(P, lut_byte, tap_off8, lut_x, lut_y);
 
-            // tap-table values of one group of records (indices past the batch
-            // wrap to lanes holding a switched-off record: the reads stay in the
-            // table and their values go unused)
-            auto lut_reads = [&](int j, real (&gy)[kGroup][NG], real (&gx)[kGroup][NG]) {
-#pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const int32_t lxy = bcast(d_lxy, (j + q) & 63);
-                    if constexpr (L3) {
-#pragma unroll
-                        for (int gi = 0; gi < NG; ++gi) {
-                            gy[q][gi] = lut[lxy + lut_y[gi]];
-                            gx[q][gi] = (real)1;
-                        }
-                    } else {
-                        const int32_t lx = lxy & 0xffff, ly = lxy >> 16;
-#pragma unroll
-                        for (int gi = 0; gi < NG; ++gi) {
-                            gy[q][gi] = *reinterpret_cast<const real *>(smem + (lut_y[gi] + ly));
-                            gx[q][gi] = *reinterpret_cast<const real *>(smem + (lut_x[gi] + lx));
-                        }
-                    }
-                }
-            };
-            auto add_group = [&](int j, const real (&gy)[kGroup][NG], const real (&gx)[kGroup][NG]) {
-#pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const int32_t base8 = bcast(d_base8, (j + q) & 63);
-                    const vreg_t vr = bcast(d_vr, (j + q) & 63), vi = bcast(d_vi, (j + q) & 63);
-#pragma unroll
-                    for (int gi = 0; gi < NG; ++gi) {
-                        // lanes holding a tap of group gi (a compile-time mask)
-                        constexpr uint64_t kAll = ~0ull;
-                        const uint64_t msk = W2 - 64 * gi >= 64 ? kAll : (1ull << (W2 - 64 * gi)) - 1;
-                        // the products are formed outside the branch, so the wait
-                        // for the table values is the same on every path
-                        const real wgt = gy[q][gi] * gx[q][gi];
-                        if constexpr (P32) {
-                            // round(g V 2^s) of re and im, then both as one 64-bit word
-                            float tr = fmaf(wgt, vr, kRoundMagic32);
-                            float ti = fmaf(wgt, vi, kRoundMagic32);
-                            __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
-                            if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
-                                acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
-                                atomicAdd(a, pack_terms(tr, ti));
-                            }
-                        } else {
-                            double tr = wgt * vr, ti = wgt * vi;
-                            __asm__ volatile("" : "+v"(tr), "+v"(ti));   // keeps them here (emits nothing)
-                            // (with one tap group the whole record loop already runs on the tap lanes)
-                            if (NG == 1 || __builtin_amdgcn_inverse_ballot_w64(msk)) {
-                                acc_t *a = reinterpret_cast<acc_t *>(smem + (base8 + tap_off8[gi]));
-                                atomicAdd(a, tr);
-                                atomicAdd(a + KOFF, ti);
-                            }
-                        }
-                    }
-                }
-            };
-            // two table buffers used in turn: the reads for group j + kGroup are
-            // issued before the atomics of group j, and no value is copied.  With
-            // one tap group (W <= 7) the loop runs on the tap lanes only: the
-            // execution mask is set once per batch, not per record (readlane
-            // reads the records of the other lanes regardless).
-            if (NG > 1 || lane < W2) {
-                real ay[kGroup][NG], ax[kGroup][NG], by[kGroup][NG], bx[kGroup][NG];
-                lut_reads(0, ay, ax);
-#pragma unroll
-                for (int j = 0; j < 64; j += 2 * kGroup) {
-                    lut_reads(j + kGroup, by, bx);
-                    add_group(j, ay, ax);
-                    if (j + kGroup >= cnt) break;
-                    lut_reads(j + 2 * kGroup, ay, ax);
-                    add_group(j + kGroup, by, bx);
-                    if (j + 2 * kGroup >= cnt) break;
-                }
-            }
-          }
-          if constexpr (P32) {
-              __syncthreads();   // the round's atomics are done
-              drain();
-              __syncthreads();   // the cells are zero again
-          }
-        }
-        if constexpr (P32) {
-            // the sums as float32 pairs in the cells, for the row-coalesced flush
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const int32_t i = (int32_t)threadIdx.x + j * kGridBlock;
-                if (i < R * P)
-                    reinterpret_cast<float2 *>(acc_re)[i] =
-                        float2{(float)((double)own_re[j] * unscale), (float)((double)own_im[j] * unscale)};
-            }
-        }
-        __syncthreads();
-
-        const bool shared_tile = nchunk > 1;
-        // a transposed plane: cell (y, x) at row x, column y, and the tile's bit
-        // at (tile column, tile row); consecutive threads take consecutive
-        // stored columns either way
-        const bool tr = plane_transposed(plane_tr, k);
-        const bool accumulate =
-            tr ? tile_set(tile_bits, g, k, rem % g.nt, rem / g.nt) : tile_set(tile_bits, g, k, rem / g.nt, rem % g.nt);
-        for (int32_t c = threadIdx.x; c < T * T; c += kGridBlock) {
-            const int32_t hi = c >> g.log2T, lo = c & (T - 1);
-            const int32_t y = tr ? lo : hi, x = tr ? hi : lo;
-            real re, im;
-            cell(y * P + x, re, im);
-            r2 *dst = tr ? m + ((int64_t)k * g.N + x0 + x) * g.N + y0 + y : m + ((int64_t)k * g.N + y0 + y) * g.N + x0 + x;
-            if (shared_tile) {
-                if (re != 0) atomic_add_real(&dst->x, re);
-                if (im != 0) atomic_add_real(&dst->y, im);
-            } else if (accumulate) {
-                const r2 old = *dst;
-                *dst = r2{old.x + re, old.y + im};
-            } else {
-                *dst = r2{re, im};
-            }
-        }
-        // margins to the bin's margin buffer (the merge adds them to the neighbours)
-        if constexpr (R_PAD > 0) {
-            r2 *mb = reinterpret_cast<r2 *>(margin) + (int64_t)b * margin_len(T, W);
-            const int32_t n_right = R * R_PAD, n_all = n_right + R_PAD * T;
-            for (int32_t c = threadIdx.x; c < n_all; c += kGridBlock) {
-                int32_t y, x;
-                if (c < n_right) {
-                    y = c / R_PAD;
-                    x = T + (c - y * R_PAD);
-                } else {
-                    const int32_t d = c - n_right;
-                    y = T + (d >> g.log2T);
-                    x = d & (T - 1);
-                }
-                real re, im;
-                cell(y * P + x, re, im);
-                if (shared_tile) {
-                    if (re != 0) atomic_add_real(&mb[c].x, re);
-                    if (im != 0) atomic_add_real(&mb[c].y, im);
-                } else {
-                    mb[c] = r2{re, im};
-                }
-            }
-        }
+    int32_t cur = -1;   // the job whose tap table is in LDS
+    int32_t item = blockIdx.x;
+    for (int it = 0; item < total; ++it) {
+        if (threadIdx.x == 0) s_next[it & 1] = (int32_t)gridDim.x + (int32_t)atomicAdd(next, 1ull);
+        int32_t j = 0;
+        while (j + 1 < n && s_pre[j + 1] <= item) ++j;
+        j = __builtin_amdgcn_readfirstlane(j);
+        const GridJob J = load_job(list.job[j]);
+        const Geom &g = J.g;
+        const real *lut = (const real *)J.lut;
+        // (the previous item's table reads ended before its last barrier; the
+        // first barrier of this item makes the new table visible)
+        if (j != cur)
+            for (int i = threadIdx.x; i < g.OS * W; i += kGridBlock) s_lut[i] = lut[i];
+        cur = j;
+        grid_item<real, W, TT, false>(g, J.scan, J.item_bin, J.rec_pos, (const real *)J.rec_vis, lut,
+                                      (real *)J.mesh, J.tile_bits, (real *)J.margin, J.bin_vmax, nullptr,
+                                      J.plane_tr, item - s_pre[j], tap_off8, lut_x, lut_y);
         __syncthreads();   // the accumulators are read out; s_next is written
         item = s_next[it & 1];
     }
@@ -673,6 +782,31 @@ hipError_t grid_wt(const Geom &g, const BinScan *scan, const int32_t *item_bin, 
 }
 
 template <typename real, int W, int TT>
+hipError_t grid_jobs_wt(const GridJobList &list, size_t lds, int64_t max_items, unsigned long long *next,
+                        hipStream_t s) {
+    constexpr size_t kStatic = 512;   // at least the kernel's own LDS (272 bytes with alignment)
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
+        (void)hipFuncSetAttribute((const void *)k_grid_jobs<real, W, TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(160 * 1024 - kStatic));
+    });
+    if (lds + kStatic > 160 * 1024) return hipErrorInvalidValue;
+    int per_cu = int((160 * 1024) / (lds + kStatic));
+    const int by_waves = 2048 / grid_threads(TT);
+    per_cu = per_cu < by_waves ? per_cu : by_waves;
+    per_cu = per_cu < 1 ? 1 : per_cu;
+    const int64_t want = int64_t(device_cus()) * per_cu;
+    const int64_t nblk = want < max_items ? want : max_items;
+    hipLaunchKernelGGL((k_grid_jobs<real, W, TT>), dim3((unsigned)(nblk > 0 ? nblk : 1)), dim3(grid_threads(TT)), lds,
+                       s, list, next);
+    return hipGetLastError();
+}
+
+__global__ void k_put_grid_job(GridJob *__restrict__ dst, GridJob v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = v;
+}
+
+template <typename real, int W, int TT>
 hipError_t grid_wt2(const Geom &g, const BinScan *scan, const int32_t *item_bin, const uint32_t *rec_pos,
                     const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                     const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
@@ -784,6 +918,28 @@ hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_b
     }
 }
 
+hipError_t launch_put_grid_job(GridJob *dst, const GridJob &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_grid_job, dim3(1), dim3(64), 0, s, dst, v);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_grid_jobs(const GridJobList &list, int W, int T, size_t lds, int64_t max_items,
+                            unsigned long long *next, hipStream_t s) {
+    if (list.n < 1 || list.n > kMaxGridJobs) return hipErrorInvalidValue;
+#define TCASE(w, t) \
+    case t: return grid_jobs_wt<real, w, t>(list, lds, max_items, next, s);
+#define WCASE(w) \
+    case w: \
+        switch (T) { TCASE(w, 16) TCASE(w, 32) TCASE(w, 64) default: return hipErrorInvalidValue; }
+    switch (W) {
+        WCASE(1) WCASE(3) WCASE(5) WCASE(7) WCASE(9) WCASE(11) WCASE(13) WCASE(15)
+        default: return hipErrorInvalidValue;
+    }
+#undef WCASE
+#undef TCASE
+}
+
 template hipError_t launch_zero_mesh<float>(float *, int64_t, hipStream_t);
 template hipError_t launch_zero_mesh<double>(double *, int64_t, hipStream_t);
 template hipError_t launch_zero_heavy<float>(const Geom &, const int32_t *, Stats *, const uint64_t *,
@@ -802,5 +958,9 @@ template hipError_t launch_grid<double>(const Geom &, const BinScan *, const int
                                         const double *, const double *, double *, const uint64_t *, double *,
                                         const uint32_t *, const float *, Stats *, const int32_t *, int32_t,
                                        hipStream_t);
+template hipError_t launch_grid_jobs<float>(const GridJobList &, int, int, size_t, int64_t, unsigned long long *,
+                                            hipStream_t);
+template hipError_t launch_grid_jobs<double>(const GridJobList &, int, int, size_t, int64_t, unsigned long long *,
+                                             hipStream_t);
 
 }  // namespace rick

@@ -103,6 +103,7 @@ struct rick_plan_s {
     double *corr = nullptr;
     double *scales = nullptr;
     Stats *stats = nullptr;
+    GridJob *job_dev = nullptr;   // this plan's operands for the multi-job gridder
     int32_t *counts = nullptr;
     BinScan *scan = nullptr;
     int32_t *block_sums = nullptr;
@@ -165,7 +166,8 @@ void free_all(rick_plan_t *p) {
                     p->scales,
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->vmax2,    p->bin_vmax, p->item_bin, p->heavy_bins,
-                    p->rec_pos,   p->rec_vis,   p->dft_wsum,  p->tapmax,    p->corr2,     p->taper_bufs.A};
+                    p->rec_pos,   p->rec_vis,   p->dft_wsum,  p->tapmax,    p->corr2,     p->taper_bufs.A,
+                    p->job_dev};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < kMaxTimers; ++i)
@@ -459,6 +461,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->corr, size_t(g.N) * 8);
     ALLOC(p->scales, size_t(kMaxChan) * 8);
     ALLOC(p->stats, sizeof(Stats));
+    ALLOC(p->job_dev, sizeof(GridJob));
     ALLOC(p->counts, sz_counts);
     ALLOC(p->scan, sz_scan);
     ALLOC(p->block_sums, sz_bsum);
@@ -618,17 +621,19 @@ hipError_t upload_scales(rick_plan_t *p, const double *freq_hz, int32_t nchan, h
     return hipSuccess;
 }
 
-// Bin-and-sort, gridding and margin merge of one call, with the sort buffers in bb.
-rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, const double *freq_hz, const void *vis,
-                      const float *weight, int64_t nrow, int32_t nchan, hipStream_t s) {
+// Bound on the gridding work items of a call of nvis visibilities: one per
+// chunk of a non-empty bin (one record per visibility).
+int32_t grid_items_bound(const Geom &g, int64_t nvis) {
+    return int32_t((nvis < g.nbins ? nvis : g.nbins) + (nvis + g.CH - 1) / g.CH + 1);
+}
+
+// Bin-and-sort of one call (sort buffers in bb), the orientation of new
+// planes and the zeroing of split bins' tiles: everything before gridding.
+rick_status bin_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, const double *freq_hz, const void *vis,
+                     const float *weight, int64_t nrow, int32_t nchan, hipStream_t s) {
     hipError_t e = upload_scales(p, freq_hz, nchan, s);
     if (e != hipSuccess) return hip_fail(e, "channel scales upload");
     const Geom &g = p->g;
-    const int64_t nvis = nrow * nchan;
-    // work items: one per chunk of a non-empty bin (one record per visibility)
-    const int64_t max_records = nvis;
-    const int32_t max_items =
-        int32_t((max_records < g.nbins ? max_records : g.nbins) + (max_records + g.CH - 1) / g.CH + 1);
     struct Pass {
         int slot;
         const char *name;
@@ -664,7 +669,33 @@ rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, cons
                                      (float *)p->margin, s);
     timer_end(p, T_ZERO_HEAVY, s);
     if (e != hipSuccess) return hip_fail(e, "zero_heavy");
+    return RICK_OK;
+}
+
+// Margins of the gridded tiles added to their neighbours, tile and row bits.
+rick_status merge_impl(rick_plan_t *p, const BinBufs &bb, hipStream_t s) {
+    const Geom &g = p->g;
+    timer_begin(p, T_MARK, "merge_margins", s);
+    const hipError_t e =
+        p->fp64 ? launch_merge_margins<double>(g, bb.scan, (const double *)p->margin, p->tile_bits, p->row_bits,
+                                               p->plane_tr, (double *)p->mesh, s)
+                : launch_merge_margins<float>(g, bb.scan, (const float *)p->margin, p->tile_bits, p->row_bits,
+                                              p->plane_tr, (float *)p->mesh, s);
+    timer_end(p, T_MARK, s);
+    if (e != hipSuccess) return hip_fail(e, "merge_margins");
+    p->state = 1;
+    return RICK_OK;
+}
+
+// Bin-and-sort, gridding and margin merge of one call, with the sort buffers in bb.
+rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, const double *freq_hz, const void *vis,
+                      const float *weight, int64_t nrow, int32_t nchan, hipStream_t s) {
+    rick_status r = bin_impl(p, bb, uvw, freq_hz, vis, weight, nrow, nchan, s);
+    if (r != RICK_OK) return r;
+    const Geom &g = p->g;
+    const int32_t max_items = grid_items_bound(g, nrow * nchan);
     timer_begin(p, T_GRID, "grid", s);
+    hipError_t e;
     if (p->fp64)
         e = launch_grid<double>(g, bb.scan, bb.item_bin, bb.rec_pos, (const double *)bb.rec_vis,
                                 (const double *)p->lut, (double *)p->mesh, p->tile_bits, (double *)p->margin,
@@ -675,15 +706,13 @@ rick_status grid_impl(rick_plan_t *p, const BinBufs &bb, const double *uvw, cons
                                p->lut3 ? p->tapmax : nullptr, p->stats, p->plane_tr, max_items, s);
     timer_end(p, T_GRID, s);
     if (e != hipSuccess) return hip_fail(e, "grid");
-    timer_begin(p, T_MARK, "merge_margins", s);
-    e = p->fp64 ? launch_merge_margins<double>(g, bb.scan, (const double *)p->margin, p->tile_bits, p->row_bits,
-                                               p->plane_tr, (double *)p->mesh, s)
-                : launch_merge_margins<float>(g, bb.scan, (const float *)p->margin, p->tile_bits, p->row_bits,
-                                              p->plane_tr, (float *)p->mesh, s);
-    timer_end(p, T_MARK, s);
-    if (e != hipSuccess) return hip_fail(e, "merge_margins");
-    p->state = 1;
-    return RICK_OK;
+    return merge_impl(p, bb, s);
+}
+
+// The plan's own sort buffers (those of rick_grid).
+BinBufs plan_bufs(rick_plan_t *p) {
+    return BinBufs{p->cnt1,   p->block_sums, p->rec1, p->key_chunk0, p->chunk_key,  p->cnt2,    p->vmax2,
+                   p->counts, p->bin_vmax,   p->scan, p->item_bin,   p->heavy_bins, p->rec_pos, p->rec_vis};
 }
 
 // Byte offsets, in the static scratch, of the per-visibility sort buffers of
@@ -726,9 +755,71 @@ rick_status rick_grid(rick_plan_t *p, const double *uvw, const double *freq_hz, 
         return fail(RICK_E_CAPACITY, "nrow*nchan=%lld > max_vis=%lld", (long long)(nrow * nchan),
                     (long long)p->d.max_vis);
     DeviceGuard guard(p->d.device);
-    const BinBufs bb{p->cnt1,     p->block_sums, p->rec1,    p->key_chunk0, p->chunk_key, p->cnt2, p->vmax2,
-                     p->counts,   p->bin_vmax,   p->scan,    p->item_bin,   p->heavy_bins, p->rec_pos, p->rec_vis};
-    return grid_impl(p, bb, uvw, freq_hz, vis, weight, nrow, nchan, (hipStream_t)stream);
+    return grid_impl(p, plan_bufs(p), uvw, freq_hz, vis, weight, nrow, nchan, (hipStream_t)stream);
+}
+
+static_assert(RICK_MAX_GRID_JOBS == kMaxGridJobs, "one job limit for the header and the kernel");
+
+rick_status rick_grid_jobs(const rick_grid_job *jobs, int32_t n, void *stream) {
+    if (!jobs) return fail(RICK_E_INVALID_ARG, "jobs is NULL");
+    if (n < 1 || n > kMaxGridJobs) return fail(RICK_E_INVALID_ARG, "n=%d (1 ... %d jobs)", n, kMaxGridJobs);
+    for (int32_t i = 0; i < n; ++i) {
+        const rick_grid_job &J = jobs[i];
+        rick_plan_t *p = J.plan;
+        if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "job %d: invalid plan", i);
+        if (p->lut3) return fail(RICK_E_UNSUPPORTED, "job %d: a user table (the joint gridder takes separable kernels)", i);
+        const rick_status st = check_grid_args(p, J.uvw, J.freq_hz, J.vis, J.weight, J.nrow, J.nchan);
+        if (st != RICK_OK) return st;
+        if (J.reserved != 0) return fail(RICK_E_INVALID_ARG, "job %d: reserved=%d (must be 0)", i, J.reserved);
+        if (J.nrow * int64_t(J.nchan) > p->d.max_vis)
+            return fail(RICK_E_CAPACITY, "job %d: nrow*nchan=%lld > max_vis=%lld", i,
+                        (long long)(J.nrow * J.nchan), (long long)p->d.max_vis);
+        if (p->fp64 != jobs[0].plan->fp64) return fail(RICK_E_INVALID_ARG, "job %d: precision differs from job 0's", i);
+        if (p->d.device != jobs[0].plan->d.device)
+            return fail(RICK_E_INVALID_ARG, "job %d: device differs from job 0's", i);
+        for (int32_t k = 0; k < i; ++k)
+            if (jobs[k].plan == p) return fail(RICK_E_INVALID_ARG, "job %d: same plan as job %d", i, k);
+    }
+    DeviceGuard guard(jobs[0].plan->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp64 = jobs[0].plan->fp64;
+    for (int32_t i = 0; i < n; ++i) {
+        const rick_grid_job &J = jobs[i];
+        const rick_status r = bin_impl(J.plan, plan_bufs(J.plan), J.uvw, J.freq_hz, J.vis, J.weight, J.nrow, J.nchan, s);
+        if (r != RICK_OK) return r;
+    }
+    // one persistent launch per (support, tile edge); the shared work-item
+    // counter is the first job's (zeroed by its binning)
+    bool done[kMaxGridJobs] = {};
+    for (int32_t i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        const Geom &gi = jobs[i].plan->g;
+        GridJobList list{};
+        size_t lds = 0;
+        int64_t max_items = 0;
+        for (int32_t j = i; j < n; ++j) {
+            rick_plan_t *p = jobs[j].plan;
+            if (done[j] || p->g.W != gi.W || p->g.T != gi.T) continue;
+            done[j] = true;
+            const GridJob d{p->g,     p->scan,      p->item_bin, p->rec_pos, p->rec_vis,   p->lut,
+                            p->mesh,  p->tile_bits, p->margin,   p->bin_vmax, p->plane_tr};
+            hipError_t e = launch_put_grid_job(p->job_dev, d, s);
+            if (e != hipSuccess) return hip_fail(e, "grid job table");
+            list.job[list.n++] = p->job_dev;
+            const size_t b = grid_lds_bytes(p->g, p->real_bytes);
+            lds = b > lds ? b : lds;
+            max_items += grid_items_bound(p->g, jobs[j].nrow * jobs[j].nchan);
+        }
+        unsigned long long *next = &jobs[i].plan->stats->grid_next;
+        const hipError_t e = fp64 ? launch_grid_jobs<double>(list, gi.W, gi.T, lds, max_items, next, s)
+                                  : launch_grid_jobs<float>(list, gi.W, gi.T, lds, max_items, next, s);
+        if (e != hipSuccess) return hip_fail(e, "grid_jobs");
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const rick_status r = merge_impl(jobs[i].plan, plan_bufs(jobs[i].plan), s);
+        if (r != RICK_OK) return r;
+    }
+    return RICK_OK;
 }
 
 rick_status rick_grid_static(rick_plan_t *p, const double *uvw, const double *freq_hz, const void *vis,
@@ -1233,6 +1324,9 @@ rick_status rick_stamps_create(int32_t n, rick_stamps_t **out) {
     if (e == hipSuccess && khz <= 0) e = hipErrorInvalidValue;
     if (e == hipSuccess) e = hipMalloc((void **)&t->dev, size_t(n) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemset(t->dev, 0, size_t(n) * sizeof(uint64_t));
+    // the memset is ordered on the null stream only, not against non-blocking
+    // streams: it must be done before a stamp on such a stream can land
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         if (t->dev) (void)hipFree(t->dev);
         delete t;

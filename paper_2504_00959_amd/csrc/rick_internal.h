@@ -197,6 +197,34 @@ hipError_t launch_grid(const Geom &g, const BinScan *scan, const int32_t *item_b
                        const real *rec_vis, const real *lut, real *mesh, const uint64_t *tile_bits, real *margin,
                        const uint32_t *bin_vmax, const float *tapmax, Stats *st, const int32_t *plane_tr,
                        int32_t max_items, hipStream_t s);
+// One plan's gridding operands as the multi-job gridder reads them (a
+// device copy per plan, written by launch_put_grid_job before the launch).
+struct GridJob {
+    Geom g;
+    const BinScan *scan;
+    const int32_t *item_bin;
+    const uint32_t *rec_pos;
+    const void *rec_vis;
+    const void *lut;   // separable tap table (real[OS][W])
+    void *mesh;
+    const uint64_t *tile_bits;
+    void *margin;
+    const uint32_t *bin_vmax;
+    const int32_t *plane_tr;
+};
+constexpr int kMaxGridJobs = 64;   // jobs of one multi-job gridding launch
+struct GridJobList {
+    int32_t n;
+    const GridJob *job[kMaxGridJobs];
+};
+hipError_t launch_put_grid_job(GridJob *dst, const GridJob &v, hipStream_t s);
+// Gridding of list.n binned jobs in one persistent launch (every job of
+// support W, tile edge T, separable table); next is the shared work-item
+// counter (zero at launch), lds the largest of the jobs' grid_lds_bytes,
+// max_items the sum of the jobs' bounds on work items.
+template <typename real>
+hipError_t launch_grid_jobs(const GridJobList &list, int W, int T, size_t lds, int64_t max_items,
+                            unsigned long long *next, hipStream_t s);
 // Orientation of every plane that holds no set tile yet: transposed iff this
 // call's records (with the margins they spill right and down) occupy fewer
 // tile columns than tile rows.  Planes already holding tiles keep theirs.

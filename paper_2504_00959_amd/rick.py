@@ -81,6 +81,13 @@ class DegridOrder:
             pass
 
 
+class GridJob(ctypes.Structure):
+    """rick_grid_job: one job of rick_grid_jobs."""
+    _fields_ = [("plan", ctypes.c_void_p), ("uvw", ctypes.c_void_p), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
+                ("vis", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("nrow", ctypes.c_int64),
+                ("nchan", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("grid_n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -120,6 +127,7 @@ def lib() -> ctypes.CDLL:
     L.rick_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]
     L.rick_grid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
     L.rick_grid_static.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
+    L.rick_grid_jobs.argtypes = [ctypes.POINTER(GridJob), ctypes.c_int32, P]
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     L.rick_plan_set_lut.argtypes = [P, P, i32, P]
     L.rick_mlp_tabulate.argtypes = [P, i32, i32, i32, P, P]
@@ -158,7 +166,7 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(ctypes.c_float)]
     for f in ("rick_plan_set_lut", "rick_mlp_tabulate", "rick_mlp_backward", "rick_adam_step", "rick_image_loss",
               "rick_table_gradient", "rick_dft_image", "rick_separable_table", "rick_table_residual",
-              "rick_plan", "rick_grid", "rick_grid_static", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
+              "rick_plan", "rick_grid", "rick_grid_static", "rick_grid_jobs", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
               "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid",
@@ -256,6 +264,13 @@ class Plan:
         vis complex [R,C], weight float32 [R,C] or None, freq host sequence [C] in Hz or None.
         static_scratch: call rick_grid_static (sort buffers in the library's static
         device scratch; nothing allocated) instead of rick_grid."""
+        a = self._grid_args(uvw, vis, weight, freq)
+        fn, name = (lib().rick_grid_static, "rick_grid_static") if static_scratch else (lib().rick_grid, "rick_grid")
+        _check(fn(self._h, a.uvw, a.freq_hz, a.vis, a.weight, a.nrow, a.nchan, _stream_handle(stream)), name)
+
+    def _grid_args(self, uvw, vis, weight, freq) -> "GridJob":
+        """Checked arguments of one rick_grid call as a rick_grid_job (the
+        frequency array is kept alive by the plan until its next call)."""
         import torch
         self._device_tensor(uvw, "uvw", torch.float64)
         self._device_tensor(vis, "vis", self.complex_dtype)
@@ -280,8 +295,7 @@ class Plan:
                 raise ValueError("freq must have nchan entries")
             self._freq_keep = f
             fptr = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        fn, name = (lib().rick_grid_static, "rick_grid_static") if static_scratch else (lib().rick_grid, "rick_grid")
-        _check(fn(self._h, uvw.data_ptr(), fptr, vis.data_ptr(), wptr, nrow, nchan, _stream_handle(stream)), name)
+        return GridJob(self._h, uvw.data_ptr(), fptr, vis.data_ptr(), wptr, nrow, nchan, 0)
 
     def fft(self, stream=None):
         _check(lib().rick_fft_planes(self._h, _stream_handle(stream)), "rick_fft_planes")
@@ -608,6 +622,22 @@ def table_residual(table, target, dtable, sums, stream=None):
         raise ValueError("sizes do not match")
     _check(lib().rick_table_residual(table.data_ptr(), target.data_ptr(), n, dtable.data_ptr(), sums.data_ptr(),
                                      _stream_handle(stream)), "rick_table_residual")
+
+
+def grid_jobs(jobs, stream=None):
+    """rick_grid_jobs: each job (plan, uvw, vis[, weight[, freq]]) binned on
+    its own plan, then the gridding of all jobs in one persistent launch per
+    (support, tile edge).  Same argument rules as Plan.grid."""
+    jobs = list(jobs)
+    if not jobs:
+        raise ValueError("no jobs")
+    arr = (GridJob * len(jobs))()
+    for i, job in enumerate(jobs):
+        plan, uvw, vis = job[0], job[1], job[2]
+        weight = job[3] if len(job) > 3 else None
+        freq = job[4] if len(job) > 4 else None
+        arr[i] = plan._grid_args(uvw, vis, weight, freq)
+    _check(lib().rick_grid_jobs(arr, len(jobs), _stream_handle(stream)), "rick_grid_jobs")
 
 
 def adam_step(theta, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -90,3 +90,13 @@ def test_learned_calls_validate_on_the_host():
     assert L.rick_image_loss(None, fake, fake, fake, fake, fake, None) == 6
     assert L.rick_table_gradient(None, fake, fake, fake, None, fake, None, 1, 1, fake, None) == 6
     assert L.rick_dft_image(None, fake, None, fake, None, 1, 1, 0, 0, 1, 1, fake, None) == 6
+
+
+def test_grid_jobs_validates_on_the_host():
+    L = rick.lib()
+    assert L.rick_grid_jobs(None, 1, None) == 1                     # RICK_E_INVALID_ARG: no jobs
+    jobs = (rick.GridJob * 2)()
+    assert L.rick_grid_jobs(jobs, 0, None) == 1                     # n out of range
+    assert L.rick_grid_jobs(jobs, 65, None) == 1
+    assert b"1 ... 64" in L.rick_last_error()
+    assert L.rick_grid_jobs(jobs, 2, None) == 6                     # RICK_E_BAD_PLAN: a NULL plan

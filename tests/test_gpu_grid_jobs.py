@@ -1,0 +1,164 @@
+"""Gridding of many jobs in one persistent launch (rick_grid_jobs) through
+the C ABI.
+
+Jobs of uneven grid size and visibility count, each on its own plan (two
+tile edges, so two launches; small chunks on some plans, so bins spanning
+several work items flush with atomics), are gridded jointly and checked
+against the same plans gridded one call at a time: equal counters and tile
+bitmaps, planes equal to float rounding, images equal to float rounding and
+to the oracle's.  The joint call is also recorded into a graph and replayed,
+with other work between the replays, and its argument checks are exercised.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2504_00959_amd import rick
+from tests.helpers import image_errors, rel_rms, to_device
+
+pytestmark = pytest.mark.gpu
+
+FP32_IMG = 1e-5
+
+
+def _jobs(n=6, seed=23):
+    return synth.batched_jobs(seed=seed, n_jobs=n, grid_sizes=(256, 512), nvis_range=(2e4, 2e5), n_dumps=200,
+                              oversample=32)
+
+
+def _plans(jobs, precision="fp32"):
+    # tiles of 32 and 64 cells in turn; small gridding chunks on every third plan
+    return [rick.Plan.for_dataset(ds, precision=precision, fused=True, tile=(32, 64)[i % 2],
+                                  chunk=(512 if i % 3 == 0 else 0)) for i, ds in enumerate(jobs)]
+
+
+def _state(p):
+    inf = p.info()
+    return dict(counts=(inf["n_gridded"], inf["n_dropped"], inf["n_records"]), sum_w=inf["sum_weights"],
+                mask=p.tile_mask(), G=p.mesh().cpu().numpy())
+
+
+def _apparent(ds):
+    c = oracle.wstack.grid_correction(oracle.wstack.tap_table(ds.support, ds.oversample), ds.grid_n)
+    return np.outer(c, c)
+
+
+def _image(p):
+    import torch
+    p.fft()
+    img = p.image().double().cpu().numpy()
+    torch.cuda.synchronize()
+    return img
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_joint_launch_equals_one_call_per_job(precision):
+    import torch
+    jobs = _jobs(6 if precision == "fp32" else 3)
+    dev = [to_device(ds, precision)[:2] for ds in jobs]
+    plans = _plans(jobs, precision)
+    try:
+        single, joint = [], []
+        for p, ds, (u, v) in zip(plans, jobs, dev):
+            p.reset()
+            p.grid(u, v, None, ds.freq)
+        torch.cuda.synchronize()
+        for p in plans:
+            single.append(_state(p))
+            single[-1]["img"] = _image(p)
+        for p in plans:
+            p.reset()
+        rick.grid_jobs([(p, u, v, None, ds.freq) for p, ds, (u, v) in zip(plans, jobs, dev)])
+        torch.cuda.synchronize()
+        for p in plans:
+            joint.append(_state(p))
+            joint[-1]["img"] = _image(p)
+    finally:
+        for p in plans:
+            p.close()
+    g_tol = 1e-12 if precision == "fp64" else 1e-6
+    for i, (a, b) in enumerate(zip(single, joint)):
+        assert a["counts"] == b["counts"], i
+        assert abs(a["sum_w"] - b["sum_w"]) <= 1e-9 * abs(a["sum_w"]), i
+        assert np.array_equal(a["mask"], b["mask"]), i
+        assert rel_rms(b["G"], a["G"]) <= g_tol, i
+        c2 = _apparent(jobs[i])
+        assert rel_rms(b["img"] * c2, a["img"] * c2) <= g_tol, i
+    # two jobs (one per tile edge) against the oracle
+    for i in (0, 1):
+        ref = oracle.wstack.wstack_dataset(jobs[i])
+        if precision == "fp64":
+            assert rel_rms(joint[i]["img"], ref.image) <= 1e-10
+        else:
+            err = image_errors(joint[i]["img"], ref.image, ref.corr)
+            assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, (i, err)
+
+
+def test_joint_launch_recorded_and_replayed():
+    import torch
+    jobs = _jobs(5, seed=24)
+    dev = [to_device(ds)[:2] for ds in jobs]
+    plans = _plans(jobs)
+    imgs = [torch.zeros((ds.grid_n, ds.grid_n), dtype=torch.float32, device="cuda:0") for ds in jobs]
+    stream = torch.cuda.Stream()
+    args = [(p, u, v, None, ds.freq) for p, ds, (u, v) in zip(plans, jobs, dev)]
+
+    def run(s):
+        for p in plans:
+            p.reset(s)
+        rick.grid_jobs(args, s)
+        for p, im in zip(plans, imgs):
+            p.fft(s)
+            p.image(im, s)
+
+    try:
+        with torch.cuda.stream(stream):
+            run(stream)                                    # eager reference
+            torch.cuda.synchronize()
+            eager = [im.double().cpu().numpy() for im in imgs]
+            with rick.Graph.record(stream) as graph:
+                run(stream)
+            for rep in range(3):
+                for im in imgs:
+                    im.fill_(float("nan"))
+                torch.cuda.synchronize()
+                graph.launch(stream)
+                torch.cuda.synchronize()
+                got = [im.double().cpu().numpy() for im in imgs]
+                for i, (a, b) in enumerate(zip(eager, got)):
+                    # apparent images: bins split over several chunks add their
+                    # partial tiles with float atomics in no fixed order, which
+                    # the taper division magnifies in the corners
+                    c2 = _apparent(jobs[i])
+                    assert np.isfinite(b).all(), (rep, i)
+                    assert rel_rms(b * c2, a * c2) <= 1e-6, (rep, i)
+                _ = torch.ones(1 << 20, device="cuda:0").sum().item()   # other eager work between replays
+            graph.close()
+    finally:
+        for p in plans:
+            p.close()
+    ref = oracle.wstack.wstack_dataset(jobs[2])
+    err = image_errors(got[2], ref.image, ref.corr)
+    assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+
+
+def test_joint_launch_argument_checks():
+    jobs = _jobs(2, seed=25)
+    dev = [to_device(ds)[:2] for ds in jobs]
+    p = rick.Plan.for_dataset(jobs[0], fused=True)
+    q = rick.Plan.for_dataset(jobs[1], precision="fp64", fused=True)
+    u = rick.Plan(grid_n=256, n_wplanes=4, support=7, oversample=32, fov=0.2, w_min=-1.0, w_max=1.0,
+                  kernel="user_lut", lut_wbins=2)
+    try:
+        u0, v0 = dev[0]
+        with pytest.raises(rick.RickError, match="INVALID_ARG"):      # the same plan twice
+            rick.grid_jobs([(p, u0, v0, None, jobs[0].freq), (p, u0, v0, None, jobs[0].freq)])
+        u1, v1, _ = to_device(jobs[1], "fp64")
+        with pytest.raises(rick.RickError, match="INVALID_ARG"):      # mixed precisions
+            rick.grid_jobs([(p, u0, v0, None, jobs[0].freq), (q, u1, v1, None, jobs[1].freq)])
+        with pytest.raises(rick.RickError, match="UNSUPPORTED"):      # a user table
+            rick.grid_jobs([(u, u0, v0, None, jobs[0].freq)])
+    finally:
+        for x in (p, q, u):
+            x.close()
