@@ -619,7 +619,8 @@ def batch_report(args):
 
     dev = "cuda:0"
     t0 = time.time()
-    jobs = synth.batched_jobs(n_jobs=args.jobs, device=dev)
+    sizes = tuple(int(x) for x in args.grid_sizes.split(","))
+    jobs = synth.batched_jobs(n_jobs=args.jobs, grid_sizes=sizes, device=dev)
     n = len(jobs)
     nvis = sum(ds.nvis for ds in jobs)
     print(f"[batch] generated {n} jobs, {nvis:,} visibilities in {time.time() - t0:.1f} s", file=sys.stderr,
@@ -839,7 +840,7 @@ def batch_report(args):
     ocheck = float(np.linalg.norm((got - ref) * c2) / np.linalg.norm(ref * c2))
     med = float(np.median(totals))
     lat_sorted = np.sort(np.asarray(lat))
-    out = {"report": "batch", "jobs": n, "n_vis": nvis, "steps": args.steps,
+    out = {"report": "batch", "jobs": n, "grid_sizes": list(sizes), "n_vis": nvis, "steps": args.steps,
            "jobs_per_s": round(n / (med * 1e-3), 2), "batch_ms": round(med, 3),
            "mvis_per_s": round(nvis / (med * 1e-3) / 1e6, 1),
            "latency_ms": {"p50": round(float(np.percentile(lat_sorted, 50)), 3),
@@ -1131,6 +1132,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the batched form: many uneven jobs recorded into a graph and replayed (jobs/s, latency)")
     ap.add_argument("--jobs", type=int, default=64, help="number of jobs of --batch")
+    ap.add_argument("--grid-sizes", default="512,1024,2048,4096",
+                    help="--batch: grid sizes the jobs are drawn from (comma-separated)")
     ap.add_argument("--replicas", type=int, default=2,
                     help="--batch: plans per (grid, planes) shape, the shape's jobs dealt to them in turn")
     ap.add_argument("--no-orient", action="store_true",
