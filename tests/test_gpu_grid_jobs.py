@@ -1,12 +1,12 @@
 """Gridding of many jobs in one persistent launch (rick_grid_jobs) through
 the C ABI.
 
-Jobs of uneven grid size and visibility count, each on its own plan (two
-tile edges, so two launches; small chunks on some plans, so bins spanning
-several work items flush with atomics), are gridded jointly and checked
-against the same plans gridded one call at a time: equal counters and tile
-bitmaps, planes equal to float rounding, images equal to float rounding and
-to the oracle's.  The joint call is also recorded into a graph and replayed,
+Eight jobs of uneven grid size, plane count and visibility count, each on
+its own plan (two tile edges, so two launches; small chunks on some plans,
+so bins spanning several work items flush with atomics), are gridded
+jointly and checked against the same plans gridded one call at a time:
+equal counters and tile bitmaps, planes equal to float rounding, images
+equal to float rounding, and every job's image against the oracle's.  The joint call is also recorded into a graph and replayed,
 with other work between the replays, and its argument checks are exercised.
 """
 import numpy as np
@@ -55,7 +55,7 @@ def _image(p):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_joint_launch_equals_one_call_per_job(precision):
     import torch
-    jobs = _jobs(6 if precision == "fp32" else 3)
+    jobs = _jobs(8 if precision == "fp32" else 4)
     dev = [to_device(ds, precision)[:2] for ds in jobs]
     plans = _plans(jobs, precision)
     try:
@@ -85,8 +85,9 @@ def test_joint_launch_equals_one_call_per_job(precision):
         assert rel_rms(b["G"], a["G"]) <= g_tol, i
         c2 = _apparent(jobs[i])
         assert rel_rms(b["img"] * c2, a["img"] * c2) <= g_tol, i
-    # two jobs (one per tile edge) against the oracle
-    for i in (0, 1):
+    # every job against the oracle
+    assert len({(ds.grid_n, ds.n_wplanes) for ds in jobs}) >= 2
+    for i in range(len(jobs)):
         ref = oracle.wstack.wstack_dataset(jobs[i])
         if precision == "fp64":
             assert rel_rms(joint[i]["img"], ref.image) <= 1e-10
