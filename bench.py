@@ -747,15 +747,13 @@ def batch_report(args):
             imgs[i].copy_(seq_imgs[i])
     # the jobs in rounds on one stream, each round's gridding ONE persistent
     # launch over the work items of all its jobs (rick_grid_jobs; one launch
-    # per tile edge among them): round r holds the r-th job of every plan
+    # per tile edge among them) and the fused column passes of its small grids
+    # one launch per grid size (rick_wstack_image_jobs): round r holds the
+    # r-th job of every plan
     plan_jobs = {k: [i for i in range(n) if slot_of[i] == k] for k in plans}
     rounds = [[lst[r] for lst in plan_jobs.values() if r < len(lst)]
               for r in range(max(len(x) for x in plan_jobs.values()))]
     jstamps = rick.Stamps(len(rounds) + 1)
-
-    # the round's transforms spread over the streams (forked after the joint
-    # gridding, joined before the next round, whose jobs reuse the plans)
-    jstreams = [stream] + [torch.cuda.Stream() for _ in range(max(1, args.streams) - 1)]
 
     def issue_joint(s):
         jstamps.stamp(0, s)
@@ -765,18 +763,16 @@ def batch_report(args):
                 p.retarget(jobs[i].fov, jobs[i].w_min, jobs[i].w_max)
                 p.reset(s)
             rick.grid_jobs([(plans[slot_of[i]], uvw[i], vis[i], None, jobs[i].freq) for i in rd], s)
-            ev = torch.cuda.Event()
-            ev.record(s)
-            for st in jstreams[1:]:
-                st.wait_event(ev)
-            for k, i in enumerate(sorted(rd, key=lambda i: -jobs[i].grid_n ** 2 * jobs[i].n_wplanes)):
-                st = jstreams[k % len(jstreams)]
-                plans[slot_of[i]].fft(st)
-                plans[slot_of[i]].image(imgs[i], st)
-            for st in jstreams[1:]:
-                e = torch.cuda.Event()
-                e.record(st)
-                s.wait_event(e)
+            for i in rd:
+                plans[slot_of[i]].fft(s)
+            # grids of at most 1024^2 share column-pass launches (their own
+            # passes have few strips); larger ones fill the device by themselves
+            small = [i for i in rd if jobs[i].grid_n <= 1024]
+            if small:
+                rick.wstack_image_jobs([(plans[slot_of[i]], imgs[i]) for i in small], s)
+            for i in rd:
+                if jobs[i].grid_n > 1024:
+                    plans[slot_of[i]].image(imgs[i], s)
             jstamps.stamp(ri + 1, s)
 
     jeager = []
@@ -800,7 +796,7 @@ def batch_report(args):
     for i in range(n):
         imgs[i].copy_(seq_imgs[i])
     jmed = float(np.median(jtot))
-    joint = {"rounds": len(rounds), "streams": len(jstreams), "jobs_per_s": round(n / (jmed * 1e-3), 2),
+    joint = {"rounds": len(rounds), "streams": 1, "jobs_per_s": round(n / (jmed * 1e-3), 2),
              "batch_ms": round(jmed, 3), "mvis_per_s": round(nvis / (jmed * 1e-3) / 1e6, 1),
              "eager_batch_ms": [round(x, 3) for x in jeager],
              "round_ms": [round(x, 3) for x in jround]}

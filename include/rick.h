@@ -20,11 +20,13 @@
  *   rick_degrid_order_create, rick_degrid_sorted, rick_degrid_order_destroy
  *                      prediction at fixed positions: quantise and sort once,
  *                      interpolate in sorted order every time
- *   rick_plan_retarget, rick_grid_jobs, rick_capture_begin/_end,
+ *   rick_plan_retarget, rick_grid_jobs, rick_wstack_image_jobs,
+ *   rick_capture_begin/_end,
  *   rick_graph_launch/_destroy, rick_stamps_create/_stamp/_elapsed/_destroy,
  *   rick_autotune
  *                      many jobs: one plan per shape retargeted per job, the
- *                      gridding of many jobs in one persistent launch, work
+ *                      gridding of many jobs in one persistent launch and
+ *                      their column passes in one launch per grid size, work
  *                      recorded into a graph and replayed, device timestamps,
  *                      tile and chunk chosen by measurement
  *
@@ -301,6 +303,32 @@ rick_status rick_fft_planes(rick_plan_t *p, void *stream);
  * (planes not transformed), RICK_E_HIP.
  */
 rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream);
+
+/*
+ * rick_wstack_image_jobs -- rick_wstack_image for several plans made with
+ * RICK_FLAG_FUSED_SCREEN at once (the w-correction and plane sum of
+ * Sec. 2.1, Eq. 1-2, of a batch of jobs): every image is the one
+ * rick_wstack_image would write for its plan, bit for bit.  The fused
+ * column pass of all plans of one grid size (and one precision mode) is
+ * ONE launch over their column strips together, so that small grids, whose
+ * own pass has few strips, fill the device.  Runs on `stream`; allocates
+ * nothing (may be recorded into a graph).
+ *   jobs   HOST array of n {plan, image} pairs (image: device, as for
+ *          rick_wstack_image); the array may be freed when the call returns
+ *   n      1 ... RICK_MAX_GRID_JOBS
+ * Every plan must be a different one, fused, after rick_fft_planes, on one
+ * device, all in float32 modes or all in FP64 mode.  All arguments are
+ * checked before any device work.
+ * Errors: RICK_E_INVALID_ARG (NULL jobs or image, n out of range, a plan
+ * given twice, a plan without the fused screen, misalignment, mixed devices
+ * or precisions), RICK_E_BAD_PLAN, RICK_E_STATE (planes not transformed),
+ * RICK_E_HIP.
+ */
+typedef struct rick_image_job {
+    rick_plan_t *plan;
+    void *image;
+} rick_image_job;
+rick_status rick_wstack_image_jobs(const rick_image_job *jobs, int32_t n, void *stream);
 
 /*
  * rick_predict_planes -- the first half of prediction (degridding): the

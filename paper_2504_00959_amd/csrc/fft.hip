@@ -574,22 +574,18 @@ __device__ __forceinline__ double screen_term(double t2, double2 f, int flip) {
 // symmetric in l and m, so the same values serve), and adds its sums to the
 // image there, unless no plane was taken.
 template <typename real, int N, int V, int VC, int PW, bool KAHAN, int E>
-__global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
-                                                                         const real *__restrict__ twr,
-                                                                         const double *__restrict__ corr,
-                                                                         const Stats *__restrict__ st,
-                                                                         const uint64_t *__restrict__ row_bits,
-                                                                         const int32_t *__restrict__ plane_tr,
-                                                                         int pass, real *__restrict__ image) {
+__device__ __forceinline__ void cols_screen_strip(const Geom &g, const real *__restrict__ mesh,
+                                                  const real *__restrict__ twr, const double *__restrict__ corr,
+                                                  const Stats *__restrict__ st, const uint64_t *__restrict__ row_bits,
+                                                  const int32_t *__restrict__ plane_tr, int pass,
+                                                  real *__restrict__ image, int strip) {
     using C = typename R2T<real>::t;
     using SH = Shape<N>;
-    constexpr int NSTRIP = N / V;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);
     constexpr int PADN = E == 8 ? padn8<N>() : SH::PADN;   // LDS elements of the exchange
     double *s_nm1 = reinterpret_cast<double *>(buf + PADN * V);
     const C *tw = reinterpret_cast<const C *>(twr);
-    const int strip = (int)xcd_order(blockIdx.x, NSTRIP);
     const int c0 = strip * V;
     const int vg = threadIdx.x % (V / VC), tb = threadIdx.x / (V / VC), v0 = vg * VC;
     // the row transforms in column-panel order: row e of column c at
@@ -715,6 +711,44 @@ __global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen(Geom g, 
     }
 }
 
+template <typename real, int N, int V, int VC, int PW, bool KAHAN, int E>
+__global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen(Geom g, const real *__restrict__ mesh,
+                                                                         const real *__restrict__ twr,
+                                                                         const double *__restrict__ corr,
+                                                                         const Stats *__restrict__ st,
+                                                                         const uint64_t *__restrict__ row_bits,
+                                                                         const int32_t *__restrict__ plane_tr,
+                                                                         int pass, real *__restrict__ image) {
+    cols_screen_strip<real, N, V, VC, PW, KAHAN, E>(g, mesh, twr, corr, st, row_bits, plane_tr, pass, image,
+                                                    (int)xcd_order(blockIdx.x, N / V));
+}
+
+// The fused column pass of several plans of one grid size in one launch:
+// block b takes strip b mod (N / V) of job b div (N / V) (after the XCD
+// ordering of the combined index), with that job's operands read from its
+// device slot (uniform: scalar loads).  The per-strip work is the
+// single-plan kernel's.
+typedef __attribute__((address_space(4))) const uint32_t const_u32_cols;
+__device__ __forceinline__ ColJob load_col_job(const ColJob *p) {
+    static_assert(sizeof(ColJob) % 4 == 0, "whole words");
+    ColJob v;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+    const const_u32_cols *src = (const const_u32_cols *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(ColJob) / 4); ++i) dst[i] = src[i];
+    return v;
+}
+template <typename real, int N, int V, int VC, int PW, bool KAHAN, int E>
+__global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen_jobs(ColJobList list, int pass) {
+    constexpr int NSTRIP = N / V;
+    const int64_t b = xcd_order(blockIdx.x, (int64_t)list.n * NSTRIP);
+    const int32_t j = __builtin_amdgcn_readfirstlane((int32_t)(b / NSTRIP));
+    const ColJob J = load_col_job(list.job[j]);
+    cols_screen_strip<real, N, V, VC, PW, KAHAN, E>(J.g, (const real *)J.mesh, (const real *)J.tw, J.corr, J.st,
+                                                    J.row_bits, J.plane_tr, pass, (real *)J.image,
+                                                    (int)(b - (int64_t)j * NSTRIP));
+}
+
 // strip width V (columns per block) and columns per thread VC
 template <typename real, int N>
 struct ColShape {
@@ -829,7 +863,53 @@ hipError_t cols_screen_n(const Geom &g, const real *mesh, const real *tw, const 
     return hipGetLastError();
 }
 
+template <typename real, int N>
+hipError_t cols_screen_jobs_n(const ColJobList &list, int pass, int kahan, hipStream_t s) {
+    using CS = ColShape<real, N>;
+    constexpr int PW = PanelShape<real, N>::PW;
+    constexpr int E = (N == 8192 && sizeof(real) == 4) ? 8 : 16;   // as the single-plan launch
+    constexpr int THREADS = (N / E) * (CS::V / CS::VC);
+    const size_t lds = size_t(E == 8 ? padn8<N>() : Shape<N>::PADN) * CS::V * sizeof(typename CS::C) +
+                       size_t(N) * CS::V * sizeof(double);
+    static std::once_flag attr_once[kMaxDevices];
+    once_per_device(attr_once, [&] {
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen_jobs<real, N, CS::V, CS::VC, PW, false, E>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void *)k_fft_cols_screen_jobs<real, N, CS::V, CS::VC, PW, true, E>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    });
+    const dim3 grid((unsigned)(list.n * (N / CS::V)));
+    if (kahan)
+        hipLaunchKernelGGL((k_fft_cols_screen_jobs<real, N, CS::V, CS::VC, PW, true, E>), grid, dim3(THREADS), lds, s,
+                           list, pass);
+    else
+        hipLaunchKernelGGL((k_fft_cols_screen_jobs<real, N, CS::V, CS::VC, PW, false, E>), grid, dim3(THREADS), lds,
+                           s, list, pass);
+    return hipGetLastError();
+}
+
+__global__ void k_put_col_job(ColJob *__restrict__ dst, ColJob v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = v;
+}
+
 }  // namespace
+
+hipError_t launch_put_col_job(ColJob *dst, const ColJob &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_col_job, dim3(1), dim3(64), 0, s, dst, v);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_fft_cols_screen_jobs(const ColJobList &list, int N, int pass, int kahan, hipStream_t s) {
+    if (list.n < 1 || list.n > kMaxGridJobs) return hipErrorInvalidValue;
+    switch (N) {
+#define CASE(n) \
+    case n: return cols_screen_jobs_n<real, n>(list, pass, kahan, s);
+        CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
 
 bool fft_supported(int N, size_t real_bytes) {
     return (N & (N - 1)) == 0 && N >= 64 && (N <= 8192 || (N == 16384 && real_bytes == 4));
@@ -937,5 +1017,7 @@ template hipError_t launch_fft_cols_screen<float>(const Geom &, const float *, c
 template hipError_t launch_fft_cols_screen<double>(const Geom &, const double *, const double *, const double *,
                                                    const Stats *, const uint64_t *, const int32_t *, int, double *,
                                                    int, hipStream_t);
+template hipError_t launch_fft_cols_screen_jobs<float>(const ColJobList &, int, int, int, hipStream_t);
+template hipError_t launch_fft_cols_screen_jobs<double>(const ColJobList &, int, int, int, hipStream_t);
 
 }  // namespace rick

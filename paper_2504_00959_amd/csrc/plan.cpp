@@ -104,6 +104,7 @@ struct rick_plan_s {
     double *scales = nullptr;
     Stats *stats = nullptr;
     GridJob *job_dev = nullptr;   // this plan's operands for the multi-job gridder
+    ColJob *coljob_dev = nullptr;   // ... and for the multi-job column pass
     int32_t *counts = nullptr;
     BinScan *scan = nullptr;
     int32_t *block_sums = nullptr;
@@ -167,7 +168,7 @@ void free_all(rick_plan_t *p) {
                     p->stats,     p->counts,     p->scan,      p->block_sums, p->cnt1,  p->rec1,
                     p->key_chunk0, p->chunk_key, p->cnt2,   p->vmax2,    p->bin_vmax, p->item_bin, p->heavy_bins,
                     p->rec_pos,   p->rec_vis,   p->dft_wsum,  p->tapmax,    p->corr2,     p->taper_bufs.A,
-                    p->job_dev};
+                    p->job_dev,   p->coljob_dev};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < kMaxTimers; ++i)
@@ -462,6 +463,7 @@ rick_status rick_plan(const rick_plan_desc *d, rick_plan_t **out) {
     ALLOC(p->scales, size_t(kMaxChan) * 8);
     ALLOC(p->stats, sizeof(Stats));
     ALLOC(p->job_dev, sizeof(GridJob));
+    ALLOC(p->coljob_dev, sizeof(ColJob));
     ALLOC(p->counts, sz_counts);
     ALLOC(p->scan, sz_scan);
     ALLOC(p->block_sums, sz_bsum);
@@ -924,6 +926,56 @@ rick_status rick_wstack_image(rick_plan_t *p, void *image, void *stream) {
         e = launch_wscreen<float>(p->g, (const float *)p->mesh, taper_of(p), p->stats, (float *)image, kahan, s);
     timer_end(p, T_SCREEN, s);
     if (e != hipSuccess) return hip_fail(e, "wscreen");
+    return RICK_OK;
+}
+
+rick_status rick_wstack_image_jobs(const rick_image_job *jobs, int32_t n, void *stream) {
+    if (!jobs) return fail(RICK_E_INVALID_ARG, "jobs is NULL");
+    if (n < 1 || n > kMaxGridJobs) return fail(RICK_E_INVALID_ARG, "n=%d (1 ... %d jobs)", n, kMaxGridJobs);
+    for (int32_t i = 0; i < n; ++i) {
+        rick_plan_t *p = jobs[i].plan;
+        if (!plan_ok(p)) return fail(RICK_E_BAD_PLAN, "job %d: invalid plan", i);
+        if (!p->fused) return fail(RICK_E_INVALID_ARG, "job %d: plan without RICK_FLAG_FUSED_SCREEN", i);
+        if (!jobs[i].image) return fail(RICK_E_INVALID_ARG, "job %d: image is NULL", i);
+        if (((uintptr_t)jobs[i].image) & (p->fp64 ? 7 : 3)) return fail(RICK_E_INVALID_ARG, "job %d: misaligned image", i);
+        if (p->state != 2) return fail(RICK_E_STATE, "job %d: planes not transformed; call rick_fft_planes first", i);
+        if (p->fp64 != jobs[0].plan->fp64) return fail(RICK_E_INVALID_ARG, "job %d: precision differs from job 0's", i);
+        if (p->d.device != jobs[0].plan->d.device)
+            return fail(RICK_E_INVALID_ARG, "job %d: device differs from job 0's", i);
+        for (int32_t k = 0; k < i; ++k)
+            if (jobs[k].plan == p) return fail(RICK_E_INVALID_ARG, "job %d: same plan as job %d", i, k);
+    }
+    DeviceGuard guard(jobs[0].plan->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp64 = jobs[0].plan->fp64;
+    // one launch per (grid size, compensated sum) and pass: pass 0 over every
+    // plan of the group (writes the images), pass 1 over those holding
+    // transposed planes (adds to them)
+    bool done[kMaxGridJobs] = {};
+    for (int32_t i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        const rick_plan_t *pi = jobs[i].plan;
+        const int kahan = pi->d.precision == RICK_PREC_FP32_KAHAN;
+        ColJobList all{}, tr{};
+        for (int32_t j = i; j < n; ++j) {
+            rick_plan_t *p = jobs[j].plan;
+            if (done[j] || p->g.N != pi->g.N || (p->d.precision == RICK_PREC_FP32_KAHAN) != (kahan != 0)) continue;
+            done[j] = true;
+            const ColJob d{p->g, p->row_mesh, p->twiddle, taper_of(p), p->stats, p->row_bits, p->plane_tr,
+                           jobs[j].image};
+            const hipError_t e = launch_put_col_job(p->coljob_dev, d, s);
+            if (e != hipSuccess) return hip_fail(e, "column job table");
+            all.job[all.n++] = p->coljob_dev;
+            if (p->plane_tr) tr.job[tr.n++] = p->coljob_dev;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            const ColJobList &list = pass ? tr : all;
+            if (list.n == 0) continue;
+            const hipError_t e = fp64 ? launch_fft_cols_screen_jobs<double>(list, pi->g.N, pass, 0, s)
+                                      : launch_fft_cols_screen_jobs<float>(list, pi->g.N, pass, kahan, s);
+            if (e != hipSuccess) return hip_fail(e, "fft_cols_screen_jobs");
+        }
+    }
     return RICK_OK;
 }
 

@@ -225,6 +225,27 @@ hipError_t launch_put_grid_job(GridJob *dst, const GridJob &v, hipStream_t s);
 template <typename real>
 hipError_t launch_grid_jobs(const GridJobList &list, int W, int T, size_t lds, int64_t max_items,
                             unsigned long long *next, hipStream_t s);
+// One fused plan's operands as the multi-job column pass reads them (a
+// device copy per plan, written by launch_put_col_job before the launch).
+struct ColJob {
+    Geom g;
+    const void *mesh;   // row transforms, column-panel order
+    const void *tw;
+    const double *corr;   // the taper the screen divides by
+    const Stats *st;
+    const uint64_t *row_bits;
+    const int32_t *plane_tr;
+    void *image;
+};
+struct ColJobList {
+    int32_t n;
+    const ColJob *job[kMaxGridJobs];
+};
+hipError_t launch_put_col_job(ColJob *dst, const ColJob &v, hipStream_t s);
+// The fused column pass (pass 0 or 1, as launch_fft_cols_screen) of list.n
+// fused plans of grid size N in one launch.
+template <typename real>
+hipError_t launch_fft_cols_screen_jobs(const ColJobList &list, int N, int pass, int kahan, hipStream_t s);
 // Orientation of every plane that holds no set tile yet: transposed iff this
 // call's records (with the margins they spill right and down) occupy fewer
 // tile columns than tile rows.  Planes already holding tiles keep theirs.

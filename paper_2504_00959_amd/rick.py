@@ -88,6 +88,11 @@ class GridJob(ctypes.Structure):
                 ("nchan", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ImageJob(ctypes.Structure):
+    """rick_image_job: one job of rick_wstack_image_jobs."""
+    _fields_ = [("plan", ctypes.c_void_p), ("image", ctypes.c_void_p)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("grid_n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -128,6 +133,7 @@ def lib() -> ctypes.CDLL:
     L.rick_grid.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
     L.rick_grid_static.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P, P, ctypes.c_int64, ctypes.c_int32, P]
     L.rick_grid_jobs.argtypes = [ctypes.POINTER(GridJob), ctypes.c_int32, P]
+    L.rick_wstack_image_jobs.argtypes = [ctypes.POINTER(ImageJob), ctypes.c_int32, P]
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     L.rick_plan_set_lut.argtypes = [P, P, i32, P]
     L.rick_mlp_tabulate.argtypes = [P, i32, i32, i32, P, P]
@@ -166,7 +172,7 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(ctypes.c_float)]
     for f in ("rick_plan_set_lut", "rick_mlp_tabulate", "rick_mlp_backward", "rick_adam_step", "rick_image_loss",
               "rick_table_gradient", "rick_dft_image", "rick_separable_table", "rick_table_residual",
-              "rick_plan", "rick_grid", "rick_grid_static", "rick_grid_jobs", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
+              "rick_plan", "rick_grid", "rick_grid_static", "rick_grid_jobs", "rick_wstack_image_jobs", "rick_fft_planes", "rick_wstack_image", "rick_reset", "rick_plan_info",
               "rick_plan_destroy", "rick_plan_bin_counts", "rick_capture_begin", "rick_capture_end",
               "rick_graph_launch", "rick_graph_destroy", "rick_stamps_create", "rick_stamp", "rick_stamps_elapsed",
               "rick_stamps_destroy", "rick_autotune", "rick_plan_retarget", "rick_predict_planes", "rick_degrid",
@@ -638,6 +644,22 @@ def grid_jobs(jobs, stream=None):
         freq = job[4] if len(job) > 4 else None
         arr[i] = plan._grid_args(uvw, vis, weight, freq)
     _check(lib().rick_grid_jobs(arr, len(jobs), _stream_handle(stream)), "rick_grid_jobs")
+
+
+def wstack_image_jobs(jobs, stream=None):
+    """rick_wstack_image_jobs: each job (plan, image) -- image a contiguous
+    device tensor [N, N] of the plan's real dtype -- as Plan.image would
+    write it, the fused column passes of one grid size in one launch."""
+    jobs = list(jobs)
+    if not jobs:
+        raise ValueError("no jobs")
+    arr = (ImageJob * len(jobs))()
+    for i, (plan, img) in enumerate(jobs):
+        plan._device_tensor(img, "image", plan.real_dtype)
+        if tuple(img.shape) != (plan.grid_n, plan.grid_n):
+            raise ValueError("image must be [grid_n, grid_n]")
+        arr[i] = ImageJob(plan._h, img.data_ptr())
+    _check(lib().rick_wstack_image_jobs(arr, len(jobs), _stream_handle(stream)), "rick_wstack_image_jobs")
 
 
 def adam_step(theta, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -100,3 +100,12 @@ def test_grid_jobs_validates_on_the_host():
     assert L.rick_grid_jobs(jobs, 65, None) == 1
     assert b"1 ... 64" in L.rick_last_error()
     assert L.rick_grid_jobs(jobs, 2, None) == 6                     # RICK_E_BAD_PLAN: a NULL plan
+
+
+def test_wstack_image_jobs_validates_on_the_host():
+    L = rick.lib()
+    assert L.rick_wstack_image_jobs(None, 1, None) == 1              # RICK_E_INVALID_ARG: no jobs
+    jobs = (rick.ImageJob * 2)()
+    assert L.rick_wstack_image_jobs(jobs, 0, None) == 1              # n out of range
+    assert L.rick_wstack_image_jobs(jobs, 65, None) == 1
+    assert L.rick_wstack_image_jobs(jobs, 2, None) == 6              # RICK_E_BAD_PLAN: a NULL plan

@@ -1,5 +1,6 @@
-"""Gridding of many jobs in one persistent launch (rick_grid_jobs) through
-the C ABI.
+"""Many jobs per launch through the C ABI: the gridding of many jobs in one
+persistent launch (rick_grid_jobs) and the fused column passes of many
+plans of one grid size in one launch (rick_wstack_image_jobs).
 
 Eight jobs of uneven grid size, plane count and visibility count, each on
 its own plan (two tile edges, so two launches; small chunks on some plans,
@@ -8,6 +9,9 @@ jointly and checked against the same plans gridded one call at a time:
 equal counters and tile bitmaps, planes equal to float rounding, images
 equal to float rounding, and every job's image against the oracle's.  The joint call is also recorded into a graph and replayed,
 with other work between the replays, and its argument checks are exercised.
+The joint column pass must give every plan's image bit for bit, with
+planes stored as they are and transposed, in float32 (plain and
+compensated sums) and float64.
 """
 import numpy as np
 import pytest
@@ -109,9 +113,9 @@ def test_joint_launch_recorded_and_replayed():
         for p in plans:
             p.reset(s)
         rick.grid_jobs(args, s)
-        for p, im in zip(plans, imgs):
+        for p in plans:
             p.fft(s)
-            p.image(im, s)
+        rick.wstack_image_jobs(list(zip(plans, imgs)), s)
 
     try:
         with torch.cuda.stream(stream):
@@ -163,3 +167,38 @@ def test_joint_launch_argument_checks():
     finally:
         for x in (p, q, u):
             x.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan", "fp64"])
+def test_joint_column_pass_equals_one_call_per_plan(precision):
+    import torch
+    jobs = _jobs(8 if precision != "fp64" else 4, seed=26)
+    dev = [to_device(ds, precision)[:2] for ds in jobs]
+    # every other plan with transposed planes allowed (a second pass)
+    plans = [rick.Plan.for_dataset(ds, precision=precision, fused=True, orient=(i % 2 == 1))
+             for i, ds in enumerate(jobs)]
+    try:
+        for p, ds, (u, v) in zip(plans, jobs, dev):
+            p.reset()
+            p.grid(u, v, None, ds.freq)
+            p.fft()
+        single = [p.image() for p in plans]
+        joint = [torch.full_like(im, float("nan")) for im in single]
+        rick.wstack_image_jobs(list(zip(plans, joint)))
+        torch.cuda.synchronize()
+        assert any(p.transposed().any() for p in plans)
+        for i, (a, b) in enumerate(zip(single, joint)):
+            assert torch.equal(a, b), i
+        ref = oracle.wstack.wstack_dataset(jobs[3])
+        got = joint[3].double().cpu().numpy()
+        if precision == "fp64":
+            assert rel_rms(got, ref.image) <= 1e-10
+        else:
+            err = image_errors(got, ref.image, ref.corr)
+            assert err["apparent"] <= FP32_IMG and err["central"] <= FP32_IMG, err
+        with pytest.raises(rick.RickError, match="STATE"):             # planes not transformed
+            plans[0].reset()
+            rick.wstack_image_jobs([(plans[0], joint[0])])
+    finally:
+        for p in plans:
+            p.close()
