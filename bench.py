@@ -765,14 +765,7 @@ def batch_report(args):
             rick.grid_jobs([(plans[slot_of[i]], uvw[i], vis[i], None, jobs[i].freq) for i in rd], s)
             for i in rd:
                 plans[slot_of[i]].fft(s)
-            # grids of at most 1024^2 share column-pass launches (their own
-            # passes have few strips); larger ones fill the device by themselves
-            small = [i for i in rd if jobs[i].grid_n <= 1024]
-            if small:
-                rick.wstack_image_jobs([(plans[slot_of[i]], imgs[i]) for i in small], s)
-            for i in rd:
-                if jobs[i].grid_n > 1024:
-                    plans[slot_of[i]].image(imgs[i], s)
+            rick.wstack_image_jobs([(plans[slot_of[i]], imgs[i]) for i in rd], s)
             jstamps.stamp(ri + 1, s)
 
     jeager = []

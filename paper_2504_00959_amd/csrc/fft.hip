@@ -723,11 +723,12 @@ __global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen(Geom g, 
                                                     (int)xcd_order(blockIdx.x, N / V));
 }
 
-// The fused column pass of several plans of one grid size in one launch:
-// block b takes strip b mod (N / V) of job b div (N / V) (after the XCD
-// ordering of the combined index), with that job's operands read from its
-// device slot (uniform: scalar loads).  The per-strip work is the
-// single-plan kernel's.
+// The fused column pass of several plans of one grid size in one launch,
+// one block per (job, strip), with that job's operands read from its device
+// slot (uniform: scalar loads).  The per-strip work is the single-plan
+// kernel's.  Blocks go to the 8 XCDs round-robin; each XCD takes the same
+// eighth of every job's strips (adjacent strips, sharing L2 lines), job
+// after job, so that jobs of unequal work keep every XCD busy.
 typedef __attribute__((address_space(4))) const uint32_t const_u32_cols;
 __device__ __forceinline__ ColJob load_col_job(const ColJob *p) {
     static_assert(sizeof(ColJob) % 4 == 0, "whole words");
@@ -741,12 +742,20 @@ __device__ __forceinline__ ColJob load_col_job(const ColJob *p) {
 template <typename real, int N, int V, int VC, int PW, bool KAHAN, int E>
 __global__ __launch_bounds__((N / E) * (V / VC)) void k_fft_cols_screen_jobs(ColJobList list, int pass) {
     constexpr int NSTRIP = N / V;
-    const int64_t b = xcd_order(blockIdx.x, (int64_t)list.n * NSTRIP);
-    const int32_t j = __builtin_amdgcn_readfirstlane((int32_t)(b / NSTRIP));
+    int32_t j, strip;
+    if constexpr (NSTRIP % 8 == 0) {
+        constexpr int PER = NSTRIP / 8;   // strips of one job per XCD
+        const int32_t x = (int32_t)(blockIdx.x & 7), r = (int32_t)(blockIdx.x >> 3);
+        j = r / PER;
+        strip = x * PER + (r - j * PER);
+    } else {
+        j = (int32_t)(blockIdx.x / NSTRIP);
+        strip = (int32_t)(blockIdx.x - j * NSTRIP);
+    }
+    j = __builtin_amdgcn_readfirstlane(j);
     const ColJob J = load_col_job(list.job[j]);
     cols_screen_strip<real, N, V, VC, PW, KAHAN, E>(J.g, (const real *)J.mesh, (const real *)J.tw, J.corr, J.st,
-                                                    J.row_bits, J.plane_tr, pass, (real *)J.image,
-                                                    (int)(b - (int64_t)j * NSTRIP));
+                                                    J.row_bits, J.plane_tr, pass, (real *)J.image, strip);
 }
 
 // strip width V (columns per block) and columns per thread VC
