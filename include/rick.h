@@ -374,8 +374,10 @@ rick_status rick_degrid(rick_plan_t *p, const double *uvw, const double *freq_hz
  * again, e.g. every cycle of a deconvolution): the positions are quantised
  * and sorted once by the offset of their footprint origin in the layout the
  * plan holds predicted planes in (plane, then row and column: row order, or
- * column panels with RICK_FLAG_FUSED_SCREEN), so that neighbouring threads
- * of rick_degrid_sorted read neighbouring footprints.
+ * column panels with RICK_FLAG_FUSED_SCREEN), down to groups of PW x 8 cells
+ * (a panel's width by 8 rows; 8 x 1 in row order) whose visibilities keep
+ * their own order, so that neighbouring threads of rick_degrid_sorted read
+ * neighbouring footprints and write neighbouring results where they can.
  *
  * rick_degrid_order_create -- quantise (exactly as rick_grid and rick_degrid
  * do, for the plan's current grid, field and w range) and sort (the

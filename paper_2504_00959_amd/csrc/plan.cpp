@@ -1136,14 +1136,22 @@ rick_status rick_degrid_order_create(rick_plan_t *p, const double *uvw, const do
     const int32_t panel = p->fused ? p->panel : 0;
     int end_bit = 1;
     while ((uint64_t(1) << end_bit) < uint64_t(g.Nw) * uint64_t(g.N) * uint64_t(g.N)) ++end_bit;
+    // the sort ignores the key's lowest bits (the column inside a panel and
+    // 3 bits of the row; 3 bits of the column in row order): footprints of one
+    // group of PW x 8 cells (8 x 1 in row order) stay together, in visibility order, so
+    // that a wave's results land in fewer, longer runs of the output
+    int begin_bit = (panel > 0 ? __builtin_ctz((unsigned)panel) : 0) + 3;
+    if (begin_bit >= end_bit) begin_bit = 0;
     size_t temp_bytes = 0;
     e = launch_set_scales(p->scales, sc.data(), nchan, s);
     if (e == hipSuccess)
         e = p->fp64 ? launch_order_keys<double>(g, uvw, p->scales, nrow, nchan, panel, kin, vin, s)
                     : launch_order_keys<float>(g, uvw, p->scales, nrow, nchan, panel, kin, vin, s);
-    if (e == hipSuccess && nvis > 0) e = sort_order(nullptr, temp_bytes, kin, kout, vin, vout, nvis, 0, end_bit, s);
+    if (e == hipSuccess && nvis > 0)
+        e = sort_order(nullptr, temp_bytes, kin, kout, vin, vout, nvis, begin_bit, end_bit, s);
     if (e == hipSuccess && nvis > 0) e = hipMalloc(&temp, temp_bytes > 0 ? temp_bytes : 1);
-    if (e == hipSuccess && nvis > 0) e = sort_order(temp, temp_bytes, kin, kout, vin, vout, nvis, 0, end_bit, s);
+    if (e == hipSuccess && nvis > 0)
+        e = sort_order(temp, temp_bytes, kin, kout, vin, vout, nvis, begin_bit, end_bit, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     release();
     if (e != hipSuccess) {

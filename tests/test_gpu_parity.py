@@ -430,8 +430,15 @@ def test_per_visibility_decisions_match_oracle(fused):
             keys, vals, panel = o.arrays()
     assert panel == plan_panel and (panel > 0) == fused
     n = ds.nvis
-    assert keys.shape == (n,) and np.all(keys[1:] >= keys[:-1])
+    # sorted on the key's bits above the group bits (the column inside a
+    # panel and 3 row bits; 3 column bits in row order), equal groups in
+    # visibility order
+    lo = np.uint64((int(panel).bit_length() - 1 if panel else 0) + 3)
+    hi = keys >> lo
     idx = (vals & np.uint64(0xffffffff)).astype(np.int64)
+    assert keys.shape == (n,) and np.all(hi[1:] >= hi[:-1])
+    same = hi[1:] == hi[:-1]
+    assert np.all(idx[1:][same] > idx[:-1][same])
     assert np.array_equal(np.sort(idx), np.arange(n))
     dropped = keys == np.uint64(0xffffffffffffffff)
     assert np.array_equal(~dropped, b.keep[idx])
