@@ -202,3 +202,43 @@ def test_joint_column_pass_equals_one_call_per_plan(precision):
     finally:
         for p in plans:
             p.close()
+
+
+def test_joint_calls_with_an_empty_job():
+    """A job without visibilities among others: no work items of its own in
+    the joint gridding (the queue's prefix skips it), zero counters and a
+    zero image through the joint column pass; the other jobs as one call
+    each would give."""
+    import torch
+    jobs = _jobs(3, seed=27)
+    dev = [to_device(ds)[:2] for ds in jobs]
+    plans = [rick.Plan.for_dataset(ds, fused=True) for ds in jobs]
+    try:
+        single = []
+        for p, ds, (u, v) in zip(plans, jobs, dev):
+            p.reset()
+            p.grid(u, v, None, ds.freq)
+            p.fft()
+            single.append(p.image())
+        empty_u = dev[1][0][:0].contiguous()
+        empty_v = dev[1][1][:0].contiguous()
+        args = [(plans[0], *dev[0], None, jobs[0].freq), (plans[1], empty_u, empty_v, None, jobs[1].freq),
+                (plans[2], *dev[2], None, jobs[2].freq)]
+        for p in plans:
+            p.reset()
+        rick.grid_jobs(args)
+        for p in plans:
+            p.fft()
+        imgs = [torch.full_like(im, float("nan")) for im in single]
+        rick.wstack_image_jobs(list(zip(plans, imgs)))
+        torch.cuda.synchronize()
+        inf = plans[1].info()
+        assert inf["n_gridded"] == 0 and inf["n_records"] == 0
+        assert torch.count_nonzero(imgs[1]) == 0
+        for i in (0, 2):
+            c2 = _apparent(jobs[i])
+            a, b = single[i].double().cpu().numpy(), imgs[i].double().cpu().numpy()
+            assert rel_rms(b * c2, a * c2) <= 1e-6, i
+    finally:
+        for p in plans:
+            p.close()
