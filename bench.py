@@ -789,7 +789,11 @@ def batch_report(args):
     for i in range(n):
         imgs[i].copy_(seq_imgs[i])
     jmed = float(np.median(jtot))
+    # a job's latency is its round's (the round's jobs complete together)
+    jl = np.sort(np.asarray([jround[r] for r, rd in enumerate(rounds) for _ in rd]))
     joint = {"rounds": len(rounds), "streams": 1, "jobs_per_s": round(n / (jmed * 1e-3), 2),
+             "latency_ms": {"p50": round(float(np.percentile(jl, 50)), 3),
+                            "p99": round(float(np.percentile(jl, 99)), 3), "max": round(float(jl[-1]), 3)},
              "batch_ms": round(jmed, 3), "mvis_per_s": round(nvis / (jmed * 1e-3) / 1e6, 1),
              "eager_batch_ms": [round(x, 3) for x in jeager],
              "round_ms": [round(x, 3) for x in jround]}
